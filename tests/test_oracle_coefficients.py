@@ -1,0 +1,145 @@
+"""Pins of the oracle's coefficient stage (limiter, gradient, R, faces).
+
+Checked against closed forms: the limits of eq. fld_lambda stated in
+Sect. 2, the Eddington-factor limits of eq. fld_f, exactness of the
+five-point stencil on quartic polynomials and its 4th-order convergence,
+and the equivalence of mirror (Neumann) ghosts with a periodic, mirrored
+domain of twice the size.
+"""
+import numpy as np
+import pytest
+
+from oracle import fldref as F
+
+
+def test_limiter_limits():
+    # optically thick limit lambda -> 1/3 (Sect. 2)
+    assert F.limiter(0.0) == pytest.approx(1.0 / 3.0, rel=0, abs=0)
+    R = np.logspace(-4, 8, 400)
+    lam = F.limiter(R)
+    # lambda decreasing in R (below 1e-4 the steps drown in rounding)
+    assert np.all(np.diff(lam) < 0)
+    # optically thin limit lambda -> 1/R, so |F| = D |grad E| -> c E
+    assert abs(F.limiter(1e9) * 1e9 - 1.0) < 1e-8
+    # diffusion-limit mode lambda == 1/3
+    assert np.all(F.limiter(R, "diffusion") == 1.0 / 3.0)
+
+
+def test_eddington_factor_limits():
+    R = np.logspace(-8, 8, 400)
+    f = F.eddington_factor(F.limiter(R), R)
+    # thick limit f -> 1/3, thin limit f -> 1 (Sect. 2, eq. fld_f)
+    assert abs(f[0] - 1.0 / 3.0) < 1e-8
+    assert abs(f[-1] - 1.0) < 1e-7
+    assert np.all(f >= 1.0 / 3.0 - 1e-15) and np.all(f <= 1.0 + 1e-15)
+
+
+def _prob(n, bc, dx=None):
+    ndim = len(n)
+    nn = tuple(list(n) + [1] * (3 - ndim))
+    if dx is None:
+        dx = tuple([1.0 / v for v in n] + [1.0] * (3 - ndim))
+    return F.Problem(ndim=ndim, n=nn, dx=dx, bc=tuple(bc))
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4])
+def test_gradient_exact_on_quartics(deg):
+    """The five-point stencil is exact for polynomials of degree <= 4."""
+    rng = np.random.default_rng(deg)
+    n = (12, 10, 9)
+    prob = _prob(n, ["neumann"] * 3, dx=(0.3, 0.7, 1.1))
+    coef = rng.standard_normal((3, deg + 1))
+    z, y, x = np.meshgrid(*[np.arange(v) * prob.dx[d] for d, v in
+                            reversed(list(enumerate(n)))], indexing="ij")
+    coords = [x, y, z]
+    E = sum(np.polyval(coef[d], coords[d]) for d in range(3))
+    G = F.gradient(E, prob)
+    for d in range(3):
+        exact = np.polyval(np.polyder(coef[d]), coords[d])
+        ax = prob.axis(d)
+        sl = [slice(None)] * 3
+        sl[ax] = slice(2, -2)  # interior: the stencil does not touch ghosts
+        err = np.abs(G[d][tuple(sl)] - exact[tuple(sl)]).max()
+        assert err <= 1e-10 * (1 + np.abs(exact).max())
+
+
+def test_gradient_fourth_order_periodic():
+    errs = []
+    for n in (32, 64, 128):
+        prob = _prob((n,), ["periodic"])
+        x = np.arange(n) / n
+        E = 2.0 + np.sin(2 * np.pi * x)
+        G = F.gradient(E, prob)[0]
+        errs.append(np.abs(G - 2 * np.pi * np.cos(2 * np.pi * x)).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 4.0) < 0.1), rates
+
+
+def _mirror_double(f, axis):
+    return np.concatenate([f, np.flip(f, axis=axis)], axis=axis)
+
+
+@pytest.mark.parametrize("limiter", ["lp", "diffusion"])
+@pytest.mark.parametrize("face_mean", ["arith", "harmonic"])
+def test_neumann_equals_mirrored_periodic(limiter, face_mean):
+    """Mirror ghosts + wall faces == periodic domain of the even extension."""
+    rng = np.random.default_rng(7)
+    ny, nx = 6, 10
+    E = np.exp(0.4 * rng.standard_normal((ny, nx)))
+    rho = np.exp(0.3 * rng.standard_normal((ny, nx)))
+    kap = 5.0 * np.exp(rng.standard_normal((ny, nx)))
+    pn = F.Problem(ndim=2, n=(nx, ny, 1), dx=(0.1, 0.2, 1.0),
+                   bc=("neumann", "periodic"), limiter=limiter,
+                   face_mean=face_mean)
+    pp = F.Problem(ndim=2, n=(2 * nx, ny, 1), dx=(0.1, 0.2, 1.0),
+                   bc=("periodic", "periodic"), limiter=limiter,
+                   face_mean=face_mean)
+    Dn, Rn, _ = F.diffusion_coefficient(E, rho, kap, pn)
+    Dp, Rp, _ = F.diffusion_coefficient(_mirror_double(E, 1),
+                                        _mirror_double(rho, 1),
+                                        _mirror_double(kap, 1), pp)
+    np.testing.assert_allclose(Rn, Rp[:, :nx], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(Dn, Dp[:, :nx], rtol=1e-13)
+    # and the solve: Neumann solution equals the mirrored periodic solution
+    dt = 3e-3
+    xn = F.diffusion_step(E, rho, kap, dt, pn)
+    xp = F.diffusion_step(_mirror_double(E, 1), _mirror_double(rho, 1),
+                          _mirror_double(kap, 1), dt, pp)
+    np.testing.assert_allclose(xn, xp[:, :nx], rtol=1e-12)
+
+
+def test_R_closed_form_linear_profile():
+    """E = 1 + s x with constant rho kappa: R = |s| / (rho kappa E) inside."""
+    n = 40
+    prob = _prob((n,), ["neumann"])
+    x = (np.arange(n) + 0.5) / n
+    s = 3.0
+    E = 1.0 + s * x
+    rho = np.full(n, 2.0)
+    kap = np.full(n, 1.5)
+    _, R, lam = F.diffusion_coefficient(E, rho, kap, prob)
+    Rex = s / (rho * kap * E)
+    np.testing.assert_allclose(R[2:-2], Rex[2:-2], rtol=1e-12)
+    np.testing.assert_allclose(lam[2:-2], (2 + Rex[2:-2]) /
+                               (6 + 3 * Rex[2:-2] + Rex[2:-2] ** 2),
+                               rtol=1e-12)
+
+
+def test_face_means_order_and_walls():
+    rng = np.random.default_rng(3)
+    n = (9, 8)
+    E = np.exp(0.3 * rng.standard_normal((8, 9)))
+    rho = np.exp(rng.standard_normal((8, 9)))
+    kap = np.exp(rng.standard_normal((8, 9)))
+    pa = F.Problem(ndim=2, n=(9, 8, 1), dx=(1 / 9, 1 / 8, 1),
+                   bc=("neumann", "neumann"), face_mean="arith")
+    ph = F.Problem(ndim=2, n=(9, 8, 1), dx=(1 / 9, 1 / 8, 1),
+                   bc=("neumann", "neumann"), face_mean="harmonic")
+    aa = F.face_coefficients(E, rho, kap, 0.1, pa)
+    ah = F.face_coefficients(E, rho, kap, 0.1, ph)
+    for d in range(2):
+        # harmonic mean <= arithmetic mean (AM-HM inequality)
+        assert np.all(ah[d] <= aa[d] * (1 + 1e-15))
+    # wall faces carry no flux
+    assert np.all(aa[0][:, -1] == 0) and np.all(aa[1][-1, :] == 0)
+    del n
