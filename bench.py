@@ -1,0 +1,141 @@
+"""Benchmark of the FLD radiation-energy update on one MI355X.
+
+A step is one whole split step on the 2D 1024^2 Kramers/log-normal
+workload: opacity law, flux-limited diffusion solve to a relative residual
+of 1e-8 (FP64 V-cycles), and the exchange quartic, all on the GPU through
+the C ABI.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with the throughput (cell-updates/s), the dominant
+kernel's roofline figures (HIP events around each of its launches, over the
+timed region) and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
+          "plain FP64 MG")
+
+
+def cpu_baseline(m, budget_s=30.0):
+    """Oracle (FP64, numpy/scipy) on one step of the same workload."""
+    from oracle import fldref as F
+    prob = F.problem_from_medium(m)
+    t0 = time.perf_counter()
+    F.step(m.E, m.e, m.rho, prob, m.dt, opacity=m.opacity)
+    t = time.perf_counter() - t0
+    return {"value": m.cells / t, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 split step of the same {m.n[0]}x{m.n[1]} medium "
+                      f"(opacity, exact solve by Jacobi-PCG to 1e-13, "
+                      f"exchange), {t:.1f} s, single-threaded numpy/scipy"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import media
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.solver import Stepper, make_params
+
+    m = media.config_c2(n=args.n)
+    params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    st = Stepper(params, opacity=m.opacity)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    rho, E, e = d(m.rho), d(m.E), d(m.e)
+    kap = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        st.step(m.dt, rho, kap, E, e)
+    torch.cuda.synchronize()
+    fld.fld_kernel_timing_enable(st.ctx, True)
+    fld.fld_kernel_timing_read(st.ctx)  # reset
+    cycles = []
+    res = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = st.step(m.dt, rho, kap, E, e)
+        cycles.append(s["cycles"])
+        res.append(s["rel_res_final"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = fld.fld_kernel_timing_read(st.ctx)
+    fld.fld_kernel_timing_enable(st.ctx, False)
+
+    secs = t1 - t0
+    value = m.cells * args.steps / secs
+    avg_ms = kt["ms"] / max(kt["launches"], 1)
+    bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2d-{m.n[0]}x{m.n[1]}-kramers-lognormal-fp64-plain-mg",
+            "grid": [m.n[0], m.n[1]],
+            "bc": "neumann",
+            "rtol": 1e-8,
+            "precision": "fp64",
+            "guess": "prev",
+            "dt": m.dt,
+        },
+        "vcycles_per_step": float(np.mean(cycles)),
+        "rel_res_final_max": float(np.max(res)),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kt["kernel"],
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "launches": kt["launches"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * fld.h - implicit flux-limited-diffusion (FLD) radiation-energy update on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The update is the stiff part of a split radiation-MHD step (Narechania et
+ * al., "Radiation-magnetohydrodynamics with MPI-AMRVAC using flux-limited
+ * diffusion", arXiv:2503.02764):
+ *
+ *   fld_step      diffusion: dE/dt = -div F with F = -D grad E (eq. fld_F),
+ *                 D = c lambda / (rho kappa), lambda the flux limiter of
+ *                 eq. fld_lambda with R of eq. fld_R, the gradient by the
+ *                 five-point central stencil of Sect. 3, advanced by one
+ *                 backward-Euler step and solved by geometric multigrid
+ *                 (Sect. 3 solves div F with multigrid).
+ *   fld_exchange  gas-radiation energy exchange qdot of eqs. heating/qdot,
+ *                 implicit in both the gas and the radiation energy, which
+ *                 leaves one quartic per cell (Sect. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Fields are DEVICE pointers to contiguous float64 arrays of
+ *   nx*ny*nz cells, x fastest: index i + nx*(j + ny*k).  The caller owns
+ *   them; the library never keeps a pointer past the call.
+ * - All work is enqueued on the HIP stream given to fld_setup, in stream
+ *   order.  The context is not thread-safe: one context per stream.
+ * - Code units are the caller's: c, a_rad, gamma and gas_const
+ *   (= k_B / (mu m_p), so that p = rho gas_const T, eq. ideal_gas_law) are
+ *   parameters.  e_int is the gas internal energy density p / (gamma - 1)
+ *   (eq. energy_density with v = B = 0).
+ * - Errors: host validation fails fast with FLD_ERR_INVALID_ARG and
+ *   launches nothing.  A HIP runtime failure gives FLD_ERR_DEVICE.  Every
+ *   failing call stores a message readable with fld_last_error.
+ */
+#ifndef FLD_H
+#define FLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fld_ctx fld_ctx;
+
+typedef enum {
+  FLD_OK = 0,
+  FLD_ERR_INVALID_ARG = 1,   /* bad argument; nothing was launched          */
+  FLD_ERR_WORKSPACE = 2,     /* workspace missing, too small or misaligned  */
+  FLD_ERR_DEVICE = 3,        /* a HIP call failed                           */
+  FLD_ERR_NONPHYSICAL = 4,   /* E <= 0, rho*kappa <= 0 or a non-finite input */
+  FLD_ERR_NOT_CONVERGED = 5, /* max_cycles reached; last iterate returned   */
+  FLD_ERR_MODEL = 6          /* learned-guess weights rejected              */
+} fld_status;
+
+/* Boundary condition of one side of one dimension.  Periodic must be set on
+ * both sides of a dimension.  Neumann is the paper's zero-gradient boundary
+ * (Sect. 4.1, 4.4): mirror ghost cells for the gradient (E[-1] = E[0],
+ * E[-2] = E[1]) and no flux through the boundary face. */
+typedef enum { FLD_BC_PERIODIC = 0, FLD_BC_NEUMANN = 1 } fld_bc;
+
+/* eq. fld_lambda (Levermore-Pomraning) or the diffusion value 1/3 used by
+ * the paper for its stationary shocks (Sect. 4.1). */
+typedef enum { FLD_LIMITER_LP = 0, FLD_LIMITER_DIFFUSION = 1 } fld_limiter;
+
+/* Mean of the two cell-centred D on a face. */
+typedef enum { FLD_FACE_ARITH = 0, FLD_FACE_HARMONIC = 1 } fld_face_mean;
+
+/* FP64 multigrid, or FP32 V-cycles inside an FP64 iterative refinement.
+ * The exchange is FP64 in both. */
+typedef enum { FLD_PREC_FP64 = 0, FLD_PREC_FP32_IR = 1 } fld_precision;
+
+/* Initial guess of the diffusion solve: E^n, zero, or a learned guess. */
+typedef enum { FLD_GUESS_PREV = 0, FLD_GUESS_ZERO = 1, FLD_GUESS_LEARNED = 2 } fld_guess;
+
+typedef struct {
+  int32_t ndim;          /* 1, 2 or 3                                      */
+  int32_t pad0;
+  int64_t n[3];          /* cells per dimension; unused dimensions = 1     */
+  double dx[3];          /* cell widths; unused = 1                        */
+  int32_t bc_lo[3];      /* fld_bc per dimension                           */
+  int32_t bc_hi[3];
+  double c;              /* speed of light                                 */
+  double a_rad;          /* radiation constant a_r = 4 sigma / c           */
+  double gamma;          /* adiabatic index, > 1                           */
+  double gas_const;      /* k_B / (mu m_p)                                 */
+  int32_t limiter;       /* fld_limiter                                    */
+  int32_t face_mean;     /* fld_face_mean                                  */
+  int32_t precision;     /* fld_precision                                  */
+  int32_t guess;         /* fld_guess                                      */
+  double rtol;           /* stop when |b - A x|_2 / |b|_2 <= rtol          */
+  int32_t max_cycles;    /* V-cycle cap (fine-level smoothing passes)      */
+  int32_t pre_smooth;    /* red-black Gauss-Seidel sweeps before restriction */
+  int32_t post_smooth;   /* sweeps after prolongation                      */
+  int32_t pad1;
+} fld_params;
+
+typedef struct {
+  int32_t cycles;          /* fine-level V-cycles started (the last one may
+                              stop after its pre-smoothing, where it found
+                              the residual below rtol)                     */
+  int32_t outer_iters;     /* FP64 refinement iterations (FP32_IR), else 0 */
+  int32_t guess_rejected;  /* 1 when a learned guess lost to E^n          */
+  int32_t pad;
+  int64_t flagged_cells;   /* cells with E <= 0, rho kappa <= 0 or NaN     */
+  double rel_res_initial;  /* |b - A x0| / |b|                              */
+  double rel_res_final;    /* |b - A x| / |b| of the returned E_out        */
+} fld_stats;
+
+/* Fill *p with defaults: 1D, 1 cell, periodic, c = a_rad = gas_const = 1,
+ * gamma = 5/3, LP limiter, arithmetic face mean, FP64, guess E^n,
+ * rtol 1e-8, max_cycles 50, V(2,2). */
+void fld_params_default(fld_params* p);
+
+/* Bytes of device workspace fld_setup needs for these parameters, or 0 if
+ * the parameters are invalid. */
+size_t fld_workspace_bytes(const fld_params* p);
+
+/* Validate the parameters, build the multigrid level list (every dimension
+ * halved while all sides are even and the halves are >= 3) and carve
+ * per-level buffers out of `workspace` (device memory, >= 256-byte aligned,
+ * ws_bytes >= fld_workspace_bytes(p)).  `hip_stream` is a hipStream_t (NULL:
+ * the default stream).  Launches nothing.  The context keeps `workspace`
+ * until fld_destroy; the caller keeps it alive. */
+fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
+                     void* hip_stream, fld_ctx** out);
+
+/* One backward-Euler diffusion step: E_out = A^-1 E_in, with
+ * (A x)_i = x_i + sum_faces alpha_f (x_i - x_nb), alpha_f = dt D_f / dx^2,
+ * D_f the face mean of D = c lambda / (rho kappa) computed from E_in
+ * (eqs. fld_F, fld_lambda, fld_R; gradient by the five-point stencil).
+ * Solved by V-cycles until |E_in - A E_out|_2 / |E_in|_2 <= rtol.
+ * rho, kappa, E_in: device, read only.  E_out: device, written; it may
+ * alias E_in.  stats: host pointer or NULL.
+ * Blocks the calling thread until convergence is known.  Returns
+ * FLD_ERR_NONPHYSICAL if any cell has E <= 0, rho kappa <= 0 or a
+ * non-finite input (outputs unspecified), FLD_ERR_NOT_CONVERGED after
+ * max_cycles (E_out holds the last iterate, stats the residual). */
+fld_status fld_step(fld_ctx* ctx, double dt, const double* rho,
+                    const double* kappa, const double* E_in, double* E_out,
+                    fld_stats* stats);
+
+/* Implicit gas-radiation exchange (eqs. heating, qdot) for one step dt:
+ * per cell, with beta = dt c kappa rho and S = E + e_int,
+ *   e' solves a4 e'^4 + (1 + beta) e' = e_int + beta S,
+ *   a4 = beta a_rad ((gamma - 1) / (rho gas_const))^4,
+ *   E' = S - e'  (e + E conserved per cell).
+ * E: in E*, out E^{n+1}.  e_int: in e^n, out e^{n+1}.  Device pointers.
+ * Asynchronous (stream-ordered).  FLD_ERR_INVALID_ARG for dt <= 0. */
+fld_status fld_exchange(fld_ctx* ctx, double dt, const double* rho,
+                        const double* kappa, double* E, double* e_int);
+
+/* Opacity power law of the synthetic workloads (not the paper's constant
+ * opacity): kappa = clip(k0 rho^a T^b, kmin, kmax) with
+ * T = (gamma - 1) e_int / (rho gas_const).  Device pointers; asynchronous. */
+fld_status fld_opacity_powerlaw(fld_ctx* ctx, const double* rho,
+                                const double* e_int, double k0, double a,
+                                double b, double kmin, double kmax,
+                                double* kappa);
+
+/* Per-launch timing of the dominant kernel (the finest-level smoother).
+ * When enabled, every launch of that kernel is bracketed by HIP events on
+ * the context's stream; fld_kernel_timing_read returns the summed
+ * milliseconds, the launch count and the algorithmic bytes those launches
+ * stream (each operand read or written once), then resets the counters. */
+fld_status fld_kernel_timing_enable(fld_ctx* ctx, int32_t on);
+fld_status fld_kernel_timing_read(fld_ctx* ctx, double* ms_total,
+                                  int64_t* launches, double* bytes_total,
+                                  const char** kernel_name);
+
+/* Release the context (host memory only; the workspace is the caller's). */
+void fld_destroy(fld_ctx* ctx);
+
+const char* fld_status_str(int32_t status);
+const char* fld_last_error(const fld_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLD_H */

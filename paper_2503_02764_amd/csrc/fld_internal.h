@@ -1,0 +1,109 @@
+// Internal declarations of the FLD library: grid geometry, per-level views,
+// the device-side control block and the kernel launch wrappers.
+//
+// Layout: every field is a contiguous array, x fastest
+// (idx = i + nx * (j + ny * k)).  A face coefficient alpha_d[idx] belongs to
+// the face between cell idx and its +d neighbour; along a Neumann dimension
+// the last cell's +d face is a wall and holds 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fld {
+
+constexpr int kMaxLevels = 24;
+constexpr int kBlock = 256;        // threads per block of the grid kernels
+constexpr int kReduceBlock = 1024; // threads of the single-block reductions
+
+struct Geom {
+  int ndim;
+  int n[3];    // cells per dimension (unused = 1)
+  int per[3];  // 1 if periodic along that dimension
+  int64_t N;   // cells
+};
+
+template <typename T>
+struct LevelView {
+  Geom g;
+  T* x;          // iterate (correction on coarse levels)
+  T* b;          // right-hand side (restricted residual on coarse levels)
+  const T* a[3]; // face coefficients, one array per dimension
+};
+
+// Device control block of one solve: norms, counters and the stop flag
+// that every multigrid kernel reads before doing any work.
+struct Control {
+  double bnorm2;      // |b|^2 of the finest level
+  double res_initial; // |b - A x0| / |b|
+  double res;         // relative residual of the returned iterate
+  double rtol;
+  int32_t done;       // 0 running, 1 converged, 2 cycle cap, 3 non-physical
+  int32_t cycles;
+  int32_t max_cycles;
+  int32_t flagged;    // non-physical cells seen by the coefficient kernel
+};
+
+enum DoneCode { kRunning = 0, kConverged = 1, kCapped = 2, kNonPhysical = 3 };
+
+struct CoefArgs {
+  Geom g;
+  double dx[3];
+  double dt, c;
+  int limiter;   // 0 LP, 1 diffusion
+  int face_mean; // 0 arithmetic, 1 harmonic
+};
+
+// ---- launch wrappers (kernels live in the .hip files) ----------------------
+hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
+                       const double* kappa, double* alpha0, double* alpha1,
+                       double* alpha2, double* copy_dst, double* partials,
+                       Control* ctrl, hipStream_t s);
+hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
+                          const double* const fa[3], double* const ca[3],
+                          hipStream_t s);
+hipError_t launch_finalize(int mode, const double* partials, int count,
+                           Control* ctrl, hipStream_t s);
+hipError_t launch_resid_norm(const LevelView<double>& L, double* partials,
+                             int* nblocks, const Control* ctrl, hipStream_t s);
+hipError_t launch_gs_color(const LevelView<double>& L, int color,
+                           const Control* ctrl, hipStream_t s);
+hipError_t launch_resid_restrict(const LevelView<double>& fine,
+                                 const LevelView<double>& coarse,
+                                 double* partials, int* nblocks,
+                                 const Control* ctrl, hipStream_t s);
+hipError_t launch_prolong(const LevelView<double>& coarse,
+                          const LevelView<double>& fine, const Control* ctrl,
+                          hipStream_t s);
+hipError_t launch_coarsest(const LevelView<double>& L, double* tmp,
+                           const Control* ctrl, hipStream_t s);
+hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,
+                           double gamma, double gas_const, const double* rho,
+                           const double* kappa, double* E, double* e,
+                           hipStream_t s);
+hipError_t launch_opacity(int64_t N, double gamma, double gas_const,
+                          const double* rho, const double* e, double k0,
+                          double pa, double pb, double kmin, double kmax,
+                          double* kappa, hipStream_t s);
+
+// Single-workgroup V-cycle tail: levels l0 .. L-1 (see k_tail).
+struct TailArgs {
+  int l0, L, pre, post;
+  LevelView<double> lv[kMaxLevels];
+  double* tmp;
+  Control* ctrl;
+};
+hipError_t launch_tail(const TailArgs& a, hipStream_t s);
+
+hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
+                            hipStream_t s);
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+
+// finalize modes
+enum FinalizeMode { kFinBnorm = 0, kFinInitial = 1, kFinCycle = 2 };
+
+inline int blocks_for(int64_t n, int bs = kBlock) {
+  return (int)((n + bs - 1) / bs);
+}
+
+}  // namespace fld

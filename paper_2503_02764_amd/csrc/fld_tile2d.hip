@@ -1,0 +1,260 @@
+// LDS-tiled, temporally blocked multigrid kernels for 2D levels (gfx950).
+//
+// One workgroup owns a region of RX x RY cells: an output tile plus a halo
+// of H cells on every side.  It loads x once into LDS and keeps, per cell,
+// the Gauss-Seidel weights in registers:
+//   x_new = b/d + (a_l x_l + a_r x_r + a_d x_d + a_u x_u)/d,  d = 1 + sum a.
+// It then runs NU red-black sweeps (2*NU colour passes) entirely on chip.
+// Each colour pass invalidates one more ring of the region, so after 2*NU
+// passes the cells at depth >= 2*NU are exactly what a global red-black
+// Gauss-Seidel sweep would produce; the tile interior is written back.
+//
+//   down kernel (H = 2*NU + 2): pre-smoothing, then the residual of the
+//     tile (needs one more valid ring), its restriction to the coarse level
+//     (mean of the 2x2 children, computed in registers) and, on the finest
+//     level, the block sum of r^2 for the convergence test.
+//   up kernel (H = 2*NU): x += P e_coarse (cell-centred bilinear
+//     interpolation, weights 9/16, 3/16, 3/16, 1/16), then post-smoothing.
+//
+// Thread layout: RX/2 x NPY threads; thread (px, py) owns the cell pair
+// (2px, 2px+1) in the K consecutive rows py*K .. py*K+K-1.  With the region
+// origin, H and K all even, the cell of colour c in row k of the pair is
+// (c + k) & 1 for every thread, so colour passes have no divergence and all
+// register arrays are indexed by compile-time constants; the 2x2 children
+// of a coarse cell sit in one thread's registers.
+//
+// Blocks are dispatched round-robin over the 8 XCDs; tiles are renumbered
+// so that each XCD sweeps one contiguous band of tiles and the halos that
+// neighbouring tiles share stay in that XCD's L2.
+#include "fld_internal.h"
+#include "fld_tile2d.h"
+
+namespace fld {
+
+namespace {
+
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// Map a (possibly out-of-range) coordinate onto the domain; -1 when it lies
+// beyond a Neumann wall.
+__device__ __forceinline__ int map_coord(int g, int n, int per) {
+  if (g >= 0 && g < n) return g;
+  if (!per) return -1;
+  g %= n;
+  return g < 0 ? g + n : g;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum_t(T v, T* sh, int nt) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T r = T(0);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (nt + 63) / 64; ++q) r += sh[q];
+  return r;
+}
+
+}  // namespace
+
+template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
+__global__ void __launch_bounds__(RX / 2 * NPY)
+    k_tile2d(Tile2DArgs<T> A) {
+  constexpr int NT = RX / 2 * NPY;
+  constexpr int RY = NPY * K;
+  constexpr int H = DOWN ? 2 * NU + 2 : 2 * NU;
+  constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
+  constexpr int LX = RX + 2, LY = RY + 2;  // LDS copy with a zero border
+  static_assert(K % 2 == 0 && RX % 2 == 0 && TX > 0 && TY > 0, "tile shape");
+  __shared__ T xs[LY * LX];
+  __shared__ double red[NT / 64 + 1];
+  if (A.ctrl->done != kRunning) return;
+
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
+  const int gx0 = txi * TX - H, gy0 = tyi * TY - H;  // region origin (even)
+  const int px = threadIdx.x % (RX / 2), py = threadIdx.x / (RX / 2);
+  const int nx = A.g.n[0], ny = A.g.n[1];
+  const int perx = A.g.per[0], pery = A.g.per[1];
+
+  // zero border of the LDS copy
+  for (int i = threadIdx.x; i < 2 * LX + 2 * RY; i += NT) {
+    int o;
+    if (i < LX) o = i;
+    else if (i < 2 * LX) o = (LY - 1) * LX + (i - LX);
+    else if (i < 2 * LX + RY) o = (1 + i - 2 * LX) * LX;
+    else o = (1 + i - 2 * LX - RY) * LX + LX - 1;
+    xs[o] = T(0);
+  }
+
+  T bp[K][2], wl[K][2], wr[K][2], wd[K][2], wu[K][2];
+  T dn[DOWN ? K : 1][2];
+  (void)dn;
+  const int mx0 = map_coord(gx0 + 2 * px, nx, perx);
+  const int mx1 = map_coord(gx0 + 2 * px + 1, nx, perx);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int ly = py * K + k;
+    const int my = map_coord(gy0 + ly, ny, pery);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int mx = q ? mx1 : mx0;
+      T xv = T(0), bv = T(0), al = T(0), ar = T(0), ad = T(0), au = T(0);
+      if (mx >= 0 && my >= 0) {
+        const int64_t gi = (int64_t)my * nx + mx;
+        if (!A.zero_init) xv = A.x[gi];
+        bv = A.b[gi];
+        ar = A.ax[gi];
+        au = A.ay[gi];
+        if (mx > 0) al = A.ax[gi - 1];
+        else if (perx) al = A.ax[gi + nx - 1];
+        if (my > 0) ad = A.ay[gi - nx];
+        else if (pery) ad = A.ay[gi + (int64_t)(ny - 1) * nx];
+        if (!DOWN && A.ce) {
+          // bilinear prolongation of the coarse correction
+          const int ncx = A.gc.n[0], ncy = A.gc.n[1];
+          const int I = mx >> 1, J = my >> 1;
+          int I2 = (mx & 1) ? I + 1 : I - 1;
+          int J2 = (my & 1) ? J + 1 : J - 1;
+          if (I2 < 0) I2 = perx ? ncx - 1 : 0;
+          if (I2 >= ncx) I2 = perx ? 0 : ncx - 1;
+          if (J2 < 0) J2 = pery ? ncy - 1 : 0;
+          if (J2 >= ncy) J2 = pery ? 0 : ncy - 1;
+          const T e00 = A.ce[(int64_t)J * ncx + I];
+          const T e10 = A.ce[(int64_t)J * ncx + I2];
+          const T e01 = A.ce[(int64_t)J2 * ncx + I];
+          const T e11 = A.ce[(int64_t)J2 * ncx + I2];
+          xv += T(0.5625) * e00 + T(0.1875) * e10 + T(0.1875) * e01 +
+                T(0.0625) * e11;
+        }
+      }
+      const T d = T(1) + al + ar + ad + au;
+      const T inv = T(1) / d;
+      bp[k][q] = bv * inv;
+      wl[k][q] = al * inv;
+      wr[k][q] = ar * inv;
+      wd[k][q] = ad * inv;
+      wu[k][q] = au * inv;
+      if constexpr (DOWN) dn[k][q] = d;
+      xs[(ly + 1) * LX + 2 * px + q + 1] = xv;
+    }
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int pass = 0; pass < 2 * NU; ++pass) {
+    const int c = pass & 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = (c + k) & 1;
+      const int ly = py * K + k;
+      const int o = (ly + 1) * LX + 2 * px + q + 1;
+      const T xn = bp[k][q] + wl[k][q] * xs[o - 1] + wr[k][q] * xs[o + 1] +
+                   wd[k][q] * xs[o - LX] + wu[k][q] * xs[o + LX];
+      xs[o] = xn;
+    }
+    __syncthreads();
+  }
+
+  // write the tile interior (cells of this tile inside the domain)
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int ly = py * K + k;
+    const int gy = gy0 + ly;
+    if (ly < H || ly >= H + TY || gy >= ny) continue;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int lx = 2 * px + q;
+      const int gx = gx0 + lx;
+      if (lx < H || lx >= H + TX || gx >= nx) continue;
+      A.x[(int64_t)gy * nx + gx] = xs[(ly + 1) * LX + lx + 1];
+    }
+  }
+
+  if constexpr (DOWN) {
+    double r2 = 0.0;
+    const int ncx = A.gc.n[0];
+    const int lx = 2 * px;
+    const int gx = gx0 + lx;
+    const bool colok = lx >= H && lx < H + TX && gx < nx;
+#pragma unroll
+    for (int k = 0; k < K; k += 2) {
+      const int ly = py * K + k;
+      const int gy = gy0 + ly;
+      if (!colok || ly < H || ly >= H + TY || gy >= ny) continue;
+      T r[2][2];
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int o = (ly + kk + 1) * LX + lx + q + 1;
+          const T xc = xs[o];
+          r[kk][q] = dn[k + kk][q] *
+                     (bp[k + kk][q] + wl[k + kk][q] * xs[o - 1] +
+                      wr[k + kk][q] * xs[o + 1] + wd[k + kk][q] * xs[o - LX] +
+                      wu[k + kk][q] * xs[o + LX] - xc);
+        }
+      const T s = (r[0][0] + r[0][1]) + (r[1][0] + r[1][1]);
+      A.cb[(int64_t)(gy >> 1) * ncx + (gx >> 1)] = T(0.25) * s;
+      r2 += (double)r[0][0] * r[0][0] + (double)r[0][1] * r[0][1] +
+            (double)r[1][0] * r[1][0] + (double)r[1][1] * r[1][1];
+    }
+    if (A.partials) {
+      const double t = block_sum_t<double>(r2, red, NT);
+      if (threadIdx.x == 0) A.partials[tile] = t;
+    }
+  }
+}
+
+template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
+static hipError_t launch_one(const Tile2DArgs<T>& a0, hipStream_t s,
+                             int* nblocks) {
+  constexpr int RY = NPY * K;
+  constexpr int H = DOWN ? 2 * NU + 2 : 2 * NU;
+  constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
+  Tile2DArgs<T> a = a0;
+  a.tiles_x = (a.g.n[0] + TX - 1) / TX;
+  a.tiles_y = (a.g.n[1] + TY - 1) / TY;
+  const int nb = a.tiles_x * a.tiles_y;
+  if (nblocks) *nblocks = nb;
+  hipLaunchKernelGGL((k_tile2d<T, RX, NPY, K, NU, DOWN>), dim3(nb),
+                     dim3(RX / 2 * NPY), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
+                         hipStream_t s, int* nblocks) {
+  if (down) {
+    switch (nu) {
+      case 1: return launch_one<T, 64, 8, 6, 1, true>(a, s, nblocks);
+      case 2: return launch_one<T, 64, 8, 6, 2, true>(a, s, nblocks);
+      case 3: return launch_one<T, 64, 8, 6, 3, true>(a, s, nblocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (nu) {
+    case 1: return launch_one<T, 64, 8, 6, 1, false>(a, s, nblocks);
+    case 2: return launch_one<T, 64, 8, 6, 2, false>(a, s, nblocks);
+    case 3: return launch_one<T, 64, 8, 6, 3, false>(a, s, nblocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int tile2d_blocks(const Geom& g, int nu, bool down) {
+  constexpr int RX = 64, RY = 48;
+  const int H = down ? 2 * nu + 2 : 2 * nu;
+  const int TX = RX - 2 * H, TY = RY - 2 * H;
+  return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
+}
+
+template hipError_t launch_tile2d<double>(const Tile2DArgs<double>&, int, bool,
+                                          hipStream_t, int*);
+
+}  // namespace fld

@@ -1,0 +1,267 @@
+"""ctypes binding of libfld.so (include/fld.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors are checked (device, dtype,
+contiguity, size) and passed as device pointers; every step of the update
+runs in the HIP kernels of the library.  There is no CPU fallback: if the
+library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libfld.so")
+
+FLD_OK = 0
+FLD_ERR_INVALID_ARG = 1
+FLD_ERR_WORKSPACE = 2
+FLD_ERR_DEVICE = 3
+FLD_ERR_NONPHYSICAL = 4
+FLD_ERR_NOT_CONVERGED = 5
+FLD_ERR_MODEL = 6
+
+FLD_BC_PERIODIC = 0
+FLD_BC_NEUMANN = 1
+FLD_LIMITER_LP = 0
+FLD_LIMITER_DIFFUSION = 1
+FLD_FACE_ARITH = 0
+FLD_FACE_HARMONIC = 1
+FLD_PREC_FP64 = 0
+FLD_PREC_FP32_IR = 1
+FLD_GUESS_PREV = 0
+FLD_GUESS_ZERO = 1
+FLD_GUESS_LEARNED = 2
+
+EXPORTED = [
+    "fld_params_default", "fld_workspace_bytes", "fld_setup", "fld_step",
+    "fld_exchange", "fld_opacity_powerlaw", "fld_kernel_timing_enable",
+    "fld_kernel_timing_read", "fld_destroy", "fld_status_str",
+    "fld_last_error",
+]
+
+
+class fld_params(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
+        ("c", ctypes.c_double), ("a_rad", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("gas_const", ctypes.c_double),
+        ("limiter", ctypes.c_int32), ("face_mean", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
+        ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32),
+        ("pre_smooth", ctypes.c_int32), ("post_smooth", ctypes.c_int32),
+        ("pad1", ctypes.c_int32),
+    ]
+
+
+class fld_stats(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+        ("guess_rejected", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("flagged_cells", ctypes.c_int64),
+        ("rel_res_initial", ctypes.c_double),
+        ("rel_res_final", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class FldError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libfld.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with "
+            "`python -m paper_2503_02764_amd.build` (there is no fallback)")
+    # Import torch first: its HIP runtime then serves this library too
+    # (same SONAME), so device pointers and streams are shared.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P, V, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double
+    lib.fld_params_default.argtypes = [P(fld_params)]
+    lib.fld_params_default.restype = None
+    lib.fld_workspace_bytes.argtypes = [P(fld_params)]
+    lib.fld_workspace_bytes.restype = ctypes.c_size_t
+    lib.fld_setup.argtypes = [P(fld_params), V, ctypes.c_size_t, V, P(V)]
+    lib.fld_setup.restype = ctypes.c_int
+    lib.fld_step.argtypes = [V, D, V, V, V, V, P(fld_stats)]
+    lib.fld_step.restype = ctypes.c_int
+    lib.fld_exchange.argtypes = [V, D, V, V, V, V]
+    lib.fld_exchange.restype = ctypes.c_int
+    lib.fld_opacity_powerlaw.argtypes = [V, V, V, D, D, D, D, D, V]
+    lib.fld_opacity_powerlaw.restype = ctypes.c_int
+    lib.fld_kernel_timing_enable.argtypes = [V, ctypes.c_int32]
+    lib.fld_kernel_timing_enable.restype = ctypes.c_int
+    lib.fld_kernel_timing_read.argtypes = [V, P(D), P(ctypes.c_int64), P(D),
+                                           P(ctypes.c_char_p)]
+    lib.fld_kernel_timing_read.restype = ctypes.c_int
+    lib.fld_destroy.argtypes = [V]
+    lib.fld_destroy.restype = None
+    lib.fld_status_str.argtypes = [ctypes.c_int32]
+    lib.fld_status_str.restype = ctypes.c_char_p
+    lib.fld_last_error.argtypes = [V]
+    lib.fld_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(status):
+    return load().fld_status_str(status).decode()
+
+
+def _check(ctx_ptr, status):
+    if status != FLD_OK:
+        msg = load().fld_last_error(ctx_ptr).decode()
+        raise FldError(status, msg)
+
+
+def fld_params_default(**overrides):
+    p = fld_params()
+    load().fld_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k in ("n", "dx", "bc_lo", "bc_hi"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def fld_workspace_bytes(params):
+    return int(load().fld_workspace_bytes(ctypes.byref(params)))
+
+
+def _ptr(t, name, numel=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Ctx:
+    """An fld_ctx* with the workspace tensor it borrows and its stream."""
+
+    def __init__(self, ptr, params, workspace, stream):
+        self.ptr = ptr
+        self.params = params
+        self.workspace = workspace
+        self.stream = stream
+        self.cells = int(params.n[0] * params.n[1] * params.n[2])
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.fld_destroy(self.ptr)
+            self.ptr = None
+
+
+def fld_setup(params, workspace=None, stream=None):
+    """Create a context; allocates the workspace tensor if none is given."""
+    import torch
+    lib = load()
+    need = fld_workspace_bytes(params)
+    if need == 0:
+        out = ctypes.c_void_p()
+        st = lib.fld_setup(ctypes.byref(params), None, 0, None,
+                           ctypes.byref(out))
+        _check(None, st)
+        raise FldError(FLD_ERR_INVALID_ARG, "invalid parameters")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_void_p()
+    st = lib.fld_setup(ctypes.byref(params),
+                       _ptr(workspace, "workspace", dtype=torch.uint8),
+                       workspace.numel(), ctypes.c_void_p(stream.cuda_stream),
+                       ctypes.byref(out))
+    _check(None, st)
+    return Ctx(out, params, workspace, stream)
+
+
+def fld_step(ctx, dt, rho, kappa, E_in, E_out, stats=True, check=True):
+    """Diffusion step; returns (status, stats dict or None)."""
+    import torch
+    n = ctx.cells
+    s = fld_stats() if stats else None
+    st = load().fld_step(ctx.ptr, float(dt),
+                         _ptr(rho, "rho", n, torch.float64),
+                         _ptr(kappa, "kappa", n, torch.float64),
+                         _ptr(E_in, "E_in", n, torch.float64),
+                         _ptr(E_out, "E_out", n, torch.float64),
+                         ctypes.byref(s) if s is not None else None)
+    if check:
+        _check(ctx.ptr, st)
+    return st, (s.as_dict() if s is not None else None)
+
+
+def fld_exchange(ctx, dt, rho, kappa, E, e_int, check=True):
+    import torch
+    n = ctx.cells
+    st = load().fld_exchange(ctx.ptr, float(dt),
+                             _ptr(rho, "rho", n, torch.float64),
+                             _ptr(kappa, "kappa", n, torch.float64),
+                             _ptr(E, "E", n, torch.float64),
+                             _ptr(e_int, "e_int", n, torch.float64))
+    if check:
+        _check(ctx.ptr, st)
+    return st
+
+
+def fld_opacity_powerlaw(ctx, rho, e_int, k0, a, b, kmin, kmax, kappa,
+                         check=True):
+    import torch
+    n = ctx.cells
+    st = load().fld_opacity_powerlaw(ctx.ptr,
+                                     _ptr(rho, "rho", n, torch.float64),
+                                     _ptr(e_int, "e_int", n, torch.float64),
+                                     float(k0), float(a), float(b),
+                                     float(kmin), float(kmax),
+                                     _ptr(kappa, "kappa", n, torch.float64))
+    if check:
+        _check(ctx.ptr, st)
+    return st
+
+
+def fld_kernel_timing_enable(ctx, on=True):
+    _check(ctx.ptr, load().fld_kernel_timing_enable(ctx.ptr, 1 if on else 0))
+
+
+def fld_kernel_timing_read(ctx):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    by = ctypes.c_double()
+    name = ctypes.c_char_p()
+    _check(ctx.ptr, load().fld_kernel_timing_read(
+        ctx.ptr, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+        ctypes.byref(name)))
+    return dict(ms=ms.value, launches=n.value, bytes=by.value,
+                kernel=name.value.decode())
+
+
+def fld_destroy(ctx):
+    if ctx.ptr:
+        load().fld_destroy(ctx.ptr)
+        ctx.ptr = None

@@ -1,0 +1,117 @@
+"""C-ABI contract checks that need no GPU.
+
+The library loads, exports every function declared in include/fld.h, and
+its host-side validation rejects bad parameters before touching a device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2503_02764_amd import fld
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fld\w*)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fld.load()
+    names = _declared("fld.h")
+    assert "fld_step" in names and "fld_exchange" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(fld.EXPORTED) == sorted(names)
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof/offsetof of a header struct, as the C compiler lays it out."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fld.h"',
+             "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    for f in fields:
+        lines.append(f'  printf("%zu\\n", offsetof({struct}, {f}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("cls,struct", [(fld.fld_params, "fld_params"),
+                                        (fld.fld_stats, "fld_stats")])
+def test_struct_layout_matches_header(cls, struct, tmp_path):
+    names = [n for n, _ in cls._fields_]
+    got = _c_layout(struct, names, tmp_path)
+    assert got[0] == ctypes.sizeof(cls)
+    for name, off in zip(names, got[1:]):
+        assert getattr(cls, name).offset == off, name
+
+
+def test_defaults_and_workspace():
+    p = fld.fld_params_default()
+    assert p.ndim == 1 and p.rtol == 1e-8 and p.max_cycles == 50
+    assert p.pre_smooth == 2 and p.post_smooth == 2
+    p = fld.fld_params_default(ndim=2, n=(1024, 1024, 1),
+                               dx=(1 / 1024, 1 / 1024, 1),
+                               bc_lo=(1, 1, 1), bc_hi=(1, 1, 1))
+    ws = fld.fld_workspace_bytes(p)
+    # level-0 face arrays + rhs copy, plus coarse levels: a bit over
+    # 3 x 8 MiB and well under 5 x 8 MiB
+    assert 3 * 8 * 2 ** 20 < ws < 5 * 8 * 2 ** 20
+
+
+@pytest.mark.parametrize("field,value", [
+    ("ndim", 0), ("ndim", 4), ("c", 0.0), ("a_rad", -1.0), ("gamma", 1.0),
+    ("gas_const", 0.0), ("rtol", 0.0), ("rtol", 1.5), ("max_cycles", 0),
+    ("limiter", 7), ("face_mean", 3), ("precision", 9), ("guess", 9),
+])
+def test_invalid_params_rejected_on_host(field, value):
+    p = fld.fld_params_default(ndim=1, n=(64, 1, 1), dx=(1 / 64, 1, 1))
+    setattr(p, field, value)
+    assert fld.fld_workspace_bytes(p) == 0
+    lib = fld.load()
+    out = ctypes.c_void_p()
+    st = lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, None,
+                       ctypes.byref(out))
+    assert st == fld.FLD_ERR_INVALID_ARG
+    assert lib.fld_last_error(None).decode()
+
+
+def test_bc_and_shape_validation():
+    lib = fld.load()
+    out = ctypes.c_void_p()
+    bad = [
+        dict(ndim=1, n=(8, 1, 1), bc_lo=(0, 0, 0), bc_hi=(1, 0, 0)),  # half-periodic
+        dict(ndim=1, n=(1, 1, 1), bc_lo=(1, 0, 0), bc_hi=(1, 0, 0)),  # 1-cell wall
+        dict(ndim=1, n=(8, 2, 1)),  # unused side != 1
+        dict(ndim=2, n=(8, 8, 1), dx=(0.1, -1, 1)),
+    ]
+    for kw in bad:
+        p = fld.fld_params_default(**kw)
+        st = lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
+                           None, ctypes.byref(out))
+        assert st == fld.FLD_ERR_INVALID_ARG, kw
+    # workspace checks come after parameter checks
+    p = fld.fld_params_default(ndim=1, n=(64, 1, 1), dx=(1 / 64, 1, 1))
+    assert lib.fld_setup(ctypes.byref(p), None, 1 << 30, None,
+                         ctypes.byref(out)) == fld.FLD_ERR_WORKSPACE
+    assert lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256 + 8), 1 << 30,
+                         None, ctypes.byref(out)) == fld.FLD_ERR_WORKSPACE
+    assert lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256), 16, None,
+                         ctypes.byref(out)) == fld.FLD_ERR_WORKSPACE
+
+
+def test_status_strings():
+    assert fld.status_str(fld.FLD_OK) == "FLD_OK"
+    assert fld.status_str(fld.FLD_ERR_NOT_CONVERGED) == "FLD_ERR_NOT_CONVERGED"

@@ -1,0 +1,275 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Diffusion solves run to rtol 1e-12, which by lambda_min(A) >= 1 bounds the
+relative error by rtol * sqrt(N) |b| / sum(b) (a factor near 1 for these
+media); the bar is relative L2 <= 1e-10 against the oracle's exact solve.
+The exchange is checked per cell to a few ulp of the conserved total S.
+"""
+import numpy as np
+import pytest
+
+import media
+from oracle import fldref as F
+from gpu_common import announce, dev, host, params_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TINY = [
+    ((8,), ("periodic",)), ((64,), ("neumann",)), ((5,), ("periodic",)),
+    ((6,), ("neumann",)), ((48,), ("periodic",)),
+    ((8, 8), ("periodic", "periodic")), ((32, 32), ("neumann", "neumann")),
+    ((24, 20), ("periodic", "neumann")), ((12, 7), ("neumann", "neumann")),
+    ((4, 4, 4), ("periodic", "periodic", "periodic")),
+    ((12, 12, 12), ("periodic", "periodic", "neumann")),
+    ((8, 6, 10), ("neumann", "periodic", "neumann")),
+]
+
+
+def _solve_gpu(m, **kw):
+    from paper_2503_02764_amd import fld
+    ctx = fld.fld_setup(params_for(m, **kw))
+    rho, kap, E = dev(m.rho), dev(m.kappa), dev(m.E)
+    out = dev(np.zeros_like(m.E))
+    st, stats = fld.fld_step(ctx, m.dt, rho, kap, E, out)
+    return host(out), stats
+
+
+@pytest.mark.parametrize("n,bc", TINY)
+@pytest.mark.parametrize("limiter,face", [("lp", "arith"),
+                                          ("diffusion", "harmonic")])
+def test_tiny_solve_vs_dense(n, bc, limiter, face):
+    m = media.random_small_medium(sum(n) + len(n), n, bc, limiter, face)
+    announce(f"tiny solve n={n} bc={bc} {limiter}/{face}")
+    x, stats = _solve_gpu(m, rtol=1e-12)
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt,
+                           F.problem_from_medium(m), method="dense")
+    assert stats["rel_res_final"] <= 1e-12
+    assert rel_l2(x, ref) <= 1e-10, (stats, rel_l2(x, ref))
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_c2_media_solve_vs_oracle(n):
+    from paper_2503_02764_amd import fld
+    m = media.config_c2(n=n)
+    prob = F.problem_from_medium(m)
+    kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    announce(f"c2 media n={n}")
+    ctx = fld.fld_setup(params_for(m, rtol=1e-12))
+    rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
+    kap_d = dev(np.zeros_like(m.E))
+    o = m.opacity
+    fld.fld_opacity_powerlaw(ctx, rho, e, o["k0"], o["a"], o["b"], o["kmin"],
+                             o["kmax"], kap_d)
+    np.testing.assert_allclose(host(kap_d), kap, rtol=1e-13)
+    out = dev(np.zeros_like(m.E))
+    _, stats = fld.fld_step(ctx, m.dt, rho, kap_d, E, out)
+    ref = F.diffusion_step(m.E, m.rho, kap, m.dt, prob)
+    assert rel_l2(host(out), ref) <= 1e-10, stats
+    # exchange on the same cells
+    fld.fld_exchange(ctx, m.dt, rho, kap_d, out, e)
+    En, en = F.exchange(ref, m.e, m.rho, kap, m.dt, prob)
+    S = ref + m.e
+    assert np.abs(host(e) - en).max() <= 1e-10 * S.max()
+
+
+def test_c1_ten_steps_vs_oracle():
+    from paper_2503_02764_amd.solver import Stepper
+    m = media.config_c1()
+    prob = F.problem_from_medium(m)
+    announce("c1 ten steps")
+    st = Stepper(params_for(m, rtol=1e-12))
+    rho, kap, E, e = dev(m.rho), dev(m.kappa), dev(m.E), dev(m.e)
+    En, en = m.E.copy(), m.e.copy()
+    for _ in range(m.steps):
+        st.step(m.dt, rho, kap, E, e)
+        En, en, _ = F.step(En, en, m.rho, prob, m.dt, kappa=m.kappa)
+    assert rel_l2(host(E), En) <= 1e-10
+    assert rel_l2(host(e), en) <= 1e-10
+    # mirror symmetry of the symmetric pulse is kept
+    x = host(E)
+    assert np.abs(x - x[::-1]).max() <= 1e-10 * x.max()
+
+
+def test_exchange_per_cell_vs_oracle():
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.solver import make_params
+    rng = np.random.default_rng(9)
+    n = 100_000
+    rho = np.exp(2 * rng.standard_normal(n))
+    kap = np.exp(3 * rng.standard_normal(n))
+    E = np.exp(3 * rng.standard_normal(n))
+    e = np.exp(3 * rng.standard_normal(n))
+    prob = F.Problem(ndim=1, n=(n, 1, 1), dx=(1, 1, 1), bc=("periodic",),
+                     gamma=1.4, gas_const=0.8, a_rad=1.3, c=2.0)
+    announce("exchange per cell 1e5")
+    ctx = fld.fld_setup(make_params(1, (n,), (1.0,), ("periodic",), c=2.0,
+                                    a_rad=1.3, gamma=1.4, gas_const=0.8))
+    for dt in (1e-3, 1.0, 1e3):
+        Ed, ed = dev(E), dev(e)
+        fld.fld_exchange(ctx, dt, dev(rho), dev(kap), Ed, ed)
+        En, en = F.exchange(E, e, rho, kap, dt, prob)
+        S = E + e
+        assert np.all(np.abs(host(ed) - en) <= 8 * np.spacing(S)), dt
+        assert np.all(np.abs(host(Ed) - En) <= 8 * np.spacing(S)), dt
+        # per-cell conservation on the GPU
+        assert np.all(np.abs(host(Ed) + host(ed) - S) <= 2 * np.spacing(S))
+
+
+def test_equilibrium_preserved_on_gpu():
+    """Uniform T_gas = T_rad with random rho, kappa: nothing moves.
+
+    The diffusion solve needs no V-cycle and returns E^n bit for bit; the
+    exchange moves each cell by at most a couple of ulp of e + E per step.
+    """
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.solver import Stepper
+    n = (64, 48)
+    m = media.random_small_medium(5, n, ("neumann", "periodic"))
+    T = 1.7
+    m.E = np.full(m.rho.shape, T ** 4)
+    m.e = m.rho * T / (m.gamma - 1)
+    announce("equilibrium preserved")
+    st = Stepper(params_for(m, rtol=1e-12))
+    E, e = dev(m.E), dev(m.e)
+    rho, kap = dev(m.rho), dev(m.kappa)
+    out = dev(np.zeros_like(m.E))
+    _, stats = fld.fld_step(st.ctx, m.dt, rho, kap, E, out)
+    assert stats["cycles"] == 0 and np.array_equal(host(out), m.E)
+    S = m.E + m.e
+    for k in range(100):
+        stats = st.step(m.dt, rho, kap, E, e)
+        assert stats["cycles"] == 0
+    ulp = np.spacing(S)
+    assert np.all(np.abs(host(E) - m.E) <= 2 * 100 * ulp)
+    assert np.all(np.abs(host(e) - m.e) <= 2 * 100 * ulp)
+    assert np.all(np.abs(host(E) + host(e) - S) <= 2 * 100 * ulp)
+
+
+def test_solve_conserves_total_energy():
+    m = media.random_small_medium(21, (96, 80), ("neumann", "periodic"))
+    announce("global conservation")
+    x, stats = _solve_gpu(m, rtol=1e-12)
+    assert abs(x.sum() - m.E.sum()) <= 1e-11 * m.E.sum()
+
+
+def test_alias_and_determinism():
+    from paper_2503_02764_amd import fld
+    m = media.config_c2(n=128)
+    prob = F.problem_from_medium(m)
+    kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    announce("alias/determinism")
+    ctx = fld.fld_setup(params_for(m, rtol=1e-10))
+    rho, kd = dev(m.rho), dev(kap)
+    outs = []
+    for _ in range(3):
+        E = dev(m.E)
+        out = dev(np.zeros_like(m.E))
+        fld.fld_step(ctx, m.dt, rho, kd, E, out)
+        outs.append(host(out))
+    E = dev(m.E)
+    fld.fld_step(ctx, m.dt, rho, kd, E, E)  # in place
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert np.array_equal(host(E), outs[0])
+
+
+def test_zero_guess_same_solution():
+    m = media.random_small_medium(3, (40, 40), ("neumann", "neumann"))
+    announce("zero guess")
+    x0, _ = _solve_gpu(m, rtol=1e-12)
+    x1, s1 = _solve_gpu(m, rtol=1e-12, guess="zero")
+    assert s1["rel_res_initial"] == pytest.approx(1.0)
+    assert rel_l2(x1, x0) <= 1e-10
+
+
+def test_error_paths():
+    from paper_2503_02764_amd import fld
+    m = media.random_small_medium(4, (32, 32), ("neumann", "neumann"))
+    announce("error paths")
+    ctx = fld.fld_setup(params_for(m, rtol=1e-14, max_cycles=1))
+    rho, kap, E = dev(m.rho), dev(m.kappa), dev(m.E)
+    out = dev(np.zeros_like(m.E))
+    st, stats = fld.fld_step(ctx, m.dt, rho, kap, E, out, check=False)
+    assert st == fld.FLD_ERR_NOT_CONVERGED
+    assert stats["cycles"] == 1 and stats["rel_res_final"] > 1e-14
+    ctx = fld.fld_setup(params_for(m, rtol=1e-10))
+    Ebad = m.E.copy()
+    Ebad[3, 4] = -1.0
+    st, stats = fld.fld_step(ctx, m.dt, rho, kap, dev(Ebad), out, check=False)
+    assert st == fld.FLD_ERR_NONPHYSICAL and stats["flagged_cells"] == 1
+    kbad = m.kappa.copy()
+    kbad[0, 0] = np.nan
+    kbad[7, 7] = 0.0
+    st, stats = fld.fld_step(ctx, m.dt, rho, dev(kbad), E, out, check=False)
+    assert st == fld.FLD_ERR_NONPHYSICAL and stats["flagged_cells"] == 2
+    # the context stays usable after an error
+    st, stats = fld.fld_step(ctx, m.dt, rho, kap, E, out)
+    assert st == fld.FLD_OK
+    with pytest.raises(fld.FldError):
+        fld.fld_step(ctx, -1.0, rho, kap, E, out)
+
+
+def test_c2_full_size_bench_configuration():
+    """1024^2 at the benchmark's rtol: oracle-side residual and sampled cells.
+
+    The oracle assembles its own operator from the same inputs and measures
+    the GPU iterate's residual; the exchange is checked cell by cell on a
+    sample (it is pointwise, so the oracle can compute single cells).
+    """
+    from paper_2503_02764_amd.solver import Stepper
+    m = media.config_c2(n=1024)
+    prob = F.problem_from_medium(m)
+    kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    announce("c2 full size 1024^2")
+    st = Stepper(params_for(m, rtol=1e-8), opacity=m.opacity)
+    rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
+    kap_d = dev(np.zeros_like(m.E))
+    from paper_2503_02764_amd import fld
+    o = m.opacity
+    fld.fld_opacity_powerlaw(st.ctx, rho, e, o["k0"], o["a"], o["b"],
+                             o["kmin"], o["kmax"], kap_d)
+    Estar = dev(np.zeros_like(m.E))
+    _, stats = fld.fld_step(st.ctx, m.dt, rho, kap_d, E, Estar)
+    x = host(Estar)
+    alphas = F.face_coefficients(m.E, m.rho, kap, m.dt, prob)
+    rr = F.relative_residual(x, m.E, alphas, prob)
+    assert rr <= 1.0e-8 * 1.001, (rr, stats)
+    assert abs(rr / stats["rel_res_final"] - 1) < 1e-3
+    fld.fld_exchange(st.ctx, m.dt, rho, kap_d, Estar, e)
+    idx = np.random.default_rng(0).choice(x.size, 4096, replace=False)
+    xs = x.ravel()[idx]
+    En, en = F.exchange(xs, m.e.ravel()[idx], m.rho.ravel()[idx],
+                        kap.ravel()[idx], m.dt, prob)
+    S = xs + m.e.ravel()[idx]
+    assert np.all(np.abs(host(e).ravel()[idx] - en) <= 8 * np.spacing(S))
+    assert np.all(np.abs(host(Estar).ravel()[idx] - En) <= 8 * np.spacing(S))
+
+
+TILED_2D = [
+    ((96, 80), ("periodic", "periodic")),
+    ((200, 136), ("neumann", "neumann")),
+    ((384, 192), ("periodic", "neumann")),
+    ((130, 66), ("neumann", "periodic")),
+]
+
+
+@pytest.mark.parametrize("n,bc", TILED_2D)
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_2d_tiled_levels_vs_oracle(n, bc, nu):
+    """Grids large enough for the LDS-tiled kernels, ragged tile edges."""
+    m = media.random_small_medium(n[0] + 7 * n[1], n, bc, contrast=1.5)
+    announce(f"tiled 2d n={n} bc={bc} nu={nu}")
+    x, stats = _solve_gpu(m, rtol=1e-12, pre_smooth=nu, post_smooth=nu)
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt,
+                           F.problem_from_medium(m))
+    assert rel_l2(x, ref) <= 1e-10, stats
+
+
+@pytest.mark.parametrize("n,bc", TILED_2D[:2] + [((12, 12, 12),
+                                                  ("periodic",) * 3)])
+def test_fast_and_simple_kernel_paths_agree(n, bc, monkeypatch):
+    m = media.random_small_medium(3 * n[0] + n[1], n, bc)
+    announce(f"fast vs simple n={n}")
+    x_fast, s_fast = _solve_gpu(m, rtol=1e-12)
+    monkeypatch.setenv("FLD_KERNEL_PATH", "simple")
+    x_simple, s_simple = _solve_gpu(m, rtol=1e-12)
+    assert rel_l2(x_fast, x_simple) <= 1e-10, (s_fast, s_simple)
