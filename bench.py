@@ -60,47 +60,59 @@ def main():
     from paper_2503_02764_amd.solver import Stepper, make_params
 
     m = media.config_c2(n=args.n)
-    params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    st = Stepper(params, opacity=m.opacity)
 
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
-    rho, E, e = d(m.rho), d(m.E), d(m.e)
-    kap = torch.empty_like(rho)
-    for _ in range(args.warmup):
-        st.step(m.dt, rho, kap, E, e)
-    torch.cuda.synchronize()
-    fld.fld_kernel_timing_enable(st.ctx, True)
-    fld.fld_kernel_timing_read(st.ctx)  # reset
-    cycles = []
-    res = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s = st.step(m.dt, rho, kap, E, e)
-        cycles.append(s["cycles"])
-        res.append(s["rel_res_final"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = fld.fld_kernel_timing_read(st.ctx)
-    fld.fld_kernel_timing_enable(st.ctx, False)
+    def run(precision, steps, warmup, timed_kernel=True):
+        """warmup + timed steps of one solver variant from the initial state"""
+        params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
+                             precision=precision)
+        st = Stepper(params, opacity=m.opacity)
+        rho, E, e = d(m.rho), d(m.E), d(m.e)
+        kap = torch.empty_like(rho)
+        for _ in range(warmup):
+            st.step(m.dt, rho, kap, E, e)
+        torch.cuda.synchronize()
+        fld.fld_kernel_timing_enable(st.ctx, timed_kernel)
+        fld.fld_kernel_timing_read(st.ctx)  # reset
+        cycles, outer, res = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s = st.step(m.dt, rho, kap, E, e)
+            cycles.append(s["cycles"])
+            outer.append(s["outer_iters"])
+            res.append(s["rel_res_final"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = fld.fld_kernel_timing_read(st.ctx)
+        fld.fld_kernel_timing_enable(st.ctx, False)
+        secs = t1 - t0
+        return dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
+                    vcycles_per_step=float(np.mean(cycles)),
+                    outer_per_step=float(np.mean(outer)),
+                    rel_res_final_max=float(np.max(res)), kernel=kt,
+                    E=E.cpu().numpy())
 
-    secs = t1 - t0
-    value = m.cells * args.steps / secs
+    base = run("fp64", args.steps, args.warmup)
+    mixed = run("fp32_ir", args.steps, args.warmup)
+    kt = base["kernel"]
     avg_ms = kt["ms"] / max(kt["launches"], 1)
     bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    diff = float(np.linalg.norm(mixed["E"] - base["E"]) /
+                 np.linalg.norm(base["E"]))
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": base["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs * 1e3 / args.steps,
+        "ms_per_step": base["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -115,8 +127,19 @@ def main():
             "guess": "prev",
             "dt": m.dt,
         },
-        "vcycles_per_step": float(np.mean(cycles)),
-        "rel_res_final_max": float(np.max(res)),
+        "vcycles_per_step": base["vcycles_per_step"],
+        "rel_res_final_max": base["rel_res_final_max"],
+        "variants": {
+            "fp32_vcycles_fp64_refinement": {
+                "value": mixed["value"],
+                "ms_per_step": mixed["ms_per_step"],
+                "vcycles_per_step": mixed["vcycles_per_step"],
+                "outer_per_step": mixed["outer_per_step"],
+                "rel_res_final_max": mixed["rel_res_final_max"],
+                "speedup_vs_fp64": mixed["value"] / base["value"],
+                "rel_l2_vs_fp64_after_steps": diff,
+            },
+        },
         "roofline": {
             "bound": "hbm",
             "kernel": kt["kernel"],

@@ -1,10 +1,19 @@
 // C ABI of the FLD library: parameter validation, workspace layout, the
 // multigrid level list and the host driver of the V-cycles.
 //
-// The solve runs entirely in the kernels of fld_kernels.hip.  The host only
-// enqueues launches on the caller's stream and, once per batch of V-cycles,
-// reads back the 48-byte control block to learn whether the device-side
-// stop test (relative residual <= rtol, or the cycle cap) has fired.
+// The solve runs entirely in the kernels of fld_kernels.hip and
+// fld_tile2d.hip.  The host only enqueues launches on the caller's stream
+// and, once per batch of cycles, reads back the control block to learn
+// whether the device-side stop test (relative residual <= rtol, or the
+// cycle cap) has fired.
+//
+// Two solvers:
+//   FP64:     V-cycles on the FP64 operator, residual tested after the
+//             finest-level pre-smoothing of every cycle.
+//   FP32_IR:  iterative refinement. Each outer iteration computes the FP64
+//             residual r = b - A x (and tests it), solves A e = r with
+//             `inner` FP32 V-cycles from e = 0 on FP32 copies of the face
+//             coefficients, and adds e to the FP64 iterate.
 #include "fld.h"
 #include "fld_internal.h"
 #include "fld_tile2d.h"
@@ -14,12 +23,24 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
-#include <cstring>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
 using namespace fld;
+
+namespace {
+
+template <typename T>
+struct Levels {
+  T* x[kMaxLevels] = {};
+  T* b[kMaxLevels] = {};
+  T* a[kMaxLevels][3] = {};
+  T* tmp = nullptr;  // coarsest-level scratch (global-memory tail only)
+};
+
+}  // namespace
 
 struct fld_ctx {
   fld_params p;
@@ -28,22 +49,24 @@ struct fld_ctx {
   size_t ws_bytes = 0;
   int L = 0;
   Geom geom[kMaxLevels];
-  double* x[kMaxLevels] = {};
-  double* b[kMaxLevels] = {};
-  double* a[kMaxLevels][3] = {};
+  Levels<double> h64;          // FP64 hierarchy (level 0 only in FP32_IR)
+  Levels<float> h32;           // FP32 hierarchy (FP32_IR only)
   double* bcopy = nullptr;     // level-0 rhs copy when E_out aliases E_in
   double* partials = nullptr;  // block partial sums
-  double* tmp = nullptr;       // coarsest-level scratch
   Control* ctrl = nullptr;     // device control block
-  Control* host_ctrl = nullptr;  // pinned host mirror
-  int last_cycles = 4;
+  Control* host_ctrl = nullptr;  // pinned host mirror, written by the GPU
+  Control* host_ctrl_dev = nullptr;  // its device-side address
+  bool mixed = false;
+  int inner = 2;               // FP32 V-cycles per refinement iteration
+  int last_batch = 4;          // cycles (or outer iterations) last step
   std::string err;
-  // timing of the dominant kernel (finest-level smoother)
+  // timing of the dominant kernel (finest-level down pass)
   bool timing = false;
   double t_ms = 0.0;
   int64_t t_launches = 0;
   double t_bytes = 0.0;
-  std::vector<hipEvent_t> ev;  // pool, used in (start, stop) pairs
+  const char* t_name = "none";
+  std::vector<hipEvent_t> ev;    // pool, used in (start, stop) pairs
   std::vector<double> ev_bytes;  // algorithmic bytes of each timed launch
   size_t ev_used = 0;
   bool fast = true;  // tiled kernels + single-workgroup tail
@@ -74,18 +97,23 @@ fld_status fail(fld_ctx* ctx, fld_status st, const char* fmt, ...) {
       return fail(ctx, FLD_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+#define FLD_TRY(expr)              \
+  do {                             \
+    fld_status s_ = (expr);        \
+    if (s_ != FLD_OK) return s_;   \
+  } while (0)
+
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxCoarsestCells = 1 << 16;
-constexpr int64_t kTailCells = 4096;  // levels this small go to k_tail
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Plan {
   int L = 0;
   Geom g[kMaxLevels];
-  size_t off_a[kMaxLevels][3];
-  size_t off_x[kMaxLevels], off_b[kMaxLevels];
-  size_t off_bcopy = 0, off_partials = 0, off_tmp = 0, off_ctrl = 0;
+  size_t a64[kMaxLevels][3] = {}, x64[kMaxLevels] = {}, b64[kMaxLevels] = {};
+  size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
+  size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0;
   int64_t n_partials = 0;
   size_t total = 0;
 };
@@ -134,7 +162,8 @@ std::string validate(const fld_params* p) {
     return "gas_const must be > 0";
   if (p->limiter < 0 || p->limiter > 1) return "unknown limiter";
   if (p->face_mean < 0 || p->face_mean > 1) return "unknown face mean";
-  if (p->precision != FLD_PREC_FP64) return "precision: only FLD_PREC_FP64 is built";
+  if (p->precision != FLD_PREC_FP64 && p->precision != FLD_PREC_FP32_IR)
+    return "unknown precision";
   if (p->guess != FLD_GUESS_PREV && p->guess != FLD_GUESS_ZERO)
     return "guess: only FLD_GUESS_PREV and FLD_GUESS_ZERO are built";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
@@ -172,14 +201,23 @@ void make_plan(const fld_params* p, Plan* P) {
     return r;
   };
   const int nd = p->ndim;
+  const bool mixed = p->precision == FLD_PREC_FP32_IR;
   for (int l = 0; l < P->L; ++l) {
     const size_t cells = (size_t)P->g[l].N;
-    for (int d = 0; d < 3; ++d)
-      P->off_a[l][d] = d < nd ? take(cells * sizeof(double)) : 0;
-    P->off_x[l] = l > 0 ? take(cells * sizeof(double)) : 0;
-    P->off_b[l] = l > 0 ? take(cells * sizeof(double)) : 0;
+    if (l == 0 || !mixed) {
+      for (int d = 0; d < nd; ++d) P->a64[l][d] = take(cells * 8);
+      if (l > 0) {
+        P->x64[l] = take(cells * 8);
+        P->b64[l] = take(cells * 8);
+      }
+    }
+    if (mixed) {
+      for (int d = 0; d < nd; ++d) P->a32[l][d] = take(cells * 4);
+      P->x32[l] = take(cells * 4);
+      P->b32[l] = take(cells * 4);
+    }
   }
-  P->off_bcopy = take((size_t)P->g[0].N * sizeof(double));
+  P->bcopy = take((size_t)P->g[0].N * 8);
   int64_t nparts = blocks_for(P->g[0].N);
   if (p->ndim == 2)
     for (int nu = 1; nu <= 3; ++nu) {
@@ -187,18 +225,19 @@ void make_plan(const fld_params* p, Plan* P) {
       if (t > nparts) nparts = t;
     }
   P->n_partials = nparts + 64;
-  P->off_partials = take((size_t)P->n_partials * sizeof(double));
-  P->off_tmp = take((size_t)P->g[P->L - 1].N * sizeof(double));
-  P->off_ctrl = take(sizeof(Control));
+  P->partials = take((size_t)P->n_partials * 8);
+  P->tmp = take((size_t)P->g[P->L - 1].N * 8);
+  P->ctrl = take(sizeof(Control));
   P->total = o;
 }
 
-LevelView<double> view(fld_ctx* c, int l) {
-  LevelView<double> v;
+template <typename T>
+LevelView<T> view(const fld_ctx* c, const Levels<T>& H, int l) {
+  LevelView<T> v;
   v.g = c->geom[l];
-  v.x = c->x[l];
-  v.b = c->b[l];
-  for (int d = 0; d < 3; ++d) v.a[d] = c->a[l][d];
+  v.x = H.x[l];
+  v.b = H.b[l];
+  for (int d = 0; d < 3; ++d) v.a[d] = H.a[l][d];
   return v;
 }
 
@@ -211,12 +250,12 @@ hipEvent_t next_event(fld_ctx* c) {
   return c->ev[c->ev_used++];
 }
 
-// Event pair around a launch of the timed kernel (level 0, down pass).
+// Event pair around one launch of the timed kernel.
 struct TimedLaunch {
   fld_ctx* c;
   hipEvent_t e1 = nullptr;
   fld_status st = FLD_OK;
-  TimedLaunch(fld_ctx* cc, bool on, double bytes) : c(cc) {
+  TimedLaunch(fld_ctx* cc, bool on, double bytes, const char* name) : c(cc) {
     if (!on || !c->timing) return;
     hipEvent_t e0 = next_event(c);
     e1 = next_event(c);
@@ -226,6 +265,7 @@ struct TimedLaunch {
       return;
     }
     c->ev_bytes.push_back(bytes);
+    c->t_name = name;
     if (hipEventRecord(e0, c->stream) != hipSuccess)
       st = fail(c, FLD_ERR_DEVICE, "hipEventRecord failed");
   }
@@ -236,113 +276,145 @@ struct TimedLaunch {
   }
 };
 
-// Simple path: one launch per colour pass.
-fld_status smooth_simple(fld_ctx* c, int l, int sweeps) {
-  LevelView<double> v = view(c, l);
-  const double bytes = (double)c->geom[l].N * (8.0 + 4.0 + 4.0 + 8.0 * c->p.ndim);
-  for (int s = 0; s < sweeps; ++s)
-    for (int color = 0; color < 2; ++color) {
-      TimedLaunch t(c, l == 0, bytes);
-      if (t.st != FLD_OK) return t.st;
-      HIP_TRY(c, launch_gs_color(v, color, c->ctrl, c->stream));
-      fld_status st = t.close();
-      if (st != FLD_OK) return st;
-    }
-  return FLD_OK;
-}
-
-bool tile_level(const fld_ctx* c) {
+bool tile_path(const fld_ctx* c) {
   return c->fast && c->p.ndim == 2 && c->p.pre_smooth >= 1 &&
          c->p.pre_smooth <= 3 && c->p.post_smooth >= 1 &&
          c->p.post_smooth <= 3;
 }
 
-TailArgs tail_args(fld_ctx* c, int l0) {
-  TailArgs t;
-  t.l0 = l0;
-  t.L = c->L;
-  t.pre = c->p.pre_smooth;
-  t.post = c->p.post_smooth;
-  for (int l = 0; l < c->L; ++l) t.lv[l] = view(c, l);
-  t.tmp = c->tmp;
-  t.ctrl = c->ctrl;
-  return t;
+template <typename T>
+fld_status fill_zero(fld_ctx* c, T* x, int64_t n);
+
+template <>
+fld_status fill_zero<double>(fld_ctx* c, double* x, int64_t n) {
+  HIP_TRY(c, launch_fill(x, n, 0.0, c->stream));
+  return FLD_OK;
 }
 
-// down pass on level l (< tail level): pre-smoothing, residual, restriction
-fld_status down(fld_ctx* c, int l) {
+template <>
+fld_status fill_zero<float>(fld_ctx* c, float* x, int64_t n) {
+  HIP_TRY(c, launch_fill32(x, n, c->stream));
+  return FLD_OK;
+}
+
+// Simple path: one launch per colour pass.
+template <typename T>
+fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps) {
+  LevelView<T> v = view(c, H, l);
+  for (int s = 0; s < sweeps; ++s)
+    for (int color = 0; color < 2; ++color)
+      HIP_TRY(c, launch_gs_color<T>(v, color, c->ctrl, c->stream));
+  return FLD_OK;
+}
+
+// Down pass on level l (above the tail): pre-smoothing, residual,
+// restriction.  `zero_init`: x starts at zero.  On the finest FP64 level
+// the residual norm feeds the stop test.
+template <typename T>
+fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
+  const bool norm = (sizeof(T) == 8) && l == 0;
   int nb = 0;
-  if (tile_level(c)) {
-    Tile2DArgs<double> a{};
+  if (tile_path(c)) {
+    Tile2DArgs<T> a{};
     a.g = c->geom[l];
-    a.x = c->x[l];
-    a.b = c->b[l];
-    a.ax = c->a[l][0];
-    a.ay = c->a[l][1];
+    a.x = H.x[l];
+    a.b = H.b[l];
+    a.ax = H.a[l][0];
+    a.ay = H.a[l][1];
     a.gc = c->geom[l + 1];
-    a.cb = c->b[l + 1];
+    a.cb = H.b[l + 1];
     a.ce = nullptr;
-    a.partials = l == 0 ? c->partials : nullptr;
-    a.zero_init = l > 0;
+    a.partials = norm ? c->partials : nullptr;
+    a.zero_init = zero_init;
     a.ctrl = c->ctrl;
-    // x, b, two face arrays read; x written; the coarse rhs written
-    const double bytes = (double)c->geom[l].N * (8.0 * 5.0 + 8.0 / 4.0);
-    TimedLaunch t(c, l == 0, bytes);
-    if (t.st != FLD_OK) return t.st;
-    HIP_TRY(c, launch_tile2d<double>(a, c->p.pre_smooth, true, c->stream, &nb));
-    fld_status st = t.close();
-    if (st != FLD_OK) return st;
+    // x (unless zero), b, two face arrays read; x and the coarse rhs written
+    const double w = sizeof(T);
+    const double bytes = (double)c->geom[l].N *
+                         (w * (zero_init ? 4.0 : 5.0) + w / 4.0);
+    TimedLaunch t(c, l == 0, bytes,
+                  sizeof(T) == 8 ? "k_tile2d<double,down>" : "k_tile2d<float,down>");
+    FLD_TRY(t.st);
+    HIP_TRY(c, launch_tile2d<T>(a, c->p.pre_smooth, true, c->stream, &nb));
+    FLD_TRY(t.close());
   } else {
-    fld_status st = smooth_simple(c, l, c->p.pre_smooth);
-    if (st != FLD_OK) return st;
-    HIP_TRY(c, launch_resid_restrict(view(c, l), view(c, l + 1),
-                                     l == 0 ? c->partials : nullptr, &nb,
-                                     c->ctrl, c->stream));
+    if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
+    FLD_TRY(smooth_simple<T>(c, H, l, c->p.pre_smooth));
+    HIP_TRY(c, launch_resid_restrict<T>(view(c, H, l), view(c, H, l + 1),
+                                        norm ? c->partials : nullptr, &nb,
+                                        c->ctrl, c->stream));
   }
-  if (l == 0)
+  if (norm)
     HIP_TRY(c, launch_finalize(kFinCycle, c->partials, nb, c->ctrl, c->stream));
   return FLD_OK;
 }
 
-// up pass on level l: prolongation of level l+1 and post-smoothing
-fld_status up(fld_ctx* c, int l) {
-  if (tile_level(c)) {
-    Tile2DArgs<double> a{};
+// Up pass on level l: prolongation of level l+1 and post-smoothing.
+template <typename T>
+fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
+  if (tile_path(c)) {
+    Tile2DArgs<T> a{};
     a.g = c->geom[l];
-    a.x = c->x[l];
-    a.b = c->b[l];
-    a.ax = c->a[l][0];
-    a.ay = c->a[l][1];
+    a.x = H.x[l];
+    a.b = H.b[l];
+    a.ax = H.a[l][0];
+    a.ay = H.a[l][1];
     a.gc = c->geom[l + 1];
     a.cb = nullptr;
-    a.ce = c->x[l + 1];
+    a.ce = H.x[l + 1];
     a.partials = nullptr;
     a.zero_init = 0;
     a.ctrl = c->ctrl;
     int nb = 0;
-    HIP_TRY(c, launch_tile2d<double>(a, c->p.post_smooth, false, c->stream, &nb));
+    HIP_TRY(c, launch_tile2d<T>(a, c->p.post_smooth, false, c->stream, &nb));
     return FLD_OK;
   }
-  HIP_TRY(c, launch_prolong(view(c, l + 1), view(c, l), c->ctrl, c->stream));
-  return smooth_simple(c, l, c->p.post_smooth);
+  HIP_TRY(c, launch_prolong<T>(view(c, H, l + 1), view(c, H, l), c->ctrl,
+                               c->stream));
+  return smooth_simple<T>(c, H, l, c->p.post_smooth);
 }
 
-fld_status vcycle(fld_ctx* c) {
-  fld_status st;
+template <typename T>
+TailArgs<T> tail_args(fld_ctx* c, const Levels<T>& H, int l0, bool whole) {
+  TailArgs<T> t;
+  t.l0 = l0;
+  t.L = c->L;
+  t.pre = c->p.pre_smooth;
+  t.post = c->p.post_smooth;
+  t.whole = whole;
+  t.zero = !whole;
+  for (int l = 0; l < c->L; ++l) t.lv[l] = view(c, H, l);
+  t.tmp = H.tmp;
+  t.ctrl = c->ctrl;
+  return t;
+}
+
+// One V-cycle.  `zero_first`: the finest iterate starts at zero (the FP32
+// correction of a refinement iteration).
+template <typename T>
+fld_status vcycle(fld_ctx* c, const Levels<T>& H, bool zero_first) {
   if (c->L == 1 && !c->fast) {
-    HIP_TRY(c, launch_coarsest(view(c, 0), c->tmp, c->ctrl, c->stream));
-    int nb = 0;
-    HIP_TRY(c, launch_resid_norm(view(c, 0), c->partials, &nb, c->ctrl,
-                                 c->stream));
-    HIP_TRY(c, launch_finalize(kFinCycle, c->partials, nb, c->ctrl, c->stream));
+    if (zero_first) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
+    HIP_TRY(c, launch_coarsest<T>(view(c, H, 0), H.tmp, c->ctrl, c->stream));
+    if (sizeof(T) == 8) {
+      int nb = 0;
+      HIP_TRY(c, launch_resid_norm<T>(view(c, H, 0), c->partials, &nb, c->ctrl,
+                                      c->stream));
+      HIP_TRY(c, launch_finalize(kFinCycle, c->partials, nb, c->ctrl, c->stream));
+    }
     return FLD_OK;
   }
-  const int l0 = c->tail_l0;
+  const int l0 = c->fast ? c->tail_l0 : c->L - 1;
   for (int l = 0; l < l0; ++l)
-    if ((st = down(c, l)) != FLD_OK) return st;
-  HIP_TRY(c, launch_tail(tail_args(c, l0), c->stream));
-  for (int l = l0 - 1; l >= 0; --l)
-    if ((st = up(c, l)) != FLD_OK) return st;
+    FLD_TRY(down<T>(c, H, l, l > 0 || zero_first));
+  if (!c->fast) {
+    // reference path: coarsest Jacobi, one launch per level otherwise
+    HIP_TRY(c, launch_coarsest<T>(view(c, H, l0), H.tmp, c->ctrl, c->stream));
+  } else {
+    TailArgs<T> ta = tail_args<T>(c, H, l0, false);
+    ta.zero = l0 > 0 || zero_first;
+    HIP_TRY(c, launch_tail<T>(ta, c->stream));
+  }
+  for (int l = l0 - 1; l >= 0; --l) FLD_TRY(up<T>(c, H, l));
   return FLD_OK;
 }
 
@@ -357,6 +429,68 @@ fld_status collect_timing(fld_ctx* c) {
   }
   c->ev_used = 0;
   c->ev_bytes.clear();
+  return FLD_OK;
+}
+
+// The kernels that decide the stop flag also write the control block into
+// host-visible pinned memory, so reading it needs only the stream sync.
+fld_status read_control(fld_ctx* c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FLD_OK;
+}
+
+// FP64 V-cycles until the device stop flag is set.
+fld_status solve_fp64(fld_ctx* c) {
+  int nb = 0;
+  HIP_TRY(c, launch_resid_norm<double>(view(c, c->h64, 0), c->partials, &nb,
+                                       c->ctrl, c->stream));
+  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl, c->stream));
+  if (c->fast && c->tail_l0 == 0) {
+    // the whole problem fits one workgroup: one launch runs every cycle
+    HIP_TRY(c, launch_tail<double>(tail_args<double>(c, c->h64, 0, true),
+                                   c->stream));
+    return read_control(c);
+  }
+  int enqueued = 0;
+  int batch = c->last_batch < 1 ? 1 : c->last_batch;
+  for (;;) {
+    if (batch > c->p.max_cycles - enqueued) batch = c->p.max_cycles - enqueued;
+    for (int k = 0; k < batch; ++k)
+      FLD_TRY(vcycle<double>(c, c->h64, false));
+    enqueued += batch;
+    FLD_TRY(read_control(c));
+    if (c->host_ctrl->done != kRunning || enqueued >= c->p.max_cycles) break;
+    batch = 2;
+  }
+  if (c->host_ctrl->done == kConverged) c->last_batch = c->host_ctrl->cycles;
+  return FLD_OK;
+}
+
+// FP32 V-cycles inside an FP64 iterative refinement.
+fld_status solve_mixed(fld_ctx* c) {
+  const Geom& g0 = c->geom[0];
+  int enqueued = 0;
+  int batch = c->last_batch < 1 ? 1 : c->last_batch;
+  const int max_outer = c->p.max_cycles / c->inner + 2;
+  for (;;) {
+    for (int k = 0; k < batch; ++k) {
+      int nb = 0;
+      HIP_TRY(c, launch_resid_to32(view(c, c->h64, 0), c->h32.b[0],
+                                   c->partials, &nb, c->ctrl, c->stream));
+      HIP_TRY(c, launch_finalize(kFinOuter, c->partials, nb, c->ctrl, c->stream));
+      for (int i = 0; i < c->inner; ++i)
+        FLD_TRY(vcycle<float>(c, c->h32, i == 0));
+      HIP_TRY(c, launch_correct(g0.N, c->h64.x[0], c->h32.x[0], c->ctrl,
+                                c->stream));
+    }
+    enqueued += batch;
+    FLD_TRY(read_control(c));
+    if (c->host_ctrl->done != kRunning || enqueued >= max_outer) break;
+    batch = 1;
+  }
+  if (c->host_ctrl->done == kRunning) c->host_ctrl->done = kCapped;
+  if (c->host_ctrl->done == kConverged)
+    c->last_batch = c->host_ctrl->outer + 1;
   return FLD_OK;
 }
 
@@ -419,27 +553,37 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
   c->L = P.L;
+  c->mixed = p->precision == FLD_PREC_FP32_IR;
+  char* w = c->ws;
   for (int l = 0; l < P.L; ++l) {
     c->geom[l] = P.g[l];
-    for (int d = 0; d < 3; ++d)
-      c->a[l][d] = d < p->ndim ? (double*)(c->ws + P.off_a[l][d]) : nullptr;
-    c->x[l] = l > 0 ? (double*)(c->ws + P.off_x[l]) : nullptr;
-    c->b[l] = l > 0 ? (double*)(c->ws + P.off_b[l]) : nullptr;
+    const bool has64 = l == 0 || !c->mixed;
+    for (int d = 0; d < p->ndim; ++d) {
+      c->h64.a[l][d] = has64 ? (double*)(w + P.a64[l][d]) : nullptr;
+      c->h32.a[l][d] = c->mixed ? (float*)(w + P.a32[l][d]) : nullptr;
+    }
+    c->h64.x[l] = (has64 && l > 0) ? (double*)(w + P.x64[l]) : nullptr;
+    c->h64.b[l] = (has64 && l > 0) ? (double*)(w + P.b64[l]) : nullptr;
+    c->h32.x[l] = c->mixed ? (float*)(w + P.x32[l]) : nullptr;
+    c->h32.b[l] = c->mixed ? (float*)(w + P.b32[l]) : nullptr;
   }
   const char* path = getenv("FLD_KERNEL_PATH");
   c->fast = !(path && strcmp(path, "simple") == 0);
   c->tail_l0 = c->L - 1;
   for (int l = 0; l < c->L; ++l)
-    if (c->geom[l].N <= kTailCells) {
+    if (c->geom[l].N <= kTailLdsCells) {
       c->tail_l0 = l;
       break;
     }
-  c->bcopy = (double*)(c->ws + P.off_bcopy);
-  c->partials = (double*)(c->ws + P.off_partials);
-  c->tmp = (double*)(c->ws + P.off_tmp);
-  c->ctrl = (Control*)(c->ws + P.off_ctrl);
+  c->bcopy = (double*)(w + P.bcopy);
+  c->partials = (double*)(w + P.partials);
+  c->h64.tmp = (double*)(w + P.tmp);
+  c->h32.tmp = (float*)(w + P.tmp);
+  c->ctrl = (Control*)(w + P.ctrl);
   hipError_t he = hipHostMalloc((void**)&c->host_ctrl, sizeof(Control),
-                                hipHostMallocDefault);
+                                hipHostMallocMapped | hipHostMallocCoherent);
+  if (he == hipSuccess)
+    he = hipHostGetDevicePointer((void**)&c->host_ctrl_dev, c->host_ctrl, 0);
   if (he != hipSuccess) {
     delete c;
     return fail(nullptr, FLD_ERR_DEVICE,
@@ -462,11 +606,12 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
   const bool aliased = (E_in == E_out);
   const Geom& g0 = c->geom[0];
   // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it)
-  c->x[0] = E_out;
-  c->b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
+  c->h64.x[0] = E_out;
+  c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
   double* copy_dst = aliased ? c->bcopy
                              : (c->p.guess == FLD_GUESS_ZERO ? nullptr : E_out);
-  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles, c->stream));
+  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles, c->inner,
+                             c->host_ctrl_dev, c->stream));
   CoefArgs A;
   A.g = g0;
   for (int d = 0; d < 3; ++d) A.dx[d] = c->p.dx[d];
@@ -474,48 +619,34 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
   A.c = c->p.c;
   A.limiter = c->p.limiter;
   A.face_mean = c->p.face_mean;
-  HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->a[0][0], c->a[0][1],
-                         c->a[0][2], copy_dst, c->partials, c->ctrl,
-                         c->stream));
+  HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
+                         copy_dst, c->partials, c->ctrl, c->stream));
   HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, blocks_for(g0.N), c->ctrl,
                              c->stream));
   for (int l = 0; l + 1 < c->L; ++l) {
-    const double* fa[3] = {c->a[l][0], c->a[l][1], c->a[l][2]};
-    double* ca[3] = {c->a[l + 1][0], c->a[l + 1][1], c->a[l + 1][2]};
-    HIP_TRY(c, launch_coarsen(c->geom[l], c->geom[l + 1], fa, ca, c->stream));
+    if (c->mixed) {
+      const float* fa[3] = {c->h32.a[l][0], c->h32.a[l][1], c->h32.a[l][2]};
+      float* ca[3] = {c->h32.a[l + 1][0], c->h32.a[l + 1][1],
+                      c->h32.a[l + 1][2]};
+      HIP_TRY(c, launch_coarsen<float>(c->geom[l], c->geom[l + 1], fa, ca,
+                                       c->stream));
+    } else {
+      const double* fa[3] = {c->h64.a[l][0], c->h64.a[l][1], c->h64.a[l][2]};
+      double* ca[3] = {c->h64.a[l + 1][0], c->h64.a[l + 1][1],
+                       c->h64.a[l + 1][2]};
+      HIP_TRY(c, launch_coarsen<double>(c->geom[l], c->geom[l + 1], fa, ca,
+                                        c->stream));
+    }
   }
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
-  int nb = 0;
-  HIP_TRY(c, launch_resid_norm(view(c, 0), c->partials, &nb, c->ctrl, c->stream));
-  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl, c->stream));
-
-  int enqueued = 0;
-  int chunk = c->last_cycles < 1 ? 1 : c->last_cycles;
-  fld_status st;
-  if (c->fast && c->tail_l0 == 0) {
-    // the whole problem fits one workgroup: one launch runs every cycle
-    HIP_TRY(c, launch_tail(tail_args(c, 0), c->stream));
-    chunk = 0;
-    enqueued = c->p.max_cycles;
-  }
-  while (true) {
-    if (chunk > c->p.max_cycles - enqueued) chunk = c->p.max_cycles - enqueued;
-    for (int k = 0; k < chunk; ++k)
-      if ((st = vcycle(c)) != FLD_OK) return st;
-    enqueued += chunk;
-    HIP_TRY(c, hipMemcpyAsync(c->host_ctrl, c->ctrl, sizeof(Control),
-                              hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->host_ctrl->done != kRunning || enqueued >= c->p.max_cycles) break;
-    chunk = 2;
-  }
-  if ((st = collect_timing(c)) != FLD_OK) return st;
+  FLD_TRY(c->mixed ? solve_mixed(c) : solve_fp64(c));
+  FLD_TRY(collect_timing(c));
   const Control& h = *c->host_ctrl;
-  if (h.done == kConverged || h.done == kCapped) c->last_cycles = h.cycles;
   if (stats) {
     memset(stats, 0, sizeof *stats);
     stats->cycles = h.cycles;
+    stats->outer_iters = c->mixed ? h.outer : 0;
     stats->flagged_cells = h.flagged;
     stats->rel_res_initial = h.res_initial;
     stats->rel_res_final = h.res;
@@ -563,6 +694,7 @@ fld_status fld_kernel_timing_enable(fld_ctx* c, int32_t on) {
   if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   c->timing = on != 0;
   c->ev_used = 0;
+  c->ev_bytes.clear();
   return FLD_OK;
 }
 
@@ -573,7 +705,7 @@ fld_status fld_kernel_timing_read(fld_ctx* c, double* ms_total,
   if (ms_total) *ms_total = c->t_ms;
   if (launches) *launches = c->t_launches;
   if (bytes_total) *bytes_total = c->t_bytes;
-  if (kernel_name) *kernel_name = "k_gs_color";
+  if (kernel_name) *kernel_name = c->t_name;
   c->t_ms = 0.0;
   c->t_launches = 0;
   c->t_bytes = 0.0;

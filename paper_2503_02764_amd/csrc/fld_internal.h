@@ -42,6 +42,9 @@ struct Control {
   int32_t cycles;
   int32_t max_cycles;
   int32_t flagged;    // non-physical cells seen by the coefficient kernel
+  int32_t outer;      // refinement iterations (corrections applied)
+  int32_t inner;      // FP32 V-cycles per refinement iteration
+  Control* mirror;    // device address of the host-visible copy (or null)
 };
 
 enum DoneCode { kRunning = 0, kConverged = 1, kCapped = 2, kNonPhysical = 3 };
@@ -56,27 +59,11 @@ struct CoefArgs {
 
 // ---- launch wrappers (kernels live in the .hip files) ----------------------
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
-                       const double* kappa, double* alpha0, double* alpha1,
-                       double* alpha2, double* copy_dst, double* partials,
+                       const double* kappa, double* const a64[3],
+                       float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s);
-hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
-                          const double* const fa[3], double* const ca[3],
-                          hipStream_t s);
 hipError_t launch_finalize(int mode, const double* partials, int count,
                            Control* ctrl, hipStream_t s);
-hipError_t launch_resid_norm(const LevelView<double>& L, double* partials,
-                             int* nblocks, const Control* ctrl, hipStream_t s);
-hipError_t launch_gs_color(const LevelView<double>& L, int color,
-                           const Control* ctrl, hipStream_t s);
-hipError_t launch_resid_restrict(const LevelView<double>& fine,
-                                 const LevelView<double>& coarse,
-                                 double* partials, int* nblocks,
-                                 const Control* ctrl, hipStream_t s);
-hipError_t launch_prolong(const LevelView<double>& coarse,
-                          const LevelView<double>& fine, const Control* ctrl,
-                          hipStream_t s);
-hipError_t launch_coarsest(const LevelView<double>& L, double* tmp,
-                           const Control* ctrl, hipStream_t s);
 hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,
                            double gamma, double gas_const, const double* rho,
                            const double* kappa, double* E, double* e,
@@ -85,22 +72,61 @@ hipError_t launch_opacity(int64_t N, double gamma, double gas_const,
                           const double* rho, const double* e, double k0,
                           double pa, double pb, double kmin, double kmax,
                           double* kappa, hipStream_t s);
+hipError_t launch_resid_to32(const LevelView<double>& L, float* r32,
+                             double* partials, int* nblocks,
+                             const Control* ctrl, hipStream_t s);
+hipError_t launch_correct(int64_t N, double* x, const float* e,
+                          const Control* ctrl, hipStream_t s);
+
+template <typename T>
+hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
+                          const T* const fa[3], T* const ca[3], hipStream_t s);
+template <typename T>
+hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
+                             int* nblocks, const Control* ctrl, hipStream_t s);
+template <typename T>
+hipError_t launch_gs_color(const LevelView<T>& L, int color,
+                           const Control* ctrl, hipStream_t s);
+template <typename T>
+hipError_t launch_resid_restrict(const LevelView<T>& fine,
+                                 const LevelView<T>& coarse, double* partials,
+                                 int* nblocks, const Control* ctrl,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(const LevelView<T>& coarse, const LevelView<T>& fine,
+                          const Control* ctrl, hipStream_t s);
+template <typename T>
+hipError_t launch_coarsest(const LevelView<T>& L, T* tmp, const Control* ctrl,
+                           hipStream_t s);
 
 // Single-workgroup V-cycle tail: levels l0 .. L-1 (see k_tail).
+template <typename T>
 struct TailArgs {
   int l0, L, pre, post;
-  LevelView<double> lv[kMaxLevels];
-  double* tmp;
+  int whole;  // run the cycle loop and the stop test (FP64, l0 == 0)
+  int zero;   // x(l0) starts at zero (else it is read)
+  LevelView<T> lv[kMaxLevels];
+  T* tmp;
   Control* ctrl;
 };
-hipError_t launch_tail(const TailArgs& a, hipStream_t s);
+template <typename T>
+hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
+// LDS variant (fld_tail.hip); *used = false when the levels do not fit.
+template <typename T>
+hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used);
 
 hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
-                            hipStream_t s);
+                            int inner, Control* mirror, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill32(float* x, int64_t n, hipStream_t s);
+
+// Levels up to this many cells run in the single-workgroup tail, in LDS.
+constexpr int64_t kTailLdsCells = 1024;
 
 // finalize modes
-enum FinalizeMode { kFinBnorm = 0, kFinInitial = 1, kFinCycle = 2 };
+// kFinOuter: FP64 residual of a refinement iteration (first call also sets
+// the initial residual); counts outer iterations.
+enum FinalizeMode { kFinBnorm = 0, kFinInitial = 1, kFinCycle = 2, kFinOuter = 3 };
 
 inline int blocks_for(int64_t n, int bs = kBlock) {
   return (int)((n + bs - 1) / bs);

@@ -10,6 +10,7 @@
 // the waves of a block, then one single-block pass over the block partials.
 #include "fld_internal.h"
 
+#include <limits.h>
 #include <math.h>
 
 namespace fld {
@@ -128,8 +129,12 @@ __device__ __forceinline__ T residual_value(const LevelView<T>& L,
 // control block
 // ---------------------------------------------------------------------------
 
-__global__ void k_ctrl_init(Control* ctrl, double rtol, int max_cycles) {
+__global__ void k_ctrl_init(Control* ctrl, double rtol, int max_cycles,
+                            int inner, Control* mirror) {
   if (threadIdx.x == 0) {
+    ctrl->mirror = mirror;
+    ctrl->outer = 0;
+    ctrl->inner = inner;
     ctrl->bnorm2 = 0.0;
     ctrl->res_initial = 0.0;
     ctrl->res = 0.0;
@@ -142,9 +147,21 @@ __global__ void k_ctrl_init(Control* ctrl, double rtol, int max_cycles) {
 }
 
 hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
-                            hipStream_t s) {
+                            int inner, Control* mirror, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, ctrl, rtol,
-                     max_cycles);
+                     max_cycles, inner, mirror);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_fill32(float* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = 0.0f;
+}
+
+hipError_t launch_fill32(float* x, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill32, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n);
   return hipGetLastError();
 }
 
@@ -160,7 +177,11 @@ hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Single-block reduction of the block partials and the stop decision.
+__device__ __forceinline__ void finalize_update(int mode, double s,
+                                                Control* ctrl);
+
+// Single-block reduction of the block partials and the stop decision; the
+// control block is then copied to its host-visible mirror.
 __global__ void __launch_bounds__(kReduceBlock)
     k_finalize(int mode, const double* __restrict__ partials, int count,
                Control* ctrl) {
@@ -171,6 +192,12 @@ __global__ void __launch_bounds__(kReduceBlock)
   for (int i = threadIdx.x; i < count; i += kReduceBlock) v += partials[i];
   const double s = block_sum<kReduceBlock>(v, sh);
   if (threadIdx.x != 0) return;
+  finalize_update(mode, s, ctrl);
+  if (ctrl->mirror) *ctrl->mirror = *ctrl;
+}
+
+__device__ __forceinline__ void finalize_update(int mode, double s,
+                                                Control* ctrl) {
   if (mode == kFinBnorm) {
     ctrl->bnorm2 = s;
     if (ctrl->flagged > 0 || !(s > 0.0)) ctrl->done = kNonPhysical;
@@ -181,6 +208,18 @@ __global__ void __launch_bounds__(kReduceBlock)
   if (mode == kFinInitial) {
     ctrl->res_initial = r;
     if (r <= ctrl->rtol) ctrl->done = kConverged;
+    return;
+  }
+  if (mode == kFinOuter) {
+    if (ctrl->outer == 0 && ctrl->cycles == 0) ctrl->res_initial = r;
+    if (r <= ctrl->rtol) {
+      ctrl->done = kConverged;
+    } else if (ctrl->cycles >= ctrl->max_cycles) {
+      ctrl->done = kCapped;
+    } else {
+      ctrl->outer += 1;
+      ctrl->cycles += ctrl->inner;
+    }
     return;
   }
   ctrl->cycles += 1;
@@ -227,12 +266,18 @@ __device__ __forceinline__ double cell_D(const CoefArgs& A, const double* E,
   return A.c * lam / rk;
 }
 
+struct CoefOut {
+  double* a64[3];
+  float* a32[3];  // FP32 copies for the mixed-precision hierarchy (or null)
+  double* copy_dst;
+  double* partials;
+  Control* ctrl;
+};
+
 __global__ void __launch_bounds__(kBlock)
     k_coef(CoefArgs A, const double* __restrict__ E,
            const double* __restrict__ rho, const double* __restrict__ kappa,
-           double* __restrict__ a0, double* __restrict__ a1,
-           double* __restrict__ a2, double* __restrict__ copy_dst,
-           double* __restrict__ partials, Control* ctrl) {
+           CoefOut O) {
   __shared__ double sh[kBlock / 64];
   __shared__ int bad_count;
   if (threadIdx.x == 0) bad_count = 0;
@@ -244,7 +289,6 @@ __global__ void __launch_bounds__(kBlock)
     coords(A.g, idx, c);
     bool bad = false;
     const double D0 = cell_D(A, E, rho, kappa, c, idx, bad);
-    double* out[3] = {a0, a1, a2};
     for (int d = 0; d < A.g.ndim; ++d) {
       double alpha = 0.0;
       if (c[d] < A.g.n[d] - 1 || A.g.per[d]) {
@@ -258,46 +302,56 @@ __global__ void __launch_bounds__(kBlock)
             A.face_mean == 0 ? 0.5 * (D0 + Dn) : 2.0 * D0 * Dn / (D0 + Dn);
         alpha = A.dt * Df / (A.dx[d] * A.dx[d]);
       }
-      out[d][idx] = alpha;
+      O.a64[d][idx] = alpha;
+      if (O.a32[d]) O.a32[d][idx] = (float)alpha;
     }
     const double Ei = E[idx];
-    if (copy_dst) copy_dst[idx] = Ei;
+    if (O.copy_dst) O.copy_dst[idx] = Ei;
     e2 = Ei * Ei;
     if (bad) atomicAdd(&bad_count, 1);
   }
   const double s = block_sum<kBlock>(e2, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = s;
-    if (bad_count > 0) atomicAdd(&ctrl->flagged, bad_count);
+    O.partials[blockIdx.x] = s;
+    if (bad_count > 0) atomicAdd(&O.ctrl->flagged, bad_count);
   }
 }
 
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
-                       const double* kappa, double* alpha0, double* alpha1,
-                       double* alpha2, double* copy_dst, double* partials,
+                       const double* kappa, double* const a64[3],
+                       float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s) {
+  CoefOut O;
+  for (int d = 0; d < 3; ++d) {
+    O.a64[d] = a64[d];
+    O.a32[d] = a32[d];
+  }
+  O.copy_dst = copy_dst;
+  O.partials = partials;
+  O.ctrl = ctrl;
   hipLaunchKernelGGL(k_coef, dim3(blocks_for(a.g.N)), dim3(kBlock), 0, s, a,
-                     E, rho, kappa, alpha0, alpha1, alpha2, copy_dst, partials,
-                     ctrl);
+                     E, rho, kappa, O);
   return hipGetLastError();
 }
 
 // Coarse face coefficient = 1/4 of the mean over the 2^(d-1) fine faces that
 // make up the coarse face (D averaged over the face, dx doubled).
+template <typename T>
 struct CoarsenArgs {
   Geom f, c;
-  const double* fa[3];
-  double* ca[3];
+  const T* fa[3];
+  T* ca[3];
 };
 
-__global__ void __launch_bounds__(kBlock) k_coarsen(CoarsenArgs A) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarsen(CoarsenArgs<T> A) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= A.c.N) return;
   int c[3];
   coords(A.c, idx, c);
   const int nd = A.c.ndim;
   for (int d = 0; d < nd; ++d) {
-    double s = 0.0;
+    T s = T(0);
     int cnt = 0;
     // fine cell on the lower side of the coarse face: 2c+1 along d,
     // 2c or 2c+1 across.
@@ -307,8 +361,8 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(CoarsenArgs A) {
         int f[3] = {2 * c[0], 2 * c[1], 2 * c[2]};
         f[d] += 1;
         // the transverse dimensions of d, in increasing order
-        int t1 = (d == 0) ? 1 : 0;
-        int t2 = (d == 2) ? 1 : 2;
+        const int t1 = (d == 0) ? 1 : 0;
+        const int t2 = (d == 2) ? 1 : 2;
         if (nd > 1) f[t1] += q1;
         if (nd > 2) f[t2] += q2;
         const int64_t fi =
@@ -316,31 +370,63 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(CoarsenArgs A) {
         s += A.fa[d][fi];
         ++cnt;
       }
-    A.ca[d][idx] = 0.25 * s / cnt;
+    A.ca[d][idx] = T(0.25) * s / T(cnt);
   }
 }
 
+template <typename T>
 hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
-                          const double* const fa[3], double* const ca[3],
+                          const T* const fa[3], T* const ca[3],
                           hipStream_t s) {
-  CoarsenArgs A;
+  CoarsenArgs<T> A;
   A.f = fine;
   A.c = coarse;
   for (int d = 0; d < 3; ++d) {
     A.fa[d] = fa[d];
     A.ca[d] = ca[d];
   }
-  hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(coarse.N)), dim3(kBlock), 0, s,
-                     A);
+  hipLaunchKernelGGL(k_coarsen<T>, dim3(blocks_for(coarse.N)), dim3(kBlock), 0,
+                     s, A);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// multigrid
+// multigrid, one launch per phase (1D/3D levels and the reference path)
 // ---------------------------------------------------------------------------
 
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_resid_norm(LevelView<double> L, double* __restrict__ partials,
+    k_resid_norm(LevelView<T> L, double* __restrict__ partials,
+                 const Control* __restrict__ ctrl) {
+  __shared__ double sh[kBlock / 64];
+  if (ctrl->done != kRunning) return;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double r2 = 0.0;
+  if (idx < L.g.N) {
+    int c[3];
+    coords(L.g, idx, c);
+    const double r = (double)residual_value(L, c, idx);
+    r2 = r * r;
+  }
+  const double s = block_sum<kBlock>(r2, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
+                             int* nblocks, const Control* ctrl,
+                             hipStream_t s) {
+  *nblocks = blocks_for(L.g.N);
+  hipLaunchKernelGGL(k_resid_norm<T>, dim3(*nblocks), dim3(kBlock), 0, s, L,
+                     partials, ctrl);
+  return hipGetLastError();
+}
+
+// FP64 residual of the refinement loop, handed to the FP32 hierarchy:
+// r32 = (float)(b - A x) and the block sums of r^2.
+__global__ void __launch_bounds__(kBlock)
+    k_resid_to32(LevelView<double> L, float* __restrict__ r32,
+                 double* __restrict__ partials,
                  const Control* __restrict__ ctrl) {
   __shared__ double sh[kBlock / 64];
   if (ctrl->done != kRunning) return;
@@ -350,24 +436,41 @@ __global__ void __launch_bounds__(kBlock)
     int c[3];
     coords(L.g, idx, c);
     const double r = residual_value(L, c, idx);
+    r32[idx] = (float)r;
     r2 = r * r;
   }
   const double s = block_sum<kBlock>(r2, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-hipError_t launch_resid_norm(const LevelView<double>& L, double* partials,
-                             int* nblocks, const Control* ctrl,
-                             hipStream_t s) {
+hipError_t launch_resid_to32(const LevelView<double>& L, float* r32,
+                             double* partials, int* nblocks,
+                             const Control* ctrl, hipStream_t s) {
   *nblocks = blocks_for(L.g.N);
-  hipLaunchKernelGGL(k_resid_norm, dim3(*nblocks), dim3(kBlock), 0, s, L,
+  hipLaunchKernelGGL(k_resid_to32, dim3(*nblocks), dim3(kBlock), 0, s, L, r32,
                      partials, ctrl);
   return hipGetLastError();
 }
 
+// x64 += e32 (the FP32 correction of one refinement iteration)
 __global__ void __launch_bounds__(kBlock)
-    k_gs_color(LevelView<double> L, int color,
-               const Control* __restrict__ ctrl) {
+    k_correct(int64_t N, double* __restrict__ x, const float* __restrict__ e,
+              const Control* __restrict__ ctrl) {
+  if (ctrl->done != kRunning) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < N) x[i] += (double)e[i];
+}
+
+hipError_t launch_correct(int64_t N, double* x, const float* e,
+                          const Control* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, x,
+                     e, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_gs_color(LevelView<T> L, int color, const Control* __restrict__ ctrl) {
   if (ctrl->done != kRunning) return;
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= L.g.N) return;
@@ -377,17 +480,19 @@ __global__ void __launch_bounds__(kBlock)
   L.x[idx] = relax_value(L, c, idx, L.x);
 }
 
-hipError_t launch_gs_color(const LevelView<double>& L, int color,
+template <typename T>
+hipError_t launch_gs_color(const LevelView<T>& L, int color,
                            const Control* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_gs_color, dim3(blocks_for(L.g.N)), dim3(kBlock), 0, s,
-                     L, color, ctrl);
+  hipLaunchKernelGGL(k_gs_color<T>, dim3(blocks_for(L.g.N)), dim3(kBlock), 0,
+                     s, L, color, ctrl);
   return hipGetLastError();
 }
 
 // Coarse rhs = mean of the 2^d fine residuals; coarse x = 0.  With a
 // partials buffer, also the block sums of the fine residual squared.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_resid_restrict(LevelView<double> F, LevelView<double> C,
+    k_resid_restrict(LevelView<T> F, LevelView<T> C,
                      double* __restrict__ partials,
                      const Control* __restrict__ ctrl) {
   __shared__ double sh[kBlock / 64];
@@ -398,21 +503,21 @@ __global__ void __launch_bounds__(kBlock)
     int c[3];
     coords(C.g, idx, c);
     const int nd = F.g.ndim;
-    const int o0 = 2, o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
-    double s = 0.0;
+    const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
+    T s = T(0);
     for (int q2 = 0; q2 < o2; ++q2)
       for (int q1 = 0; q1 < o1; ++q1)
-        for (int q0 = 0; q0 < o0; ++q0) {
+        for (int q0 = 0; q0 < 2; ++q0) {
           int f[3] = {2 * c[0] + q0, nd > 1 ? 2 * c[1] + q1 : 0,
                       nd > 2 ? 2 * c[2] + q2 : 0};
           const int64_t fi =
               f[0] + (int64_t)F.g.n[0] * (f[1] + (int64_t)F.g.n[1] * f[2]);
-          const double r = residual_value(F, f, fi);
+          const T r = residual_value(F, f, fi);
           s += r;
-          r2 += r * r;
+          r2 += (double)r * (double)r;
         }
-    C.b[idx] = s / (double)(o0 * o1 * o2);
-    C.x[idx] = 0.0;
+    C.b[idx] = s / T(2 * o1 * o2);
+    C.x[idx] = T(0);
   }
   if (partials) {
     const double t = block_sum<kBlock>(r2, sh);
@@ -420,28 +525,24 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-hipError_t launch_resid_restrict(const LevelView<double>& fine,
-                                 const LevelView<double>& coarse,
-                                 double* partials, int* nblocks,
-                                 const Control* ctrl, hipStream_t s) {
+template <typename T>
+hipError_t launch_resid_restrict(const LevelView<T>& fine,
+                                 const LevelView<T>& coarse, double* partials,
+                                 int* nblocks, const Control* ctrl,
+                                 hipStream_t s) {
   *nblocks = blocks_for(coarse.g.N);
-  hipLaunchKernelGGL(k_resid_restrict, dim3(*nblocks), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_resid_restrict<T>, dim3(*nblocks), dim3(kBlock), 0, s,
                      fine, coarse, partials, ctrl);
   return hipGetLastError();
 }
 
-// x_fine += P e_coarse, cell-centred (bi/tri)linear interpolation: weight
-// 3/4 on the parent and 1/4 on the next coarse cell on the child's side,
-// per dimension; mirror (Neumann) or wrapped (periodic) coarse ghosts.
-__global__ void __launch_bounds__(kBlock)
-    k_prolong(LevelView<double> C, LevelView<double> F,
-              const Control* __restrict__ ctrl) {
-  if (ctrl->done != kRunning) return;
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= F.g.N) return;
-  int f[3];
-  coords(F.g, idx, f);
-  const int nd = F.g.ndim;
+// Correction of fine cell f from the coarse level: cell-centred
+// (bi/tri)linear interpolation, weight 3/4 on the parent and 1/4 on the next
+// coarse cell on the child's side, per dimension; mirror (Neumann) or
+// wrapped (periodic) coarse ghosts.
+template <typename T>
+__device__ __forceinline__ T prolong_value(const LevelView<T>& C,
+                                           const int f[3], int nd) {
   int p[3], q[3];
   for (int d = 0; d < 3; ++d) {
     if (d < nd) {
@@ -452,168 +553,50 @@ __global__ void __launch_bounds__(kBlock)
       if (o >= nc) o = C.g.per[d] ? 0 : nc - 1;
       q[d] = o;
     } else {
-      p[d] = 0;
-      q[d] = 0;
+      p[d] = q[d] = 0;
     }
   }
   const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
-  double e = 0.0;
+  T e = T(0);
   for (int s2 = 0; s2 < o2; ++s2)
     for (int s1 = 0; s1 < o1; ++s1)
       for (int s0 = 0; s0 < 2; ++s0) {
         const int i = s0 ? q[0] : p[0];
         const int j = s1 ? q[1] : p[1];
         const int k = s2 ? q[2] : p[2];
-        const double w = (s0 ? 0.25 : 0.75) * (nd > 1 ? (s1 ? 0.25 : 0.75) : 1.0) *
-                         (nd > 2 ? (s2 ? 0.25 : 0.75) : 1.0);
+        const T w = T((s0 ? 0.25 : 0.75) * (nd > 1 ? (s1 ? 0.25 : 0.75) : 1.0) *
+                      (nd > 2 ? (s2 ? 0.25 : 0.75) : 1.0));
         e += w * C.x[i + (int64_t)C.g.n[0] * (j + (int64_t)C.g.n[1] * k)];
       }
-  F.x[idx] += e;
+  return e;
 }
 
-hipError_t launch_prolong(const LevelView<double>& coarse,
-                          const LevelView<double>& fine, const Control* ctrl,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(fine.g.N)), dim3(kBlock), 0, s,
-                     coarse, fine, ctrl);
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_prolong(LevelView<T> C, LevelView<T> F,
+              const Control* __restrict__ ctrl) {
+  if (ctrl->done != kRunning) return;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= F.g.N) return;
+  int f[3];
+  coords(F.g, idx, f);
+  F.x[idx] += prolong_value(C, f, F.g.ndim);
+}
+
+template <typename T>
+hipError_t launch_prolong(const LevelView<T>& coarse, const LevelView<T>& fine,
+                          const Control* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for(fine.g.N)), dim3(kBlock), 0,
+                     s, coarse, fine, ctrl);
   return hipGetLastError();
 }
 
 // Coarsest level: Jacobi sweeps in one block until the residual norm has
 // dropped by 1e-6 (A = I + L is strictly diagonally dominant, so Jacobi
 // converges for any alpha).  tmp holds the next iterate.
-__global__ void __launch_bounds__(kReduceBlock)
-    k_coarsest(LevelView<double> L, double* __restrict__ tmp,
-               const Control* __restrict__ ctrl) {
-  __shared__ double sh[kReduceBlock / 64];
-  __shared__ double r0, rn;
-  if (ctrl->done != kRunning) return;
-  const int64_t N = L.g.N;
-  for (int it = 0; it < 4000; ++it) {
-    if ((it & 7) == 0) {
-      double v = 0.0;
-      for (int64_t i = threadIdx.x; i < N; i += kReduceBlock) {
-        int c[3];
-        coords(L.g, i, c);
-        const double r = residual_value(L, c, i);
-        v += r * r;
-      }
-      const double s = block_sum<kReduceBlock>(v, sh);
-      if (threadIdx.x == 0) {
-        if (it == 0) r0 = s;
-        rn = s;
-      }
-      __syncthreads();
-      if (!(rn > 1e-12 * r0)) break;
-    }
-    for (int64_t i = threadIdx.x; i < N; i += kReduceBlock) {
-      int c[3];
-      coords(L.g, i, c);
-      tmp[i] = relax_value(L, c, i, L.x);
-    }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < N; i += kReduceBlock) L.x[i] = tmp[i];
-    __syncthreads();
-  }
-}
-
-hipError_t launch_coarsest(const LevelView<double>& L, double* tmp,
-                           const Control* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(kReduceBlock), 0, s, L, tmp,
-                     ctrl);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// single-workgroup tail of the V-cycle
-// ---------------------------------------------------------------------------
-//
-// Levels small enough for one workgroup (a few thousand cells) are handled
-// by one block of kReduceBlock threads with block barriers between phases,
-// instead of one launch per phase and level.  With l0 == 0 the whole
-// problem fits and the block also runs the cycle loop and the stop test.
-
-__device__ void t_smooth(const LevelView<double>& L, int sweeps) {
-  for (int s = 0; s < sweeps; ++s)
-    for (int color = 0; color < 2; ++color) {
-      for (int64_t i = threadIdx.x; i < L.g.N; i += kReduceBlock) {
-        int c[3];
-        coords(L.g, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) == color)
-          L.x[i] = relax_value(L, c, i, L.x);
-      }
-      __syncthreads();
-    }
-}
-
-// restriction of the residual; returns this thread's share of sum r^2
-__device__ double t_resid_restrict(const LevelView<double>& F,
-                                   const LevelView<double>& C) {
-  const int nd = F.g.ndim;
-  const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
-  double r2 = 0.0;
-  for (int64_t idx = threadIdx.x; idx < C.g.N; idx += kReduceBlock) {
-    int c[3];
-    coords(C.g, idx, c);
-    double s = 0.0;
-    for (int q2 = 0; q2 < o2; ++q2)
-      for (int q1 = 0; q1 < o1; ++q1)
-        for (int q0 = 0; q0 < 2; ++q0) {
-          int f[3] = {2 * c[0] + q0, nd > 1 ? 2 * c[1] + q1 : 0,
-                      nd > 2 ? 2 * c[2] + q2 : 0};
-          const int64_t fi =
-              f[0] + (int64_t)F.g.n[0] * (f[1] + (int64_t)F.g.n[1] * f[2]);
-          const double r = residual_value(F, f, fi);
-          s += r;
-          r2 += r * r;
-        }
-    C.b[idx] = s / (double)(2 * o1 * o2);
-    C.x[idx] = 0.0;
-  }
-  __syncthreads();
-  return r2;
-}
-
-__device__ void t_prolong(const LevelView<double>& C,
-                          const LevelView<double>& F) {
-  const int nd = F.g.ndim;
-  for (int64_t idx = threadIdx.x; idx < F.g.N; idx += kReduceBlock) {
-    int f[3];
-    coords(F.g, idx, f);
-    int p[3], q[3];
-    for (int d = 0; d < 3; ++d) {
-      if (d < nd) {
-        p[d] = f[d] >> 1;
-        int o = (f[d] & 1) ? p[d] + 1 : p[d] - 1;
-        const int nc = C.g.n[d];
-        if (o < 0) o = C.g.per[d] ? nc - 1 : 0;
-        if (o >= nc) o = C.g.per[d] ? 0 : nc - 1;
-        q[d] = o;
-      } else {
-        p[d] = q[d] = 0;
-      }
-    }
-    const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
-    double e = 0.0;
-    for (int s2 = 0; s2 < o2; ++s2)
-      for (int s1 = 0; s1 < o1; ++s1)
-        for (int s0 = 0; s0 < 2; ++s0) {
-          const int i = s0 ? q[0] : p[0];
-          const int j = s1 ? q[1] : p[1];
-          const int k = s2 ? q[2] : p[2];
-          const double w = (s0 ? 0.25 : 0.75) *
-                           (nd > 1 ? (s1 ? 0.25 : 0.75) : 1.0) *
-                           (nd > 2 ? (s2 ? 0.25 : 0.75) : 1.0);
-          e += w * C.x[i + (int64_t)C.g.n[0] * (j + (int64_t)C.g.n[1] * k)];
-        }
-    F.x[idx] += e;
-  }
-  __syncthreads();
-}
-
-// Jacobi until the residual norm dropped by 1e-6 (or 4000 sweeps).
-__device__ void t_coarsest(const LevelView<double>& L, double* tmp,
-                           double* sh, double* bc) {
+template <typename T>
+__device__ void t_coarsest(const LevelView<T>& L, T* tmp, double* sh,
+                           double* bc) {
   const int64_t N = L.g.N;
   double r0 = 0.0;
   for (int it = 0; it < 4000; ++it) {
@@ -622,7 +605,7 @@ __device__ void t_coarsest(const LevelView<double>& L, double* tmp,
       for (int64_t i = threadIdx.x; i < N; i += kReduceBlock) {
         int c[3];
         coords(L.g, i, c);
-        const double r = residual_value(L, c, i);
+        const double r = (double)residual_value(L, c, i);
         v += r * r;
       }
       const double s = block_sum<kReduceBlock>(v, sh);
@@ -644,73 +627,228 @@ __device__ void t_coarsest(const LevelView<double>& L, double* tmp,
   }
 }
 
-// sub-V-cycle from level l0 down to the coarsest and back to l0
-__device__ void t_subcycle(const TailArgs& A, int l0, double* sh, double* bc) {
-  for (int l = l0; l + 1 < A.L; ++l) {
-    t_smooth(A.lv[l], A.pre);
-    (void)t_resid_restrict(A.lv[l], A.lv[l + 1]);
-  }
-  t_coarsest(A.lv[A.L - 1], A.tmp, sh, bc);
-  for (int l = A.L - 2; l >= l0; --l) {
-    t_prolong(A.lv[l + 1], A.lv[l]);
-    t_smooth(A.lv[l], A.post);
-  }
+template <typename T>
+__global__ void __launch_bounds__(kReduceBlock)
+    k_coarsest(LevelView<T> L, T* __restrict__ tmp,
+               const Control* __restrict__ ctrl) {
+  __shared__ double sh[kReduceBlock / 64];
+  __shared__ double bc[2];
+  if (ctrl->done != kRunning) return;
+  t_coarsest(L, tmp, sh, bc);
 }
 
-__global__ void __launch_bounds__(kReduceBlock) k_tail(TailArgs A) {
+template <typename T>
+hipError_t launch_coarsest(const LevelView<T>& L, T* tmp, const Control* ctrl,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(kReduceBlock), 0, s, L, tmp,
+                     ctrl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// single-workgroup tail of the V-cycle
+// ---------------------------------------------------------------------------
+//
+// Levels small enough for one workgroup (a few thousand cells) are handled
+// by one block of kReduceBlock threads with block barriers between phases,
+// instead of one launch per phase and level.  In "whole" mode (l0 == 0 in
+// FP64) the block also runs the cycle loop and the stop test.
+
+template <typename T>
+__device__ void t_smooth(const LevelView<T>& L, int sweeps) {
+  for (int s = 0; s < sweeps; ++s)
+    for (int color = 0; color < 2; ++color) {
+      for (int64_t i = threadIdx.x; i < L.g.N; i += kReduceBlock) {
+        int c[3];
+        coords(L.g, i, c);
+        if (((c[0] + c[1] + c[2]) & 1) == color)
+          L.x[i] = relax_value(L, c, i, L.x);
+      }
+      __syncthreads();
+    }
+}
+
+// restriction of the residual; returns this thread's share of sum r^2
+template <typename T>
+__device__ double t_resid_restrict(const LevelView<T>& F,
+                                   const LevelView<T>& C) {
+  const int nd = F.g.ndim;
+  const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
+  double r2 = 0.0;
+  for (int64_t idx = threadIdx.x; idx < C.g.N; idx += kReduceBlock) {
+    int c[3];
+    coords(C.g, idx, c);
+    T s = T(0);
+    for (int q2 = 0; q2 < o2; ++q2)
+      for (int q1 = 0; q1 < o1; ++q1)
+        for (int q0 = 0; q0 < 2; ++q0) {
+          int f[3] = {2 * c[0] + q0, nd > 1 ? 2 * c[1] + q1 : 0,
+                      nd > 2 ? 2 * c[2] + q2 : 0};
+          const int64_t fi =
+              f[0] + (int64_t)F.g.n[0] * (f[1] + (int64_t)F.g.n[1] * f[2]);
+          const T r = residual_value(F, f, fi);
+          s += r;
+          r2 += (double)r * (double)r;
+        }
+    C.b[idx] = s / T(2 * o1 * o2);
+    C.x[idx] = T(0);
+  }
+  __syncthreads();
+  return r2;
+}
+
+template <typename T>
+__device__ void t_prolong(const LevelView<T>& C, const LevelView<T>& F) {
+  for (int64_t idx = threadIdx.x; idx < F.g.N; idx += kReduceBlock) {
+    int f[3];
+    coords(F.g, idx, f);
+    F.x[idx] += prolong_value(C, f, F.g.ndim);
+  }
+  __syncthreads();
+}
+
+// The tail levels are copied into LDS first when they fit (kTailLdsCells),
+// so every phase works on LDS rather than on L2-resident global memory; the
+// result x(l0) is written back at the end.
+template <typename T, bool kLds>
+__global__ void __launch_bounds__(kReduceBlock) k_tail(TailArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[kReduceBlock / 64];
   __shared__ double bc[2];
   __shared__ int stop;
+  __shared__ LevelView<T> lv[kMaxLevels];
+  __shared__ T* tmp_s;
   if (A.ctrl->done != kRunning) return;
-  if (A.l0 > 0) {
-    const LevelView<double>& L = A.lv[A.l0];
-    for (int64_t i = threadIdx.x; i < L.g.N; i += kReduceBlock) L.x[i] = 0.0;
-    __syncthreads();
-    t_subcycle(A, A.l0, sh, bc);
-    return;
-  }
-  // whole problem: cycle loop with the stop test of k_finalize
-  for (;;) {
-    double r2;
-    if (A.L > 1) {
-      t_smooth(A.lv[0], A.pre);
-      r2 = t_resid_restrict(A.lv[0], A.lv[1]);
-    } else {
-      t_coarsest(A.lv[0], A.tmp, sh, bc);
-      r2 = 0.0;
-      for (int64_t i = threadIdx.x; i < A.lv[0].g.N; i += kReduceBlock) {
-        int c[3];
-        coords(A.lv[0].g, i, c);
-        const double r = residual_value(A.lv[0], c, i);
-        r2 += r * r;
+  const int l0 = A.l0;
+  if (threadIdx.x == 0) {
+    T* p = (T*)smem;
+    for (int l = 0; l < A.L; ++l) {
+      lv[l] = A.lv[l];
+      if (!kLds || l < l0) continue;
+      const int64_t n = A.lv[l].g.N;
+      lv[l].x = p;
+      p += n;
+      lv[l].b = p;
+      p += n;
+      for (int d = 0; d < A.lv[l].g.ndim; ++d) {
+        lv[l].a[d] = p;
+        p += n;
       }
     }
-    const double s = block_sum<kReduceBlock>(r2, sh);
-    if (threadIdx.x == 0) {
-      Control* C = A.ctrl;
-      const double r = sqrt(s / C->bnorm2);
-      C->res = r;
-      C->cycles += 1;
-      if (r <= C->rtol)
-        C->done = kConverged;
-      else if (C->cycles >= C->max_cycles)
-        C->done = kCapped;
-      stop = C->done != kRunning;
+    tmp_s = kLds ? p : A.tmp;
+  }
+  __syncthreads();
+  if (kLds) {
+    for (int l = l0; l < A.L; ++l) {
+      const int n = (int)A.lv[l].g.N;
+      for (int d = 0; d < A.lv[l].g.ndim; ++d) {
+        T* dst = const_cast<T*>(lv[l].a[d]);
+        for (int i = threadIdx.x; i < n; i += kReduceBlock)
+          dst[i] = A.lv[l].a[d][i];
+      }
     }
-    __syncthreads();
-    if (stop) return;
-    if (A.L > 1) {
-      t_subcycle(A, 1, sh, bc);
-      t_prolong(A.lv[1], A.lv[0]);
-      t_smooth(A.lv[0], A.post);
+    const int n0 = (int)A.lv[l0].g.N;
+    for (int i = threadIdx.x; i < n0; i += kReduceBlock) {
+      lv[l0].b[i] = A.lv[l0].b[i];
+      lv[l0].x[i] = A.zero ? T(0) : A.lv[l0].x[i];
     }
+  } else if (A.zero) {
+    for (int64_t i = threadIdx.x; i < A.lv[l0].g.N; i += kReduceBlock)
+      A.lv[l0].x[i] = T(0);
+  }
+  __syncthreads();
+  TailArgs<T> const& G = A;
+  (void)G;
+  if (!A.whole) {
+    for (int l = l0; l + 1 < A.L; ++l) {
+      t_smooth(lv[l], A.pre);
+      (void)t_resid_restrict(lv[l], lv[l + 1]);
+    }
+    t_coarsest(lv[A.L - 1], tmp_s, sh, bc);
+    for (int l = A.L - 2; l >= l0; --l) {
+      t_prolong(lv[l + 1], lv[l]);
+      t_smooth(lv[l], A.post);
+    }
+  } else {
+    // whole problem: cycle loop with the stop test of k_finalize
+    for (;;) {
+      double r2;
+      if (A.L > 1) {
+        t_smooth(lv[0], A.pre);
+        r2 = t_resid_restrict(lv[0], lv[1]);
+      } else {
+        t_coarsest(lv[0], tmp_s, sh, bc);
+        r2 = 0.0;
+        for (int64_t i = threadIdx.x; i < lv[0].g.N; i += kReduceBlock) {
+          int c[3];
+          coords(lv[0].g, i, c);
+          const double r = (double)residual_value(lv[0], c, i);
+          r2 += r * r;
+        }
+      }
+      const double s = block_sum<kReduceBlock>(r2, sh);
+      if (threadIdx.x == 0) {
+        Control* C = A.ctrl;
+        const double r = sqrt(s / C->bnorm2);
+        C->res = r;
+        C->cycles += 1;
+        if (r <= C->rtol)
+          C->done = kConverged;
+        else if (C->cycles >= C->max_cycles)
+          C->done = kCapped;
+        stop = C->done != kRunning;
+      }
+      __syncthreads();
+      if (stop) break;
+      if (A.L > 1) {
+        for (int l = 1; l + 1 < A.L; ++l) {
+          t_smooth(lv[l], A.pre);
+          (void)t_resid_restrict(lv[l], lv[l + 1]);
+        }
+        t_coarsest(lv[A.L - 1], tmp_s, sh, bc);
+        for (int l = A.L - 2; l >= 0; --l) {
+          t_prolong(lv[l + 1], lv[l]);
+          t_smooth(lv[l], A.post);
+        }
+      }
+    }
+  }
+  if (kLds) {
+    const int n0 = (int)A.lv[l0].g.N;
+    for (int i = threadIdx.x; i < n0; i += kReduceBlock)
+      A.lv[l0].x[i] = lv[l0].x[i];
   }
 }
 
-hipError_t launch_tail(const TailArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_tail, dim3(1), dim3(kReduceBlock), 0, s, a);
+template <typename T>
+hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s) {
+  bool used = false;
+  hipError_t e = launch_tail_lds<T>(a, s, &used);
+  if (used || e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
+
+#define FLD_INSTANTIATE_MG(T)                                                  \
+  template hipError_t launch_coarsen<T>(const Geom&, const Geom&,              \
+                                        const T* const[3], T* const[3],        \
+                                        hipStream_t);                          \
+  template hipError_t launch_resid_norm<T>(const LevelView<T>&, double*, int*, \
+                                           const Control*, hipStream_t);       \
+  template hipError_t launch_gs_color<T>(const LevelView<T>&, int,             \
+                                         const Control*, hipStream_t);         \
+  template hipError_t launch_resid_restrict<T>(                                \
+      const LevelView<T>&, const LevelView<T>&, double*, int*, const Control*, \
+      hipStream_t);                                                            \
+  template hipError_t launch_prolong<T>(const LevelView<T>&,                   \
+                                        const LevelView<T>&, const Control*,   \
+                                        hipStream_t);                          \
+  template hipError_t launch_coarsest<T>(const LevelView<T>&, T*,              \
+                                         const Control*, hipStream_t);         \
+  template hipError_t launch_tail<T>(const TailArgs<T>&, hipStream_t);
+
+FLD_INSTANTIATE_MG(double)
+FLD_INSTANTIATE_MG(float)
 
 // ---------------------------------------------------------------------------
 // exchange and opacity
@@ -775,16 +913,32 @@ hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,
   return hipGetLastError();
 }
 
+// x^(h/2) for an integer h: repeated squaring and one square root.
+__device__ __forceinline__ double pow_half(double x, int h) {
+  const bool neg = h < 0;
+  int n = neg ? -h : h;
+  double r = 1.0, base = x;
+  for (int k = n >> 1; k; k >>= 1) {
+    if (k & 1) r *= base;
+    base *= base;
+  }
+  if (n & 1) r *= sqrt(x);
+  return neg ? 1.0 / r : r;
+}
+
+// ha, hb: twice the exponents when both are half-integers (|2a|, |2b| <= 32),
+// so the power law needs no pow(); otherwise ha = INT_MIN and pow() is used.
 __global__ void __launch_bounds__(kBlock)
     k_opacity(int64_t N, double gm1, double gas_const,
               const double* __restrict__ rho, const double* __restrict__ e,
-              double k0, double pa, double pb, double kmin, double kmax,
-              double* __restrict__ kappa) {
+              double k0, double pa, double pb, int ha, int hb, double kmin,
+              double kmax, double* __restrict__ kappa) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= N) return;
   const double r = rho[i];
   const double T = gm1 * e[i] / (r * gas_const);
-  const double k = k0 * pow(r, pa) * pow(T, pb);
+  const double k = ha != INT_MIN ? k0 * pow_half(r, ha) * pow_half(T, hb)
+                                 : k0 * pow(r, pa) * pow(T, pb);
   kappa[i] = fmin(fmax(k, kmin), kmax);
 }
 
@@ -793,9 +947,15 @@ hipError_t launch_opacity(int64_t N, double gamma, double gas_const,
                           double pa, double pb, double kmin, double kmax,
                           double* kappa, hipStream_t s) {
   if (N == 0) return hipSuccess;
+  int ha = INT_MIN, hb = INT_MIN;
+  if (2.0 * pa == floor(2.0 * pa) && 2.0 * pb == floor(2.0 * pb) &&
+      fabs(pa) <= 16.0 && fabs(pb) <= 16.0) {
+    ha = (int)(2.0 * pa);
+    hb = (int)(2.0 * pb);
+  }
   hipLaunchKernelGGL(k_opacity, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
-                     gamma - 1.0, gas_const, rho, e, k0, pa, pb, kmin, kmax,
-                     kappa);
+                     gamma - 1.0, gas_const, rho, e, k0, pa, pb, ha, hb, kmin,
+                     kmax, kappa);
   return hipGetLastError();
 }
 

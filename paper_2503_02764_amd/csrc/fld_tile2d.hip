@@ -98,52 +98,80 @@ __global__ void __launch_bounds__(RX / 2 * NPY)
   (void)dn;
   const int mx0 = map_coord(gx0 + 2 * px, nx, perx);
   const int mx1 = map_coord(gx0 + 2 * px + 1, nx, perx);
+  // Loads are issued branch-free (indices clamped into the domain, values
+  // masked afterwards) for all rows of the thread at once, so that they are
+  // all in flight before the first use.
+  constexpr int KG = DOWN ? K : K / 2;  // rows per load group
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int ly = py * K + k;
-    const int my = map_coord(gy0 + ly, ny, pery);
+  for (int k0 = 0; k0 < K; k0 += KG) {
+    T lx[KG][2], lb[KG][2], lal[KG][2], lar[KG][2], lad[KG][2], lau[KG][2];
+    T le[DOWN ? 1 : KG][2][4];
+    (void)le;
+    bool vv[KG][2], vl[KG][2], vd[KG][2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int mx = q ? mx1 : mx0;
-      T xv = T(0), bv = T(0), al = T(0), ar = T(0), ad = T(0), au = T(0);
-      if (mx >= 0 && my >= 0) {
-        const int64_t gi = (int64_t)my * nx + mx;
-        if (!A.zero_init) xv = A.x[gi];
-        bv = A.b[gi];
-        ar = A.ax[gi];
-        au = A.ay[gi];
-        if (mx > 0) al = A.ax[gi - 1];
-        else if (perx) al = A.ax[gi + nx - 1];
-        if (my > 0) ad = A.ay[gi - nx];
-        else if (pery) ad = A.ay[gi + (int64_t)(ny - 1) * nx];
-        if (!DOWN && A.ce) {
+    for (int kk = 0; kk < KG; ++kk) {
+      const int my = map_coord(gy0 + py * K + k0 + kk, ny, pery);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int mx = q ? mx1 : mx0;
+        const bool v = mx >= 0 && my >= 0;
+        const int cx = v ? mx : 0, cy = v ? my : 0;
+        vv[kk][q] = v;
+        vl[kk][q] = v && (cx > 0 || perx);
+        vd[kk][q] = v && (cy > 0 || pery);
+        const int64_t gi = (int64_t)cy * nx + cx;
+        const int64_t gl = cx > 0 ? gi - 1 : gi + nx - 1;
+        const int64_t gd = cy > 0 ? gi - nx : gi + (int64_t)(ny - 1) * nx;
+        lx[kk][q] = A.zero_init ? T(0) : A.x[gi];
+        lb[kk][q] = A.b[gi];
+        lar[kk][q] = A.ax[gi];
+        lau[kk][q] = A.ay[gi];
+        lal[kk][q] = A.ax[gl];
+        lad[kk][q] = A.ay[gd];
+        if constexpr (!DOWN) {
           // bilinear prolongation of the coarse correction
           const int ncx = A.gc.n[0], ncy = A.gc.n[1];
-          const int I = mx >> 1, J = my >> 1;
-          int I2 = (mx & 1) ? I + 1 : I - 1;
-          int J2 = (my & 1) ? J + 1 : J - 1;
+          const int I = cx >> 1, J = cy >> 1;
+          int I2 = (cx & 1) ? I + 1 : I - 1;
+          int J2 = (cy & 1) ? J + 1 : J - 1;
           if (I2 < 0) I2 = perx ? ncx - 1 : 0;
           if (I2 >= ncx) I2 = perx ? 0 : ncx - 1;
           if (J2 < 0) J2 = pery ? ncy - 1 : 0;
           if (J2 >= ncy) J2 = pery ? 0 : ncy - 1;
-          const T e00 = A.ce[(int64_t)J * ncx + I];
-          const T e10 = A.ce[(int64_t)J * ncx + I2];
-          const T e01 = A.ce[(int64_t)J2 * ncx + I];
-          const T e11 = A.ce[(int64_t)J2 * ncx + I2];
-          xv += T(0.5625) * e00 + T(0.1875) * e10 + T(0.1875) * e01 +
-                T(0.0625) * e11;
+          le[kk][q][0] = A.ce[(int64_t)J * ncx + I];
+          le[kk][q][1] = A.ce[(int64_t)J * ncx + I2];
+          le[kk][q][2] = A.ce[(int64_t)J2 * ncx + I];
+          le[kk][q][3] = A.ce[(int64_t)J2 * ncx + I2];
         }
       }
-      const T d = T(1) + al + ar + ad + au;
-      const T inv = T(1) / d;
-      bp[k][q] = bv * inv;
-      wl[k][q] = al * inv;
-      wr[k][q] = ar * inv;
-      wd[k][q] = ad * inv;
-      wu[k][q] = au * inv;
-      if constexpr (DOWN) dn[k][q] = d;
-      xs[(ly + 1) * LX + 2 * px + q + 1] = xv;
     }
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = k0 + kk;
+        const bool v = vv[kk][q];
+        T xv = v ? lx[kk][q] : T(0);
+        const T bv = v ? lb[kk][q] : T(0);
+        const T ar = v ? lar[kk][q] : T(0);
+        const T au = v ? lau[kk][q] : T(0);
+        const T al = vl[kk][q] ? lal[kk][q] : T(0);
+        const T ad = vd[kk][q] ? lad[kk][q] : T(0);
+        if constexpr (!DOWN) {
+          if (v)
+            xv += T(0.5625) * le[kk][q][0] + T(0.1875) * le[kk][q][1] +
+                  T(0.1875) * le[kk][q][2] + T(0.0625) * le[kk][q][3];
+        }
+        const T d = T(1) + al + ar + ad + au;
+        const T inv = T(1) / d;
+        bp[k][q] = bv * inv;
+        wl[k][q] = al * inv;
+        wr[k][q] = ar * inv;
+        wd[k][q] = ad * inv;
+        wu[k][q] = au * inv;
+        if constexpr (DOWN) dn[k][q] = d;
+        xs[(py * K + k + 1) * LX + 2 * px + q + 1] = xv;
+      }
   }
   __syncthreads();
 
@@ -256,5 +284,7 @@ int tile2d_blocks(const Geom& g, int nu, bool down) {
 
 template hipError_t launch_tile2d<double>(const Tile2DArgs<double>&, int, bool,
                                           hipStream_t, int*);
+template hipError_t launch_tile2d<float>(const Tile2DArgs<float>&, int, bool,
+                                         hipStream_t, int*);
 
 }  // namespace fld
