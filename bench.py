@@ -25,6 +25,31 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
           "plain FP64 MG")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None.
+
+    profiles/*.md carry a `traffic_record:` line written from two rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE, scaled by a plain-copy calibration)
+    together with the hash of the kernel source they were taken on; a
+    changed source makes the record stale and the figure null.
+    """
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic_record:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") != kernel:
+                continue
+            src = os.path.join(ROOT, kv["source"])
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            if sha != kv["sha256_16"]:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(m, budget_s=30.0):
     """Oracle (FP64, numpy/scipy) on one step of the same workload."""
     from oracle import fldref as F
@@ -46,6 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -54,6 +82,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 27  # 1 GiB of float64 read, 1 GiB written
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}))
+        return
 
     import media
     from paper_2503_02764_amd import fld
@@ -147,7 +185,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(kt["kernel"]),
             "avg_launch_us": avg_ms * 1e3,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": kt["launches"],
