@@ -168,6 +168,55 @@ fld_status fld_kernel_timing_read(fld_ctx* ctx, double* ms_total,
                                   int64_t* launches, double* bytes_total,
                                   const char** kernel_name);
 
+/* ---- Batched grids ---------------------------------------------------------
+ * Many independent 2D grids (each with its own size, boundaries, constants
+ * and dt) advanced together: every phase of the step above is one launch
+ * over all grids, so the launch count does not grow with the number of
+ * grids.  Each grid gets the same result as fld_step / fld_exchange /
+ * fld_opacity_powerlaw on its own (same operator, same stop test on its own
+ * residual); grids that have converged skip their share of later launches.
+ * Restrictions (FLD_ERR_INVALID_ARG otherwise): ndim == 2, one precision and
+ * one pre/post smoothing count (1..3) for all grids, guess E^n, and every
+ * grid coarsenable to at most 1024 cells but larger than that itself.
+ * Pointer arrays (const double* const* ...) are HOST arrays of `count`
+ * DEVICE pointers. */
+
+/* Workspace bytes for fld_setup_batch (0 if the parameters are invalid). */
+size_t fld_workspace_bytes_batch(int32_t count, const fld_params* each);
+
+/* Set up `count` grids in one workspace; *out is a batched context. */
+fld_status fld_setup_batch(int32_t count, const fld_params* each,
+                           void* workspace, size_t ws_bytes, void* hip_stream,
+                           fld_ctx** out);
+
+/* fld_step for every grid g with dt[g] (host array).  stats: host array of
+ * `count` entries, or NULL.  Blocks until every grid has stopped.  Returns
+ * FLD_OK if all converged, else the worst status (NONPHYSICAL before
+ * NOT_CONVERGED); fld_last_error names the grid. */
+fld_status fld_step_batch(fld_ctx* ctx, const double* dt,
+                          const double* const* rho, const double* const* kappa,
+                          const double* const* E_in, double* const* E_out,
+                          fld_stats* stats);
+
+/* fld_exchange for every grid (one launch).  Waits for earlier work on the
+ * stream before it stages its argument table. */
+fld_status fld_exchange_batch(fld_ctx* ctx, const double* dt,
+                              const double* const* rho,
+                              const double* const* kappa, double* const* E,
+                              double* const* e_int);
+
+/* fld_opacity_powerlaw for every grid (one launch); same staging rule. */
+fld_status fld_opacity_powerlaw_batch(fld_ctx* ctx, const double* const* rho,
+                                      const double* const* e_int, double k0,
+                                      double a, double b, double kmin,
+                                      double kmax, double* const* kappa);
+
+/* on != 0: capture the launches of one batch of iterations into a hipGraph
+ * once and replay it in later steps (argument tables stay at fixed device
+ * addresses, so new field pointers do not invalidate it).  Needs a
+ * non-default stream (FLD_ERR_INVALID_ARG for the null stream). */
+fld_status fld_batch_set_graph(fld_ctx* ctx, int32_t on);
+
 /* Release the context (host memory only; the workspace is the caller's). */
 void fld_destroy(fld_ctx* ctx);
 

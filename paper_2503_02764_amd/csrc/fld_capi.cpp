@@ -17,9 +17,12 @@
 #include "fld.h"
 #include "fld_internal.h"
 #include "fld_tile2d.h"
+#include "fld_batch.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,6 +44,8 @@ struct Levels {
 };
 
 }  // namespace
+
+struct BatchState;
 
 struct fld_ctx {
   fld_params p;
@@ -71,6 +76,7 @@ struct fld_ctx {
   size_t ev_used = 0;
   bool fast = true;  // tiled kernels + single-workgroup tail
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
+  BatchState* batch = nullptr;  // set for a batched context (sub-grids)
 };
 
 namespace {
@@ -496,6 +502,373 @@ fld_status solve_mixed(fld_ctx* c) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batched solve: many independent 2D grids per launch
+// ---------------------------------------------------------------------------
+//
+// Each grid keeps an ordinary sub-context (its own slice of the workspace,
+// its own control block and stop flag).  Every phase of a step is one launch
+// over all grids: the per-grid arguments are laid out in a device table
+// (rebuilt on the host each step and uploaded only when it changed), and
+// blocks are mapped onto grids by prefix sums.  Grids that have converged
+// skip their blocks.  Optionally the sequence of one batch of refinement
+// iterations is captured once into a hipGraph and replayed.
+
+namespace {
+
+struct Image {
+  std::vector<char> buf;
+  template <typename X>
+  size_t put(const std::vector<X>& v) {
+    const size_t o = align_up(buf.size());
+    buf.resize(o + v.size() * sizeof(X));
+    if (!v.empty()) memcpy(buf.data() + o, v.data(), v.size() * sizeof(X));
+    return o;
+  }
+};
+
+struct Phase {  // one batched launch: table offset, block starts, counts
+  size_t tab = 0, start = 0;
+  int ng = 0, nblocks = 0;
+};
+
+}  // namespace
+
+struct BatchState {
+  int ng = 0;
+  std::vector<fld_ctx*> sub;
+  char* dev_tab = nullptr;  // device table area (end of the workspace)
+  size_t tab_cap = 0;
+  char* host_tab = nullptr;  // pinned staging of the table image
+  std::vector<char> last;    // last image uploaded
+  char* dev_aux = nullptr;   // tables of the pointwise calls
+  char* host_aux = nullptr;
+  size_t aux_cap = 0;
+  // layout of the step image
+  Phase ctrl, coef, fin_b, resid, fin_r, correct, fin_c;
+  std::vector<Phase> coarsen, down[2], up;
+  Phase tail[2];
+  size_t tail_lds = 0;
+  int maxL = 0, maxl0 = 0;
+  bool graph_on = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_iters = 0;
+  int last_batch = 3;
+};
+
+namespace {
+
+template <typename X>
+void add_phase(Image& im, Phase& ph, const std::vector<X>& jobs,
+               const std::vector<int>& blocks) {
+  ph.ng = (int)jobs.size();
+  ph.tab = im.put(jobs);
+  std::vector<int> start(jobs.size() + 1, 0);
+  for (size_t g = 0; g < jobs.size(); ++g) start[g + 1] = start[g] + blocks[g];
+  ph.nblocks = start.back();
+  ph.start = im.put(start);
+}
+
+template <typename T>
+Levels<T>& hier(fld_ctx* c);
+template <>
+Levels<double>& hier<double>(fld_ctx* c) { return c->h64; }
+template <>
+Levels<float>& hier<float>(fld_ctx* c) { return c->h32; }
+
+template <typename T>
+Tile2DArgs<T> tile_job(fld_ctx* c, int l, bool down, bool zero_init,
+                       double* partials) {
+  Levels<T>& H = hier<T>(c);
+  Tile2DArgs<T> a{};
+  a.g = c->geom[l];
+  a.x = H.x[l];
+  a.b = H.b[l];
+  a.ax = H.a[l][0];
+  a.ay = H.a[l][1];
+  a.gc = c->geom[l + 1];
+  a.cb = down ? H.b[l + 1] : nullptr;
+  a.ce = down ? nullptr : H.x[l + 1];
+  a.partials = partials;
+  a.zero_init = zero_init;
+  a.ctrl = c->ctrl;
+  tile2d_grid(a.g, down ? c->p.pre_smooth : c->p.post_smooth, down, &a.tiles_x,
+              &a.tiles_y);
+  return a;
+}
+
+// Build the step image for the current field pointers (levels of
+// precision T carry the V-cycles).
+template <typename T>
+void build_image(fld_ctx* bc, Image& im, const double* dt,
+                 const double* const* rho, const double* const* kappa,
+                 const double* const* E_in, double* const* E_out) {
+  BatchState* B = bc->batch;
+  const int ng = B->ng;
+  std::vector<JobCtrl> jc(ng);
+  std::vector<JobCoef> jf(ng);
+  std::vector<JobFinalize> fb(ng), fr(ng), fcy(ng);
+  std::vector<JobResid> jr(ng);
+  std::vector<JobCorrect> jx(ng);
+  std::vector<int> bcoef(ng), bres(ng), one(ng, 1);
+  for (int g = 0; g < ng; ++g) {
+    fld_ctx* c = B->sub[g];
+    const bool aliased = E_in[g] == E_out[g];
+    c->h64.x[0] = E_out[g];
+    c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in[g]);
+    jc[g] = {c->ctrl, c->p.rtol, c->p.max_cycles, c->inner, c->host_ctrl_dev};
+    JobCoef& J = jf[g];
+    J.A.g = c->geom[0];
+    for (int d = 0; d < 3; ++d) J.A.dx[d] = c->p.dx[d];
+    J.A.dt = dt[g];
+    J.A.c = c->p.c;
+    J.A.limiter = c->p.limiter;
+    J.A.face_mean = c->p.face_mean;
+    J.E = E_in[g];
+    J.rho = rho[g];
+    J.kappa = kappa[g];
+    for (int d = 0; d < 3; ++d) {
+      J.O.a64[d] = c->h64.a[0][d];
+      J.O.a32[d] = c->mixed ? c->h32.a[0][d] : nullptr;
+    }
+    J.O.copy_dst = aliased ? c->bcopy : E_out[g];
+    J.O.partials = c->partials;
+    J.O.ctrl = c->ctrl;
+    bcoef[g] = blocks_for(c->geom[0].N);
+    fb[g] = {c->partials, bcoef[g], c->ctrl};
+    LevelView<double> v0;
+    v0.g = c->geom[0];
+    v0.x = c->h64.x[0];
+    v0.b = c->h64.b[0];
+    for (int d = 0; d < 3; ++d) v0.a[d] = c->h64.a[0][d];
+    jr[g] = {v0, c->mixed ? c->h32.b[0] : nullptr, c->partials, c->ctrl};
+    bres[g] = blocks_for(c->geom[0].N);
+    fr[g] = {c->partials, bres[g], c->ctrl};
+    jx[g] = {c->geom[0].N, c->h64.x[0], c->mixed ? c->h32.x[0] : nullptr,
+             c->ctrl};
+    fcy[g] = {c->partials,
+              tile2d_blocks(c->geom[0], c->p.pre_smooth, true), c->ctrl};
+  }
+  add_phase(im, B->ctrl, jc, one);
+  add_phase(im, B->coef, jf, bcoef);
+  add_phase(im, B->fin_b, fb, one);
+  add_phase(im, B->resid, jr, bres);
+  add_phase(im, B->fin_r, fr, one);
+  add_phase(im, B->correct, jx, bres);
+  add_phase(im, B->fin_c, fcy, one);
+  // coarse face coefficients of precision T, per level index
+  B->coarsen.assign(B->maxL > 1 ? B->maxL - 1 : 0, Phase());
+  for (int l = 0; l + 1 < B->maxL; ++l) {
+    std::vector<CoarsenArgs<T>> jobs;
+    std::vector<int> blocks;
+    for (int g = 0; g < ng; ++g) {
+      fld_ctx* c = B->sub[g];
+      if (l + 1 >= c->L) continue;
+      Levels<T>& H = hier<T>(c);
+      CoarsenArgs<T> a;
+      a.f = c->geom[l];
+      a.c = c->geom[l + 1];
+      for (int d = 0; d < 3; ++d) {
+        a.fa[d] = H.a[l][d];
+        a.ca[d] = H.a[l + 1][d];
+      }
+      jobs.push_back(a);
+      blocks.push_back(blocks_for(c->geom[l + 1].N));
+    }
+    add_phase(im, B->coarsen[l], jobs, blocks);
+  }
+  // multigrid tile passes per level index; variant 0 starts the finest
+  // iterate at zero (first FP32 cycle of a refinement iteration)
+  const bool mixed = B->sub[0]->mixed;
+  for (int v = 0; v < 2; ++v) {
+    B->down[v].assign(B->maxl0, Phase());
+    for (int l = 0; l < B->maxl0; ++l) {
+      std::vector<Tile2DArgs<T>> jobs;
+      std::vector<int> blocks;
+      for (int g = 0; g < ng; ++g) {
+        fld_ctx* c = B->sub[g];
+        if (l >= c->tail_l0) continue;
+        const bool zero = l > 0 || (mixed && v == 0);
+        double* parts = (!mixed && l == 0) ? c->partials : nullptr;
+        jobs.push_back(tile_job<T>(c, l, true, zero, parts));
+        blocks.push_back(tile2d_blocks(c->geom[l], c->p.pre_smooth, true));
+      }
+      add_phase(im, B->down[v][l], jobs, blocks);
+    }
+    std::vector<TailArgs<T>> tails(ng);
+    std::vector<int> ones(ng, 1);
+    size_t lds = 0;
+    for (int g = 0; g < ng; ++g) {
+      fld_ctx* c = B->sub[g];
+      TailArgs<T> t = tail_args<T>(c, hier<T>(c), c->tail_l0, false);
+      t.zero = c->tail_l0 > 0 || (mixed && v == 0);
+      tails[g] = t;
+      lds = std::max(lds, tail_lds_bytes<T>(t));
+    }
+    add_phase(im, B->tail[v], tails, ones);
+    B->tail_lds = lds;
+  }
+  B->up.assign(B->maxl0, Phase());
+  for (int l = 0; l < B->maxl0; ++l) {
+    std::vector<Tile2DArgs<T>> jobs;
+    std::vector<int> blocks;
+    for (int g = 0; g < ng; ++g) {
+      fld_ctx* c = B->sub[g];
+      if (l >= c->tail_l0) continue;
+      jobs.push_back(tile_job<T>(c, l, false, false, nullptr));
+      blocks.push_back(tile2d_blocks(c->geom[l], c->p.post_smooth, false));
+    }
+    add_phase(im, B->up[l], jobs, blocks);
+  }
+}
+
+template <typename X>
+const X* tab_ptr(BatchState* B, const Phase& ph) {
+  return (const X*)(B->dev_tab + ph.tab);
+}
+inline const int* start_ptr(BatchState* B, const Phase& ph) {
+  return (const int*)(B->dev_tab + ph.start);
+}
+
+// One V-cycle of precision T over all grids.  `var`: 0 = the finest iterate
+// starts at zero.
+template <typename T>
+fld_status batch_vcycle(fld_ctx* bc, int var) {
+  BatchState* B = bc->batch;
+  hipStream_t s = bc->stream;
+  const fld_params& p = B->sub[0]->p;
+  for (int l = 0; l < B->maxl0; ++l) {
+    const Phase& ph = B->down[var][l];
+    HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
+                                       start_ptr(B, ph), ph.ng, ph.nblocks,
+                                       p.pre_smooth, true, s));
+    if (sizeof(T) == 8 && l == 0)
+      HIP_TRY(bc, launch_finalize_batch(kFinCycle,
+                                        tab_ptr<JobFinalize>(B, B->fin_c),
+                                        B->fin_c.ng, s));
+  }
+  HIP_TRY(bc, launch_tail_lds_batch<T>(tab_ptr<TailArgs<T>>(B, B->tail[var]),
+                                       B->tail[var].ng, 2, B->tail_lds, s));
+  for (int l = B->maxl0 - 1; l >= 0; --l) {
+    const Phase& ph = B->up[l];
+    HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
+                                       start_ptr(B, ph), ph.ng, ph.nblocks,
+                                       p.post_smooth, false, s));
+  }
+  return FLD_OK;
+}
+
+// One refinement iteration (mixed) or one V-cycle (FP64) over all grids.
+fld_status batch_iteration(fld_ctx* bc) {
+  BatchState* B = bc->batch;
+  hipStream_t s = bc->stream;
+  if (!B->sub[0]->mixed) return batch_vcycle<double>(bc, 1);
+  HIP_TRY(bc, launch_resid_batch(tab_ptr<JobResid>(B, B->resid),
+                                 start_ptr(B, B->resid), B->resid.ng,
+                                 B->resid.nblocks, s));
+  HIP_TRY(bc, launch_finalize_batch(kFinOuter, tab_ptr<JobFinalize>(B, B->fin_r),
+                                    B->fin_r.ng, s));
+  const int inner = B->sub[0]->inner;
+  for (int i = 0; i < inner; ++i) FLD_TRY(batch_vcycle<float>(bc, i == 0 ? 0 : 1));
+  HIP_TRY(bc, launch_correct_batch(tab_ptr<JobCorrect>(B, B->correct),
+                                   start_ptr(B, B->correct), B->correct.ng,
+                                   B->correct.nblocks, s));
+  return FLD_OK;
+}
+
+// `iters` iterations, replayed from a captured graph when enabled.
+fld_status batch_iterations(fld_ctx* bc, int iters) {
+  BatchState* B = bc->batch;
+  if (!B->graph_on) {
+    for (int k = 0; k < iters; ++k) FLD_TRY(batch_iteration(bc));
+    return FLD_OK;
+  }
+  if (!B->gexec || B->graph_iters != iters) {
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->gexec = nullptr;
+    B->graph = nullptr;
+    HIP_TRY(bc, hipStreamBeginCapture(bc->stream, hipStreamCaptureModeRelaxed));
+    fld_status st = FLD_OK;
+    for (int k = 0; k < iters && st == FLD_OK; ++k) st = batch_iteration(bc);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(bc->stream, &g);
+    if (st != FLD_OK) return st;
+    if (e != hipSuccess)
+      return fail(bc, FLD_ERR_DEVICE, "hipStreamEndCapture: %s",
+                  hipGetErrorString(e));
+    B->graph = g;
+    HIP_TRY(bc, hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+    B->graph_iters = iters;
+  }
+  HIP_TRY(bc, hipGraphLaunch(B->gexec, bc->stream));
+  return FLD_OK;
+}
+
+bool all_stopped(BatchState* B) {
+  for (fld_ctx* c : B->sub)
+    if (c->host_ctrl->done == kRunning) return false;
+  return true;
+}
+
+template <typename T>
+fld_status batch_step_impl(fld_ctx* bc, const double* dt,
+                           const double* const* rho, const double* const* kappa,
+                           const double* const* E_in, double* const* E_out) {
+  BatchState* B = bc->batch;
+  hipStream_t s = bc->stream;
+  Image im;
+  build_image<T>(bc, im, dt, rho, kappa, E_in, E_out);
+  if (im.buf.size() > B->tab_cap)
+    return fail(bc, FLD_ERR_WORKSPACE, "batch table needs %zu bytes, has %zu",
+                im.buf.size(), B->tab_cap);
+  if (im.buf != B->last) {
+    memcpy(B->host_tab, im.buf.data(), im.buf.size());
+    HIP_TRY(bc, hipMemcpyAsync(B->dev_tab, B->host_tab, im.buf.size(),
+                               hipMemcpyHostToDevice, s));
+    B->last = im.buf;
+  }
+  HIP_TRY(bc, launch_ctrl_init_batch(tab_ptr<JobCtrl>(B, B->ctrl), B->ctrl.ng, s));
+  HIP_TRY(bc, launch_coef_batch(tab_ptr<JobCoef>(B, B->coef),
+                                start_ptr(B, B->coef), B->coef.ng,
+                                B->coef.nblocks, s));
+  HIP_TRY(bc, launch_finalize_batch(kFinBnorm, tab_ptr<JobFinalize>(B, B->fin_b),
+                                    B->fin_b.ng, s));
+  for (size_t l = 0; l < B->coarsen.size(); ++l) {
+    const Phase& ph = B->coarsen[l];
+    HIP_TRY(bc, launch_coarsen_batch<T>(tab_ptr<CoarsenArgs<T>>(B, ph),
+                                        start_ptr(B, ph), ph.ng, ph.nblocks, s));
+  }
+  if (sizeof(T) == 8) {
+    HIP_TRY(bc, launch_resid_batch(tab_ptr<JobResid>(B, B->resid),
+                                   start_ptr(B, B->resid), B->resid.ng,
+                                   B->resid.nblocks, s));
+    HIP_TRY(bc, launch_finalize_batch(kFinInitial,
+                                      tab_ptr<JobFinalize>(B, B->fin_r),
+                                      B->fin_r.ng, s));
+  }
+  int maxc = 0;
+  for (fld_ctx* c : B->sub) maxc = std::max(maxc, c->p.max_cycles);
+  const int max_iters =
+      B->sub[0]->mixed ? maxc / B->sub[0]->inner + 2 : maxc;
+  int done_iters = 0;
+  int batch = B->last_batch < 1 ? 1 : B->last_batch;
+  for (;;) {
+    if (batch > max_iters - done_iters) batch = max_iters - done_iters;
+    if (batch < 1) break;
+    FLD_TRY(batch_iterations(bc, batch));
+    done_iters += batch;
+    FLD_TRY(read_control(bc));
+    if (all_stopped(B) || done_iters >= max_iters) break;
+    batch = 1;
+  }
+  if (all_stopped(B)) B->last_batch = done_iters;
+  return FLD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void fld_params_default(fld_params* p) {
@@ -714,6 +1087,16 @@ fld_status fld_kernel_timing_read(fld_ctx* c, double* ms_total,
 
 void fld_destroy(fld_ctx* c) {
   if (!c) return;
+  if (c->batch) {
+    BatchState* B = c->batch;
+    for (fld_ctx* s : B->sub) fld_destroy(s);
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->host_tab) (void)hipHostFree(B->host_tab);
+    if (B->host_aux) (void)hipHostFree(B->host_aux);
+    delete B;
+    c->batch = nullptr;
+  }
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
   delete c;
@@ -734,6 +1117,299 @@ const char* fld_status_str(int32_t s) {
 
 const char* fld_last_error(const fld_ctx* c) {
   return c ? c->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"
+
+// ---- batched entry points --------------------------------------------------
+
+static std::string validate_batch(int32_t count, const fld_params* each) {
+  if (count < 1) return "count must be >= 1";
+  if (!each) return "params array is NULL";
+  for (int g = 0; g < count; ++g) {
+    std::string why = validate(&each[g]);
+    if (!why.empty()) return "grid " + std::to_string(g) + ": " + why;
+    const fld_params& p = each[g];
+    if (p.ndim != 2) return "batched grids must be 2D";
+    if (p.precision != each[0].precision)
+      return "batched grids must share the precision";
+    if (p.pre_smooth < 1 || p.pre_smooth > 3 || p.post_smooth < 1 ||
+        p.post_smooth > 3 || p.pre_smooth != each[0].pre_smooth ||
+        p.post_smooth != each[0].post_smooth)
+      return "batched grids need equal pre/post smoothing in 1..3";
+    if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
+    Plan P;
+    make_plan(&p, &P);
+    int l0 = P.L - 1;
+    for (int l = 0; l < P.L; ++l)
+      if (P.g[l].N <= kTailLdsCells) {
+        l0 = l;
+        break;
+      }
+    if (l0 == 0 || P.g[l0].N > kTailLdsCells || P.L - l0 > 10)
+      return "grid " + std::to_string(g) +
+             ": too small (<= 1024 cells) or not coarsenable to 1024 cells";
+  }
+  return "";
+}
+
+static size_t batch_sub_bytes(int32_t count, const fld_params* each,
+                              std::vector<size_t>* offs) {
+  size_t o = 0;
+  for (int g = 0; g < count; ++g) {
+    Plan P;
+    make_plan(&each[g], &P);
+    if (offs) offs->push_back(o);
+    o = align_up(o + P.total);
+  }
+  return o;
+}
+
+static size_t batch_aux_bytes(int32_t count) {
+  return 2 * (align_up(sizeof(JobOpacity) * count) +
+              align_up(sizeof(int) * (count + 1))) + 4 * kAlign;
+}
+
+extern "C" {
+
+size_t fld_workspace_bytes_batch(int32_t count, const fld_params* each) {
+  if (!validate_batch(count, each).empty()) return 0;
+  // table image size: build one with the real level structure
+  std::vector<size_t> offs;
+  const size_t subs = batch_sub_bytes(count, each, &offs);
+  fld_ctx tmp_batch;
+  BatchState B;
+  tmp_batch.batch = &B;
+  B.ng = count;
+  std::vector<fld_ctx> subs_ctx(count);
+  char* fake = (char*)kAlign;  // layout only: no memory is touched
+  for (int g = 0; g < count; ++g) {
+    Plan P;
+    make_plan(&each[g], &P);
+    fld_ctx* c = &subs_ctx[g];
+    c->p = each[g];
+    c->L = P.L;
+    c->mixed = each[g].precision == FLD_PREC_FP32_IR;
+    for (int l = 0; l < P.L; ++l) c->geom[l] = P.g[l];
+    c->tail_l0 = P.L - 1;
+    for (int l = 0; l < P.L; ++l)
+      if (P.g[l].N <= kTailLdsCells) {
+        c->tail_l0 = l;
+        break;
+      }
+    B.sub.push_back(c);
+    B.maxL = std::max(B.maxL, c->L);
+    B.maxl0 = std::max(B.maxl0, c->tail_l0);
+  }
+  std::vector<const double*> pc(count, (const double*)fake);
+  std::vector<double*> pm(count, (double*)fake);
+  std::vector<double> dts(count, 1.0);
+  Image im;
+  if (each[0].precision == FLD_PREC_FP32_IR)
+    build_image<float>(&tmp_batch, im, dts.data(), pc.data(), pc.data(),
+                       pc.data(), pm.data());
+  else
+    build_image<double>(&tmp_batch, im, dts.data(), pc.data(), pc.data(),
+                        pc.data(), pm.data());
+  tmp_batch.batch = nullptr;
+  return subs + align_up(im.buf.size() + kAlign) + batch_aux_bytes(count);
+}
+
+fld_status fld_setup_batch(int32_t count, const fld_params* each,
+                           void* workspace, size_t ws_bytes, void* hip_stream,
+                           fld_ctx** out) {
+  if (!out) return fail(nullptr, FLD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::string why = validate_batch(count, each);
+  if (!why.empty()) return fail(nullptr, FLD_ERR_INVALID_ARG, "%s", why.c_str());
+  const size_t need = fld_workspace_bytes_batch(count, each);
+  if (!workspace) return fail(nullptr, FLD_ERR_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)workspace % kAlign)
+    return fail(nullptr, FLD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(nullptr, FLD_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu",
+                ws_bytes, need);
+  std::vector<size_t> offs;
+  const size_t subs = batch_sub_bytes(count, each, &offs);
+  fld_ctx* bc = new fld_ctx();
+  bc->p = each[0];
+  bc->stream = (hipStream_t)hip_stream;
+  bc->ws = (char*)workspace;
+  bc->ws_bytes = ws_bytes;
+  BatchState* B = new BatchState();
+  bc->batch = B;
+  B->ng = count;
+  for (int g = 0; g < count; ++g) {
+    Plan P;
+    make_plan(&each[g], &P);
+    fld_ctx* c = nullptr;
+    fld_status st = fld_setup(&each[g], bc->ws + offs[g], P.total, hip_stream, &c);
+    if (st != FLD_OK) {
+      std::string msg = g_err;
+      fld_destroy(bc);
+      return fail(nullptr, st, "grid %d: %s", g, msg.c_str());
+    }
+    B->sub.push_back(c);
+    B->maxL = std::max(B->maxL, c->L);
+    B->maxl0 = std::max(B->maxl0, c->tail_l0);
+  }
+  B->aux_cap = batch_aux_bytes(count);
+  B->tab_cap = need - subs - B->aux_cap;
+  B->dev_tab = bc->ws + subs;
+  B->dev_aux = B->dev_tab + B->tab_cap;
+  hipError_t he = hipHostMalloc((void**)&B->host_tab, B->tab_cap, hipHostMallocDefault);
+  if (he == hipSuccess)
+    he = hipHostMalloc((void**)&B->host_aux, B->aux_cap, hipHostMallocDefault);
+  if (he != hipSuccess) {
+    fld_destroy(bc);
+    return fail(nullptr, FLD_ERR_DEVICE, "hipHostMalloc of the batch tables: %s",
+                hipGetErrorString(he));
+  }
+  *out = bc;
+  return FLD_OK;
+}
+
+fld_status fld_step_batch(fld_ctx* bc, const double* dt,
+                          const double* const* rho, const double* const* kappa,
+                          const double* const* E_in, double* const* E_out,
+                          fld_stats* stats) {
+  if (!bc || !bc->batch)
+    return fail(bc, FLD_ERR_INVALID_ARG, "not a batched context");
+  BatchState* B = bc->batch;
+  if (!dt || !rho || !kappa || !E_in || !E_out)
+    return fail(bc, FLD_ERR_INVALID_ARG, "NULL array");
+  for (int g = 0; g < B->ng; ++g) {
+    if (!(dt[g] > 0.0) || !std::isfinite(dt[g]))
+      return fail(bc, FLD_ERR_INVALID_ARG, "grid %d: dt must be positive", g);
+    if (!rho[g] || !kappa[g] || !E_in[g] || !E_out[g])
+      return fail(bc, FLD_ERR_INVALID_ARG, "grid %d: NULL field pointer", g);
+  }
+  if (B->sub[0]->mixed)
+    FLD_TRY((batch_step_impl<float>(bc, dt, rho, kappa, E_in, E_out)));
+  else
+    FLD_TRY((batch_step_impl<double>(bc, dt, rho, kappa, E_in, E_out)));
+  fld_status worst = FLD_OK;
+  int worst_g = -1;
+  for (int g = 0; g < B->ng; ++g) {
+    const Control& h = *B->sub[g]->host_ctrl;
+    if (stats) {
+      memset(&stats[g], 0, sizeof(fld_stats));
+      stats[g].cycles = h.cycles;
+      stats[g].outer_iters = B->sub[g]->mixed ? h.outer : 0;
+      stats[g].flagged_cells = h.flagged;
+      stats[g].rel_res_initial = h.res_initial;
+      stats[g].rel_res_final = h.res;
+    }
+    fld_status st = h.done == kConverged     ? FLD_OK
+                    : h.done == kNonPhysical ? FLD_ERR_NONPHYSICAL
+                                             : FLD_ERR_NOT_CONVERGED;
+    if (st != FLD_OK && (worst == FLD_OK || st == FLD_ERR_NONPHYSICAL)) {
+      worst = st;
+      worst_g = g;
+    }
+  }
+  if (worst != FLD_OK)
+    return fail(bc, worst, "grid %d: %s", worst_g,
+                worst == FLD_ERR_NONPHYSICAL ? "non-physical input"
+                                             : "not converged");
+  return FLD_OK;
+}
+
+}  // extern "C"
+
+// Tables of the pointwise batched calls: staged and uploaded per call
+// (after the previous use of the staging buffer has finished).
+template <typename X>
+static fld_status aux_upload(fld_ctx* bc, const std::vector<X>& jobs,
+                             const std::vector<int>& blocks, Phase* ph) {
+  BatchState* B = bc->batch;
+  Image im;
+  add_phase(im, *ph, jobs, blocks);
+  if (im.buf.size() > B->aux_cap)
+    return fail(bc, FLD_ERR_WORKSPACE, "aux table too large");
+  HIP_TRY(bc, hipStreamSynchronize(bc->stream));
+  memcpy(B->host_aux, im.buf.data(), im.buf.size());
+  HIP_TRY(bc, hipMemcpyAsync(B->dev_aux, B->host_aux, im.buf.size(),
+                             hipMemcpyHostToDevice, bc->stream));
+  return FLD_OK;
+}
+
+extern "C" {
+
+fld_status fld_exchange_batch(fld_ctx* bc, const double* dt,
+                              const double* const* rho,
+                              const double* const* kappa, double* const* E,
+                              double* const* e_int) {
+  if (!bc || !bc->batch)
+    return fail(bc, FLD_ERR_INVALID_ARG, "not a batched context");
+  BatchState* B = bc->batch;
+  if (!dt || !rho || !kappa || !E || !e_int)
+    return fail(bc, FLD_ERR_INVALID_ARG, "NULL array");
+  std::vector<JobExchange> jobs(B->ng);
+  std::vector<int> blocks(B->ng);
+  for (int g = 0; g < B->ng; ++g) {
+    if (!(dt[g] > 0.0) || !std::isfinite(dt[g]))
+      return fail(bc, FLD_ERR_INVALID_ARG, "grid %d: dt must be positive", g);
+    if (!rho[g] || !kappa[g] || !E[g] || !e_int[g])
+      return fail(bc, FLD_ERR_INVALID_ARG, "grid %d: NULL field pointer", g);
+    const fld_params& p = B->sub[g]->p;
+    jobs[g] = {B->sub[g]->geom[0].N, dt[g], p.c, p.a_rad, p.gamma - 1.0,
+               p.gas_const, rho[g], kappa[g], E[g], e_int[g]};
+    blocks[g] = blocks_for(B->sub[g]->geom[0].N);
+  }
+  Phase ph;
+  FLD_TRY(aux_upload(bc, jobs, blocks, &ph));
+  HIP_TRY(bc, launch_exchange_batch((const JobExchange*)(B->dev_aux + ph.tab),
+                                    (const int*)(B->dev_aux + ph.start), ph.ng,
+                                    ph.nblocks, bc->stream));
+  return FLD_OK;
+}
+
+fld_status fld_opacity_powerlaw_batch(fld_ctx* bc, const double* const* rho,
+                                      const double* const* e_int, double k0,
+                                      double a, double b, double kmin,
+                                      double kmax, double* const* kappa) {
+  if (!bc || !bc->batch)
+    return fail(bc, FLD_ERR_INVALID_ARG, "not a batched context");
+  BatchState* B = bc->batch;
+  if (!rho || !e_int || !kappa) return fail(bc, FLD_ERR_INVALID_ARG, "NULL array");
+  if (!(k0 > 0.0) || !(kmin > 0.0) || !(kmax >= kmin) || !std::isfinite(a) ||
+      !std::isfinite(b) || !std::isfinite(kmax))
+    return fail(bc, FLD_ERR_INVALID_ARG,
+                "need k0 > 0, 0 < kmin <= kmax, finite exponents");
+  int ha = INT_MIN, hb = INT_MIN;
+  if (2.0 * a == std::floor(2.0 * a) && 2.0 * b == std::floor(2.0 * b) &&
+      std::fabs(a) <= 16.0 && std::fabs(b) <= 16.0) {
+    ha = (int)(2.0 * a);
+    hb = (int)(2.0 * b);
+  }
+  std::vector<JobOpacity> jobs(B->ng);
+  std::vector<int> blocks(B->ng);
+  for (int g = 0; g < B->ng; ++g) {
+    if (!rho[g] || !e_int[g] || !kappa[g])
+      return fail(bc, FLD_ERR_INVALID_ARG, "grid %d: NULL field pointer", g);
+    const fld_params& p = B->sub[g]->p;
+    jobs[g] = {B->sub[g]->geom[0].N, p.gamma - 1.0, p.gas_const, rho[g],
+               e_int[g], k0, a, b, ha, hb, kmin, kmax, kappa[g]};
+    blocks[g] = blocks_for(B->sub[g]->geom[0].N);
+  }
+  Phase ph;
+  FLD_TRY(aux_upload(bc, jobs, blocks, &ph));
+  HIP_TRY(bc, launch_opacity_batch((const JobOpacity*)(B->dev_aux + ph.tab),
+                                   (const int*)(B->dev_aux + ph.start), ph.ng,
+                                   ph.nblocks, bc->stream));
+  return FLD_OK;
+}
+
+fld_status fld_batch_set_graph(fld_ctx* bc, int32_t on) {
+  if (!bc || !bc->batch)
+    return fail(bc, FLD_ERR_INVALID_ARG, "not a batched context");
+  if (on && bc->stream == nullptr)
+    return fail(bc, FLD_ERR_INVALID_ARG,
+                "graph capture needs a non-default stream (fld_setup_batch "
+                "was given the null stream)");
+  bc->batch->graph_on = on != 0;
+  return FLD_OK;
 }
 
 }  // extern "C"

@@ -114,6 +114,13 @@ hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
 // LDS variant (fld_tail.hip); *used = false when the levels do not fit.
 template <typename T>
 hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used);
+// LDS bytes the LDS tail needs (0 when the levels do not fit).
+template <typename T>
+size_t tail_lds_bytes(const TailArgs<T>& a);
+// Batched LDS tail: block g runs tab[g] (device memory); lds = max bytes.
+template <typename T>
+hipError_t launch_tail_lds_batch(const TailArgs<T>* tab, int ng, int nd,
+                                 size_t lds, hipStream_t s);
 
 hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
                             int inner, Control* mirror, hipStream_t s);

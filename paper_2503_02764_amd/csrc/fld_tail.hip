@@ -234,7 +234,7 @@ __device__ __forceinline__ void subcycle(T* S, const TL* tl, int l0, int nt,
 }  // namespace
 
 template <typename T, int ND>
-__global__ void __launch_bounds__(kReduceBlock) k_tail_lds(TailArgs<T> A) {
+__device__ __forceinline__ void tail_lds_body(const TailArgs<T>& A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double sh[kReduceBlock / 64];
   __shared__ double red;
@@ -341,6 +341,18 @@ __global__ void __launch_bounds__(kReduceBlock) k_tail_lds(TailArgs<T> A) {
   }
 }
 
+template <typename T, int ND>
+__global__ void __launch_bounds__(kReduceBlock) k_tail_lds(TailArgs<T> A) {
+  tail_lds_body<T, ND>(A);
+}
+
+// Batched form: block g runs the tail of grid g (arguments in device memory).
+template <typename T, int ND>
+__global__ void __launch_bounds__(kReduceBlock)
+    k_tail_lds_batch(const TailArgs<T>* __restrict__ tab) {
+  tail_lds_body<T, ND>(tab[blockIdx.x]);
+}
+
 template <typename T>
 size_t tail_lds_bytes(const TailArgs<T>& a) {
   if (a.lv[a.l0].g.N > kTailLdsCells || a.L - a.l0 > kMaxTail) return 0;
@@ -366,6 +378,25 @@ hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_tail_lds_batch(const TailArgs<T>* tab, int ng, int nd,
+                                 size_t lds, hipStream_t s) {
+  if (ng == 0) return hipSuccess;
+  if (nd == 1)
+    hipLaunchKernelGGL((k_tail_lds_batch<T, 1>), dim3(ng), dim3(kReduceBlock), lds, s, tab);
+  else if (nd == 2)
+    hipLaunchKernelGGL((k_tail_lds_batch<T, 2>), dim3(ng), dim3(kReduceBlock), lds, s, tab);
+  else
+    hipLaunchKernelGGL((k_tail_lds_batch<T, 3>), dim3(ng), dim3(kReduceBlock), lds, s, tab);
+  return hipGetLastError();
+}
+
+template size_t tail_lds_bytes<double>(const TailArgs<double>&);
+template size_t tail_lds_bytes<float>(const TailArgs<float>&);
+template hipError_t launch_tail_lds_batch<double>(const TailArgs<double>*, int,
+                                                  int, size_t, hipStream_t);
+template hipError_t launch_tail_lds_batch<float>(const TailArgs<float>*, int,
+                                                 int, size_t, hipStream_t);
 template hipError_t launch_tail_lds<double>(const TailArgs<double>&,
                                             hipStream_t, bool*);
 template hipError_t launch_tail_lds<float>(const TailArgs<float>&, hipStream_t,

@@ -31,5 +31,15 @@ hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
 
 // Number of tiles (blocks) the launcher will use.
 int tile2d_blocks(const Geom& g, int nu, bool down);
+// Same, also returning the tile grid (for the batched form's argument table).
+int tile2d_grid(const Geom& g, int nu, bool down, int* tiles_x, int* tiles_y);
+
+// Batched form: tab[g] (device memory, tiles_x/tiles_y filled in) are the
+// arguments of grid g, whose tiles are blocks start[g] .. start[g+1]-1 of a
+// launch of nblocks blocks.
+template <typename T>
+hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
+                               int ng, int nblocks, int nu, bool down,
+                               hipStream_t s);
 
 }  // namespace fld

@@ -64,8 +64,8 @@ __device__ __forceinline__ T block_sum_t(T v, T* sh, int nt) {
 }  // namespace
 
 template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
-__global__ void __launch_bounds__(RX / 2 * NPY)
-    k_tile2d(Tile2DArgs<T> A) {
+__device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
+                                            const int tile) {
   constexpr int NT = RX / 2 * NPY;
   constexpr int RY = NPY * K;
   constexpr int H = DOWN ? 2 * NU + 2 : 2 * NU;
@@ -76,7 +76,6 @@ __global__ void __launch_bounds__(RX / 2 * NPY)
   __shared__ double red[NT / 64 + 1];
   if (A.ctrl->done != kRunning) return;
 
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
   const int gx0 = txi * TX - H, gy0 = tyi * TY - H;  // region origin (even)
   const int px = threadIdx.x % (RX / 2), py = threadIdx.x / (RX / 2);
@@ -241,6 +240,56 @@ __global__ void __launch_bounds__(RX / 2 * NPY)
 }
 
 template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
+__global__ void __launch_bounds__(RX / 2 * NPY) k_tile2d(Tile2DArgs<T> A) {
+  tile2d_body<T, RX, NPY, K, NU, DOWN>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Batched form: the tiles of many independent grids in one launch.  Block
+// b (after the XCD renumbering) belongs to the grid g with
+// start[g] <= b < start[g + 1]; its arguments are tab[g] (device memory).
+template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
+__global__ void __launch_bounds__(RX / 2 * NPY)
+    k_tile2d_batch(const Tile2DArgs<T>* __restrict__ tab,
+                   const int* __restrict__ start, int ng) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {  // last g with start[g] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  tile2d_body<T, RX, NPY, K, NU, DOWN>(tab[lo], b - start[lo]);
+}
+
+template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
+static hipError_t launch_batch_one(const Tile2DArgs<T>* tab, const int* start,
+                                   int ng, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_tile2d_batch<T, RX, NPY, K, NU, DOWN>), dim3(nblocks),
+                     dim3(RX / 2 * NPY), 0, s, tab, start, ng);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
+                               int ng, int nblocks, int nu, bool down,
+                               hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (down) {
+    switch (nu) {
+      case 1: return launch_batch_one<T, 64, 8, 6, 1, true>(tab, start, ng, nblocks, s);
+      case 2: return launch_batch_one<T, 64, 8, 6, 2, true>(tab, start, ng, nblocks, s);
+      case 3: return launch_batch_one<T, 64, 8, 6, 3, true>(tab, start, ng, nblocks, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (nu) {
+    case 1: return launch_batch_one<T, 64, 8, 6, 1, false>(tab, start, ng, nblocks, s);
+    case 2: return launch_batch_one<T, 64, 8, 6, 2, false>(tab, start, ng, nblocks, s);
+    case 3: return launch_batch_one<T, 64, 8, 6, 3, false>(tab, start, ng, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
 static hipError_t launch_one(const Tile2DArgs<T>& a0, hipStream_t s,
                              int* nblocks) {
   constexpr int RY = NPY * K;
@@ -276,10 +325,17 @@ hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
 }
 
 int tile2d_blocks(const Geom& g, int nu, bool down) {
+  int tx, ty;
+  return tile2d_grid(g, nu, down, &tx, &ty);
+}
+
+int tile2d_grid(const Geom& g, int nu, bool down, int* tiles_x, int* tiles_y) {
   constexpr int RX = 64, RY = 48;
   const int H = down ? 2 * nu + 2 : 2 * nu;
   const int TX = RX - 2 * H, TY = RY - 2 * H;
-  return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
+  *tiles_x = (g.n[0] + TX - 1) / TX;
+  *tiles_y = (g.n[1] + TY - 1) / TY;
+  return *tiles_x * *tiles_y;
 }
 
 template hipError_t launch_tile2d<double>(const Tile2DArgs<double>&, int, bool,
@@ -287,4 +343,13 @@ template hipError_t launch_tile2d<double>(const Tile2DArgs<double>&, int, bool,
 template hipError_t launch_tile2d<float>(const Tile2DArgs<float>&, int, bool,
                                          hipStream_t, int*);
 
+}  // namespace fld
+
+namespace fld {
+template hipError_t launch_tile2d_batch<double>(const Tile2DArgs<double>*,
+                                                const int*, int, int, int,
+                                                bool, hipStream_t);
+template hipError_t launch_tile2d_batch<float>(const Tile2DArgs<float>*,
+                                               const int*, int, int, int, bool,
+                                               hipStream_t);
 }  // namespace fld

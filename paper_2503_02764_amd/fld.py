@@ -115,6 +115,7 @@ def load(path=LIB_PATH):
     lib.fld_status_str.restype = ctypes.c_char_p
     lib.fld_last_error.argtypes = [V]
     lib.fld_last_error.restype = ctypes.c_char_p
+    _batch_argtypes(lib)
     _lib = lib
     return lib
 
@@ -265,3 +266,137 @@ def fld_destroy(ctx):
     if ctx.ptr:
         load().fld_destroy(ctx.ptr)
         ctx.ptr = None
+
+
+# ---- batched grids -----------------------------------------------------------
+
+EXPORTED += ["fld_workspace_bytes_batch", "fld_setup_batch", "fld_step_batch",
+             "fld_exchange_batch", "fld_opacity_powerlaw_batch",
+             "fld_batch_set_graph"]
+
+
+def _batch_argtypes(lib):
+    P, V, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double
+    VP = P(ctypes.c_void_p)
+    lib.fld_workspace_bytes_batch.argtypes = [ctypes.c_int32, P(fld_params)]
+    lib.fld_workspace_bytes_batch.restype = ctypes.c_size_t
+    lib.fld_setup_batch.argtypes = [ctypes.c_int32, P(fld_params), V,
+                                    ctypes.c_size_t, V, P(V)]
+    lib.fld_setup_batch.restype = ctypes.c_int
+    lib.fld_step_batch.argtypes = [V, P(D), VP, VP, VP, VP, P(fld_stats)]
+    lib.fld_step_batch.restype = ctypes.c_int
+    lib.fld_exchange_batch.argtypes = [V, P(D), VP, VP, VP, VP]
+    lib.fld_exchange_batch.restype = ctypes.c_int
+    lib.fld_opacity_powerlaw_batch.argtypes = [V, VP, VP, D, D, D, D, D, VP]
+    lib.fld_opacity_powerlaw_batch.restype = ctypes.c_int
+    lib.fld_batch_set_graph.argtypes = [V, ctypes.c_int32]
+    lib.fld_batch_set_graph.restype = ctypes.c_int
+
+
+class BatchCtx:
+    """A batched fld_ctx* over `count` grids and the workspace it borrows."""
+
+    def __init__(self, ptr, params_list, workspace, stream):
+        self.ptr = ptr
+        self.params = params_list
+        self.workspace = workspace
+        self.stream = stream
+        self.count = len(params_list)
+        self.cells = [int(p.n[0] * p.n[1] * p.n[2]) for p in params_list]
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.fld_destroy(self.ptr)
+            self.ptr = None
+
+
+def _params_array(params_list):
+    arr = (fld_params * len(params_list))()
+    for i, p in enumerate(params_list):
+        arr[i] = p
+    return arr
+
+
+def fld_workspace_bytes_batch(params_list):
+    lib = load()
+    _batch_argtypes(lib)
+    arr = _params_array(params_list)
+    return int(lib.fld_workspace_bytes_batch(len(params_list), arr))
+
+
+def fld_setup_batch(params_list, workspace=None, stream=None):
+    import torch
+    lib = load()
+    _batch_argtypes(lib)
+    arr = _params_array(params_list)
+    need = int(lib.fld_workspace_bytes_batch(len(params_list), arr))
+    out = ctypes.c_void_p()
+    if need == 0:
+        st = lib.fld_setup_batch(len(params_list), arr, None, 0, None,
+                                 ctypes.byref(out))
+        _check(None, st)
+        raise FldError(FLD_ERR_INVALID_ARG, "invalid parameters")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.fld_setup_batch(len(params_list), arr,
+                             _ptr(workspace, "workspace", dtype=torch.uint8),
+                             workspace.numel(),
+                             ctypes.c_void_p(stream.cuda_stream),
+                             ctypes.byref(out))
+    _check(None, st)
+    return BatchCtx(out, params_list, workspace, stream)
+
+
+def _ptr_array(ctx, tensors, name):
+    import torch
+    if len(tensors) != ctx.count:
+        raise ValueError(f"{name}: expected {ctx.count} tensors")
+    arr = (ctypes.c_void_p * ctx.count)()
+    for i, t in enumerate(tensors):
+        arr[i] = _ptr(t, f"{name}[{i}]", ctx.cells[i], torch.float64).value
+    return arr
+
+
+def fld_step_batch(ctx, dts, rho, kappa, E_in, E_out, check=True):
+    """Diffusion step of every grid; returns (status, list of stats dicts)."""
+    lib = load()
+    dt = (ctypes.c_double * ctx.count)(*[float(v) for v in dts])
+    stats = (fld_stats * ctx.count)()
+    st = lib.fld_step_batch(ctx.ptr, dt, _ptr_array(ctx, rho, "rho"),
+                            _ptr_array(ctx, kappa, "kappa"),
+                            _ptr_array(ctx, E_in, "E_in"),
+                            _ptr_array(ctx, E_out, "E_out"), stats)
+    if check:
+        _check(ctx.ptr, st)
+    return st, [s.as_dict() for s in stats]
+
+
+def fld_exchange_batch(ctx, dts, rho, kappa, E, e_int, check=True):
+    lib = load()
+    dt = (ctypes.c_double * ctx.count)(*[float(v) for v in dts])
+    st = lib.fld_exchange_batch(ctx.ptr, dt, _ptr_array(ctx, rho, "rho"),
+                                _ptr_array(ctx, kappa, "kappa"),
+                                _ptr_array(ctx, E, "E"),
+                                _ptr_array(ctx, e_int, "e_int"))
+    if check:
+        _check(ctx.ptr, st)
+    return st
+
+
+def fld_opacity_powerlaw_batch(ctx, rho, e_int, k0, a, b, kmin, kmax, kappa,
+                               check=True):
+    lib = load()
+    st = lib.fld_opacity_powerlaw_batch(
+        ctx.ptr, _ptr_array(ctx, rho, "rho"), _ptr_array(ctx, e_int, "e_int"),
+        float(k0), float(a), float(b), float(kmin), float(kmax),
+        _ptr_array(ctx, kappa, "kappa"))
+    if check:
+        _check(ctx.ptr, st)
+    return st
+
+
+def fld_batch_set_graph(ctx, on=True):
+    lib = load()
+    _check(ctx.ptr, lib.fld_batch_set_graph(ctx.ptr, 1 if on else 0))

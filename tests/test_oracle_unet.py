@@ -1,0 +1,102 @@
+"""Pins of the CPU FP64 U-Net reference (the learned guess's arithmetic).
+
+- convolution against scipy.signal.correlate (an independent routine);
+- every parameter gradient and the input gradient against central finite
+  differences of the loss (FP64, relative error <= 1e-6 on sampled entries);
+- pooling/upsampling adjointness.
+"""
+import numpy as np
+import pytest
+from scipy.signal import correlate
+
+from oracle import unet_ref as U
+
+
+def test_conv_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 9, 7, 3))
+    w = rng.standard_normal((3, 3, 3, 5))
+    b = rng.standard_normal(5)
+    y = U.conv(x, w, b)
+    for n in range(2):
+        for co in range(5):
+            ref = b[co] + sum(
+                correlate(x[n, :, :, ci], w[:, :, ci, co], mode="same")
+                for ci in range(3))
+            np.testing.assert_allclose(y[n, :, :, co], ref, rtol=1e-12,
+                                       atol=1e-12)
+
+
+def test_pool_up_adjoint():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((1, 8, 6, 3))
+    y = rng.standard_normal((1, 4, 3, 3))
+    # <pool x, y> = <x, pool^T y>; <up y, x> = <y, up^T x>
+    assert np.isclose(np.sum(U.pool(x) * y), np.sum(x * U.pool_backward(y)))
+    assert np.isclose(np.sum(U.up(y) * x), np.sum(y * U.up_backward(x)))
+
+
+def _loss(p, x, t):
+    d, _ = U.forward(p, x)
+    return U.mse_loss(d, t)[0]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradients_vs_finite_differences(seed):
+    rng = np.random.default_rng(10 + seed)
+    p = U.init_params(seed)
+    for k in p:  # non-zero biases so every term is exercised
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((2, 8, 8, 4))
+    t = 0.1 * rng.standard_normal((2, 8, 8, 1))
+    d, cache = U.forward(p, x)
+    _, dd = U.mse_loss(d, t)
+    g, dx = U.backward(p, cache, dd)
+    h = 1e-6
+    for name in sorted(p):
+        flat = p[name].reshape(-1)
+        idx = rng.choice(flat.size, size=min(3, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            lp = _loss(p, x, t)
+            flat[i] = old - h
+            lm = _loss(p, x, t)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-6 * max(1e-3, abs(fd)) + 1e-10, \
+                (name, i, fd, an)
+    xf = x.reshape(-1)
+    for i in rng.choice(xf.size, size=5, replace=False):
+        old = xf[i]
+        xf[i] = old + h
+        lp = _loss(p, x, t)
+        xf[i] = old - h
+        lm = _loss(p, x, t)
+        xf[i] = old
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - dx.reshape(-1)[i]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-10
+
+
+def test_parameter_count():
+    p = U.init_params(0)
+    n = sum(v.size for v in p.values())
+    assert 480_000 < n < 500_000
+
+
+def test_adam_descends():
+    rng = np.random.default_rng(3)
+    p = U.init_params(3)
+    x = rng.standard_normal((1, 8, 8, 4))
+    t = 0.05 * rng.standard_normal((1, 8, 8, 1))
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    l0 = _loss(p, x, t)
+    for step in range(1, 30):
+        d, c = U.forward(p, x)
+        _, dd = U.mse_loss(d, t)
+        g, _ = U.backward(p, c, dd)
+        U.adam_step(p, g, m, v, step, lr=1e-3)
+    assert _loss(p, x, t) < 0.5 * l0
