@@ -14,10 +14,17 @@
 //             residual r = b - A x (and tests it), solves A e = r with
 //             `inner` FP32 V-cycles from e = 0 on FP32 copies of the face
 //             coefficients, and adds e to the FP64 iterate.
+//
+// Initial guess: E^n, zero, or the learned guess E^n (1 + delta) of the
+// U-Net (fld_unet_net.cpp), kept only when its FP64 residual is smaller
+// than that of E^n.
 #include "fld.h"
+#include "fldnn.h"
 #include "fld_internal.h"
 #include "fld_tile2d.h"
 #include "fld_batch.h"
+#include "fld_unet.h"
+#include "fld_unet_net.h"
 
 #include <hip/hip_runtime.h>
 
@@ -77,6 +84,11 @@ struct fld_ctx {
   bool fast = true;  // tiled kernels + single-workgroup tail
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
+  // learned guess: network carved out of net_ws by fld_set_model
+  nn::Net* net = nullptr;
+  char* net_ws = nullptr;
+  size_t net_bytes = 0;
+  double* mean = nullptr;  // per-slice mean of log E (network features)
 };
 
 namespace {
@@ -119,7 +131,8 @@ struct Plan {
   Geom g[kMaxLevels];
   size_t a64[kMaxLevels][3] = {}, x64[kMaxLevels] = {}, b64[kMaxLevels] = {};
   size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
-  size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0;
+  size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
+  size_t net_bytes = 0;
   int64_t n_partials = 0;
   size_t total = 0;
 };
@@ -170,8 +183,12 @@ std::string validate(const fld_params* p) {
   if (p->face_mean < 0 || p->face_mean > 1) return "unknown face mean";
   if (p->precision != FLD_PREC_FP64 && p->precision != FLD_PREC_FP32_IR)
     return "unknown precision";
-  if (p->guess != FLD_GUESS_PREV && p->guess != FLD_GUESS_ZERO)
-    return "guess: only FLD_GUESS_PREV and FLD_GUESS_ZERO are built";
+  if (p->guess != FLD_GUESS_PREV && p->guess != FLD_GUESS_ZERO &&
+      p->guess != FLD_GUESS_LEARNED)
+    return "unknown guess";
+  if (p->guess == FLD_GUESS_LEARNED &&
+      (p->ndim < 2 || p->n[0] % 8 || p->n[1] % 8))
+    return "the learned guess needs ndim >= 2 and n[0], n[1] multiples of 8";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
   if (p->pre_smooth < 0 || p->post_smooth < 0 ||
@@ -234,6 +251,12 @@ void make_plan(const fld_params* p, Plan* P) {
   P->partials = take((size_t)P->n_partials * 8);
   P->tmp = take((size_t)P->g[P->L - 1].N * 8);
   P->ctrl = take(sizeof(Control));
+  if (p->ndim >= 2) P->mean = take((size_t)p->n[2] * 8);
+  if (p->guess == FLD_GUESS_LEARNED) {
+    P->net_bytes = nn::workspace_bytes((int)p->n[2], (int)p->n[1],
+                                       (int)p->n[0], 0);
+    P->net = take(P->net_bytes);
+  }
   P->total = o;
 }
 
@@ -953,6 +976,11 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   c->h64.tmp = (double*)(w + P.tmp);
   c->h32.tmp = (float*)(w + P.tmp);
   c->ctrl = (Control*)(w + P.ctrl);
+  if (p->ndim >= 2) c->mean = (double*)(w + P.mean);
+  if (p->guess == FLD_GUESS_LEARNED) {
+    c->net_ws = w + P.net;
+    c->net_bytes = P.net_bytes;
+  }
   hipError_t he = hipHostMalloc((void**)&c->host_ctrl, sizeof(Control),
                                 hipHostMallocMapped | hipHostMallocCoherent);
   if (he == hipSuccess)
@@ -968,6 +996,34 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   return FLD_OK;
 }
 
+namespace {
+
+// x (= E^n on entry) <- E^n (1 + delta) of the network, unless the guess's
+// FP64 residual is not smaller than that of E^n.  Entirely on the device;
+// the decision lands in ctrl->guess_rejected.
+fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
+  const LevelView<double> v0 = view(c, c->h64, 0);
+  const Geom& g = c->geom[0];
+  const int64_t slice = (int64_t)g.n[0] * g.n[1];
+  int nb = 0;
+  HIP_TRY(c, launch_resid_norm<double>(v0, c->partials, &nb, c->ctrl, c->stream));
+  HIP_TRY(c, launch_guess_judge(0, c->partials, nb, c->ctrl, c->stream));
+  HIP_TRY(c, nn::launch_mean_log(v0.b, slice, g.n[2], c->mean, c->stream));
+  HIP_TRY(c, nn::launch_features(v0.b, rho, kappa, c->h64.a[0][0],
+                                 c->h64.a[0][1], c->p.dx[0], c->mean, g.N,
+                                 slice, nn::input_ptr(c->net), nullptr,
+                                 c->stream));
+  HIP_TRY(c, nn::forward_x(c->net));
+  HIP_TRY(c, nn::launch_apply_guess(v0.b, nn::delta_ptr(c->net), g.N, v0.x,
+                                    c->stream));
+  HIP_TRY(c, launch_resid_norm<double>(v0, c->partials, &nb, c->ctrl, c->stream));
+  HIP_TRY(c, launch_guess_judge(1, c->partials, nb, c->ctrl, c->stream));
+  HIP_TRY(c, launch_guess_restore(g.N, v0.b, v0.x, c->ctrl, c->stream));
+  return FLD_OK;
+}
+
+}  // namespace
+
 fld_status fld_step(fld_ctx* c, double dt, const double* rho,
                     const double* kappa, const double* E_in, double* E_out,
                     fld_stats* stats) {
@@ -976,6 +1032,8 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
     return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
   if (!(dt > 0.0) || !std::isfinite(dt))
     return fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
+  if (c->p.guess == FLD_GUESS_LEARNED && !c->net)
+    return fail(c, FLD_ERR_MODEL, "no model: call fld_set_model first");
   const bool aliased = (E_in == E_out);
   const Geom& g0 = c->geom[0];
   // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it)
@@ -1013,12 +1071,14 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
   }
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
+  if (c->p.guess == FLD_GUESS_LEARNED) FLD_TRY(learned_guess(c, rho, kappa));
   FLD_TRY(c->mixed ? solve_mixed(c) : solve_fp64(c));
   FLD_TRY(collect_timing(c));
   const Control& h = *c->host_ctrl;
   if (stats) {
     memset(stats, 0, sizeof *stats);
     stats->cycles = h.cycles;
+    stats->guess_rejected = h.guess_rejected;
     stats->outer_iters = c->mixed ? h.outer : 0;
     stats->flagged_cells = h.flagged;
     stats->rel_res_initial = h.res_initial;
@@ -1085,8 +1145,62 @@ fld_status fld_kernel_timing_read(fld_ctx* c, double* ms_total,
   return FLD_OK;
 }
 
+fld_status fld_set_model(fld_ctx* c, const float* host, size_t count) {
+  if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (!host) return fail(c, FLD_ERR_INVALID_ARG, "weights pointer is NULL");
+  if (c->p.guess != FLD_GUESS_LEARNED || !c->net_ws)
+    return fail(c, FLD_ERR_INVALID_ARG,
+                "the context was not set up with FLD_GUESS_LEARNED");
+  if (count != nn::param_count())
+    return fail(c, FLD_ERR_MODEL, "%zu parameters given, the network has %zu",
+                count, nn::param_count());
+  if (!c->net) {
+    std::string err;
+    const Geom& g = c->geom[0];
+    c->net = nn::create(g.n[2], g.n[1], g.n[0], 0, c->net_ws, c->net_bytes,
+                        c->stream, &err);
+    if (!c->net) return fail(c, FLD_ERR_DEVICE, "%s", err.c_str());
+  }
+  if (!nn::set_params(c->net, host, count))
+    return fail(c, FLD_ERR_MODEL, "non-finite parameter or device error");
+  return FLD_OK;
+}
+
+fld_status fld_features(fld_ctx* c, double dt, const double* rho,
+                        const double* kappa, const double* E, float* out) {
+  if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->batch) return fail(c, FLD_ERR_INVALID_ARG, "batched context");
+  if (c->p.ndim < 2) return fail(c, FLD_ERR_INVALID_ARG, "needs ndim >= 2");
+  if (!rho || !kappa || !E || !out)
+    return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
+  const Geom& g0 = c->geom[0];
+  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles, c->inner,
+                             nullptr, c->stream));
+  CoefArgs A;
+  A.g = g0;
+  for (int d = 0; d < 3; ++d) A.dx[d] = c->p.dx[d];
+  A.dt = dt;
+  A.c = c->p.c;
+  A.limiter = c->p.limiter;
+  A.face_mean = c->p.face_mean;
+  HIP_TRY(c, launch_coef(A, E, rho, kappa, c->h64.a[0], c->h32.a[0], nullptr,
+                         c->partials, c->ctrl, c->stream));
+  const int64_t slice = (int64_t)g0.n[0] * g0.n[1];
+  HIP_TRY(c, nn::launch_mean_log(E, slice, g0.n[2], c->mean, c->stream));
+  HIP_TRY(c, nn::launch_features(E, rho, kappa, c->h64.a[0][0], c->h64.a[0][1],
+                                 c->p.dx[0], c->mean, g0.N, slice, nullptr, out,
+                                 c->stream));
+  return FLD_OK;
+}
+
 void fld_destroy(fld_ctx* c) {
   if (!c) return;
+  if (c->net) {
+    nn::destroy(c->net);
+    c->net = nullptr;
+  }
   if (c->batch) {
     BatchState* B = c->batch;
     for (fld_ctx* s : B->sub) fld_destroy(s);

@@ -136,6 +136,8 @@ __device__ __forceinline__ void ctrl_init_body(Control* ctrl, double rtol,
     ctrl->cycles = 0;
     ctrl->max_cycles = max_cycles;
     ctrl->flagged = 0;
+    ctrl->guess_ref = 0.0;
+    ctrl->guess_rejected = 0;
   }
 }
 

@@ -38,12 +38,14 @@ struct Control {
   double res_initial; // |b - A x0| / |b|
   double res;         // relative residual of the returned iterate
   double rtol;
+  double guess_ref;   // |b - A E^n|^2, the learned guess's benchmark
   int32_t done;       // 0 running, 1 converged, 2 cycle cap, 3 non-physical
   int32_t cycles;
   int32_t max_cycles;
   int32_t flagged;    // non-physical cells seen by the coefficient kernel
   int32_t outer;      // refinement iterations (corrections applied)
   int32_t inner;      // FP32 V-cycles per refinement iteration
+  int32_t guess_rejected;  // 1 when the learned guess lost to E^n
   Control* mirror;    // device address of the host-visible copy (or null)
 };
 
@@ -125,6 +127,14 @@ hipError_t launch_tail_lds_batch(const TailArgs<T>* tab, int ng, int nd,
 hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
                             int inner, Control* mirror, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+// Learned guess judge: mode 0 stores the summed partials as the benchmark
+// |b - A E^n|^2; mode 1 rejects the guess when its |b - A x|^2 is not
+// smaller (or not finite).  launch_guess_restore then sets x = b (= E^n)
+// where the guess was rejected.
+hipError_t launch_guess_judge(int mode, const double* partials, int count,
+                              Control* ctrl, hipStream_t s);
+hipError_t launch_guess_restore(int64_t n, const double* b, double* x,
+                                const Control* ctrl, hipStream_t s);
 hipError_t launch_fill32(float* x, int64_t n, hipStream_t s);
 
 // Levels up to this many cells run in the single-workgroup tail, in LDS.

@@ -69,6 +69,43 @@ hipError_t launch_finalize(int mode, const double* partials, int count,
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(kReduceBlock)
+    k_guess_judge(int mode, const double* __restrict__ partials, int count,
+                  Control* ctrl) {
+  __shared__ double sh[kReduceBlock / 64];
+  if (ctrl->done != kRunning) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += kReduceBlock) v += partials[i];
+  const double s = block_sum<kReduceBlock>(v, sh);
+  if (threadIdx.x != 0) return;
+  if (mode == 0)
+    ctrl->guess_ref = s;
+  else
+    ctrl->guess_rejected = (s < ctrl->guess_ref) ? 0 : 1;  // NaN: rejected
+}
+
+hipError_t launch_guess_judge(int mode, const double* partials, int count,
+                              Control* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_judge, dim3(1), dim3(kReduceBlock), 0, s, mode,
+                     partials, count, ctrl);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_guess_restore(int64_t n, const double* __restrict__ b,
+                    double* __restrict__ x, const Control* ctrl) {
+  if (ctrl->done != kRunning || !ctrl->guess_rejected) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = b[i];
+}
+
+hipError_t launch_guess_restore(int64_t n, const double* b, double* x,
+                                const Control* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_restore, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                     n, b, x, ctrl);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // coefficient stage
 // ---------------------------------------------------------------------------

@@ -1,0 +1,601 @@
+// Kernels of the learned initial guess: a small 2D U-Net in BF16 with FP32
+// accumulation on the gfx950 matrix cores.
+//
+// Activations are NHWC BF16 tensors addressed through (stride, offset) views
+// so that a concatenation is just two producers writing disjoint channel
+// slices of one buffer.  Gradients are FP32 tensors of the same views.
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: per MFMA a
+// wave multiplies 16 pixels x 16 input channels (A) by 16 input channels x
+// 16 output channels (B) of one filter tap.  Operand layout (verified on the
+// device): lane l holds A[m = l%16][k = 4(l/16) .. +3], B[k = 4(l/16) .. +3]
+// [n = l%16], and receives D[m = 4(l/16) .. +3][n = l%16].
+//   forward / input gradient: M = pixels, N = output channels, K = taps x Cin
+//   weight gradient:          M = output channels, N = input channels,
+//                             K = pixels (partial tiles summed with atomics)
+// Weights are stored per tap as [co][ci] (BF16 for the GEMMs, FP32 master
+// copy for the optimizer), channels padded to multiples of 16.
+#include "fld_unet.h"
+
+namespace fld {
+namespace nn {
+
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+// four consecutive channels of one pixel as an MFMA operand
+__device__ __forceinline__ bf16x4 load4_bf(const uint16_t* p) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  bf16x4 r;
+  r[0] = (short)(v.x & 0xffff);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xffff);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+
+__device__ __forceinline__ bf16x4 load4_f32(const float* p) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  bf16x4 r;
+  r[0] = (short)f2bf(v.x);
+  r[1] = (short)f2bf(v.y);
+  r[2] = (short)f2bf(v.z);
+  r[3] = (short)f2bf(v.w);
+  return r;
+}
+
+__device__ __forceinline__ bf16x4 zero4() {
+  bf16x4 r;
+  r[0] = r[1] = r[2] = r[3] = 0;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// convolution (forward, and input gradient with flipped/transposed weights)
+// ---------------------------------------------------------------------------
+
+// Block: 4 waves, 64 consecutive pixels of one image row; wave w owns
+// pixels x0 + 16w .. +15 and NCO chunks of 16 output channels starting at
+// chunk `cg * NCO` (blockIdx.z = n * groups + cg).
+template <int NCO>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int groups = (A.cout_pad / 16 + NCO - 1) / NCO;
+  const int n = blockIdx.z / groups, cg = blockIdx.z % groups;
+  const int y = blockIdx.y;
+  const int x0 = blockIdx.x * 64 + wv * 16;
+  const int m = l & 15, kq = l >> 4;
+  const int r = A.ksize / 2;
+  const int taps = A.ksize * A.ksize;
+  const int cchunks = A.cin_pad / 16;
+  f32x4 acc[NCO];
+#pragma unroll
+  for (int j = 0; j < NCO; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < taps; ++t) {
+    const int yy = y + t / A.ksize - r;
+    const int xx = x0 + m + t % A.ksize - r;
+    const bool valid = yy >= 0 && yy < A.H && xx >= 0 && xx < A.W;
+    const int64_t pix = ((int64_t)n * A.H + (valid ? yy : 0)) * A.W + (valid ? xx : 0);
+    for (int cc = 0; cc < cchunks; ++cc) {
+      const int ci = cc * 16 + 4 * kq;
+      bf16x4 a;
+      if (!valid)
+        a = zero4();
+      else if (A.in_f32)
+        a = load4_f32((const float*)A.in + pix * A.in_stride + A.in_off + ci);
+      else
+        a = load4_bf((const uint16_t*)A.in + pix * A.in_stride + A.in_off + ci);
+#pragma unroll
+      for (int j = 0; j < NCO; ++j) {
+        const int co = (cg * NCO + j) * 16 + m;
+        if ((cg * NCO + j) * 16 < A.cout_pad) {
+          const bf16x4 b =
+              load4_bf(A.w + ((int64_t)t * A.cout_pad + co) * A.cin_pad + ci);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NCO; ++j) {
+    const int co = (cg * NCO + j) * 16 + m;
+    if ((cg * NCO + j) * 16 >= A.cout_pad || co >= A.cout) continue;
+    const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int x = x0 + 4 * kq + i;
+      if (x >= A.W) continue;
+      const int64_t o = (((int64_t)n * A.H + y) * A.W + x) * A.out_stride + A.out_off + co;
+      float v = acc[j][i] + bias;
+      if (A.relu) v = fmaxf(v, 0.f);
+      if (A.out_f32) {
+        float* out = (float*)A.out;
+        out[o] = A.accumulate ? out[o] + v : v;
+      } else {
+        uint16_t* out = (uint16_t*)A.out;
+        out[o] = f2bf(A.accumulate ? bf2f(out[o]) + v : v);
+      }
+    }
+  }
+}
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
+  const int chunks = a.cout_pad / 16;
+  const int nco = chunks >= 4 ? 4 : chunks;
+  const int groups = (chunks + nco - 1) / nco;
+  dim3 grid((a.W + 63) / 64, a.H, a.N * groups);
+  switch (nco) {
+    case 1: hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_conv<2>, grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_conv<3>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_conv<4>, grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[t][co][ci] += sum_p in[p + off_t][ci] dz[p][co]
+// ---------------------------------------------------------------------------
+
+// grid.x: groups of 4 (tap, co chunk, ci chunk) tiles, one per wave;
+// grid.y: slices of `rows` image rows.  Partial tiles are added to dW.
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + wv;
+  const int coc = A.cout_pad / 16, cic = A.cin_pad / 16;
+  const int taps = A.ksize * A.ksize;
+  if (tile >= taps * coc * cic) return;
+  const int t = tile / (coc * cic);
+  const int co0 = ((tile / cic) % coc) * 16;
+  const int ci0 = (tile % cic) * 16;
+  const int r = A.ksize / 2;
+  const int dy = t / A.ksize - r, dx = t % A.ksize - r;
+  const int m = l & 15, kq = l >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int row0 = blockIdx.y * A.rows;
+  const int row1 = min(row0 + A.rows, A.N * A.H);
+  for (int row = row0; row < row1; ++row) {
+    const int n = row / A.H, y = row % A.H;
+    const int yy = y + dy;
+    const bool yok = yy >= 0 && yy < A.H;
+    for (int xb = 0; xb < A.W; xb += 16) {
+      bf16x4 a, b;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = xb + 4 * kq + j;
+        float av = 0.f, bv = 0.f;
+        if (x < A.W) {
+          const int64_t p = ((int64_t)n * A.H + y) * A.W + x;
+          av = A.dz[p * A.dz_stride + A.dz_off + co0 + m];
+          const int xx = x + dx;
+          if (yok && xx >= 0 && xx < A.W) {
+            const int64_t q = ((int64_t)n * A.H + yy) * A.W + xx;
+            bv = bf2f(A.in[q * A.in_stride + A.in_off + ci0 + m]);
+          }
+        }
+        a[j] = (short)f2bf(av);
+        b[j] = (short)f2bf(bv);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D[co0 + 4kq + i][ci0 + m]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int co = co0 + 4 * kq + i;
+    atomicAdd(&A.dw[((int64_t)t * A.cout_pad + co) * A.cin_pad + ci0 + m], acc[i]);
+  }
+}
+
+hipError_t launch_wgrad(const WgradArgs& a0, hipStream_t s) {
+  WgradArgs a = a0;
+  const int tiles = a.ksize * a.ksize * (a.cout_pad / 16) * (a.cin_pad / 16);
+  const int rows_total = a.N * a.H;
+  // aim for about 2048 blocks in flight
+  const int gx = (tiles + 3) / 4;
+  int slices = 2048 / gx;
+  if (slices < 1) slices = 1;
+  if (slices > rows_total) slices = rows_total;
+  a.rows = (rows_total + slices - 1) / slices;
+  const int gy = (rows_total + a.rows - 1) / a.rows;
+  hipLaunchKernelGGL(k_wgrad, dim3(gx, gy), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// bias gradient: db[co] += sum_p dz[p][co] (block partial sums + atomics)
+__global__ void __launch_bounds__(256)
+    k_bgrad(const float* __restrict__ dz, int64_t P, int stride, int off,
+            int cout, float* __restrict__ db) {
+  // thread handles channel c = tid % 16 + 16 * (blockIdx.y) for pixels
+  // strided by 16 within this block's range
+  const int c = blockIdx.y * 16 + (threadIdx.x & 15);
+  const int lane_p = threadIdx.x >> 4;  // 0..15
+  if (c >= cout) return;
+  const int64_t p0 = (int64_t)blockIdx.x * 1024;
+  float s = 0.f;
+  for (int64_t p = p0 + lane_p; p < p0 + 1024 && p < P; p += 16)
+    s += dz[p * stride + off + c];
+  atomicAdd(&db[c], s);
+}
+
+hipError_t launch_bgrad(const float* dz, int64_t P, int stride, int off,
+                        int cout, float* db, hipStream_t s) {
+  dim3 grid((unsigned)((P + 1023) / 1024), (cout + 15) / 16);
+  hipLaunchKernelGGL(k_bgrad, grid, dim3(256), 0, s, dz, P, stride, off, cout,
+                     db);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise pieces
+// ---------------------------------------------------------------------------
+
+// 2x2 average pool, BF16 -> BF16 (C channels of two views)
+__global__ void k_pool(const uint16_t* __restrict__ in, int is, int io,
+                       uint16_t* __restrict__ out, int os, int oo, int N,
+                       int Ho, int Wo, int C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)N * Ho * Wo * C;
+  if (i >= total) return;
+  const int c = i % C;
+  int64_t p = i / C;
+  const int x = p % Wo;
+  p /= Wo;
+  const int y = p % Ho;
+  const int n = p / Ho;
+  const int Wi = 2 * Wo, Hi = 2 * Ho;
+  float s = 0.f;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int64_t q = ((int64_t)n * Hi + 2 * y + dy) * Wi + 2 * x + dx;
+      s += bf2f(in[q * is + io + c]);
+    }
+  out[(((int64_t)n * Ho + y) * Wo + x) * os + oo + c] = f2bf(0.25f * s);
+}
+
+// gradient of the pool: g_in[child] += 1/4 g_out[parent] (FP32)
+__global__ void k_pool_bwd(const float* __restrict__ gout, int gs, int go,
+                           float* __restrict__ gin, int is, int io, int N,
+                           int Ho, int Wo, int C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int Hi = 2 * Ho, Wi = 2 * Wo;
+  const int64_t total = (int64_t)N * Hi * Wi * C;
+  if (i >= total) return;
+  const int c = i % C;
+  int64_t p = i / C;
+  const int x = p % Wi;
+  p /= Wi;
+  const int y = p % Hi;
+  const int n = p / Hi;
+  const int64_t q = (((int64_t)n * Ho + y / 2) * Wo + x / 2);
+  gin[(((int64_t)n * Hi + y) * Wi + x) * is + io + c] += 0.25f * gout[q * gs + go + c];
+}
+
+// nearest 2x upsampling, BF16 -> BF16 view
+__global__ void k_up(const uint16_t* __restrict__ in, int is, int io,
+                     uint16_t* __restrict__ out, int os, int oo, int N, int Hi,
+                     int Wi, int C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int Ho = 2 * Hi, Wo = 2 * Wi;
+  const int64_t total = (int64_t)N * Ho * Wo * C;
+  if (i >= total) return;
+  const int c = i % C;
+  int64_t p = i / C;
+  const int x = p % Wo;
+  p /= Wo;
+  const int y = p % Ho;
+  const int n = p / Ho;
+  const int64_t q = ((int64_t)n * Hi + y / 2) * Wi + x / 2;
+  out[(((int64_t)n * Ho + y) * Wo + x) * os + oo + c] = in[q * is + io + c];
+}
+
+// gradient of the upsampling: g_in[parent] = sum of the 4 children (FP32)
+__global__ void k_up_bwd(const float* __restrict__ gout, int gs, int go,
+                         float* __restrict__ gin, int is, int io, int N, int Hi,
+                         int Wi, int C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)N * Hi * Wi * C;
+  if (i >= total) return;
+  const int c = i % C;
+  int64_t p = i / C;
+  const int x = p % Wi;
+  p /= Wi;
+  const int y = p % Hi;
+  const int n = p / Hi;
+  const int Ho = 2 * Hi, Wo = 2 * Wi;
+  float s = 0.f;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx)
+      s += gout[(((int64_t)n * Ho + 2 * y + dy) * Wo + 2 * x + dx) * gs + go + c];
+  gin[(((int64_t)n * Hi + y) * Wi + x) * is + io + c] = s;
+}
+
+// ReLU gradient in place: g *= (a > 0)
+__global__ void k_relu_bwd(float* __restrict__ g, int gs, int go,
+                           const uint16_t* __restrict__ a, int as, int ao,
+                           int64_t P, int C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P * C) return;
+  const int64_t p = i / C;
+  const int c = i % C;
+  if (!(bf2f(a[p * as + ao + c]) > 0.f)) g[p * gs + go + c] = 0.f;
+}
+
+// 1x1 head: delta[p] = b + sum_c u[p][c] w[c]  (FP32)
+__global__ void k_head(const uint16_t* __restrict__ u, int us, int uo,
+                       const float* __restrict__ w, const float* __restrict__ b,
+                       int C, int64_t P, float* __restrict__ delta) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  float s = b[0];
+  for (int c = 0; c < C; ++c) s += bf2f(u[p * us + uo + c]) * w[c];
+  delta[p] = s;
+}
+
+// MSE loss and its gradient: g = 2 (delta - target) / P; partial losses
+__global__ void __launch_bounds__(256)
+    k_mse(const float* __restrict__ delta, const float* __restrict__ target,
+          int64_t P, float* __restrict__ g, float* __restrict__ loss) {
+  __shared__ float sh[4];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float d2 = 0.f;
+  if (p < P) {
+    const float d = delta[p] - target[p];
+    g[p] = 2.f * d / (float)P;
+    d2 = d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_down(d2, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (float)P);
+}
+
+// head backward: du[p][c] = g[p] w[c]; dw[c] += sum_p g[p] u[p][c]; db += sum g
+__global__ void __launch_bounds__(256)
+    k_head_bwd(const float* __restrict__ g, const uint16_t* __restrict__ u,
+               int us, int uo, const float* __restrict__ w, int C, int64_t P,
+               float* __restrict__ du, int dus, int duo,
+               float* __restrict__ dw, float* __restrict__ db) {
+  __shared__ float sw[64 + 1];
+  if (threadIdx.x <= C) sw[threadIdx.x] = 0.f;
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p < P) {
+    const float gp = g[p];
+    for (int c = 0; c < C; ++c) {
+      du[p * dus + duo + c] = gp * w[c];
+      atomicAdd(&sw[c], gp * bf2f(u[p * us + uo + c]));
+    }
+    atomicAdd(&sw[C], gp);
+  }
+  __syncthreads();
+  if (threadIdx.x < C) atomicAdd(&dw[threadIdx.x], sw[threadIdx.x]);
+  if (threadIdx.x == C) atomicAdd(db, sw[C]);
+}
+
+// Adam on the FP32 master weights; refreshes the BF16 GEMM copy.
+__global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ w16,
+                       const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (w16) w16[i] = f2bf(wi);
+}
+
+__global__ void k_zero(float* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ w16,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) w16[i] = f2bf(w[i]);
+}
+
+// Weights of the input gradient: Wd[t][ci][co] = W[taps-1-t][co][ci]
+__global__ void k_flip(const uint16_t* __restrict__ w, uint16_t* __restrict__ wd,
+                       int taps, int cout_pad, int cin_pad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)taps * cout_pad * cin_pad;
+  if (i >= n) return;
+  const int co = i % cout_pad;
+  int64_t r = i / cout_pad;
+  const int ci = r % cin_pad;
+  const int t = r / cin_pad;
+  wd[i] = w[((int64_t)(taps - 1 - t) * cout_pad + co) * cin_pad + ci];
+}
+
+// Network inputs from the step's data: log E minus its mean over the image,
+// log optical depth of a cell, log(1 + alpha) of the two face coefficients
+// (diffusion numbers); each scaled to order one.  mean_logE (one value per
+// image of `slice` cells) is read from device memory (k_mean_log).  Written
+// either as channels 0..3 of the 16-channel BF16 network input (bf16 set) or
+// as FP32 [P][4] (f32 set).
+__global__ void k_features(const double* __restrict__ E,
+                           const double* __restrict__ rho,
+                           const double* __restrict__ kappa,
+                           const double* __restrict__ ax,
+                           const double* __restrict__ ay, double dx,
+                           const double* __restrict__ mean_logE, int64_t P,
+                           int64_t slice, uint16_t* __restrict__ bf16,
+                           float* __restrict__ f32) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const double m = mean_logE[p / slice];
+  const float f[4] = {(float)(log(E[p]) - m),
+                      (float)(log(rho[p] * kappa[p] * dx) / 4.0),
+                      (float)(log1p(ax[p]) / 4.0),
+                      (float)(log1p(ay[p]) / 4.0)};
+  if (f32) {
+    *reinterpret_cast<float4*>(f32 + p * 4) = make_float4(f[0], f[1], f[2], f[3]);
+  } else {
+    uint32_t w[8];
+    w[0] = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+    w[1] = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    for (int i = 2; i < 8; ++i) w[i] = 0;
+    uint4* o = reinterpret_cast<uint4*>(bf16 + p * 16);
+    o[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    o[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+}
+
+// FP32 [P][4] network inputs -> the 16-channel BF16 input tensor
+__global__ void k_input(const float* __restrict__ in, int64_t P,
+                        uint16_t* __restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const float4 v = *reinterpret_cast<const float4*>(in + p * 4);
+  uint4* o = reinterpret_cast<uint4*>(x + p * 16);
+  o[0] = make_uint4((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                    (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16), 0u, 0u);
+  o[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// mean of log E over each slice of `slice` cells (one block per slice)
+__global__ void __launch_bounds__(256)
+    k_mean_log(const double* __restrict__ E, int64_t slice,
+               double* __restrict__ mean) {
+  __shared__ double sh[4];
+  const double* e = E + (int64_t)blockIdx.x * slice;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < slice; i += 256) s += log(e[i]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) mean[blockIdx.x] = (sh[0] + sh[1] + sh[2] + sh[3]) / (double)slice;
+}
+
+// x = E (1 + delta) in FP64
+__global__ void k_apply_guess(const double* __restrict__ E,
+                              const float* __restrict__ delta, int64_t P,
+                              double* __restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p < P) x[p] = E[p] * (1.0 + (double)delta[p]);
+}
+
+static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_pool(const uint16_t* in, int is, int io, uint16_t* out,
+                       int os, int oo, int N, int Ho, int Wo, int C,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pool, dim3(nb((int64_t)N * Ho * Wo * C)), dim3(256), 0,
+                     s, in, is, io, out, os, oo, N, Ho, Wo, C);
+  return hipGetLastError();
+}
+hipError_t launch_pool_bwd(const float* gout, int gs, int go, float* gin,
+                           int is, int io, int N, int Ho, int Wo, int C,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd, dim3(nb((int64_t)N * 4 * Ho * Wo * C)),
+                     dim3(256), 0, s, gout, gs, go, gin, is, io, N, Ho, Wo, C);
+  return hipGetLastError();
+}
+hipError_t launch_up(const uint16_t* in, int is, int io, uint16_t* out, int os,
+                     int oo, int N, int Hi, int Wi, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_up, dim3(nb((int64_t)N * 4 * Hi * Wi * C)), dim3(256),
+                     0, s, in, is, io, out, os, oo, N, Hi, Wi, C);
+  return hipGetLastError();
+}
+hipError_t launch_up_bwd(const float* gout, int gs, int go, float* gin, int is,
+                         int io, int N, int Hi, int Wi, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_up_bwd, dim3(nb((int64_t)N * Hi * Wi * C)), dim3(256),
+                     0, s, gout, gs, go, gin, is, io, N, Hi, Wi, C);
+  return hipGetLastError();
+}
+hipError_t launch_relu_bwd(float* g, int gs, int go, const uint16_t* a, int as,
+                           int ao, int64_t P, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nb(P * C)), dim3(256), 0, s, g, gs, go,
+                     a, as, ao, P, C);
+  return hipGetLastError();
+}
+hipError_t launch_head(const uint16_t* u, int us, int uo, const float* w,
+                       const float* b, int C, int64_t P, float* delta,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_head, dim3(nb(P)), dim3(256), 0, s, u, us, uo, w, b, C,
+                     P, delta);
+  return hipGetLastError();
+}
+hipError_t launch_mse(const float* delta, const float* target, int64_t P,
+                      float* g, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(nb(P)), dim3(256), 0, s, delta, target, P, g,
+                     loss);
+  return hipGetLastError();
+}
+hipError_t launch_head_bwd(const float* g, const uint16_t* u, int us, int uo,
+                           const float* w, int C, int64_t P, float* du,
+                           int dus, int duo, float* dw, float* db,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_head_bwd, dim3(nb(P)), dim3(256), 0, s, g, u, us, uo, w,
+                     C, P, du, dus, duo, dw, db);
+  return hipGetLastError();
+}
+hipError_t launch_adam(float* w, uint16_t* w16, const float* g, float* m,
+                       float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(nb(n)), dim3(256), 0, s, w, w16, g, m, v, n,
+                     lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+hipError_t launch_zero(float* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(nb(n)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_to_bf16(const float* w, uint16_t* w16, int64_t n,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb(n)), dim3(256), 0, s, w, w16, n);
+  return hipGetLastError();
+}
+hipError_t launch_flip(const uint16_t* w, uint16_t* wd, int taps, int cout_pad,
+                       int cin_pad, hipStream_t s) {
+  hipLaunchKernelGGL(k_flip, dim3(nb((int64_t)taps * cout_pad * cin_pad)),
+                     dim3(256), 0, s, w, wd, taps, cout_pad, cin_pad);
+  return hipGetLastError();
+}
+hipError_t launch_features(const double* E, const double* rho,
+                           const double* kappa, const double* ax,
+                           const double* ay, double dx, const double* mean_logE,
+                           int64_t P, int64_t slice, uint16_t* bf16, float* f32,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_features, dim3(nb(P)), dim3(256), 0, s, E, rho, kappa,
+                     ax, ay, dx, mean_logE, P, slice, bf16, f32);
+  return hipGetLastError();
+}
+hipError_t launch_input(const float* in, int64_t P, uint16_t* x,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_input, dim3(nb(P)), dim3(256), 0, s, in, P, x);
+  return hipGetLastError();
+}
+hipError_t launch_mean_log(const double* E, int64_t slice, int nslices,
+                           double* mean, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_log, dim3(nslices), dim3(256), 0, s, E, slice,
+                     mean);
+  return hipGetLastError();
+}
+hipError_t launch_apply_guess(const double* E, const float* delta, int64_t P,
+                              double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_guess, dim3(nb(P)), dim3(256), 0, s, E, delta, P,
+                     x);
+  return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace fld

@@ -400,3 +400,170 @@ def fld_opacity_powerlaw_batch(ctx, rho, e_int, k0, a, b, kmin, kmax, kappa,
 def fld_batch_set_graph(ctx, on=True):
     lib = load()
     _check(ctx.ptr, lib.fld_batch_set_graph(ctx.ptr, 1 if on else 0))
+
+
+# ---- learned initial guess (include/fldnn.h) --------------------------------
+
+EXPORTED_NN = ["fldnn_param_count", "fldnn_workspace_bytes", "fldnn_create",
+               "fldnn_set_params", "fldnn_get_params", "fldnn_forward",
+               "fldnn_gradients", "fldnn_train_step", "fldnn_destroy",
+               "fld_features", "fld_set_model"]
+
+
+def _nn_argtypes(lib):
+    if getattr(lib, "_nn_ready", False):
+        return
+    P, V, F = ctypes.POINTER, ctypes.c_void_p, ctypes.c_float
+    I32, SZ = ctypes.c_int32, ctypes.c_size_t
+    lib.fldnn_param_count.argtypes = []
+    lib.fldnn_param_count.restype = SZ
+    lib.fldnn_workspace_bytes.argtypes = [I32, I32, I32, I32]
+    lib.fldnn_workspace_bytes.restype = SZ
+    lib.fldnn_create.argtypes = [I32, I32, I32, I32, V, SZ, V, P(V)]
+    lib.fldnn_create.restype = ctypes.c_int
+    lib.fldnn_set_params.argtypes = [V, P(F), SZ]
+    lib.fldnn_set_params.restype = ctypes.c_int
+    lib.fldnn_get_params.argtypes = [V, P(F), SZ]
+    lib.fldnn_get_params.restype = ctypes.c_int
+    lib.fldnn_forward.argtypes = [V, V, V]
+    lib.fldnn_forward.restype = ctypes.c_int
+    lib.fldnn_gradients.argtypes = [V, V, V, P(F), P(F), SZ]
+    lib.fldnn_gradients.restype = ctypes.c_int
+    lib.fldnn_train_step.argtypes = [V, V, V, F, I32, P(F)]
+    lib.fldnn_train_step.restype = ctypes.c_int
+    lib.fldnn_destroy.argtypes = [V]
+    lib.fldnn_destroy.restype = None
+    lib.fld_features.argtypes = [V, ctypes.c_double, V, V, V, V]
+    lib.fld_features.restype = ctypes.c_int
+    lib.fld_set_model.argtypes = [V, P(F), SZ]
+    lib.fld_set_model.restype = ctypes.c_int
+    lib._nn_ready = True
+
+
+def _nnlib():
+    lib = load()
+    _nn_argtypes(lib)
+    return lib
+
+
+def _f32_host(arr, count):
+    import numpy as np
+    a = np.ascontiguousarray(arr, dtype=np.float32).reshape(-1)
+    if a.size != count:
+        raise ValueError(f"expected {count} parameters, got {a.size}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def fldnn_param_count():
+    return int(_nnlib().fldnn_param_count())
+
+
+def fldnn_workspace_bytes(N, H, W, training):
+    return int(_nnlib().fldnn_workspace_bytes(N, H, W, 1 if training else 0))
+
+
+class Net:
+    """An fldnn* with the workspace tensor it borrows and its stream."""
+
+    def __init__(self, ptr, shape, training, workspace, stream):
+        self.ptr = ptr
+        self.shape = shape
+        self.training = training
+        self.workspace = workspace
+        self.stream = stream
+        self.count = fldnn_param_count()
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.fldnn_destroy(self.ptr)
+            self.ptr = None
+
+
+def fldnn_create(N, H, W, training=False, workspace=None, stream=None):
+    import torch
+    lib = _nnlib()
+    need = fldnn_workspace_bytes(N, H, W, training)
+    if need == 0:
+        raise FldError(FLD_ERR_INVALID_ARG,
+                       f"invalid network shape N={N} H={H} W={W}")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_void_p()
+    st = lib.fldnn_create(N, H, W, 1 if training else 0,
+                          _ptr(workspace, "workspace", dtype=torch.uint8),
+                          workspace.numel(),
+                          ctypes.c_void_p(stream.cuda_stream),
+                          ctypes.byref(out))
+    _check(None, st)
+    return Net(out, (N, H, W), training, workspace, stream)
+
+
+def fldnn_set_params(net, flat):
+    a, p = _f32_host(flat, net.count)
+    _check(None, _nnlib().fldnn_set_params(net.ptr, p, a.size))
+
+
+def fldnn_get_params(net):
+    import numpy as np
+    a = np.empty(net.count, dtype=np.float32)
+    _check(None, _nnlib().fldnn_get_params(
+        net.ptr, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+    return a
+
+
+def fldnn_forward(net, inputs, delta):
+    import torch
+    N, H, W = net.shape
+    _check(None, _nnlib().fldnn_forward(
+        net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
+        _ptr(delta, "delta", N * H * W, torch.float32)))
+
+
+def fldnn_gradients(net, inputs, targets):
+    """Returns (loss, FP32 gradient array in the parameter layout)."""
+    import numpy as np
+    import torch
+    N, H, W = net.shape
+    g = np.empty(net.count, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(None, _nnlib().fldnn_gradients(
+        net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
+        _ptr(targets, "targets", N * H * W, torch.float32),
+        ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+        g.size))
+    return float(loss.value), g
+
+
+def fldnn_train_step(net, inputs, targets, lr, step, want_loss=False):
+    import torch
+    N, H, W = net.shape
+    loss = ctypes.c_float()
+    _check(None, _nnlib().fldnn_train_step(
+        net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
+        _ptr(targets, "targets", N * H * W, torch.float32), float(lr),
+        int(step), ctypes.byref(loss) if want_loss else None))
+    return float(loss.value) if want_loss else None
+
+
+def fldnn_destroy(net):
+    if net.ptr:
+        _nnlib().fldnn_destroy(net.ptr)
+        net.ptr = None
+
+
+def fld_features(ctx, dt, rho, kappa, E, out):
+    import torch
+    n = ctx.cells
+    _check(ctx.ptr, _nnlib().fld_features(
+        ctx.ptr, float(dt), _ptr(rho, "rho", n, torch.float64),
+        _ptr(kappa, "kappa", n, torch.float64),
+        _ptr(E, "E", n, torch.float64),
+        _ptr(out, "out", 4 * n, torch.float32)))
+
+
+def fld_set_model(ctx, flat):
+    lib = _nnlib()
+    a, p = _f32_host(flat, fldnn_param_count())
+    _check(ctx.ptr, lib.fld_set_model(ctx.ptr, p, a.size))

@@ -30,6 +30,24 @@ def test_library_exports_every_declared_symbol():
     assert sorted(fld.EXPORTED) == sorted(names)
 
 
+def test_library_exports_every_network_symbol():
+    lib = fld.load()
+    names = _declared("fldnn.h")
+    assert "fldnn_train_step" in names and "fld_set_model" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(fld.EXPORTED_NN) == sorted(names)
+
+
+def test_network_parameter_count_matches_oracle_architecture():
+    from oracle import unet_ref
+    n = sum(k * k * ci * co + co for _, ci, co, k in unet_ref.LAYERS)
+    assert fld.fldnn_param_count() == n
+    assert fld.fldnn_workspace_bytes(1, 12, 16, 0) == 0  # H not /8
+    assert fld.fldnn_workspace_bytes(2, 16, 16, 1) > \
+        fld.fldnn_workspace_bytes(2, 16, 16, 0) > 0
+
+
 def _c_layout(struct, fields, tmp_path):
     """sizeof/offsetof of a header struct, as the C compiler lays it out."""
     src = tmp_path / "layout.c"
@@ -96,6 +114,8 @@ def test_bc_and_shape_validation():
         dict(ndim=1, n=(1, 1, 1), bc_lo=(1, 0, 0), bc_hi=(1, 0, 0)),  # 1-cell wall
         dict(ndim=1, n=(8, 2, 1)),  # unused side != 1
         dict(ndim=2, n=(8, 8, 1), dx=(0.1, -1, 1)),
+        dict(ndim=1, n=(64, 1, 1), guess=fld.FLD_GUESS_LEARNED),
+        dict(ndim=2, n=(64, 60, 1), guess=fld.FLD_GUESS_LEARNED),  # 60 % 8
     ]
     for kw in bad:
         p = fld.fld_params_default(**kw)
