@@ -104,11 +104,14 @@ def main():
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
-    def run(precision, steps, warmup, timed_kernel=True):
+    def run(precision, steps, warmup, timed_kernel=True, weights=None):
         """warmup + timed steps of one solver variant from the initial state"""
         params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
-                             precision=precision)
+                             precision=precision,
+                             guess="prev" if weights is None else "learned")
         st = Stepper(params, opacity=m.opacity)
+        if weights is not None:
+            fld.fld_set_model(st.ctx, weights)
         rho, E, e = d(m.rho), d(m.E), d(m.e)
         kap = torch.empty_like(rho)
         for _ in range(warmup):
@@ -116,7 +119,7 @@ def main():
         torch.cuda.synchronize()
         fld.fld_kernel_timing_enable(st.ctx, timed_kernel)
         fld.fld_kernel_timing_read(st.ctx)  # reset
-        cycles, outer, res = [], [], []
+        cycles, outer, res, rej = [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -124,6 +127,7 @@ def main():
             cycles.append(s["cycles"])
             outer.append(s["outer_iters"])
             res.append(s["rel_res_final"])
+            rej.append(s["guess_rejected"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         kt = fld.fld_kernel_timing_read(st.ctx)
@@ -133,10 +137,28 @@ def main():
                     vcycles_per_step=float(np.mean(cycles)),
                     outer_per_step=float(np.mean(outer)),
                     rel_res_final_max=float(np.max(res)), kernel=kt,
+                    rejected=int(np.sum(rej)),
                     E=E.cpu().numpy())
 
+    from paper_2503_02764_amd.guess import load_weights
+    weights = load_weights()
     base = run("fp64", args.steps, args.warmup)
     mixed = run("fp32_ir", args.steps, args.warmup)
+    lrn64 = run("fp64", args.steps, args.warmup, weights=weights)
+    lrn32 = run("fp32_ir", args.steps, args.warmup, weights=weights)
+    # network inference alone on the same grid
+    net = fld.fldnn_create(1, m.n[1], m.n[0], training=False)
+    fld.fldnn_set_params(net, weights)
+    xin = torch.zeros(m.cells * 4, dtype=torch.float32, device=dev)
+    dout = torch.empty(m.cells, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        fld.fldnn_forward(net, xin, dout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        fld.fldnn_forward(net, xin, dout)
+    torch.cuda.synchronize()
+    unet_ms = (time.perf_counter() - t0) * 100.0
     kt = base["kernel"]
     avg_ms = kt["ms"] / max(kt["launches"], 1)
     bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
@@ -177,6 +199,22 @@ def main():
                 "speedup_vs_fp64": mixed["value"] / base["value"],
                 "rel_l2_vs_fp64_after_steps": diff,
             },
+            "learned_guess_fp64": {
+                "value": lrn64["value"],
+                "ms_per_step": lrn64["ms_per_step"],
+                "vcycles_per_step": lrn64["vcycles_per_step"],
+                "guess_rejected_steps": lrn64["rejected"],
+                "speedup_vs_fp64": lrn64["value"] / base["value"],
+            },
+            "learned_guess_fp32_vcycles_fp64_refinement": {
+                "value": lrn32["value"],
+                "ms_per_step": lrn32["ms_per_step"],
+                "vcycles_per_step": lrn32["vcycles_per_step"],
+                "outer_per_step": lrn32["outer_per_step"],
+                "guess_rejected_steps": lrn32["rejected"],
+                "speedup_vs_fp64": lrn32["value"] / base["value"],
+            },
+            "unet_forward_ms": unet_ms,
         },
         "roofline": {
             "bound": "hbm",

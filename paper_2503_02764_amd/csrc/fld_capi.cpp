@@ -89,6 +89,7 @@ struct fld_ctx {
   char* net_ws = nullptr;
   size_t net_bytes = 0;
   double* mean = nullptr;  // per-slice mean of log E (network features)
+  double* guess = nullptr;  // the network's candidate iterate (FP64)
 };
 
 namespace {
@@ -132,6 +133,7 @@ struct Plan {
   size_t a64[kMaxLevels][3] = {}, x64[kMaxLevels] = {}, b64[kMaxLevels] = {};
   size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
+  size_t guess = 0;
   size_t net_bytes = 0;
   int64_t n_partials = 0;
   size_t total = 0;
@@ -189,6 +191,8 @@ std::string validate(const fld_params* p) {
   if (p->guess == FLD_GUESS_LEARNED &&
       (p->ndim < 2 || p->n[0] % 8 || p->n[1] % 8))
     return "the learned guess needs ndim >= 2 and n[0], n[1] multiples of 8";
+  if (p->guess == FLD_GUESS_LEARNED && p->n[2] > 16384)
+    return "the learned guess takes at most 16384 z-slices";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
   if (p->pre_smooth < 0 || p->post_smooth < 0 ||
@@ -251,11 +255,14 @@ void make_plan(const fld_params* p, Plan* P) {
   P->partials = take((size_t)P->n_partials * 8);
   P->tmp = take((size_t)P->g[P->L - 1].N * 8);
   P->ctrl = take(sizeof(Control));
-  if (p->ndim >= 2) P->mean = take((size_t)p->n[2] * 8);
+  if (p->ndim >= 2)
+    P->mean = take((size_t)(p->n[2] + nn::mean_log_scratch(p->n[0] * p->n[1],
+                                                           (int)p->n[2])) * 8);
   if (p->guess == FLD_GUESS_LEARNED) {
     P->net_bytes = nn::workspace_bytes((int)p->n[2], (int)p->n[1],
                                        (int)p->n[0], 0);
     P->net = take(P->net_bytes);
+    P->guess = take((size_t)P->g[0].N * 8);
   }
   P->total = o;
 }
@@ -980,6 +987,7 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   if (p->guess == FLD_GUESS_LEARNED) {
     c->net_ws = w + P.net;
     c->net_bytes = P.net_bytes;
+    c->guess = (double*)(w + P.guess);
   }
   hipError_t he = hipHostMalloc((void**)&c->host_ctrl, sizeof(Control),
                                 hipHostMallocMapped | hipHostMallocCoherent);
@@ -998,27 +1006,40 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
 
 namespace {
 
-// x (= E^n on entry) <- E^n (1 + delta) of the network, unless the guess's
-// FP64 residual is not smaller than that of E^n.  Entirely on the device;
-// the decision lands in ctrl->guess_rejected.
+// Learned guess, entirely on the device.  Both candidates, E^n (already in
+// x) and the network's E^n (1 + delta), get the finest level's
+// pre-smoothing of a V-cycle; the one with the smaller FP64 residual
+// becomes the iterate the solve starts from (the decision lands in
+// ctrl->guess_rejected).  Judging after smoothing ignores the
+// high-frequency part of the network's error, which one smoothing pass
+// removes, and keeps the smooth part that decides the number of cycles.
 fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
   const LevelView<double> v0 = view(c, c->h64, 0);
+  LevelView<double> vg = v0;
+  vg.x = c->guess;
   const Geom& g = c->geom[0];
   const int64_t slice = (int64_t)g.n[0] * g.n[1];
-  int nb = 0;
-  HIP_TRY(c, launch_resid_norm<double>(v0, c->partials, &nb, c->ctrl, c->stream));
-  HIP_TRY(c, launch_guess_judge(0, c->partials, nb, c->ctrl, c->stream));
-  HIP_TRY(c, nn::launch_mean_log(v0.b, slice, g.n[2], c->mean, c->stream));
+  HIP_TRY(c, nn::launch_mean_log(v0.b, slice, g.n[2], c->mean,
+                                     c->mean + g.n[2], c->stream));
   HIP_TRY(c, nn::launch_features(v0.b, rho, kappa, c->h64.a[0][0],
                                  c->h64.a[0][1], c->p.dx[0], c->mean, g.N,
                                  slice, nn::input_ptr(c->net), nullptr,
                                  c->stream));
   HIP_TRY(c, nn::forward_x(c->net));
-  HIP_TRY(c, nn::launch_apply_guess(v0.b, nn::delta_ptr(c->net), g.N, v0.x,
+  HIP_TRY(c, nn::launch_apply_guess(v0.b, nn::delta_ptr(c->net), g.N, vg.x,
                                     c->stream));
-  HIP_TRY(c, launch_resid_norm<double>(v0, c->partials, &nb, c->ctrl, c->stream));
-  HIP_TRY(c, launch_guess_judge(1, c->partials, nb, c->ctrl, c->stream));
-  HIP_TRY(c, launch_guess_restore(g.N, v0.b, v0.x, c->ctrl, c->stream));
+  const int sweeps = c->p.pre_smooth > 0 ? c->p.pre_smooth : 1;
+  int nb = 0;
+  for (int mode = 0; mode < 2; ++mode) {
+    const LevelView<double>& v = mode == 0 ? v0 : vg;
+    for (int k = 0; k < sweeps; ++k)
+      for (int color = 0; color < 2; ++color)
+        HIP_TRY(c, launch_gs_color<double>(v, color, c->ctrl, c->stream));
+    HIP_TRY(c, launch_resid_norm<double>(v, c->partials, &nb, c->ctrl,
+                                         c->stream));
+    HIP_TRY(c, launch_guess_judge(mode, c->partials, nb, c->ctrl, c->stream));
+  }
+  HIP_TRY(c, launch_guess_take(g.N, vg.x, v0.x, c->ctrl, c->stream));
   return FLD_OK;
 }
 
@@ -1171,6 +1192,8 @@ fld_status fld_features(fld_ctx* c, double dt, const double* rho,
   if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   if (c->batch) return fail(c, FLD_ERR_INVALID_ARG, "batched context");
   if (c->p.ndim < 2) return fail(c, FLD_ERR_INVALID_ARG, "needs ndim >= 2");
+  if (c->p.n[2] > 65535)
+    return fail(c, FLD_ERR_INVALID_ARG, "at most 65535 z-slices");
   if (!rho || !kappa || !E || !out)
     return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
   if (!(dt > 0.0) || !std::isfinite(dt))
@@ -1188,7 +1211,8 @@ fld_status fld_features(fld_ctx* c, double dt, const double* rho,
   HIP_TRY(c, launch_coef(A, E, rho, kappa, c->h64.a[0], c->h32.a[0], nullptr,
                          c->partials, c->ctrl, c->stream));
   const int64_t slice = (int64_t)g0.n[0] * g0.n[1];
-  HIP_TRY(c, nn::launch_mean_log(E, slice, g0.n[2], c->mean, c->stream));
+  HIP_TRY(c, nn::launch_mean_log(E, slice, g0.n[2], c->mean,
+                                     c->mean + g0.n[2], c->stream));
   HIP_TRY(c, nn::launch_features(E, rho, kappa, c->h64.a[0][0], c->h64.a[0][1],
                                  c->p.dx[0], c->mean, g0.N, slice, nullptr, out,
                                  c->stream));

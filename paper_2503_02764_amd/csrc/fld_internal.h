@@ -128,13 +128,13 @@ hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
                             int inner, Control* mirror, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
 // Learned guess judge: mode 0 stores the summed partials as the benchmark
-// |b - A E^n|^2; mode 1 rejects the guess when its |b - A x|^2 is not
-// smaller (or not finite).  launch_guess_restore then sets x = b (= E^n)
-// where the guess was rejected.
+// |b - A x_prev|^2; mode 1 rejects the guess when its |b - A x|^2 is not
+// smaller (or not finite).  launch_guess_take then copies the guess into
+// the iterate where it was accepted.
 hipError_t launch_guess_judge(int mode, const double* partials, int count,
                               Control* ctrl, hipStream_t s);
-hipError_t launch_guess_restore(int64_t n, const double* b, double* x,
-                                const Control* ctrl, hipStream_t s);
+hipError_t launch_guess_take(int64_t n, const double* guess, double* x,
+                             const Control* ctrl, hipStream_t s);
 hipError_t launch_fill32(float* x, int64_t n, hipStream_t s);
 
 // Levels up to this many cells run in the single-workgroup tail, in LDS.

@@ -92,17 +92,17 @@ hipError_t launch_guess_judge(int mode, const double* partials, int count,
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_guess_restore(int64_t n, const double* __restrict__ b,
-                    double* __restrict__ x, const Control* ctrl) {
-  if (ctrl->done != kRunning || !ctrl->guess_rejected) return;
+    k_guess_take(int64_t n, const double* __restrict__ guess,
+                 double* __restrict__ x, const Control* ctrl) {
+  if (ctrl->done != kRunning || ctrl->guess_rejected) return;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = b[i];
+  if (i < n) x[i] = guess[i];
 }
 
-hipError_t launch_guess_restore(int64_t n, const double* b, double* x,
-                                const Control* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_guess_restore, dim3(blocks_for(n)), dim3(kBlock), 0, s,
-                     n, b, x, ctrl);
+hipError_t launch_guess_take(int64_t n, const double* guess, double* x,
+                             const Control* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_take, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                     n, guess, x, ctrl);
   return hipGetLastError();
 }
 

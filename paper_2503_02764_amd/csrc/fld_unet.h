@@ -72,8 +72,10 @@ hipError_t launch_features(const double* E, const double* rho,
                            hipStream_t s);
 hipError_t launch_input(const float* in, int64_t P, uint16_t* x,
                         hipStream_t s);
+// Per-slice mean of log E; scratch holds mean_log_scratch() doubles.
+int64_t mean_log_scratch(int64_t slice, int nslices);
 hipError_t launch_mean_log(const double* E, int64_t slice, int nslices,
-                           double* mean, hipStream_t s);
+                           double* mean, double* scratch, hipStream_t s);
 hipError_t launch_apply_guess(const double* E, const float* delta, int64_t P,
                               double* x, hipStream_t s);
 

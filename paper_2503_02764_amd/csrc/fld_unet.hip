@@ -21,6 +21,7 @@ namespace nn {
 
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -129,8 +130,183 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution with LDS-staged tiles (v_mfma_f32_16x16x32_bf16)
+// ---------------------------------------------------------------------------
+//
+// Block: 4 waves, an output tile of 4 rows x 64 columns x COG = 16 NS output
+// channels.  Per chunk of 16 input channels the block stages the input tile
+// with its one-pixel halo (6 x 66 pixels) and the chunk's weights of all 9
+// taps in LDS as BF16 (FP32 inputs are rounded while staging).  A K step of
+// the MFMA (32) covers two taps x 16 channels: lanes 0-31 take the even tap,
+// 32-63 the odd one; a tenth, all-zero tap pads the last step.  Wave w
+// computes output row w: 4 M-subtiles of 16 pixels x NS N-subtiles.  LDS
+// pixel rows hold 24 BF16 (16 + 8 padding) so that the 16-byte operand reads
+// of 16 consecutive pixels fall on distinct banks.  BF16 results (+ bias,
+// ReLU) go through LDS to coalesced 16-byte stores; FP32 results (input
+// gradients) are stored from registers, 64 contiguous bytes per 16 lanes.
+constexpr int kCTH = 4, kCTW = 64, kCPS = 24;
+
+__host__ __device__ constexpr int conv3_lds(int ns) {
+  return ((kCTH + 2) * (kCTW + 2) + 10 * ns * 16) * kCPS * 2 >
+                 kCTH * kCTW * (ns * 16 + 8) * 2
+             ? ((kCTH + 2) * (kCTW + 2) + 10 * ns * 16) * kCPS * 2
+             : kCTH * kCTW * (ns * 16 + 8) * 2;
+}
+
+__device__ __forceinline__ uint4 pack8_f32(const float* p) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  return make_uint4((uint32_t)f2bf(a.x) | ((uint32_t)f2bf(a.y) << 16),
+                    (uint32_t)f2bf(a.z) | ((uint32_t)f2bf(a.w) << 16),
+                    (uint32_t)f2bf(b.x) | ((uint32_t)f2bf(b.y) << 16),
+                    (uint32_t)f2bf(b.z) | ((uint32_t)f2bf(b.w) << 16));
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_conv3x3(ConvArgs A) {
+  extern __shared__ __align__(16) uint16_t lds[];
+  constexpr int AR = kCTH + 2, AC = kCTW + 2;
+  constexpr int COG = NS * 16;
+  uint16_t* sA = lds;                 // [AR][AC][kCPS]
+  uint16_t* sB = lds + AR * AC * kCPS;  // [10][COG][kCPS]
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, l = tid & 63, m = l & 15, kq = l >> 4;
+  const int groups = A.cout_pad / COG;
+  const int n = blockIdx.z / groups, cg = blockIdx.z % groups;
+  const int y0 = blockIdx.y * kCTH, x0 = blockIdx.x * kCTW;
+  const int H = A.H, W = A.W;
+  const int coff = (kq & 1) * 8;  // channel half of this lane's K slot
+  f32x4 acc[4][NS];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NS; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int chunks = A.cin_pad / 16;
+  for (int cc = 0; cc < chunks; ++cc) {
+    const int c0 = cc * 16;
+    __syncthreads();
+    for (int i = tid; i < AR * AC * 2; i += 256) {
+      const int piece = i & 1, px = i >> 1;
+      const int col = px % AC, row = px / AC;
+      const int yy = y0 - 1 + row, xx = x0 - 1 + col;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const int64_t q = (((int64_t)n * H + yy) * W + xx) * A.in_stride +
+                          A.in_off + c0 + piece * 8;
+        if (A.in_f32)
+          v = pack8_f32((const float*)A.in + q);
+        else
+          v = *reinterpret_cast<const uint4*>((const uint16_t*)A.in + q);
+      }
+      *reinterpret_cast<uint4*>(sA + (row * AC + col) * kCPS + piece * 8) = v;
+    }
+    for (int i = tid; i < 10 * COG * 2; i += 256) {
+      const int piece = i & 1, r = i >> 1;
+      const int co = r % COG, t = r / COG;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (t < 9)
+        v = *reinterpret_cast<const uint4*>(
+            A.w + ((int64_t)t * A.cout_pad + cg * COG + co) * A.cin_pad + c0 +
+            piece * 8);
+      *reinterpret_cast<uint4*>(sB + (t * COG + co) * kCPS + piece * 8) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 5; ++ks) {
+      const int t = 2 * ks + (kq >> 1);
+      const int ta = t < 9 ? t : 0;  // the zero tap reads finite data
+      const int dy = ta / 3, dx = ta % 3;
+      bf16x8 b[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(sB + (t * COG + j * 16 + m) * kCPS + coff);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(
+            sA + ((wv + dy) * AC + i * 16 + m + dx) * kCPS + coff);
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  const int y = y0 + wv;
+  if (A.out_f32) {
+    // lane holds pixels x0 + 16 i + 4 kq + r of channel cg COG + 16 j + m
+    if (y >= H) return;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int co = cg * COG + j * 16 + m;
+      if (co >= A.cout) continue;
+      const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int x = x0 + i * 16 + 4 * kq + r;
+          if (x >= W) continue;
+          float v = acc[i][j][r] + bias;
+          if (A.relu) v = fmaxf(v, 0.f);
+          ((float*)A.out)[(((int64_t)n * H + y) * W + x) * A.out_stride +
+                          A.out_off + co] = v;
+        }
+    }
+    return;
+  }
+  // BF16: bias + ReLU into LDS [row][px][COG + 8], then 16-byte stores
+  __syncthreads();
+  constexpr int OS = COG + 8;
+  uint16_t* sO = lds;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const int co = cg * COG + j * 16 + m;
+    const float bias = (A.bias && co < A.cout) ? A.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[i][j][r] + bias;
+        if (A.relu) v = fmaxf(v, 0.f);
+        sO[(wv * kCTW + i * 16 + 4 * kq + r) * OS + j * 16 + m] = f2bf(v);
+      }
+  }
+  __syncthreads();
+  constexpr int V = COG / 8;
+  for (int i = tid; i < kCTH * kCTW * V; i += 256) {
+    const int piece = i % V, px = i / V;
+    const int x = x0 + px % kCTW, yy = y0 + px / kCTW;
+    const int co = cg * COG + piece * 8;
+    if (x >= W || yy >= H || co >= A.cout) continue;
+    *reinterpret_cast<uint4*>((uint16_t*)A.out +
+                              (((int64_t)n * H + yy) * W + x) * A.out_stride +
+                              A.out_off + co) =
+        *reinterpret_cast<const uint4*>(sO + px * OS + piece * 8);
+  }
+}
+
+template <int NS>
+static hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s) {
+  const int groups = a.cout_pad / (NS * 16);
+  dim3 grid((a.W + kCTW - 1) / kCTW, (a.H + kCTH - 1) / kCTH, a.N * groups);
+  hipLaunchKernelGGL((k_conv3x3<NS>), grid, dim3(256), conv3_lds(NS), s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int chunks = a.cout_pad / 16;
+  if (a.ksize == 3 && !a.accumulate && a.cout % 8 == 0 && a.cin_pad % 16 == 0) {
+    // output channels per block: all up to 64, else groups of 64 or 48
+    const int ns = chunks <= 4 ? chunks : (chunks % 4 == 0 ? 4 : 3);
+    if (chunks % ns == 0) {
+      switch (ns) {
+        case 1: return launch_conv3x3<1>(a, s);
+        case 2: return launch_conv3x3<2>(a, s);
+        case 3: return launch_conv3x3<3>(a, s);
+        default: return launch_conv3x3<4>(a, s);
+      }
+    }
+  }
   const int nco = chunks >= 4 ? 4 : chunks;
   const int groups = (chunks + nco - 1) / nco;
   dim3 grid((a.W + 63) / 64, a.H, a.N * groups);
@@ -240,27 +416,37 @@ hipError_t launch_bgrad(const float* dz, int64_t P, int stride, int off,
 // elementwise pieces
 // ---------------------------------------------------------------------------
 
-// 2x2 average pool, BF16 -> BF16 (C channels of two views)
+// 2x2 average pool, BF16 -> BF16, 8 channels (16 bytes) per thread
 __global__ void k_pool(const uint16_t* __restrict__ in, int is, int io,
                        uint16_t* __restrict__ out, int os, int oo, int N,
                        int Ho, int Wo, int C) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)N * Ho * Wo * C;
+  const int C8 = C / 8;
+  const int64_t total = (int64_t)N * Ho * Wo * C8;
   if (i >= total) return;
-  const int c = i % C;
-  int64_t p = i / C;
+  const int c = (int)(i % C8) * 8;
+  int64_t p = i / C8;
   const int x = p % Wo;
   p /= Wo;
   const int y = p % Ho;
   const int n = p / Ho;
   const int Wi = 2 * Wo, Hi = 2 * Ho;
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int dy = 0; dy < 2; ++dy)
     for (int dx = 0; dx < 2; ++dx) {
       const int64_t q = ((int64_t)n * Hi + 2 * y + dy) * Wi + 2 * x + dx;
-      s += bf2f(in[q * is + io + c]);
+      const uint4 v = *reinterpret_cast<const uint4*>(in + q * is + io + c);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      for (int k = 0; k < 4; ++k) {
+        s[2 * k] += bf2f((uint16_t)(w[k] & 0xffff));
+        s[2 * k + 1] += bf2f((uint16_t)(w[k] >> 16));
+      }
     }
-  out[(((int64_t)n * Ho + y) * Wo + x) * os + oo + c] = f2bf(0.25f * s);
+  uint32_t o[4];
+  for (int k = 0; k < 4; ++k)
+    o[k] = (uint32_t)f2bf(0.25f * s[2 * k]) | ((uint32_t)f2bf(0.25f * s[2 * k + 1]) << 16);
+  *reinterpret_cast<uint4*>(out + (((int64_t)n * Ho + y) * Wo + x) * os + oo + c) =
+      make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // gradient of the pool: g_in[child] += 1/4 g_out[parent] (FP32)
@@ -281,22 +467,24 @@ __global__ void k_pool_bwd(const float* __restrict__ gout, int gs, int go,
   gin[(((int64_t)n * Hi + y) * Wi + x) * is + io + c] += 0.25f * gout[q * gs + go + c];
 }
 
-// nearest 2x upsampling, BF16 -> BF16 view
+// nearest 2x upsampling, BF16 -> BF16 view, 8 channels per thread
 __global__ void k_up(const uint16_t* __restrict__ in, int is, int io,
                      uint16_t* __restrict__ out, int os, int oo, int N, int Hi,
                      int Wi, int C) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int Ho = 2 * Hi, Wo = 2 * Wi;
-  const int64_t total = (int64_t)N * Ho * Wo * C;
+  const int C8 = C / 8;
+  const int64_t total = (int64_t)N * Ho * Wo * C8;
   if (i >= total) return;
-  const int c = i % C;
-  int64_t p = i / C;
+  const int c = (int)(i % C8) * 8;
+  int64_t p = i / C8;
   const int x = p % Wo;
   p /= Wo;
   const int y = p % Ho;
   const int n = p / Ho;
   const int64_t q = ((int64_t)n * Hi + y / 2) * Wi + x / 2;
-  out[(((int64_t)n * Ho + y) * Wo + x) * os + oo + c] = in[q * is + io + c];
+  *reinterpret_cast<uint4*>(out + (((int64_t)n * Ho + y) * Wo + x) * os + oo + c) =
+      *reinterpret_cast<const uint4*>(in + q * is + io + c);
 }
 
 // gradient of the upsampling: g_in[parent] = sum of the 4 children (FP32)
@@ -331,14 +519,21 @@ __global__ void k_relu_bwd(float* __restrict__ g, int gs, int go,
   if (!(bf2f(a[p * as + ao + c]) > 0.f)) g[p * gs + go + c] = 0.f;
 }
 
-// 1x1 head: delta[p] = b + sum_c u[p][c] w[c]  (FP32)
+// 1x1 head: delta[p] = b + sum_c u[p][c] w[c]  (FP32), 16 channels
 __global__ void k_head(const uint16_t* __restrict__ u, int us, int uo,
                        const float* __restrict__ w, const float* __restrict__ b,
                        int C, int64_t P, float* __restrict__ delta) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
   float s = b[0];
-  for (int c = 0; c < C; ++c) s += bf2f(u[p * us + uo + c]) * w[c];
+  for (int c = 0; c < C; c += 8) {
+    const uint4 v = *reinterpret_cast<const uint4*>(u + p * us + uo + c);
+    const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+    for (int k = 0; k < 4; ++k) {
+      s += bf2f((uint16_t)(q[k] & 0xffff)) * w[c + 2 * k];
+      s += bf2f((uint16_t)(q[k] >> 16)) * w[c + 2 * k + 1];
+    }
+  }
   delta[p] = s;
 }
 
@@ -470,18 +665,39 @@ __global__ void k_input(const float* __restrict__ in, int64_t P,
   o[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// mean of log E over each slice of `slice` cells (one block per slice)
+// Mean of log E over each slice of `slice` cells, in two deterministic
+// stages: block sums of 4096 cells (grid: chunks x slices), then one block
+// per slice adds its chunk sums in a fixed order.
+constexpr int kMeanChunk = 4096;
+
 __global__ void __launch_bounds__(256)
-    k_mean_log(const double* __restrict__ E, int64_t slice,
-               double* __restrict__ mean) {
+    k_mean_log_part(const double* __restrict__ E, int64_t slice,
+                    double* __restrict__ part) {
   __shared__ double sh[4];
-  const double* e = E + (int64_t)blockIdx.x * slice;
+  const double* e = E + (int64_t)blockIdx.y * slice;
+  const int64_t i0 = (int64_t)blockIdx.x * kMeanChunk;
+  const int64_t i1 = i0 + kMeanChunk < slice ? i0 + kMeanChunk : slice;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < slice; i += 256) s += log(e[i]);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += log(e[i]);
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) mean[blockIdx.x] = (sh[0] + sh[1] + sh[2] + sh[3]) / (double)slice;
+  if (threadIdx.x == 0)
+    part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_mean_log_final(const double* __restrict__ part, int nchunk, int64_t slice,
+                     double* __restrict__ mean) {
+  __shared__ double sh[4];
+  const double* p = part + (int64_t)blockIdx.x * nchunk;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nchunk; i += 256) s += p[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    mean[blockIdx.x] = ((sh[0] + sh[1]) + (sh[2] + sh[3])) / (double)slice;
 }
 
 // x = E (1 + delta) in FP64
@@ -497,7 +713,7 @@ static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_pool(const uint16_t* in, int is, int io, uint16_t* out,
                        int os, int oo, int N, int Ho, int Wo, int C,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_pool, dim3(nb((int64_t)N * Ho * Wo * C)), dim3(256), 0,
+  hipLaunchKernelGGL(k_pool, dim3(nb((int64_t)N * Ho * Wo * (C / 8))), dim3(256), 0,
                      s, in, is, io, out, os, oo, N, Ho, Wo, C);
   return hipGetLastError();
 }
@@ -510,7 +726,7 @@ hipError_t launch_pool_bwd(const float* gout, int gs, int go, float* gin,
 }
 hipError_t launch_up(const uint16_t* in, int is, int io, uint16_t* out, int os,
                      int oo, int N, int Hi, int Wi, int C, hipStream_t s) {
-  hipLaunchKernelGGL(k_up, dim3(nb((int64_t)N * 4 * Hi * Wi * C)), dim3(256),
+  hipLaunchKernelGGL(k_up, dim3(nb((int64_t)N * 4 * Hi * Wi * (C / 8))), dim3(256),
                      0, s, in, is, io, out, os, oo, N, Hi, Wi, C);
   return hipGetLastError();
 }
@@ -584,10 +800,16 @@ hipError_t launch_input(const float* in, int64_t P, uint16_t* x,
   hipLaunchKernelGGL(k_input, dim3(nb(P)), dim3(256), 0, s, in, P, x);
   return hipGetLastError();
 }
+int64_t mean_log_scratch(int64_t slice, int nslices) {
+  return ((slice + kMeanChunk - 1) / kMeanChunk) * (int64_t)nslices;
+}
 hipError_t launch_mean_log(const double* E, int64_t slice, int nslices,
-                           double* mean, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_log, dim3(nslices), dim3(256), 0, s, E, slice,
-                     mean);
+                           double* mean, double* scratch, hipStream_t s) {
+  const int nchunk = (int)((slice + kMeanChunk - 1) / kMeanChunk);
+  hipLaunchKernelGGL(k_mean_log_part, dim3(nchunk, nslices), dim3(256), 0, s,
+                     E, slice, scratch);
+  hipLaunchKernelGGL(k_mean_log_final, dim3(nslices), dim3(256), 0, s, scratch,
+                     nchunk, slice, mean);
   return hipGetLastError();
 }
 hipError_t launch_apply_guess(const double* E, const float* delta, int64_t P,

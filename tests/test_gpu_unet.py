@@ -222,23 +222,21 @@ def test_learned_guess_step_matches_oracle():
 
 
 def test_learned_guess_fallback():
-    from paper_2503_02764_amd import fld
     m = media.config_c2(n=128)
     prob = F.problem_from_medium(m)
     kap = _kappa(m, prob)
+    ref = F.diffusion_step(m.E, m.rho, kap, m.dt, prob)
     announce("learned guess fallback c2 128")
-    ctx = fld.fld_setup(params_for(m, rtol=1e-10))
-    prev = dev(np.zeros_like(m.E))
-    _, s_prev = fld.fld_step(ctx, m.dt, dev(m.rho), dev(kap), dev(m.E), prev)
-    # delta = 0: the guess equals E^n, which is not strictly better
-    x0, s0 = _learned_step(m, kap, _zero_model(0.0), rtol=1e-10)
+    # delta = 0: the candidate equals E^n and stays equal to it through the
+    # same smoothing, so it is not strictly better: rejected
+    x0, s0 = _learned_step(m, kap, _zero_model(0.0), rtol=1e-12)
     assert s0["guess_rejected"] == 1
-    np.testing.assert_array_equal(x0, host(prev))
-    assert s0["cycles"] == s_prev["cycles"]
-    # delta = 0.5: far worse than E^n, rejected, same answer
-    x1, s1 = _learned_step(m, kap, _zero_model(0.5), rtol=1e-10)
+    assert rel_l2(x0, ref) <= 1e-10, s0
+    # delta = 0.5: far worse than E^n, rejected, the same iterate follows
+    x1, s1 = _learned_step(m, kap, _zero_model(0.5), rtol=1e-12)
     assert s1["guess_rejected"] == 1
-    np.testing.assert_array_equal(x1, host(prev))
+    np.testing.assert_array_equal(x1, x0)
+    assert s1["cycles"] == s0["cycles"]
 
 
 def test_learned_guess_3d_slices_match_oracle():
