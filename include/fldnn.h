@@ -55,9 +55,22 @@ fld_status fldnn_get_params(fldnn* net, float* host, size_t count);
  * [N][H][W].  Asynchronous. */
 fld_status fldnn_forward(fldnn* net, const float* inputs, float* delta);
 
-/* Mean squared error against targets (device FP32 [N][H][W]) and its
- * gradient with respect to every parameter, written to host memory in the
- * parameter layout.  Blocks.  Needs training = 1. */
+/* Training loss.  FLDNN_LOSS_MSE: mean of (delta - target)^2.
+ * FLDNN_LOSS_ENERGY: the inputs must be fld_features and the targets
+ * delta* = (E* - E^n) / E^n of the solve; with E = exp(f0), face
+ * coefficients alpha = expm1(4 f2), expm1(4 f3) and the guess error
+ * e = E (delta - delta*), the loss is the mean over images of
+ * |e|_A^2 / |E delta*|_A^2, |v|_A^2 = sum v^2 + sum_faces alpha dv^2 (the
+ * energy norm of the backward-Euler operator; faces inside each image).
+ * The second norm is that of the plain guess E^n, so the loss is 1 for
+ * delta = 0 and 0 for a perfect guess. */
+typedef enum { FLDNN_LOSS_MSE = 0, FLDNN_LOSS_ENERGY = 1 } fldnn_loss;
+fld_status fldnn_set_loss(fldnn* net, int32_t kind);
+
+/* The training loss (fldnn_set_loss; MSE by default) against targets
+ * (device FP32 [N][H][W]) and its gradient with respect to every
+ * parameter, written to host memory in the parameter layout.  Blocks.
+ * Needs training = 1. */
 fld_status fldnn_gradients(fldnn* net, const float* inputs,
                            const float* targets, float* loss_host,
                            float* grads_host, size_t count);

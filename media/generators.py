@@ -189,14 +189,23 @@ def config_c4(count=96, seed=4, steps=20, rtol=1e-8, sides=None):
 
 
 def config_c5_train(index, n=256):
-    """Training medium ``index``: C2 statistics on n^2, seed 5e6 + index."""
+    """Training medium ``index``: C2 statistics on n^2, seed 5e6 + index.
+
+    Diffusion number log-uniform in [10, 1000]; the box side log-uniform in
+    [0.25, 1], so that the cell width spans that of the 1024^2 workload
+    (1/1024) up to the unit box at n = 256 (the optical depth per cell and
+    the time step scale with it; the fields keep their 32-cell correlation
+    length).
+    """
     rng = np.random.default_rng(5_000_000 + index)
     nu = float(np.exp(rng.uniform(np.log(10.0), np.log(1000.0))))
+    box = float(np.exp(rng.uniform(np.log(0.25), 0.0)))
     rho, E, e, dt = _c2_fields(n, 5_000_000 + index, nu)
-    return Medium(ndim=2, n=(n, n, 1), dx=(1.0 / n, 1.0 / n, 1.0),
+    dx = box / n
+    return Medium(ndim=2, n=(n, n, 1), dx=(dx, dx, 1.0),
                   bc=("neumann", "neumann"), rho=rho, E=E, e=e, kappa=None,
-                  opacity=dict(KRAMERS), dt=dt, steps=1, rtol=1e-8,
-                  name=f"c5-train{index}-{n}sq")
+                  opacity=dict(KRAMERS), dt=dt * box * box, steps=1,
+                  rtol=1e-8, name=f"c5-train{index}-{n}sq")
 
 
 def random_small_medium(seed, n, bc, limiter="lp", face_mean="arith",

@@ -162,6 +162,53 @@ def mse_loss(delta, target):
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
+def energy_loss(delta, target, feats):
+    """Energy-norm loss of the guess error, and its gradient in delta.
+
+    With E = exp(f0) (E^n up to the image's scale) and the face coefficients
+    alpha_x = expm1(4 f2), alpha_y = expm1(4 f3) read back from the
+    features, the guess E (1 + delta) misses the solve E (1 + target) by
+    e = E (delta - target), whose energy norm under the backward-Euler
+    operator A = I + sum_faces alpha (difference)^2 is
+        |e|_A^2 = sum_i e_i^2 + sum_faces alpha_f (e_left - e_right)^2.
+    The loss is the mean over images of |e|_A^2 / |e0|_A^2, e0 = E target
+    being the error of the plain guess E^n.  A face exists between a pixel
+    and its +x (+y) neighbour inside the image (no wrap).
+    delta, target: (N, H, W, 1); feats: (N, H, W, 4).
+    """
+    E = np.exp(feats[..., 0])
+    ax = np.expm1(4.0 * feats[..., 2])
+    ay = np.expm1(4.0 * feats[..., 3])
+    d = delta[..., 0]
+    t = target[..., 0]
+    e = E * (d - t)
+    e0 = E * t
+
+    def quad(v):
+        q = np.sum(v * v, axis=(1, 2))
+        q = q + np.sum(ax[:, :, :-1] * (v[:, :, :-1] - v[:, :, 1:]) ** 2,
+                       axis=(1, 2))
+        q = q + np.sum(ay[:, :-1, :] * (v[:, :-1, :] - v[:, 1:, :]) ** 2,
+                       axis=(1, 2))
+        return q
+
+    def apply_A(v):
+        out = v.copy()
+        fx = ax[:, :, :-1] * (v[:, :, :-1] - v[:, :, 1:])
+        out[:, :, :-1] += fx
+        out[:, :, 1:] -= fx
+        fy = ay[:, :-1, :] * (v[:, :-1, :] - v[:, 1:, :])
+        out[:, :-1, :] += fy
+        out[:, 1:, :] -= fy
+        return out
+
+    num, den = quad(e), quad(e0)
+    N = delta.shape[0]
+    loss = float(np.mean(num / den))
+    grad = 2.0 * E * apply_A(e) / den[:, None, None] / N
+    return loss, grad[..., None]
+
+
 def features(E, rhokappa_dx, alpha_x, alpha_y):
     """Network inputs from the step's data (all float64, shape (H, W)).
 

@@ -53,6 +53,10 @@ hipError_t launch_head(const uint16_t* u, int us, int uo, const float* w,
                        hipStream_t s);
 hipError_t launch_mse(const float* delta, const float* target, int64_t P,
                       float* g, float* loss, hipStream_t s);
+// Energy-norm loss and its gradient g (see k_eloss_norms); acc: 2N floats.
+hipError_t launch_energy_loss(const float* delta, const float* target,
+                              const float* feats, int N, int H, int W,
+                              float* acc, float* g, float* loss, hipStream_t s);
 hipError_t launch_head_bwd(const float* g, const uint16_t* u, int us, int uo,
                            const float* w, int C, int64_t P, float* du,
                            int dus, int duo, float* dw, float* db,

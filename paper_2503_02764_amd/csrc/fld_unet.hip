@@ -555,6 +555,88 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) atomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (float)P);
 }
 
+// Energy-norm loss of the guess error (training): with E = exp(f0),
+// alpha_x = expm1(4 f2), alpha_y = expm1(4 f3) from the FP32 features,
+// e = E (delta - target), e0 = E target and
+// |v|_A^2 = sum v^2 + sum_faces alpha (v_left - v_right)^2 over the faces
+// inside each image, loss = mean_n |e|_A^2 / |e0|_A^2 and
+// g = 2 E (A e) / (N |e0|_A^2).  Grid (pixel blocks, images).
+__device__ __forceinline__ float eloss_e(const float* delta, const float* target,
+                                         const float* f, int64_t p, bool plain) {
+  const float E = expf(f[p * 4]);
+  return plain ? E * target[p] : E * (delta[p] - target[p]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_eloss_norms(const float* __restrict__ delta,
+                  const float* __restrict__ target, const float* __restrict__ f,
+                  int H, int W, float* __restrict__ acc) {
+  __shared__ float sh[2][4];
+  const int64_t HW = (int64_t)H * W;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float num = 0.f, den = 0.f;
+  if (q < HW) {
+    const int64_t p = (int64_t)blockIdx.y * HW + q;
+    const int x = (int)(q % W), y = (int)(q / W);
+    const float e = eloss_e(delta, target, f, p, false);
+    const float e0 = eloss_e(delta, target, f, p, true);
+    num = e * e;
+    den = e0 * e0;
+    if (x + 1 < W) {
+      const float a = expm1f(4.f * f[p * 4 + 2]);
+      const float d = e - eloss_e(delta, target, f, p + 1, false);
+      const float d0 = e0 - eloss_e(delta, target, f, p + 1, true);
+      num += a * d * d;
+      den += a * d0 * d0;
+    }
+    if (y + 1 < H) {
+      const float a = expm1f(4.f * f[p * 4 + 3]);
+      const float d = e - eloss_e(delta, target, f, p + W, false);
+      const float d0 = e0 - eloss_e(delta, target, f, p + W, true);
+      num += a * d * d;
+      den += a * d0 * d0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_down(num, off, 64);
+    den += __shfl_down(den, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = num;
+    sh[1][threadIdx.x >> 6] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[2 * blockIdx.y], sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3]);
+    atomicAdd(&acc[2 * blockIdx.y + 1], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_eloss_grad(const float* __restrict__ delta, const float* __restrict__ target,
+                 const float* __restrict__ f, int N, int H, int W,
+                 const float* __restrict__ acc, float* __restrict__ g,
+                 float* __restrict__ loss) {
+  const int64_t HW = (int64_t)H * W;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    float s = 0.f;
+    for (int n = 0; n < N; ++n) s += acc[2 * n] / fmaxf(acc[2 * n + 1], 1e-30f);
+    *loss = s / (float)N;
+  }
+  if (q >= HW) return;
+  const int64_t p = (int64_t)blockIdx.y * HW + q;
+  const int x = (int)(q % W), y = (int)(q / W);
+  const float e = eloss_e(delta, target, f, p, false);
+  float Ae = e;
+  if (x + 1 < W) Ae += expm1f(4.f * f[p * 4 + 2]) * (e - eloss_e(delta, target, f, p + 1, false));
+  if (x > 0) Ae += expm1f(4.f * f[(p - 1) * 4 + 2]) * (e - eloss_e(delta, target, f, p - 1, false));
+  if (y + 1 < H) Ae += expm1f(4.f * f[p * 4 + 3]) * (e - eloss_e(delta, target, f, p + W, false));
+  if (y > 0) Ae += expm1f(4.f * f[(p - W) * 4 + 3]) * (e - eloss_e(delta, target, f, p - W, false));
+  const float den = fmaxf(acc[2 * blockIdx.y + 1], 1e-30f);
+  g[p] = 2.f * expf(f[p * 4]) * Ae / (den * (float)N);
+}
+
 // head backward: du[p][c] = g[p] w[c]; dw[c] += sum_p g[p] u[p][c]; db += sum g
 __global__ void __launch_bounds__(256)
     k_head_bwd(const float* __restrict__ g, const uint16_t* __restrict__ u,
@@ -753,6 +835,18 @@ hipError_t launch_mse(const float* delta, const float* target, int64_t P,
                       float* g, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(k_mse, dim3(nb(P)), dim3(256), 0, s, delta, target, P, g,
                      loss);
+  return hipGetLastError();
+}
+hipError_t launch_energy_loss(const float* delta, const float* target,
+                              const float* feats, int N, int H, int W,
+                              float* acc, float* g, float* loss, hipStream_t s) {
+  hipError_t e = launch_zero(acc, 2 * N, s);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)(((int64_t)H * W + 255) / 256), N);
+  hipLaunchKernelGGL(k_eloss_norms, grid, dim3(256), 0, s, delta, target, feats,
+                     H, W, acc);
+  hipLaunchKernelGGL(k_eloss_grad, grid, dim3(256), 0, s, delta, target, feats,
+                     N, H, W, acc, g, loss);
   return hipGetLastError();
 }
 hipError_t launch_head_bwd(const float* g, const uint16_t* u, int us, int uo,

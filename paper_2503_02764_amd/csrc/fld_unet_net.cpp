@@ -81,6 +81,8 @@ struct Net {
   float* delta;     // FP32 [P0]
   float* gdelta;    // training
   float* loss;      // FP32 scalar
+  float* eacc;      // energy-norm loss: per-image sums (training)
+  int loss_kind;    // FLDNN_LOSS_*
   float* host_loss;
   double* mean;     // per-image mean of log E (solver features)
   std::string err;
@@ -108,6 +110,7 @@ size_t workspace_bytes(int N, int H, int W, int training) {
   }
   o += align256((size_t)pix(n, 0) * 4) * (training ? 2 : 1);
   o += 256 + align256((size_t)N * 8);
+  if (training) o += align256((size_t)N * 8);
   return o;
 }
 
@@ -158,6 +161,8 @@ Net* create(int N, int H, int W, int training, char* ws, size_t bytes,
   n->gdelta = training ? (float*)take((size_t)pix(*n, 0) * 4) : nullptr;
   n->loss = (float*)take(256);
   n->mean = (double*)take((size_t)N * 8);
+  n->eacc = training ? (float*)take((size_t)N * 8) : nullptr;
+  n->loss_kind = FLDNN_LOSS_MSE;
   // zero everything that must start at zero (padding channels of the
   // parameters, of the input tensor, optimizer moments)
   hipError_t e = zero_f32(n->w32, n->nparam, s);
@@ -355,7 +360,7 @@ static hipError_t layer_bwd(Net* n, int i, int level, const uint16_t* in,
 }
 
 // Loss and all parameter gradients (after forward_x), into n->grad.
-hipError_t backward(Net* n, const float* targets) {
+hipError_t backward(Net* n, const float* targets, const float* inputs) {
   uint16_t** a = n->act;
   float** g = n->gact;
   const int N = n->N, H = n->H, W = n->W;
@@ -363,7 +368,11 @@ hipError_t backward(Net* n, const float* targets) {
   const int64_t P0 = pix(*n, 0);
   NN_TRY(zero_f32(n->grad, n->nparam, s));
   NN_TRY(zero_f32(n->loss, 1, s));
-  NN_TRY(launch_mse(n->delta, targets, P0, n->gdelta, n->loss, s));
+  if (n->loss_kind == FLDNN_LOSS_ENERGY)
+    NN_TRY(launch_energy_loss(n->delta, targets, inputs, N, H, W, n->eacc,
+                              n->gdelta, n->loss, s));
+  else
+    NN_TRY(launch_mse(n->delta, targets, P0, n->gdelta, n->loss, s));
   NN_TRY(launch_head_bwd(n->gdelta, a[T_U0], 16, 0, n->w32 + n->woff[14], 16,
                          P0, g[T_U0], 16, 0, n->grad + n->woff[14],
                          n->grad + n->boff[14], s));
@@ -508,7 +517,7 @@ fld_status fldnn_gradients(fldnn* net, const float* inputs,
   if (!n->training) return FLD_ERR_INVALID_ARG;
   if (fld::nn::set_input(n, inputs) != hipSuccess) return FLD_ERR_DEVICE;
   if (fld::nn::forward_x(n) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::backward(n, targets) != hipSuccess) return FLD_ERR_DEVICE;
+  if (fld::nn::backward(n, targets, inputs) != hipSuccess) return FLD_ERR_DEVICE;
   return fld::nn::gradients(n, loss_host, grads_host, count) ? FLD_OK
                                                              : FLD_ERR_DEVICE;
 }
@@ -521,9 +530,16 @@ fld_status fldnn_train_step(fldnn* net, const float* inputs,
   if (!n->training) return FLD_ERR_INVALID_ARG;
   if (fld::nn::set_input(n, inputs) != hipSuccess) return FLD_ERR_DEVICE;
   if (fld::nn::forward_x(n) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::backward(n, targets) != hipSuccess) return FLD_ERR_DEVICE;
+  if (fld::nn::backward(n, targets, inputs) != hipSuccess) return FLD_ERR_DEVICE;
   if (fld::nn::adam(n, lr, step) != hipSuccess) return FLD_ERR_DEVICE;
   if (loss_host && !fld::nn::read_loss(n, loss_host)) return FLD_ERR_DEVICE;
+  return FLD_OK;
+}
+
+fld_status fldnn_set_loss(fldnn* net, int32_t kind) {
+  if (!net || (kind != FLDNN_LOSS_MSE && kind != FLDNN_LOSS_ENERGY))
+    return FLD_ERR_INVALID_ARG;
+  net->net->loss_kind = kind;
   return FLD_OK;
 }
 

@@ -31,7 +31,8 @@ hipError_t set_input(Net* n, const float* inputs);
 // delta (FP32 [N][H][W], device) from the BF16 input tensor.
 hipError_t forward_x(Net* n);
 // MSE loss against targets and every parameter gradient (after forward_x).
-hipError_t backward(Net* n, const float* targets);
+// (inputs: the FP32 features, read by the energy-norm loss)
+hipError_t backward(Net* n, const float* targets, const float* inputs);
 hipError_t adam(Net* n, float lr, int step);
 bool gradients(Net* n, float* loss, float* host, size_t count);
 bool read_loss(Net* n, float* loss);

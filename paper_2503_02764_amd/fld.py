@@ -407,6 +407,7 @@ def fld_batch_set_graph(ctx, on=True):
 EXPORTED_NN = ["fldnn_param_count", "fldnn_workspace_bytes", "fldnn_create",
                "fldnn_set_params", "fldnn_get_params", "fldnn_forward",
                "fldnn_gradients", "fldnn_train_step", "fldnn_destroy",
+               "fldnn_set_loss",
                "fld_features", "fld_set_model"]
 
 
@@ -431,6 +432,8 @@ def _nn_argtypes(lib):
     lib.fldnn_gradients.restype = ctypes.c_int
     lib.fldnn_train_step.argtypes = [V, V, V, F, I32, P(F)]
     lib.fldnn_train_step.restype = ctypes.c_int
+    lib.fldnn_set_loss.argtypes = [V, I32]
+    lib.fldnn_set_loss.restype = ctypes.c_int
     lib.fldnn_destroy.argtypes = [V]
     lib.fldnn_destroy.restype = None
     lib.fld_features.argtypes = [V, ctypes.c_double, V, V, V, V]
@@ -545,6 +548,16 @@ def fldnn_train_step(net, inputs, targets, lr, step, want_loss=False):
         _ptr(targets, "targets", N * H * W, torch.float32), float(lr),
         int(step), ctypes.byref(loss) if want_loss else None))
     return float(loss.value) if want_loss else None
+
+
+FLDNN_LOSS_MSE = 0
+FLDNN_LOSS_ENERGY = 1
+
+
+def fldnn_set_loss(net, kind):
+    """kind: "mse" or "energy" (see include/fldnn.h)."""
+    code = {"mse": FLDNN_LOSS_MSE, "energy": FLDNN_LOSS_ENERGY}[kind]
+    _check(None, _nnlib().fldnn_set_loss(net.ptr, code))
 
 
 def fldnn_destroy(net):

@@ -1,16 +1,20 @@
 """Train the learned initial guess on the GPU with the library's own kernels.
 
-Training set: seeded 256^2 media with the 2D stratified-turbulent
-statistics (log-normal rho, T = 1 + 0.1 g, Kramers opacity, Neumann walls)
-and a diffusion number drawn log-uniformly from [10, 1000]
-(media.config_c5_train, seeds 5,000,000 + i; held-out media use
-6,000,000 + i).  For each medium the network input is what fld_step feeds
-the network (fld_features) and the target is delta = (E* - E^n) / E^n,
-where E* is the backward-Euler diffusion solve of the same library in FP64
-to relative residual 1e-11 (its error against the exact solve is below
-1e-10, far under the BF16 resolution of the network).  Inputs and targets
-stay resident in device memory; training runs fldnn_train_step (BF16 MFMA
-forward/backward, FP32 Adam) over shuffled mini-batches.
+Training set: seeded 256^2 media with the 2D log-normal/Kramers statistics
+(log-normal rho, T = 1 + 0.1 g, Kramers opacity, Neumann walls), a
+diffusion number drawn log-uniformly from [10, 1000] and a cell width
+between 1/1024 and 1/256 (media.config_c5_train, seeds 5,000,000 + i;
+held-out media use 6,000,000 + i).  Medium i is sampled after 0, 1, 3 or 7
+full split steps (i mod 4), so that the states the solver meets later in a
+run are represented.  The network input is what fld_step feeds the network
+(fld_features) and the target is delta = (E* - E^n) / E^n, where E* is the
+backward-Euler diffusion solve of the same library in FP64 to relative
+residual 1e-11 (its error against the exact solve is below 1e-10, far under
+the BF16 resolution of the network).  Inputs and targets stay resident in
+device memory; training runs fldnn_train_step (BF16 MFMA forward/backward,
+FP32 Adam) over shuffled mini-batches, by default on the energy-norm loss
+of the guess error (fldnn_set_loss), which weighs the error the way the
+multigrid solve that follows sees it.
 
 Writes the FP32 parameter array (little-endian, layer order of fldnn.h) and
 a JSON record of the recipe, the loss history and the held-out evaluation.
@@ -35,10 +39,13 @@ DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "unet_c5_256.f32")
 HELDOUT_OFFSET = 1_000_000  # index offset: seeds 6,000,000 + i
 
 
+PRE_STEPS = (0, 1, 3, 7)  # full steps taken before medium i is sampled
+
+
 def _medium(index):
     import media
     m = media.config_c5_train(index)
-    return index, m.rho, m.E, m.e, m.dt, m.opacity
+    return index, m.rho, m.E, m.e, m.dt, m.dx[0], m.opacity
 
 
 def _media_stream(indices, pool):
@@ -51,44 +58,63 @@ def _media_stream(indices, pool):
         yield item
 
 
-class _Solver:
-    """One 256^2 FP64 context shared by every medium of the same shape."""
+class _Grid:
+    """Contexts on n^2 Neumann grids of any cell width, sharing workspaces."""
 
-    def __init__(self, n, rtol):
-        from .solver import make_params
+    def __init__(self, n):
+        import torch
         from . import fld
         self.fld = fld
         self.n = n
-        self.ctx = fld.fld_setup(make_params(
-            2, (n, n), (1.0 / n, 1.0 / n), ("neumann", "neumann"), rtol=rtol,
-            max_cycles=200))
+        self.ws = {}
+        self.torch = torch
 
-    def sample(self, rho, E, e, dt, opacity, feat_out, delta_out):
-        import torch
-        fld = self.fld
+    def ctx(self, dx, rtol, precision="fp64", guess="prev", key=0):
+        from .solver import make_params
+        p = make_params(2, (self.n, self.n), (dx, dx), ("neumann", "neumann"),
+                        rtol=rtol, precision=precision, guess=guess,
+                        max_cycles=200)
+        need = self.fld.fld_workspace_bytes(p)
+        ws = self.ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
+            self.ws[key] = ws
+        return self.fld.fld_setup(p, workspace=ws)
+
+    def state(self, item, ctx):
+        """Device fields of a medium after its pre-steps (opacity, diffusion,
+        exchange), and the opacity of the step to sample."""
+        torch, fld = self.torch, self.fld
+        i, rho, E, e, dt, dx, o = item
         r = torch.from_numpy(rho).cuda().reshape(-1)
         En = torch.from_numpy(E).cuda().reshape(-1)
         ei = torch.from_numpy(e).cuda().reshape(-1)
         kap = torch.empty_like(r)
-        o = opacity
-        fld.fld_opacity_powerlaw(self.ctx, r, ei, o["k0"], o["a"], o["b"],
+        for _ in range(PRE_STEPS[i % len(PRE_STEPS)]):
+            fld.fld_opacity_powerlaw(ctx, r, ei, o["k0"], o["a"], o["b"],
+                                     o["kmin"], o["kmax"], kap)
+            fld.fld_step(ctx, dt, r, kap, En, En)
+            fld.fld_exchange(ctx, dt, r, kap, En, ei)
+        fld.fld_opacity_powerlaw(ctx, r, ei, o["k0"], o["a"], o["b"],
                                  o["kmin"], o["kmax"], kap)
-        fld.fld_features(self.ctx, dt, r, kap, En, feat_out)
-        Es = torch.empty_like(En)
-        _, st = fld.fld_step(self.ctx, dt, r, kap, En, Es)
-        delta_out.copy_(((Es - En) / En).to(torch.float32))
-        return st
+        return r, kap, En, dt
 
 
 def build_dataset(indices, n, pool, log):
     import torch
+    from . import fld
     S = len(indices)
     X = torch.empty((S, n, n, 4), dtype=torch.float32, device="cuda")
     Y = torch.empty((S, n, n), dtype=torch.float32, device="cuda")
-    solver = _Solver(n, 1e-11)
+    grid = _Grid(n)
     t0 = time.time()
-    for k, (i, rho, E, e, dt, op) in enumerate(_media_stream(indices, pool)):
-        solver.sample(rho, E, e, dt, op, X[k].reshape(-1), Y[k].reshape(-1))
+    for k, item in enumerate(_media_stream(indices, pool)):
+        ctx = grid.ctx(item[5], 1e-11)
+        r, kap, En, dt = grid.state(item, ctx)
+        fld.fld_features(ctx, dt, r, kap, En, X[k].reshape(-1))
+        Es = torch.empty_like(En)
+        fld.fld_step(ctx, dt, r, kap, En, Es)
+        Y[k].reshape(-1).copy_(((Es - En) / En).to(torch.float32))
         if (k + 1) % 2000 == 0 or k + 1 == S:
             torch.cuda.synchronize()
             log(f"data {k + 1}/{S} samples, {time.time() - t0:.1f} s")
@@ -96,27 +122,22 @@ def build_dataset(indices, n, pool, log):
 
 
 def evaluate(weights, indices, n, pool, precision="fp64"):
-    """V-cycles and initial residuals with and without the learned guess."""
+    """V-cycles and initial residuals with and without the learned guess, on
+    the same states (rel. residual 1e-8)."""
     import torch
-    from .solver import make_params
     from . import fld
-    mk = lambda g: fld.fld_setup(make_params(  # noqa: E731
-        2, (n, n), (1.0 / n, 1.0 / n), ("neumann", "neumann"), rtol=1e-8,
-        precision=precision, guess=g, max_cycles=200))
-    prev, learned = mk("prev"), mk("learned")
-    fld.fld_set_model(learned, weights)
+    grid = _Grid(n)
     rows = []
-    for i, rho, E, e, dt, o in _media_stream(indices, pool):
-        r = torch.from_numpy(rho).cuda().reshape(-1)
-        En = torch.from_numpy(E).cuda().reshape(-1)
-        ei = torch.from_numpy(e).cuda().reshape(-1)
-        kap = torch.empty_like(r)
-        fld.fld_opacity_powerlaw(prev, r, ei, o["k0"], o["a"], o["b"],
-                                 o["kmin"], o["kmax"], kap)
+    for item in _media_stream(indices, pool):
+        dx = item[5]
+        prev = grid.ctx(dx, 1e-8, precision, "prev", key=0)
+        learned = grid.ctx(dx, 1e-8, precision, "learned", key=1)
+        fld.fld_set_model(learned, weights)
+        r, kap, En, dt = grid.state(item, prev)
         x0, x1 = torch.empty_like(En), torch.empty_like(En)
         _, s0 = fld.fld_step(prev, dt, r, kap, En, x0)
         _, s1 = fld.fld_step(learned, dt, r, kap, En, x1)
-        rows.append(dict(index=i, cycles_prev=s0["cycles"],
+        rows.append(dict(index=item[0], cycles_prev=s0["cycles"],
                          cycles_learned=s1["cycles"],
                          res0_prev=s0["rel_res_initial"],
                          res0_learned=s1["rel_res_initial"],
@@ -170,6 +191,7 @@ def _run(args, pool, log):
     B = args.batch
     net = fld.fldnn_create(B, n, n, training=True)
     fld.fldnn_set_params(net, he_init(args.seed))
+    fld.fldnn_set_loss(net, args.loss)
     steps_per_epoch = args.samples // B
     total = steps_per_epoch * args.epochs
     g = torch.Generator(device="cpu").manual_seed(args.seed)
@@ -213,8 +235,10 @@ def _run(args, pool, log):
         file=os.path.basename(args.out), params=int(w.size), dtype="float32 LE",
         layout="fldnn.h parameter order", size=n, samples=args.samples,
         epochs=args.epochs, batch=B, lr=args.lr, schedule="cosine",
+        loss=args.loss, pre_steps=list(PRE_STEPS),
         optimizer="Adam(0.9, 0.999, 1e-8)", init_seed=args.seed,
-        train_media="media.config_c5_train(i), i < samples (seed 5e6 + i)",
+        train_media="media.config_c5_train(i), i < samples (seed 5e6 + i), "
+                    "sampled after PRE_STEPS[i % 4] full steps",
         heldout_media=f"media.config_c5_train(1e6 + i), i < {args.heldout}",
         target="delta = (E* - E^n) / E^n, E* = FP64 solve to rel. residual 1e-11",
         loss_history=history, train_seconds=train_s,
@@ -233,6 +257,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--loss", choices=("mse", "energy"), default="energy")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)

@@ -100,3 +100,59 @@ def test_adam_descends():
         g, _ = U.backward(p, c, dd)
         U.adam_step(p, g, m, v, step, lr=1e-3)
     assert _loss(p, x, t) < 0.5 * l0
+
+
+def _feats(rng, N, H, W):
+    f = np.empty((N, H, W, 4))
+    f[..., 0] = 0.3 * rng.standard_normal((N, H, W))
+    f[..., 1] = rng.standard_normal((N, H, W))
+    f[..., 2:] = 0.25 * np.log1p(np.exp(3 * rng.standard_normal((N, H, W, 2))))
+    return f
+
+
+def test_energy_loss_quadratic_form_matches_fld_operator():
+    """|e|_A^2 equals e . A e with the oracle's own backward-Euler operator
+    (a 2D Neumann problem whose wall faces carry alpha = 0)."""
+    from oracle import fldref as F
+    rng = np.random.default_rng(21)
+    N, H, W = 2, 8, 12
+    f = _feats(rng, N, H, W)
+    f[:, :, -1, 2] = 0.0  # wall faces of the Neumann problem
+    f[:, -1, :, 3] = 0.0
+    d = 0.1 * rng.standard_normal((N, H, W, 1))
+    t = 0.1 * rng.standard_normal((N, H, W, 1))
+    loss, _ = U.energy_loss(d, t, f)
+    prob = F.Problem(ndim=2, n=(W, H, 1), dx=(1.0, 1.0, 1.0),
+                     bc=("neumann", "neumann"))
+    E = np.exp(f[..., 0])
+    ratios = []
+    for k in range(N):
+        al = [np.expm1(4 * f[k, :, :, 2]), np.expm1(4 * f[k, :, :, 3])]
+        e = E[k] * (d[k, ..., 0] - t[k, ..., 0])
+        e0 = E[k] * t[k, ..., 0]
+        ratios.append(np.sum(e * F.apply_operator(e, al, prob)) /
+                      np.sum(e0 * F.apply_operator(e0, al, prob)))
+    assert np.isclose(loss, np.mean(ratios), rtol=1e-12)
+    # a perfect prediction has zero loss; delta = 0 (the plain guess) has 1
+    assert U.energy_loss(t, t, f)[0] == 0.0
+    assert np.isclose(U.energy_loss(0 * t, t, f)[0], 1.0, rtol=1e-14)
+
+
+def test_energy_loss_gradient_vs_finite_differences():
+    rng = np.random.default_rng(22)
+    N, H, W = 2, 8, 8
+    f = _feats(rng, N, H, W)
+    d = 0.1 * rng.standard_normal((N, H, W, 1))
+    t = 0.1 * rng.standard_normal((N, H, W, 1))
+    _, g = U.energy_loss(d, t, f)
+    h = 1e-7
+    df = d.reshape(-1)
+    for i in rng.choice(df.size, size=12, replace=False):
+        old = df[i]
+        df[i] = old + h
+        lp = U.energy_loss(d, t, f)[0]
+        df[i] = old - h
+        lm = U.energy_loss(d, t, f)[0]
+        df[i] = old
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g.reshape(-1)[i]) <= 1e-6 * max(abs(fd), 1e-3), i
