@@ -71,6 +71,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shape on every level")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline variant (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -110,6 +114,7 @@ def main():
                              precision=precision,
                              guess="prev" if weights is None else "learned")
         st = Stepper(params, opacity=m.opacity)
+        shapes = fld.fld_autotune(st.ctx)[:6] if not args.no_autotune else None
         if weights is not None:
             fld.fld_set_model(st.ctx, weights)
         rho, E, e = d(m.rho), d(m.E), d(m.e)
@@ -137,12 +142,17 @@ def main():
                     vcycles_per_step=float(np.mean(cycles)),
                     outer_per_step=float(np.mean(outer)),
                     rel_res_final_max=float(np.max(res)), kernel=kt,
-                    rejected=int(np.sum(rej)),
+                    rejected=int(np.sum(rej)), tile_shapes=shapes,
                     E=E.cpu().numpy())
 
     from paper_2503_02764_amd.guess import load_weights
     weights = load_weights()
     base = run("fp64", args.steps, args.warmup)
+    if args.headline_only:
+        print(json.dumps({"ms_per_step": base["ms_per_step"],
+                          "vcycles_per_step": base["vcycles_per_step"],
+                          "tile_shapes": base["tile_shapes"]}))
+        return
     mixed = run("fp32_ir", args.steps, args.warmup)
     lrn64 = run("fp64", args.steps, args.warmup, weights=weights)
     lrn32 = run("fp32_ir", args.steps, args.warmup, weights=weights)
@@ -189,6 +199,7 @@ def main():
         },
         "vcycles_per_step": base["vcycles_per_step"],
         "rel_res_final_max": base["rel_res_final_max"],
+        "tile_shapes_autotuned": base["tile_shapes"],
         "variants": {
             "fp32_vcycles_fp64_refinement": {
                 "value": mixed["value"],

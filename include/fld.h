@@ -168,6 +168,19 @@ fld_status fld_kernel_timing_read(fld_ctx* ctx, double* ms_total,
                                   int64_t* launches, double* bytes_total,
                                   const char** kernel_name);
 
+/* Autotuner of the 2D tiled multigrid kernels: times every tile shape of
+ * the down (pre-smoothing, residual, restriction) and up (prolongation,
+ * post-smoothing) passes on each tiled level of this context and keeps the
+ * fastest per level and pass; a batched context is tuned on its largest
+ * grid, one shape per level index for all grids.  Untuned contexts use
+ * shape 0.  The shapes change only the speed, never the result.  Uses the
+ * context's workspace as scratch: call it between steps.  Blocks.  choices
+ * (host, nullable): 2 * max_levels int32, the chosen shape per level (down,
+ * up).  Contexts without tiled levels (1D, 3D) tune nothing. */
+fld_status fld_autotune(fld_ctx* ctx, int32_t* choices, int32_t max_levels);
+/* Name of a tile shape ("64x48/256": region and threads per block). */
+const char* fld_tile_shape_name(int32_t variant);
+
 /* ---- Batched grids ---------------------------------------------------------
  * Many independent 2D grids (each with its own size, boundaries, constants
  * and dt) advanced together: every phase of the step above is one launch

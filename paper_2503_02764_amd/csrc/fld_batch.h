@@ -43,6 +43,13 @@ struct JobCorrect {
   Control* ctrl;
 };
 
+struct JobTake {  // x = alt where the grid stopped after its finest down pass
+  int64_t N;
+  const double* alt;
+  double* x;
+  const Control* ctrl;
+};
+
 struct JobOpacity {
   int64_t N;
   double gm1, gas_const;
@@ -72,6 +79,8 @@ hipError_t launch_resid_batch(const JobResid* tab, const int* start, int ng,
                               int nblocks, hipStream_t s);
 hipError_t launch_correct_batch(const JobCorrect* tab, const int* start,
                                 int ng, int nblocks, hipStream_t s);
+hipError_t launch_take_batch(const JobTake* tab, const int* start, int ng,
+                             int nblocks, hipStream_t s);
 hipError_t launch_opacity_batch(const JobOpacity* tab, const int* start,
                                 int ng, int nblocks, hipStream_t s);
 hipError_t launch_exchange_batch(const JobExchange* tab, const int* start,

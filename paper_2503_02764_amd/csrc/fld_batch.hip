@@ -53,6 +53,16 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock)
+    k_take_batch(const JobTake* __restrict__ tab, const int* __restrict__ start,
+                 int ng) {
+  const int g = find_grid(start, ng, blockIdx.x);
+  const JobTake& J = tab[g];
+  if (!J.ctrl->stop_in_down) return;
+  const int64_t i = (int64_t)(blockIdx.x - start[g]) * kBlock + threadIdx.x;
+  if (i < J.N) J.x[i] = J.alt[i];
+}
+
+__global__ void __launch_bounds__(kBlock)
     k_opacity_batch(const JobOpacity* __restrict__ tab,
                     const int* __restrict__ start, int ng) {
   const int g = find_grid(start, ng, blockIdx.x);
@@ -114,6 +124,14 @@ hipError_t launch_correct_batch(const JobCorrect* tab, const int* start,
                                 int ng, int nblocks, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_correct_batch, dim3(nblocks), dim3(kBlock), 0, s, tab,
+                     start, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_batch(const JobTake* tab, const int* start, int ng,
+                             int nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_take_batch, dim3(nblocks), dim3(kBlock), 0, s, tab,
                      start, ng);
   return hipGetLastError();
 }

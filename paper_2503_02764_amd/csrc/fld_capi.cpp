@@ -47,6 +47,7 @@ struct Levels {
   T* x[kMaxLevels] = {};
   T* b[kMaxLevels] = {};
   T* a[kMaxLevels][3] = {};
+  T* alt[kMaxLevels] = {};  // second iterate buffer of the tiled 2D levels
   T* tmp = nullptr;  // coarsest-level scratch (global-memory tail only)
 };
 
@@ -83,6 +84,7 @@ struct fld_ctx {
   size_t ev_used = 0;
   bool fast = true;  // tiled kernels + single-workgroup tail
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
+  int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
   // learned guess: network carved out of net_ws by fld_set_model
   nn::Net* net = nullptr;
@@ -132,6 +134,7 @@ struct Plan {
   Geom g[kMaxLevels];
   size_t a64[kMaxLevels][3] = {}, x64[kMaxLevels] = {}, b64[kMaxLevels] = {};
   size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
+  size_t alt[kMaxLevels] = {};  // tiled 2D levels: iterate double buffer
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
   size_t guess = 0;
   size_t net_bytes = 0;
@@ -243,14 +246,16 @@ void make_plan(const fld_params* p, Plan* P) {
       P->x32[l] = take(cells * 4);
       P->b32[l] = take(cells * 4);
     }
+    if (nd == 2 && l + 1 < P->L) P->alt[l] = take(cells * (mixed ? 4 : 8));
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   int64_t nparts = blocks_for(P->g[0].N);
   if (p->ndim == 2)
-    for (int nu = 1; nu <= 3; ++nu) {
-      const int64_t t = tile2d_blocks(P->g[0], nu, true);
-      if (t > nparts) nparts = t;
-    }
+    for (int nu = 1; nu <= 3; ++nu)
+      for (int v = 0; v < kTileVariants; ++v) {
+        const int64_t t = tile2d_blocks(P->g[0], nu, true, v);
+        if (t > nparts) nparts = t;
+      }
   P->n_partials = nparts + 64;
   P->partials = take((size_t)P->n_partials * 8);
   P->tmp = take((size_t)P->g[P->L - 1].N * 8);
@@ -354,6 +359,7 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
     Tile2DArgs<T> a{};
     a.g = c->geom[l];
     a.x = H.x[l];
+    a.xo = H.alt[l];
     a.b = H.b[l];
     a.ax = H.a[l][0];
     a.ay = H.a[l][1];
@@ -370,7 +376,8 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
     TimedLaunch t(c, l == 0, bytes,
                   sizeof(T) == 8 ? "k_tile2d<double,down>" : "k_tile2d<float,down>");
     FLD_TRY(t.st);
-    HIP_TRY(c, launch_tile2d<T>(a, c->p.pre_smooth, true, c->stream, &nb));
+    HIP_TRY(c, launch_tile2d<T>(a, c->p.pre_smooth, true, c->tile_var[l][0],
+                                c->stream, &nb));
     FLD_TRY(t.close());
   } else {
     if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
@@ -390,7 +397,8 @@ fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
   if (tile_path(c)) {
     Tile2DArgs<T> a{};
     a.g = c->geom[l];
-    a.x = H.x[l];
+    a.x = H.alt[l];  // the down pass's output
+    a.xo = H.x[l];
     a.b = H.b[l];
     a.ax = H.a[l][0];
     a.ay = H.a[l][1];
@@ -401,7 +409,8 @@ fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
     a.zero_init = 0;
     a.ctrl = c->ctrl;
     int nb = 0;
-    HIP_TRY(c, launch_tile2d<T>(a, c->p.post_smooth, false, c->stream, &nb));
+    HIP_TRY(c, launch_tile2d<T>(a, c->p.post_smooth, false, c->tile_var[l][1],
+                                c->stream, &nb));
     return FLD_OK;
   }
   HIP_TRY(c, launch_prolong<T>(view(c, H, l + 1), view(c, H, l), c->ctrl,
@@ -493,6 +502,11 @@ fld_status solve_fp64(fld_ctx* c) {
     if (batch > c->p.max_cycles - enqueued) batch = c->p.max_cycles - enqueued;
     for (int k = 0; k < batch; ++k)
       FLD_TRY(vcycle<double>(c, c->h64, false));
+    // a stop right after the finest down pass leaves the iterate in the
+    // alternate buffer of the tiled path (the copy checks the device flag)
+    if (tile_path(c))
+      HIP_TRY(c, launch_take_alt(c->geom[0].N, c->h64.alt[0], c->h64.x[0],
+                                 c->ctrl, c->stream));
     enqueued += batch;
     FLD_TRY(read_control(c));
     if (c->host_ctrl->done != kRunning || enqueued >= c->p.max_cycles) break;
@@ -566,6 +580,7 @@ struct Phase {  // one batched launch: table offset, block starts, counts
 
 struct BatchState {
   int ng = 0;
+  int tile_var[kMaxLevels][2] = {};  // tile shape per level index: down, up
   std::vector<fld_ctx*> sub;
   char* dev_tab = nullptr;  // device table area (end of the workspace)
   size_t tab_cap = 0;
@@ -575,7 +590,7 @@ struct BatchState {
   char* host_aux = nullptr;
   size_t aux_cap = 0;
   // layout of the step image
-  Phase ctrl, coef, fin_b, resid, fin_r, correct, fin_c;
+  Phase ctrl, coef, fin_b, resid, fin_r, correct, fin_c, take;
   std::vector<Phase> coarsen, down[2], up;
   Phase tail[2];
   size_t tail_lds = 0;
@@ -609,11 +624,12 @@ Levels<float>& hier<float>(fld_ctx* c) { return c->h32; }
 
 template <typename T>
 Tile2DArgs<T> tile_job(fld_ctx* c, int l, bool down, bool zero_init,
-                       double* partials) {
+                       double* partials, int variant) {
   Levels<T>& H = hier<T>(c);
   Tile2DArgs<T> a{};
   a.g = c->geom[l];
-  a.x = H.x[l];
+  a.x = down ? H.x[l] : H.alt[l];
+  a.xo = down ? H.alt[l] : H.x[l];
   a.b = H.b[l];
   a.ax = H.a[l][0];
   a.ay = H.a[l][1];
@@ -623,8 +639,8 @@ Tile2DArgs<T> tile_job(fld_ctx* c, int l, bool down, bool zero_init,
   a.partials = partials;
   a.zero_init = zero_init;
   a.ctrl = c->ctrl;
-  tile2d_grid(a.g, down ? c->p.pre_smooth : c->p.post_smooth, down, &a.tiles_x,
-              &a.tiles_y);
+  tile2d_grid(a.g, down ? c->p.pre_smooth : c->p.post_smooth, down, variant,
+              &a.tiles_x, &a.tiles_y);
   return a;
 }
 
@@ -641,6 +657,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
   std::vector<JobFinalize> fb(ng), fr(ng), fcy(ng);
   std::vector<JobResid> jr(ng);
   std::vector<JobCorrect> jx(ng);
+  std::vector<JobTake> jt(ng);
   std::vector<int> bcoef(ng), bres(ng), one(ng, 1);
   for (int g = 0; g < ng; ++g) {
     fld_ctx* c = B->sub[g];
@@ -677,8 +694,10 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
     fr[g] = {c->partials, bres[g], c->ctrl};
     jx[g] = {c->geom[0].N, c->h64.x[0], c->mixed ? c->h32.x[0] : nullptr,
              c->ctrl};
+    jt[g] = {c->geom[0].N, c->h64.alt[0], c->h64.x[0], c->ctrl};
     fcy[g] = {c->partials,
-              tile2d_blocks(c->geom[0], c->p.pre_smooth, true), c->ctrl};
+              tile2d_blocks(c->geom[0], c->p.pre_smooth, true, B->tile_var[0][0]),
+              c->ctrl};
   }
   add_phase(im, B->ctrl, jc, one);
   add_phase(im, B->coef, jf, bcoef);
@@ -686,6 +705,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
   add_phase(im, B->resid, jr, bres);
   add_phase(im, B->fin_r, fr, one);
   add_phase(im, B->correct, jx, bres);
+  add_phase(im, B->take, jt, bres);
   add_phase(im, B->fin_c, fcy, one);
   // coarse face coefficients of precision T, per level index
   B->coarsen.assign(B->maxL > 1 ? B->maxL - 1 : 0, Phase());
@@ -721,8 +741,9 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
         if (l >= c->tail_l0) continue;
         const bool zero = l > 0 || (mixed && v == 0);
         double* parts = (!mixed && l == 0) ? c->partials : nullptr;
-        jobs.push_back(tile_job<T>(c, l, true, zero, parts));
-        blocks.push_back(tile2d_blocks(c->geom[l], c->p.pre_smooth, true));
+        jobs.push_back(tile_job<T>(c, l, true, zero, parts, B->tile_var[l][0]));
+        blocks.push_back(tile2d_blocks(c->geom[l], c->p.pre_smooth, true,
+                                       B->tile_var[l][0]));
       }
       add_phase(im, B->down[v][l], jobs, blocks);
     }
@@ -746,8 +767,9 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
     for (int g = 0; g < ng; ++g) {
       fld_ctx* c = B->sub[g];
       if (l >= c->tail_l0) continue;
-      jobs.push_back(tile_job<T>(c, l, false, false, nullptr));
-      blocks.push_back(tile2d_blocks(c->geom[l], c->p.post_smooth, false));
+      jobs.push_back(tile_job<T>(c, l, false, false, nullptr, B->tile_var[l][1]));
+      blocks.push_back(tile2d_blocks(c->geom[l], c->p.post_smooth, false,
+                                     B->tile_var[l][1]));
     }
     add_phase(im, B->up[l], jobs, blocks);
   }
@@ -772,7 +794,8 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
     const Phase& ph = B->down[var][l];
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
                                        start_ptr(B, ph), ph.ng, ph.nblocks,
-                                       p.pre_smooth, true, s));
+                                       p.pre_smooth, true, B->tile_var[l][0],
+                                       s));
     if (sizeof(T) == 8 && l == 0)
       HIP_TRY(bc, launch_finalize_batch(kFinCycle,
                                         tab_ptr<JobFinalize>(B, B->fin_c),
@@ -784,7 +807,8 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
     const Phase& ph = B->up[l];
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
                                        start_ptr(B, ph), ph.ng, ph.nblocks,
-                                       p.post_smooth, false, s));
+                                       p.post_smooth, false, B->tile_var[l][1],
+                                       s));
   }
   return FLD_OK;
 }
@@ -888,6 +912,10 @@ fld_status batch_step_impl(fld_ctx* bc, const double* dt,
     if (batch > max_iters - done_iters) batch = max_iters - done_iters;
     if (batch < 1) break;
     FLD_TRY(batch_iterations(bc, batch));
+    if (!B->sub[0]->mixed)  // FP64: a grid may stop after its down pass
+      HIP_TRY(bc, launch_take_batch(tab_ptr<JobTake>(B, B->take),
+                                    start_ptr(B, B->take), B->take.ng,
+                                    B->take.nblocks, s));
     done_iters += batch;
     FLD_TRY(read_control(bc));
     if (all_stopped(B) || done_iters >= max_iters) break;
@@ -969,9 +997,21 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
     c->h64.b[l] = (has64 && l > 0) ? (double*)(w + P.b64[l]) : nullptr;
     c->h32.x[l] = c->mixed ? (float*)(w + P.x32[l]) : nullptr;
     c->h32.b[l] = c->mixed ? (float*)(w + P.b32[l]) : nullptr;
+    if (P.alt[l]) {
+      if (c->mixed)
+        c->h32.alt[l] = (float*)(w + P.alt[l]);
+      else
+        c->h64.alt[l] = (double*)(w + P.alt[l]);
+    }
   }
   const char* path = getenv("FLD_KERNEL_PATH");
   c->fast = !(path && strcmp(path, "simple") == 0);
+  // fixed tile shape for every level (tests of shape independence)
+  if (const char* tv = getenv("FLD_TILE_VARIANT")) {
+    const int v = atoi(tv);
+    if (v >= 0 && v < kTileVariants)
+      for (int l = 0; l < kMaxLevels; ++l) c->tile_var[l][0] = c->tile_var[l][1] = v;
+  }
   c->tail_l0 = c->L - 1;
   for (int l = 0; l < c->L; ++l)
     if (c->geom[l].N <= kTailLdsCells) {
@@ -1164,6 +1204,135 @@ fld_status fld_kernel_timing_read(fld_ctx* c, double* ms_total,
   c->t_launches = 0;
   c->t_bytes = 0.0;
   return FLD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Time every tile shape of the down and up passes on each tiled level of c
+// (zeroed level buffers of the context: the kernels' speed does not depend
+// on the values) and keep the fastest.  choice[l][0 / 1]: down / up.
+template <typename T>
+fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2]) {
+  hipStream_t s = c->stream;
+  // Level-0 buffers: the FP32 iterate and rhs of a mixed context belong to
+  // the workspace; the FP64 ones are the caller's arrays during a step (the
+  // pointers of the last step are stale here), so the rhs copy stands in
+  // for both.
+  const bool own0 = sizeof(T) == sizeof(float);
+  T* x0 = own0 ? H.x[0] : (T*)c->bcopy;
+  T* b0 = own0 ? H.b[0] : (T*)c->bcopy;
+  FLD_TRY(fill_zero<T>(c, (T*)c->bcopy, c->geom[0].N * (int64_t)sizeof(double) /
+                                            (int64_t)sizeof(T)));
+  for (int l = 0; l <= c->tail_l0 && l < c->L; ++l) {
+    if (l > 0 || own0) {
+      FLD_TRY(fill_zero<T>(c, H.x[l], c->geom[l].N));
+      FLD_TRY(fill_zero<T>(c, H.b[l], c->geom[l].N));
+    }
+    for (int d = 0; d < 2; ++d) FLD_TRY(fill_zero<T>(c, H.a[l][d], c->geom[l].N));
+  }
+  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles, c->inner,
+                             nullptr, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, FLD_ERR_DEVICE, "hipEventCreate failed");
+  }
+  fld_status st = FLD_OK;
+  constexpr int kReps = 6;
+  for (int l = 0; l < c->tail_l0 && st == FLD_OK; ++l)
+    for (int dir = 0; dir < 2 && st == FLD_OK; ++dir) {
+      Tile2DArgs<T> a{};
+      a.g = c->geom[l];
+      T* xl = l == 0 ? x0 : H.x[l];
+      a.x = dir == 0 ? xl : H.alt[l];
+      a.xo = dir == 0 ? H.alt[l] : xl;
+      a.b = l == 0 ? b0 : H.b[l];
+      a.ax = H.a[l][0];
+      a.ay = H.a[l][1];
+      a.gc = c->geom[l + 1];
+      a.cb = dir == 0 ? H.b[l + 1] : nullptr;
+      a.ce = dir == 0 ? nullptr : H.x[l + 1];
+      a.partials = (dir == 0 && l == 0) ? c->partials : nullptr;
+      a.zero_init = 0;
+      a.ctrl = c->ctrl;
+      const int nu = dir == 0 ? c->p.pre_smooth : c->p.post_smooth;
+      float best = 1e30f;
+      for (int v = 0; v < kTileVariants && st == FLD_OK; ++v) {
+        int nb = 0;
+        hipError_t e = launch_tile2d<T>(a, nu, dir == 0, v, s, &nb);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r)
+          e = launch_tile2d<T>(a, nu, dir == 0, v, s, &nb);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = fail(c, FLD_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          choice[l][dir] = v;
+        }
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+fld_status tune_ctx(fld_ctx* c, int choice[kMaxLevels][2]) {
+  for (int l = 0; l < kMaxLevels; ++l) choice[l][0] = choice[l][1] = 0;
+  if (!tile_path(c)) return FLD_OK;
+  return c->mixed ? tune_levels<float>(c, c->h32, choice)
+                  : tune_levels<double>(c, c->h64, choice);
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_autotune(fld_ctx* c, int32_t* choices, int32_t max_levels) {
+  if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (choices && max_levels < 0)
+    return fail(c, FLD_ERR_INVALID_ARG, "max_levels must be >= 0");
+  int choice[kMaxLevels][2];
+  if (c->batch) {
+    // tune on the largest grid; one shape per level index for all grids
+    BatchState* B = c->batch;
+    fld_ctx* big = B->sub[0];
+    for (fld_ctx* sub : B->sub)
+      if (sub->geom[0].N > big->geom[0].N) big = sub;
+    const fld_status st = tune_ctx(big, choice);
+    if (st != FLD_OK) return fail(c, st, "%s", big->err.c_str());
+    for (int l = 0; l < kMaxLevels; ++l)
+      for (int d = 0; d < 2; ++d) B->tile_var[l][d] = choice[l][d];
+    // the captured graph holds the old launch shapes
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->gexec = nullptr;
+    B->graph = nullptr;
+    B->last.clear();
+  } else {
+    FLD_TRY(tune_ctx(c, choice));
+    for (int l = 0; l < kMaxLevels; ++l)
+      for (int d = 0; d < 2; ++d) c->tile_var[l][d] = choice[l][d];
+  }
+  if (choices)
+    for (int l = 0; l < max_levels && l < kMaxLevels; ++l) {
+      choices[2 * l] = choice[l][0];
+      choices[2 * l + 1] = choice[l][1];
+    }
+  return FLD_OK;
+}
+
+const char* fld_tile_shape_name(int32_t variant) {
+  return (variant >= 0 && variant < kTileVariants) ? tile2d_variant_name(variant)
+                                                   : "invalid";
 }
 
 fld_status fld_set_model(fld_ctx* c, const float* host, size_t count) {
@@ -1377,6 +1546,11 @@ fld_status fld_setup_batch(int32_t count, const fld_params* each,
   BatchState* B = new BatchState();
   bc->batch = B;
   B->ng = count;
+  if (const char* tv = getenv("FLD_TILE_VARIANT")) {  // as in fld_setup
+    const int v = atoi(tv);
+    if (v >= 0 && v < kTileVariants)
+      for (int l = 0; l < kMaxLevels; ++l) B->tile_var[l][0] = B->tile_var[l][1] = v;
+  }
   for (int g = 0; g < count; ++g) {
     Plan P;
     make_plan(&each[g], &P);

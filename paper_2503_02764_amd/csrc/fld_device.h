@@ -138,6 +138,7 @@ __device__ __forceinline__ void ctrl_init_body(Control* ctrl, double rtol,
     ctrl->flagged = 0;
     ctrl->guess_ref = 0.0;
     ctrl->guess_rejected = 0;
+    ctrl->stop_in_down = 0;
   }
 }
 
@@ -192,6 +193,7 @@ __device__ __forceinline__ void finalize_update(int mode, double s,
     ctrl->done = kConverged;
   else if (ctrl->cycles >= ctrl->max_cycles)
     ctrl->done = kCapped;
+  if (ctrl->done != kRunning) ctrl->stop_in_down = 1;
 }
 
 

@@ -46,6 +46,9 @@ struct Control {
   int32_t outer;      // refinement iterations (corrections applied)
   int32_t inner;      // FP32 V-cycles per refinement iteration
   int32_t guess_rejected;  // 1 when the learned guess lost to E^n
+  int32_t stop_in_down;    // the stop test fired after a finest down pass
+                           // (tiled path: the iterate is in the alternate
+                           // buffer)
   Control* mirror;    // device address of the host-visible copy (or null)
 };
 
@@ -135,6 +138,9 @@ hipError_t launch_guess_judge(int mode, const double* partials, int count,
                               Control* ctrl, hipStream_t s);
 hipError_t launch_guess_take(int64_t n, const double* guess, double* x,
                              const Control* ctrl, hipStream_t s);
+// x = alt where the solve stopped right after a finest down pass
+hipError_t launch_take_alt(int64_t n, const double* alt, double* x,
+                           const Control* ctrl, hipStream_t s);
 hipError_t launch_fill32(float* x, int64_t n, hipStream_t s);
 
 // Levels up to this many cells run in the single-workgroup tail, in LDS.

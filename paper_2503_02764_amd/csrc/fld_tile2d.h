@@ -9,7 +9,9 @@ namespace fld {
 template <typename T>
 struct Tile2DArgs {
   Geom g;             // this level
-  T* x;               // iterate, read (unless zero_init) and written
+  const T* x;         // iterate read (unless zero_init), halo included
+  T* xo;              // iterate written (tile interiors); never x: blocks
+                      // read their halo from x while neighbours write
   const T* b;         // right-hand side
   const T* ax;        // face coefficients along x and y
   const T* ay;
@@ -22,17 +24,23 @@ struct Tile2DArgs {
   const Control* ctrl;
 };
 
+// Tile shapes available to the launchers (see fld_tile2d.hip).
+constexpr int kTileVariants = 7;
+const char* tile2d_variant_name(int variant);
+
 // Launch the down (pre-smoothing + residual + restriction) or up
 // (prolongation + post-smoothing) kernel with nu red-black sweeps
-// (nu in 1..3).  *nblocks receives the number of tiles.
+// (nu in 1..3) and tile shape `variant`.  *nblocks receives the number of
+// tiles.
 template <typename T>
 hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
-                         hipStream_t s, int* nblocks);
+                         int variant, hipStream_t s, int* nblocks);
 
 // Number of tiles (blocks) the launcher will use.
-int tile2d_blocks(const Geom& g, int nu, bool down);
+int tile2d_blocks(const Geom& g, int nu, bool down, int variant);
 // Same, also returning the tile grid (for the batched form's argument table).
-int tile2d_grid(const Geom& g, int nu, bool down, int* tiles_x, int* tiles_y);
+int tile2d_grid(const Geom& g, int nu, bool down, int variant, int* tiles_x,
+                int* tiles_y);
 
 // Batched form: tab[g] (device memory, tiles_x/tiles_y filled in) are the
 // arguments of grid g, whose tiles are blocks start[g] .. start[g+1]-1 of a
@@ -40,6 +48,6 @@ int tile2d_grid(const Geom& g, int nu, bool down, int* tiles_x, int* tiles_y);
 template <typename T>
 hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
                                int ng, int nblocks, int nu, bool down,
-                               hipStream_t s);
+                               int variant, hipStream_t s);
 
 }  // namespace fld

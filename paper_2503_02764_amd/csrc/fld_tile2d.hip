@@ -23,6 +23,10 @@
 // register arrays are indexed by compile-time constants; the 2x2 children
 // of a coarse cell sit in one thread's registers.
 //
+// The iterate is double-buffered: a block reads its region (halo included)
+// from x and writes its tile interior to xo, so no block can see a
+// neighbour's already-updated cells, whatever the dispatch order.
+//
 // Blocks are dispatched round-robin over the 8 XCDs; tiles are renumbered
 // so that each XCD sweeps one contiguous band of tiles and the halos that
 // neighbouring tiles share stay in that XCD's L2.
@@ -200,7 +204,7 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
       const int lx = 2 * px + q;
       const int gx = gx0 + lx;
       if (lx < H || lx >= H + TX || gx >= nx) continue;
-      A.x[(int64_t)gy * nx + gx] = xs[(ly + 1) * LX + lx + 1];
+      A.xo[(int64_t)gy * nx + gx] = xs[(ly + 1) * LX + lx + 1];
     }
   }
 
@@ -260,6 +264,43 @@ __global__ void __launch_bounds__(RX / 2 * NPY)
   tile2d_body<T, RX, NPY, K, NU, DOWN>(tab[lo], b - start[lo]);
 }
 
+// Tile shapes (region RX x NPY*K cells, RX/2 * NPY threads); the
+// autotuner picks one per level and direction.
+//   0: 64 x 48, 256 threads (6 rows per thread)
+//   1: 64 x 64, 512 threads (4 rows)
+//   2: 64 x 64, 1024 threads (2 rows)
+//   3: 32 x 32, 256 threads (2 rows)  -- small levels: more, lighter blocks
+//   4: 128 x 48, 512 threads (6 rows)
+//   5: 32 x 64, 256 threads (4 rows)
+//   6: 64 x 32, 512 threads (2 rows)
+#define FLD_TILE_SHAPES(X)                                                  \
+  X(0, 64, 8, 6) X(1, 64, 16, 4) X(2, 64, 32, 2) X(3, 32, 16, 2) X(4, 128, 8, 6) \
+  X(5, 32, 16, 4) X(6, 64, 16, 2)
+
+namespace {
+struct Shape {
+  int rx, npy, k;
+};
+constexpr Shape kShapes[kTileVariants] = {
+#define FLD_SHAPE_ROW(v, rx, npy, k) {rx, npy, k},
+    FLD_TILE_SHAPES(FLD_SHAPE_ROW)
+#undef FLD_SHAPE_ROW
+};
+}  // namespace
+
+const char* tile2d_variant_name(int v) {
+  switch (v) {
+    case 0: return "64x48/256";
+    case 1: return "64x64/512";
+    case 2: return "64x64/1024";
+    case 3: return "32x32/256";
+    case 4: return "128x48/512";
+    case 5: return "32x64/256";
+    case 6: return "64x32/512";
+    default: return "?";
+  }
+}
+
 template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
 static hipError_t launch_batch_one(const Tile2DArgs<T>* tab, const int* start,
                                    int ng, int nblocks, hipStream_t s) {
@@ -268,23 +309,36 @@ static hipError_t launch_batch_one(const Tile2DArgs<T>* tab, const int* start,
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
-                               int ng, int nblocks, int nu, bool down,
-                               hipStream_t s) {
-  if (nblocks == 0) return hipSuccess;
+template <typename T, int RX, int NPY, int K>
+static hipError_t batch_shape(const Tile2DArgs<T>* tab, const int* start,
+                              int ng, int nblocks, int nu, bool down,
+                              hipStream_t s) {
   if (down) {
     switch (nu) {
-      case 1: return launch_batch_one<T, 64, 8, 6, 1, true>(tab, start, ng, nblocks, s);
-      case 2: return launch_batch_one<T, 64, 8, 6, 2, true>(tab, start, ng, nblocks, s);
-      case 3: return launch_batch_one<T, 64, 8, 6, 3, true>(tab, start, ng, nblocks, s);
+      case 1: return launch_batch_one<T, RX, NPY, K, 1, true>(tab, start, ng, nblocks, s);
+      case 2: return launch_batch_one<T, RX, NPY, K, 2, true>(tab, start, ng, nblocks, s);
+      case 3: return launch_batch_one<T, RX, NPY, K, 3, true>(tab, start, ng, nblocks, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (nu) {
-    case 1: return launch_batch_one<T, 64, 8, 6, 1, false>(tab, start, ng, nblocks, s);
-    case 2: return launch_batch_one<T, 64, 8, 6, 2, false>(tab, start, ng, nblocks, s);
-    case 3: return launch_batch_one<T, 64, 8, 6, 3, false>(tab, start, ng, nblocks, s);
+    case 1: return launch_batch_one<T, RX, NPY, K, 1, false>(tab, start, ng, nblocks, s);
+    case 2: return launch_batch_one<T, RX, NPY, K, 2, false>(tab, start, ng, nblocks, s);
+    case 3: return launch_batch_one<T, RX, NPY, K, 3, false>(tab, start, ng, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
+                               int ng, int nblocks, int nu, bool down,
+                               int variant, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  switch (variant) {
+#define FLD_SHAPE_CASE(v, rx, npy, k) \
+  case v: return batch_shape<T, rx, npy, k>(tab, start, ng, nblocks, nu, down, s);
+    FLD_TILE_SHAPES(FLD_SHAPE_CASE)
+#undef FLD_SHAPE_CASE
     default: return hipErrorInvalidValue;
   }
 }
@@ -305,51 +359,61 @@ static hipError_t launch_one(const Tile2DArgs<T>& a0, hipStream_t s,
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
-                         hipStream_t s, int* nblocks) {
+template <typename T, int RX, int NPY, int K>
+static hipError_t single_shape(const Tile2DArgs<T>& a, int nu, bool down,
+                               hipStream_t s, int* nblocks) {
   if (down) {
     switch (nu) {
-      case 1: return launch_one<T, 64, 8, 6, 1, true>(a, s, nblocks);
-      case 2: return launch_one<T, 64, 8, 6, 2, true>(a, s, nblocks);
-      case 3: return launch_one<T, 64, 8, 6, 3, true>(a, s, nblocks);
+      case 1: return launch_one<T, RX, NPY, K, 1, true>(a, s, nblocks);
+      case 2: return launch_one<T, RX, NPY, K, 2, true>(a, s, nblocks);
+      case 3: return launch_one<T, RX, NPY, K, 3, true>(a, s, nblocks);
       default: return hipErrorInvalidValue;
     }
   }
   switch (nu) {
-    case 1: return launch_one<T, 64, 8, 6, 1, false>(a, s, nblocks);
-    case 2: return launch_one<T, 64, 8, 6, 2, false>(a, s, nblocks);
-    case 3: return launch_one<T, 64, 8, 6, 3, false>(a, s, nblocks);
+    case 1: return launch_one<T, RX, NPY, K, 1, false>(a, s, nblocks);
+    case 2: return launch_one<T, RX, NPY, K, 2, false>(a, s, nblocks);
+    case 3: return launch_one<T, RX, NPY, K, 3, false>(a, s, nblocks);
     default: return hipErrorInvalidValue;
   }
 }
 
-int tile2d_blocks(const Geom& g, int nu, bool down) {
-  int tx, ty;
-  return tile2d_grid(g, nu, down, &tx, &ty);
+template <typename T>
+hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
+                         int variant, hipStream_t s, int* nblocks) {
+  switch (variant) {
+#define FLD_SHAPE_CASE(v, rx, npy, k) \
+  case v: return single_shape<T, rx, npy, k>(a, nu, down, s, nblocks);
+    FLD_TILE_SHAPES(FLD_SHAPE_CASE)
+#undef FLD_SHAPE_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
-int tile2d_grid(const Geom& g, int nu, bool down, int* tiles_x, int* tiles_y) {
-  constexpr int RX = 64, RY = 48;
+int tile2d_blocks(const Geom& g, int nu, bool down, int variant) {
+  int tx, ty;
+  return tile2d_grid(g, nu, down, variant, &tx, &ty);
+}
+
+int tile2d_grid(const Geom& g, int nu, bool down, int variant, int* tiles_x,
+                int* tiles_y) {
+  const Shape sh = kShapes[variant];
   const int H = down ? 2 * nu + 2 : 2 * nu;
-  const int TX = RX - 2 * H, TY = RY - 2 * H;
+  const int TX = sh.rx - 2 * H, TY = sh.npy * sh.k - 2 * H;
   *tiles_x = (g.n[0] + TX - 1) / TX;
   *tiles_y = (g.n[1] + TY - 1) / TY;
   return *tiles_x * *tiles_y;
 }
 
 template hipError_t launch_tile2d<double>(const Tile2DArgs<double>&, int, bool,
-                                          hipStream_t, int*);
+                                          int, hipStream_t, int*);
 template hipError_t launch_tile2d<float>(const Tile2DArgs<float>&, int, bool,
-                                         hipStream_t, int*);
-
-}  // namespace fld
-
-namespace fld {
+                                         int, hipStream_t, int*);
 template hipError_t launch_tile2d_batch<double>(const Tile2DArgs<double>*,
                                                 const int*, int, int, int,
-                                                bool, hipStream_t);
+                                                bool, int, hipStream_t);
 template hipError_t launch_tile2d_batch<float>(const Tile2DArgs<float>*,
                                                const int*, int, int, int, bool,
-                                               hipStream_t);
+                                               int, hipStream_t);
+
 }  // namespace fld

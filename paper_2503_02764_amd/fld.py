@@ -37,7 +37,7 @@ EXPORTED = [
     "fld_params_default", "fld_workspace_bytes", "fld_setup", "fld_step",
     "fld_exchange", "fld_opacity_powerlaw", "fld_kernel_timing_enable",
     "fld_kernel_timing_read", "fld_destroy", "fld_status_str",
-    "fld_last_error",
+    "fld_last_error", "fld_autotune", "fld_tile_shape_name",
 ]
 
 
@@ -115,6 +115,10 @@ def load(path=LIB_PATH):
     lib.fld_status_str.restype = ctypes.c_char_p
     lib.fld_last_error.argtypes = [V]
     lib.fld_last_error.restype = ctypes.c_char_p
+    lib.fld_autotune.argtypes = [V, P(ctypes.c_int32), ctypes.c_int32]
+    lib.fld_autotune.restype = ctypes.c_int
+    lib.fld_tile_shape_name.argtypes = [ctypes.c_int32]
+    lib.fld_tile_shape_name.restype = ctypes.c_char_p
     _batch_argtypes(lib)
     _lib = lib
     return lib
@@ -260,6 +264,16 @@ def fld_kernel_timing_read(ctx):
         ctypes.byref(name)))
     return dict(ms=ms.value, launches=n.value, bytes=by.value,
                 kernel=name.value.decode())
+
+
+def fld_autotune(ctx, max_levels=24):
+    """Tune the tile shapes; returns [(down, up) shape name per level]."""
+    lib = load()
+    arr = (ctypes.c_int32 * (2 * max_levels))()
+    _check(ctx.ptr, lib.fld_autotune(ctx.ptr, arr, max_levels))
+    return [(lib.fld_tile_shape_name(arr[2 * l]).decode(),
+             lib.fld_tile_shape_name(arr[2 * l + 1]).decode())
+            for l in range(max_levels)]
 
 
 def fld_destroy(ctx):

@@ -118,3 +118,54 @@ def test_batch_rejects_bad_setups():
                                                 ("neumann", "neumann")))
     with pytest.raises(fld.FldError):
         fld.fld_setup_batch([tiny])
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_batch_tile_shapes_give_identical_iterates(variant, monkeypatch):
+    from paper_2503_02764_amd import fld
+    ms = _media()
+    announce(f"batch tile shape {variant} vs 0")
+    out = {}
+    for v in (0, variant):
+        monkeypatch.setenv("FLD_TILE_VARIANT", str(v))
+        for prec in ("fp64", "fp32_ir"):
+            params = [params_for(m, rtol=1e-10, precision=prec) for m in ms]
+            bctx = fld.fld_setup_batch(params)
+            o = [dev(np.zeros_like(m.E)) for m in ms]
+            fld.fld_step_batch(bctx, [m.dt for m in ms],
+                               [dev(m.rho) for m in ms],
+                               [dev(m.kappa) for m in ms],
+                               [dev(m.E) for m in ms], o)
+            out[(v, prec)] = [host(x) for x in o]
+    for prec in ("fp64", "fp32_ir"):
+        for g in range(len(ms)):
+            np.testing.assert_array_equal(out[(0, prec)][g],
+                                          out[(variant, prec)][g],
+                                          err_msg=f"{prec} grid {g}")
+
+
+def test_batch_autotune_keeps_results_and_graph():
+    """Tuned shapes give the same iterates; a graph captured before the
+    tuning is dropped and captured again with the new launch shapes."""
+    from paper_2503_02764_amd import fld
+    import torch
+    ms = _media()
+    announce("batch autotune + graph")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        params = [params_for(m, rtol=1e-10, precision="fp32_ir") for m in ms]
+        bctx = fld.fld_setup_batch(params, stream=stream)
+        fld.fld_batch_set_graph(bctx, True)
+        rho = [dev(m.rho) for m in ms]
+        kap = [dev(m.kappa) for m in ms]
+        E = [dev(m.E) for m in ms]
+        dts = [m.dt for m in ms]
+        out0 = [torch.zeros_like(x) for x in E]
+        fld.fld_step_batch(bctx, dts, rho, kap, E, out0)
+        shapes = fld.fld_autotune(bctx)
+        out1 = [torch.zeros_like(x) for x in E]
+        fld.fld_step_batch(bctx, dts, rho, kap, E, out1)
+        stream.synchronize()
+    assert shapes[0][0] != "invalid"
+    for g in range(len(ms)):
+        np.testing.assert_array_equal(host(out1[g]), host(out0[g]))

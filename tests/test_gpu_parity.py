@@ -336,3 +336,47 @@ def test_mixed_precision_c3_like_stratified():
     assert rel_l2(x, ref) <= 1e-8, stats
     x64, s64 = _solve_gpu(m, rtol=1e-9, max_cycles=400)
     assert rel_l2(x64, ref) <= 1e-8, s64
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+def test_tile_shapes_give_identical_iterates(variant, monkeypatch):
+    """Every tile shape performs the same red-black sweeps, residuals and
+    transfers cell by cell: the same iterate bit for bit (the residual norm
+    is summed in another order, so the stop test could differ only at a
+    tie; the cycle count is checked too)."""
+    from paper_2503_02764_amd import fld
+    m = media.config_c2(n=256)
+    prob = F.problem_from_medium(m)
+    kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    announce(f"tile shape {variant} vs 0 on c2 256")
+    out = {}
+    for v in (0, variant):
+        monkeypatch.setenv("FLD_TILE_VARIANT", str(v))
+        for prec in ("fp64", "fp32_ir"):
+            ctx = fld.fld_setup(params_for(m, rtol=1e-10, precision=prec))
+            x = dev(np.zeros_like(m.E))
+            _, st = fld.fld_step(ctx, m.dt, dev(m.rho), dev(kap), dev(m.E), x)
+            out[(v, prec)] = (host(x), st["cycles"])
+    for prec in ("fp64", "fp32_ir"):
+        assert out[(0, prec)][1] == out[(variant, prec)][1]
+        np.testing.assert_array_equal(out[(0, prec)][0], out[(variant, prec)][0])
+
+
+def test_autotune_keeps_results():
+    from paper_2503_02764_amd import fld
+    m = media.config_c2(n=256)
+    prob = F.problem_from_medium(m)
+    kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    ref = F.diffusion_step(m.E, m.rho, kap, m.dt, prob)
+    announce("autotune c2 256")
+    ctx = fld.fld_setup(params_for(m, rtol=1e-12))
+    x0 = dev(np.zeros_like(m.E))
+    fld.fld_step(ctx, m.dt, dev(m.rho), dev(kap), dev(m.E), x0)
+    shapes = fld.fld_autotune(ctx)
+    names = {"64x48/256", "64x64/512", "64x64/1024", "32x32/256", "128x48/512",
+             "32x64/256", "64x32/512"}
+    assert all(d in names and u in names for d, u in shapes[:4]), shapes
+    x1 = dev(np.zeros_like(m.E))
+    fld.fld_step(ctx, m.dt, dev(m.rho), dev(kap), dev(m.E), x1)
+    assert rel_l2(host(x1), ref) <= 1e-10
+    np.testing.assert_array_equal(host(x1), host(x0))
