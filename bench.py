@@ -75,6 +75,9 @@ def main():
                     help="keep the default tile shape on every level")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline variant (for profiling)")
+    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
+                    help="c2: 2D 1024^2 (the headline); c3: 3D 256^3 "
+                         "stratified; c4: 96 batched 2D grids")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -101,6 +104,10 @@ def main():
     from paper_2503_02764_amd import fld
     from paper_2503_02764_amd.solver import Stepper, make_params
 
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     m = media.config_c2(n=args.n)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -245,6 +252,163 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def _line(metric_value, ms, args, workload, dtype, extra):
+    out = {
+        "metric": METRIC, "value": metric_value, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": workload}, "roofline": None,
+        "cpu_baseline": None}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3(args):
+    """3D 256^3 stratified medium: FP64 V-cycles vs FP32 V-cycles in FP64
+    refinement (and with the learned guess applied per z-slice)."""
+    import numpy as np
+    import torch
+    import media
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.guess import load_weights
+    from paper_2503_02764_amd.solver import Stepper, make_params
+    m = media.config_c3()
+    steps = min(args.steps, 5)
+    warm = min(args.warmup, 1)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def run(precision, weights=None):
+        params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
+                             guess="prev" if weights is None else "learned")
+        st = Stepper(params, opacity=m.opacity)
+        if weights is not None:
+            fld.fld_set_model(st.ctx, weights)
+        rho, E, e = d(m.rho), d(m.E), d(m.e)
+        kap = torch.empty_like(rho)
+        for _ in range(warm):
+            st.step(m.dt, rho, kap, E, e)
+        torch.cuda.synchronize()
+        cyc = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cyc.append(st.step(m.dt, rho, kap, E, e)["cycles"])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        res = dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
+                   vcycles_per_step=float(np.mean(cyc)))
+        E_out = E.cpu().numpy()
+        del st, rho, E, e, kap
+        torch.cuda.empty_cache()
+        return res, E_out
+
+    f64, E64 = run("fp64")
+    f32, E32 = run("fp32_ir")
+    lrn, _ = run("fp32_ir", load_weights())
+    f32["rel_l2_vs_fp64_after_steps"] = float(
+        np.linalg.norm(E32 - E64) / np.linalg.norm(E64))
+    f32["speedup_vs_fp64"] = f32["value"] / f64["value"]
+    lrn["speedup_vs_fp64"] = lrn["value"] / f64["value"]
+    args.steps, args.warmup = steps, warm
+    _line(f32["value"], f32["ms_per_step"], args,
+          "3d-256cube-stratified-kramers-fp32-vcycles-fp64-refinement", "f32",
+          {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
+                        "learned_guess_fp32_vcycles": lrn}})
+
+
+def bench_c4(args):
+    """96 independent 2D grids (sides 128..1024) in one batched context:
+    FP32 V-cycles in FP64 refinement, one launch per phase, hipGraph
+    replay, autotuned tiles; against the same grids stepped one by one with
+    single-grid contexts (same precision, and plain FP64)."""
+    import numpy as np
+    import torch
+    import media
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.solver import Stepper, make_params
+    ms = media.config_c4()
+    steps = min(args.steps, 5)
+    warm = min(args.warmup, 1)
+    o = ms[0].opacity
+    cells = sum(m.cells for m in ms)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def fields():
+        rho = [d(m.rho) for m in ms]
+        return rho, [d(m.E) for m in ms], [d(m.e) for m in ms], \
+            [torch.empty_like(r) for r in rho]
+
+    dts = [m.dt for m in ms]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        params = [make_params(2, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
+                              precision="fp32_ir") for m in ms]
+        bctx = fld.fld_setup_batch(params, stream=stream)
+        fld.fld_batch_set_graph(bctx, True)
+        shapes = fld.fld_autotune(bctx)[:6]
+        rho, E, e, kap = fields()
+
+        def step():
+            fld.fld_opacity_powerlaw_batch(bctx, rho, e, o["k0"], o["a"],
+                                           o["b"], o["kmin"], o["kmax"], kap)
+            fld.fld_step_batch(bctx, dts, rho, kap, E, E)
+            fld.fld_exchange_batch(bctx, dts, rho, kap, E, e)
+
+        for _ in range(warm):
+            step()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        stream.synchronize()
+        secs = time.perf_counter() - t0
+        E_batch = [x.cpu().numpy() for x in E]
+    batch = dict(value=cells * steps / secs, ms_per_step=secs * 1e3 / steps,
+                 tile_shapes_autotuned=shapes)
+    del bctx, rho, E, e, kap
+    torch.cuda.empty_cache()
+
+    def one_by_one(precision):
+        sts = []
+        for m in ms:
+            st = Stepper(make_params(2, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
+                                     precision=precision), opacity=m.opacity)
+            fld.fld_autotune(st.ctx)
+            sts.append(st)
+        rho, E, e, kap = fields()
+        for _ in range(warm):
+            for g, st in enumerate(sts):
+                st.step(dts[g], rho[g], kap[g], E[g], e[g])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for g, st in enumerate(sts):
+                st.step(dts[g], rho[g], kap[g], E[g], e[g])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out = [x.cpu().numpy() for x in E]
+        del sts, rho, E, e, kap
+        torch.cuda.empty_cache()
+        return dict(value=cells * steps / secs, ms_per_step=secs * 1e3 / steps), out
+
+    seq32, E32 = one_by_one("fp32_ir")
+    seq64, E64 = one_by_one("fp64")
+    diff = max(float(np.linalg.norm(a - b) / np.linalg.norm(b))
+               for a, b in zip(E_batch, E64))
+    batch["speedup_vs_one_by_one_fp32"] = batch["value"] / seq32["value"]
+    batch["speedup_vs_one_by_one_fp64"] = batch["value"] / seq64["value"]
+    batch["max_rel_l2_vs_fp64_after_steps"] = diff
+    args.steps, args.warmup = steps, warm
+    _line(batch["value"], batch["ms_per_step"], args,
+          f"2d-batched-{len(ms)}-grids-{cells}-cells-fp32-vcycles-fp64-refinement-graph",
+          "f32", {"variants": {"batched": batch, "one_by_one_fp32": seq32,
+                               "one_by_one_fp64": seq64}})
 
 
 if __name__ == "__main__":
