@@ -293,23 +293,38 @@ __device__ __forceinline__ void coarsen_body(const CoarsenArgs<T>& A, int bid) {
   coords(A.c, idx, c);
   const int nd = A.c.ndim;
   for (int d = 0; d < nd; ++d) {
+    // the coarse face between coarse cells c and c+1 along d: on a Neumann
+    // wall it stays a wall
+    if (c[d] == A.c.n[d] - 1 && !A.c.per[d]) {
+      A.ca[d][idx] = T(0);
+      continue;
+    }
     T s = T(0);
     int cnt = 0;
-    // fine cell on the lower side of the coarse face: 2c+1 along d,
-    // 2c or 2c+1 across.
     const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
     for (int q2 = 0; q2 < o2; ++q2)
       for (int q1 = 0; q1 < o1; ++q1) {
+        // one fine path along d at a fixed transverse position: the face
+        // inside coarse cell c (2c | 2c+1), the face on the coarse face
+        // (2c+1 | 2c+2) and the face inside coarse cell c+1 (2c+2 | 2c+3),
+        // conductances in series
         int f[3] = {2 * c[0], 2 * c[1], 2 * c[2]};
-        f[d] += 1;
-        // the transverse dimensions of d, in increasing order
         const int t1 = (d == 0) ? 1 : 0;
         const int t2 = (d == 2) ? 1 : 2;
         if (nd > 1) f[t1] += q1;
         if (nd > 2) f[t2] += q2;
-        const int64_t fi =
-            f[0] + (int64_t)A.f.n[0] * (f[1] + (int64_t)A.f.n[1] * f[2]);
-        s += A.fa[d][fi];
+        T a3[3];
+        for (int k = 0; k < 3; ++k) {
+          int g[3] = {f[0], f[1], f[2]};
+          g[d] = (2 * c[d] + k) % A.f.n[d];  // wraps only when periodic
+          const int64_t fi =
+              g[0] + (int64_t)A.f.n[0] * (g[1] + (int64_t)A.f.n[1] * g[2]);
+          a3[k] = A.fa[d][fi];
+        }
+        T path = T(0);
+        if (a3[0] > T(0) && a3[1] > T(0) && a3[2] > T(0))
+          path = T(2) / (T(0.5) / a3[0] + T(1) / a3[1] + T(0.5) / a3[2]);
+        s += path;
         ++cnt;
       }
     A.ca[d][idx] = T(0.25) * s / T(cnt);
