@@ -348,3 +348,51 @@ def test_learned_guess_requires_model():
         fld.fld_set_model(ctx, bad)
     with pytest.raises(ValueError):
         fld.fld_set_model(ctx, bad[:-1])
+
+
+def test_training_targets_match_oracle_solve():
+    """The training pipeline's targets (library FP64 solve after the
+    medium's pre-steps) equal the oracle's exact solve of the same state."""
+    import torch
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd import train_guess as TG
+    idx = 2  # sampled after 3 full steps
+    item = TG._medium(idx)
+    _, rho, E, e, dt, dx, o = item
+    announce("training target vs oracle, medium 2 (3 pre-steps)")
+    grid = TG._Grid(rho.shape[0])
+    ctx = grid.ctx(dx, 1e-11)
+    r, kap, En, dt = grid.state(item, ctx)
+    feats = torch.empty(En.numel() * 4, dtype=torch.float32, device="cuda")
+    fld.fld_features(ctx, dt, r, kap, En, feats)
+    Es = torch.empty_like(En)
+    fld.fld_step(ctx, dt, r, kap, En, Es)
+    n = rho.shape[0]
+    prob = F.Problem(ndim=2, n=(n, n, 1), dx=(dx, dx, 1.0),
+                     bc=("neumann", "neumann"))
+    En_h = host(En).reshape(n, n)
+    kap_h = host(kap).reshape(n, n)
+    ref = F.diffusion_step(En_h, rho, kap_h, dt, prob)
+    assert rel_l2(host(Es).reshape(n, n), ref) <= 1e-10
+    al = F.face_coefficients(En_h, rho, kap_h, dt, prob)
+    fref = U.features(En_h, rho * kap_h * dx, al[0], al[1])[0]
+    np.testing.assert_allclose(host(feats).reshape(n, n, 4), fref, rtol=2e-7,
+                               atol=1e-7)
+
+
+def test_trained_network_gains_over_plain_guess():
+    """What the committed network gains on held-out media (seeds never seen
+    in training): its guess, after the finest pre-smoothing, has a smaller
+    residual than E^n on most media and the solve needs fewer V-cycles on
+    average, with the same answer."""
+    from paper_2503_02764_amd import train_guess as TG
+    from paper_2503_02764_amd.guess import load_weights
+    w = load_weights()
+    held = list(range(TG.HELDOUT_OFFSET + 500, TG.HELDOUT_OFFSET + 532))
+    announce("trained network on 32 held-out 256^2 media")
+    ev = TG.evaluate(w, held, 256, None, "fp64")
+    print("held-out evaluation:", ev)
+    assert ev["media"] == 32
+    assert ev["median_initial_residual_ratio"] < 0.5, ev
+    assert ev["rejected"] <= 4, ev
+    assert ev["mean_cycles_learned"] < ev["mean_cycles_prev"], ev
