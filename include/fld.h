@@ -92,7 +92,8 @@ typedef struct {
   int32_t max_cycles;    /* V-cycle cap (fine-level smoothing passes)      */
   int32_t pre_smooth;    /* red-black Gauss-Seidel sweeps before restriction */
   int32_t post_smooth;   /* sweeps after prolongation                      */
-  int32_t pad1;
+  int32_t ir_inner;      /* FP32 V-cycles per refinement iteration
+                            (FP32_IR), 1..8; 0 selects 2             */
 } fld_params;
 
 typedef struct {

@@ -197,6 +197,7 @@ std::string validate(const fld_params* p) {
   if (p->guess == FLD_GUESS_LEARNED && p->n[2] > 16384)
     return "the learned guess takes at most 16384 z-slices";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
+  if (p->ir_inner < 0 || p->ir_inner > 8) return "ir_inner must be in [0, 8]";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
   if (p->pre_smooth < 0 || p->post_smooth < 0 ||
       p->pre_smooth + p->post_smooth < 1 || p->pre_smooth > 16 ||
@@ -985,6 +986,7 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   c->ws_bytes = ws_bytes;
   c->L = P.L;
   c->mixed = p->precision == FLD_PREC_FP32_IR;
+  c->inner = p->ir_inner > 0 ? p->ir_inner : 2;
   char* w = c->ws;
   for (int l = 0; l < P.L; ++l) {
     c->geom[l] = P.g[l];
@@ -1214,7 +1216,8 @@ namespace {
 // (zeroed level buffers of the context: the kernels' speed does not depend
 // on the values) and keep the fastest.  choice[l][0 / 1]: down / up.
 template <typename T>
-fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2]) {
+fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2],
+                       int nvar) {
   hipStream_t s = c->stream;
   // Level-0 buffers: the FP32 iterate and rhs of a mixed context belong to
   // the workspace; the FP64 ones are the caller's arrays during a step (the
@@ -1262,7 +1265,7 @@ fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2]) {
       // best of 3 rounds per shape; a shape replaces the current choice
       // only when it is more than 3% faster (stable choices across runs)
       float best = 1e30f;
-      for (int v = 0; v < kTileVariants && st == FLD_OK; ++v) {
+      for (int v = 0; v < nvar && st == FLD_OK; ++v) {
         float vbest = 1e30f;
         for (int round = 0; round < 3 && st == FLD_OK; ++round) {
           int nb = 0;
@@ -1291,11 +1294,11 @@ fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2]) {
   return st;
 }
 
-fld_status tune_ctx(fld_ctx* c, int choice[kMaxLevels][2]) {
+fld_status tune_ctx(fld_ctx* c, int choice[kMaxLevels][2], int nvar) {
   for (int l = 0; l < kMaxLevels; ++l) choice[l][0] = choice[l][1] = 0;
   if (!tile_path(c)) return FLD_OK;
-  return c->mixed ? tune_levels<float>(c, c->h32, choice)
-                  : tune_levels<double>(c, c->h64, choice);
+  return c->mixed ? tune_levels<float>(c, c->h32, choice, nvar)
+                  : tune_levels<double>(c, c->h64, choice, nvar);
 }
 
 }  // namespace
@@ -1313,7 +1316,7 @@ fld_status fld_autotune(fld_ctx* c, int32_t* choices, int32_t max_levels) {
     fld_ctx* big = B->sub[0];
     for (fld_ctx* sub : B->sub)
       if (sub->geom[0].N > big->geom[0].N) big = sub;
-    const fld_status st = tune_ctx(big, choice);
+    const fld_status st = tune_ctx(big, choice, kTileVariantsBatch);
     if (st != FLD_OK) return fail(c, st, "%s", big->err.c_str());
     for (int l = 0; l < kMaxLevels; ++l)
       for (int d = 0; d < 2; ++d) B->tile_var[l][d] = choice[l][d];
@@ -1324,7 +1327,7 @@ fld_status fld_autotune(fld_ctx* c, int32_t* choices, int32_t max_levels) {
     B->graph = nullptr;
     B->last.clear();
   } else {
-    FLD_TRY(tune_ctx(c, choice));
+    FLD_TRY(tune_ctx(c, choice, kTileVariants));
     for (int l = 0; l < kMaxLevels; ++l)
       for (int d = 0; d < 2; ++d) c->tile_var[l][d] = choice[l][d];
   }
@@ -1451,6 +1454,8 @@ static std::string validate_batch(int32_t count, const fld_params* each) {
         p.post_smooth != each[0].post_smooth)
       return "batched grids need equal pre/post smoothing in 1..3";
     if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
+    if (p.ir_inner != each[0].ir_inner)
+      return "batched grids must share ir_inner";
     Plan P;
     make_plan(&p, &P);
     int l0 = P.L - 1;
@@ -1554,7 +1559,7 @@ fld_status fld_setup_batch(int32_t count, const fld_params* each,
   B->ng = count;
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {  // as in fld_setup
     const int v = atoi(tv);
-    if (v >= 0 && v < kTileVariants)
+    if (v >= 0 && v < kTileVariantsBatch)
       for (int l = 0; l < kMaxLevels; ++l) B->tile_var[l][0] = B->tile_var[l][1] = v;
   }
   for (int g = 0; g < count; ++g) {

@@ -24,14 +24,16 @@ struct Tile2DArgs {
   const Control* ctrl;
 };
 
-// Tile shapes available to the launchers (see fld_tile2d.hip).
-constexpr int kTileVariants = 7;
+// Tile shapes available to the launchers (see fld_tile2d.hip); the batched
+// launcher takes the first kTileVariantsBatch.
+constexpr int kTileVariants = 10;
+constexpr int kTileVariantsBatch = 7;
 const char* tile2d_variant_name(int variant);
 
 // Launch the down (pre-smoothing + residual + restriction) or up
 // (prolongation + post-smoothing) kernel with nu red-black sweeps
 // (nu in 1..3) and tile shape `variant`.  *nblocks receives the number of
-// tiles.
+// tiles (one partial sum each on the finest down pass).
 template <typename T>
 hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
                          int variant, hipStream_t s, int* nblocks);

@@ -52,7 +52,7 @@ class fld_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
         ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32),
         ("pre_smooth", ctypes.c_int32), ("post_smooth", ctypes.c_int32),
-        ("pad1", ctypes.c_int32),
+        ("ir_inner", ctypes.c_int32),
     ]
 
 
