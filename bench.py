@@ -176,6 +176,8 @@ def main():
         fld.fldnn_forward(net, xin, dout)
     torch.cuda.synchronize()
     unet_ms = (time.perf_counter() - t0) * 100.0
+    from paper_2503_02764_amd.train_guess import forward_flops
+    unet_flops = forward_flops(m.n[1], m.n[0])
     kt = base["kernel"]
     avg_ms = kt["ms"] / max(kt["launches"], 1)
     bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
@@ -233,6 +235,11 @@ def main():
                 "speedup_vs_fp64": lrn32["value"] / base["value"],
             },
             "unet_forward_ms": unet_ms,
+            "unet_forward": {
+                "gflop_executed": unet_flops / 1e9,
+                "gflop_useful": forward_flops(m.n[1], m.n[0], False) / 1e9,
+                "tflops": unet_flops / (unet_ms * 1e-3) / 1e12,
+                "frac_of_bf16_peak": unet_flops / (unet_ms * 1e-3) / 2.5e15},
         },
         "roofline": {
             "bound": "hbm",

@@ -152,13 +152,29 @@ def evaluate(weights, indices, n, pool, precision="fp64"):
                 rejected=int(sum(r["rejected"] for r in rows)))
 
 
+# the network of fldnn.h: (input channels, output channels, kernel size,
+# resolution level) per layer, in parameter order
+LAYERS = [(4, 16, 3, 0), (16, 16, 3, 0), (16, 32, 3, 1), (32, 32, 3, 1),
+          (32, 64, 3, 2), (64, 64, 3, 2), (64, 128, 3, 3), (128, 128, 3, 3),
+          (192, 64, 3, 2), (64, 64, 3, 2), (96, 32, 3, 1), (32, 32, 3, 1),
+          (48, 16, 3, 0), (16, 16, 3, 0), (16, 1, 1, 0)]
+
+
+def forward_flops(H, W, padded=True):
+    """Multiply-add flops of one forward pass on an H x W image (the kernels
+    pad channel counts to multiples of 16)."""
+    pad = (lambda c: (c + 15) // 16 * 16) if padded else (lambda c: c)
+    total = 0
+    for ci, co, k, lev in LAYERS:
+        pixels = (H >> lev) * (W >> lev)
+        total += 2 * k * k * pad(ci) * (pad(co) if k > 1 else co) * pixels
+    return total
+
+
 def he_init(seed):
     """He-normal weights, zero biases, head scaled down (FP32, fldnn.h order)."""
     rng = np.random.default_rng(seed)
-    layers = [(4, 16, 3), (16, 16, 3), (16, 32, 3), (32, 32, 3), (32, 64, 3),
-              (64, 64, 3), (64, 128, 3), (128, 128, 3), (192, 64, 3),
-              (64, 64, 3), (96, 32, 3), (32, 32, 3), (48, 16, 3), (16, 16, 3),
-              (16, 1, 1)]
+    layers = [(ci, co, k) for ci, co, k, _ in LAYERS]
     parts = []
     for li, (ci, co, k) in enumerate(layers):
         std = math.sqrt(2.0 / (ci * k * k))
