@@ -84,6 +84,9 @@ fld_status fldnn_train_step(fldnn* net, const float* inputs,
 
 void fldnn_destroy(fldnn* net);
 
+/* Message of the last failed fldnn_* call on this thread ("" if none). */
+const char* fldnn_last_error(void);
+
 /* The network inputs fld_step computes for its learned guess, for training:
  * per cell, FP32 [4] = (log E - mean over the cell's z-slice of log E,
  * log(rho kappa dx[0]) / 4, log(1 + alpha_x) / 4, log(1 + alpha_y) / 4),

@@ -458,7 +458,23 @@ struct fldnn {
 
 namespace {
 thread_local std::string g_nn_err;
+
+fld_status nn_fail(fld_status st, const std::string& msg) {
+  g_nn_err = msg;
+  return st;
 }
+
+fld_status nn_dev(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FLD_OK;
+  return nn_fail(FLD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NN_OK(expr)                \
+  do {                             \
+    const fld_status s_ = (expr);  \
+    if (s_ != FLD_OK) return s_;   \
+  } while (0)
+}  // namespace
 
 extern "C" {
 
@@ -468,77 +484,94 @@ size_t fldnn_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t training) 
   return fld::nn::workspace_bytes(N, H, W, training);
 }
 
+const char* fldnn_last_error(void) { return g_nn_err.c_str(); }
+
 fld_status fldnn_create(int32_t N, int32_t H, int32_t W, int32_t training,
                         void* workspace, size_t ws_bytes, void* hip_stream,
                         fldnn** out) {
-  if (!out) return FLD_ERR_INVALID_ARG;
+  if (!out) return nn_fail(FLD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (!workspace || (uintptr_t)workspace % 256) return FLD_ERR_WORKSPACE;
+  if (fld::nn::workspace_bytes(N, H, W, training) == 0)
+    return nn_fail(FLD_ERR_INVALID_ARG,
+                   "N >= 1 and H, W multiples of 8 (>= 8) are required");
+  if (!workspace || (uintptr_t)workspace % 256)
+    return nn_fail(FLD_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
   std::string err;
   fld::nn::Net* n = fld::nn::create(N, H, W, training, (char*)workspace,
                                     ws_bytes, (hipStream_t)hip_stream, &err);
-  if (!n) {
-    g_nn_err = err;
-    return fld::nn::workspace_bytes(N, H, W, training) == 0 ? FLD_ERR_INVALID_ARG
-                                                            : FLD_ERR_WORKSPACE;
-  }
+  if (!n) return nn_fail(FLD_ERR_WORKSPACE, err);
   *out = new fldnn{n};
   return FLD_OK;
 }
 
 fld_status fldnn_set_params(fldnn* net, const float* host, size_t count) {
-  if (!net || !host) return FLD_ERR_INVALID_ARG;
-  return fld::nn::set_params(net->net, host, count) ? FLD_OK : FLD_ERR_MODEL;
+  if (!net || !host) return nn_fail(FLD_ERR_INVALID_ARG, "NULL argument");
+  if (count != fld::nn::param_count())
+    return nn_fail(FLD_ERR_MODEL, "wrong parameter count");
+  return fld::nn::set_params(net->net, host, count)
+             ? FLD_OK
+             : nn_fail(FLD_ERR_MODEL, "non-finite parameter or device error");
 }
 
 fld_status fldnn_get_params(fldnn* net, float* host, size_t count) {
-  if (!net || !host) return FLD_ERR_INVALID_ARG;
-  return fld::nn::get_params(net->net, host, count) ? FLD_OK
-                                                    : FLD_ERR_INVALID_ARG;
+  if (!net || !host) return nn_fail(FLD_ERR_INVALID_ARG, "NULL argument");
+  if (count != fld::nn::param_count())
+    return nn_fail(FLD_ERR_INVALID_ARG, "wrong parameter count");
+  return fld::nn::get_params(net->net, host, count)
+             ? FLD_OK
+             : nn_fail(FLD_ERR_DEVICE, "copy of the parameters failed");
 }
 
 fld_status fldnn_forward(fldnn* net, const float* inputs, float* delta) {
-  if (!net || !inputs || !delta) return FLD_ERR_INVALID_ARG;
+  if (!net || !inputs || !delta)
+    return nn_fail(FLD_ERR_INVALID_ARG, "NULL argument");
   fld::nn::Net* n = net->net;
-  if (fld::nn::set_input(n, inputs) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::forward_x(n) != hipSuccess) return FLD_ERR_DEVICE;
+  NN_OK(nn_dev(fld::nn::set_input(n, inputs), "input conversion"));
+  NN_OK(nn_dev(fld::nn::forward_x(n), "forward pass"));
   const size_t bytes = (size_t)n->N * n->H * n->W * sizeof(float);
-  if (hipMemcpyAsync(delta, n->delta, bytes, hipMemcpyDeviceToDevice,
-                     n->stream) != hipSuccess)
-    return FLD_ERR_DEVICE;
-  return FLD_OK;
+  return nn_dev(hipMemcpyAsync(delta, n->delta, bytes, hipMemcpyDeviceToDevice,
+                               n->stream),
+                "copy of delta");
 }
 
 fld_status fldnn_gradients(fldnn* net, const float* inputs,
                            const float* targets, float* loss_host,
                            float* grads_host, size_t count) {
-  if (!net || !inputs || !targets || !grads_host) return FLD_ERR_INVALID_ARG;
+  if (!net || !inputs || !targets || !grads_host)
+    return nn_fail(FLD_ERR_INVALID_ARG, "NULL argument");
   fld::nn::Net* n = net->net;
-  if (!n->training) return FLD_ERR_INVALID_ARG;
-  if (fld::nn::set_input(n, inputs) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::forward_x(n) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::backward(n, targets, inputs) != hipSuccess) return FLD_ERR_DEVICE;
-  return fld::nn::gradients(n, loss_host, grads_host, count) ? FLD_OK
-                                                             : FLD_ERR_DEVICE;
+  if (!n->training)
+    return nn_fail(FLD_ERR_INVALID_ARG, "the network was created without training buffers");
+  if (count != fld::nn::param_count())
+    return nn_fail(FLD_ERR_INVALID_ARG, "wrong parameter count");
+  NN_OK(nn_dev(fld::nn::set_input(n, inputs), "input conversion"));
+  NN_OK(nn_dev(fld::nn::forward_x(n), "forward pass"));
+  NN_OK(nn_dev(fld::nn::backward(n, targets, inputs), "backward pass"));
+  return fld::nn::gradients(n, loss_host, grads_host, count)
+             ? FLD_OK
+             : nn_fail(FLD_ERR_DEVICE, "copy of the gradients failed");
 }
 
 fld_status fldnn_train_step(fldnn* net, const float* inputs,
                             const float* targets, float lr, int32_t step,
                             float* loss_host) {
-  if (!net || !inputs || !targets || step < 1) return FLD_ERR_INVALID_ARG;
+  if (!net || !inputs || !targets || step < 1)
+    return nn_fail(FLD_ERR_INVALID_ARG, "NULL argument or step < 1");
   fld::nn::Net* n = net->net;
-  if (!n->training) return FLD_ERR_INVALID_ARG;
-  if (fld::nn::set_input(n, inputs) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::forward_x(n) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::backward(n, targets, inputs) != hipSuccess) return FLD_ERR_DEVICE;
-  if (fld::nn::adam(n, lr, step) != hipSuccess) return FLD_ERR_DEVICE;
-  if (loss_host && !fld::nn::read_loss(n, loss_host)) return FLD_ERR_DEVICE;
+  if (!n->training)
+    return nn_fail(FLD_ERR_INVALID_ARG, "the network was created without training buffers");
+  NN_OK(nn_dev(fld::nn::set_input(n, inputs), "input conversion"));
+  NN_OK(nn_dev(fld::nn::forward_x(n), "forward pass"));
+  NN_OK(nn_dev(fld::nn::backward(n, targets, inputs), "backward pass"));
+  NN_OK(nn_dev(fld::nn::adam(n, lr, step), "Adam update"));
+  if (loss_host && !fld::nn::read_loss(n, loss_host))
+    return nn_fail(FLD_ERR_DEVICE, "reading the loss failed");
   return FLD_OK;
 }
 
 fld_status fldnn_set_loss(fldnn* net, int32_t kind) {
   if (!net || (kind != FLDNN_LOSS_MSE && kind != FLDNN_LOSS_ENERGY))
-    return FLD_ERR_INVALID_ARG;
+    return nn_fail(FLD_ERR_INVALID_ARG, "NULL network or unknown loss");
   net->net->loss_kind = kind;
   return FLD_OK;
 }

@@ -421,7 +421,7 @@ def fld_batch_set_graph(ctx, on=True):
 EXPORTED_NN = ["fldnn_param_count", "fldnn_workspace_bytes", "fldnn_create",
                "fldnn_set_params", "fldnn_get_params", "fldnn_forward",
                "fldnn_gradients", "fldnn_train_step", "fldnn_destroy",
-               "fldnn_set_loss",
+               "fldnn_set_loss", "fldnn_last_error",
                "fld_features", "fld_set_model"]
 
 
@@ -446,6 +446,8 @@ def _nn_argtypes(lib):
     lib.fldnn_gradients.restype = ctypes.c_int
     lib.fldnn_train_step.argtypes = [V, V, V, F, I32, P(F)]
     lib.fldnn_train_step.restype = ctypes.c_int
+    lib.fldnn_last_error.argtypes = []
+    lib.fldnn_last_error.restype = ctypes.c_char_p
     lib.fldnn_set_loss.argtypes = [V, I32]
     lib.fldnn_set_loss.restype = ctypes.c_int
     lib.fldnn_destroy.argtypes = [V]
@@ -461,6 +463,11 @@ def _nnlib():
     lib = load()
     _nn_argtypes(lib)
     return lib
+
+
+def _check_nn(status):
+    if status != FLD_OK:
+        raise FldError(status, _nnlib().fldnn_last_error().decode())
 
 
 def _f32_host(arr, count):
@@ -513,19 +520,19 @@ def fldnn_create(N, H, W, training=False, workspace=None, stream=None):
                           workspace.numel(),
                           ctypes.c_void_p(stream.cuda_stream),
                           ctypes.byref(out))
-    _check(None, st)
+    _check_nn(st)
     return Net(out, (N, H, W), training, workspace, stream)
 
 
 def fldnn_set_params(net, flat):
     a, p = _f32_host(flat, net.count)
-    _check(None, _nnlib().fldnn_set_params(net.ptr, p, a.size))
+    _check_nn(_nnlib().fldnn_set_params(net.ptr, p, a.size))
 
 
 def fldnn_get_params(net):
     import numpy as np
     a = np.empty(net.count, dtype=np.float32)
-    _check(None, _nnlib().fldnn_get_params(
+    _check_nn(_nnlib().fldnn_get_params(
         net.ptr, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
     return a
 
@@ -533,7 +540,7 @@ def fldnn_get_params(net):
 def fldnn_forward(net, inputs, delta):
     import torch
     N, H, W = net.shape
-    _check(None, _nnlib().fldnn_forward(
+    _check_nn(_nnlib().fldnn_forward(
         net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
         _ptr(delta, "delta", N * H * W, torch.float32)))
 
@@ -545,7 +552,7 @@ def fldnn_gradients(net, inputs, targets):
     N, H, W = net.shape
     g = np.empty(net.count, dtype=np.float32)
     loss = ctypes.c_float()
-    _check(None, _nnlib().fldnn_gradients(
+    _check_nn(_nnlib().fldnn_gradients(
         net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
         _ptr(targets, "targets", N * H * W, torch.float32),
         ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
@@ -557,7 +564,7 @@ def fldnn_train_step(net, inputs, targets, lr, step, want_loss=False):
     import torch
     N, H, W = net.shape
     loss = ctypes.c_float()
-    _check(None, _nnlib().fldnn_train_step(
+    _check_nn(_nnlib().fldnn_train_step(
         net.ptr, _ptr(inputs, "inputs", N * H * W * 4, torch.float32),
         _ptr(targets, "targets", N * H * W, torch.float32), float(lr),
         int(step), ctypes.byref(loss) if want_loss else None))
@@ -571,7 +578,7 @@ FLDNN_LOSS_ENERGY = 1
 def fldnn_set_loss(net, kind):
     """kind: "mse" or "energy" (see include/fldnn.h)."""
     code = {"mse": FLDNN_LOSS_MSE, "energy": FLDNN_LOSS_ENERGY}[kind]
-    _check(None, _nnlib().fldnn_set_loss(net.ptr, code))
+    _check_nn(_nnlib().fldnn_set_loss(net.ptr, code))
 
 
 def fldnn_destroy(net):

@@ -389,3 +389,36 @@ def test_autotune_keeps_results():
     fld.fld_step(ctx, m.dt, dev(m.rho), dev(kap), dev(m.E), x1)
     assert rel_l2(host(x1), ref) <= 1e-10
     np.testing.assert_array_equal(host(x1), host(x0))
+
+
+@pytest.mark.parametrize("case", [((16, 12), (0, 1)), ((8, 8, 6), (1, 0, 1)),
+                                  ((40,), (1,))])
+def test_same_calls_on_both_sides(case):
+    """One parameter mapping drives the library (fld_setup / fld_step /
+    fld_exchange) and the oracle's calls of the same names."""
+    from paper_2503_02764_amd import fld
+    from oracle.fldref_api import fldref_exchange, fldref_setup, fldref_step
+    n, codes = case
+    nd = len(n)
+    bcs = tuple("periodic" if c == 0 else "neumann" for c in codes)
+    m = media.random_small_medium(7 + nd, n, bcs)
+    spec = dict(ndim=nd, n=tuple(n) + (1,) * (3 - nd), dx=m.dx,
+                bc_lo=tuple(codes) + (0,) * (3 - nd),
+                bc_hi=tuple(codes) + (0,) * (3 - nd), c=1.0, a_rad=1.0,
+                gamma=5.0 / 3.0, gas_const=1.0, limiter=0, face_mean=0,
+                rtol=1e-12)
+    announce(f"same calls on both sides n={n}")
+    ctx = fld.fld_setup(fld.fld_params_default(**spec))
+    ref_ctx = fldref_setup(spec)
+    rho, kap = dev(m.rho), dev(m.kappa)
+    E = dev(m.E)
+    out = dev(np.zeros_like(m.E))
+    fld.fld_step(ctx, m.dt, rho, kap, E, out)
+    x, _ = fldref_step(ref_ctx, m.dt, m.rho, m.kappa, m.E)
+    assert rel_l2(host(out).reshape(x.shape), x) <= 1e-10
+    e = dev(m.e)
+    fld.fld_exchange(ctx, m.dt, rho, kap, out, e)
+    En, en = fldref_exchange(ref_ctx, m.dt, m.rho, m.kappa, x, m.e)
+    S = x + m.e
+    assert np.abs(host(e).reshape(en.shape) - en).max() <= 1e-9 * S.max()
+    assert np.abs(host(out).reshape(En.shape) - En).max() <= 1e-9 * S.max()

@@ -169,3 +169,24 @@ def test_gaussian_pulse_analytic():
     _, R, lam = F.diffusion_coefficient(m.E, m.rho, m.kappa, prob)
     assert R.max() < 0.07
     assert np.all(np.abs(3 * lam - 1) <= R ** 2 / 6 + 1e-15)
+
+
+def test_fldref_api_drives_the_oracle_like_the_library():
+    """The oracle's three calls (host arrays, library parameter names and
+    codes) give what the oracle's functions give."""
+    import numpy as np
+    import media
+    from oracle import fldref as F
+    from oracle.fldref_api import fldref_exchange, fldref_setup, fldref_step
+    m = media.random_small_medium(5, (12, 10), ("periodic", "neumann"))
+    prob = F.problem_from_medium(m)
+    ctx = fldref_setup(dict(ndim=2, n=(12, 10, 1), dx=m.dx, bc_lo=(0, 1, 0),
+                            bc_hi=(0, 1, 0), c=1.0, a_rad=1.0, gamma=5 / 3,
+                            gas_const=1.0, limiter=0, face_mean=0))
+    x, st = fldref_step(ctx, m.dt, m.rho.ravel(), m.kappa.ravel(), m.E.ravel())
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt, prob, method="dense")
+    assert np.allclose(x, ref, rtol=1e-12, atol=0)
+    assert st["rel_res_final"] <= 1e-13
+    En, en = fldref_exchange(ctx, m.dt, m.rho, m.kappa, x, m.e)
+    En2, en2 = F.exchange(x, m.e, m.rho, m.kappa, m.dt, prob)
+    assert np.array_equal(En, En2) and np.array_equal(en, en2)
