@@ -25,22 +25,24 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
           "plain FP64 MG")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, or None.
+def measured_traffic(kernel, shape):
+    """HBM bytes per launch of `kernel` in tile shape `shape`, or None.
 
-    profiles/*.md carry a `traffic_record:` line written from two rocprofv3
-    --pmc runs (FETCH_SIZE, WRITE_SIZE, scaled by a plain-copy calibration)
-    together with the hash of the kernel source they were taken on; a
-    changed source makes the record stale and the figure null.
+    profiles/*.md carry `traffic_record:` lines, one per tile shape, written
+    from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, scaled by a
+    plain-copy calibration) together with the hash of the kernel source they
+    were taken on; a changed source makes the record stale and the figure
+    null, and so does a shape with no record.
     """
     import glob
     import hashlib
+    shape = shape.replace(" ", "_")
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("traffic_record:"):
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if kv.get("kernel") != kernel:
+            if kv.get("kernel") != kernel or kv.get("shape") != shape:
                 continue
             src = os.path.join(ROOT, kv["source"])
             sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -179,6 +181,12 @@ def main():
     from paper_2503_02764_amd.train_guess import forward_flops
     unet_flops = forward_flops(m.n[1], m.n[0])
     kt = base["kernel"]
+    if base["tile_shapes"]:
+        level0_down = base["tile_shapes"][0][0]
+    else:  # the library's fixed shape (0 unless FLD_TILE_VARIANT names one)
+        v = int(os.environ.get("FLD_TILE_VARIANT", "0"))
+        level0_down = fld.load().fld_tile_shape_name(
+            v if 0 <= v < 10 else 0).decode()
     avg_ms = kt["ms"] / max(kt["launches"], 1)
     bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -248,7 +256,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kt["kernel"]),
+            "traffic": measured_traffic(kt["kernel"], level0_down),
+            "tile_shape": level0_down,
             "avg_launch_us": avg_ms * 1e3,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": kt["launches"],
