@@ -186,7 +186,7 @@ def main():
     else:  # the library's fixed shape (0 unless FLD_TILE_VARIANT names one)
         v = int(os.environ.get("FLD_TILE_VARIANT", "0"))
         level0_down = fld.load().fld_tile_shape_name(
-            v if 0 <= v < 10 else 0).decode()
+            v if 0 <= v < 7 else 0).decode()
     avg_ms = kt["ms"] / max(kt["launches"], 1)
     bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0

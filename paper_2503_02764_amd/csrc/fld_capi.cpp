@@ -292,29 +292,22 @@ hipEvent_t next_event(fld_ctx* c) {
   return c->ev[c->ev_used++];
 }
 
-// Event pair around one launch of the timed kernel.
+// Event pair recorded by one launch of the timed kernel itself
+// (hipExtLaunchKernelGGL): the interval is the kernel's own execution.
 struct TimedLaunch {
-  fld_ctx* c;
-  hipEvent_t e1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   fld_status st = FLD_OK;
-  TimedLaunch(fld_ctx* cc, bool on, double bytes, const char* name) : c(cc) {
+  TimedLaunch(fld_ctx* c, bool on, double bytes, const char* name) {
     if (!on || !c->timing) return;
-    hipEvent_t e0 = next_event(c);
+    e0 = next_event(c);
     e1 = next_event(c);
     if (!e0 || !e1) {
       st = fail(c, FLD_ERR_DEVICE, "hipEventCreate failed");
-      e1 = nullptr;
+      e0 = e1 = nullptr;
       return;
     }
     c->ev_bytes.push_back(bytes);
     c->t_name = name;
-    if (hipEventRecord(e0, c->stream) != hipSuccess)
-      st = fail(c, FLD_ERR_DEVICE, "hipEventRecord failed");
-  }
-  fld_status close() {
-    if (e1 && hipEventRecord(e1, c->stream) != hipSuccess)
-      return fail(c, FLD_ERR_DEVICE, "hipEventRecord failed");
-    return st;
   }
 };
 
@@ -378,8 +371,7 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
                   sizeof(T) == 8 ? "k_tile2d<double,down>" : "k_tile2d<float,down>");
     FLD_TRY(t.st);
     HIP_TRY(c, launch_tile2d<T>(a, c->p.pre_smooth, true, c->tile_var[l][0],
-                                c->stream, &nb));
-    FLD_TRY(t.close());
+                                c->stream, &nb, t.e0, t.e1));
   } else {
     if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
     FLD_TRY(smooth_simple<T>(c, H, l, c->p.pre_smooth));
@@ -464,9 +456,12 @@ fld_status vcycle(fld_ctx* c, const Levels<T>& H, bool zero_first) {
   return FLD_OK;
 }
 
+// Launches after the stop flag was set return at once; the first `cycles`
+// timed launches of the solve are the ones that did the work.
 fld_status collect_timing(fld_ctx* c) {
   if (!c->timing) return FLD_OK;
-  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+  const size_t real = (size_t)std::max(0, c->host_ctrl->cycles);
+  for (size_t i = 0; i + 1 < c->ev_used && i / 2 < real; i += 2) {
     float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
     c->t_ms += ms;
@@ -642,6 +637,7 @@ Tile2DArgs<T> tile_job(fld_ctx* c, int l, bool down, bool zero_init,
   a.ctrl = c->ctrl;
   tile2d_grid(a.g, down ? c->p.pre_smooth : c->p.post_smooth, down, variant,
               &a.tiles_x, &a.tiles_y);
+  a.vec = tile2d_vec_ok(a);
   return a;
 }
 

@@ -21,22 +21,30 @@ struct Tile2DArgs {
   double* partials;   // down on the finest level: per-tile sum of r^2
   int zero_init;      // x starts at zero and is not read
   int tiles_x, tiles_y;  // set by the launcher
+  int vec;            // x, xo, b, ax, ay 16-byte aligned and n[0] even
+                      // (tile2d_vec_ok; set by the launcher)
   const Control* ctrl;
 };
 
 // Tile shapes available to the launchers (see fld_tile2d.hip); the batched
-// launcher takes the first kTileVariantsBatch.
-constexpr int kTileVariants = 10;
+// launcher takes the same shapes.
+constexpr int kTileVariants = 7;
 constexpr int kTileVariantsBatch = 7;
 const char* tile2d_variant_name(int variant);
 
 // Launch the down (pre-smoothing + residual + restriction) or up
 // (prolongation + post-smoothing) kernel with nu red-black sweeps
 // (nu in 1..3) and tile shape `variant`.  *nblocks receives the number of
-// tiles (one partial sum each on the finest down pass).
+// tiles (one partial sum each on the finest down pass).  Given ev0 and ev1,
+// the launch records them around the kernel's own execution.
 template <typename T>
 hipError_t launch_tile2d(const Tile2DArgs<T>& a, int nu, bool down,
-                         int variant, hipStream_t s, int* nblocks);
+                         int variant, hipStream_t s, int* nblocks,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// 1 when the 16-byte load path may be used for these arguments.
+template <typename T>
+int tile2d_vec_ok(const Tile2DArgs<T>& a);
 
 // Number of tiles (blocks) the launcher will use.
 int tile2d_blocks(const Geom& g, int nu, bool down, int variant);
