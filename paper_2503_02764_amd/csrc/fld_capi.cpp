@@ -590,6 +590,7 @@ struct BatchState {
   std::vector<Phase> coarsen, down[2], up;
   Phase tail[2];
   size_t tail_lds = 0;
+  bool tail2d[2] = {false, false};  // every grid's tail fits the 2D register tail
   int maxL = 0, maxl0 = 0;
   bool graph_on = false;
   hipGraph_t graph = nullptr;
@@ -756,6 +757,9 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
     }
     add_phase(im, B->tail[v], tails, ones);
     B->tail_lds = lds;
+    bool t2 = true;
+    for (int g = 0; g < ng; ++g) t2 = t2 && tail2d_ok(tails[g]);
+    B->tail2d[v] = t2;
   }
   B->up.assign(B->maxl0, Phase());
   for (int l = 0; l < B->maxl0; ++l) {
@@ -798,8 +802,12 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
                                         tab_ptr<JobFinalize>(B, B->fin_c),
                                         B->fin_c.ng, s));
   }
-  HIP_TRY(bc, launch_tail_lds_batch<T>(tab_ptr<TailArgs<T>>(B, B->tail[var]),
-                                       B->tail[var].ng, 2, B->tail_lds, s));
+  if (B->tail2d[var])
+    HIP_TRY(bc, launch_tail2d_batch<T>(tab_ptr<TailArgs<T>>(B, B->tail[var]),
+                                       B->tail[var].ng, s));
+  else
+    HIP_TRY(bc, launch_tail_lds_batch<T>(tab_ptr<TailArgs<T>>(B, B->tail[var]),
+                                         B->tail[var].ng, 2, B->tail_lds, s));
   for (int l = B->maxl0 - 1; l >= 0; --l) {
     const Phase& ph = B->up[l];
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),

@@ -119,6 +119,14 @@ hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
 // LDS variant (fld_tail.hip); *used = false when the levels do not fit.
 template <typename T>
 hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used);
+// Two-dimensional register tail (fld_tail2d.hip) for sub-V-cycles whose
+// levels fit it (tail2d_ok); launched by launch_tail_lds when they do.
+template <typename T>
+bool tail2d_ok(const TailArgs<T>& a);
+template <typename T>
+hipError_t launch_tail2d(const TailArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_tail2d_batch(const TailArgs<T>* tab, int ng, hipStream_t s);
 // LDS bytes the LDS tail needs (0 when the levels do not fit).
 template <typename T>
 size_t tail_lds_bytes(const TailArgs<T>& a);

@@ -413,6 +413,10 @@ size_t tail_lds_bytes(const TailArgs<T>& a) {
 
 template <typename T>
 hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used) {
+  if (tail2d_ok(a)) {
+    *used = true;
+    return launch_tail2d(a, s);
+  }
   const size_t lds = tail_lds_bytes(a);
   *used = lds > 0 && lds <= 62 * 1024;
   if (!*used) return hipSuccess;

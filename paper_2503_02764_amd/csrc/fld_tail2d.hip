@@ -1,0 +1,503 @@
+// Two-dimensional multigrid tail with every cell's Gauss-Seidel weights in
+// registers (gfx950).
+//
+// One block of 256 threads runs one sub-V-cycle over the tail levels (at
+// most 1024 cells on the first; each later level is a quarter of the one
+// before).  Levels come in three kinds:
+//   wide   (257..1024 cells): thread t owns the 2x2 cell block t, so two of
+//          every cell's four neighbours, the 2x2 restriction and the
+//          injection of the coarse correction's own term are in registers;
+//   narrow (65..256 cells): thread t owns cell t;
+//   tiny   (<= 64 cells): wave 0 alone, lane t owns cell t; its phases are
+//          ordered by LDS fences instead of block barriers.
+// The sequence is therefore [wide] [narrow] tiny+, and the coarsest level
+// is tiny.  Weights and the LDS offsets of the neighbours are computed once
+// per call from the face coefficients; a red-black update is then
+//   x = b/d + sum_f (alpha_f/d) x_f,   d = 1 + sum_f alpha_f,
+// with the rounding of the tiled kernels, and the residual is
+// d (x_update - x).  Only the iterates (and a residual scratch for the
+// restriction onto tiny levels) live in LDS.
+//
+// The multigrid itself is that of the other tail kernels: pre-smoothing,
+// residual restricted by the mean of the 2x2 children, coarse correction
+// from zero, coarsest red-black sweeps until the residual drops by 1e-3
+// (tested every 2 sweeps, at most 4000), cell-centred bilinear prolongation
+// (weights 9/16, 3/16, 3/16, 1/16), post-smoothing.
+#include "fld_internal.h"
+
+namespace fld {
+
+namespace {
+
+constexpr int NT2 = 256;
+constexpr int kTinyMax = 3;
+constexpr int kWideMax = 1024, kNarrowMax = 256, kTinyCells = 64;
+// LDS layout (elements of T)
+constexpr int kSW = 0;                        // wide iterate
+constexpr int kSN = kSW + kWideMax;           // narrow iterate
+constexpr int kST = kSN + kNarrowMax;         // tiny iterates, 64 each
+constexpr int kSR = kST + kTinyMax * kTinyCells;  // residual scratch
+constexpr int kSTotal = kSR + kNarrowMax;
+
+enum Kind { kWide = 0, kNarrow = 1, kTinyKind = 2 };
+
+__host__ __device__ inline int kind_of(int64_t n) {
+  return n > kNarrowMax ? kWide : (n > kTinyCells ? kNarrow : kTinyKind);
+}
+
+template <typename T>
+__device__ __forceinline__ T gs_val(T bp, T wl, T xl, T wr, T xr, T wd, T xd,
+                                    T wu, T xu) {
+  return fma(wu, xu, fma(wd, xd, fma(wr, xr, fma(wl, xl, bp))));
+}
+
+template <typename T>
+__device__ __forceinline__ T bilin(T e0, T e1, T e2, T e3) {
+  return fma(T(0.0625), e3,
+             fma(T(0.1875), e2, fma(T(0.1875), e1, T(0.5625) * e0)));
+}
+
+// Weights of one cell and the LDS offsets of its neighbours (the cell's own
+// offset behind a Neumann wall, where the weight is zero).
+template <typename T>
+struct CellW {
+  T wl, wr, wd, wu, inv, dn;
+  int ol, orr, od, ou;
+};
+
+template <typename T>
+__device__ __forceinline__ CellW<T> cell_weights(const LevelView<T>& L, int i,
+                                                 int j, int base) {
+  const int nx = L.g.n[0], ny = L.g.n[1];
+  const int px = L.g.per[0], py = L.g.per[1];
+  const int idx = j * nx + i;
+  const bool hl = i > 0 || px, hd = j > 0 || py;
+  const bool hr = i < nx - 1 || px, hu = j < ny - 1 || py;
+  const int il = i > 0 ? idx - 1 : idx + nx - 1;
+  const int id = j > 0 ? idx - nx : idx + (ny - 1) * nx;
+  const int ir = i < nx - 1 ? idx + 1 : idx - (nx - 1);
+  const int iu = j < ny - 1 ? idx + nx : idx - (ny - 1) * nx;
+  const T al = hl ? L.a[0][il] : T(0);
+  const T ad = hd ? L.a[1][id] : T(0);
+  const T ar = L.a[0][idx];  // zero on a Neumann wall face
+  const T au = L.a[1][idx];
+  const T d = T(1) + al + ar + ad + au;
+  const T inv = T(1) / d;
+  CellW<T> c;
+  c.wl = al * inv;
+  c.wr = ar * inv;
+  c.wd = ad * inv;
+  c.wu = au * inv;
+  c.inv = inv;
+  c.dn = d;
+  c.ol = base + (hl ? il : idx);
+  c.orr = base + (hr ? ir : idx);
+  c.od = base + (hd ? id : idx);
+  c.ou = base + (hu ? iu : idx);
+  return c;
+}
+
+// LDS writes of this wave complete before its later reads (tiny levels).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Second coarse index of a fine cell along one dimension (bilinear
+// prolongation): the nearer neighbour of its parent, wrapped or clamped.
+__device__ __forceinline__ int second_parent(int f, int nc, int per) {
+  const int p = f >> 1;
+  int o = (f & 1) ? p + 1 : p - 1;
+  if (o < 0) o = per ? nc - 1 : 0;
+  if (o >= nc) o = per ? 0 : nc - 1;
+  return o;
+}
+
+}  // namespace
+
+// Host check: the tail levels of `a` fit this kernel.
+template <typename T>
+bool tail2d_ok(const TailArgs<T>& a) {
+  if (a.whole) return false;
+  const int nt = a.L - a.l0;
+  if (nt < 2) return false;
+  int ntiny = 0;
+  for (int j = 0; j < nt; ++j) {
+    const Geom& g = a.lv[a.l0 + j].g;
+    if (g.ndim != 2) return false;
+    const int k = kind_of(g.N);
+    if (j == 0 && g.N > kWideMax) return false;
+    if (j > 0) {
+      const int kp = kind_of(a.lv[a.l0 + j - 1].g.N);
+      // wide -> narrow -> tiny...: each level a quarter of the one before
+      if (g.N * 4 != a.lv[a.l0 + j - 1].g.N) return false;
+      if (kp == kWide && k != kNarrow) return false;
+      if (kp != kWide && k != kTinyKind) return false;
+    }
+    if (k == kWide && (g.n[0] % 2 || g.n[1] % 2)) return false;
+    if (k == kTinyKind) ++ntiny;
+  }
+  if (kind_of(a.lv[a.L - 1].g.N) != kTinyKind) return false;
+  return ntiny <= kTinyMax;
+}
+
+template <typename T>
+__device__ __forceinline__ void tail2d_body(const TailArgs<T>& A) {
+  __shared__ T S[kSTotal];
+  if (A.ctrl->done != kRunning) return;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const bool wave0 = t < 64;
+  const int l0 = A.l0, nt = A.L - l0;
+  const int k0 = kind_of(A.lv[l0].g.N);
+  const bool has_wide = k0 == kWide;
+  const bool has_narrow = k0 != kTinyKind;
+  const int jn = has_wide ? 1 : 0;        // narrow level index
+  const int jt0 = has_narrow ? jn + 1 : 0;  // first tiny level
+  const int ntiny = nt - jt0;
+
+  // ---- set-up: weights of every owned cell, starting iterate and rhs ----
+  CellW<T> cw[2][2];
+  T xw[2][2], bw[2][2];
+  bool own_w = false;
+  int bi = 0, bj = 0;
+  if (has_wide) {
+    const LevelView<T>& L = A.lv[l0];
+    const int hx = L.g.n[0] / 2;
+    own_w = t < (int)L.g.N / 4;
+    bi = own_w ? t % hx : 0;
+    bj = own_w ? t / hx : 0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = 2 * bi + u, j = 2 * bj + v;
+        const int idx = j * L.g.n[0] + i;
+        cw[v][u] = cell_weights(L, i, j, kSW);
+        xw[v][u] = (A.zero || !own_w) ? T(0) : L.x[idx];
+        bw[v][u] = own_w ? L.b[idx] : T(0);
+      }
+  }
+  CellW<T> cn{};
+  T xn = T(0), bn = T(0);
+  bool own_n = false;
+  int ni = 0, nj = 0;
+  if (has_narrow) {
+    const LevelView<T>& L = A.lv[l0 + jn];
+    own_n = t < (int)L.g.N;
+    ni = own_n ? t % L.g.n[0] : 0;
+    nj = own_n ? t / L.g.n[0] : 0;
+    cn = cell_weights(L, ni, nj, kSN);
+    if (!has_wide && own_n) {
+      xn = A.zero ? T(0) : L.x[t];
+      bn = L.b[t];
+    }
+  }
+  CellW<T> ct[kTinyMax];
+  T bt[kTinyMax];
+  bool own_t[kTinyMax];
+  int ti[kTinyMax], tj[kTinyMax];
+  T xt0 = T(0);
+#pragma unroll
+  for (int q = 0; q < kTinyMax; ++q) {
+    own_t[q] = false;
+    ti[q] = tj[q] = 0;
+    bt[q] = T(0);
+    ct[q] = CellW<T>{};
+    if (wave0 && q < ntiny) {
+      const LevelView<T>& L = A.lv[l0 + jt0 + q];
+      own_t[q] = lane < (int)L.g.N;
+      ti[q] = own_t[q] ? lane % L.g.n[0] : 0;
+      tj[q] = own_t[q] ? lane / L.g.n[0] : 0;
+      ct[q] = cell_weights(L, ti[q], tj[q], kST + q * kTinyCells);
+      if (q == 0 && jt0 == 0 && own_t[0]) {
+        xt0 = A.zero ? T(0) : L.x[lane];
+        bt[0] = L.b[lane];
+      }
+    }
+  }
+  if (has_wide) {
+    const int nx = A.lv[l0].g.n[0];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (own_w) S[kSW + (2 * bj + v) * nx + 2 * bi + u] = xw[v][u];
+  } else if (has_narrow) {
+    if (own_n) S[kSN + t] = xn;
+  } else if (wave0 && own_t[0]) {
+    S[kST + lane] = xt0;
+  }
+  __syncthreads();
+
+  // ---- wide level: pre-smoothing, residual, restriction onto narrow ----
+  T bpw[2][2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) bpw[v][u] = bw[v][u] * cw[v][u].inv;
+  const int wnx = has_wide ? A.lv[l0].g.n[0] : 0;
+  auto wide_pass = [&](int c) {
+    if (own_w) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (((u + v) & 1) != c) continue;
+          const CellW<T>& w = cw[v][u];
+          const T xl = u ? xw[v][0] : S[w.ol];
+          const T xr = u ? S[w.orr] : xw[v][1];
+          const T xd = v ? xw[0][u] : S[w.od];
+          const T xu = v ? S[w.ou] : xw[1][u];
+          xw[v][u] = gs_val(bpw[v][u], w.wl, xl, w.wr, xr, w.wd, xd, w.wu, xu);
+          S[kSW + (2 * bj + v) * wnx + 2 * bi + u] = xw[v][u];
+        }
+    }
+    __syncthreads();
+  };
+  if (has_wide) {
+    for (int s = 0; s < A.pre; ++s) {
+      wide_pass(0);
+      wide_pass(1);
+    }
+    // residual of the 2x2 block; its mean is the narrow cell t's rhs
+    if (own_w) {
+      T r[2][2];
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const CellW<T>& w = cw[v][u];
+          const T xl = u ? xw[v][0] : S[w.ol];
+          const T xr = u ? S[w.orr] : xw[v][1];
+          const T xd = v ? xw[0][u] : S[w.od];
+          const T xu = v ? S[w.ou] : xw[1][u];
+          r[v][u] = w.dn * (gs_val(bpw[v][u], w.wl, xl, w.wr, xr, w.wd, xd,
+                                   w.wu, xu) -
+                            xw[v][u]);
+        }
+      bn = T(0.25) * ((r[0][0] + r[0][1]) + (r[1][0] + r[1][1]));
+    }
+    xn = T(0);
+    if (own_n) S[kSN + t] = T(0);
+    __syncthreads();
+  }
+
+  // ---- narrow level ----
+  const T bpn = bn * cn.inv;
+  const int ncolor = (ni + nj) & 1;
+  auto narrow_pass = [&](int c) {
+    if (own_n && ncolor == c) {
+      xn = gs_val(bpn, cn.wl, S[cn.ol], cn.wr, S[cn.orr], cn.wd, S[cn.od],
+                  cn.wu, S[cn.ou]);
+      S[kSN + t] = xn;
+    }
+    __syncthreads();
+  };
+  if (has_narrow) {
+    for (int s = 0; s < A.pre; ++s) {
+      narrow_pass(0);
+      narrow_pass(1);
+    }
+    if (own_n)
+      S[kSR + t] = cn.dn * (gs_val(bpn, cn.wl, S[cn.ol], cn.wr, S[cn.orr],
+                                   cn.wd, S[cn.od], cn.wu, S[cn.ou]) -
+                            xn);
+    __syncthreads();
+  }
+
+  // ---- tiny levels: wave 0 alone ----
+  if (wave0) {
+    T xt[kTinyMax], bpt[kTinyMax];
+    xt[0] = xt0;
+#pragma unroll
+    for (int q = 0; q < kTinyMax; ++q) {
+      if (q >= ntiny) break;
+      const int base = kST + q * kTinyCells;
+      if (q > 0 || jt0 > 0) {
+        // rhs: mean of the four children's residuals (scratch), x = 0
+        if (own_t[q]) {
+          const int fnx = A.lv[l0 + jt0 + q - 1].g.n[0];
+          const int f0 = 2 * tj[q] * fnx + 2 * ti[q];
+          const T r00 = S[kSR + f0], r01 = S[kSR + f0 + 1];
+          const T r10 = S[kSR + f0 + fnx], r11 = S[kSR + f0 + fnx + 1];
+          bt[q] = T(0.25) * ((r00 + r01) + (r10 + r11));
+          S[base + lane] = T(0);
+        }
+        xt[q] = T(0);
+      }
+      bpt[q] = bt[q] * ct[q].inv;
+      wave_lds_sync();
+      const int color = (ti[q] + tj[q]) & 1;
+      const CellW<T>& w = ct[q];
+      const bool last = q == ntiny - 1;
+      auto tiny_sweeps = [&](int sweeps) {
+        for (int s = 0; s < sweeps; ++s)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (own_t[q] && color == c) {
+              xt[q] = gs_val(bpt[q], w.wl, S[w.ol], w.wr, S[w.orr], w.wd,
+                             S[w.od], w.wu, S[w.ou]);
+              S[base + lane] = xt[q];
+            }
+            wave_lds_sync();
+          }
+      };
+      auto tiny_r2 = [&]() {
+        double r2 = 0.0;
+        if (own_t[q]) {
+          const double r = (double)(w.dn * (gs_val(bpt[q], w.wl, S[w.ol], w.wr,
+                                                   S[w.orr], w.wd, S[w.od],
+                                                   w.wu, S[w.ou]) -
+                                            xt[q]));
+          r2 = r * r;
+        }
+        return wave_sum(r2);
+      };
+      if (!last) {
+        tiny_sweeps(A.pre);
+        if (own_t[q])
+          S[kSR + lane] = w.dn * (gs_val(bpt[q], w.wl, S[w.ol], w.wr, S[w.orr],
+                                         w.wd, S[w.od], w.wu, S[w.ou]) -
+                                  xt[q]);
+        wave_lds_sync();
+      } else {
+        // coarsest: sweeps from zero until the residual dropped by 1e-3
+        const double b = own_t[q] ? (double)bt[q] : 0.0;
+        const double r0 = wave_sum(b * b);
+        tiny_sweeps(2);
+        if (tiny_r2() > 1e-6 * r0) {  // squared norms
+          for (int it = 0; it < 4000; it += 2) {
+            tiny_sweeps(2);
+            if (!(tiny_r2() > 1e-6 * r0)) break;
+          }
+        }
+      }
+    }
+    // up through the tiny levels
+#pragma unroll
+    for (int q = kTinyMax - 2; q >= 0; --q) {
+      if (q + 1 >= ntiny) continue;
+      const LevelView<T>& C = A.lv[l0 + jt0 + q + 1];
+      const int cbase = kST + (q + 1) * kTinyCells;
+      const int base = kST + q * kTinyCells;
+      if (own_t[q]) {
+        const int cnx = C.g.n[0], cny = C.g.n[1];
+        const int I = ti[q] >> 1, J = tj[q] >> 1;
+        const int I2 = second_parent(ti[q], cnx, C.g.per[0]);
+        const int J2 = second_parent(tj[q], cny, C.g.per[1]);
+        xt[q] += bilin(S[cbase + J * cnx + I], S[cbase + J * cnx + I2],
+                       S[cbase + J2 * cnx + I], S[cbase + J2 * cnx + I2]);
+        S[base + lane] = xt[q];
+      }
+      wave_lds_sync();
+      const int color = (ti[q] + tj[q]) & 1;
+      const CellW<T>& w = ct[q];
+      for (int s = 0; s < A.post; ++s)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (own_t[q] && color == c) {
+            xt[q] = gs_val(bpt[q], w.wl, S[w.ol], w.wr, S[w.orr], w.wd,
+                           S[w.od], w.wu, S[w.ou]);
+            S[base + lane] = xt[q];
+          }
+          wave_lds_sync();
+        }
+    }
+    if (jt0 == 0 && own_t[0]) A.lv[l0].x[lane] = xt[0];
+  }
+  __syncthreads();
+
+  // ---- narrow level: correction from the first tiny level, post-smoothing
+  if (has_narrow) {
+    if (own_n) {
+      const LevelView<T>& C = A.lv[l0 + jt0];
+      const int cnx = C.g.n[0], cny = C.g.n[1];
+      const int I = ni >> 1, J = nj >> 1;
+      const int I2 = second_parent(ni, cnx, C.g.per[0]);
+      const int J2 = second_parent(nj, cny, C.g.per[1]);
+      xn += bilin(S[kST + J * cnx + I], S[kST + J * cnx + I2],
+                  S[kST + J2 * cnx + I], S[kST + J2 * cnx + I2]);
+      S[kSN + t] = xn;
+    }
+    __syncthreads();
+    for (int s = 0; s < A.post; ++s) {
+      narrow_pass(0);
+      narrow_pass(1);
+    }
+    if (!has_wide && own_n) A.lv[l0].x[t] = xn;
+  }
+
+  // ---- wide level: correction from the narrow level, post-smoothing ----
+  if (has_wide) {
+    if (own_w) {
+      const LevelView<T>& C = A.lv[l0 + 1];
+      const int cnx = C.g.n[0], cny = C.g.n[1];
+      const T e = xn;  // the parent (bi, bj) is this thread's narrow cell
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int I2 = second_parent(2 * bi + u, cnx, C.g.per[0]);
+          const int J2 = second_parent(2 * bj + v, cny, C.g.per[1]);
+          xw[v][u] += bilin(e, S[kSN + bj * cnx + I2], S[kSN + J2 * cnx + bi],
+                            S[kSN + J2 * cnx + I2]);
+          S[kSW + (2 * bj + v) * wnx + 2 * bi + u] = xw[v][u];
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < A.post; ++s) {
+      wide_pass(0);
+      wide_pass(1);
+    }
+    if (own_w) {
+      const LevelView<T>& L = A.lv[l0];
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          L.x[(2 * bj + v) * wnx + 2 * bi + u] = xw[v][u];
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT2) k_tail2d(TailArgs<T> A) {
+  tail2d_body<T>(A);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT2)
+    k_tail2d_batch(const TailArgs<T>* __restrict__ tab) {
+  tail2d_body<T>(tab[blockIdx.x]);
+}
+
+template <typename T>
+hipError_t launch_tail2d(const TailArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail2d<T>), dim3(1), dim3(NT2), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail2d_batch(const TailArgs<T>* tab, int ng, hipStream_t s) {
+  if (ng == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_tail2d_batch<T>), dim3(ng), dim3(NT2), 0, s, tab);
+  return hipGetLastError();
+}
+
+template bool tail2d_ok<double>(const TailArgs<double>&);
+template bool tail2d_ok<float>(const TailArgs<float>&);
+template hipError_t launch_tail2d<double>(const TailArgs<double>&, hipStream_t);
+template hipError_t launch_tail2d<float>(const TailArgs<float>&, hipStream_t);
+template hipError_t launch_tail2d_batch<double>(const TailArgs<double>*, int,
+                                                hipStream_t);
+template hipError_t launch_tail2d_batch<float>(const TailArgs<float>*, int,
+                                               hipStream_t);
+
+}  // namespace fld
