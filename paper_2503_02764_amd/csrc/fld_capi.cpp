@@ -75,6 +75,7 @@ struct fld_ctx {
   std::string err;
   // timing of the dominant kernel (finest-level down pass)
   bool timing = false;
+  bool init_fused = false;  // this step's coefficient stage formed the initial residual
   double t_ms = 0.0;
   int64_t t_launches = 0;
   double t_bytes = 0.0;
@@ -251,6 +252,8 @@ void make_plan(const fld_params* p, Plan* P) {
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   int64_t nparts = blocks_for(P->g[0].N);
+  if (coef2d_ok(P->g[0]))  // |b|^2 and |r0|^2 partials of the 2D stage
+    nparts = std::max<int64_t>(nparts, 2 * (int64_t)coef2d_blocks(P->g[0]));
   if (p->ndim == 2)
     for (int nu = 1; nu <= 3; ++nu)
       for (int v = 0; v < kTileVariants; ++v) {
@@ -483,9 +486,12 @@ fld_status read_control(fld_ctx* c) {
 // FP64 V-cycles until the device stop flag is set.
 fld_status solve_fp64(fld_ctx* c) {
   int nb = 0;
-  HIP_TRY(c, launch_resid_norm<double>(view(c, c->h64, 0), c->partials, &nb,
-                                       c->ctrl, c->stream));
-  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl, c->stream));
+  if (!c->init_fused) {
+    HIP_TRY(c, launch_resid_norm<double>(view(c, c->h64, 0), c->partials, &nb,
+                                         c->ctrl, c->stream));
+    HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl,
+                               c->stream));
+  }
   if (c->fast && c->tail_l0 == 0) {
     // the whole problem fits one workgroup: one launch runs every cycle
     HIP_TRY(c, launch_tail<double>(tail_args<double>(c, c->h64, 0, true),
@@ -1117,10 +1123,22 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
   A.c = c->p.c;
   A.limiter = c->p.limiter;
   A.face_mean = c->p.face_mean;
-  HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
-                         copy_dst, c->partials, c->ctrl, c->stream));
-  HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, blocks_for(g0.N), c->ctrl,
+  // 2D grids: the LDS-tiled coefficient stage; with x0 = E^n in FP64 it also
+  // forms the initial residual, so the solve needs no separate first pass
+  c->init_fused = coef2d_ok(g0) && !c->mixed && c->p.guess == FLD_GUESS_PREV;
+  if (coef2d_ok(g0)) {
+    HIP_TRY(c, launch_coef2d(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
+                             copy_dst, c->partials, c->ctrl, c->init_fused,
                              c->stream));
+    HIP_TRY(c, launch_finalize(c->init_fused ? kFinCoef : kFinBnorm,
+                               c->partials, coef2d_blocks(g0), c->ctrl,
+                               c->stream));
+  } else {
+    HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
+                           copy_dst, c->partials, c->ctrl, c->stream));
+    HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, blocks_for(g0.N),
+                               c->ctrl, c->stream));
+  }
   for (int l = 0; l + 1 < c->L; ++l) {
     if (c->mixed) {
       const float* fa[3] = {c->h32.a[l][0], c->h32.a[l][1], c->h32.a[l][2]};

@@ -153,6 +153,21 @@ __device__ __forceinline__ void finalize_body(int mode,
                                               int count, Control* ctrl) {
   __shared__ double sh[kReduceBlock / 64];
   const int done = ctrl->done;
+  if (mode == kFinCoef) {
+    double v1 = 0.0, v2 = 0.0;
+    for (int i = threadIdx.x; i < count; i += kReduceBlock) {
+      v1 += partials[i];
+      v2 += partials[count + i];
+    }
+    const double s1 = block_sum<kReduceBlock>(v1, sh);
+    __syncthreads();
+    const double s2 = block_sum<kReduceBlock>(v2, sh);
+    if (threadIdx.x != 0) return;
+    finalize_update(kFinBnorm, s1, ctrl);
+    if (ctrl->done == kRunning) finalize_update(kFinInitial, s2, ctrl);
+    if (ctrl->mirror) *ctrl->mirror = *ctrl;
+    return;
+  }
   if (mode != kFinBnorm && done != kRunning) return;
   double v = 0.0;
   for (int i = threadIdx.x; i < count; i += kReduceBlock) v += partials[i];

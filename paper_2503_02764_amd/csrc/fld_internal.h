@@ -119,6 +119,16 @@ hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
 // LDS variant (fld_tail.hip); *used = false when the levels do not fit.
 template <typename T>
 hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used);
+// LDS-tiled coefficient stage of a 2D grid (fld_coef2d.hip), for grids of at
+// least 4 x 4 cells (coef2d_ok): k_coef's coefficients, and with `resid` the
+// initial residual of x0 = E^n as well (finalize with kFinCoef).
+bool coef2d_ok(const Geom& g);
+int coef2d_blocks(const Geom& g);
+hipError_t launch_coef2d(const CoefArgs& a, const double* E, const double* rho,
+                         const double* kappa, double* const a64[3],
+                         float* const a32[3], double* copy_dst,
+                         double* partials, Control* ctrl, bool resid,
+                         hipStream_t s);
 // Two-dimensional register tail (fld_tail2d.hip) for sub-V-cycles whose
 // levels fit it (tail2d_ok); launched by launch_tail_lds when they do.
 template <typename T>
@@ -157,7 +167,13 @@ constexpr int64_t kTailLdsCells = 1024;
 // finalize modes
 // kFinOuter: FP64 residual of a refinement iteration (first call also sets
 // the initial residual); counts outer iterations.
-enum FinalizeMode { kFinBnorm = 0, kFinInitial = 1, kFinCycle = 2, kFinOuter = 3 };
+enum FinalizeMode {
+  kFinBnorm = 0,
+  kFinInitial = 1,
+  kFinCycle = 2,
+  kFinOuter = 3,
+  kFinCoef = 4  // |b|^2 in partials[0, count), |b - A x0|^2 in [count, 2 count)
+};
 
 inline int blocks_for(int64_t n, int bs = kBlock) {
   return (int)((n + bs - 1) / bs);

@@ -65,11 +65,38 @@ struct CellW {
   int ol, orr, od, ou;
 };
 
+// Face coefficients around cell (i, j) of a level, as loaded: left, right,
+// down, up (the left and lower loads are clamped into the array and masked
+// later, behind a Neumann wall).
 template <typename T>
-__device__ __forceinline__ CellW<T> cell_weights(const LevelView<T>& L, int i,
-                                                 int j, int base) {
+struct CellA {
+  T al, ar, ad, au;
+  int i, j;
+};
+
+template <typename T>
+__device__ __forceinline__ CellA<T> cell_alpha(const LevelView<T>& L, int i,
+                                               int j) {
   const int nx = L.g.n[0], ny = L.g.n[1];
-  const int px = L.g.per[0], py = L.g.per[1];
+  const int idx = j * nx + i;
+  const int il = i > 0 ? idx - 1 : idx + nx - 1;
+  const int id = j > 0 ? idx - nx : idx + (ny - 1) * nx;
+  CellA<T> a;
+  a.al = L.a[0][il];
+  a.ad = L.a[1][id];
+  a.ar = L.a[0][idx];  // zero on a Neumann wall face
+  a.au = L.a[1][idx];
+  a.i = i;
+  a.j = j;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ CellW<T> cell_weights(const Geom& g, const CellA<T>& a,
+                                                 int base) {
+  const int nx = g.n[0], ny = g.n[1];
+  const int px = g.per[0], py = g.per[1];
+  const int i = a.i, j = a.j;
   const int idx = j * nx + i;
   const bool hl = i > 0 || px, hd = j > 0 || py;
   const bool hr = i < nx - 1 || px, hu = j < ny - 1 || py;
@@ -77,17 +104,15 @@ __device__ __forceinline__ CellW<T> cell_weights(const LevelView<T>& L, int i,
   const int id = j > 0 ? idx - nx : idx + (ny - 1) * nx;
   const int ir = i < nx - 1 ? idx + 1 : idx - (nx - 1);
   const int iu = j < ny - 1 ? idx + nx : idx - (ny - 1) * nx;
-  const T al = hl ? L.a[0][il] : T(0);
-  const T ad = hd ? L.a[1][id] : T(0);
-  const T ar = L.a[0][idx];  // zero on a Neumann wall face
-  const T au = L.a[1][idx];
-  const T d = T(1) + al + ar + ad + au;
+  const T al = hl ? a.al : T(0);
+  const T ad = hd ? a.ad : T(0);
+  const T d = T(1) + al + a.ar + ad + a.au;
   const T inv = T(1) / d;
   CellW<T> c;
   c.wl = al * inv;
-  c.wr = ar * inv;
+  c.wr = a.ar * inv;
   c.wd = ad * inv;
-  c.wu = au * inv;
+  c.wu = a.au * inv;
   c.inv = inv;
   c.dn = d;
   c.ol = base + (hl ? il : idx);
@@ -150,7 +175,10 @@ bool tail2d_ok(const TailArgs<T>& a) {
 template <typename T>
 __device__ __forceinline__ void tail2d_body(const TailArgs<T>& A) {
   __shared__ T S[kSTotal];
-  if (A.ctrl->done != kRunning) return;
+  // The stop flag and every set-up operand are loaded before the first is
+  // used (loads of absent levels read valid cells of the first level and
+  // are discarded), so the set-up costs one memory round trip.
+  const int done = A.ctrl->done;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const bool wave0 = t < 64;
@@ -162,76 +190,87 @@ __device__ __forceinline__ void tail2d_body(const TailArgs<T>& A) {
   const int jt0 = has_narrow ? jn + 1 : 0;  // first tiny level
   const int ntiny = nt - jt0;
 
-  // ---- set-up: weights of every owned cell, starting iterate and rhs ----
-  CellW<T> cw[2][2];
+  // ---- set-up loads ----
+  const LevelView<T>& Lw = A.lv[l0];
+  const int hx = Lw.g.n[0] / 2;
+  const bool own_w = has_wide && t < (int)Lw.g.N / 4;
+  const int bi = own_w ? t % hx : 0, bj = own_w ? t / hx : 0;
+  const int wnx = Lw.g.n[0];
+  CellA<T> aw[2][2];
   T xw[2][2], bw[2][2];
-  bool own_w = false;
-  int bi = 0, bj = 0;
-  if (has_wide) {
-    const LevelView<T>& L = A.lv[l0];
-    const int hx = L.g.n[0] / 2;
-    own_w = t < (int)L.g.N / 4;
-    bi = own_w ? t % hx : 0;
-    bj = own_w ? t / hx : 0;
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
+  for (int v = 0; v < 2; ++v)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int i = 2 * bi + u, j = 2 * bj + v;
-        const int idx = j * L.g.n[0] + i;
-        cw[v][u] = cell_weights(L, i, j, kSW);
-        xw[v][u] = (A.zero || !own_w) ? T(0) : L.x[idx];
-        bw[v][u] = own_w ? L.b[idx] : T(0);
-      }
-  }
-  CellW<T> cn{};
-  T xn = T(0), bn = T(0);
-  bool own_n = false;
-  int ni = 0, nj = 0;
-  if (has_narrow) {
-    const LevelView<T>& L = A.lv[l0 + jn];
-    own_n = t < (int)L.g.N;
-    ni = own_n ? t % L.g.n[0] : 0;
-    nj = own_n ? t / L.g.n[0] : 0;
-    cn = cell_weights(L, ni, nj, kSN);
-    if (!has_wide && own_n) {
-      xn = A.zero ? T(0) : L.x[t];
-      bn = L.b[t];
+    for (int u = 0; u < 2; ++u) {
+      const int i = min(2 * bi + u, Lw.g.n[0] - 1);
+      const int j = min(2 * bj + v, Lw.g.n[1] - 1);
+      aw[v][u] = cell_alpha(Lw, i, j);
+      xw[v][u] = Lw.x[j * wnx + i];
+      bw[v][u] = Lw.b[j * wnx + i];
     }
+  const LevelView<T>& Ln = A.lv[l0 + jn];
+  const bool own_n = has_narrow && t < (int)Ln.g.N;
+  const int ni = own_n ? t % Ln.g.n[0] : 0, nj = own_n ? t / Ln.g.n[0] : 0;
+  const CellA<T> an = cell_alpha(Ln, ni, nj);
+  T xn = Ln.x[nj * Ln.g.n[0] + ni];
+  T bn = Ln.b[nj * Ln.g.n[0] + ni];
+  CellA<T> at[kTinyMax];
+  bool own_t[kTinyMax];
+#pragma unroll
+  for (int q = 0; q < kTinyMax; ++q) {
+    const LevelView<T>& L = A.lv[l0 + min(jt0 + q, nt - 1)];
+    own_t[q] = wave0 && q < ntiny && lane < (int)L.g.N;
+    at[q] = cell_alpha(L, own_t[q] ? lane % L.g.n[0] : 0,
+                       own_t[q] ? lane / L.g.n[0] : 0);
+  }
+  const LevelView<T>& Lt = A.lv[l0 + jt0];
+  T xt0 = Lt.x[own_t[0] ? lane : 0];
+  T bt0 = Lt.b[own_t[0] ? lane : 0];
+  if (done != kRunning) return;
+
+  // ---- weights, starting iterates ----
+  CellW<T> cw[2][2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      cw[v][u] = cell_weights(Lw.g, aw[v][u], kSW);
+      if (A.zero || !own_w) xw[v][u] = T(0);
+      if (!own_w) bw[v][u] = T(0);
+    }
+  const CellW<T> cn = cell_weights(Ln.g, an, kSN);
+  if (has_wide || !own_n) {
+    xn = T(0);
+    bn = T(0);
+  } else if (A.zero) {
+    xn = T(0);
   }
   CellW<T> ct[kTinyMax];
   T bt[kTinyMax];
-  bool own_t[kTinyMax];
   int ti[kTinyMax], tj[kTinyMax];
-  T xt0 = T(0);
 #pragma unroll
   for (int q = 0; q < kTinyMax; ++q) {
-    own_t[q] = false;
-    ti[q] = tj[q] = 0;
+    const LevelView<T>& L = A.lv[l0 + min(jt0 + q, nt - 1)];
+    ct[q] = cell_weights(L.g, at[q], kST + q * kTinyCells);
+    ti[q] = at[q].i;
+    tj[q] = at[q].j;
     bt[q] = T(0);
-    ct[q] = CellW<T>{};
-    if (wave0 && q < ntiny) {
-      const LevelView<T>& L = A.lv[l0 + jt0 + q];
-      own_t[q] = lane < (int)L.g.N;
-      ti[q] = own_t[q] ? lane % L.g.n[0] : 0;
-      tj[q] = own_t[q] ? lane / L.g.n[0] : 0;
-      ct[q] = cell_weights(L, ti[q], tj[q], kST + q * kTinyCells);
-      if (q == 0 && jt0 == 0 && own_t[0]) {
-        xt0 = A.zero ? T(0) : L.x[lane];
-        bt[0] = L.b[lane];
-      }
-    }
+  }
+  if (jt0 == 0 && own_t[0]) {
+    bt[0] = bt0;
+    if (A.zero) xt0 = T(0);
+  } else {
+    xt0 = T(0);
   }
   if (has_wide) {
-    const int nx = A.lv[l0].g.n[0];
 #pragma unroll
     for (int v = 0; v < 2; ++v)
 #pragma unroll
       for (int u = 0; u < 2; ++u)
-        if (own_w) S[kSW + (2 * bj + v) * nx + 2 * bi + u] = xw[v][u];
+        if (own_w) S[kSW + (2 * bj + v) * wnx + 2 * bi + u] = xw[v][u];
   } else if (has_narrow) {
     if (own_n) S[kSN + t] = xn;
-  } else if (wave0 && own_t[0]) {
+  } else if (own_t[0]) {
     S[kST + lane] = xt0;
   }
   __syncthreads();
@@ -242,7 +281,6 @@ __device__ __forceinline__ void tail2d_body(const TailArgs<T>& A) {
   for (int v = 0; v < 2; ++v)
 #pragma unroll
     for (int u = 0; u < 2; ++u) bpw[v][u] = bw[v][u] * cw[v][u].inv;
-  const int wnx = has_wide ? A.lv[l0].g.n[0] : 0;
   auto wide_pass = [&](int c) {
     if (own_w) {
 #pragma unroll
