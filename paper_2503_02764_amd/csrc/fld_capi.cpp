@@ -76,6 +76,8 @@ struct fld_ctx {
   // timing of the dominant kernel (finest-level down pass)
   bool timing = false;
   bool init_fused = false;  // this step's coefficient stage formed the initial residual
+  int fin_cycle = -1;       // index of the FP64 V-cycle being enqueued
+  int pending_fin = 0;      // finest down partials awaiting their stop test
   double t_ms = 0.0;
   int64_t t_launches = 0;
   double t_bytes = 0.0;
@@ -366,6 +368,13 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
     a.partials = norm ? c->partials : nullptr;
     a.zero_init = zero_init;
     a.ctrl = c->ctrl;
+    if (sizeof(T) == 8 && l == 1 && c->pending_fin > 0) {
+      a.fin_partials = c->partials;
+      a.fin_count = c->pending_fin;
+      a.fin_cycle = c->fin_cycle;
+      a.fin_ctrl = c->ctrl;
+      c->pending_fin = 0;
+    }
     // x (unless zero), b, two face arrays read; x and the coarse rhs written
     const double w = sizeof(T);
     const double bytes = (double)c->geom[l].N *
@@ -382,8 +391,15 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
                                         norm ? c->partials : nullptr, &nb,
                                         c->ctrl, c->stream));
   }
-  if (norm)
-    HIP_TRY(c, launch_finalize(kFinCycle, c->partials, nb, c->ctrl, c->stream));
+  if (norm) {
+    // a tiled level 1 takes the stop test itself (its blocks reduce the
+    // partials), saving a launch per V-cycle
+    if (tile_path(c) && c->tail_l0 >= 2 && c->fin_cycle >= 0)
+      c->pending_fin = nb;
+    else
+      HIP_TRY(c, launch_finalize(kFinCycle, c->partials, nb, c->ctrl,
+                                 c->stream));
+  }
   return FLD_OK;
 }
 
@@ -502,8 +518,13 @@ fld_status solve_fp64(fld_ctx* c) {
   int batch = c->last_batch < 1 ? 1 : c->last_batch;
   for (;;) {
     if (batch > c->p.max_cycles - enqueued) batch = c->p.max_cycles - enqueued;
-    for (int k = 0; k < batch; ++k)
-      FLD_TRY(vcycle<double>(c, c->h64, false));
+    for (int k = 0; k < batch; ++k) {
+      c->fin_cycle = enqueued + k;
+      const fld_status st = vcycle<double>(c, c->h64, false);
+      c->fin_cycle = -1;
+      c->pending_fin = 0;
+      FLD_TRY(st);
+    }
     // a stop right after the finest down pass leaves the iterate in the
     // alternate buffer of the tiled path (the copy checks the device flag)
     if (tile_path(c))

@@ -49,6 +49,7 @@
 #include <hip/hip_ext.h>
 
 #include "fld_internal.h"
+#include "fld_device.h"
 #include "fld_tile2d.h"
 
 namespace fld {
@@ -119,7 +120,7 @@ __device__ __forceinline__ T gs_value(T bp, T wl, T xl, T wr, T xr, T wd,
 
 // Bilinear prolongation weights of the four nearest coarse cells.
 template <typename T>
-__device__ __forceinline__ T prolong_value(T e0, T e1, T e2, T e3) {
+__device__ __forceinline__ T bilinear4(T e0, T e1, T e2, T e3) {
   return fma(T(0.0625), e3, fma(T(0.1875), e2, fma(T(0.1875), e1, T(0.5625) * e0)));
 }
 
@@ -140,7 +141,29 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
   // parity; thread-row py sits at index py + 1, between two zero rows.
   __shared__ T xb[2][NPY + 2][2][PX];
   __shared__ double red[NT / 64 + 1];
+  __shared__ int stop_now;
   if (A.ctrl->done != kRunning) return;
+  if constexpr (DOWN) {
+    if (A.fin_count > 0) {
+      // stop test of the finest down pass, taken by every block of this
+      // launch from the same partial sums in the same order (so all reach
+      // the same decision); block 0 records it in the control block
+      double v = 0.0;
+      for (int i = threadIdx.x; i < A.fin_count; i += NT) v += A.fin_partials[i];
+      const double s = block_sum_t<double>(v, red, NT);
+      if (threadIdx.x == 0) {
+        const Control* C = A.ctrl;
+        const double r = sqrt(s / C->bnorm2);
+        stop_now = r <= C->rtol || A.fin_cycle + 1 >= C->max_cycles;
+        if (blockIdx.x == 0) {
+          finalize_update(kFinCycle, s, A.fin_ctrl);
+          if (A.fin_ctrl->mirror) *A.fin_ctrl->mirror = *A.fin_ctrl;
+        }
+      }
+      __syncthreads();
+      if (stop_now) return;
+    }
+  }
 
   const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
   const int gx0 = txi * TX - H, gy0 = tyi * TY - H;  // region origin (even)
@@ -234,8 +257,8 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
               n2 = e2;
             }
           }
-          cr[k][0] = prolong_value(ce0[k], p0, ce2[k], p2);
-          cr[k][1] = prolong_value(ce0[k], n0, ce2[k], n2);
+          cr[k][0] = bilinear4(ce0[k], p0, ce2[k], p2);
+          cr[k][1] = bilinear4(ce0[k], n0, ce2[k], n2);
         }
       }
     } else {
@@ -275,7 +298,7 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
             if (I2 >= ncx) I2 = perx ? 0 : ncx - 1;
             if (J2 < 0) J2 = pery ? ncy - 1 : 0;
             if (J2 >= ncy) J2 = pery ? 0 : ncy - 1;
-            cr[k][q] = prolong_value(A.ce[(int64_t)J * ncx + I],
+            cr[k][q] = bilinear4(A.ce[(int64_t)J * ncx + I],
                                      A.ce[(int64_t)J * ncx + I2],
                                      A.ce[(int64_t)J2 * ncx + I],
                                      A.ce[(int64_t)J2 * ncx + I2]);
