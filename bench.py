@@ -158,8 +158,10 @@ def main():
     weights = load_weights()
     base = run("fp64", args.steps, args.warmup)
     if args.headline_only:
+        kt = base["kernel"]
         print(json.dumps({"ms_per_step": base["ms_per_step"],
                           "vcycles_per_step": base["vcycles_per_step"],
+                          "finest_down_us": 1e3 * kt["ms"] / max(kt["launches"], 1),
                           "tile_shapes": base["tile_shapes"]}))
         return
     mixed = run("fp32_ir", args.steps, args.warmup)
