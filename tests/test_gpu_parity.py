@@ -181,6 +181,31 @@ def test_zero_guess_same_solution():
     assert rel_l2(x1, x0) <= 1e-10
 
 
+@pytest.mark.parametrize("n,bc", [((96, 80), ("periodic", "neumann")),
+                                  ((130, 70), ("neumann", "periodic"))])
+def test_initial_residual_of_previous_energy(n, bc):
+    """The coefficient stage of a 2D grid also forms |b - A E^n| / |b| for
+    the default guess (x0 = E^n): equal to the oracle's residual of E^n with
+    the oracle's coefficients, to rounding (each term alpha (E - E_f) loses
+    digits to the difference of neighbouring E, a few ulp of |E| / |E - E_f|
+    on these media, far inside the 1e-12 bar)."""
+    m = media.random_small_medium(17 + n[0], n, bc)
+    prob = F.problem_from_medium(m)
+    alphas = F.face_coefficients(m.E, m.rho, m.kappa, m.dt, prob)
+    ref = F.relative_residual(m.E, m.E, alphas, prob)
+    announce(f"initial residual n={n} bc={bc}")
+    from paper_2503_02764_amd import fld
+    ctx = fld.fld_setup(params_for(m, rtol=1e-10))
+    rho, kap = dev(m.rho), dev(m.kappa)
+    for aliased in (False, True):
+        E = dev(m.E)
+        out = E if aliased else dev(np.zeros_like(m.E))
+        _, stats = fld.fld_step(ctx, m.dt, rho, kap, E, out)
+        assert stats["rel_res_initial"] == pytest.approx(ref, rel=1e-12,
+                                                         abs=1e-15), aliased
+        assert stats["rel_res_final"] <= 1e-10
+
+
 def test_error_paths():
     from paper_2503_02764_amd import fld
     m = media.random_small_medium(4, (32, 32), ("neumann", "neumann"))
@@ -220,10 +245,14 @@ def test_c2_full_size_bench_configuration():
     prob = F.problem_from_medium(m)
     kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
     announce("c2 full size 1024^2")
-    st = Stepper(params_for(m, rtol=1e-8), opacity=m.opacity)
+    import bench
+    from paper_2503_02764_amd import fld
+    # the cycle and the autotuned tile shapes the bench runs with
+    st = Stepper(params_for(m, rtol=1e-8, pre_smooth=bench.PRE,
+                            post_smooth=bench.POST), opacity=m.opacity)
+    fld.fld_autotune(st.ctx)
     rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
     kap_d = dev(np.zeros_like(m.E))
-    from paper_2503_02764_amd import fld
     o = m.opacity
     fld.fld_opacity_powerlaw(st.ctx, rho, e, o["k0"], o["a"], o["b"],
                              o["kmin"], o["kmax"], kap_d)
