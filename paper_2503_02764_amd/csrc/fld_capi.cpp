@@ -357,6 +357,7 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
   if (tile_path(c)) {
     Tile2DArgs<T> a{};
     a.g = c->geom[l];
+    a.spec = l == 0;
     a.x = H.x[l];
     a.xo = H.alt[l];
     a.b = H.b[l];
@@ -1292,6 +1293,7 @@ fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2],
     for (int dir = 0; dir < 2 && st == FLD_OK; ++dir) {
       Tile2DArgs<T> a{};
       a.g = c->geom[l];
+      a.spec = l == 0 && dir == 0;
       T* xl = l == 0 ? x0 : H.x[l];
       a.x = dir == 0 ? xl : H.alt[l];
       a.xo = dir == 0 ? H.alt[l] : xl;

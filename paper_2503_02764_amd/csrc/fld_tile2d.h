@@ -23,6 +23,7 @@ struct Tile2DArgs {
   int tiles_x, tiles_y;  // set by the launcher
   int vec;            // x, xo, b, ax, ay 16-byte aligned and n[0] even
                       // (tile2d_vec_ok; set by the launcher)
+  int spec;           // load the operands before testing the stop flag
   // down on level 1, FP64: the finest down pass's partial sums of r^2, to be
   // reduced here for its stop test (instead of a separate finalize launch);
   // fin_cycle is the index of the V-cycle within the solve, fin_ctrl the

@@ -142,7 +142,12 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
   __shared__ T xb[2][NPY + 2][2][PX];
   __shared__ double red[NT / 64 + 1];
   __shared__ int stop_now;
-  if (A.ctrl->done != kRunning) return;
+  // With A.spec the operands are loaded before the stop flag is tested, so
+  // that the flag's memory round trip overlaps theirs (used on the finest
+  // down pass, which rarely runs after convergence: the stop test follows
+  // it; a launch past the stop then reads its operands for nothing).
+  const int done = A.ctrl->done;
+  if (!A.spec && done != kRunning) return;
   if constexpr (DOWN) {
     if (A.fin_count > 0) {
       // stop test of the finest down pass, taken by every block of this
@@ -325,6 +330,7 @@ __device__ __forceinline__ void tile2d_body(const Tile2DArgs<T>& A,
         if constexpr (DOWN) dn[k][q] = d;
       }
   }
+  if (done != kRunning) return;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     xb[0][py + 1][q][px] = x[0][q];
