@@ -254,6 +254,8 @@ void make_plan(const fld_params* p, Plan* P) {
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   int64_t nparts = blocks_for(P->g[0].N);
+  if (p->ndim == 3)  // one partial per block of the 3D launch grid
+    nparts = std::max<int64_t>(nparts, blocks3(P->g[0]));
   if (coef2d_ok(P->g[0]))  // |b|^2 and |r0|^2 partials of the 2D stage
     nparts = std::max<int64_t>(nparts, 2 * (int64_t)coef2d_blocks(P->g[0]));
   if (p->ndim == 2)

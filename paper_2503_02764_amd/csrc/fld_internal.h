@@ -119,6 +119,9 @@ hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
 // LDS variant (fld_tail.hip); *used = false when the levels do not fit.
 template <typename T>
 hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used);
+// Blocks of the 3D launch grid of the one-pass kernels over level g (their
+// partial sums: one per block).
+int64_t blocks3(const Geom& g);
 // LDS-tiled coefficient stage of a 2D grid (fld_coef2d.hip), for grids of at
 // least 4 x 4 cells (coef2d_ok): k_coef's coefficients, and with `resid` the
 // initial residual of x0 = E^n as well (finalize with kFinCoef).

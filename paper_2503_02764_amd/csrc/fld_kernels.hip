@@ -209,9 +209,61 @@ __global__ void __launch_bounds__(kBlock)
   resid_to32_body(L, r32, partials, ctrl, blockIdx.x);
 }
 
+// 3D levels: a block of kBlock threads covers a run of k3X cells along x in
+// k3Y consecutive rows of one z-plane (thread t: x offset t % k3X, row
+// t / k3X), so the cell coordinates come from the block and thread indices
+// without divisions; a colour pass covers only the cells of its colour.
+constexpr int k3X = 64, k3Y = kBlock / k3X;
+
+dim3 grid3(int64_t xcells, int ny, int nz) {
+  return dim3((unsigned)((xcells + k3X - 1) / k3X),
+              (unsigned)((ny + k3Y - 1) / k3Y), (unsigned)nz);
+}
+
+// the 3D launch grid applies (grid dimensions y and z within their limits)
+bool fits3(const Geom& g) {
+  return g.ndim == 3 && (g.n[1] + k3Y - 1) / k3Y <= 65535 && g.n[2] <= 65535;
+}
+
+int64_t blocks3(const Geom& g) {
+  const dim3 b = grid3(g.n[0], g.n[1], g.n[2]);
+  return (int64_t)b.x * b.y * b.z;
+}
+
+__device__ __forceinline__ int block3_id() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_resid_to32_3d(LevelView<double> L, float* __restrict__ r32,
+                    double* __restrict__ partials,
+                    const Control* __restrict__ ctrl) {
+  __shared__ double sh[kBlock / 64];
+  if (ctrl->done != kRunning) return;
+  const int nx = L.g.n[0], ny = L.g.n[1];
+  const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  double r2 = 0.0;
+  if (x < nx && y < ny) {
+    const int c[3] = {x, y, z};
+    const int64_t idx = ((int64_t)z * ny + y) * nx + x;
+    const double r = residual_value(L, c, idx);
+    if (r32) r32[idx] = (float)r;
+    r2 = r * r;
+  }
+  const double t = block_sum<kBlock>(r2, sh);
+  if (threadIdx.x == 0) partials[block3_id()] = t;
+}
+
 hipError_t launch_resid_to32(const LevelView<double>& L, float* r32,
                              double* partials, int* nblocks,
                              const Control* ctrl, hipStream_t s) {
+  if (fits3(L.g)) {
+    *nblocks = (int)blocks3(L.g);
+    hipLaunchKernelGGL(k_resid_to32_3d, grid3(L.g.n[0], L.g.n[1], L.g.n[2]),
+                       dim3(kBlock), 0, s, L, r32, partials, ctrl);
+    return hipGetLastError();
+  }
   *nblocks = blocks_for(L.g.N);
   hipLaunchKernelGGL(k_resid_to32, dim3(*nblocks), dim3(kBlock), 0, s, L, r32,
                      partials, ctrl);
@@ -243,9 +295,31 @@ __global__ void __launch_bounds__(kBlock)
   L.x[idx] = relax_value(L, c, idx, L.x);
 }
 
+// 3D colour pass: thread (i, y, z) updates cell x = 2i + ((y + z + color) & 1)
+// of row (y, z), the one of this colour in its pair.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_gs_color_3d(LevelView<T> L, int color, const Control* __restrict__ ctrl) {
+  if (ctrl->done != kRunning) return;
+  const int nx = L.g.n[0], ny = L.g.n[1];
+  const int i = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  const int x = 2 * i + ((y + z + color) & 1);
+  if (x >= nx || y >= ny) return;
+  const int c[3] = {x, y, z};
+  const int64_t idx = ((int64_t)z * ny + y) * nx + x;
+  L.x[idx] = relax_value(L, c, idx, L.x);
+}
+
 template <typename T>
 hipError_t launch_gs_color(const LevelView<T>& L, int color,
                            const Control* ctrl, hipStream_t s) {
+  if (fits3(L.g)) {
+    hipLaunchKernelGGL(k_gs_color_3d<T>,
+                       grid3((L.g.n[0] + 1) / 2, L.g.n[1], L.g.n[2]),
+                       dim3(kBlock), 0, s, L, color, ctrl);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_gs_color<T>, dim3(blocks_for(L.g.N)), dim3(kBlock), 0,
                      s, L, color, ctrl);
   return hipGetLastError();
@@ -288,11 +362,52 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// 3D form: one thread per coarse cell (i, j, k), coordinates from the grid.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_resid_restrict_3d(LevelView<T> F, LevelView<T> C,
+                        double* __restrict__ partials,
+                        const Control* __restrict__ ctrl) {
+  __shared__ double sh[kBlock / 64];
+  if (ctrl->done != kRunning) return;
+  const int ncx = C.g.n[0], ncy = C.g.n[1];
+  const int nx = F.g.n[0], ny = F.g.n[1];
+  const int ci = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int cj = blockIdx.y * k3Y + (threadIdx.x / k3X), ck = blockIdx.z;
+  double r2 = 0.0;
+  if (ci < ncx && cj < ncy) {
+    T s = T(0);
+    for (int q2 = 0; q2 < 2; ++q2)
+      for (int q1 = 0; q1 < 2; ++q1)
+        for (int q0 = 0; q0 < 2; ++q0) {
+          const int f[3] = {2 * ci + q0, 2 * cj + q1, 2 * ck + q2};
+          const int64_t fi = ((int64_t)f[2] * ny + f[1]) * nx + f[0];
+          const T r = residual_value(F, f, fi);
+          s += r;
+          r2 += (double)r * (double)r;
+        }
+    const int64_t idx = ((int64_t)ck * ncy + cj) * ncx + ci;
+    C.b[idx] = s / T(8);
+    C.x[idx] = T(0);
+  }
+  if (partials) {
+    const double t = block_sum<kBlock>(r2, sh);
+    if (threadIdx.x == 0) partials[block3_id()] = t;
+  }
+}
+
 template <typename T>
 hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  const LevelView<T>& coarse, double* partials,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
+  if (fits3(fine.g)) {
+    *nblocks = (int)blocks3(coarse.g);
+    hipLaunchKernelGGL(k_resid_restrict_3d<T>,
+                       grid3(coarse.g.n[0], coarse.g.n[1], coarse.g.n[2]),
+                       dim3(kBlock), 0, s, fine, coarse, partials, ctrl);
+    return hipGetLastError();
+  }
   *nblocks = blocks_for(coarse.g.N);
   hipLaunchKernelGGL(k_resid_restrict<T>, dim3(*nblocks), dim3(kBlock), 0, s,
                      fine, coarse, partials, ctrl);
@@ -312,8 +427,27 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_prolong_3d(LevelView<T> C, LevelView<T> F,
+                 const Control* __restrict__ ctrl) {
+  if (ctrl->done != kRunning) return;
+  const int nx = F.g.n[0], ny = F.g.n[1];
+  const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int f[3] = {x, y, z};
+  F.x[((int64_t)z * ny + y) * nx + x] += prolong_value(C, f, 3);
+}
+
+template <typename T>
 hipError_t launch_prolong(const LevelView<T>& coarse, const LevelView<T>& fine,
                           const Control* ctrl, hipStream_t s) {
+  if (fits3(fine.g)) {
+    hipLaunchKernelGGL(k_prolong_3d<T>,
+                       grid3(fine.g.n[0], fine.g.n[1], fine.g.n[2]),
+                       dim3(kBlock), 0, s, coarse, fine, ctrl);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for(fine.g.N)), dim3(kBlock), 0,
                      s, coarse, fine, ctrl);
   return hipGetLastError();
