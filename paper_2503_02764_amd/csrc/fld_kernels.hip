@@ -362,37 +362,56 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// 3D form: one thread per coarse cell (i, j, k), coordinates from the grid.
+// 3D form: a block covers fine cells 64 (x) x 4 (y) x 2 (z), thread t the
+// two cells 2 (t % 32) + {0, 1} of row (t / 32) % 4 in plane t / 128; the
+// residuals go through LDS, and each of the block's 32 x 2 coarse cells sums
+// its eight children in the order of the loop above (z, y, x from the low
+// corner), so the coarse right-hand side is the same to the bit.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_resid_restrict_3d(LevelView<T> F, LevelView<T> C,
                         double* __restrict__ partials,
                         const Control* __restrict__ ctrl) {
   __shared__ double sh[kBlock / 64];
+  __shared__ T R[2][4][64];
   if (ctrl->done != kRunning) return;
-  const int ncx = C.g.n[0], ncy = C.g.n[1];
   const int nx = F.g.n[0], ny = F.g.n[1];
-  const int ci = blockIdx.x * k3X + (threadIdx.x % k3X);
-  const int cj = blockIdx.y * k3Y + (threadIdx.x / k3X), ck = blockIdx.z;
+  const int t = threadIdx.x;
+  const int tx = t % 32, ty = (t / 32) % 4, tz = t / 128;
+  const int y = blockIdx.y * 4 + ty, z = blockIdx.z * 2 + tz;
   double r2 = 0.0;
-  if (ci < ncx && cj < ncy) {
-    T s = T(0);
-    for (int q2 = 0; q2 < 2; ++q2)
-      for (int q1 = 0; q1 < 2; ++q1)
-        for (int q0 = 0; q0 < 2; ++q0) {
-          const int f[3] = {2 * ci + q0, 2 * cj + q1, 2 * ck + q2};
-          const int64_t fi = ((int64_t)f[2] * ny + f[1]) * nx + f[0];
-          const T r = residual_value(F, f, fi);
-          s += r;
-          r2 += (double)r * (double)r;
-        }
-    const int64_t idx = ((int64_t)ck * ncy + cj) * ncx + ci;
-    C.b[idx] = s / T(8);
-    C.x[idx] = T(0);
+#pragma unroll
+  for (int q0 = 0; q0 < 2; ++q0) {
+    const int x = blockIdx.x * 64 + 2 * tx + q0;
+    T r = T(0);
+    if (x < nx && y < ny) {
+      const int f[3] = {x, y, z};
+      r = residual_value(F, f, ((int64_t)z * ny + y) * nx + x);
+      r2 += (double)r * (double)r;
+    }
+    R[tz][ty][2 * tx + q0] = r;
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int cx = t % 32, cy = t / 32;
+    const int ci = blockIdx.x * 32 + cx, cj = blockIdx.y * 2 + cy;
+    const int ncx = C.g.n[0], ncy = C.g.n[1];
+    if (ci < ncx && cj < ncy) {
+      T s = T(0);
+#pragma unroll
+      for (int q2 = 0; q2 < 2; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < 2; ++q1)
+#pragma unroll
+          for (int q0 = 0; q0 < 2; ++q0) s += R[q2][2 * cy + q1][2 * cx + q0];
+      const int64_t idx = ((int64_t)blockIdx.z * ncy + cj) * ncx + ci;
+      C.b[idx] = s / T(8);
+      C.x[idx] = T(0);
+    }
   }
   if (partials) {
-    const double t = block_sum<kBlock>(r2, sh);
-    if (threadIdx.x == 0) partials[block3_id()] = t;
+    const double tsum = block_sum<kBlock>(r2, sh);
+    if (threadIdx.x == 0) partials[block3_id()] = tsum;
   }
 }
 
@@ -402,10 +421,12 @@ hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
   if (fits3(fine.g)) {
-    *nblocks = (int)blocks3(coarse.g);
-    hipLaunchKernelGGL(k_resid_restrict_3d<T>,
-                       grid3(coarse.g.n[0], coarse.g.n[1], coarse.g.n[2]),
-                       dim3(kBlock), 0, s, fine, coarse, partials, ctrl);
+    // fine blocks of 64 x 4 x 2 cells (the fine sides are even)
+    const dim3 g((fine.g.n[0] + 63) / 64, (fine.g.n[1] + 3) / 4,
+                 fine.g.n[2] / 2);
+    *nblocks = (int)(g.x * g.y * g.z);
+    hipLaunchKernelGGL(k_resid_restrict_3d<T>, g, dim3(kBlock), 0, s, fine,
+                       coarse, partials, ctrl);
     return hipGetLastError();
   }
   *nblocks = blocks_for(coarse.g.N);
