@@ -1158,10 +1158,11 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
                                c->partials, coef2d_blocks(g0), c->ctrl,
                                c->stream));
   } else {
+    int nb = 0;
     HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
-                           copy_dst, c->partials, c->ctrl, c->stream));
-    HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, blocks_for(g0.N),
-                               c->ctrl, c->stream));
+                           copy_dst, c->partials, c->ctrl, c->stream, &nb));
+    HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
+                               c->stream));
   }
   for (int l = 0; l + 1 < c->L; ++l) {
     if (c->mixed) {

@@ -246,6 +246,37 @@ struct CoefOut {
   Control* ctrl;
 };
 
+// One cell's face coefficients (and its copy of E); returns E^2 and sets
+// `bad` for a non-physical cell.
+__device__ __forceinline__ double coef_cell(const CoefArgs& A,
+                                            const double* __restrict__ E,
+                                            const double* __restrict__ rho,
+                                            const double* __restrict__ kappa,
+                                            const CoefOut& O, const int c[3],
+                                            int64_t idx, bool& bad) {
+  bad = false;
+  const double D0 = cell_D(A, E, rho, kappa, c, idx, bad);
+  for (int d = 0; d < A.g.ndim; ++d) {
+    double alpha = 0.0;
+    if (c[d] < A.g.n[d] - 1 || A.g.per[d]) {
+      int cn[3] = {c[0], c[1], c[2]};
+      cn[d] = (c[d] + 1) % A.g.n[d];
+      const int64_t nidx =
+          cn[0] + (int64_t)A.g.n[0] * (cn[1] + (int64_t)A.g.n[1] * cn[2]);
+      bool bad_n = false;
+      const double Dn = cell_D(A, E, rho, kappa, cn, nidx, bad_n);
+      const double Df =
+          A.face_mean == 0 ? 0.5 * (D0 + Dn) : 2.0 * D0 * Dn / (D0 + Dn);
+      alpha = A.dt * Df / (A.dx[d] * A.dx[d]);
+    }
+    O.a64[d][idx] = alpha;
+    if (O.a32[d]) O.a32[d][idx] = (float)alpha;
+  }
+  const double Ei = E[idx];
+  if (O.copy_dst) O.copy_dst[idx] = Ei;
+  return Ei * Ei;
+}
+
 __device__ __forceinline__ void coef_body(const CoefArgs& A,
                                           const double* __restrict__ E,
                                           const double* __restrict__ rho,
@@ -261,26 +292,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs& A,
     int c[3];
     coords(A.g, idx, c);
     bool bad = false;
-    const double D0 = cell_D(A, E, rho, kappa, c, idx, bad);
-    for (int d = 0; d < A.g.ndim; ++d) {
-      double alpha = 0.0;
-      if (c[d] < A.g.n[d] - 1 || A.g.per[d]) {
-        int cn[3] = {c[0], c[1], c[2]};
-        cn[d] = (c[d] + 1) % A.g.n[d];
-        const int64_t nidx =
-            cn[0] + (int64_t)A.g.n[0] * (cn[1] + (int64_t)A.g.n[1] * cn[2]);
-        bool bad_n = false;
-        const double Dn = cell_D(A, E, rho, kappa, cn, nidx, bad_n);
-        const double Df =
-            A.face_mean == 0 ? 0.5 * (D0 + Dn) : 2.0 * D0 * Dn / (D0 + Dn);
-        alpha = A.dt * Df / (A.dx[d] * A.dx[d]);
-      }
-      O.a64[d][idx] = alpha;
-      if (O.a32[d]) O.a32[d][idx] = (float)alpha;
-    }
-    const double Ei = E[idx];
-    if (O.copy_dst) O.copy_dst[idx] = Ei;
-    e2 = Ei * Ei;
+    e2 = coef_cell(A, E, rho, kappa, O, c, idx, bad);
     if (bad) atomicAdd(&bad_count, 1);
   }
   const double s = block_sum<kBlock>(e2, sh);

@@ -63,10 +63,11 @@ struct CoefArgs {
 };
 
 // ---- launch wrappers (kernels live in the .hip files) ----------------------
+// *nblocks (if given) receives the number of block partial sums of |E|^2.
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
-                       Control* ctrl, hipStream_t s);
+                       Control* ctrl, hipStream_t s, int* nblocks = nullptr);
 hipError_t launch_finalize(int mode, const double* partials, int count,
                            Control* ctrl, hipStream_t s);
 hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,

@@ -132,10 +132,19 @@ __global__ void __launch_bounds__(kBlock)
   coef_body(A, E, rho, kappa, O, blockIdx.x);
 }
 
+dim3 grid3(int64_t xcells, int ny, int nz);
+bool fits3(const Geom& g);
+
+// 3D grids: the same per cell on the 3D launch grid (no index divisions).
+__global__ void __launch_bounds__(kBlock)
+    k_coef_3d(CoefArgs A, const double* __restrict__ E,
+              const double* __restrict__ rho, const double* __restrict__ kappa,
+              CoefOut O);
+
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
-                       Control* ctrl, hipStream_t s) {
+                       Control* ctrl, hipStream_t s, int* nblocks) {
   CoefOut O;
   for (int d = 0; d < 3; ++d) {
     O.a64[d] = a64[d];
@@ -144,6 +153,13 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
   O.copy_dst = copy_dst;
   O.partials = partials;
   O.ctrl = ctrl;
+  if (fits3(a.g)) {
+    if (nblocks) *nblocks = (int)blocks3(a.g);
+    hipLaunchKernelGGL(k_coef_3d, grid3(a.g.n[0], a.g.n[1], a.g.n[2]),
+                       dim3(kBlock), 0, s, a, E, rho, kappa, O);
+    return hipGetLastError();
+  }
+  if (nblocks) *nblocks = blocks_for(a.g.N);
   hipLaunchKernelGGL(k_coef, dim3(blocks_for(a.g.N)), dim3(kBlock), 0, s, a,
                      E, rho, kappa, O);
   return hipGetLastError();
@@ -232,6 +248,31 @@ int64_t blocks3(const Geom& g) {
 
 __device__ __forceinline__ int block3_id() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_coef_3d(CoefArgs A, const double* __restrict__ E,
+              const double* __restrict__ rho, const double* __restrict__ kappa,
+              CoefOut O) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int bad_count;
+  if (threadIdx.x == 0) bad_count = 0;
+  __syncthreads();
+  const int nx = A.g.n[0], ny = A.g.n[1];
+  const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  double e2 = 0.0;
+  if (x < nx && y < ny) {
+    const int c[3] = {x, y, z};
+    bool bad = false;
+    e2 = coef_cell(A, E, rho, kappa, O, c, ((int64_t)z * ny + y) * nx + x, bad);
+    if (bad) atomicAdd(&bad_count, 1);
+  }
+  const double t = block_sum<kBlock>(e2, sh);
+  if (threadIdx.x == 0) {
+    O.partials[block3_id()] = t;
+    if (bad_count > 0) atomicAdd(&O.ctrl->flagged, bad_count);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
