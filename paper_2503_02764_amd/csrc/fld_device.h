@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include "fld_internal.h"
+#include "fld_wave.h"
 
 namespace fld {
 
@@ -41,8 +42,7 @@ __device__ __forceinline__ int ghost(int m, int n, int per) {
 // Sum over a block of kBlockSize threads; the result is valid in thread 0.
 template <int kBlockSize>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();

@@ -17,6 +17,7 @@
 // loop with the stop test runs here too, exactly as in the multi-launch
 // path: pre-smoothing, residual norm of the finest level, stop or continue.
 #include "fld_internal.h"
+#include "fld_wave.h"
 
 namespace fld {
 
@@ -81,8 +82,7 @@ __device__ __forceinline__ T resid_at(const T* S, const TL& t, int i,
 
 // sum of v over the block, returned to every thread
 __device__ __forceinline__ double tail_block_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
@@ -195,11 +195,8 @@ __device__ __forceinline__ double resid2(const T* S, const int* C,
 // sums of a and b over the block, returned to every thread
 __device__ __forceinline__ void tail_block_sum2(double& a, double& b,
                                                 double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-  }
+  a = wave_sum(a);
+  b = wave_sum(b);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) {

@@ -24,6 +24,7 @@
 // (tested every 2 sweeps, at most 4000), cell-centred bilinear prolongation
 // (weights 9/16, 3/16, 3/16, 1/16), post-smoothing.
 #include "fld_internal.h"
+#include "fld_wave.h"
 
 namespace fld {
 
@@ -126,12 +127,6 @@ __device__ __forceinline__ CellW<T> cell_weights(const Geom& g, const CellA<T>& 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
 }
 
 // Second coarse index of a fine cell along one dimension (bilinear

@@ -73,8 +73,7 @@ __device__ __forceinline__ int map_coord(int g, int n, int per) {
 
 template <typename T>
 __device__ __forceinline__ T block_sum_t(T v, T* sh, int nt) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();
