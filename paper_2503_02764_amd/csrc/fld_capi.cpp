@@ -87,6 +87,7 @@ struct fld_ctx {
   size_t ev_used = 0;
   bool fast = true;  // tiled kernels + single-workgroup tail
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
+  bool coarsen_multi = true;  // 2D: several coarse levels per launch
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
   // learned guess: network carved out of net_ws by fld_set_model
@@ -344,7 +345,7 @@ template <typename T>
 fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps) {
   LevelView<T> v = view(c, H, l);
   for (int s = 0; s < sweeps; ++s)
-    for (int color = 0; color < 2; ++color)
+    for (int color = 0; color < gs_colors(v.g); ++color)
       HIP_TRY(c, launch_gs_color<T>(v, color, c->ctrl, c->stream));
   return FLD_OK;
 }
@@ -1042,6 +1043,8 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   }
   const char* path = getenv("FLD_KERNEL_PATH");
   c->fast = !(path && strcmp(path, "simple") == 0);
+  // one coarsening launch per level (tests that both forms agree bitwise)
+  c->coarsen_multi = c->fast && !getenv("FLD_COARSEN_PER_LEVEL");
   // fixed tile shape for every level (tests of shape independence)
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {
     const int v = atoi(tv);
@@ -1109,7 +1112,7 @@ fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
   for (int mode = 0; mode < 2; ++mode) {
     const LevelView<double>& v = mode == 0 ? v0 : vg;
     for (int k = 0; k < sweeps; ++k)
-      for (int color = 0; color < 2; ++color)
+      for (int color = 0; color < gs_colors(v.g); ++color)
         HIP_TRY(c, launch_gs_color<double>(v, color, c->ctrl, c->stream));
     HIP_TRY(c, launch_resid_norm<double>(v, c->partials, &nb, c->ctrl,
                                          c->stream));
@@ -1164,7 +1167,13 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
     HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
                                c->stream));
   }
-  for (int l = 0; l + 1 < c->L; ++l) {
+  if (c->coarsen_multi && g0.ndim == 2) {
+    if (c->mixed)
+      HIP_TRY(c, launch_coarsen2d<float>(c->geom, c->L, c->h32.a, c->stream));
+    else
+      HIP_TRY(c, launch_coarsen2d<double>(c->geom, c->L, c->h64.a, c->stream));
+  }
+  for (int l = 0; l + 1 < c->L && !(c->coarsen_multi && g0.ndim == 2); ++l) {
     if (c->mixed) {
       const float* fa[3] = {c->h32.a[l][0], c->h32.a[l][1], c->h32.a[l][2]};
       float* ca[3] = {c->h32.a[l + 1][0], c->h32.a[l + 1][1],

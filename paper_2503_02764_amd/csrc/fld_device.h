@@ -303,8 +303,19 @@ __device__ __forceinline__ void coef_body(const CoefArgs& A,
 }
 
 
-// Coarse face coefficient = 1/4 of the mean over the 2^(d-1) fine faces that
-// make up the coarse face (D averaged over the face, dx doubled).
+// Series conductance of one fine path across a coarse face: half of the face
+// inside the lower coarse cell, the face on the coarse face, half of the face
+// inside the upper coarse cell; 0 if any of them is 0 (a wall on the path).
+template <typename T>
+__device__ __forceinline__ T series_path(T a0, T a1, T a2) {
+  T path = T(0);
+  if (a0 > T(0) && a1 > T(0) && a2 > T(0))
+    path = T(2) / (T(0.5) / a0 + T(1) / a1 + T(0.5) / a2);
+  return path;
+}
+
+// Coarse face coefficient = 1/4 of the mean, over the 2^(d-1) fine paths
+// crossing the coarse face, of their series conductance (series_path).
 template <typename T>
 struct CoarsenArgs {
   Geom f, c;
@@ -348,10 +359,7 @@ __device__ __forceinline__ void coarsen_body(const CoarsenArgs<T>& A, int bid) {
               g[0] + (int64_t)A.f.n[0] * (g[1] + (int64_t)A.f.n[1] * g[2]);
           a3[k] = A.fa[d][fi];
         }
-        T path = T(0);
-        if (a3[0] > T(0) && a3[1] > T(0) && a3[2] > T(0))
-          path = T(2) / (T(0.5) / a3[0] + T(1) / a3[1] + T(0.5) / a3[2]);
-        s += path;
+        s += series_path(a3[0], a3[1], a3[2]);
         ++cnt;
       }
     A.ca[d][idx] = T(0.25) * s / T(cnt);

@@ -87,6 +87,11 @@ hipError_t launch_correct(int64_t N, double* x, const float* e,
 template <typename T>
 hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
                           const T* const fa[3], T* const ca[3], hipStream_t s);
+// Coefficients of levels 1 .. L-1 of a 2D hierarchy from those of level 0,
+// several levels per launch; a[l][d] holds level l's faces along d.
+template <typename T>
+hipError_t launch_coarsen2d(const Geom* g, int L, T* const (*a)[3],
+                            hipStream_t s);
 template <typename T>
 hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
                              int* nblocks, const Control* ctrl, hipStream_t s);
@@ -178,6 +183,40 @@ enum FinalizeMode {
   kFinOuter = 3,
   kFinCoef = 4  // |b|^2 in partials[0, count), |b - A x0|^2 in [count, 2 count)
 };
+
+// Colour classes of the Gauss-Seidel sweeps.  Red-black by (x + y + z) & 1
+// is a proper colouring unless a periodic dimension has odd length: there
+// cells n-1 and 0 are neighbours of the same parity.  Cells on the last
+// slab of such a dimension therefore get passes of their own: the class of a
+// cell is (set of odd periodic dimensions on whose last slab it lies, parity
+// of its other coordinates), numbered 2 * set + parity.  Two neighbours
+// differ in one coordinate: either the set differs, or the parity does.
+// Without odd periodic dimensions the classes are the two usual colours.
+template <class G>
+__host__ __device__ inline bool gs_odd_periodic(const G& g, int d) {
+  return g.per[d] && (g.n[d] & 1) && g.n[d] > 1;
+}
+
+template <class G>
+__host__ __device__ inline int gs_colors(const G& g) {
+  int k = 0;
+  for (int d = 0; d < 3; ++d) k += gs_odd_periodic(g, d) ? 1 : 0;
+  return 2 << k;
+}
+
+template <class G>
+__host__ __device__ inline int gs_color(const G& g, const int c[3]) {
+  int set = 0, bit = 0, par = 0;
+  for (int d = 0; d < 3; ++d) {
+    const bool odd = gs_odd_periodic(g, d);
+    if (odd && c[d] == g.n[d] - 1)
+      set |= 1 << bit;
+    else
+      par += c[d];
+    bit += odd ? 1 : 0;
+  }
+  return 2 * set + (par & 1);
+}
 
 inline int blocks_for(int64_t n, int bs = kBlock) {
   return (int)((n + bs - 1) / bs);

@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(kBlock)
   if (idx >= L.g.N) return;
   int c[3];
   coords(L.g, idx, c);
-  if (((c[0] + c[1] + c[2]) & 1) != color) return;
+  if (gs_color(L.g, c) != color) return;
   L.x[idx] = relax_value(L, c, idx, L.x);
 }
 
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 hipError_t launch_gs_color(const LevelView<T>& L, int color,
                            const Control* ctrl, hipStream_t s) {
-  if (fits3(L.g)) {
+  if (fits3(L.g) && gs_colors(L.g) == 2) {
     hipLaunchKernelGGL(k_gs_color_3d<T>,
                        grid3((L.g.n[0] + 1) / 2, L.g.n[1], L.g.n[2]),
                        dim3(kBlock), 0, s, L, color, ctrl);
@@ -542,11 +542,11 @@ __device__ void t_coarsest(const LevelView<T>& L, T* tmp, double* sh,
     if (it == 0) r0 = rn;
     if (!(rn > 1e-6 * r0)) break;  // squared norms
     for (int sw = 0; sw < 2; ++sw)
-      for (int color = 0; color < 2; ++color) {
+      for (int color = 0; color < gs_colors(L.g); ++color) {
         for (int64_t i = threadIdx.x; i < N; i += kReduceBlock) {
           int c[3];
           coords(L.g, i, c);
-          if (((c[0] + c[1] + c[2]) & 1) == color)
+          if (gs_color(L.g, c) == color)
             L.x[i] = relax_value(L, c, i, L.x);
         }
         __syncthreads();
@@ -584,11 +584,11 @@ hipError_t launch_coarsest(const LevelView<T>& L, T* tmp, const Control* ctrl,
 template <typename T>
 __device__ void t_smooth(const LevelView<T>& L, int sweeps) {
   for (int s = 0; s < sweeps; ++s)
-    for (int color = 0; color < 2; ++color) {
+    for (int color = 0; color < gs_colors(L.g); ++color) {
       for (int64_t i = threadIdx.x; i < L.g.N; i += kReduceBlock) {
         int c[3];
         coords(L.g, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) == color)
+        if (gs_color(L.g, c) == color)
           L.x[i] = relax_value(L, c, i, L.x);
       }
       __syncthreads();
@@ -724,6 +724,8 @@ __global__ void __launch_bounds__(kReduceBlock) k_tail(TailArgs<T> A) {
         else if (C->cycles >= C->max_cycles)
           C->done = kCapped;
         stop = C->done != kRunning;
+        // the host reads the outcome from the mirror after this launch
+        if (stop && C->mirror) *C->mirror = *C;
       }
       __syncthreads();
       if (stop) break;

@@ -102,9 +102,10 @@ __device__ __forceinline__ void smooth(T* S, const int* C, const TL& tls,
   const int i = threadIdx.x;
   int c[3] = {0, 0, 0};
   if (i < t.N) unpack(C[t.oc + i], c);
-  const int color = (c[0] + c[1] + c[2]) & 1;
+  const int color = gs_color(t, c);
+  const int ncol = gs_colors(t);
   for (int s = 0; s < sweeps; ++s)
-    for (int col = 0; col < 2; ++col) {
+    for (int col = 0; col < ncol; ++col) {
       if (i < t.N && color == col) {
         T sax = T(0), sa = T(0);
         gather<T, ND>(S, t, i, c, sax, sa);

@@ -151,6 +151,8 @@ bool tail2d_ok(const TailArgs<T>& a) {
   for (int j = 0; j < nt; ++j) {
     const Geom& g = a.lv[a.l0 + j].g;
     if (g.ndim != 2) return false;
+    // red-black colouring only (no odd periodic dimension)
+    if (gs_colors(g) != 2) return false;
     const int k = kind_of(g.N);
     if (j == 0 && g.N > kWideMax) return false;
     if (j > 0) {

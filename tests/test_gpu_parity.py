@@ -443,3 +443,70 @@ def test_same_calls_on_both_sides(case):
     S = x + m.e
     assert np.abs(host(e).reshape(en.shape) - en).max() <= 1e-9 * S.max()
     assert np.abs(host(out).reshape(En.shape) - En).max() <= 1e-9 * S.max()
+
+
+@pytest.mark.parametrize("n,bc", [((96, 80), ("periodic", "neumann")),
+                                  ((130, 70), ("neumann", "periodic")),
+                                  ((200, 136), ("periodic", "periodic")),
+                                  ((1000, 520), ("neumann", "neumann")),
+                                  ((384, 256), ("neumann", "periodic")),
+                                  ((512, 512), ("neumann", "neumann"))])
+def test_multilevel_coarsening_matches_per_level(n, bc, monkeypatch):
+    """The 2D coarse coefficients computed several levels per launch (pair
+    tiles, whole small levels in one block, single-level fallback) are those
+    of one launch per level: the same iterate bit for bit, in FP64 and in
+    the FP32 hierarchy."""
+    from paper_2503_02764_amd import fld
+    m = media.random_small_medium(31 + n[0], n, bc)
+    announce(f"multi-level coarsening {n} {bc}")
+    out = {}
+    for per_level in (False, True):
+        if per_level:
+            monkeypatch.setenv("FLD_COARSEN_PER_LEVEL", "1")
+        else:
+            monkeypatch.delenv("FLD_COARSEN_PER_LEVEL", raising=False)
+        for prec in ("fp64", "fp32_ir"):
+            ctx = fld.fld_setup(params_for(m, rtol=1e-10, precision=prec,
+                                           max_cycles=200))
+            x = dev(np.zeros_like(m.E))
+            _, st = fld.fld_step(ctx, m.dt, dev(m.rho), dev(m.kappa),
+                                 dev(m.E), x)
+            out[(per_level, prec)] = (host(x), st["cycles"])
+    for prec in ("fp64", "fp32_ir"):
+        assert out[(False, prec)][1] == out[(True, prec)][1]
+        np.testing.assert_array_equal(out[(False, prec)][0],
+                                      out[(True, prec)][0])
+
+
+@pytest.mark.parametrize("n,bc", [((75,), ("periodic",)),
+                                  ((1501,), ("periodic",)),
+                                  ((65, 35), ("periodic", "periodic")),
+                                  ((200, 136), ("periodic", "periodic")),
+                                  ((130, 70), ("neumann", "periodic")),
+                                  ((96, 80), ("periodic", "periodic")),
+                                  ((20, 12, 28), ("periodic", "neumann",
+                                                  "periodic"))])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_odd_periodic_levels_are_deterministic(n, bc, precision):
+    """A periodic dimension of odd length (on the finest level or on the
+    coarsest one that coarsening reaches) has same-parity neighbours across
+    the wrap; the sweeps then use the extra colour classes.  A data race
+    there would show as run-to-run differences in the last bits; the answer
+    must also be the oracle's.  (1501,) and (65, 35) are single levels too
+    large for the LDS tail: the whole solve runs in the global-memory tail,
+    whose outcome the host reads from the control block's mirror.)"""
+    from paper_2503_02764_amd import fld
+    m = media.random_small_medium(7 + sum(n), n, bc)
+    announce(f"odd periodic determinism {n} {bc} {precision}")
+    outs = []
+    for _ in range(3):
+        ctx = fld.fld_setup(params_for(m, rtol=1e-11, precision=precision,
+                                       max_cycles=400))
+        x = dev(np.zeros_like(m.E))
+        _, st = fld.fld_step(ctx, m.dt, dev(m.rho), dev(m.kappa), dev(m.E), x)
+        assert st["rel_res_final"] <= 1e-11, st
+        outs.append(host(x))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt, F.problem_from_medium(m))
+    assert rel_l2(outs[0], ref) <= 1e-9
