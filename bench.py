@@ -280,6 +280,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _hbm_roofline(kt, shape):
+    """Roofline entry of a kernel timed with fld_kernel_timing (algorithmic
+    bytes per launch over its mean launch duration, against HBM peak)."""
+    if not kt["launches"]:
+        return None
+    avg_ms = kt["ms"] / kt["launches"]
+    per_launch = kt["bytes"] / kt["launches"]
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kt["kernel"], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kt["kernel"], shape),
+            "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": per_launch,
+            "launches": kt["launches"]}
+
+
 def _line(metric_value, ms, args, workload, dtype, extra):
     out = {
         "metric": METRIC, "value": metric_value, "unit": "cell-updates/s",
@@ -322,14 +339,21 @@ def bench_c3(args):
         for _ in range(warm):
             st.step(m.dt, rho, kap, E, e)
         torch.cuda.synchronize()
+        # the first finest-level colour pass of every V-cycle records its own
+        # duration (HIP events the launch records)
+        fld.fld_kernel_timing_enable(st.ctx, True)
+        fld.fld_kernel_timing_read(st.ctx)  # reset
         cyc = []
         t0 = time.perf_counter()
         for _ in range(steps):
             cyc.append(st.step(m.dt, rho, kap, E, e)["cycles"])
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
+        kt = fld.fld_kernel_timing_read(st.ctx)
+        fld.fld_kernel_timing_enable(st.ctx, False)
         res = dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
-                   vcycles_per_step=float(np.mean(cyc)))
+                   vcycles_per_step=float(np.mean(cyc)),
+                   roofline=_hbm_roofline(kt, "256^3"))
         E_out = E.cpu().numpy()
         del st, rho, E, e, kap
         torch.cuda.empty_cache()
@@ -346,7 +370,8 @@ def bench_c3(args):
     _line(f32["value"], f32["ms_per_step"], args,
           "3d-256cube-stratified-kramers-fp32-vcycles-fp64-refinement", "f32",
           {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
-                        "learned_guess_fp32_vcycles": lrn}})
+                        "learned_guess_fp32_vcycles": lrn},
+           "roofline": f32["roofline"]})
 
 
 def bench_c4(args):

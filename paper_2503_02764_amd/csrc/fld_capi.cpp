@@ -65,6 +65,7 @@ struct fld_ctx {
   Levels<double> h64;          // FP64 hierarchy (level 0 only in FP32_IR)
   Levels<float> h32;           // FP32 hierarchy (FP32_IR only)
   double* bcopy = nullptr;     // level-0 rhs copy when E_out aliases E_in
+  double* dscr = nullptr;      // 3D: cell-centred D of the coefficient stage
   double* partials = nullptr;  // block partial sums
   Control* ctrl = nullptr;     // device control block
   Control* host_ctrl = nullptr;  // pinned host mirror, written by the GPU
@@ -140,6 +141,7 @@ struct Plan {
   size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
   size_t alt[kMaxLevels] = {};  // tiled 2D levels: iterate double buffer
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
+  size_t dscr = 0;  // 3D coefficient stage: D per cell
   size_t guess = 0;
   size_t net_bytes = 0;
   int64_t n_partials = 0;
@@ -254,6 +256,7 @@ void make_plan(const fld_params* p, Plan* P) {
     if (nd == 2 && l + 1 < P->L) P->alt[l] = take(cells * (mixed ? 4 : 8));
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
+  if (nd == 3) P->dscr = take((size_t)P->g[0].N * 8);
   int64_t nparts = blocks_for(P->g[0].N);
   if (p->ndim == 3)  // one partial per block of the 3D launch grid
     nparts = std::max<int64_t>(nparts, blocks3(P->g[0]));
@@ -340,13 +343,25 @@ fld_status fill_zero<float>(fld_ctx* c, float* x, int64_t n) {
   return FLD_OK;
 }
 
-// Simple path: one launch per colour pass.
+// Simple path: one launch per colour pass.  With `timed` (the finest
+// level's pre-smoothing in 3D), the first colour pass records its own
+// duration for the kernel timing: it updates half the cells, reading b of
+// those, all three face arrays and the iterate, and writing its half, i.e.
+// 4.5 N elements per pass touched once.
 template <typename T>
-fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps) {
+fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
+                         bool timed = false) {
   LevelView<T> v = view(c, H, l);
   for (int s = 0; s < sweeps; ++s)
-    for (int color = 0; color < gs_colors(v.g); ++color)
-      HIP_TRY(c, launch_gs_color<T>(v, color, c->ctrl, c->stream));
+    for (int color = 0; color < gs_colors(v.g); ++color) {
+      const bool t = timed && s == 0 && color == 0 && v.g.ndim == 3;
+      TimedLaunch tl(c, t, 4.5 * (double)v.g.N * sizeof(T),
+                     sizeof(T) == 8 ? "k_gs_color_3d<double>"
+                                    : "k_gs_color_3d<float>");
+      FLD_TRY(tl.st);
+      HIP_TRY(c, launch_gs_color<T>(v, color, c->ctrl, c->stream, tl.e0,
+                                    tl.e1));
+    }
   return FLD_OK;
 }
 
@@ -390,7 +405,7 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
                                 c->stream, &nb, t.e0, t.e1));
   } else {
     if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
-    FLD_TRY(smooth_simple<T>(c, H, l, c->p.pre_smooth));
+    FLD_TRY(smooth_simple<T>(c, H, l, c->p.pre_smooth, l == 0));
     HIP_TRY(c, launch_resid_restrict<T>(view(c, H, l), view(c, H, l + 1),
                                         norm ? c->partials : nullptr, &nb,
                                         c->ctrl, c->stream));
@@ -1058,6 +1073,7 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
       break;
     }
   c->bcopy = (double*)(w + P.bcopy);
+  c->dscr = P.dscr ? (double*)(w + P.dscr) : nullptr;
   c->partials = (double*)(w + P.partials);
   c->h64.tmp = (double*)(w + P.tmp);
   c->h32.tmp = (float*)(w + P.tmp);
@@ -1163,7 +1179,8 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
   } else {
     int nb = 0;
     HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
-                           copy_dst, c->partials, c->ctrl, c->stream, &nb));
+                           copy_dst, c->partials, c->ctrl, c->stream, &nb,
+                           c->dscr));
     HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
                                c->stream));
   }

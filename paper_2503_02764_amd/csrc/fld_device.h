@@ -277,6 +277,30 @@ __device__ __forceinline__ double coef_cell(const CoefArgs& A,
   return Ei * Ei;
 }
 
+// The face coefficients of cell c from cell-centred D already computed for
+// every cell (Dc): coef_cell's arithmetic with D read instead of recomputed.
+__device__ __forceinline__ void faces_from_D(const CoefArgs& A,
+                                             const double* __restrict__ Dc,
+                                             const CoefOut& O, const int c[3],
+                                             int64_t idx) {
+  const double D0 = Dc[idx];
+  for (int d = 0; d < A.g.ndim; ++d) {
+    double alpha = 0.0;
+    if (c[d] < A.g.n[d] - 1 || A.g.per[d]) {
+      int cn[3] = {c[0], c[1], c[2]};
+      cn[d] = (c[d] + 1) % A.g.n[d];
+      const int64_t nidx =
+          cn[0] + (int64_t)A.g.n[0] * (cn[1] + (int64_t)A.g.n[1] * cn[2]);
+      const double Dn = Dc[nidx];
+      const double Df =
+          A.face_mean == 0 ? 0.5 * (D0 + Dn) : 2.0 * D0 * Dn / (D0 + Dn);
+      alpha = A.dt * Df / (A.dx[d] * A.dx[d]);
+    }
+    O.a64[d][idx] = alpha;
+    if (O.a32[d]) O.a32[d][idx] = (float)alpha;
+  }
+}
+
 __device__ __forceinline__ void coef_body(const CoefArgs& A,
                                           const double* __restrict__ E,
                                           const double* __restrict__ rho,

@@ -67,7 +67,8 @@ struct CoefArgs {
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
-                       Control* ctrl, hipStream_t s, int* nblocks = nullptr);
+                       Control* ctrl, hipStream_t s, int* nblocks = nullptr,
+                       double* dscr = nullptr);
 hipError_t launch_finalize(int mode, const double* partials, int count,
                            Control* ctrl, hipStream_t s);
 hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,
@@ -95,9 +96,11 @@ hipError_t launch_coarsen2d(const Geom* g, int L, T* const (*a)[3],
 template <typename T>
 hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
                              int* nblocks, const Control* ctrl, hipStream_t s);
+// With ev0/ev1 given (3D levels), the launch itself records them.
 template <typename T>
 hipError_t launch_gs_color(const LevelView<T>& L, int color,
-                           const Control* ctrl, hipStream_t s);
+                           const Control* ctrl, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  const LevelView<T>& coarse, double* partials,

@@ -6,8 +6,10 @@
 // gas-radiation exchange quartic (eqs. heating, qdot; Sect. 3).
 //
 // Every kernel here is memory-bound (well under 10 flop/byte).  Reductions
-// are deterministic: a fixed wave-level shuffle tree, then a fixed loop over
-// the waves of a block, then one single-block pass over the block partials.
+// are deterministic: a fixed wave-level DPP tree, then a fixed loop over the
+// waves of a block, then one single-block pass over the block partials.
+#include <hip/hip_ext.h>
+
 #include "fld_internal.h"
 #include "fld_device.h"
 
@@ -141,10 +143,19 @@ __global__ void __launch_bounds__(kBlock)
               const double* __restrict__ rho, const double* __restrict__ kappa,
               CoefOut O);
 
+// 3D grids with a scratch array: two passes, D once per cell, then the faces.
+__global__ void __launch_bounds__(kBlock)
+    k_cellD_3d(CoefArgs A, const double* __restrict__ E,
+               const double* __restrict__ rho, const double* __restrict__ kappa,
+               double* __restrict__ Dc, CoefOut O);
+__global__ void __launch_bounds__(kBlock)
+    k_faces_3d(CoefArgs A, const double* __restrict__ Dc, CoefOut O);
+
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
-                       Control* ctrl, hipStream_t s, int* nblocks) {
+                       Control* ctrl, hipStream_t s, int* nblocks,
+                       double* dscr) {
   CoefOut O;
   for (int d = 0; d < 3; ++d) {
     O.a64[d] = a64[d];
@@ -155,8 +166,16 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
   O.ctrl = ctrl;
   if (fits3(a.g)) {
     if (nblocks) *nblocks = (int)blocks3(a.g);
-    hipLaunchKernelGGL(k_coef_3d, grid3(a.g.n[0], a.g.n[1], a.g.n[2]),
-                       dim3(kBlock), 0, s, a, E, rho, kappa, O);
+    const dim3 grid = grid3(a.g.n[0], a.g.n[1], a.g.n[2]);
+    if (dscr) {
+      hipLaunchKernelGGL(k_cellD_3d, grid, dim3(kBlock), 0, s, a, E, rho,
+                         kappa, dscr, O);
+      hipLaunchKernelGGL(k_faces_3d, grid, dim3(kBlock), 0, s, a,
+                         (const double*)dscr, O);
+    } else {
+      hipLaunchKernelGGL(k_coef_3d, grid, dim3(kBlock), 0, s, a, E, rho,
+                         kappa, O);
+    }
     return hipGetLastError();
   }
   if (nblocks) *nblocks = blocks_for(a.g.N);
@@ -276,6 +295,45 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock)
+    k_cellD_3d(CoefArgs A, const double* __restrict__ E,
+               const double* __restrict__ rho, const double* __restrict__ kappa,
+               double* __restrict__ Dc, CoefOut O) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int bad_count;
+  if (threadIdx.x == 0) bad_count = 0;
+  __syncthreads();
+  const int nx = A.g.n[0], ny = A.g.n[1];
+  const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  double e2 = 0.0;
+  if (x < nx && y < ny) {
+    const int c[3] = {x, y, z};
+    const int64_t idx = ((int64_t)z * ny + y) * nx + x;
+    bool bad = false;
+    Dc[idx] = cell_D(A, E, rho, kappa, c, idx, bad);
+    if (bad) atomicAdd(&bad_count, 1);
+    const double Ei = E[idx];
+    if (O.copy_dst) O.copy_dst[idx] = Ei;
+    e2 = Ei * Ei;
+  }
+  const double t = block_sum<kBlock>(e2, sh);
+  if (threadIdx.x == 0) {
+    O.partials[block3_id()] = t;
+    if (bad_count > 0) atomicAdd(&O.ctrl->flagged, bad_count);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_faces_3d(CoefArgs A, const double* __restrict__ Dc, CoefOut O) {
+  const int nx = A.g.n[0], ny = A.g.n[1];
+  const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
+  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int c[3] = {x, y, z};
+  faces_from_D(A, Dc, O, c, ((int64_t)z * ny + y) * nx + x);
+}
+
+__global__ void __launch_bounds__(kBlock)
     k_resid_to32_3d(LevelView<double> L, float* __restrict__ r32,
                     double* __restrict__ partials,
                     const Control* __restrict__ ctrl) {
@@ -354,11 +412,16 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T>
 hipError_t launch_gs_color(const LevelView<T>& L, int color,
-                           const Control* ctrl, hipStream_t s) {
+                           const Control* ctrl, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
   if (fits3(L.g) && gs_colors(L.g) == 2) {
-    hipLaunchKernelGGL(k_gs_color_3d<T>,
-                       grid3((L.g.n[0] + 1) / 2, L.g.n[1], L.g.n[2]),
-                       dim3(kBlock), 0, s, L, color, ctrl);
+    const dim3 grid = grid3((L.g.n[0] + 1) / 2, L.g.n[1], L.g.n[2]);
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL(k_gs_color_3d<T>, grid, dim3(kBlock), 0, s, ev0,
+                            ev1, 0, L, color, ctrl);
+    else
+      hipLaunchKernelGGL(k_gs_color_3d<T>, grid, dim3(kBlock), 0, s, L, color,
+                         ctrl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_gs_color<T>, dim3(blocks_for(L.g.N)), dim3(kBlock), 0,
@@ -765,7 +828,8 @@ hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s) {
   template hipError_t launch_resid_norm<T>(const LevelView<T>&, double*, int*, \
                                            const Control*, hipStream_t);       \
   template hipError_t launch_gs_color<T>(const LevelView<T>&, int,             \
-                                         const Control*, hipStream_t);         \
+                                         const Control*, hipStream_t,          \
+                                         hipEvent_t, hipEvent_t);              \
   template hipError_t launch_resid_restrict<T>(                                \
       const LevelView<T>&, const LevelView<T>&, double*, int*, const Control*, \
       hipStream_t);                                                            \
