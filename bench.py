@@ -272,12 +272,32 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": kt["launches"],
         },
+        "step_model_roofline": step_model_roofline(
+            2, "fp64", base["value"], base["vcycles_per_step"]),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def step_model_roofline(ndim, precision, value, vcycles, outer=None, inner=2):
+    """Step-level roofline from the byte model of the path (each pass streams
+    its operands once; V(2,2); w = 8 FP64, 4 FP32): per fine cell and step,
+    FP64 131 + 283 n_V bytes (2D) or 143 + 286 n_V (3D); FP32 V-cycles in FP64
+    refinement with m outer iterations of k inner cycles, 125 + m(56 + 141 k)
+    (2D) or 140 + m(64 + 143 k) (3D).  Model bytes x cell-updates/s against
+    8 TB/s."""
+    if precision == "fp64":
+        base, per = (131.0, 283.0) if ndim == 2 else (143.0, 286.0)
+        b = base + per * vcycles
+    else:
+        base, ob, ib = (125.0, 56.0, 141.0) if ndim == 2 else (140.0, 64.0, 143.0)
+        b = base + outer * (ob + ib * inner)
+    gbs = b * value / 1e9
+    return {"bytes_per_cell_step": b, "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
 def _hbm_roofline(kt, shape):
@@ -343,17 +363,23 @@ def bench_c3(args):
         # duration (HIP events the launch records)
         fld.fld_kernel_timing_enable(st.ctx, True)
         fld.fld_kernel_timing_read(st.ctx)  # reset
-        cyc = []
+        cyc, outer = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
-            cyc.append(st.step(m.dt, rho, kap, E, e)["cycles"])
+            s = st.step(m.dt, rho, kap, E, e)
+            cyc.append(s["cycles"])
+            outer.append(s["outer_iters"])
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         kt = fld.fld_kernel_timing_read(st.ctx)
         fld.fld_kernel_timing_enable(st.ctx, False)
         res = dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
                    vcycles_per_step=float(np.mean(cyc)),
+                   outer_per_step=float(np.mean(outer)),
                    roofline=_hbm_roofline(kt, "256^3"))
+        res["step_model_roofline"] = step_model_roofline(
+            3, precision, res["value"], res["vcycles_per_step"],
+            res["outer_per_step"])
         E_out = E.cpu().numpy()
         del st, rho, E, e, kap
         torch.cuda.empty_cache()
@@ -371,7 +397,8 @@ def bench_c3(args):
           "3d-256cube-stratified-kramers-fp32-vcycles-fp64-refinement", "f32",
           {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
                         "learned_guess_fp32_vcycles": lrn},
-           "roofline": f32["roofline"]})
+           "roofline": f32["roofline"],
+           "step_model_roofline": f32["step_model_roofline"]})
 
 
 def bench_c4(args):
