@@ -274,12 +274,35 @@ def main():
         },
         "step_model_roofline": step_model_roofline(
             2, "fp64", base["value"], base["vcycles_per_step"]),
+        "achievable_copy": copy_bandwidth(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(reps=10):
+    """Achievable HBM bandwidth: a plain 1 GiB device-to-device copy (read +
+    write bytes over the mean time per copy, torch events on the stream the
+    copies run on)."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "bytes_per_copy": 2 * n * 8}
 
 
 def step_model_roofline(ndim, precision, value, vcycles, outer=None, inner=2):
@@ -398,7 +421,8 @@ def bench_c3(args):
           {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
                         "learned_guess_fp32_vcycles": lrn},
            "roofline": f32["roofline"],
-           "step_model_roofline": f32["step_model_roofline"]})
+           "step_model_roofline": f32["step_model_roofline"],
+           "achievable_copy": copy_bandwidth()})
 
 
 def bench_c4(args):
