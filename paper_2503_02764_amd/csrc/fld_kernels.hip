@@ -395,14 +395,20 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // 3D colour pass: thread (i, y, z) updates cell x = 2i + ((y + z + color) & 1)
-// of row (y, z), the one of this colour in its pair.
+// of row (y, z), the one of this colour in its pair.  A block takes kColRY
+// rows: the rows above and below a block, which its stencil also reads and
+// which neighbouring blocks (on other XCDs, through another L2) own, are then
+// a smaller share of what it loads.  8 rows measured best on 256^3 (FP32
+// pass 99 -> 98 us; 16 rows were slower than 4).
+constexpr int kColRY = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3X * kColRY)
     k_gs_color_3d(LevelView<T> L, int color, const Control* __restrict__ ctrl) {
   if (ctrl->done != kRunning) return;
   const int nx = L.g.n[0], ny = L.g.n[1];
   const int i = blockIdx.x * k3X + (threadIdx.x % k3X);
-  const int y = blockIdx.y * k3Y + (threadIdx.x / k3X), z = blockIdx.z;
+  const int y = blockIdx.y * kColRY + (threadIdx.x / k3X), z = blockIdx.z;
   const int x = 2 * i + ((y + z + color) & 1);
   if (x >= nx || y >= ny) return;
   const int c[3] = {x, y, z};
@@ -415,13 +421,15 @@ hipError_t launch_gs_color(const LevelView<T>& L, int color,
                            const Control* ctrl, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
   if (fits3(L.g) && gs_colors(L.g) == 2) {
-    const dim3 grid = grid3((L.g.n[0] + 1) / 2, L.g.n[1], L.g.n[2]);
+    const dim3 grid((unsigned)(((L.g.n[0] + 1) / 2 + k3X - 1) / k3X),
+                    (unsigned)((L.g.n[1] + kColRY - 1) / kColRY),
+                    (unsigned)L.g.n[2]);
+    const dim3 block(k3X * kColRY);
     if (ev0 && ev1)
-      hipExtLaunchKernelGGL(k_gs_color_3d<T>, grid, dim3(kBlock), 0, s, ev0,
-                            ev1, 0, L, color, ctrl);
+      hipExtLaunchKernelGGL(k_gs_color_3d<T>, grid, block, 0, s, ev0, ev1, 0,
+                            L, color, ctrl);
     else
-      hipLaunchKernelGGL(k_gs_color_3d<T>, grid, dim3(kBlock), 0, s, L, color,
-                         ctrl);
+      hipLaunchKernelGGL(k_gs_color_3d<T>, grid, block, 0, s, L, color, ctrl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_gs_color<T>, dim3(blocks_for(L.g.N)), dim3(kBlock), 0,
