@@ -479,18 +479,24 @@ __global__ void __launch_bounds__(kBlock)
 // residuals go through LDS, and each of the block's 32 x 2 coarse cells sums
 // its eight children in the order of the loop above (z, y, x from the low
 // corner), so the coarse right-hand side is the same to the bit.
+// A block takes 64 x kRRY x 2 fine cells (kRRY even): the rows above and
+// below it, which the residual stencil reads and neighbouring blocks own,
+// are a smaller share of its loads than with 4 rows.
+constexpr int kRRY = 8;
+constexpr int kRRT = 32 * kRRY * 2;  // threads: two fine cells along x each
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRRT)
     k_resid_restrict_3d(LevelView<T> F, LevelView<T> C,
                         double* __restrict__ partials,
                         const Control* __restrict__ ctrl) {
-  __shared__ double sh[kBlock / 64];
-  __shared__ T R[2][4][64];
+  __shared__ double sh[kRRT / 64];
+  __shared__ T R[2][kRRY][64];
   if (ctrl->done != kRunning) return;
   const int nx = F.g.n[0], ny = F.g.n[1];
   const int t = threadIdx.x;
-  const int tx = t % 32, ty = (t / 32) % 4, tz = t / 128;
-  const int y = blockIdx.y * 4 + ty, z = blockIdx.z * 2 + tz;
+  const int tx = t % 32, ty = (t / 32) % kRRY, tz = t / (32 * kRRY);
+  const int y = blockIdx.y * kRRY + ty, z = blockIdx.z * 2 + tz;
   double r2 = 0.0;
 #pragma unroll
   for (int q0 = 0; q0 < 2; ++q0) {
@@ -504,9 +510,9 @@ __global__ void __launch_bounds__(kBlock)
     R[tz][ty][2 * tx + q0] = r;
   }
   __syncthreads();
-  if (t < 64) {
+  if (t < 32 * (kRRY / 2)) {
     const int cx = t % 32, cy = t / 32;
-    const int ci = blockIdx.x * 32 + cx, cj = blockIdx.y * 2 + cy;
+    const int ci = blockIdx.x * 32 + cx, cj = blockIdx.y * (kRRY / 2) + cy;
     const int ncx = C.g.n[0], ncy = C.g.n[1];
     if (ci < ncx && cj < ncy) {
       T s = T(0);
@@ -522,7 +528,7 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
   if (partials) {
-    const double tsum = block_sum<kBlock>(r2, sh);
+    const double tsum = block_sum<kRRT>(r2, sh);
     if (threadIdx.x == 0) partials[block3_id()] = tsum;
   }
 }
@@ -533,11 +539,11 @@ hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
   if (fits3(fine.g)) {
-    // fine blocks of 64 x 4 x 2 cells (the fine sides are even)
-    const dim3 g((fine.g.n[0] + 63) / 64, (fine.g.n[1] + 3) / 4,
+    // fine blocks of 64 x kRRY x 2 cells (the fine sides are even)
+    const dim3 g((fine.g.n[0] + 63) / 64, (fine.g.n[1] + kRRY - 1) / kRRY,
                  fine.g.n[2] / 2);
     *nblocks = (int)(g.x * g.y * g.z);
-    hipLaunchKernelGGL(k_resid_restrict_3d<T>, g, dim3(kBlock), 0, s, fine,
+    hipLaunchKernelGGL(k_resid_restrict_3d<T>, g, dim3(kRRT), 0, s, fine,
                        coarse, partials, ctrl);
     return hipGetLastError();
   }
