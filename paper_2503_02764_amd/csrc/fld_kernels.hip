@@ -134,6 +134,14 @@ __global__ void __launch_bounds__(kBlock)
   coef_body(A, E, rho, kappa, O, blockIdx.x);
 }
 
+// 3D levels: a block of k3T threads covers a run of k3X cells along x in
+// k3Y consecutive rows of one z-plane (thread t: x offset t % k3X, row
+// t / k3X), so the cell coordinates come from the block and thread indices
+// without divisions; a colour pass covers only the cells of its colour.
+// Eight rows rather than four: the rows above and below a block, which its
+// stencils read and neighbouring blocks (other XCDs) own, are a smaller share
+// of its loads.
+constexpr int k3X = 64, k3Y = 8, k3T = k3X * k3Y;
 dim3 grid3(int64_t xcells, int ny, int nz);
 bool fits3(const Geom& g);
 
@@ -168,12 +176,12 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
     if (nblocks) *nblocks = (int)blocks3(a.g);
     const dim3 grid = grid3(a.g.n[0], a.g.n[1], a.g.n[2]);
     if (dscr) {
-      hipLaunchKernelGGL(k_cellD_3d, grid, dim3(kBlock), 0, s, a, E, rho,
+      hipLaunchKernelGGL(k_cellD_3d, grid, dim3(k3T), 0, s, a, E, rho,
                          kappa, dscr, O);
-      hipLaunchKernelGGL(k_faces_3d, grid, dim3(kBlock), 0, s, a,
+      hipLaunchKernelGGL(k_faces_3d, grid, dim3(k3T), 0, s, a,
                          (const double*)dscr, O);
     } else {
-      hipLaunchKernelGGL(k_coef_3d, grid, dim3(kBlock), 0, s, a, E, rho,
+      hipLaunchKernelGGL(k_coef_3d, grid, dim3(k3T), 0, s, a, E, rho,
                          kappa, O);
     }
     return hipGetLastError();
@@ -244,11 +252,6 @@ __global__ void __launch_bounds__(kBlock)
   resid_to32_body(L, r32, partials, ctrl, blockIdx.x);
 }
 
-// 3D levels: a block of kBlock threads covers a run of k3X cells along x in
-// k3Y consecutive rows of one z-plane (thread t: x offset t % k3X, row
-// t / k3X), so the cell coordinates come from the block and thread indices
-// without divisions; a colour pass covers only the cells of its colour.
-constexpr int k3X = 64, k3Y = kBlock / k3X;
 
 dim3 grid3(int64_t xcells, int ny, int nz) {
   return dim3((unsigned)((xcells + k3X - 1) / k3X),
@@ -269,11 +272,11 @@ __device__ __forceinline__ int block3_id() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_coef_3d(CoefArgs A, const double* __restrict__ E,
               const double* __restrict__ rho, const double* __restrict__ kappa,
               CoefOut O) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[k3T / 64];
   __shared__ int bad_count;
   if (threadIdx.x == 0) bad_count = 0;
   __syncthreads();
@@ -287,18 +290,18 @@ __global__ void __launch_bounds__(kBlock)
     e2 = coef_cell(A, E, rho, kappa, O, c, ((int64_t)z * ny + y) * nx + x, bad);
     if (bad) atomicAdd(&bad_count, 1);
   }
-  const double t = block_sum<kBlock>(e2, sh);
+  const double t = block_sum<k3T>(e2, sh);
   if (threadIdx.x == 0) {
     O.partials[block3_id()] = t;
     if (bad_count > 0) atomicAdd(&O.ctrl->flagged, bad_count);
   }
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_cellD_3d(CoefArgs A, const double* __restrict__ E,
                const double* __restrict__ rho, const double* __restrict__ kappa,
                double* __restrict__ Dc, CoefOut O) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[k3T / 64];
   __shared__ int bad_count;
   if (threadIdx.x == 0) bad_count = 0;
   __syncthreads();
@@ -316,14 +319,14 @@ __global__ void __launch_bounds__(kBlock)
     if (O.copy_dst) O.copy_dst[idx] = Ei;
     e2 = Ei * Ei;
   }
-  const double t = block_sum<kBlock>(e2, sh);
+  const double t = block_sum<k3T>(e2, sh);
   if (threadIdx.x == 0) {
     O.partials[block3_id()] = t;
     if (bad_count > 0) atomicAdd(&O.ctrl->flagged, bad_count);
   }
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_faces_3d(CoefArgs A, const double* __restrict__ Dc, CoefOut O) {
   const int nx = A.g.n[0], ny = A.g.n[1];
   const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
@@ -333,11 +336,11 @@ __global__ void __launch_bounds__(kBlock)
   faces_from_D(A, Dc, O, c, ((int64_t)z * ny + y) * nx + x);
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_resid_to32_3d(LevelView<double> L, float* __restrict__ r32,
                     double* __restrict__ partials,
                     const Control* __restrict__ ctrl) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[k3T / 64];
   if (ctrl->done != kRunning) return;
   const int nx = L.g.n[0], ny = L.g.n[1];
   const int x = blockIdx.x * k3X + (threadIdx.x % k3X);
@@ -350,7 +353,7 @@ __global__ void __launch_bounds__(kBlock)
     if (r32) r32[idx] = (float)r;
     r2 = r * r;
   }
-  const double t = block_sum<kBlock>(r2, sh);
+  const double t = block_sum<k3T>(r2, sh);
   if (threadIdx.x == 0) partials[block3_id()] = t;
 }
 
@@ -360,7 +363,7 @@ hipError_t launch_resid_to32(const LevelView<double>& L, float* r32,
   if (fits3(L.g)) {
     *nblocks = (int)blocks3(L.g);
     hipLaunchKernelGGL(k_resid_to32_3d, grid3(L.g.n[0], L.g.n[1], L.g.n[2]),
-                       dim3(kBlock), 0, s, L, r32, partials, ctrl);
+                       dim3(k3T), 0, s, L, r32, partials, ctrl);
     return hipGetLastError();
   }
   *nblocks = blocks_for(L.g.N);
@@ -566,7 +569,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_prolong_3d(LevelView<T> C, LevelView<T> F,
                  const Control* __restrict__ ctrl) {
   if (ctrl->done != kRunning) return;
@@ -584,7 +587,7 @@ hipError_t launch_prolong(const LevelView<T>& coarse, const LevelView<T>& fine,
   if (fits3(fine.g)) {
     hipLaunchKernelGGL(k_prolong_3d<T>,
                        grid3(fine.g.n[0], fine.g.n[1], fine.g.n[2]),
-                       dim3(kBlock), 0, s, coarse, fine, ctrl);
+                       dim3(k3T), 0, s, coarse, fine, ctrl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for(fine.g.N)), dim3(kBlock), 0,
