@@ -146,18 +146,22 @@ dim3 grid3(int64_t xcells, int ny, int nz);
 bool fits3(const Geom& g);
 
 // 3D grids: the same per cell on the 3D launch grid (no index divisions).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_coef_3d(CoefArgs A, const double* __restrict__ E,
               const double* __restrict__ rho, const double* __restrict__ kappa,
               CoefOut O);
 
 // 3D grids with a scratch array: two passes, D once per cell, then the faces.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_cellD_3d(CoefArgs A, const double* __restrict__ E,
                const double* __restrict__ rho, const double* __restrict__ kappa,
                double* __restrict__ Dc, CoefOut O);
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(k3T)
     k_faces_3d(CoefArgs A, const double* __restrict__ Dc, CoefOut O);
+__global__ void __launch_bounds__(k3T)
+    k_resid_to32_3d(LevelView<double> L, float* __restrict__ r32,
+                    double* __restrict__ partials,
+                    const Control* __restrict__ ctrl);
 
 hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
@@ -239,6 +243,16 @@ template <typename T>
 hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
                              int* nblocks, const Control* ctrl,
                              hipStream_t s) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    // 3D FP64: the residual kernel of the 3D launch grid, without its FP32
+    // output (same residual per cell)
+    if (fits3(L.g)) {
+      *nblocks = (int)blocks3(L.g);
+      hipLaunchKernelGGL(k_resid_to32_3d, grid3(L.g.n[0], L.g.n[1], L.g.n[2]),
+                         dim3(k3T), 0, s, L, (float*)nullptr, partials, ctrl);
+      return hipGetLastError();
+    }
+  }
   *nblocks = blocks_for(L.g.N);
   hipLaunchKernelGGL(k_resid_norm<T>, dim3(*nblocks), dim3(kBlock), 0, s, L,
                      partials, ctrl);
