@@ -711,7 +711,10 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
     jc[g] = {c->ctrl, c->p.rtol, c->p.max_cycles, c->inner, c->host_ctrl_dev};
     JobCoef& J = jf[g];
     J.A.g = c->geom[0];
-    for (int d = 0; d < 3; ++d) J.A.dx[d] = c->p.dx[d];
+    for (int d = 0; d < 3; ++d) {
+      J.A.dx[d] = c->p.dx[d];
+      J.A.gscale[d] = 1.0 / (12.0 * c->p.dx[d]);
+    }
     J.A.dt = dt[g];
     J.A.c = c->p.c;
     J.A.limiter = c->p.limiter;
@@ -1161,7 +1164,10 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
                              c->host_ctrl_dev, c->stream));
   CoefArgs A;
   A.g = g0;
-  for (int d = 0; d < 3; ++d) A.dx[d] = c->p.dx[d];
+  for (int d = 0; d < 3; ++d) {
+    A.dx[d] = c->p.dx[d];
+    A.gscale[d] = 1.0 / (12.0 * c->p.dx[d]);
+  }
   A.dt = dt;
   A.c = c->p.c;
   A.limiter = c->p.limiter;
@@ -1455,7 +1461,10 @@ fld_status fld_features(fld_ctx* c, double dt, const double* rho,
                              nullptr, c->stream));
   CoefArgs A;
   A.g = g0;
-  for (int d = 0; d < 3; ++d) A.dx[d] = c->p.dx[d];
+  for (int d = 0; d < 3; ++d) {
+    A.dx[d] = c->p.dx[d];
+    A.gscale[d] = 1.0 / (12.0 * c->p.dx[d]);
+  }
   A.dt = dt;
   A.c = c->p.c;
   A.limiter = c->p.limiter;

@@ -85,14 +85,14 @@ __global__ void __launch_bounds__(NTC) k_coef2d(Coef2DArgs P) {
     double g2 = 0.0;
     {
       const double G = (Es[ey][ex - 2] - 8.0 * Es[ey][ex - 1] +
-                        8.0 * Es[ey][ex + 1] - Es[ey][ex + 2]) /
-                       (12.0 * A.dx[0]);
+                        8.0 * Es[ey][ex + 1] - Es[ey][ex + 2]) *
+                       A.gscale[0];
       g2 += G * G;
     }
     {
       const double G = (Es[ey - 2][ex] - 8.0 * Es[ey - 1][ex] +
-                        8.0 * Es[ey + 1][ex] - Es[ey + 2][ex]) /
-                       (12.0 * A.dx[1]);
+                        8.0 * Es[ey + 1][ex] - Es[ey + 2][ex]) *
+                       A.gscale[1];
       g2 += G * G;
     }
     const double R = sqrt(g2) / (rk * E0);

@@ -228,7 +228,7 @@ __device__ __forceinline__ double cell_D(const CoefArgs& A, const double* E,
     const double em1 = E[base + (int64_t)ghost(c[d] - 1, n, p) * st];
     const double ep1 = E[base + (int64_t)ghost(c[d] + 1, n, p) * st];
     const double ep2 = E[base + (int64_t)ghost(c[d] + 2, n, p) * st];
-    const double G = (em2 - 8.0 * em1 + 8.0 * ep1 - ep2) / (12.0 * A.dx[d]);
+    const double G = (em2 - 8.0 * em1 + 8.0 * ep1 - ep2) * A.gscale[d];
     g2 += G * G;
   }
   const double R = sqrt(g2) / (rk * E0);
@@ -460,14 +460,17 @@ __device__ __forceinline__ T prolong_value(const LevelView<T>& C,
 
 
 // Unique positive root of a4 x^4 + a1 x - c0 (a4 >= 0, a1 > 0, c0 > 0) by
-// Newton from the upper bound min(c0/a1, (c0/a4)^(1/4)); on this increasing
-// convex function the iterates fall monotonically onto the root.
+// Newton from `start` (the current gas energy, usually close), capped at the
+// upper bound min(c0/a1, (c0/a4)^(1/4)).  On this increasing convex function
+// a start below the root steps once above it; from above the iterates fall
+// monotonically onto the root.
 __device__ __forceinline__ double quartic_root(double a4, double a1,
-                                               double c0) {
+                                               double c0, double start) {
   const double u1 = c0 / a1;
   const double u4 = a4 > 0.0 ? sqrt(sqrt(c0 / a4)) : u1;
-  double x = fmin(u1, u4);
-  const double lo = 0.5 * x;  // f(lo) < 0 for this bound
+  const double ub = fmin(u1, u4);
+  double x = start > 0.0 ? fmin(start, ub) : ub;
+  const double lo = 0.5 * ub;  // f(lo) < 0: the root lies above it
   for (int it = 0; it < 100; ++it) {
     const double x2 = x * x;
     const double f = (a4 * x2) * x2 + a1 * x - c0;
@@ -502,7 +505,7 @@ __device__ __forceinline__ void exchange_body(
   const double t = gm1 / (r * gas_const);
   const double t2 = t * t;
   const double a4 = beta * a_rad * (t2 * t2);
-  const double x = quartic_root(a4, 1.0 + beta, ei + beta * S);
+  const double x = quartic_root(a4, 1.0 + beta, ei + beta * S, ei);
   e[i] = x;
   E[i] = S - x;
 }

@@ -57,6 +57,7 @@ enum DoneCode { kRunning = 0, kConverged = 1, kCapped = 2, kNonPhysical = 3 };
 struct CoefArgs {
   Geom g;
   double dx[3];
+  double gscale[3];  // 1 / (12 dx): the five-point gradient's scale
   double dt, c;
   int limiter;   // 0 LP, 1 diffusion
   int face_mean; // 0 arithmetic, 1 harmonic
