@@ -26,10 +26,13 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
 
 
 # V-cycle of the 2D workloads: V(2,3) (two pre-, three post-smoothing
-# sweeps).  On the 1024^2 workload it needs 5.15 cycles per step instead of
-# V(2,2)'s 5.85 and is 6% faster per step; the finest down pass (the timed
-# kernel) is the same.  The library's default stays V(2,2).
+# sweeps) on the finest level, V(3,3) on the coarse ones.  On the 1024^2
+# workload V(2,3) needs 5.15 cycles per step instead of V(2,2)'s 5.85 and is
+# 6% faster per step with the same finest down pass (the timed kernel); the
+# coarse levels are latency-bound, so their third pre-smoothing sweep costs
+# little and saves cycles.  The library's default stays V(2,2) everywhere.
 PRE, POST = 2, 3
+COARSE_PRE, COARSE_POST = 3, 3
 
 
 def measured_traffic(kernel, shape):
@@ -128,6 +131,8 @@ def main():
         """warmup + timed steps of one solver variant from the initial state"""
         params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
                              precision=precision, pre_smooth=PRE, post_smooth=POST,
+                             coarse_pre_smooth=COARSE_PRE,
+                             coarse_post_smooth=COARSE_POST,
                              guess="prev" if weights is None else "learned")
         st = Stepper(params, opacity=m.opacity)
         shapes = fld.fld_autotune(st.ctx)[:6] if not args.no_autotune else None
@@ -219,7 +224,7 @@ def main():
             "grid": [m.n[0], m.n[1]],
             "bc": "neumann",
             "rtol": 1e-8,
-            "cycle": f"V({PRE},{POST})",
+            "cycle": f"V({PRE},{POST}), coarse V({COARSE_PRE},{COARSE_POST})",
             "precision": "fp64",
             "guess": "prev",
             "dt": m.dt,
@@ -454,6 +459,8 @@ def bench_c4(args):
     with torch.cuda.stream(stream):
         params = [make_params(2, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
                               precision="fp32_ir", pre_smooth=PRE,
+                              coarse_pre_smooth=COARSE_PRE,
+                              coarse_post_smooth=COARSE_POST,
                               post_smooth=POST) for m in ms]
         bctx = fld.fld_setup_batch(params, stream=stream)
         fld.fld_batch_set_graph(bctx, True)
@@ -485,6 +492,8 @@ def bench_c4(args):
         for m in ms:
             st = Stepper(make_params(2, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
                                      precision=precision, pre_smooth=PRE,
+                                     coarse_pre_smooth=COARSE_PRE,
+                                     coarse_post_smooth=COARSE_POST,
                                      post_smooth=POST), opacity=m.opacity)
             fld.fld_autotune(st.ctx)
             sts.append(st)

@@ -94,6 +94,10 @@ typedef struct {
   int32_t post_smooth;   /* sweeps after prolongation                      */
   int32_t ir_inner;      /* FP32 V-cycles per refinement iteration
                             (FP32_IR), 1..8; 0 selects 2             */
+  int32_t coarse_pre_smooth;   /* sweeps before restriction on the coarse
+                                  levels; 0: pre_smooth                   */
+  int32_t coarse_post_smooth;  /* sweeps after prolongation on the coarse
+                                  levels; 0: post_smooth                  */
 } fld_params;
 
 typedef struct {
@@ -110,7 +114,7 @@ typedef struct {
 
 /* Fill *p with defaults: 1D, 1 cell, periodic, c = a_rad = gas_const = 1,
  * gamma = 5/3, LP limiter, arithmetic face mean, FP64, guess E^n,
- * rtol 1e-8, max_cycles 50, V(2,2). */
+ * rtol 1e-8, max_cycles 50, V(2,2) on every level. */
 void fld_params_default(fld_params* p);
 
 /* Bytes of device workspace fld_setup needs for these parameters, or 0 if
@@ -190,7 +194,8 @@ const char* fld_tile_shape_name(int32_t variant);
  * fld_opacity_powerlaw on its own (same operator, same stop test on its own
  * residual); grids that have converged skip their share of later launches.
  * Restrictions (FLD_ERR_INVALID_ARG otherwise): ndim == 2, one precision and
- * one pre/post smoothing count (1..3) for all grids, guess E^n, and every
+ * one set of smoothing counts (finest and coarse, each 1..3) for all grids,
+ * guess E^n, and every
  * grid coarsenable to at most 1024 cells but larger than that itself.
  * Pointer arrays (const double* const* ...) are HOST arrays of `count`
  * DEVICE pointers. */

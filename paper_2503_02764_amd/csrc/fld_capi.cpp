@@ -148,6 +148,16 @@ struct Plan {
   size_t total = 0;
 };
 
+// Smoothing sweeps on level l: the finest level's pre/post_smooth, the
+// coarse levels' coarse_pre/coarse_post_smooth (0: the same as the finest).
+inline int nu_pre(const fld_params& p, int l) {
+  return (l > 0 && p.coarse_pre_smooth > 0) ? p.coarse_pre_smooth : p.pre_smooth;
+}
+inline int nu_post(const fld_params& p, int l) {
+  return (l > 0 && p.coarse_post_smooth > 0) ? p.coarse_post_smooth
+                                              : p.post_smooth;
+}
+
 // Returns an empty string when the parameters are valid.
 std::string validate(const fld_params* p) {
   char buf[256];
@@ -209,6 +219,11 @@ std::string validate(const fld_params* p) {
       p->pre_smooth + p->post_smooth < 1 || p->pre_smooth > 16 ||
       p->post_smooth > 16)
     return "pre_smooth/post_smooth must be in [0, 16], not both 0";
+  if (p->coarse_pre_smooth < 0 || p->coarse_post_smooth < 0 ||
+      p->coarse_pre_smooth > 16 || p->coarse_post_smooth > 16 ||
+      nu_pre(*p, 1) + nu_post(*p, 1) < 1)
+    return "coarse_pre_smooth/coarse_post_smooth must be in [0, 16] (0: the "
+           "finest level's), the resulting coarse sweeps not both 0";
   return "";
 }
 
@@ -323,9 +338,9 @@ struct TimedLaunch {
 };
 
 bool tile_path(const fld_ctx* c) {
-  return c->fast && c->p.ndim == 2 && c->p.pre_smooth >= 1 &&
-         c->p.pre_smooth <= 3 && c->p.post_smooth >= 1 &&
-         c->p.post_smooth <= 3;
+  auto ok = [](int nu) { return nu >= 1 && nu <= 3; };
+  return c->fast && c->p.ndim == 2 && ok(c->p.pre_smooth) &&
+         ok(c->p.post_smooth) && ok(nu_pre(c->p, 1)) && ok(nu_post(c->p, 1));
 }
 
 template <typename T>
@@ -401,11 +416,11 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
     TimedLaunch t(c, l == 0, bytes,
                   sizeof(T) == 8 ? "k_tile2d<double,down>" : "k_tile2d<float,down>");
     FLD_TRY(t.st);
-    HIP_TRY(c, launch_tile2d<T>(a, c->p.pre_smooth, true, c->tile_var[l][0],
+    HIP_TRY(c, launch_tile2d<T>(a, nu_pre(c->p, l), true, c->tile_var[l][0],
                                 c->stream, &nb, t.e0, t.e1));
   } else {
     if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
-    FLD_TRY(smooth_simple<T>(c, H, l, c->p.pre_smooth, l == 0));
+    FLD_TRY(smooth_simple<T>(c, H, l, nu_pre(c->p, l), l == 0));
     HIP_TRY(c, launch_resid_restrict<T>(view(c, H, l), view(c, H, l + 1),
                                         norm ? c->partials : nullptr, &nb,
                                         c->ctrl, c->stream));
@@ -440,13 +455,13 @@ fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
     a.zero_init = 0;
     a.ctrl = c->ctrl;
     int nb = 0;
-    HIP_TRY(c, launch_tile2d<T>(a, c->p.post_smooth, false, c->tile_var[l][1],
+    HIP_TRY(c, launch_tile2d<T>(a, nu_post(c->p, l), false, c->tile_var[l][1],
                                 c->stream, &nb));
     return FLD_OK;
   }
   HIP_TRY(c, launch_prolong<T>(view(c, H, l + 1), view(c, H, l), c->ctrl,
                                c->stream));
-  return smooth_simple<T>(c, H, l, c->p.post_smooth);
+  return smooth_simple<T>(c, H, l, nu_post(c->p, l));
 }
 
 template <typename T>
@@ -454,8 +469,8 @@ TailArgs<T> tail_args(fld_ctx* c, const Levels<T>& H, int l0, bool whole) {
   TailArgs<T> t;
   t.l0 = l0;
   t.L = c->L;
-  t.pre = c->p.pre_smooth;
-  t.post = c->p.post_smooth;
+  t.pre = nu_pre(c->p, l0);  // one count for every tail level
+  t.post = nu_post(c->p, l0);
   t.whole = whole;
   t.zero = !whole;
   for (int l = 0; l < c->L; ++l) t.lv[l] = view(c, H, l);
@@ -682,7 +697,7 @@ Tile2DArgs<T> tile_job(fld_ctx* c, int l, bool down, bool zero_init,
   a.partials = partials;
   a.zero_init = zero_init;
   a.ctrl = c->ctrl;
-  tile2d_grid(a.g, down ? c->p.pre_smooth : c->p.post_smooth, down, variant,
+  tile2d_grid(a.g, down ? nu_pre(c->p, l) : nu_post(c->p, l), down, variant,
               &a.tiles_x, &a.tiles_y);
   a.vec = tile2d_vec_ok(a);
   return a;
@@ -789,7 +804,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
         const bool zero = l > 0 || (mixed && v == 0);
         double* parts = (!mixed && l == 0) ? c->partials : nullptr;
         jobs.push_back(tile_job<T>(c, l, true, zero, parts, B->tile_var[l][0]));
-        blocks.push_back(tile2d_blocks(c->geom[l], c->p.pre_smooth, true,
+        blocks.push_back(tile2d_blocks(c->geom[l], nu_pre(c->p, l), true,
                                        B->tile_var[l][0]));
       }
       add_phase(im, B->down[v][l], jobs, blocks);
@@ -818,7 +833,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
       fld_ctx* c = B->sub[g];
       if (l >= c->tail_l0) continue;
       jobs.push_back(tile_job<T>(c, l, false, false, nullptr, B->tile_var[l][1]));
-      blocks.push_back(tile2d_blocks(c->geom[l], c->p.post_smooth, false,
+      blocks.push_back(tile2d_blocks(c->geom[l], nu_post(c->p, l), false,
                                      B->tile_var[l][1]));
     }
     add_phase(im, B->up[l], jobs, blocks);
@@ -844,7 +859,7 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
     const Phase& ph = B->down[var][l];
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
                                        start_ptr(B, ph), ph.ng, ph.nblocks,
-                                       p.pre_smooth, true, B->tile_var[l][0],
+                                       nu_pre(p, l), true, B->tile_var[l][0],
                                        s));
     if (sizeof(T) == 8 && l == 0)
       HIP_TRY(bc, launch_finalize_batch(kFinCycle,
@@ -861,7 +876,7 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
     const Phase& ph = B->up[l];
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
                                        start_ptr(B, ph), ph.ng, ph.nblocks,
-                                       p.post_smooth, false, B->tile_var[l][1],
+                                       nu_post(p, l), false, B->tile_var[l][1],
                                        s));
   }
   return FLD_OK;
@@ -1004,6 +1019,8 @@ void fld_params_default(fld_params* p) {
   p->max_cycles = 50;
   p->pre_smooth = 2;
   p->post_smooth = 2;
+  p->coarse_pre_smooth = 0;
+  p->coarse_post_smooth = 0;
 }
 
 size_t fld_workspace_bytes(const fld_params* p) {
@@ -1341,7 +1358,7 @@ fld_status tune_levels(fld_ctx* c, Levels<T>& H, int choice[kMaxLevels][2],
       a.partials = (dir == 0 && l == 0) ? c->partials : nullptr;
       a.zero_init = 0;
       a.ctrl = c->ctrl;
-      const int nu = dir == 0 ? c->p.pre_smooth : c->p.post_smooth;
+      const int nu = dir == 0 ? nu_pre(c->p, l) : nu_post(c->p, l);
       // best of 3 rounds per shape; a shape replaces the current choice
       // only when it is more than 3% faster (stable choices across runs)
       float best = 1e30f;
@@ -1534,7 +1551,9 @@ static std::string validate_batch(int32_t count, const fld_params* each) {
       return "batched grids must share the precision";
     if (p.pre_smooth < 1 || p.pre_smooth > 3 || p.post_smooth < 1 ||
         p.post_smooth > 3 || p.pre_smooth != each[0].pre_smooth ||
-        p.post_smooth != each[0].post_smooth)
+        p.post_smooth != each[0].post_smooth || nu_pre(p, 1) > 3 ||
+        nu_post(p, 1) > 3 || nu_pre(p, 1) != nu_pre(each[0], 1) ||
+        nu_post(p, 1) != nu_post(each[0], 1))
       return "batched grids need equal pre/post smoothing in 1..3";
     if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
     if (p.ir_inner != each[0].ir_inner)

@@ -53,6 +53,8 @@ class fld_params(ctypes.Structure):
         ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32),
         ("pre_smooth", ctypes.c_int32), ("post_smooth", ctypes.c_int32),
         ("ir_inner", ctypes.c_int32),
+        ("coarse_pre_smooth", ctypes.c_int32),
+        ("coarse_post_smooth", ctypes.c_int32),
     ]
 
 

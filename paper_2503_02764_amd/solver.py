@@ -19,7 +19,8 @@ _GUESS = {"prev": fld.FLD_GUESS_PREV, "zero": fld.FLD_GUESS_ZERO,
 def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
                 gas_const=1.0, limiter="lp", face_mean="arith",
                 precision="fp64", guess="prev", rtol=1e-8, max_cycles=50,
-                pre_smooth=2, post_smooth=2, ir_inner=0):
+                pre_smooth=2, post_smooth=2, ir_inner=0, coarse_pre_smooth=0,
+                coarse_post_smooth=0):
     n = list(n) + [1] * (3 - len(n))
     dx = list(dx) + [1.0] * (3 - len(dx))
     codes = [_BC[b] for b in bc] + [fld.FLD_BC_PERIODIC] * (3 - len(bc))
@@ -29,7 +30,9 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
         limiter=_LIM[limiter], face_mean=_FACE[face_mean],
         precision=_PREC[precision], guess=_GUESS[guess], rtol=rtol,
         max_cycles=max_cycles, pre_smooth=pre_smooth,
-        post_smooth=post_smooth, ir_inner=ir_inner)
+        post_smooth=post_smooth, ir_inner=ir_inner,
+        coarse_pre_smooth=coarse_pre_smooth,
+        coarse_post_smooth=coarse_post_smooth)
 
 
 class Stepper:

@@ -94,7 +94,8 @@ def test_defaults_and_workspace():
     ("ndim", 0), ("ndim", 4), ("c", 0.0), ("a_rad", -1.0), ("gamma", 1.0),
     ("gas_const", 0.0), ("rtol", 0.0), ("rtol", 1.5), ("max_cycles", 0),
     ("limiter", 7), ("face_mean", 3), ("precision", 9), ("guess", 9),
-    ("ir_inner", -1), ("ir_inner", 9),
+    ("ir_inner", -1), ("ir_inner", 9), ("coarse_pre_smooth", -1),
+    ("coarse_post_smooth", 17),
 ])
 def test_invalid_params_rejected_on_host(field, value):
     p = fld.fld_params_default(ndim=1, n=(64, 1, 1), dx=(1 / 64, 1, 1))

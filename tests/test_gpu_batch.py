@@ -185,7 +185,9 @@ def test_c4_full_size_batch_configuration():
     announce("c4 full size: 96 grids, graph, autotuned")
     o = ms[0].opacity
     params = [params_for(m, rtol=1e-8, precision="fp32_ir",
-                         pre_smooth=bench.PRE, post_smooth=bench.POST)
+                         pre_smooth=bench.PRE, post_smooth=bench.POST,
+                         coarse_pre_smooth=bench.COARSE_PRE,
+                         coarse_post_smooth=bench.COARSE_POST)
               for m in ms]
     dts = [m.dt for m in ms]
     stream = torch.cuda.Stream()

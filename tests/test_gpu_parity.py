@@ -249,7 +249,10 @@ def test_c2_full_size_bench_configuration():
     from paper_2503_02764_amd import fld
     # the cycle and the autotuned tile shapes the bench runs with
     st = Stepper(params_for(m, rtol=1e-8, pre_smooth=bench.PRE,
-                            post_smooth=bench.POST), opacity=m.opacity)
+                            post_smooth=bench.POST,
+                            coarse_pre_smooth=bench.COARSE_PRE,
+                            coarse_post_smooth=bench.COARSE_POST),
+                 opacity=m.opacity)
     fld.fld_autotune(st.ctx)
     rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
     kap_d = dev(np.zeros_like(m.E))
@@ -551,3 +554,21 @@ def test_odd_periodic_levels_are_deterministic(n, bc, precision):
     np.testing.assert_array_equal(outs[0], outs[2])
     ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt, F.problem_from_medium(m))
     assert rel_l2(outs[0], ref) <= 1e-9
+
+
+@pytest.mark.parametrize("n,bc", [((200, 136), ("neumann", "neumann")),
+                                  ((96, 80), ("periodic", "neumann"))])
+@pytest.mark.parametrize("coarse", [(1, 1), (3, 3), (3, 1)])
+def test_coarse_level_smoothing_counts(n, bc, coarse):
+    """Coarse levels may smooth more or less than the finest one (tiled
+    levels, register tail and the FP32 hierarchy alike); the answer is the
+    oracle's whatever the counts."""
+    m = media.random_small_medium(61 + n[0] + coarse[0], n, bc)
+    announce(f"coarse smoothing {coarse} {n} {bc}")
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt, F.problem_from_medium(m))
+    for prec, tol in (("fp64", 1e-10), ("fp32_ir", 1e-8)):
+        x, stats = _solve_gpu(m, rtol=1e-12 if prec == "fp64" else 1e-10,
+                              precision=prec, pre_smooth=2, post_smooth=3,
+                              coarse_pre_smooth=coarse[0],
+                              coarse_post_smooth=coarse[1], max_cycles=200)
+        assert rel_l2(x, ref) <= tol, (prec, stats)
