@@ -33,6 +33,13 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
 # little and saves cycles.  The library's default stays V(2,2) everywhere.
 PRE, POST = 2, 3
 COARSE_PRE, COARSE_POST = 3, 3
+# V-cycle of the 3D workload: V(1,2) on the finest level, V(4,4) on the
+# coarse ones.  On the 256^3 stratified medium (face alpha spanning ~8
+# decades) the coarse levels need the extra sweeps: 7.6 V-cycles per step
+# instead of V(2,2)'s 11.6, and the cheaper finest level pays for them
+# (FP64 14.4 instead of 22.8 ms per step; V(2,2) with coarse V(3,3) 15.8).
+PRE3, POST3 = 1, 2
+COARSE_PRE3, COARSE_POST3 = 4, 4
 
 
 def measured_traffic(kernel, shape):
@@ -378,7 +385,9 @@ def bench_c3(args):
         # about 50-60 V-cycles per step with rediscretised coarse operators
         params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
                              guess="prev" if weights is None else "learned",
-                             max_cycles=300)
+                             max_cycles=300, pre_smooth=PRE3,
+                             post_smooth=POST3, coarse_pre_smooth=COARSE_PRE3,
+                             coarse_post_smooth=COARSE_POST3)
         st = Stepper(params, opacity=m.opacity)
         if weights is not None:
             fld.fld_set_model(st.ctx, weights)
@@ -425,6 +434,7 @@ def bench_c3(args):
           "3d-256cube-stratified-kramers-fp32-vcycles-fp64-refinement", "f32",
           {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
                         "learned_guess_fp32_vcycles": lrn},
+           "cycle": f"V({PRE3},{POST3}), coarse V({COARSE_PRE3},{COARSE_POST3})",
            "roofline": f32["roofline"],
            "step_model_roofline": f32["step_model_roofline"],
            "achievable_copy": copy_bandwidth()})

@@ -279,8 +279,8 @@ def test_c2_full_size_bench_configuration():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_c3_full_size_bench_configuration(precision):
-    """256^3 stratified medium in the bench's configuration (V(2,2), rtol
-    1e-8): the oracle assembles its own operator from the same inputs and
+    """256^3 stratified medium in the bench's configuration (its V-cycle,
+    rtol 1e-8): the oracle assembles its own operator from the same inputs and
     measures the GPU iterate's residual.  A has every eigenvalue >= 1, so
     |x - A^-1 b| <= |b - A x|: a relative residual of 1e-8 bounds the error
     against the exact solve as well.  The exchange is checked on sampled
@@ -291,8 +291,12 @@ def test_c3_full_size_bench_configuration(precision):
     prob = F.problem_from_medium(m)
     kap = F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
     announce(f"c3 full size 256^3 {precision}")
+    import bench
     params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
-                         max_cycles=300)
+                         max_cycles=300, pre_smooth=bench.PRE3,
+                         post_smooth=bench.POST3,
+                         coarse_pre_smooth=bench.COARSE_PRE3,
+                         coarse_post_smooth=bench.COARSE_POST3)
     ctx = fld.fld_setup(params)
     rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
     kap_d = dev(np.zeros_like(m.E))
