@@ -25,13 +25,14 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
           "plain FP64 MG")
 
 
-# V-cycle of the 2D workloads: V(2,3) (two pre-, three post-smoothing
-# sweeps) on the finest level, V(3,3) on the coarse ones.  On the 1024^2
-# workload V(2,3) needs 5.15 cycles per step instead of V(2,2)'s 5.85 and is
-# 6% faster per step with the same finest down pass (the timed kernel); the
-# coarse levels are latency-bound, so their third pre-smoothing sweep costs
-# little and saves cycles.  The library's default stays V(2,2) everywhere.
-PRE, POST = 2, 3
+# V-cycle of the 2D workloads: V(1,1) on the finest level, V(3,3) on the
+# coarse ones.  The coarse levels are latency-bound, so three sweeps there
+# cost little; with them the 1024^2 workload needs 5.05 cycles per step
+# whatever the finest level's counts (V(1,1) to V(3,3)), and V(1,1) makes
+# the finest passes cheapest (6% less time per step than V(2,3) with the same
+# coarse levels; V(2,3) everywhere needed 5.15 cycles, V(2,2) everywhere
+# 5.85).  The library's default stays V(2,2) everywhere.
+PRE, POST = 1, 1
 COARSE_PRE, COARSE_POST = 3, 3
 # V-cycle of the 3D workload: V(1,2) on the finest level, V(4,4) on the
 # coarse ones.  On the 256^3 stratified medium (face alpha spanning ~8
