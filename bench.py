@@ -43,8 +43,9 @@ PRE3, POST3 = 1, 2
 COARSE_PRE3, COARSE_POST3 = 4, 4
 
 
-def measured_traffic(kernel, shape):
-    """HBM bytes per launch of `kernel` in tile shape `shape`, or None.
+def measured_traffic(kernel, shape, nu=None):
+    """HBM bytes per launch of `kernel` in tile shape `shape` (and, when the
+    record states it, smoothing sweep count `nu`), or None.
 
     profiles/*.md carry `traffic_record:` lines, one per tile shape, written
     from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, scaled by a
@@ -61,6 +62,8 @@ def measured_traffic(kernel, shape):
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if kv.get("kernel") != kernel or kv.get("shape") != shape:
+                continue
+            if nu is not None and "nu" in kv and int(kv["nu"]) != nu:
                 continue
             src = os.path.join(ROOT, kv["source"])
             sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -279,7 +282,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kt["kernel"], level0_down),
+            "traffic": measured_traffic(kt["kernel"], level0_down, PRE),
             "tile_shape": level0_down,
             "avg_launch_us": avg_ms * 1e3,
             "algorithmic_bytes_per_launch": bytes_per_launch,
