@@ -89,6 +89,8 @@ struct fld_ctx {
   bool fast = true;  // tiled kernels + single-workgroup tail
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
   bool coarsen_multi = true;  // 2D: several coarse levels per launch
+  bool sweep3d = true;        // 3D: fused red-black sweeps where planned
+  int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
   // learned guess: network carved out of net_ws by fld_set_model
@@ -131,6 +133,17 @@ fld_status fail(fld_ctx* ctx, fld_status st, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxCoarsestCells = 1 << 16;
+// 3D levels of at least this many cells smooth by fused sweeps (smaller
+// ones are launch-latency bound, where a block's march through its planes
+// costs more than the second colour launch)
+constexpr int64_t kSweepMinCells = 1 << 22;
+
+// FLD_SWEEP3D set to a number > 1 (planes per block) also takes fused sweeps
+// on the smaller levels (tests on small grids)
+int64_t sweep_min_cells() {
+  const char* sw = getenv("FLD_SWEEP3D");
+  return (sw && atoi(sw) > 1) ? 0 : kSweepMinCells;
+}
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -269,6 +282,10 @@ void make_plan(const fld_params* p, Plan* P) {
       P->b32[l] = take(cells * 4);
     }
     if (nd == 2 && l + 1 < P->L) P->alt[l] = take(cells * (mixed ? 4 : 8));
+    // 3D: out-of-place buffer of the fused red-black sweep
+    if (nd == 3 && l + 1 < P->L && (int64_t)cells >= sweep_min_cells() &&
+        gs_sweep3d_ok(P->g[l]))
+      P->alt[l] = take(cells * (mixed ? 4 : 8));
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   if (nd == 3) P->dscr = take((size_t)P->g[0].N * 8);
@@ -309,10 +326,15 @@ LevelView<T> view(const fld_ctx* c, const Levels<T>& H, int l) {
   return v;
 }
 
+// The timing events only timestamp launches; their intervals are read after
+// the step's stream synchronisation, so they skip the system-scope cache
+// writeback a default event performs when it completes (that writeback cost
+// about 6.5 us per timed launch and slowed the work after it).
 hipEvent_t next_event(fld_ctx* c) {
   if (c->ev_used == c->ev.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+      return nullptr;
     c->ev.push_back(e);
   }
   return c->ev[c->ev_used++];
@@ -358,25 +380,54 @@ fld_status fill_zero<float>(fld_ctx* c, float* x, int64_t n) {
   return FLD_OK;
 }
 
-// Simple path: one launch per colour pass.  With `timed` (the finest
-// level's pre-smoothing in 3D), the first colour pass records its own
-// duration for the kernel timing: it updates half the cells, reading b of
-// those, all three face arrays and the iterate, and writing its half, i.e.
-// 4.5 N elements per pass touched once.
+// Whether level l smooths by fused 3D sweeps (it has the alternate buffer
+// and some pre or post count of at least two).
+template <typename T>
+bool fused_level(const fld_ctx* c, const Levels<T>& H, int l) {
+  return c->sweep3d && c->geom[l].ndim == 3 && H.alt[l] &&
+         gs_sweep3d_ok(c->geom[l]) &&
+         (nu_pre(c->p, l) >= 2 || nu_post(c->p, l) >= 2);
+}
+
+// Simple path: one launch per colour pass, or, on a 3D level with an
+// alternate buffer, pairs of fused red-black sweeps (x -> alt -> x) after
+// one sweep of colour passes when the count is odd.  With `timed` (the
+// finest level's smoothing in 3D), the first fused launch of the call
+// records its own duration for the kernel timing, or, on a level without
+// fused sweeps, the first colour pass of the pre-smoothing.  A colour pass
+// updates half the cells, reading b of those, all three face arrays and the
+// iterate, and writing its half: 4.5 N elements touched once; a fused sweep
+// reads b, the three face arrays and the iterate and writes the whole
+// iterate: 6 N.
 template <typename T>
 fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
-                         bool timed = false) {
+                         bool timed_fused, bool timed_colour) {
   LevelView<T> v = view(c, H, l);
-  for (int s = 0; s < sweeps; ++s)
+  T* alt = H.alt[l];
+  const bool fused = fused_level(c, H, l);
+  const int pairs = fused ? sweeps / 2 : 0;
+  const int plain = sweeps - 2 * pairs;
+  for (int s = 0; s < plain; ++s)
     for (int color = 0; color < gs_colors(v.g); ++color) {
-      const bool t = timed && s == 0 && color == 0 && v.g.ndim == 3;
-      TimedLaunch tl(c, t, 4.5 * (double)v.g.N * sizeof(T),
+      TimedLaunch tl(c, timed_colour && !fused && s == 0 && color == 0,
+                     4.5 * (double)v.g.N * sizeof(T),
                      sizeof(T) == 8 ? "k_gs_color_3d<double>"
                                     : "k_gs_color_3d<float>");
       FLD_TRY(tl.st);
       HIP_TRY(c, launch_gs_color<T>(v, color, c->ctrl, c->stream, tl.e0,
                                     tl.e1));
     }
+  LevelView<T> va = v;
+  va.x = alt;
+  for (int s = 0; s < pairs; ++s) {
+    TimedLaunch tl(c, timed_fused && s == 0, 6.0 * (double)v.g.N * sizeof(T),
+                   sizeof(T) == 8 ? "k_gs_sweep_3d<double>"
+                                  : "k_gs_sweep_3d<float>");
+    FLD_TRY(tl.st);
+    HIP_TRY(c, launch_gs_sweep3d<T>(v, alt, c->sweep_zc, c->ctrl, c->stream,
+                                    tl.e0, tl.e1));
+    HIP_TRY(c, launch_gs_sweep3d<T>(va, v.x, c->sweep_zc, c->ctrl, c->stream));
+  }
   return FLD_OK;
 }
 
@@ -420,7 +471,12 @@ fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
                                 c->stream, &nb, t.e0, t.e1));
   } else {
     if (zero_init && l == 0) FLD_TRY(fill_zero<T>(c, H.x[0], c->geom[0].N));
-    FLD_TRY(smooth_simple<T>(c, H, l, nu_pre(c->p, l), l == 0));
+    // level 0 of a 3D solve times one launch per V-cycle: the first fused
+    // sweep (pre-smoothing if it has one, else post), or the first colour
+    // pass of the pre-smoothing on a level without fused sweeps
+    const bool t0 = l == 0 && c->geom[0].ndim == 3;
+    FLD_TRY(smooth_simple<T>(c, H, l, nu_pre(c->p, l),
+                             t0 && nu_pre(c->p, l) >= 2, t0));
     HIP_TRY(c, launch_resid_restrict<T>(view(c, H, l), view(c, H, l + 1),
                                         norm ? c->partials : nullptr, &nb,
                                         c->ctrl, c->stream));
@@ -461,7 +517,8 @@ fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
   }
   HIP_TRY(c, launch_prolong<T>(view(c, H, l + 1), view(c, H, l), c->ctrl,
                                c->stream));
-  return smooth_simple<T>(c, H, l, nu_post(c->p, l));
+  const bool t0 = l == 0 && c->geom[0].ndim == 3 && nu_pre(c->p, l) < 2;
+  return smooth_simple<T>(c, H, l, nu_post(c->p, l), t0, false);
 }
 
 template <typename T>
@@ -1080,6 +1137,14 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   c->fast = !(path && strcmp(path, "simple") == 0);
   // one coarsening launch per level (tests that both forms agree bitwise)
   c->coarsen_multi = c->fast && !getenv("FLD_COARSEN_PER_LEVEL");
+  // 3D smoothing by colour passes only ("0"; tests that both forms agree),
+  // or fused sweeps with a fixed number of z planes per block (a number > 1)
+  if (const char* sw = getenv("FLD_SWEEP3D")) {
+    const int v = atoi(sw);
+    c->sweep3d = v != 0;
+    if (v > 1) c->sweep_zc = v;
+  }
+  c->sweep3d = c->sweep3d && c->fast;
   // fixed tile shape for every level (tests of shape independence)
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {
     const int v = atoi(tv);

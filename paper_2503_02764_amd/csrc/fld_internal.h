@@ -86,6 +86,15 @@ hipError_t launch_resid_to32(const LevelView<double>& L, float* r32,
 hipError_t launch_correct(int64_t N, double* x, const float* e,
                           const Control* ctrl, hipStream_t s);
 
+// Fused red-black sweep of a 3D level, out of place: xo = one Gauss-Seidel
+// sweep (red, then black) of L.x.  Levels of nx % 64 == 0, ny % 16 == 0 and
+// two colours; zc = z planes per block (0: chosen from the shape).
+bool gs_sweep3d_ok(const Geom& g);
+template <typename T>
+hipError_t launch_gs_sweep3d(const LevelView<T>& L, T* xo, int zc,
+                             const Control* ctrl, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 template <typename T>
 hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
                           const T* const fa[3], T* const ca[3], hipStream_t s);
