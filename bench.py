@@ -34,13 +34,15 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
 # 5.85).  The library's default stays V(2,2) everywhere.
 PRE, POST = 1, 1
 COARSE_PRE, COARSE_POST = 3, 3
-# V-cycle of the 3D workload: V(1,2) on the finest level, V(4,4) on the
-# coarse ones.  On the 256^3 stratified medium (face alpha spanning ~8
-# decades) the coarse levels need the extra sweeps: 7.6 V-cycles per step
-# instead of V(2,2)'s 11.6, and the cheaper finest level pays for them
-# (FP64 14.4 instead of 22.8 ms per step; V(2,2) with coarse V(3,3) 15.8).
-PRE3, POST3 = 1, 2
-COARSE_PRE3, COARSE_POST3 = 4, 4
+# V-cycle of the 3D workload: V(2,2) on the finest level (two fused
+# one-launch sweeps), V(3,3) on the coarse ones.  On the 256^3 stratified
+# medium (face alpha spanning ~8 decades) the coarse levels need the extra
+# sweeps: 7.2-7.6 V-cycles per step instead of 11.6 with V(2,2) everywhere.
+# Against V(1,2) with coarse V(4,4) (one sweep of colour passes and one
+# fused pair on the finest level): FP64 12.7 instead of 12.9 ms per step,
+# FP32 refinement 10.6 instead of 11.3.
+PRE3, POST3 = 2, 2
+COARSE_PRE3, COARSE_POST3 = 3, 3
 
 
 def measured_traffic(kernel, shape, nu=None):
