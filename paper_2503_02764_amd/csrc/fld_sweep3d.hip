@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kSwT)
 
 // z planes per block: the blocks of one launch fill the chip once, one per
 // CU (on 256^3, 64 planes: FP64 206 us per sweep against 226 with 32, FP32
-// 134 against 140; a second round of blocks costs more than the two extra
+// 134 against 140; a second wave of blocks costs more than the two extra
 // planes a block redoes at each end of its chunk).
 template <typename T>
 int sw_zchunk(const Geom& g) {
