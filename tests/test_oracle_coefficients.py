@@ -143,3 +143,84 @@ def test_face_means_order_and_walls():
     # wall faces carry no flux
     assert np.all(aa[0][:, -1] == 0) and np.all(aa[1][-1, :] == 0)
     del n
+
+
+# ---------------------------------------------------------------------------
+# Hand-computed face coefficients (distinct D on every face)
+#
+# With the diffusion limiter (lambda = 1/3), rho = 1 and c = 3 the cell
+# value is D = c lambda / (rho kappa) = 1 / kappa (eq. fld_F), so kappa
+# fixes D exactly.  alpha_d = dt D_face / dx_d^2 on the face between a cell
+# and its upper neighbour along d; a Neumann wall face carries 0.
+#   arithmetic mean:  (D_L + D_R) / 2
+#   harmonic mean:    2 D_L D_R / (D_L + D_R)
+# Every expected value below was worked out by hand from those two lines.
+# ---------------------------------------------------------------------------
+
+def _hand_problem(n, bc, dx, face_mean):
+    ndim = len(n)
+    return F.Problem(ndim=ndim, n=tuple(list(n) + [1] * (3 - ndim)),
+                     dx=tuple(list(dx) + [1.0] * (3 - ndim)), bc=tuple(bc),
+                     c=3.0, limiter="diffusion", face_mean=face_mean)
+
+
+@pytest.mark.parametrize("face_mean,expect_neu,expect_per", [
+    # D = (1, 1/2, 1/4), dt / dx^2 = 1
+    ("arith", [0.75, 0.375, 0.0], [0.75, 0.375, 0.625]),
+    ("harmonic", [2.0 / 3.0, 1.0 / 3.0, 0.0], [2.0 / 3.0, 1.0 / 3.0, 0.4]),
+])
+def test_face_means_hand_values_1d(face_mean, expect_neu, expect_per):
+    kap = np.array([1.0, 2.0, 4.0])
+    rho = np.ones(3)
+    E = np.array([1.0, 3.0, 2.0])  # any positive E: lambda = 1/3 here
+    for bc, expect in (("neumann", expect_neu), ("periodic", expect_per)):
+        prob = _hand_problem((3,), [bc], (0.5,), face_mean)
+        a = F.face_coefficients(E, rho, kap, 0.25, prob)[0]
+        np.testing.assert_allclose(a, expect, rtol=1e-15, atol=0)
+
+
+def test_operator_entries_hand_values_1d():
+    """A = I + sum_faces alpha (difference)^T (difference), written out for
+    the Neumann case above (arithmetic mean): alpha = (0.75, 0.375, wall)."""
+    kap = np.array([1.0, 2.0, 4.0])
+    prob = _hand_problem((3,), ["neumann"], (0.5,), "arith")
+    al = F.face_coefficients(np.ones(3), np.ones(3), kap, 0.25, prob)
+    A = F.assemble(al, prob).toarray()
+    expect = np.array([[1.75, -0.75, 0.0],
+                       [-0.75, 2.125, -0.375],
+                       [0.0, -0.375, 1.375]])
+    np.testing.assert_allclose(A, expect, rtol=1e-15, atol=0)
+    v = np.array([2.0, -1.0, 0.5])
+    # A v by hand: 1.75*2 + 0.75 = 4.25; -1.5 - 2.125 - 0.1875 = -3.8125;
+    # 0.375 + 0.6875 = 1.0625
+    np.testing.assert_allclose(F.apply_operator(v, al, prob),
+                               [4.25, -3.8125, 1.0625], rtol=1e-15)
+    # and the periodic case couples cell 2 to cell 0 through 0.625
+    pp = _hand_problem((3,), ["periodic"], (0.5,), "arith")
+    Ap = F.assemble(F.face_coefficients(np.ones(3), np.ones(3), kap, 0.25,
+                                        pp), pp).toarray()
+    np.testing.assert_allclose(Ap, [[2.375, -0.75, -0.625],
+                                    [-0.75, 2.125, -0.375],
+                                    [-0.625, -0.375, 2.0]], rtol=1e-15)
+
+
+@pytest.mark.parametrize("face_mean,ax_expect,ay_expect", [
+    ("arith",
+     [[0.75, 0.375, 0.0], [0.375, 0.1875, 0.0]],
+     [[3.0, 1.5, 0.75], [0.0, 0.0, 0.0]]),
+    ("harmonic",
+     [[2.0 / 3.0, 1.0 / 3.0, 0.0], [1.0 / 3.0, 1.0 / 6.0, 0.0]],
+     [[8.0 / 3.0, 4.0 / 3.0, 2.0 / 3.0], [0.0, 0.0, 0.0]]),
+])
+def test_face_means_hand_values_2d(face_mean, ax_expect, ay_expect):
+    """nx = 3, ny = 2, Neumann; kappa rows (1, 2, 4) and (2, 4, 8), so
+    D rows (1, 1/2, 1/4) and (1/2, 1/4, 1/8); dx = 0.5, dy = 0.25, dt = 0.25:
+    dt/dx^2 = 1 along x, dt/dy^2 = 4 along y (a swapped axis or spacing
+    changes every entry)."""
+    kap = np.array([[1.0, 2.0, 4.0], [2.0, 4.0, 8.0]])
+    prob = _hand_problem((3, 2), ["neumann", "neumann"], (0.5, 0.25),
+                         face_mean)
+    ax, ay = F.face_coefficients(np.ones((2, 3)), np.ones((2, 3)), kap, 0.25,
+                                 prob)
+    np.testing.assert_allclose(ax, ax_expect, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(ay, ay_expect, rtol=1e-15, atol=0)

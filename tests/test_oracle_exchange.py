@@ -142,3 +142,40 @@ def test_quartic_root_vs_numpy_roots():
         assert abs(pos[0] - x[i]) <= 1e-13 * x[i]
     # a4 = 0 reduces to the linear root exactly
     assert F.quartic_root(0.0, 3.0, 6.0) == 2.0
+
+
+# ---------------------------------------------------------------------------
+# Gas temperature and the workload opacity law, against hand-computed values
+# ---------------------------------------------------------------------------
+
+def test_temperature_hand_values():
+    """T = p / (rho R_g) with p = (gamma - 1) e (eqs. ideal_gas_law and
+    energy_density with v = B = 0): gamma = 1.4, R_g = 0.5, rho = 2, e = 3
+    gives p = 1.2 and T = 1.2 / 1 = 1.2; gamma = 5/3, R_g = 1, rho = 0.5,
+    e = 1.5 gives p = 1 and T = 2."""
+    p1 = F.Problem(ndim=1, n=(1, 1, 1), dx=(1.0, 1.0, 1.0),
+                   bc=("periodic",), gamma=1.4, gas_const=0.5)
+    assert F.temperature(np.array(3.0), np.array(2.0), p1) == \
+        pytest.approx(1.2, rel=1e-15)
+    p2 = F.Problem(ndim=1, n=(1, 1, 1), dx=(1.0, 1.0, 1.0),
+                   bc=("periodic",))
+    assert F.temperature(np.array(1.5), np.array(0.5), p2) == \
+        pytest.approx(2.0, rel=1e-15)
+
+
+def test_opacity_powerlaw_hand_values():
+    """kappa = clip(1e2 rho T^-3.5, 1e-2, 1e6), gamma = 5/3, R_g = 1, so
+    T = (2/3) e / rho:
+      rho = 0.5,  e = 1.5:    T = 2,    kappa = 50 / (8 sqrt 2) = 4.41941738...
+      rho = 2,    e = 3:      T = 1,    kappa = 200
+      rho = 1,    e = 0.015:  T = 0.01, 100 * 1e7 = 1e9 -> clipped to 1e6
+      rho = 1e-3, e = 3e-3:   T = 2,    0.1 / (8 sqrt 2) = 8.84e-3 -> 1e-2
+    (2^-3.5 = 1 / (8 sqrt 2))."""
+    prob = F.Problem(ndim=1, n=(4, 1, 1), dx=(1.0, 1.0, 1.0),
+                     bc=("periodic",))
+    rho = np.array([0.5, 2.0, 1.0, 1e-3])
+    e = np.array([1.5, 3.0, 0.015, 3e-3])
+    kap = F.opacity_powerlaw(rho, e, prob, k0=1e2, a=1.0, b=-3.5, kmin=1e-2,
+                             kmax=1e6)
+    np.testing.assert_allclose(
+        kap, [50.0 / (8.0 * np.sqrt(2.0)), 200.0, 1e6, 1e-2], rtol=1e-14)

@@ -156,3 +156,39 @@ def test_energy_loss_gradient_vs_finite_differences():
         df[i] = old
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g.reshape(-1)[i]) <= 1e-6 * max(abs(fd), 1e-3), i
+
+
+def test_adam_three_steps_hand_values():
+    """Adam (Kingma & Ba, Algorithm 1) on one scalar parameter, p0 = 1,
+    lr = 0.1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8, gradients 0.5, -0.25, 2:
+      t=1: m = 0.05,  v = 2.5e-4,      m^ = 0.5,      v^ = 0.25,
+           p = 1 - 0.1 * 0.5 / (0.5 + 1e-8)              = 0.90000000199999996
+      t=2: m = 0.02,  v = 3.1225e-4,   m^ = 0.02/0.19, v^ = 3.1225e-4/1.999e-3,
+           p                                             = 0.87336629870784616
+      t=3: m = 0.218, v = 4.31193775e-3, m^ = 0.218/0.271,
+           v^ = 4.31193775e-3 / 2.997001e-3,  p          = 0.80630153452915290
+    (worked to 30 digits; without the bias correction the first step alone
+    gives 0.6838)."""
+    p = {"w": np.array([1.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    expect = [0.90000000199999996, 0.87336629870784616, 0.80630153452915290]
+    for t, (g, want) in enumerate(zip([0.5, -0.25, 2.0], expect), start=1):
+        U.adam_step(p, {"w": np.array([g])}, m, v, t, lr=0.1)
+        assert p["w"][0] == pytest.approx(want, rel=1e-14), t
+    assert m["w"][0] == pytest.approx(0.218, rel=1e-14)
+    assert v["w"][0] == pytest.approx(4.31193775e-3, rel=1e-14)
+
+
+def test_features_hand_values():
+    """Network inputs on a 1 x 2 image with E = (1, e^2) (log E = 0, 2, mean
+    1), rho kappa dx = (e^4, e^-8), alpha_x = (e^8 - 1, 0),
+    alpha_y = (0, e^4 - 1): features (-1, 1) / (1, -2) / (2, 0) / (0, 1)."""
+    E = np.exp(np.array([[0.0, 2.0]]))
+    f = U.features(E, np.exp(np.array([[4.0, -8.0]])),
+                   np.array([[np.expm1(8.0), 0.0]]),
+                   np.array([[0.0, np.expm1(4.0)]]))
+    assert f.shape == (1, 1, 2, 4)
+    np.testing.assert_allclose(f[0, 0], [[-1.0, 1.0, 2.0, 0.0],
+                                         [1.0, -2.0, 0.0, 1.0]],
+                               rtol=1e-14, atol=1e-15)
