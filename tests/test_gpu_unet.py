@@ -10,8 +10,11 @@ stored value, accumulated over 15 layers): forward rel-L2 <= 1e-2, loss
 of every layer to BF16 before its two GEMMs, so the error grows with the
 number of layers crossed (measured: 0.8% at the last decoder level, 2.5% at
 the bottleneck); it is largest on the first layer's weights (3.5%), whose
-sums over zero-mean inputs cancel.  Bar: rel-L2 <= 5e-2 for every
-parameter tensor and <= 2.5e-2 on average.
+sums over zero-mean inputs cancel.  The stored activations that feed every
+weight gradient are BF16 as well (the forward pass differs from the FP64
+reference by about 1e-2), so no tensor can be held much below that.
+Bar: rel-L2 <= 2e-2 averaged over the parameter tensors, <= 4e-2 for every
+tensor.
 
 The solver side: the features fld_step feeds the network match the
 oracle's coefficients to FP32 rounding, and a step with the learned guess
@@ -105,8 +108,8 @@ def test_gradients_vs_oracle():
     errs = {name: rel_l2(g[a:b].reshape(shape), g_ref[name])
             for name, (a, b, shape) in _slices().items()}
     print("gradient rel-L2 per parameter:", errs)
-    assert max(errs.values()) <= 5e-2, errs
-    assert np.mean(list(errs.values())) <= 2.5e-2, errs
+    assert max(errs.values()) <= 4e-2, errs
+    assert np.mean(list(errs.values())) <= 2e-2, errs
 
 
 def test_energy_loss_kernel_vs_oracle():
@@ -396,3 +399,39 @@ def test_trained_network_gains_over_plain_guess():
     assert ev["median_initial_residual_ratio"] < 0.5, ev
     assert ev["rejected"] <= 4, ev
     assert ev["mean_cycles_learned"] < ev["mean_cycles_prev"], ev
+
+
+def test_adam_three_steps_match_oracle():
+    """Three Adam steps on three different batches: from the second step on
+    the bias corrections 1 - beta^t no longer cancel (at t = 1 the update is
+    about lr sign(g) whatever they are), so this pins them on the GPU.  The
+    oracle's Adam (pinned by hand-worked values) replays the same three
+    gradients, read from the GPU before each step."""
+    from paper_2503_02764_amd import fld
+    N, H, W = 1, 16, 24
+    rng = np.random.default_rng(28)
+    p = _params(5)
+    announce("unet adam three steps")
+    net = fld.fldnn_create(N, H, W, training=True)
+    flat = _flat(p)
+    fld.fldnn_set_params(net, flat)
+    lr = 1e-3
+    pd = {"w": flat.astype(np.float64)}
+    m = {"w": np.zeros_like(pd["w"])}
+    v = {"w": np.zeros_like(pd["w"])}
+    for step in (1, 2, 3):
+        x = _bf16(rng.standard_normal((N, H, W, 4)))
+        t = (0.1 * step * rng.standard_normal((N, H, W, 1))).astype(np.float32)
+        xd, td = _f32dev(x), _f32dev(t)
+        _, g = fld.fldnn_gradients(net, xd, td)
+        fld.fldnn_train_step(net, xd, td, lr, step)
+        # the oracle steps from the GPU's current parameters (FP32) with the
+        # same gradient
+        U.adam_step(pd, {"w": g.astype(np.float64)}, m, v, step, lr=lr)
+        got = fld.fldnn_get_params(net).astype(np.float64)
+        err = np.abs(got - pd["w"])
+        tol = 3e-3 * lr * step + 4 * np.spacing(np.abs(got).astype(np.float32)
+                                                ).astype(np.float64) * step
+        assert np.mean(err <= tol) >= 0.999, (step, np.sort(err - tol)[-5:])
+        assert err.max() <= 2 * lr * step
+        pd["w"] = got  # carry the GPU's FP32 parameters forward
