@@ -145,6 +145,33 @@ fld_status fld_step(fld_ctx* ctx, double dt, const double* rho,
                     const double* kappa, const double* E_in, double* E_out,
                     fld_stats* stats);
 
+/* fld_step for callers that cannot allocate (code that must not call
+ * hipMalloc or hipHostMalloc: inside HIP graph capture set-up, tight serving
+ * loops, harnesses that forbid allocation).  Same operation, arguments and
+ * results as fld_setup + fld_step with the same parameters (the same kernels
+ * with the default tile shape on every level), but with no context and no
+ * workspace argument: the step's workspace is a static device array of
+ * 64 MiB inside the library (one per device, held until the process ends),
+ * and the control block is read back by a stream copy instead of a mapped
+ * host mirror.  It calls no device or pinned allocation routine.
+ *   p: host parameters (guess E^n or zero; FLD_GUESS_LEARNED gives
+ *      FLD_ERR_INVALID_ARG).
+ *   rho, kappa, E_in, E_out, stats: as for fld_step (device fields, E_out
+ *      may alias E_in; stats host or NULL).
+ *   hip_stream: a hipStream_t of the current device (NULL: default stream).
+ * Limit: parameters whose fld_workspace_bytes exceeds 64 MiB are rejected
+ * with FLD_ERR_WORKSPACE before anything is launched (2D grids up to about
+ * 1024 x 1024 in either precision, 3D up to about 96^3).  Every call on one
+ * device shares that device's array and leaves its contents behind (each
+ * step initialises what it reads), so calls that overlap on one device,
+ * from several threads or streams, race and must be serialised by the
+ * caller.  Blocks until convergence is known, like fld_step.  Errors are
+ * read with fld_last_error(NULL). */
+fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
+                            const double* kappa, const double* E_in,
+                            double* E_out, fld_stats* stats,
+                            void* hip_stream);
+
 /* Implicit gas-radiation exchange (eqs. heating, qdot) for one step dt:
  * per cell, with beta = dt c kappa rho and S = E + e_int,
  *   e' solves a4 e'^4 + (1 + beta) e' = e_int + beta S,

@@ -35,6 +35,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,10 @@ struct fld_ctx {
   Control* ctrl = nullptr;     // device control block
   Control* host_ctrl = nullptr;  // pinned host mirror, written by the GPU
   Control* host_ctrl_dev = nullptr;  // its device-side address
+  // contexts without a mapped mirror (the allocation-free step) copy the
+  // control block here after each synchronisation
+  Control host_copy{};
+  bool ctrl_by_copy = false;  // read_control copies ctrl into host_copy
   bool mixed = false;
   int inner = 2;               // FP32 V-cycles per refinement iteration
   int last_batch = 4;          // cycles (or outer iterations) last step
@@ -132,6 +137,39 @@ fld_status fail(fld_ctx* ctx, fld_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+
+// Static scratch of fld_step_noalloc: the workspace of a step carved out of
+// a file-scope device array instead of caller or library allocations.  Each
+// device that loads this library holds its own copy until the process ends.
+// Host code must use the address hipGetSymbolAddress returns on the device
+// (the array's name in host code is only a stand-in), kept per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+fld_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return fail(nullptr, FLD_ERR_DEVICE, "hipGetDevice: %s",
+                hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(nullptr, FLD_ERR_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, FLD_ERR_DEVICE,
+                  "hipGetSymbolAddress of the static scratch: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FLD_OK;
+}
 constexpr int64_t kMaxCoarsestCells = 1 << 16;
 // 3D levels of at least this many cells smooth by fused sweeps (smaller
 // ones are launch-latency bound, where a block's march through its planes
@@ -586,6 +624,9 @@ fld_status collect_timing(fld_ctx* c) {
 // The kernels that decide the stop flag also write the control block into
 // host-visible pinned memory, so reading it needs only the stream sync.
 fld_status read_control(fld_ctx* c) {
+  if (c->ctrl_by_copy)
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctrl, c->ctrl, sizeof(Control),
+                              hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return FLD_OK;
 }
@@ -1087,13 +1128,15 @@ size_t fld_workspace_bytes(const fld_params* p) {
   return P.total;
 }
 
-fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
-                     void* hip_stream, fld_ctx** out) {
-  if (!out) return fail(nullptr, FLD_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Validate the parameters and the workspace and plan the levels.
+fld_status check_setup(const fld_params* p, const void* workspace,
+                       size_t ws_bytes, Plan& P) {
   std::string why = validate(p);
   if (!why.empty()) return fail(nullptr, FLD_ERR_INVALID_ARG, "%s", why.c_str());
-  Plan P;
   make_plan(p, &P);
   if (P.g[P.L - 1].N > kMaxCoarsestCells)
     return fail(nullptr, FLD_ERR_INVALID_ARG,
@@ -1106,7 +1149,14 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
   if (ws_bytes < P.total)
     return fail(nullptr, FLD_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu",
                 ws_bytes, P.total);
-  fld_ctx* c = new fld_ctx();
+  return FLD_OK;
+}
+
+// Point a context's level buffers into the workspace and apply the
+// environment switches of the tests (kernel path, coarsening form, fused
+// 3D sweeps, fixed tile shape).  Allocates nothing.
+void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
+              size_t ws_bytes, void* hip_stream) {
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)workspace;
@@ -1169,6 +1219,20 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
     c->net_bytes = P.net_bytes;
     c->guess = (double*)(w + P.guess);
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
+                     void* hip_stream, fld_ctx** out) {
+  if (!out) return fail(nullptr, FLD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Plan P;
+  FLD_TRY(check_setup(p, workspace, ws_bytes, P));
+  fld_ctx* c = new fld_ctx();
+  fill_ctx(c, p, P, workspace, ws_bytes, hip_stream);
   hipError_t he = hipHostMalloc((void**)&c->host_ctrl, sizeof(Control),
                                 hipHostMallocMapped | hipHostMallocCoherent);
   if (he == hipSuccess)
@@ -1225,9 +1289,9 @@ fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
 
 }  // namespace
 
-fld_status fld_step(fld_ctx* c, double dt, const double* rho,
-                    const double* kappa, const double* E_in, double* E_out,
-                    fld_stats* stats) {
+static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
+                            const double* kappa, const double* E_in,
+                            double* E_out, fld_stats* stats) {
   if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   if (!rho || !kappa || !E_in || !E_out)
     return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
@@ -1317,6 +1381,45 @@ fld_status fld_step(fld_ctx* c, double dt, const double* rho,
                 "relative residual %.3e > rtol %.3e after %d V-cycles", h.res,
                 c->p.rtol, h.cycles);
   return FLD_OK;
+}
+
+fld_status fld_step(fld_ctx* c, double dt, const double* rho,
+                    const double* kappa, const double* E_in, double* E_out,
+                    fld_stats* stats) {
+  return step_impl(c, dt, rho, kappa, E_in, E_out, stats);
+}
+
+fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
+                            const double* kappa, const double* E_in,
+                            double* E_out, fld_stats* stats,
+                            void* hip_stream) {
+  if (!p) return fail(nullptr, FLD_ERR_INVALID_ARG, "params is NULL");
+  if (p->guess == FLD_GUESS_LEARNED)
+    return fail(nullptr, FLD_ERR_INVALID_ARG,
+                "fld_step_noalloc takes guess E^n or zero (the learned guess "
+                "needs a context with a model)");
+  void* ws = nullptr;
+  FLD_TRY(static_scratch(&ws));
+  Plan P;
+  if (validate(p).empty()) {
+    make_plan(p, &P);
+    if (P.total > kScratchBytes)
+      return fail(nullptr, FLD_ERR_WORKSPACE,
+                  "fld_step_noalloc: this grid needs %zu bytes of workspace, "
+                  "the static scratch holds %zu",
+                  P.total, (size_t)kScratchBytes);
+  }
+  FLD_TRY(check_setup(p, ws, kScratchBytes, P));
+  fld_ctx c;  // host-side state only, on this call's stack
+  fill_ctx(&c, p, P, ws, kScratchBytes, hip_stream);
+  c.host_ctrl = &c.host_copy;  // no mapped mirror: read_control copies
+  c.host_ctrl_dev = nullptr;
+  c.ctrl_by_copy = true;
+  const fld_status st = step_impl(&c, dt, rho, kappa, E_in, E_out, stats);
+  if (st != FLD_OK) g_err = c.err;
+  // the step has synchronised with the stream (its stop test reads the
+  // control block), so nothing of this call is still in flight
+  return st;
 }
 
 fld_status fld_exchange(fld_ctx* c, double dt, const double* rho,

@@ -35,7 +35,8 @@ FLD_GUESS_LEARNED = 2
 
 EXPORTED = [
     "fld_params_default", "fld_workspace_bytes", "fld_setup", "fld_step",
-    "fld_exchange", "fld_opacity_powerlaw", "fld_kernel_timing_enable",
+    "fld_step_noalloc", "fld_exchange", "fld_opacity_powerlaw",
+    "fld_kernel_timing_enable",
     "fld_kernel_timing_read", "fld_destroy", "fld_status_str",
     "fld_last_error", "fld_autotune", "fld_tile_shape_name",
 ]
@@ -102,6 +103,9 @@ def load(path=LIB_PATH):
     lib.fld_setup.restype = ctypes.c_int
     lib.fld_step.argtypes = [V, D, V, V, V, V, P(fld_stats)]
     lib.fld_step.restype = ctypes.c_int
+    lib.fld_step_noalloc.argtypes = [P(fld_params), D, V, V, V, V,
+                                     P(fld_stats), V]
+    lib.fld_step_noalloc.restype = ctypes.c_int
     lib.fld_exchange.argtypes = [V, D, V, V, V, V]
     lib.fld_exchange.restype = ctypes.c_int
     lib.fld_opacity_powerlaw.argtypes = [V, V, V, D, D, D, D, D, V]
@@ -221,6 +225,27 @@ def fld_step(ctx, dt, rho, kappa, E_in, E_out, stats=True, check=True):
                          ctypes.byref(s) if s is not None else None)
     if check:
         _check(ctx.ptr, st)
+    return st, (s.as_dict() if s is not None else None)
+
+
+def fld_step_noalloc(params, dt, rho, kappa, E_in, E_out, stats=True,
+                     check=True, stream=None):
+    """fld_step without a context or workspace (the library's static
+    scratch); returns (status, stats dict or None)."""
+    import torch
+    n = int(params.n[0] * params.n[1] * params.n[2])
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = fld_stats() if stats else None
+    st = load().fld_step_noalloc(ctypes.byref(params), float(dt),
+                                 _ptr(rho, "rho", n, torch.float64),
+                                 _ptr(kappa, "kappa", n, torch.float64),
+                                 _ptr(E_in, "E_in", n, torch.float64),
+                                 _ptr(E_out, "E_out", n, torch.float64),
+                                 ctypes.byref(s) if s is not None else None,
+                                 ctypes.c_void_p(stream.cuda_stream))
+    if check:
+        _check(None, st)
     return st, (s.as_dict() if s is not None else None)
 
 
