@@ -1,13 +1,19 @@
 """Benchmark of the FLD radiation-energy update on one MI355X.
 
-A step is one whole split step on the 2D 1024^2 Kramers/log-normal
-workload: opacity law, flux-limited diffusion solve to a relative residual
-of 1e-8 (FP64 V-cycles), and the exchange quartic, all on the GPU through
-the C ABI.  Inputs are resident in HBM before the timed region.
+A step is one whole split step: opacity law, flux-limited diffusion solve to
+a relative residual of 1e-8, and the exchange quartic, all on the GPU
+through the C ABI, with inputs resident in HBM before the timed region.
 
-Prints one JSON line with the throughput (cell-updates/s), the dominant
-kernel's roofline figures (HIP events around each of its launches, over the
-timed region) and the CPU oracle's rate on a bounded sample.
+The headline (`value`) is the 2D 1024^2 Kramers/log-normal workload with
+plain FP64 multigrid, timed over --steps steps after --warmup.  The same
+line carries the metric's comparison on that workload (FP32 V-cycles in FP64
+refinement, the learned guess with either precision), the dominant kernel's
+roofline (HIP events the kernel's own launches record over the timed
+region), and under `configs` the 3D 256^3 stratified workload (50 steps,
+FP64 / FP32 refinement / learned guess, each step's error bound against the
+exact solve, one step checked by the CPU oracle) and the 96 batched 2D grids
+(20 steps).  `cpu_baseline` is the FP64 oracle on the host's cores, timed
+on a bounded sample before the GPU is touched.
 """
 from __future__ import annotations
 
@@ -44,6 +50,8 @@ COARSE_PRE, COARSE_POST = 3, 3
 PRE3, POST3 = 2, 2
 COARSE_PRE3, COARSE_POST3 = 3, 3
 
+C3_STEPS, C4_STEPS = 50, 20  # the step counts of the 3D and batched configs
+
 
 def measured_traffic(kernel, shape, nu=None):
     """HBM bytes per launch of `kernel` in tile shape `shape` (and, when the
@@ -75,232 +83,132 @@ def measured_traffic(kernel, shape, nu=None):
     return None
 
 
-def cpu_baseline(m, budget_s=30.0):
-    """Oracle (FP64, numpy/scipy) on one step of the same workload."""
-    from oracle import fldref as F
-    prob = F.problem_from_medium(m)
-    t0 = time.perf_counter()
-    F.step(m.E, m.e, m.rho, prob, m.dt, opacity=m.opacity)
-    t = time.perf_counter() - t0
-    return {"value": m.cells / t, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"1 split step of the same {m.n[0]}x{m.n[1]} medium "
-                      f"(opacity, exact solve by Jacobi-PCG to 1e-13, "
-                      f"exchange), {t:.1f} s, single-threaded numpy/scipy"}
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle, timed before the GPU is initialised
+# ---------------------------------------------------------------------------
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default tile shape on every level")
-    ap.add_argument("--headline-only", action="store_true",
-                    help="run only the headline variant (for profiling)")
-    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
-                    help="c2: 2D 1024^2 (the headline); c3: 3D 256^3 "
-                         "stratified; c4: 96 batched 2D grids")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (reference for "
-                         "the FETCH_SIZE / WRITE_SIZE counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    if args.copy_calibration:
-        n = 1 << 27  # 1 GiB of float64 read, 1 GiB written
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}))
-        return
-
+def _oracle_steps(workload, n, steps, rtol):
+    """Worker: `steps` oracle split steps of a seeded workload; returns
+    (seconds, cells).  Runs in a fresh process (no GPU)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import media
-    from paper_2503_02764_amd import fld
-    from paper_2503_02764_amd.solver import Stepper, make_params
-
-    if args.workload == "c3":
-        return bench_c3(args)
-    if args.workload == "c4":
-        return bench_c4(args)
-    m = media.config_c2(n=args.n)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    def d(a):
-        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-    def run(precision, steps, warmup, timed_kernel=True, weights=None):
-        """warmup + timed steps of one solver variant from the initial state"""
-        params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
-                             precision=precision, pre_smooth=PRE, post_smooth=POST,
-                             coarse_pre_smooth=COARSE_PRE,
-                             coarse_post_smooth=COARSE_POST,
-                             guess="prev" if weights is None else "learned")
-        st = Stepper(params, opacity=m.opacity)
-        shapes = fld.fld_autotune(st.ctx)[:6] if not args.no_autotune else None
-        if weights is not None:
-            fld.fld_set_model(st.ctx, weights)
-        rho, E, e = d(m.rho), d(m.E), d(m.e)
-        kap = torch.empty_like(rho)
-        for _ in range(warmup):
-            st.step(m.dt, rho, kap, E, e)
-        torch.cuda.synchronize()
-        fld.fld_kernel_timing_enable(st.ctx, timed_kernel)
-        fld.fld_kernel_timing_read(st.ctx)  # reset
-        cycles, outer, res, rej = [], [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            s = st.step(m.dt, rho, kap, E, e)
-            cycles.append(s["cycles"])
-            outer.append(s["outer_iters"])
-            res.append(s["rel_res_final"])
-            rej.append(s["guess_rejected"])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kt = fld.fld_kernel_timing_read(st.ctx)
-        fld.fld_kernel_timing_enable(st.ctx, False)
-        secs = t1 - t0
-        return dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
-                    vcycles_per_step=float(np.mean(cycles)),
-                    outer_per_step=float(np.mean(outer)),
-                    rel_res_final_max=float(np.max(res)), kernel=kt,
-                    rejected=int(np.sum(rej)), tile_shapes=shapes,
-                    E=E.cpu().numpy())
-
-    from paper_2503_02764_amd.guess import load_weights
-    weights = load_weights()
-    base = run("fp64", args.steps, args.warmup)
-    if args.headline_only:
-        kt = base["kernel"]
-        print(json.dumps({"ms_per_step": base["ms_per_step"],
-                          "vcycles_per_step": base["vcycles_per_step"],
-                          "finest_down_us": 1e3 * kt["ms"] / max(kt["launches"], 1),
-                          "tile_shapes": base["tile_shapes"]}))
-        return
-    # only the headline run's kernel is priced against the roofline; the
-    # variants run without per-launch timing events
-    mixed = run("fp32_ir", args.steps, args.warmup, timed_kernel=False)
-    lrn64 = run("fp64", args.steps, args.warmup, timed_kernel=False, weights=weights)
-    lrn32 = run("fp32_ir", args.steps, args.warmup, timed_kernel=False, weights=weights)
-    # network inference alone on the same grid
-    net = fld.fldnn_create(1, m.n[1], m.n[0], training=False)
-    fld.fldnn_set_params(net, weights)
-    xin = torch.zeros(m.cells * 4, dtype=torch.float32, device=dev)
-    dout = torch.empty(m.cells, dtype=torch.float32, device=dev)
-    for _ in range(3):
-        fld.fldnn_forward(net, xin, dout)
-    torch.cuda.synchronize()
+    from oracle import fldref as F
+    m = media.config_c2(n=n) if workload == "c2" else media.config_c3(n=n)
+    prob = F.problem_from_medium(m)
+    E, e = m.E, m.e
     t0 = time.perf_counter()
-    for _ in range(10):
-        fld.fldnn_forward(net, xin, dout)
-    torch.cuda.synchronize()
-    unet_ms = (time.perf_counter() - t0) * 100.0
-    from paper_2503_02764_amd.train_guess import forward_flops
-    unet_flops = forward_flops(m.n[1], m.n[0])
-    kt = base["kernel"]
-    if base["tile_shapes"]:
-        level0_down = base["tile_shapes"][0][0]
-    else:  # the library's fixed shape (0 unless FLD_TILE_VARIANT names one)
-        v = int(os.environ.get("FLD_TILE_VARIANT", "0"))
-        level0_down = fld.load().fld_tile_shape_name(
-            v if 0 <= v < 7 else 0).decode()
-    avg_ms = kt["ms"] / max(kt["launches"], 1)
-    bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    diff = float(np.linalg.norm(mixed["E"] - base["E"]) /
-                 np.linalg.norm(base["E"]))
-    out = {
-        "metric": METRIC,
-        "value": base["value"],
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": base["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"2d-{m.n[0]}x{m.n[1]}-kramers-lognormal-fp64-plain-mg",
-            "grid": [m.n[0], m.n[1]],
-            "bc": "neumann",
-            "rtol": 1e-8,
-            "cycle": f"V({PRE},{POST}), coarse V({COARSE_PRE},{COARSE_POST})",
-            "precision": "fp64",
-            "guess": "prev",
-            "dt": m.dt,
-        },
-        "vcycles_per_step": base["vcycles_per_step"],
-        "rel_res_final_max": base["rel_res_final_max"],
-        "tile_shapes_autotuned": base["tile_shapes"],
-        "variants": {
-            "fp32_vcycles_fp64_refinement": {
-                "value": mixed["value"],
-                "ms_per_step": mixed["ms_per_step"],
-                "vcycles_per_step": mixed["vcycles_per_step"],
-                "outer_per_step": mixed["outer_per_step"],
-                "rel_res_final_max": mixed["rel_res_final_max"],
-                "speedup_vs_fp64": mixed["value"] / base["value"],
-                "rel_l2_vs_fp64_after_steps": diff,
-            },
-            "learned_guess_fp64": {
-                "value": lrn64["value"],
-                "ms_per_step": lrn64["ms_per_step"],
-                "vcycles_per_step": lrn64["vcycles_per_step"],
-                "guess_rejected_steps": lrn64["rejected"],
-                "speedup_vs_fp64": lrn64["value"] / base["value"],
-            },
-            "learned_guess_fp32_vcycles_fp64_refinement": {
-                "value": lrn32["value"],
-                "ms_per_step": lrn32["ms_per_step"],
-                "vcycles_per_step": lrn32["vcycles_per_step"],
-                "outer_per_step": lrn32["outer_per_step"],
-                "guess_rejected_steps": lrn32["rejected"],
-                "speedup_vs_fp64": lrn32["value"] / base["value"],
-            },
-            "unet_forward_ms": unet_ms,
-            "unet_forward": {
-                "gflop_executed": unet_flops / 1e9,
-                "gflop_useful": forward_flops(m.n[1], m.n[0], False) / 1e9,
-                "tflops": unet_flops / (unet_ms * 1e-3) / 1e12,
-                "frac_of_bf16_peak": unet_flops / (unet_ms * 1e-3) / 2.5e15},
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kt["kernel"],
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kt["kernel"], level0_down, PRE),
-            "tile_shape": level0_down,
-            "avg_launch_us": avg_ms * 1e3,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "launches": kt["launches"],
-        },
-        "step_model_roofline": step_model_roofline(
-            2, "fp64", base["value"], base["vcycles_per_step"]),
-        "achievable_copy": copy_bandwidth(),
+    for _ in range(steps):
+        E, e, _ = F.step(E, e, m.rho, prob, m.dt, opacity=m.opacity, rtol=rtol)
+    return time.perf_counter() - t0, m.cells
+
+
+def cpu_baseline(steps_c2=3, n3=128):
+    """The oracle (numpy/scipy FP64, exact solve by Jacobi-preconditioned CG
+    to the benchmark's relative residual 1e-8, then the exchange) on the
+    headline workload, single-threaded over `steps_c2` steps, and on every
+    usable core at once (one independent step of the same medium per worker
+    process: the aggregate rate of the host), plus one step of the 3D
+    workload's statistics at n3^3.  Worker processes are started before
+    this process touches the GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, 16))
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        secs, cells = ex.submit(_oracle_steps, "c2", 1024, steps_c2, 1e-8).result()
+        t0 = time.perf_counter()
+        futs = [ex.submit(_oracle_steps, "c2", 1024, 1, 1e-8)
+                for _ in range(workers)]
+        for f in futs:
+            f.result()
+        wall = time.perf_counter() - t0
+        s3, c3 = ex.submit(_oracle_steps, "c3", n3, 1, 1e-8).result()
+    return {
+        "value": cells * steps_c2 / secs, "unit": "cell-updates/s", "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps_c2} split steps of the 1024x1024 workload (opacity, "
+                  f"Jacobi-PCG to rel. residual 1e-8, exchange), {secs:.1f} s, "
+                  f"one thread of numpy/scipy (the oracle is single-threaded); "
+                  f"its 100 configured steps extrapolate linearly per step",
+        "all_cores": {"value": workers * cells / wall, "workers": workers,
+                      "seconds": wall,
+                      "sample": f"{workers} worker processes, one independent "
+                                f"split step of the same medium each"},
+        "c3_sample": {"value": c3 / s3, "cells": c3, "seconds": s3,
+                      "sample": f"1 split step of the 3D workload's statistics "
+                                f"at {n3}^3, one thread"},
+        "nproc": os.cpu_count(), "usable_cores": cores,
+        "cpu_model": _cpu_model(), "threads": 1,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m)
-    else:
-        out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Byte models and rooflines
+# ---------------------------------------------------------------------------
+
+def step_model_bytes(ndim, precision, vcycles, pre, post, cpre, cpost,
+                     outer=0.0, inner=2):
+    """Per-pass byte model of one split step per fine cell, at the V-cycle
+    actually run: every pass streams its operands once (w = 8 FP64, 4 FP32),
+    each smoothing sweep reads b, the d face arrays and the iterate and
+    writes it ((3 + d) w), the residual + restriction reads (2 + d) w and
+    writes 2 w and the prolongation 2 w / 2^d, with the finest level's sweep
+    counts (pre, post) and the coarse levels' (cpre, cpost), the coarse
+    levels holding 1/3 (2D) or 1/7 (3D) of the cells.  Fixed per step:
+    coefficients (3 + d) 8 (+ 4 d for the FP32 copies), hierarchy
+    d w (2g - 1) (g = 4/3, 8/7), copy of E^n 16, exchange 48.  FP32
+    refinement adds per outer iteration the FP64 residual (2 + d) 8 + 4 and
+    the correction 20."""
+    d = ndim
+    gsum = {1: 1.0, 2: 1.0 / 3.0, 3: 1.0 / 7.0}[d]
+    g = 1.0 + gsum
+
+    def cycle(w):
+        def level(nu):
+            return nu * (3 + d) * w + (2 + d) * w + 2 * w + 2 * w / 2 ** d
+        return level(pre + post) + gsum * level(cpre + cpost)
+
+    if precision == "fp64":
+        base = (3 + d) * 8 + d * 8 * (2 * g - 1) + 16 + 48
+        return base + vcycles * cycle(8)
+    base = (3 + d) * 8 + 4 * d + d * 4 * (2 * g - 1) + 16 + 48
+    return base + outer * ((2 + d) * 8 + 4 + 20 + inner * cycle(4))
+
+
+def step_model_roofline(bytes_per_cell, value, cycle):
+    gbs = bytes_per_cell * value / 1e9
+    return {"bytes_per_cell_step": bytes_per_cell, "cycle": cycle,
+            "model": "per-pass streaming byte model at the cycle run",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS}
+
+
+def _hbm_roofline(kt, shape):
+    """Roofline entry of a kernel timed with fld_kernel_timing (algorithmic
+    bytes per launch over its mean launch duration, against HBM peak)."""
+    if not kt["launches"]:
+        return None
+    avg_ms = kt["ms"] / kt["launches"]
+    per_launch = kt["bytes"] / kt["launches"]
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kt["kernel"], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kt["kernel"], shape),
+            "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": per_launch,
+            "launches": kt["launches"]}
 
 
 def copy_bandwidth(reps=10):
@@ -325,74 +233,223 @@ def copy_bandwidth(reps=10):
             "frac": gbs / HBM_PEAK_GBS, "bytes_per_copy": 2 * n * 8}
 
 
-def step_model_roofline(ndim, precision, value, vcycles, outer=None, inner=2):
-    """Step-level roofline from the byte model of the path (each pass streams
-    its operands once; V(2,2); w = 8 FP64, 4 FP32): per fine cell and step,
-    FP64 131 + 283 n_V bytes (2D) or 143 + 286 n_V (3D); FP32 V-cycles in FP64
-    refinement with m outer iterations of k inner cycles, 125 + m(56 + 141 k)
-    (2D) or 140 + m(64 + 143 k) (3D).  Model bytes x cell-updates/s against
-    8 TB/s."""
-    if precision == "fp64":
-        base, per = (131.0, 283.0) if ndim == 2 else (143.0, 286.0)
-        b = base + per * vcycles
-    else:
-        base, ob, ib = (125.0, 56.0, 141.0) if ndim == 2 else (140.0, 64.0, 143.0)
-        b = base + outer * (ob + ib * inner)
-    gbs = b * value / 1e9
-    return {"bytes_per_cell_step": b, "achieved": gbs, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+def _bound_factor(E):
+    """sqrt(N) |b| / sum(b): rel-L2 error <= rel-residual x this factor (A
+    has eigenvalues >= 1 and unit column sums)."""
+    b = E.reshape(-1)
+    return float(b.numel() ** 0.5 * b.norm() / b.sum())
 
 
-def _hbm_roofline(kt, shape):
-    """Roofline entry of a kernel timed with fld_kernel_timing (algorithmic
-    bytes per launch over its mean launch duration, against HBM peak)."""
-    if not kt["launches"]:
-        return None
-    avg_ms = kt["ms"] / kt["launches"]
-    per_launch = kt["bytes"] / kt["launches"]
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": kt["kernel"], "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kt["kernel"], shape),
-            "avg_launch_us": avg_ms * 1e3,
-            "algorithmic_bytes_per_launch": per_launch,
-            "launches": kt["launches"]}
+# ---------------------------------------------------------------------------
+# The headline: 2D 1024^2
+# ---------------------------------------------------------------------------
 
-
-def _line(metric_value, ms, args, workload, dtype, extra):
-    out = {
-        "metric": METRIC, "value": metric_value, "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": {"workload": workload}, "roofline": None,
-        "cpu_baseline": None}
-    out.update(extra)
-    print(json.dumps(out), flush=True)
-
-
-def bench_c3(args):
-    """3D 256^3 stratified medium: FP64 V-cycles vs FP32 V-cycles in FP64
-    refinement (and with the learned guess applied per z-slice)."""
+def run_c2(args, weights):
     import numpy as np
     import torch
     import media
     from paper_2503_02764_amd import fld
-    from paper_2503_02764_amd.guess import load_weights
+    from paper_2503_02764_amd.solver import Stepper, make_params
+    m = media.config_c2(n=args.n)
+    dev = torch.device("cuda:0")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    def run(precision, steps, warmup, timed_kernel=True, weights=None,
+            policy="adaptive"):
+        """warmup + timed steps of one solver variant from the initial state"""
+        params = make_params(m.ndim, m.n[:2], m.dx[:2], m.bc, rtol=1e-8,
+                             precision=precision, pre_smooth=PRE, post_smooth=POST,
+                             coarse_pre_smooth=COARSE_PRE,
+                             coarse_post_smooth=COARSE_POST,
+                             guess="prev" if weights is None else "learned",
+                             guess_policy=policy)
+        st = Stepper(params, opacity=m.opacity)
+        shapes = fld.fld_autotune(st.ctx)[:6] if not args.no_autotune else None
+        if weights is not None:
+            fld.fld_set_model(st.ctx, weights)
+        rho, E, e = d(m.rho), d(m.E), d(m.e)
+        kap = torch.empty_like(rho)
+        for _ in range(warmup):
+            st.step(m.dt, rho, kap, E, e)
+        torch.cuda.synchronize()
+        fld.fld_kernel_timing_enable(st.ctx, timed_kernel)
+        fld.fld_kernel_timing_read(st.ctx)  # reset
+        cycles, outer, res, rej, skip = [], [], [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s = st.step(m.dt, rho, kap, E, e)
+            cycles.append(s["cycles"])
+            outer.append(s["outer_iters"])
+            res.append(s["rel_res_final"])
+            rej.append(s["guess_rejected"])
+            skip.append(s["guess_skipped"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = fld.fld_kernel_timing_read(st.ctx)
+        fld.fld_kernel_timing_enable(st.ctx, False)
+        secs = t1 - t0
+        return dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
+                    vcycles_per_step=float(np.mean(cycles)),
+                    outer_per_step=float(np.mean(outer)),
+                    rel_res_final_max=float(np.max(res)), kernel=kt,
+                    rejected=int(np.sum(rej)), skipped=int(np.sum(skip)),
+                    tile_shapes=shapes,
+                    E=E.cpu().numpy(), bound_factor=_bound_factor(E))
+
+    base = run("fp64", args.steps, args.warmup)
+    if args.headline_only:
+        kt = base["kernel"]
+        print(json.dumps({"ms_per_step": base["ms_per_step"],
+                          "vcycles_per_step": base["vcycles_per_step"],
+                          "finest_down_us": 1e3 * kt["ms"] / max(kt["launches"], 1),
+                          "tile_shapes": base["tile_shapes"]}))
+        return None
+    # only the headline run's kernel is priced against the roofline; the
+    # variants run without per-launch timing events
+    mixed = run("fp32_ir", args.steps, args.warmup, timed_kernel=False)
+    lrn64 = run("fp64", args.steps, args.warmup, timed_kernel=False, weights=weights)
+    lrn32 = run("fp32_ir", args.steps, args.warmup, timed_kernel=False, weights=weights)
+    # the network evaluated on every step, whatever it saves
+    lrn32e = run("fp32_ir", args.steps, args.warmup, timed_kernel=False,
+                 weights=weights, policy="every_step")
+    # network inference alone on the same grid
+    net = fld.fldnn_create(1, m.n[1], m.n[0], training=False)
+    fld.fldnn_set_params(net, weights)
+    xin = torch.zeros(m.cells * 4, dtype=torch.float32, device=dev)
+    dout = torch.empty(m.cells, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        fld.fldnn_forward(net, xin, dout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        fld.fldnn_forward(net, xin, dout)
+    torch.cuda.synchronize()
+    unet_ms = (time.perf_counter() - t0) * 100.0
+    del net
+    from paper_2503_02764_amd.train_guess import forward_flops
+    unet_flops = forward_flops(m.n[1], m.n[0])
+    kt = base["kernel"]
+    if base["tile_shapes"]:
+        level0_down = base["tile_shapes"][0][0]
+    else:  # the library's fixed shape (0 unless FLD_TILE_VARIANT names one)
+        v = int(os.environ.get("FLD_TILE_VARIANT", "0"))
+        level0_down = fld.load().fld_tile_shape_name(
+            v if 0 <= v < 7 else 0).decode()
+    avg_ms = kt["ms"] / max(kt["launches"], 1)
+    bytes_per_launch = kt["bytes"] / max(kt["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    diff = float(np.linalg.norm(mixed["E"] - base["E"]) /
+                 np.linalg.norm(base["E"]))
+    cyc = f"V({PRE},{POST}), coarse V({COARSE_PRE},{COARSE_POST})"
+
+    def model(r, precision):
+        return step_model_roofline(step_model_bytes(
+            2, precision, r["vcycles_per_step"], PRE, POST, COARSE_PRE,
+            COARSE_POST, r["outer_per_step"], 2), r["value"], cyc)
+
+    def variant(r, precision, learned=False):
+        out = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+               "vcycles_per_step": r["vcycles_per_step"],
+               "outer_per_step": r["outer_per_step"],
+               "rel_res_final_max": r["rel_res_final_max"],
+               "error_bound_max": r["rel_res_final_max"] * r["bound_factor"],
+               "speedup_vs_fp64": r["value"] / base["value"],
+               "step_model_roofline": model(r, precision)}
+        if learned:
+            out["network_steps"] = args.steps - r["skipped"]
+            out["guess_rejected_steps"] = r["rejected"]
+        return out
+
+    out = {
+        "metric": METRIC,
+        "value": base["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": base["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2d-{m.n[0]}x{m.n[1]}-kramers-lognormal-fp64-plain-mg",
+            "grid": [m.n[0], m.n[1]],
+            "bc": "neumann",
+            "rtol": 1e-8,
+            "cycle": cyc,
+            "precision": "fp64",
+            "guess": "prev",
+            "dt": m.dt,
+        },
+        "vcycles_per_step": base["vcycles_per_step"],
+        "rel_res_final_max": base["rel_res_final_max"],
+        "error_bound_max": base["rel_res_final_max"] * base["bound_factor"],
+        "learned_fp32_vs_plain_fp64": lrn32["value"] / base["value"],
+        "tile_shapes_autotuned": base["tile_shapes"],
+        "variants": {
+            "fp32_vcycles_fp64_refinement": dict(
+                variant(mixed, "fp32_ir"), rel_l2_vs_fp64_after_steps=diff),
+            "learned_guess_fp64": variant(lrn64, "fp64", True),
+            "learned_guess_fp32_vcycles_fp64_refinement":
+                variant(lrn32, "fp32_ir", True),
+            "learned_guess_every_step_fp32_vcycles_fp64_refinement":
+                variant(lrn32e, "fp32_ir", True),
+            "unet_forward_ms": unet_ms,
+            "unet_forward": {
+                "gflop_executed": unet_flops / 1e9,
+                "gflop_useful": forward_flops(m.n[1], m.n[0], False) / 1e9,
+                "tflops": unet_flops / (unet_ms * 1e-3) / 1e12,
+                "frac_of_bf16_peak": unet_flops / (unet_ms * 1e-3) / 2.5e15},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kt["kernel"],
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kt["kernel"], level0_down, PRE),
+            "tile_shape": level0_down,
+            "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "launches": kt["launches"],
+        },
+        "step_model_roofline": model(base, "fp64"),
+    }
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 3D 256^3 stratified medium
+# ---------------------------------------------------------------------------
+
+def run_c3(steps, warmup, weights, oracle_check=True):
+    """FP64 V-cycles, FP32 V-cycles in FP64 refinement, and the latter with
+    the learned guess applied per z-slice, each from the initial state over
+    `steps` steps.  Every step's error against its exact solve is bounded by
+    its FP64 relative residual x sqrt(N)|b|/sum(b); after the timed steps of
+    the FP32 refinement one more step is taken untimed and the CPU oracle
+    measures the residual of its iterate under its own operator."""
+    import numpy as np
+    import torch
+    import media
+    from paper_2503_02764_amd import fld
     from paper_2503_02764_amd.solver import Stepper, make_params
     m = media.config_c3()
-    steps = min(args.steps, 5)
-    warm = min(args.warmup, 1)
+    cyc = f"V({PRE3},{POST3}), coarse V({COARSE_PRE3},{COARSE_POST3})"
 
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
-    def run(precision, weights=None):
-        # the strongly stratified medium (face alpha spans ~8 decades) takes
-        # about 50-60 V-cycles per step with rediscretised coarse operators
+    def run(precision, weights=None, check=False, policy="adaptive"):
         params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
                              guess="prev" if weights is None else "learned",
+                             guess_policy=policy,
                              max_cycles=300, pre_smooth=PRE3,
                              post_smooth=POST3, coarse_pre_smooth=COARSE_PRE3,
                              coarse_post_smooth=COARSE_POST3)
@@ -401,68 +458,113 @@ def bench_c3(args):
             fld.fld_set_model(st.ctx, weights)
         rho, E, e = d(m.rho), d(m.E), d(m.e)
         kap = torch.empty_like(rho)
-        for _ in range(warm):
+        for _ in range(warmup):
             st.step(m.dt, rho, kap, E, e)
         torch.cuda.synchronize()
-        # the first finest-level colour pass of every V-cycle records its own
+        f0 = _bound_factor(E)
+        # the first fused finest-level sweep of every V-cycle records its own
         # duration (HIP events the launch records)
         fld.fld_kernel_timing_enable(st.ctx, True)
         fld.fld_kernel_timing_read(st.ctx)  # reset
-        cyc, outer = [], []
+        cyc_n, outer, res, rej, skip = [], [], [], [], []
         t0 = time.perf_counter()
         for _ in range(steps):
             s = st.step(m.dt, rho, kap, E, e)
-            cyc.append(s["cycles"])
+            cyc_n.append(s["cycles"])
             outer.append(s["outer_iters"])
+            res.append(s["rel_res_final"])
+            rej.append(s["guess_rejected"])
+            skip.append(s["guess_skipped"])
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         kt = fld.fld_kernel_timing_read(st.ctx)
         fld.fld_kernel_timing_enable(st.ctx, False)
-        res = dict(value=m.cells * steps / secs, ms_per_step=secs * 1e3 / steps,
-                   vcycles_per_step=float(np.mean(cyc)),
-                   outer_per_step=float(np.mean(outer)),
-                   roofline=_hbm_roofline(kt, "256^3"))
-        res["step_model_roofline"] = step_model_roofline(
-            3, precision, res["value"], res["vcycles_per_step"],
-            res["outer_per_step"])
+        factor = max(f0, _bound_factor(E))
+        value = m.cells * steps / secs
+        r = dict(value=value, ms_per_step=secs * 1e3 / steps,
+                 vcycles_per_step=float(np.mean(cyc_n)),
+                 outer_per_step=float(np.mean(outer)),
+                 rel_res_final_max=float(np.max(res)),
+                 bound_factor=factor,
+                 error_bound_per_step=[float(x) * factor for x in res],
+                 roofline=_hbm_roofline(kt, "256^3"))
+        r["step_model_roofline"] = step_model_roofline(step_model_bytes(
+            3, precision, r["vcycles_per_step"], PRE3, POST3, COARSE_PRE3,
+            COARSE_POST3, r["outer_per_step"], 2), value, cyc)
+        if weights is not None:
+            r["network_steps"] = steps - int(np.sum(skip))
+            r["guess_rejected_steps"] = int(np.sum(rej))
+        if check:
+            r["oracle_checked_step"] = _oracle_check_c3(m, st, rho, kap, E, e)
         E_out = E.cpu().numpy()
         del st, rho, E, e, kap
         torch.cuda.empty_cache()
-        return res, E_out
+        return r, E_out
 
     f64, E64 = run("fp64")
-    f32, E32 = run("fp32_ir")
-    lrn, _ = run("fp32_ir", load_weights())
+    f32, E32 = run("fp32_ir", check=oracle_check)
+    lrn, _ = run("fp32_ir", weights)
+    lrne, _ = run("fp32_ir", weights, policy="every_step")
     f32["rel_l2_vs_fp64_after_steps"] = float(
         np.linalg.norm(E32 - E64) / np.linalg.norm(E64))
-    f32["speedup_vs_fp64"] = f32["value"] / f64["value"]
-    lrn["speedup_vs_fp64"] = lrn["value"] / f64["value"]
-    args.steps, args.warmup = steps, warm
-    _line(f32["value"], f32["ms_per_step"], args,
-          "3d-256cube-stratified-kramers-fp32-vcycles-fp64-refinement", "f32",
-          {"variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
-                        "learned_guess_fp32_vcycles": lrn},
-           "cycle": f"V({PRE3},{POST3}), coarse V({COARSE_PRE3},{COARSE_POST3})",
-           "roofline": f32["roofline"],
-           "step_model_roofline": f32["step_model_roofline"],
-           "achievable_copy": copy_bandwidth()})
+    for r in (f32, lrn, lrne):
+        r["speedup_vs_fp64"] = r["value"] / f64["value"]
+    return {
+        "workload": "3d-256cube-stratified-kramers",
+        "grid": list(m.n), "bc": list(m.bc), "rtol": 1e-8, "cycle": cyc,
+        "steps": steps, "warmup": warmup, "dt": m.dt,
+        "value": f32["value"], "ms_per_step": f32["ms_per_step"],
+        "dtype": "f32 V-cycles, f64 refinement and exchange",
+        "learned_fp32_vs_plain_fp64": lrn["value"] / f64["value"],
+        "roofline": f32["roofline"],
+        "variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
+                     "learned_guess_fp32_vcycles_fp64_refinement": lrn,
+                     "learned_guess_every_step_fp32_vcycles_fp64_refinement":
+                         lrne},
+    }
 
 
-def bench_c4(args):
+def _oracle_check_c3(m, st, rho, kap, E, e):
+    """One more (untimed) step; the oracle rebuilds the operator from the
+    step's inputs and measures the residual of the GPU iterate."""
+    import numpy as np
+    import torch
+    from paper_2503_02764_amd import fld
+    from oracle import fldref as F
+    o = st.opacity
+    fld.fld_opacity_powerlaw(st.ctx, rho, e, o["k0"], o["a"], o["b"],
+                             o["kmin"], o["kmax"], kap)
+    En = E.cpu().numpy()
+    Es = torch.empty_like(E)
+    _, s = fld.fld_step(st.ctx, m.dt, rho, kap, E, Es)
+    prob = F.problem_from_medium(m)
+    alphas = F.face_coefficients(En, m.rho, kap.cpu().numpy(), m.dt, prob)
+    rr = F.relative_residual(Es.cpu().numpy(), En, alphas, prob)
+    b = En.ravel()
+    factor = float(np.sqrt(b.size) * np.linalg.norm(b) / b.sum())
+    return {"oracle_rel_residual": rr, "gpu_rel_residual": s["rel_res_final"],
+            "error_bound_vs_exact_solve": rr * factor}
+
+
+# ---------------------------------------------------------------------------
+# 96 batched 2D grids
+# ---------------------------------------------------------------------------
+
+def run_c4(steps, warmup):
     """96 independent 2D grids (sides 128..1024) in one batched context:
     FP32 V-cycles in FP64 refinement, one launch per phase, hipGraph
     replay, autotuned tiles; against the same grids stepped one by one with
-    single-grid contexts (same precision, and plain FP64)."""
+    single-grid contexts (same precision, and plain FP64).  The learned
+    guess is not offered for batches."""
     import numpy as np
     import torch
     import media
     from paper_2503_02764_amd import fld
     from paper_2503_02764_amd.solver import Stepper, make_params
     ms = media.config_c4()
-    steps = min(args.steps, 5)
-    warm = min(args.warmup, 1)
     o = ms[0].opacity
     cells = sum(m.cells for m in ms)
+    cyc = f"V({PRE},{POST}), coarse V({COARSE_PRE},{COARSE_POST})"
 
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -484,24 +586,35 @@ def bench_c4(args):
         fld.fld_batch_set_graph(bctx, True)
         shapes = fld.fld_autotune(bctx)[:6]
         rho, E, e, kap = fields()
+        res = []
 
         def step():
             fld.fld_opacity_powerlaw_batch(bctx, rho, e, o["k0"], o["a"],
                                            o["b"], o["kmin"], o["kmax"], kap)
-            fld.fld_step_batch(bctx, dts, rho, kap, E, E)
+            _, s = fld.fld_step_batch(bctx, dts, rho, kap, E, E)
             fld.fld_exchange_batch(bctx, dts, rho, kap, E, e)
+            return s
 
-        for _ in range(warm):
+        for _ in range(warmup):
             step()
         stream.synchronize()
+        factor0 = max(_bound_factor(x) for x in E)
+        outer = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            step()
+            s = step()
+            res.append(max(x["rel_res_final"] for x in s))
+            outer.append(float(np.mean([x["outer_iters"] for x in s])))
         stream.synchronize()
         secs = time.perf_counter() - t0
+        factor = max(factor0, max(_bound_factor(x) for x in E))
         E_batch = [x.cpu().numpy() for x in E]
-    batch = dict(value=cells * steps / secs, ms_per_step=secs * 1e3 / steps,
-                 tile_shapes_autotuned=shapes)
+    value = cells * steps / secs
+    batch = dict(value=value, ms_per_step=secs * 1e3 / steps,
+                 tile_shapes_autotuned=shapes,
+                 outer_per_step=float(np.mean(outer)),
+                 rel_res_final_max=float(np.max(res)), bound_factor=factor,
+                 error_bound_per_step=[r * factor for r in res])
     del bctx, rho, E, e, kap
     torch.cuda.empty_cache()
 
@@ -516,7 +629,7 @@ def bench_c4(args):
             fld.fld_autotune(st.ctx)
             sts.append(st)
         rho, E, e, kap = fields()
-        for _ in range(warm):
+        for _ in range(warmup):
             for g, st in enumerate(sts):
                 st.step(dts[g], rho[g], kap[g], E[g], e[g])
         torch.cuda.synchronize()
@@ -531,18 +644,117 @@ def bench_c4(args):
         torch.cuda.empty_cache()
         return dict(value=cells * steps / secs, ms_per_step=secs * 1e3 / steps), out
 
-    seq32, E32 = one_by_one("fp32_ir")
+    seq32, _ = one_by_one("fp32_ir")
     seq64, E64 = one_by_one("fp64")
     diff = max(float(np.linalg.norm(a - b) / np.linalg.norm(b))
                for a, b in zip(E_batch, E64))
     batch["speedup_vs_one_by_one_fp32"] = batch["value"] / seq32["value"]
     batch["speedup_vs_one_by_one_fp64"] = batch["value"] / seq64["value"]
     batch["max_rel_l2_vs_fp64_after_steps"] = diff
-    args.steps, args.warmup = steps, warm
-    _line(batch["value"], batch["ms_per_step"], args,
-          f"2d-batched-{len(ms)}-grids-{cells}-cells-fp32-vcycles-fp64-refinement-graph",
-          "f32", {"variants": {"batched": batch, "one_by_one_fp32": seq32,
-                               "one_by_one_fp64": seq64}})
+    # the outer count varies per grid: the model takes the mean
+    batch["step_model_roofline"] = step_model_roofline(step_model_bytes(
+        2, "fp32_ir", 0.0, PRE, POST, COARSE_PRE, COARSE_POST,
+        batch["outer_per_step"], 2), value, cyc)
+    return {
+        "workload": f"2d-batched-{len(ms)}-grids-{cells}-cells",
+        "grids": len(ms), "cells": cells, "rtol": 1e-8, "cycle": cyc,
+        "steps": steps, "warmup": warmup,
+        "value": value, "ms_per_step": batch["ms_per_step"],
+        "dtype": "f32 V-cycles, f64 refinement and exchange",
+        "roofline": None,
+        "variants": {"batched_fp32_vcycles_fp64_refinement_graph": batch,
+                     "one_by_one_fp32": seq32, "one_by_one_fp64": seq64},
+    }
+
+
+def _line(metric_value, ms, args, workload, dtype, extra):
+    out = {
+        "metric": METRIC, "value": metric_value, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": workload}, "roofline": None,
+        "cpu_baseline": None}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shape on every level")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline variant (for profiling)")
+    ap.add_argument("--workload", choices=("all", "c2", "c3", "c4"),
+                    default="all",
+                    help="all: the headline line with the 3D and batched "
+                         "configs under `configs`; c2 / c3 / c4: one workload "
+                         "alone (for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if (not args.no_cpu_baseline and not args.headline_only
+            and not args.copy_calibration and args.workload in ("all", "c2")):
+        cpu = cpu_baseline()  # before this process touches the GPU
+
+    import torch
+
+    if args.copy_calibration:
+        n = 1 << 27  # 1 GiB of float64 read, 1 GiB written
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}))
+        return
+
+    torch.cuda.set_device(0)
+    from paper_2503_02764_amd.guess import load_weights
+    weights = load_weights()
+    if args.workload == "c3":
+        r = run_c3(min(args.steps, C3_STEPS), min(args.warmup, 1), weights,
+                   oracle_check=False)
+        args.steps, args.warmup = r["steps"], r["warmup"]
+        _line(r["value"], r["ms_per_step"], args, r["workload"], "f32",
+              {"roofline": r["roofline"], "c3": r,
+               "achievable_copy": copy_bandwidth()})
+        return
+    if args.workload == "c4":
+        r = run_c4(min(args.steps, C4_STEPS), min(args.warmup, 1))
+        args.steps, args.warmup = r["steps"], r["warmup"]
+        _line(r["value"], r["ms_per_step"], args, r["workload"], "f32",
+              {"c4": r})
+        return
+    out = run_c2(args, weights)
+    if out is None:
+        return
+    if args.workload == "all":
+        out["configs"] = {}
+        for name, fn in (("c3", lambda: run_c3(C3_STEPS, 1, weights)),
+                         ("c4", lambda: run_c4(C4_STEPS, 1))):
+            try:
+                out["configs"][name] = fn()
+            except Exception as exc:  # reported in the line, not hidden
+                out["configs"][name] = {"error": f"{type(exc).__name__}: {exc}"}
+                import torch
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+    out["achievable_copy"] = copy_bandwidth()
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

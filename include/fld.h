@@ -59,9 +59,13 @@ typedef enum {
  * E[-2] = E[1]) and no flux through the boundary face. */
 typedef enum { FLD_BC_PERIODIC = 0, FLD_BC_NEUMANN = 1 } fld_bc;
 
-/* eq. fld_lambda (Levermore-Pomraning) or the diffusion value 1/3 used by
- * the paper for its stationary shocks (Sect. 4.1). */
-typedef enum { FLD_LIMITER_LP = 0, FLD_LIMITER_DIFFUSION = 1 } fld_limiter;
+/* eq. fld_lambda (Levermore-Pomraning), the diffusion value 1/3 used by
+ * the paper for its stationary shocks (Sect. 4.1), or Minerbo's limiter
+ * (named in Sect. 2 as an alternative; the paper gives no formula, so its
+ * published piecewise form is used: lambda = 2 / (3 + sqrt(9 + 12 R^2)) for
+ * R <= 3/2 and 1 / (1 + R + sqrt(1 + 2 R)) above). */
+typedef enum { FLD_LIMITER_LP = 0, FLD_LIMITER_DIFFUSION = 1,
+               FLD_LIMITER_MINERBO = 2 } fld_limiter;
 
 /* Mean of the two cell-centred D on a face. */
 typedef enum { FLD_FACE_ARITH = 0, FLD_FACE_HARMONIC = 1 } fld_face_mean;
@@ -72,6 +76,18 @@ typedef enum { FLD_PREC_FP64 = 0, FLD_PREC_FP32_IR = 1 } fld_precision;
 
 /* Initial guess of the diffusion solve: E^n, zero, or a learned guess. */
 typedef enum { FLD_GUESS_PREV = 0, FLD_GUESS_ZERO = 1, FLD_GUESS_LEARNED = 2 } fld_guess;
+
+/* When the learned guess evaluates its network (FLD_GUESS_LEARNED only).
+ * FLD_GUESS_ADAPTIVE: the context's first step runs without the network and
+ * its count of V-cycles (FP64) or refinement iterations (FP32_IR) becomes
+ * the reference, which every later step without the network renews.  A
+ * step with the network that does not lower that count (or whose guess the
+ * residual judge rejects) makes the next 1, 2, 4, 8, then 16 steps run
+ * without it before it is tried again; a step where it lowers the count
+ * keeps it on for the next step.  A step without the network is exactly a
+ * step with guess E^n.  FLD_GUESS_EVERY_STEP: the network runs on every
+ * step. */
+typedef enum { FLD_GUESS_ADAPTIVE = 0, FLD_GUESS_EVERY_STEP = 1 } fld_guess_policy;
 
 typedef struct {
   int32_t ndim;          /* 1, 2 or 3                                      */
@@ -98,6 +114,8 @@ typedef struct {
                                   levels; 0: pre_smooth                   */
   int32_t coarse_post_smooth;  /* sweeps after prolongation on the coarse
                                   levels; 0: post_smooth                  */
+  int32_t guess_policy;  /* fld_guess_policy (learned guess only)         */
+  int32_t pad1;
 } fld_params;
 
 typedef struct {
@@ -106,15 +124,17 @@ typedef struct {
                               the residual below rtol)                     */
   int32_t outer_iters;     /* FP64 refinement iterations (FP32_IR), else 0 */
   int32_t guess_rejected;  /* 1 when a learned guess lost to E^n          */
-  int32_t pad;
+  int32_t guess_skipped;   /* 1 when FLD_GUESS_ADAPTIVE ran this step
+                              without the network (guess E^n)              */
   int64_t flagged_cells;   /* cells with E <= 0, rho kappa <= 0 or NaN     */
   double rel_res_initial;  /* |b - A x0| / |b|                              */
   double rel_res_final;    /* |b - A x| / |b| of the returned E_out        */
 } fld_stats;
 
 /* Fill *p with defaults: 1D, 1 cell, periodic, c = a_rad = gas_const = 1,
- * gamma = 5/3, LP limiter, arithmetic face mean, FP64, guess E^n,
- * rtol 1e-8, max_cycles 50, V(2,2) on every level. */
+ * gamma = 5/3, LP limiter, arithmetic face mean, FP64, guess E^n
+ * (adaptive network policy if the learned guess is chosen), rtol 1e-8,
+ * max_cycles 50, V(2,2) on every level. */
 void fld_params_default(fld_params* p);
 
 /* Bytes of device workspace fld_setup needs for these parameters, or 0 if
@@ -181,6 +201,32 @@ fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
  * Asynchronous (stream-ordered).  FLD_ERR_INVALID_ARG for dt <= 0. */
 fld_status fld_exchange(fld_ctx* ctx, double dt, const double* rho,
                         const double* kappa, double* E, double* e_int);
+
+/* Explicit FLD source terms at cell centres (Sect. 3 adds them explicitly,
+ * around the implicit update), from E and the gas velocity v:
+ *   f_r    = rho kappa F / c = -lambda grad E   (eqs. rad_force, fld_F)
+ *   work   = v . f_r                            (its work on the gas)
+ *   tiring = P : grad v,  P = f E,  f_ij = (1 - f)/2 delta_ij
+ *            + (3 f - 1)/2 n_i n_j,  n = grad E / |grad E|  (0 where
+ *            grad E = 0),  f = lambda + lambda^2 R^2
+ *            (eqs. fld_P, fld_Eddington_tensor, fld_f)
+ *   fedd   = f, the scalar Eddington factor.
+ * grad E and grad v by the context's five-point stencil and ghost cells
+ * (periodic wrap, Neumann mirror ghosts for E and every velocity component),
+ * R = |grad E| / (rho kappa E) and lambda the context's limiter, as in
+ * fld_step.  Only derivatives along the grid's ndim dimensions exist.
+ * rho, kappa, E: device fields.  v: HOST array of ndim DEVICE pointers
+ * (v_x, v_y, v_z), or NULL when neither work nor tiring is asked for.
+ * f_r: HOST array of ndim DEVICE output pointers, or NULL; work, tiring,
+ * fedd: DEVICE outputs, each nullable.  A caller advancing the split step
+ * adds -dt tiring to E, dt f_r to the momentum and dt work to the gas
+ * energy.  Outputs are unspecified for cells with E <= 0 or rho kappa <= 0.
+ * Asynchronous (stream-ordered); FLD_ERR_INVALID_ARG for a NULL input, for
+ * work or tiring without v, or for a batched context. */
+fld_status fld_explicit_sources(fld_ctx* ctx, const double* rho,
+                                const double* kappa, const double* E,
+                                const double* const* v, double* const* f_r,
+                                double* work, double* tiring, double* fedd);
 
 /* Opacity power law of the synthetic workloads (not the paper's constant
  * opacity): kappa = clip(k0 rho^a T^b, kmin, kmax) with

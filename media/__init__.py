@@ -15,5 +15,6 @@ from .generators import (  # noqa: F401
     config_c4,
     config_c5_train,
     random_small_medium,
+    velocity_field,
     KRAMERS,
 )

@@ -48,7 +48,8 @@ class Medium:
     a_rad: float = 1.0
     gamma: float = 5.0 / 3.0
     gas_const: float = 1.0
-    limiter: str = "lp"  # "lp" (Levermore-Pomraning) or "diffusion" (1/3)
+    limiter: str = "lp"  # "lp" (Levermore-Pomraning), "diffusion" (1/3) or
+    #                      "minerbo"
     face_mean: str = "arith"  # "arith" or "harmonic"
     name: str = ""
 
@@ -233,3 +234,11 @@ def random_small_medium(seed, n, bc, limiter="lp", face_mean="arith",
                   kappa=kappa, opacity=None, dt=dt, steps=1, rtol=1e-12,
                   limiter=limiter, face_mean=face_mean,
                   name=f"rand{seed}-{'x'.join(map(str, n))}")
+
+
+def velocity_field(shape, ndim, seed, amplitude=0.1, ell=16.0):
+    """Gas velocity for the explicit source terms: ndim components (x, y, z
+    order), each amplitude * grf(shape, ell) from its own stream of `seed`.
+    The update does not evolve v; it only differentiates it."""
+    rng = np.random.default_rng(seed)
+    return [amplitude * grf(tuple(shape), ell, rng) for _ in range(ndim)]

@@ -59,7 +59,7 @@ class Problem:
     a_rad: float = 1.0
     gamma: float = 5.0 / 3.0
     gas_const: float = 1.0  # R_g = k_B / (mu m_p)
-    limiter: str = "lp"  # "lp" or "diffusion"
+    limiter: str = "lp"  # "lp", "diffusion" or "minerbo"
     face_mean: str = "arith"  # "arith" or "harmonic"
 
     @property
@@ -122,12 +122,20 @@ def gradient(E, prob):
 
 
 def limiter(R, kind="lp"):
-    """Flux limiter lambda(R): eq. fld_lambda (LP) or the diffusion value 1/3."""
+    """Flux limiter lambda(R): eq. fld_lambda (LP), the diffusion value 1/3,
+    or Minerbo's limiter, which Sect. 2 names after eq. fld_lambda without a
+    formula; the published piecewise form is taken (Minerbo 1978):
+    2 / (3 + sqrt(9 + 12 R^2)) up to R = 3/2, 1 / (1 + R + sqrt(1 + 2 R))
+    beyond."""
     R = np.asarray(R, dtype=np.float64)
     if kind == "lp":
         return (2.0 + R) / (6.0 + 3.0 * R + R * R)
     if kind == "diffusion":
         return np.full_like(R, 1.0 / 3.0)
+    if kind == "minerbo":
+        low = 2.0 / (3.0 + np.sqrt(9.0 + 12.0 * R * R))
+        high = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))
+        return np.where(R <= 1.5, low, high)
     raise ValueError(kind)
 
 

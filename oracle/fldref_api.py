@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY: tests drive the GPU library (fld_setup / fld_step
 with the HIP path and does not import the library: parameters are a plain
 mapping with the field names and codes of the library's parameter struct
 (ndim, n, dx, bc_lo, bc_hi with 0 = periodic / 1 = Neumann, c, a_rad,
-gamma, gas_const, limiter with 0 = Levermore-Pomraning / 1 = 1/3,
+gamma, gas_const, limiter with 0 = Levermore-Pomraning / 1 = 1/3 /
+2 = Minerbo,
 face_mean with 0 = arithmetic / 1 = harmonic).
 
 fldref_step returns the exact backward-Euler diffusion solve E* = A^-1 E^n
@@ -47,7 +48,7 @@ def fldref_setup(params):
         ndim=nd, n=n, dx=dx, bc=bc, c=float(p.get("c", 1.0)),
         a_rad=float(p.get("a_rad", 1.0)), gamma=float(p.get("gamma", 5.0 / 3.0)),
         gas_const=float(p.get("gas_const", 1.0)),
-        limiter="lp" if int(p.get("limiter", 0)) == 0 else "diffusion",
+        limiter=("lp", "diffusion", "minerbo")[int(p.get("limiter", 0))],
         face_mean="arith" if int(p.get("face_mean", 0)) == 0 else "harmonic")
     return RefCtx(prob=prob, rtol=float(p.get("rtol", 1e-13)))
 

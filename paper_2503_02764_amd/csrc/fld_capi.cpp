@@ -104,6 +104,17 @@ struct fld_ctx {
   size_t net_bytes = 0;
   double* mean = nullptr;  // per-slice mean of log E (network features)
   double* guess = nullptr;  // the network's candidate iterate (FP64)
+  // adaptive network policy: steps left without the network, the length
+  // of the next pause, and the work (V-cycles, or refinement iterations)
+  // of the last step without it
+  int net_skip = 1;
+  int net_span = 0;
+  int plain_units = -1;
+  // the judge's bar on the guess's squared residual relative to that of
+  // E^n: 1, or (adaptive policy, once a step without the network has run)
+  // the square of that step's contraction per V-cycle or refinement
+  // iteration, so that an accepted guess is predicted to save one
+  double judge_q2 = 1.0;
 };
 
 namespace {
@@ -171,6 +182,8 @@ fld_status static_scratch(void** out) {
   return FLD_OK;
 }
 constexpr int64_t kMaxCoarsestCells = 1 << 16;
+// longest run of steps the adaptive policy takes without the network
+constexpr int kMaxNetPause = 16;
 // 3D levels of at least this many cells smooth by fused sweeps (smaller
 // ones are launch-latency bound, where a block's march through its planes
 // costs more than the second colour launch)
@@ -251,7 +264,7 @@ std::string validate(const fld_params* p) {
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return "gamma must be > 1";
   if (!(p->gas_const > 0.0) || !std::isfinite(p->gas_const))
     return "gas_const must be > 0";
-  if (p->limiter < 0 || p->limiter > 1) return "unknown limiter";
+  if (p->limiter < 0 || p->limiter > 2) return "unknown limiter";
   if (p->face_mean < 0 || p->face_mean > 1) return "unknown face mean";
   if (p->precision != FLD_PREC_FP64 && p->precision != FLD_PREC_FP32_IR)
     return "unknown precision";
@@ -263,6 +276,9 @@ std::string validate(const fld_params* p) {
     return "the learned guess needs ndim >= 2 and n[0], n[1] multiples of 8";
   if (p->guess == FLD_GUESS_LEARNED && p->n[2] > 16384)
     return "the learned guess takes at most 16384 z-slices";
+  if (p->guess_policy != FLD_GUESS_ADAPTIVE &&
+      p->guess_policy != FLD_GUESS_EVERY_STEP)
+    return "unknown guess_policy";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->ir_inner < 0 || p->ir_inner > 8) return "ir_inner must be in [0, 8]";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
@@ -1281,7 +1297,8 @@ fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
         HIP_TRY(c, launch_gs_color<double>(v, color, c->ctrl, c->stream));
     HIP_TRY(c, launch_resid_norm<double>(v, c->partials, &nb, c->ctrl,
                                          c->stream));
-    HIP_TRY(c, launch_guess_judge(mode, c->partials, nb, c->ctrl, c->stream));
+    HIP_TRY(c, launch_guess_judge(mode, c->partials, nb, c->judge_q2, c->ctrl,
+                                  c->stream));
   }
   HIP_TRY(c, launch_guess_take(g.N, vg.x, v0.x, c->ctrl, c->stream));
   return FLD_OK;
@@ -1301,6 +1318,11 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     return fail(c, FLD_ERR_MODEL, "no model: call fld_set_model first");
   const bool aliased = (E_in == E_out);
   const Geom& g0 = c->geom[0];
+  const bool learned = c->p.guess == FLD_GUESS_LEARNED;
+  const bool use_net = learned && (c->p.guess_policy == FLD_GUESS_EVERY_STEP ||
+                                   c->net_skip == 0);
+  // a learned-guess step without its network is a step with guess E^n
+  const bool prev_guess = c->p.guess == FLD_GUESS_PREV || (learned && !use_net);
   // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it)
   c->h64.x[0] = E_out;
   c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
@@ -1320,7 +1342,7 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   A.face_mean = c->p.face_mean;
   // 2D grids: the LDS-tiled coefficient stage; with x0 = E^n in FP64 it also
   // forms the initial residual, so the solve needs no separate first pass
-  c->init_fused = coef2d_ok(g0) && !c->mixed && c->p.guess == FLD_GUESS_PREV;
+  c->init_fused = coef2d_ok(g0) && !c->mixed && prev_guess;
   if (coef2d_ok(g0)) {
     HIP_TRY(c, launch_coef2d(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
                              copy_dst, c->partials, c->ctrl, c->init_fused,
@@ -1359,14 +1381,34 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   }
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
-  if (c->p.guess == FLD_GUESS_LEARNED) FLD_TRY(learned_guess(c, rho, kappa));
+  if (use_net) FLD_TRY(learned_guess(c, rho, kappa));
   FLD_TRY(c->mixed ? solve_mixed(c) : solve_fp64(c));
   FLD_TRY(collect_timing(c));
   const Control& h = *c->host_ctrl;
+  if (learned && c->p.guess_policy == FLD_GUESS_ADAPTIVE &&
+      h.done == kConverged) {
+    const int units = c->mixed ? h.outer : h.cycles;
+    if (!use_net) {
+      c->plain_units = units;
+      if (c->net_skip > 0) --c->net_skip;
+      if (units > 0 && h.res_initial > 0.0 && h.res > 0.0) {
+        const double rho = std::pow(h.res / h.res_initial, 1.0 / units);
+        const double r = std::min(std::max(rho, 1e-3), 1.0);
+        c->judge_q2 = r * r;
+      }
+    } else if (h.guess_rejected ||
+               (c->plain_units >= 0 && units >= c->plain_units)) {
+      c->net_span = std::min(std::max(1, 2 * c->net_span), kMaxNetPause);
+      c->net_skip = c->net_span;
+    } else {
+      c->net_span = 0;
+    }
+  }
   if (stats) {
     memset(stats, 0, sizeof *stats);
     stats->cycles = h.cycles;
-    stats->guess_rejected = h.guess_rejected;
+    stats->guess_rejected = use_net ? h.guess_rejected : 0;
+    stats->guess_skipped = learned && !use_net;
     stats->outer_iters = c->mixed ? h.outer : 0;
     stats->flagged_cells = h.flagged;
     stats->rel_res_initial = h.res_initial;
@@ -1431,6 +1473,40 @@ fld_status fld_exchange(fld_ctx* c, double dt, const double* rho,
     return fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
   HIP_TRY(c, launch_exchange(c->geom[0].N, dt, c->p.c, c->p.a_rad, c->p.gamma,
                              c->p.gas_const, rho, kappa, E, e_int, c->stream));
+  return FLD_OK;
+}
+
+fld_status fld_explicit_sources(fld_ctx* c, const double* rho,
+                                const double* kappa, const double* E,
+                                const double* const* v, double* const* f_r,
+                                double* work, double* tiring, double* fedd) {
+  if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->batch)
+    return fail(c, FLD_ERR_INVALID_ARG, "batched contexts have no explicit "
+                                        "source call");
+  if (!rho || !kappa || !E)
+    return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
+  const Geom& g = c->geom[0];
+  ExplicitArgs a{};
+  a.g = g;
+  a.limiter = c->p.limiter;
+  a.E = E;
+  a.rho = rho;
+  a.kappa = kappa;
+  for (int d = 0; d < g.ndim; ++d) a.gscale[d] = 1.0 / (12.0 * c->p.dx[d]);
+  if ((work || tiring) && !v)
+    return fail(c, FLD_ERR_INVALID_ARG, "work and tiring need the velocity");
+  for (int d = 0; d < g.ndim; ++d) {
+    if (v) {
+      if (!v[d]) return fail(c, FLD_ERR_INVALID_ARG, "NULL velocity component");
+      a.v[d] = v[d];
+    }
+    if (f_r) a.fr[d] = f_r[d];
+  }
+  a.work = work;
+  a.tiring = tiring;
+  a.fedd = fedd;
+  HIP_TRY(c, launch_explicit(a, c->stream));
   return FLD_OK;
 }
 
@@ -1627,6 +1703,9 @@ fld_status fld_set_model(fld_ctx* c, const float* host, size_t count) {
   }
   if (!nn::set_params(c->net, host, count))
     return fail(c, FLD_ERR_MODEL, "non-finite parameter or device error");
+  // a new network is tried at the next step once a reference step exists
+  c->net_span = 0;
+  if (c->plain_units >= 0) c->net_skip = 0;
   return FLD_OK;
 }
 

@@ -96,8 +96,7 @@ __global__ void __launch_bounds__(NTC) k_coef2d(Coef2DArgs P) {
       g2 += G * G;
     }
     const double R = sqrt(g2) / (rk * E0);
-    const double lam =
-        A.limiter == 0 ? (2.0 + R) / (6.0 + 3.0 * R + R * R) : 1.0 / 3.0;
+    const double lam = flux_limiter(A.limiter, R);
     Ds[ly][lx] = A.c * lam / rk;
     // non-physical state of a tile cell
     const bool inside = lx >= 1 && lx <= CX && ly >= 1 && ly <= CY &&

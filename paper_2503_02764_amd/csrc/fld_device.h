@@ -39,6 +39,17 @@ __device__ __forceinline__ int ghost(int m, int n, int per) {
   return m;
 }
 
+// Flux limiter lambda(R): 0 Levermore-Pomraning (eq. fld_lambda), 1 the
+// diffusion value 1/3, 2 Minerbo's (named in Sect. 2 without a formula; its
+// published piecewise form: 2 / (3 + sqrt(9 + 12 R^2)) for R <= 3/2,
+// 1 / (1 + R + sqrt(1 + 2 R)) above, continuous at 2/9).
+__device__ __forceinline__ double flux_limiter(int kind, double R) {
+  if (kind == 0) return (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  if (kind == 1) return 1.0 / 3.0;
+  return R <= 1.5 ? 2.0 / (3.0 + sqrt(9.0 + 12.0 * R * R))
+                  : 1.0 / (1.0 + R + sqrt(1.0 + 2.0 * R));
+}
+
 // Sum over a block of kBlockSize threads; the result is valid in thread 0.
 template <int kBlockSize>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -232,8 +243,7 @@ __device__ __forceinline__ double cell_D(const CoefArgs& A, const double* E,
     g2 += G * G;
   }
   const double R = sqrt(g2) / (rk * E0);
-  const double lam =
-      A.limiter == 0 ? (2.0 + R) / (6.0 + 3.0 * R + R * R) : 1.0 / 3.0;
+  const double lam = flux_limiter(A.limiter, R);
   bad = !(E0 > 0.0) || !(rk > 0.0) || !isfinite(E0) || !isfinite(rk);
   return A.c * lam / rk;
 }

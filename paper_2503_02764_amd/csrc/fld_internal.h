@@ -59,8 +59,24 @@ struct CoefArgs {
   double dx[3];
   double gscale[3];  // 1 / (12 dx): the five-point gradient's scale
   double dt, c;
-  int limiter;   // 0 LP, 1 diffusion
+  int limiter;   // 0 LP, 1 diffusion, 2 Minerbo
   int face_mean; // 0 arithmetic, 1 harmonic
+};
+
+// Explicit source terms of one grid (fld_explicit_sources): inputs E, rho,
+// kappa and ndim velocity components; every output pointer may be null.
+struct ExplicitArgs {
+  Geom g;
+  double gscale[3];  // 1 / (12 dx): the five-point gradient's scale
+  int limiter;
+  const double* E;
+  const double* rho;
+  const double* kappa;
+  const double* v[3];
+  double* fr[3];
+  double* work;
+  double* tiring;
+  double* fedd;
 };
 
 // ---- launch wrappers (kernels live in the .hip files) ----------------------
@@ -170,12 +186,15 @@ hipError_t launch_tail_lds_batch(const TailArgs<T>* tab, int ng, int nd,
 hipError_t launch_ctrl_init(Control* ctrl, double rtol, int max_cycles,
                             int inner, Control* mirror, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_explicit(const ExplicitArgs& a, hipStream_t s);
 // Learned guess judge: mode 0 stores the summed partials as the benchmark
-// |b - A x_prev|^2; mode 1 rejects the guess when its |b - A x|^2 is not
-// smaller (or not finite).  launch_guess_take then copies the guess into
-// the iterate where it was accepted.
+// |b - A x_prev|^2; mode 1 rejects the guess unless its |b - A x|^2 is below
+// q2 times that benchmark (q2 = 1: any smaller residual; q2 = rho^2, rho a
+// V-cycle's contraction: the guess must be worth at least one cycle), or
+// when it is not finite.  launch_guess_take then copies the guess into the
+// iterate where it was accepted.
 hipError_t launch_guess_judge(int mode, const double* partials, int count,
-                              Control* ctrl, hipStream_t s);
+                              double q2, Control* ctrl, hipStream_t s);
 hipError_t launch_guess_take(int64_t n, const double* guess, double* x,
                              const Control* ctrl, hipStream_t s);
 // x = alt where the solve stopped right after a finest down pass

@@ -73,7 +73,7 @@ hipError_t launch_finalize(int mode, const double* partials, int count,
 
 __global__ void __launch_bounds__(kReduceBlock)
     k_guess_judge(int mode, const double* __restrict__ partials, int count,
-                  Control* ctrl) {
+                  double q2, Control* ctrl) {
   __shared__ double sh[kReduceBlock / 64];
   if (ctrl->done != kRunning) return;
   double v = 0.0;
@@ -83,13 +83,13 @@ __global__ void __launch_bounds__(kReduceBlock)
   if (mode == 0)
     ctrl->guess_ref = s;
   else
-    ctrl->guess_rejected = (s < ctrl->guess_ref) ? 0 : 1;  // NaN: rejected
+    ctrl->guess_rejected = (s < q2 * ctrl->guess_ref) ? 0 : 1;  // NaN: rejected
 }
 
 hipError_t launch_guess_judge(int mode, const double* partials, int count,
-                              Control* ctrl, hipStream_t s) {
+                              double q2, Control* ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_guess_judge, dim3(1), dim3(kReduceBlock), 0, s, mode,
-                     partials, count, ctrl);
+                     partials, count, q2, ctrl);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ FLD_ERR_MODEL = 6
 FLD_BC_PERIODIC = 0
 FLD_BC_NEUMANN = 1
 FLD_LIMITER_LP = 0
+FLD_LIMITER_MINERBO = 2
 FLD_LIMITER_DIFFUSION = 1
 FLD_FACE_ARITH = 0
 FLD_FACE_HARMONIC = 1
@@ -32,10 +33,13 @@ FLD_PREC_FP32_IR = 1
 FLD_GUESS_PREV = 0
 FLD_GUESS_ZERO = 1
 FLD_GUESS_LEARNED = 2
+FLD_GUESS_ADAPTIVE = 0
+FLD_GUESS_EVERY_STEP = 1
 
 EXPORTED = [
     "fld_params_default", "fld_workspace_bytes", "fld_setup", "fld_step",
     "fld_step_noalloc", "fld_exchange", "fld_opacity_powerlaw",
+    "fld_explicit_sources",
     "fld_kernel_timing_enable",
     "fld_kernel_timing_read", "fld_destroy", "fld_status_str",
     "fld_last_error", "fld_autotune", "fld_tile_shape_name",
@@ -56,20 +60,21 @@ class fld_params(ctypes.Structure):
         ("ir_inner", ctypes.c_int32),
         ("coarse_pre_smooth", ctypes.c_int32),
         ("coarse_post_smooth", ctypes.c_int32),
+        ("guess_policy", ctypes.c_int32), ("pad1", ctypes.c_int32),
     ]
 
 
 class fld_stats(ctypes.Structure):
     _fields_ = [
         ("cycles", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
-        ("guess_rejected", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("guess_rejected", ctypes.c_int32), ("guess_skipped", ctypes.c_int32),
         ("flagged_cells", ctypes.c_int64),
         ("rel_res_initial", ctypes.c_double),
         ("rel_res_final", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class FldError(RuntimeError):
@@ -106,6 +111,8 @@ def load(path=LIB_PATH):
     lib.fld_step_noalloc.argtypes = [P(fld_params), D, V, V, V, V,
                                      P(fld_stats), V]
     lib.fld_step_noalloc.restype = ctypes.c_int
+    lib.fld_explicit_sources.argtypes = [V, V, V, V, V, V, V, V, V]
+    lib.fld_explicit_sources.restype = ctypes.c_int
     lib.fld_exchange.argtypes = [V, D, V, V, V, V]
     lib.fld_exchange.restype = ctypes.c_int
     lib.fld_opacity_powerlaw.argtypes = [V, V, V, D, D, D, D, D, V]
@@ -247,6 +254,38 @@ def fld_step_noalloc(params, dt, rho, kappa, E_in, E_out, stats=True,
     if check:
         _check(None, st)
     return st, (s.as_dict() if s is not None else None)
+
+
+def fld_explicit_sources(ctx, rho, kappa, E, v=None, f_r=None, work=None,
+                         tiring=None, fedd=None, check=True):
+    """Explicit source terms; v and f_r are lists of ndim device tensors (or
+    None), work / tiring / fedd device tensors or None."""
+    import torch
+    n = ctx.cells
+    nd = int(ctx.params.ndim)
+
+    def arr(ts, name):
+        if ts is None:
+            return None, None
+        if len(ts) != nd:
+            raise ValueError(f"{name} needs {nd} components")
+        a = (ctypes.c_void_p * nd)(*[_ptr(t, f"{name}[{i}]", n, torch.float64)
+                                     for i, t in enumerate(ts)])
+        return ctypes.cast(a, ctypes.c_void_p), a
+
+    vp, _va = arr(v, "v")
+    fp, _fa = arr(f_r, "f_r")
+
+    def opt(t, name):
+        return None if t is None else _ptr(t, name, n, torch.float64)
+
+    st = load().fld_explicit_sources(
+        ctx.ptr, _ptr(rho, "rho", n, torch.float64),
+        _ptr(kappa, "kappa", n, torch.float64), _ptr(E, "E", n, torch.float64),
+        vp, fp, opt(work, "work"), opt(tiring, "tiring"), opt(fedd, "fedd"))
+    if check:
+        _check(ctx.ptr, st)
+    return st
 
 
 def fld_exchange(ctx, dt, rho, kappa, E, e_int, check=True):

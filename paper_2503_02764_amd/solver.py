@@ -9,18 +9,21 @@ from __future__ import annotations
 from . import fld
 
 _BC = {"periodic": fld.FLD_BC_PERIODIC, "neumann": fld.FLD_BC_NEUMANN}
-_LIM = {"lp": fld.FLD_LIMITER_LP, "diffusion": fld.FLD_LIMITER_DIFFUSION}
+_LIM = {"lp": fld.FLD_LIMITER_LP, "diffusion": fld.FLD_LIMITER_DIFFUSION,
+        "minerbo": fld.FLD_LIMITER_MINERBO}
 _FACE = {"arith": fld.FLD_FACE_ARITH, "harmonic": fld.FLD_FACE_HARMONIC}
 _PREC = {"fp64": fld.FLD_PREC_FP64, "fp32_ir": fld.FLD_PREC_FP32_IR}
 _GUESS = {"prev": fld.FLD_GUESS_PREV, "zero": fld.FLD_GUESS_ZERO,
           "learned": fld.FLD_GUESS_LEARNED}
+_POLICY = {"adaptive": fld.FLD_GUESS_ADAPTIVE,
+           "every_step": fld.FLD_GUESS_EVERY_STEP}
 
 
 def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
                 gas_const=1.0, limiter="lp", face_mean="arith",
                 precision="fp64", guess="prev", rtol=1e-8, max_cycles=50,
                 pre_smooth=2, post_smooth=2, ir_inner=0, coarse_pre_smooth=0,
-                coarse_post_smooth=0):
+                coarse_post_smooth=0, guess_policy="adaptive"):
     n = list(n) + [1] * (3 - len(n))
     dx = list(dx) + [1.0] * (3 - len(dx))
     codes = [_BC[b] for b in bc] + [fld.FLD_BC_PERIODIC] * (3 - len(bc))
@@ -32,7 +35,8 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
         max_cycles=max_cycles, pre_smooth=pre_smooth,
         post_smooth=post_smooth, ir_inner=ir_inner,
         coarse_pre_smooth=coarse_pre_smooth,
-        coarse_post_smooth=coarse_post_smooth)
+        coarse_post_smooth=coarse_post_smooth,
+        guess_policy=_POLICY[guess_policy])
 
 
 class Stepper:

@@ -73,7 +73,7 @@ class _Grid:
         from .solver import make_params
         p = make_params(2, (self.n, self.n), (dx, dx), ("neumann", "neumann"),
                         rtol=rtol, precision=precision, guess=guess,
-                        max_cycles=200)
+                        max_cycles=200, guess_policy="every_step")
         need = self.fld.fld_workspace_bytes(p)
         ws = self.ws.get(key)
         if ws is None or ws.numel() < need:

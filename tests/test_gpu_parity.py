@@ -36,7 +36,8 @@ def _solve_gpu(m, **kw):
 
 @pytest.mark.parametrize("n,bc", TINY)
 @pytest.mark.parametrize("limiter,face", [("lp", "arith"),
-                                          ("diffusion", "harmonic")])
+                                          ("diffusion", "harmonic"),
+                                          ("minerbo", "arith")])
 def test_tiny_solve_vs_dense(n, bc, limiter, face):
     m = media.random_small_medium(sum(n) + len(n), n, bc, limiter, face)
     announce(f"tiny solve n={n} bc={bc} {limiter}/{face}")
@@ -45,6 +46,26 @@ def test_tiny_solve_vs_dense(n, bc, limiter, face):
                            F.problem_from_medium(m), method="dense")
     assert stats["rel_res_final"] <= 1e-12
     assert rel_l2(x, ref) <= 1e-10, (stats, rel_l2(x, ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_minerbo_limiter_c2_statistics_vs_oracle(precision):
+    """Minerbo's limiter on a 256^2 medium of the 2D workload's statistics
+    with a fifth of its opacity, so that R spans both branches of the
+    limiter (R = 3/2 falls inside its range): the LDS-tiled coefficient
+    stage and the solve against the oracle's sparse direct solve."""
+    m = media.config_c2(n=256)
+    m.limiter = "minerbo"
+    prob = F.problem_from_medium(m)
+    kap = 0.2 * F.opacity_powerlaw(m.rho, m.e, prob, **m.opacity)
+    _, R, _ = F.diffusion_coefficient(m.E, m.rho, kap, prob)
+    assert R.min() < 1.5 < R.max()
+    m.kappa = kap
+    announce(f"minerbo c2 statistics 256^2 {precision}")
+    x, stats = _solve_gpu(m, rtol=1e-12 if precision == "fp64" else 1e-10,
+                          precision=precision, max_cycles=200)
+    ref = F.diffusion_step(m.E, m.rho, kap, m.dt, prob, method="splu")
+    assert rel_l2(x, ref) <= (1e-10 if precision == "fp64" else 1e-8), stats
 
 
 @pytest.mark.parametrize("n", [128, 256])

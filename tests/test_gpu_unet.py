@@ -286,7 +286,9 @@ def _zero_model(head_bias):
 
 
 def _learned_step(m, kap, model, **kw):
+    """One step with the network evaluated (FLD_GUESS_EVERY_STEP)."""
     from paper_2503_02764_amd import fld
+    kw.setdefault("guess_policy", "every_step")
     ctx = fld.fld_setup(params_for(m, guess="learned", **kw))
     fld.fld_set_model(ctx, model)
     out = dev(np.zeros_like(m.E))
@@ -435,3 +437,56 @@ def test_adam_three_steps_match_oracle():
         assert np.mean(err <= tol) >= 0.999, (step, np.sort(err - tol)[-5:])
         assert err.max() <= 2 * lr * step
         pd["w"] = got  # carry the GPU's FP32 parameters forward
+
+
+def test_adaptive_policy_on_heldout_1024():
+    """The default network policy (FLD_GUESS_ADAPTIVE) on the 1024^2
+    workload, a medium the network never saw (it was trained on 256^2 media
+    of other seeds), over 12 steps that each start both solvers from the
+    same E^n: a step that ran without the network is bit for bit a plain
+    step; a step whose guess the judge accepted needed no more V-cycles than
+    the plain step (the judge asks the guess's smoothed residual to be a
+    cycle's contraction below that of E^n); the first step runs without
+    the network and unproductive tries pause it."""
+    import torch
+    import bench
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.guess import load_weights
+    from paper_2503_02764_amd.solver import Stepper
+    m = media.config_c2(n=1024)
+    kw = dict(rtol=1e-8, pre_smooth=bench.PRE, post_smooth=bench.POST,
+              coarse_pre_smooth=bench.COARSE_PRE,
+              coarse_post_smooth=bench.COARSE_POST)
+    plain = Stepper(params_for(m, **kw), opacity=m.opacity)
+    lrn = fld.fld_setup(params_for(m, guess="learned", **kw))
+    fld.fld_set_model(lrn, load_weights())
+    rho, E, e = dev(m.rho), dev(m.E), dev(m.e)
+    kap = torch.empty_like(rho)
+    o = m.opacity
+    announce("adaptive learned-guess policy, 12 steps of 1024^2")
+    net_steps, accepted, cyc_p, cyc_l = 0, 0, 0, 0
+    for step in range(12):
+        fld.fld_opacity_powerlaw(plain.ctx, rho, e, o["k0"], o["a"], o["b"],
+                                 o["kmin"], o["kmax"], kap)
+        xp, xl = torch.empty_like(E), torch.empty_like(E)
+        _, sp = fld.fld_step(plain.ctx, m.dt, rho, kap, E, xp)
+        _, sl = fld.fld_step(lrn, m.dt, rho, kap, E, xl)
+        cyc_p += sp["cycles"]
+        cyc_l += sl["cycles"]
+        if sl["guess_skipped"]:
+            assert torch.equal(xl, xp), step
+            assert sl["cycles"] == sp["cycles"]
+        else:
+            net_steps += 1
+            if not sl["guess_rejected"]:
+                accepted += 1
+                assert sl["cycles"] <= sp["cycles"], (step, sp, sl)
+        assert sl["rel_res_final"] <= 1e-8
+        if step == 0:
+            assert sl["guess_skipped"] == 1
+        fld.fld_exchange(plain.ctx, m.dt, rho, kap, xp, e)
+        E = xp
+    print(f"network on {net_steps} of 12 steps, accepted {accepted}; "
+          f"V-cycles {cyc_l} (plain {cyc_p})")
+    assert 1 <= net_steps <= 11
+    assert cyc_l <= cyc_p

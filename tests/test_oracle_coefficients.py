@@ -224,3 +224,24 @@ def test_face_means_hand_values_2d(face_mean, ax_expect, ay_expect):
                                  prob)
     np.testing.assert_allclose(ax, ax_expect, rtol=1e-15, atol=0)
     np.testing.assert_allclose(ay, ay_expect, rtol=1e-15, atol=0)
+
+
+def test_minerbo_limiter_hand_values_and_limits():
+    """Minerbo's limiter (its published piecewise form; Sect. 2 names it
+    without a formula): lambda(0) = 1/3; at R = 1 the lower branch gives
+    2 / (3 + sqrt 21) = 0.263763...; at R = 3/2 both branches give 2/9
+    (2 / (3 + 6) and 1 / (1 + 3/2 + 2)); at R = 4, 1 / (5 + 3) = 1/8;
+    decreasing; lambda R -> 1 in the free-streaming limit; below LP's
+    value for R > 0."""
+    lam = F.limiter
+    assert lam(0.0, "minerbo") == pytest.approx(1.0 / 3.0, rel=1e-15)
+    assert lam(1.0, "minerbo") == pytest.approx(2.0 / (3.0 + np.sqrt(21.0)),
+                                                rel=1e-15)
+    assert lam(1.5, "minerbo") == pytest.approx(2.0 / 9.0, rel=1e-15)
+    assert lam(1.5 + 1e-12, "minerbo") == pytest.approx(2.0 / 9.0, rel=1e-10)
+    assert lam(4.0, "minerbo") == pytest.approx(0.125, rel=1e-15)
+    R = np.logspace(-4, 8, 400)
+    m = lam(R, "minerbo")
+    assert np.all(np.diff(m) < 0)
+    assert abs(lam(1e9, "minerbo") * 1e9 - 1.0) < 1e-4
+    assert np.all(m < lam(R, "lp"))
