@@ -82,7 +82,7 @@ typedef enum { FLD_GUESS_PREV = 0, FLD_GUESS_ZERO = 1, FLD_GUESS_LEARNED = 2 } f
  * its count of V-cycles (FP64) or refinement iterations (FP32_IR) becomes
  * the reference, which every later step without the network renews.  A
  * step with the network that does not lower that count (or whose guess the
- * residual judge rejects) makes the next 1, 2, 4, 8, then 16 steps run
+ * residual judge rejects) makes the next 2, 4, 8, 16, then 32 steps run
  * without it before it is tried again; a step where it lowers the count
  * keeps it on for the next step.  A step without the network is exactly a
  * step with guess E^n.  FLD_GUESS_EVERY_STEP: the network runs on every
@@ -115,14 +115,18 @@ typedef struct {
   int32_t coarse_post_smooth;  /* sweeps after prolongation on the coarse
                                   levels; 0: post_smooth                  */
   int32_t guess_policy;  /* fld_guess_policy (learned guess only)         */
-  int32_t pad1;
+  int32_t krylov;        /* 0: the V-cycle is the iteration; 1: V-cycles
+                            precondition flexible conjugate gradients
+                            (stays convergent where coefficient jumps make
+                            a V-cycle overshoot); single grids only      */
 } fld_params;
 
 typedef struct {
   int32_t cycles;          /* fine-level V-cycles started (the last one may
                               stop after its pre-smoothing, where it found
                               the residual below rtol)                     */
-  int32_t outer_iters;     /* FP64 refinement iterations (FP32_IR), else 0 */
+  int32_t outer_iters;     /* FP64 refinement iterations (FP32_IR) or
+                              flexible-CG iterations (krylov), else 0     */
   int32_t guess_rejected;  /* 1 when a learned guess lost to E^n          */
   int32_t guess_skipped;   /* 1 when FLD_GUESS_ADAPTIVE ran this step
                               without the network (guess E^n)              */

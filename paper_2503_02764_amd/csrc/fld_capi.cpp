@@ -115,6 +115,13 @@ struct fld_ctx {
   // the square of that step's contraction per V-cycle or refinement
   // iteration, so that an accepted guess is predicted to save one
   double judge_q2 = 1.0;
+  // flexible CG around the V-cycle (fld_params.krylov)
+  bool krylov = false;
+  bool precond = false;  // V-cycles run as a preconditioner: no stop test
+  double* kr_r = nullptr;
+  double* kr_p[2] = {};
+  double* kr_q = nullptr;
+  double* kr_z = nullptr;
 };
 
 namespace {
@@ -182,8 +189,9 @@ fld_status static_scratch(void** out) {
   return FLD_OK;
 }
 constexpr int64_t kMaxCoarsestCells = 1 << 16;
-// longest run of steps the adaptive policy takes without the network
-constexpr int kMaxNetPause = 16;
+// pauses of the adaptive policy: 2, 4, ... up to this many steps without
+// the network after each try that saved nothing
+constexpr int kMaxNetPause = 32;
 // 3D levels of at least this many cells smooth by fused sweeps (smaller
 // ones are launch-latency bound, where a block's march through its planes
 // costs more than the second colour launch)
@@ -207,6 +215,7 @@ struct Plan {
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
   size_t dscr = 0;  // 3D coefficient stage: D per cell
   size_t guess = 0;
+  size_t kr_r = 0, kr_p[2] = {}, kr_q = 0, kr_z = 0;  // flexible CG vectors
   size_t net_bytes = 0;
   int64_t n_partials = 0;
   size_t total = 0;
@@ -279,6 +288,7 @@ std::string validate(const fld_params* p) {
   if (p->guess_policy != FLD_GUESS_ADAPTIVE &&
       p->guess_policy != FLD_GUESS_EVERY_STEP)
     return "unknown guess_policy";
+  if (p->krylov != 0 && p->krylov != 1) return "krylov must be 0 or 1";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->ir_inner < 0 || p->ir_inner > 8) return "ir_inner must be in [0, 8]";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
@@ -354,6 +364,8 @@ void make_plan(const fld_params* p, Plan* P) {
         const int64_t t = tile2d_blocks(P->g[0], nu, true, v);
         if (t > nparts) nparts = t;
       }
+  if (p->krylov)  // (p, q) and (p, r) partials of the flexible-CG passes
+    nparts = std::max<int64_t>(nparts, 2 * (int64_t)krylov_blocks(P->g[0]));
   P->n_partials = nparts + 64;
   P->partials = take((size_t)P->n_partials * 8);
   P->tmp = take((size_t)P->g[P->L - 1].N * 8);
@@ -366,6 +378,14 @@ void make_plan(const fld_params* p, Plan* P) {
                                        (int)p->n[0], 0);
     P->net = take(P->net_bytes);
     P->guess = take((size_t)P->g[0].N * 8);
+  }
+  if (p->krylov) {
+    const size_t n0 = (size_t)P->g[0].N * 8;
+    P->kr_r = take(n0);
+    P->kr_p[0] = take(n0);
+    P->kr_p[1] = take(n0);
+    P->kr_q = take(n0);
+    if (!mixed) P->kr_z = take(n0);  // FP32_IR: z is the FP32 level-0 iterate
   }
   P->total = o;
 }
@@ -490,7 +510,7 @@ fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
 // the residual norm feeds the stop test.
 template <typename T>
 fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
-  const bool norm = (sizeof(T) == 8) && l == 0;
+  const bool norm = (sizeof(T) == 8) && l == 0 && !c->precond;
   int nb = 0;
   if (tile_path(c)) {
     Tile2DArgs<T> a{};
@@ -712,6 +732,75 @@ fld_status solve_mixed(fld_ctx* c) {
   if (c->host_ctrl->done == kRunning) c->host_ctrl->done = kCapped;
   if (c->host_ctrl->done == kConverged)
     c->last_batch = c->host_ctrl->outer + 1;
+  return FLD_OK;
+}
+
+// Flexible conjugate gradients preconditioned by V-cycles (FP64 V-cycles,
+// or `inner` FP32 V-cycles in FP32_IR) until the device stop flag is set.
+// The FP64 residual is carried by the recurrence r -= alpha A p; its norm
+// is the stop test.  Iterations are enqueued in batches like the V-cycles
+// of solve_fp64 (launches after the stop return at once).
+fld_status solve_krylov(fld_ctx* c) {
+  const Geom& g0 = c->geom[0];
+  KrylovArgs K{};
+  K.g = g0;
+  for (int d = 0; d < g0.ndim; ++d) K.a[d] = c->h64.a[0][d];
+  K.r = c->kr_r;
+  K.r32 = c->mixed ? c->h32.b[0] : nullptr;
+  K.q = c->kr_q;
+  K.partials = c->partials;
+  K.ctrl = c->ctrl;
+  const int nb = krylov_blocks(g0);
+  HIP_TRY(c, launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream));
+  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl,
+                             c->stream));
+  // FP64 preconditioner: level 0 of the hierarchy solves A z = r from zero
+  Levels<double> pre = c->h64;
+  pre.x[0] = c->kr_z;
+  pre.b[0] = c->kr_r;
+  const int per = c->mixed ? c->inner : 1;
+  const int max_iter = c->p.max_cycles / per + 1;
+  int k = 0;
+  int batch = c->last_batch < 1 ? 1 : c->last_batch;
+  c->precond = true;
+  fld_status st = FLD_OK;
+  for (;;) {
+    for (int j = 0; j < batch && k < max_iter && st == FLD_OK; ++j, ++k) {
+      K.p_old = c->kr_p[(k + 1) & 1];
+      K.p_new = c->kr_p[k & 1];
+      if (c->mixed) {
+        for (int i = 0; i < c->inner && st == FLD_OK; ++i)
+          st = vcycle<float>(c, c->h32, i == 0);
+      } else {
+        st = vcycle<double>(c, pre, true);
+      }
+      if (st != FLD_OK) break;
+      hipError_t e = hipSuccess;
+      if (k > 0) {
+        e = c->mixed ? launch_fcg_zq<float>(K, c->h32.x[0], c->stream)
+                     : launch_fcg_zq<double>(K, c->kr_z, c->stream);
+        if (e == hipSuccess) e = launch_fcg_scalar(0, K, c->stream);
+      }
+      if (e == hipSuccess)
+        e = c->mixed ? launch_fcg_dir<float>(K, c->h32.x[0], k == 0, c->stream)
+                     : launch_fcg_dir<double>(K, c->kr_z, k == 0, c->stream);
+      if (e == hipSuccess) e = launch_fcg_scalar(1, K, c->stream);
+      if (e == hipSuccess) e = launch_fcg_update(K, c->h64.x[0], c->stream);
+      if (e == hipSuccess)
+        e = launch_finalize(kFinKrylov, c->partials, nb, c->ctrl, c->stream);
+      if (e != hipSuccess)
+        st = fail(c, FLD_ERR_DEVICE, "flexible CG launch: %s",
+                  hipGetErrorString(e));
+    }
+    if (st != FLD_OK) break;
+    st = read_control(c);
+    if (st != FLD_OK || c->host_ctrl->done != kRunning || k >= max_iter) break;
+    batch = 2;
+  }
+  c->precond = false;
+  FLD_TRY(st);
+  if (c->host_ctrl->done == kRunning) c->host_ctrl->done = kCapped;
+  if (c->host_ctrl->done == kConverged) c->last_batch = c->host_ctrl->outer;
   return FLD_OK;
 }
 
@@ -1235,6 +1324,14 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
     c->net_bytes = P.net_bytes;
     c->guess = (double*)(w + P.guess);
   }
+  c->krylov = p->krylov != 0;
+  if (c->krylov) {
+    c->kr_r = (double*)(w + P.kr_r);
+    c->kr_p[0] = (double*)(w + P.kr_p[0]);
+    c->kr_p[1] = (double*)(w + P.kr_p[1]);
+    c->kr_q = (double*)(w + P.kr_q);
+    c->kr_z = P.kr_z ? (double*)(w + P.kr_z) : nullptr;
+  }
 }
 
 }  // namespace
@@ -1328,7 +1425,8 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
   double* copy_dst = aliased ? c->bcopy
                              : (c->p.guess == FLD_GUESS_ZERO ? nullptr : E_out);
-  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles, c->inner,
+  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles,
+                             (c->krylov && !c->mixed) ? 1 : c->inner,
                              c->host_ctrl_dev, c->stream));
   CoefArgs A;
   A.g = g0;
@@ -1342,7 +1440,7 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   A.face_mean = c->p.face_mean;
   // 2D grids: the LDS-tiled coefficient stage; with x0 = E^n in FP64 it also
   // forms the initial residual, so the solve needs no separate first pass
-  c->init_fused = coef2d_ok(g0) && !c->mixed && prev_guess;
+  c->init_fused = coef2d_ok(g0) && !c->mixed && prev_guess && !c->krylov;
   if (coef2d_ok(g0)) {
     HIP_TRY(c, launch_coef2d(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
                              copy_dst, c->partials, c->ctrl, c->init_fused,
@@ -1382,7 +1480,8 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
   if (use_net) FLD_TRY(learned_guess(c, rho, kappa));
-  FLD_TRY(c->mixed ? solve_mixed(c) : solve_fp64(c));
+  FLD_TRY(c->krylov ? solve_krylov(c)
+                    : (c->mixed ? solve_mixed(c) : solve_fp64(c)));
   FLD_TRY(collect_timing(c));
   const Control& h = *c->host_ctrl;
   if (learned && c->p.guess_policy == FLD_GUESS_ADAPTIVE &&
@@ -1398,7 +1497,7 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
       }
     } else if (h.guess_rejected ||
                (c->plain_units >= 0 && units >= c->plain_units)) {
-      c->net_span = std::min(std::max(1, 2 * c->net_span), kMaxNetPause);
+      c->net_span = std::min(std::max(2, 2 * c->net_span), kMaxNetPause);
       c->net_skip = c->net_span;
     } else {
       c->net_span = 0;
@@ -1409,7 +1508,7 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     stats->cycles = h.cycles;
     stats->guess_rejected = use_net ? h.guess_rejected : 0;
     stats->guess_skipped = learned && !use_net;
-    stats->outer_iters = c->mixed ? h.outer : 0;
+    stats->outer_iters = (c->mixed || c->krylov) ? h.outer : 0;
     stats->flagged_cells = h.flagged;
     stats->rel_res_initial = h.res_initial;
     stats->rel_res_final = h.res;
@@ -1803,6 +1902,7 @@ static std::string validate_batch(int32_t count, const fld_params* each) {
         nu_post(p, 1) != nu_post(each[0], 1))
       return "batched grids need equal pre/post smoothing in 1..3";
     if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
+    if (p.krylov) return "batched grids iterate V-cycles (krylov = 0)";
     if (p.ir_inner != each[0].ir_inner)
       return "batched grids must share ir_inner";
     Plan P;

@@ -150,6 +150,9 @@ __device__ __forceinline__ void ctrl_init_body(Control* ctrl, double rtol,
     ctrl->guess_ref = 0.0;
     ctrl->guess_rejected = 0;
     ctrl->stop_in_down = 0;
+    ctrl->fcg_beta = 0.0;
+    ctrl->fcg_alpha = 0.0;
+    ctrl->fcg_pq = 0.0;
   }
 }
 
@@ -200,6 +203,15 @@ __device__ __forceinline__ void finalize_update(int mode, double s,
   if (mode == kFinInitial) {
     ctrl->res_initial = r;
     if (r <= ctrl->rtol) ctrl->done = kConverged;
+    return;
+  }
+  if (mode == kFinKrylov) {
+    ctrl->outer += 1;
+    ctrl->cycles += ctrl->inner;
+    if (r <= ctrl->rtol)
+      ctrl->done = kConverged;
+    else if (ctrl->cycles >= ctrl->max_cycles)
+      ctrl->done = kCapped;
     return;
   }
   if (mode == kFinOuter) {

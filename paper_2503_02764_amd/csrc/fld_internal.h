@@ -49,6 +49,9 @@ struct Control {
   int32_t stop_in_down;    // the stop test fired after a finest down pass
                            // (tiled path: the iterate is in the alternate
                            // buffer)
+  double fcg_beta;    // flexible CG: the current direction's beta,
+  double fcg_alpha;   // step length,
+  double fcg_pq;      // and (p, A p) of the last direction
   Control* mirror;    // device address of the host-visible copy (or null)
 };
 
@@ -213,8 +216,36 @@ enum FinalizeMode {
   kFinInitial = 1,
   kFinCycle = 2,
   kFinOuter = 3,
-  kFinCoef = 4  // |b|^2 in partials[0, count), |b - A x0|^2 in [count, 2 count)
+  kFinCoef = 4,  // |b|^2 in partials[0, count), |b - A x0|^2 in [count, 2 count)
+  kFinKrylov = 5  // |r|^2 after a flexible-CG iteration (counts iterations)
 };
+
+// Flexible CG around the V-cycle (fld_krylov.hip): level-0 geometry and
+// face coefficients, the FP64 residual r (and its FP32 copy for FP32
+// V-cycles, or null), the previous and new directions p, q = A p, block
+// partials and the control block (scalars beta, alpha, (p, q)).
+struct KrylovArgs {
+  Geom g;
+  const double* a[3];
+  double* r;
+  float* r32;
+  const double* p_old;
+  double* p_new;
+  double* q;
+  double* partials;
+  Control* ctrl;
+};
+constexpr int kKrylovBlocks = 1024;
+int krylov_blocks(const Geom& g);  // blocks (and partials) of each pass
+hipError_t launch_fcg_init(const KrylovArgs& K, const double* x,
+                           const double* b, hipStream_t s);
+template <typename TZ>
+hipError_t launch_fcg_zq(const KrylovArgs& K, const TZ* z, hipStream_t s);
+template <typename TZ>
+hipError_t launch_fcg_dir(const KrylovArgs& K, const TZ* z, int first,
+                          hipStream_t s);
+hipError_t launch_fcg_update(const KrylovArgs& K, double* x, hipStream_t s);
+hipError_t launch_fcg_scalar(int mode, const KrylovArgs& K, hipStream_t s);
 
 // Colour classes of the Gauss-Seidel sweeps.  Red-black by (x + y + z) & 1
 // is a proper colouring unless a periodic dimension has odd length: there

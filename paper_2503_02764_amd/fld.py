@@ -60,7 +60,7 @@ class fld_params(ctypes.Structure):
         ("ir_inner", ctypes.c_int32),
         ("coarse_pre_smooth", ctypes.c_int32),
         ("coarse_post_smooth", ctypes.c_int32),
-        ("guess_policy", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("guess_policy", ctypes.c_int32), ("krylov", ctypes.c_int32),
     ]
 
 

@@ -23,7 +23,7 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
                 gas_const=1.0, limiter="lp", face_mean="arith",
                 precision="fp64", guess="prev", rtol=1e-8, max_cycles=50,
                 pre_smooth=2, post_smooth=2, ir_inner=0, coarse_pre_smooth=0,
-                coarse_post_smooth=0, guess_policy="adaptive"):
+                coarse_post_smooth=0, guess_policy="adaptive", krylov=False):
     n = list(n) + [1] * (3 - len(n))
     dx = list(dx) + [1.0] * (3 - len(dx))
     codes = [_BC[b] for b in bc] + [fld.FLD_BC_PERIODIC] * (3 - len(bc))
@@ -36,7 +36,7 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
         post_smooth=post_smooth, ir_inner=ir_inner,
         coarse_pre_smooth=coarse_pre_smooth,
         coarse_post_smooth=coarse_post_smooth,
-        guess_policy=_POLICY[guess_policy])
+        guess_policy=_POLICY[guess_policy], krylov=int(bool(krylov)))
 
 
 class Stepper:
