@@ -9,10 +9,11 @@ plain FP64 multigrid, timed over --steps steps after --warmup.  The same
 line carries the metric's comparison on that workload (FP32 V-cycles in FP64
 refinement, the learned guess with either precision), the dominant kernel's
 roofline (HIP events the kernel's own launches record over the timed
-region), and under `configs` the 3D 256^3 stratified workload (50 steps,
-FP64 / FP32 refinement / learned guess, each step's error bound against the
-exact solve, one step checked by the CPU oracle) and the 96 batched 2D grids
-(20 steps).  `cpu_baseline` is the FP64 oracle on the host's cores, timed
+region), and under `configs` the 3D 256^3 stratified workload (its first
+12 steps: FP64 / FP32 refinement / both inside flexible CG / learned guess,
+each step's error bound against the exact solve from its FP64 residual, and
+the explicit-source kernel's roofline) and the 96 batched 2D grids (20
+steps).  `cpu_baseline` is the FP64 oracle on the host's cores, timed
 on a bounded sample before the GPU is touched.
 """
 from __future__ import annotations
@@ -437,13 +438,13 @@ def run_c2(args, weights):
 # 3D 256^3 stratified medium
 # ---------------------------------------------------------------------------
 
-def run_c3(steps, warmup, weights, oracle_check=True):
-    """FP64 V-cycles, FP32 V-cycles in FP64 refinement, and the latter with
-    the learned guess applied per z-slice, each from the initial state over
-    `steps` steps.  Every step's error against its exact solve is bounded by
-    its FP64 relative residual x sqrt(N)|b|/sum(b); after the timed steps of
-    the FP32 refinement one more step is taken untimed and the CPU oracle
-    measures the residual of its iterate under its own operator."""
+def run_c3(steps, warmup, weights):
+    """FP64 V-cycles, FP32 V-cycles in FP64 refinement, both inside flexible
+    CG, and FP32 refinement with the learned guess applied per z-slice,
+    each from the initial state over `steps` steps.  Every step's error
+    against its exact solve is bounded by its FP64 relative residual x
+    sqrt(N)|b|/sum(b) (the GPU tests check, on the same workload, that the
+    oracle's own residual of the iterate agrees with the GPU's)."""
     import numpy as np
     import torch
     import media
@@ -455,8 +456,7 @@ def run_c3(steps, warmup, weights, oracle_check=True):
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
-    def run(precision, weights=None, check=False, policy="adaptive",
-            krylov=False):
+    def run(precision, weights=None, policy="adaptive", krylov=False):
         params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
                              guess="prev" if weights is None else "learned",
                              guess_policy=policy, krylov=krylov,
@@ -504,15 +504,14 @@ def run_c3(steps, warmup, weights, oracle_check=True):
         if weights is not None:
             r["network_steps"] = steps - int(np.sum(skip))
             r["guess_rejected_steps"] = int(np.sum(rej))
-        if check:
-            r["oracle_checked_step"] = _oracle_check_c3(m, st, rho, kap, E, e)
         E_out = E.cpu().numpy()
         del st, rho, E, e, kap
         torch.cuda.empty_cache()
         return r, E_out
 
+    explicit = _explicit_roofline(m)
     f64, E64 = run("fp64")
-    f32, E32 = run("fp32_ir", check=oracle_check)
+    f32, E32 = run("fp32_ir")
     k64, _ = run("fp64", krylov=True)
     k32, _ = run("fp32_ir", krylov=True)
     lrn, _ = run("fp32_ir", weights)
@@ -535,6 +534,7 @@ def run_c3(steps, warmup, weights, oracle_check=True):
         "learned_fp32_vs_plain_fp64": lrn["value"] / f64["value"],
         "learned_fp32_krylov_vs_plain_fp64": lrnk["value"] / f64["value"],
         "roofline": f32["roofline"],
+        "explicit_sources": explicit,
         "variants": {"fp64_plain_mg": f64, "fp32_vcycles_fp64_refinement": f32,
                      "fp64_vcycles_in_flexible_cg": k64,
                      "fp32_vcycles_in_fp64_flexible_cg": k32,
@@ -545,26 +545,43 @@ def run_c3(steps, warmup, weights, oracle_check=True):
     }
 
 
-def _oracle_check_c3(m, st, rho, kap, E, e):
-    """One more (untimed) step; the oracle rebuilds the operator from the
-    step's inputs and measures the residual of the GPU iterate."""
+def _explicit_roofline(m, reps=10):
+    """fld_explicit_sources on the 256^3 medium with a seeded velocity field,
+    all outputs: algorithmic bytes (E, rho, kappa, 3 velocity components
+    read; 3 force components, work, tiring, Eddington factor written: 96 B
+    per cell) over the mean time per launch (torch events on the context's
+    stream, which is torch's current stream here)."""
     import numpy as np
     import torch
+    import media
     from paper_2503_02764_amd import fld
-    from oracle import fldref as F
-    o = st.opacity
-    fld.fld_opacity_powerlaw(st.ctx, rho, e, o["k0"], o["a"], o["b"],
+    from paper_2503_02764_amd.solver import make_params
+    ctx = fld.fld_setup(make_params(3, m.n, m.dx, m.bc))
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    rho, E = d(m.rho), d(m.E)
+    kap = torch.full_like(rho, 1.0)
+    o = m.opacity
+    fld.fld_opacity_powerlaw(ctx, rho, d(m.e), o["k0"], o["a"], o["b"],
                              o["kmin"], o["kmax"], kap)
-    En = E.cpu().numpy()
-    Es = torch.empty_like(E)
-    _, s = fld.fld_step(st.ctx, m.dt, rho, kap, E, Es)
-    prob = F.problem_from_medium(m)
-    alphas = F.face_coefficients(En, m.rho, kap.cpu().numpy(), m.dt, prob)
-    rr = F.relative_residual(Es.cpu().numpy(), En, alphas, prob)
-    b = En.ravel()
-    factor = float(np.sqrt(b.size) * np.linalg.norm(b) / b.sum())
-    return {"oracle_rel_residual": rr, "gpu_rel_residual": s["rel_res_final"],
-            "error_bound_vs_exact_solve": rr * factor}
+    v = [d(c) for c in media.velocity_field(m.E.shape, 3, seed=31, ell=8.0)]
+    outs = [torch.empty_like(rho) for _ in range(6)]
+    args = (ctx, rho, kap, E, v, outs[:3], outs[3], outs[4], outs[5])
+    fld.fld_explicit_sources(*args)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fld.fld_explicit_sources(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = 96.0 * m.cells
+    gbs = nbytes / (us * 1e-6) / 1e9
+    del ctx, outs, v
+    torch.cuda.empty_cache()
+    return {"bound": "hbm", "kernel": "k_explicit", "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "avg_launch_us": us,
+            "algorithmic_bytes_per_launch": nbytes, "launches": reps}
 
 
 # ---------------------------------------------------------------------------
@@ -716,6 +733,9 @@ def main():
                     help="all: the headline line with the 3D and batched "
                          "configs under `configs`; c2 / c3 / c4: one workload "
                          "alone (for profiling)")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only run the learned guess's network on a 1024^2 "
+                         "image (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -727,7 +747,8 @@ def main():
 
     cpu = None
     if (not args.no_cpu_baseline and not args.headline_only
-            and not args.copy_calibration and args.workload in ("all", "c2")):
+            and not args.copy_calibration and not args.unet_only
+            and args.workload in ("all", "c2")):
         cpu = cpu_baseline()  # before this process touches the GPU
 
     import torch
@@ -745,9 +766,28 @@ def main():
     torch.cuda.set_device(0)
     from paper_2503_02764_amd.guess import load_weights
     weights = load_weights()
+    if args.unet_only:
+        from paper_2503_02764_amd import fld
+        from paper_2503_02764_amd.train_guess import forward_flops
+        n = args.n
+        net = fld.fldnn_create(1, n, n, training=False)
+        fld.fldnn_set_params(net, weights)
+        xin = torch.randn(n * n * 4, dtype=torch.float32, device="cuda")
+        dout = torch.empty(n * n, dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup):
+            fld.fldnn_forward(net, xin, dout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fld.fldnn_forward(net, xin, dout)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        fl = forward_flops(n, n)
+        print(json.dumps({"unet_forward_ms": ms, "n": n,
+                          "tflops": fl / (ms * 1e-3) / 1e12}))
+        return
     if args.workload == "c3":
-        r = run_c3(min(args.steps, C3_STEPS), min(args.warmup, 1), weights,
-                   oracle_check=False)
+        r = run_c3(min(args.steps, C3_STEPS), min(args.warmup, 1), weights)
         args.steps, args.warmup = r["steps"], r["warmup"]
         _line(r["value"], r["ms_per_step"], args, r["workload"], "f32",
               {"roofline": r["roofline"], "c3": r,

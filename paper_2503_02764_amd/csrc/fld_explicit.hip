@@ -9,7 +9,8 @@
 //
 // One thread per cell, one pass: E and the velocity components are read
 // with their stencil neighbours (cache hits after the first touch), rho and
-// kappa once, and each requested output written once.  Expanding
+// kappa once, and each requested output written once.  The cell's
+// coordinates come from the launch grid, not from index divisions.  Expanding
 //   P : grad v = E [ (1 - f)/2 div v + (3 f - 1)/2 n . (grad v) . n ]
 // keeps the Eddington tensor implicit: no 3 x 3 array per thread.
 #include "fld_internal.h"
@@ -30,11 +31,18 @@ __device__ __forceinline__ double grad5(const double* __restrict__ f,
   return (m2 - 8.0 * m1 + 8.0 * p1 - p2) * scale;
 }
 
-__global__ void __launch_bounds__(kBlock) k_explicit(ExplicitArgs A) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= A.g.N) return;
-  int c[3];
-  coords(A.g, idx, c);
+// Launch grid: 64-cell x-runs by 4 rows per 256-thread block, one plane per
+// blockIdx.z (no index divisions; a row's stencil neighbours along x share
+// cache lines, those along y and z the block's and its neighbours' rows).
+constexpr int kEX = 64, kEY = 4;
+
+__global__ void __launch_bounds__(kEX * kEY) k_explicit(ExplicitArgs A) {
+  const int x = blockIdx.x * kEX + threadIdx.x % kEX;
+  const int y = blockIdx.y * kEY + threadIdx.x / kEX;
+  const int z = blockIdx.z;
+  if (x >= A.g.n[0] || y >= A.g.n[1]) return;
+  const int c[3] = {x, y, z};
+  const int64_t idx = ((int64_t)z * A.g.n[1] + y) * A.g.n[0] + x;
   const int nd = A.g.ndim;
   double G[3] = {0.0, 0.0, 0.0};
   double g2 = 0.0;
@@ -72,8 +80,9 @@ __global__ void __launch_bounds__(kBlock) k_explicit(ExplicitArgs A) {
 
 hipError_t launch_explicit(const ExplicitArgs& a, hipStream_t s) {
   if (a.g.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_explicit, dim3(blocks_for(a.g.N)), dim3(kBlock), 0, s,
-                     a);
+  const dim3 grid((a.g.n[0] + kEX - 1) / kEX, (a.g.n[1] + kEY - 1) / kEY,
+                  a.g.n[2]);
+  hipLaunchKernelGGL(k_explicit, grid, dim3(kEX * kEY), 0, s, a);
   return hipGetLastError();
 }
 

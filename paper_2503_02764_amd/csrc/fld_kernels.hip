@@ -14,6 +14,9 @@
 #include "fld_device.h"
 
 #include <limits.h>
+#include <stdlib.h>
+
+#include <algorithm>
 #include <math.h>
 
 namespace fld {
@@ -550,11 +553,150 @@ __global__ void __launch_bounds__(kRRT)
   }
 }
 
+// Residual + restriction of a large 3D level marching through z: a block
+// owns a tile of 64 x kRRY columns (two cells along x per thread) and walks
+// a chunk of `zc` fine planes (even) upwards, keeping the iterate of the
+// planes below, at and above the current one, and the face coefficient
+// below it, in registers, so each plane of x and of alpha_z is fetched once
+// instead of again as the neighbour of the next block's plane pair.  The
+// residual takes the faces in residual_value's order (-x, +x, -y, +y, -z,
+// +z) and each coarse cell sums its eight children in the same order as
+// k_resid_restrict_3d.  A 1D launch: tiles are numbered x fastest, then y,
+// then z chunk, and each XCD (blocks are dealt round-robin over the 8)
+// takes a contiguous run of tile numbers, so a tile's neighbours in y share
+// its XCD's L2.
+template <typename T>
+__global__ void __launch_bounds__(32 * kRRY)
+    k_resid_restrict_3dm(LevelView<T> F, LevelView<T> C, int zc, int gx,
+                         int gy, double* __restrict__ partials,
+                         const Control* __restrict__ ctrl) {
+  __shared__ double sh[32 * kRRY / 64];
+  __shared__ T R[2][kRRY][64];
+  if (ctrl->done != kRunning) return;
+  const int nbk = gridDim.x, bk = blockIdx.x;
+  const int tile = (nbk % 8 == 0) ? (bk % 8) * (nbk / 8) + bk / 8 : bk;
+  const int bxi = tile % gx, byi = (tile / gx) % gy, bzi = tile / (gx * gy);
+  const Geom& g = F.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2], perz = g.per[2];
+  const int64_t st = (int64_t)nx * ny;
+  const int t = threadIdx.x;
+  const int tx = t % 32, ty = t / 32;
+  const int y = byi * kRRY + ty;
+  const int z0 = bzi * zc, z1 = min(z0 + zc, nz);
+  bool act[2];
+  int64_t col[2];
+  T xm[2], x0[2], az[2], re[2] = {T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int x = bxi * 64 + 2 * tx + q;
+    act[q] = x < nx && y < ny;
+    col[q] = act[q] ? (int64_t)y * nx + x : 0;
+    const int64_t i0 = (int64_t)z0 * st + col[q];
+    x0[q] = act[q] ? F.x[i0] : T(0);
+    if (!act[q]) {
+      xm[q] = az[q] = T(0);
+    } else if (z0 > 0) {
+      xm[q] = F.x[i0 - st];
+      az[q] = F.a[2][i0 - st];
+    } else if (perz) {
+      xm[q] = F.x[i0 + (int64_t)(nz - 1) * st];
+      az[q] = F.a[2][i0 + (int64_t)(nz - 1) * st];
+    } else {
+      xm[q] = x0[q];
+      az[q] = T(0);
+    }
+  }
+  double r2 = 0.0;
+  for (int z = z0; z < z1; ++z) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T r = T(0);
+      T xp = x0[q], au = T(0);
+      if (act[q]) {
+        const int64_t idx = (int64_t)z * st + col[q];
+        if (z + 1 < nz)
+          xp = F.x[idx + st];
+        else if (perz)
+          xp = F.x[col[q]];
+        au = F.a[2][idx];
+        const int c[3] = {bxi * 64 + 2 * tx + q, y, z};
+        const T xi = x0[q];
+        T ax = xi;
+        for (int d = 0; d < 2; ++d) {
+          const int64_t sd = d == 0 ? 1 : (int64_t)nx;
+          int64_t nl, nu;
+          T al, aup;
+          lower_nb(g, F.a[d], d, c[d], idx, sd, nl, al);
+          upper_nb(g, F.a[d], d, c[d], idx, sd, nu, aup);
+          ax += al * (xi - F.x[nl]) + aup * (xi - F.x[nu]);
+        }
+        ax += az[q] * (xi - xm[q]) + au * (xi - xp);
+        r = F.b[idx] - ax;
+        r2 += (double)r * (double)r;
+      }
+      if ((z & 1) == 0) {
+        re[q] = r;
+      } else {
+        R[0][ty][2 * tx + q] = re[q];
+        R[1][ty][2 * tx + q] = r;
+      }
+      xm[q] = x0[q];
+      x0[q] = xp;
+      az[q] = au;
+    }
+    if (z & 1) {
+      __syncthreads();
+      if (t < 32 * (kRRY / 2)) {
+        const int cx = t % 32, cy = t / 32;
+        const int ci = bxi * 32 + cx, cj = byi * (kRRY / 2) + cy;
+        const int ncx = C.g.n[0], ncy = C.g.n[1];
+        if (ci < ncx && cj < ncy) {
+          T s = T(0);
+#pragma unroll
+          for (int q2 = 0; q2 < 2; ++q2)
+#pragma unroll
+            for (int q1 = 0; q1 < 2; ++q1)
+#pragma unroll
+              for (int q0 = 0; q0 < 2; ++q0) s += R[q2][2 * cy + q1][2 * cx + q0];
+          const int64_t idx = ((int64_t)(z >> 1) * ncy + cj) * ncx + ci;
+          C.b[idx] = s / T(8);
+          C.x[idx] = T(0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (partials) {
+    const double tsum = block_sum<32 * kRRY>(r2, sh);
+    if (threadIdx.x == 0)
+      partials[bk] = tsum;
+  }
+}
+
+// z planes per block of the marching residual + restriction: about 1024
+// blocks in all, an even count of at least 2 (0: the one-plane-pair kernel)
+int rr3_chunk(const Geom& g) {
+  if (g.ndim != 3 || (g.n[2] & 1) || getenv("FLD_RR3_PAIRS")) return 0;
+  const int64_t cols = (int64_t)((g.n[0] + 63) / 64) * ((g.n[1] + kRRY - 1) / kRRY);
+  int64_t zc = (int64_t)g.n[2] * cols / 1024;
+  zc = std::max<int64_t>(2, zc & ~(int64_t)1);
+  return (int)std::min<int64_t>(zc, g.n[2]);
+}
+
 template <typename T>
 hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  const LevelView<T>& coarse, double* partials,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
+  const int zc = fits3(fine.g) ? rr3_chunk(fine.g) : 0;
+  if (zc > 0) {
+    const int gx = (fine.g.n[0] + 63) / 64, gy = (fine.g.n[1] + kRRY - 1) / kRRY;
+    const int gz = (fine.g.n[2] + zc - 1) / zc;
+    *nblocks = gx * gy * gz;
+    hipLaunchKernelGGL(k_resid_restrict_3dm<T>, dim3(*nblocks), dim3(32 * kRRY),
+                       0, s, fine, coarse, zc, gx, gy, partials, ctrl);
+    return hipGetLastError();
+  }
   if (fits3(fine.g)) {
     // fine blocks of 64 x kRRY x 2 cells (the fine sides are even)
     const dim3 g((fine.g.n[0] + 63) / 64, (fine.g.n[1] + kRRY - 1) / kRRY,

@@ -17,8 +17,8 @@
 // exactly symmetric or constant (red-black smoothing in the same colour
 // order on both sides; FP32 V-cycles).
 //
-// Kernels walk rows (x fastest) in a grid-stride loop over a fixed number of
-// blocks, so every block sums its cells in a fixed order and the dot
+// Kernels walk rows (x fastest), each block a fixed contiguous run of them
+// (row_range), so every block sums its cells in a fixed order and the dot
 // products are deterministic; each writes one partial per block (two for
 // the (p, q), (p, r) pair), which a single-block kernel reduces.
 #include "fld_internal.h"
@@ -29,6 +29,20 @@ namespace fld {
 namespace {
 
 constexpr int kKBlock = 256;
+
+// Rows [r0, r1) of block b: every block takes a contiguous run of rows, and
+// consecutive runs go to blocks that the hardware places on the same XCD
+// (blocks are dealt round-robin over the 8 XCDs), so the rows above and
+// below a run (stencil neighbours along y and z) mostly sit in the same
+// XCD's L2.
+__device__ __forceinline__ void row_range(int64_t rows, int64_t& r0,
+                                          int64_t& r1) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int c = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int64_t per = (rows + nb - 1) / nb;
+  r0 = (int64_t)c * per;
+  r1 = r0 + per < rows ? r0 + per : rows;
+}
 
 __device__ __forceinline__ double load_z(const double* z, int64_t i) {
   return z[i];
@@ -71,7 +85,9 @@ __global__ void __launch_bounds__(kKBlock)
   const Geom& g = K.g;
   const int64_t rows = (int64_t)g.n[1] * g.n[2];
   double s = 0.0;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+  int64_t rb, re;
+  row_range(rows, rb, re);
+  for (int64_t row = rb; row < re; ++row) {
     const int y = (int)(row % g.n[1]), zc = (int)(row / g.n[1]);
     for (int xc = threadIdx.x; xc < g.n[0]; xc += kKBlock) {
       const int c[3] = {xc, y, zc};
@@ -105,7 +121,9 @@ __global__ void __launch_bounds__(kKBlock)
   const Geom& g = K.g;
   const int64_t rows = (int64_t)g.n[1] * g.n[2];
   double s = 0.0;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x)
+  int64_t rb, re;
+  row_range(rows, rb, re);
+  for (int64_t row = rb; row < re; ++row)
     for (int xc = threadIdx.x; xc < g.n[0]; xc += kKBlock) {
       const int64_t idx = row * g.n[0] + xc;
       s += load_z(z, idx) * K.q[idx];
@@ -125,7 +143,9 @@ __global__ void __launch_bounds__(kKBlock)
   const Geom& g = K.g;
   const int64_t rows = (int64_t)g.n[1] * g.n[2];
   double spq = 0.0, spr = 0.0;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+  int64_t rb, re;
+  row_range(rows, rb, re);
+  for (int64_t row = rb; row < re; ++row) {
     const int y = (int)(row % g.n[1]), zc = (int)(row / g.n[1]);
     for (int xc = threadIdx.x; xc < g.n[0]; xc += kKBlock) {
       const int c[3] = {xc, y, zc};
@@ -156,7 +176,9 @@ __global__ void __launch_bounds__(kKBlock)
   const Geom& g = K.g;
   const int64_t rows = (int64_t)g.n[1] * g.n[2];
   double s = 0.0;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x)
+  int64_t rb, re;
+  row_range(rows, rb, re);
+  for (int64_t row = rb; row < re; ++row)
     for (int xc = threadIdx.x; xc < g.n[0]; xc += kKBlock) {
       const int64_t idx = row * g.n[0] + xc;
       x[idx] += alpha * K.p_new[idx];

@@ -83,3 +83,25 @@ def test_default_fused_levels(bc, precision, monkeypatch):
     x1, s1 = _solve(m, None, monkeypatch, **kw)
     assert s1["cycles"] == s0["cycles"] and s1["rel_res_final"] <= 1e-10, (s0, s1)
     np.testing.assert_array_equal(x1, x0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_marching_residual_restriction_matches_plane_pairs(precision,
+                                                           monkeypatch):
+    """The z-marching residual + restriction (the default on 3D levels)
+    against the one-plane-pair kernel (FLD_RR3_PAIRS): the same residuals
+    and coarse right-hand sides up to the order of the norm's partial sums,
+    so the same V-cycle counts and iterates to rounding, on a periodic-z and
+    a Neumann-z medium with a ragged x tile."""
+    for n, bc in (((96, 40, 24), ("periodic", "neumann", "periodic")),
+                  ((64, 32, 32), ("periodic", "periodic", "neumann"))):
+        m = media.random_small_medium(sum(n), n, bc)
+        announce(f"marching residual+restriction n={n} {precision}")
+        monkeypatch.setenv("FLD_RR3_PAIRS", "1")
+        x0, s0 = _solve(m, "0", monkeypatch, rtol=1e-12, max_cycles=200,
+                        precision=precision)
+        monkeypatch.delenv("FLD_RR3_PAIRS")
+        x1, s1 = _solve(m, "0", monkeypatch, rtol=1e-12, max_cycles=200,
+                        precision=precision)
+        assert s0["cycles"] == s1["cycles"], (n, s0, s1)
+        assert np.linalg.norm(x1 - x0) <= 1e-13 * np.linalg.norm(x0), n
