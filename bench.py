@@ -41,23 +41,27 @@ METRIC = ("FLD cell-updates/s at rel. residual 1e-8, learned+FP32-MG vs "
 # 5.85).  The library's default stays V(2,2) everywhere.
 PRE, POST = 1, 1
 COARSE_PRE, COARSE_POST = 3, 3
-# V-cycle of the 3D workload: V(2,2) on the finest level (two fused
-# one-launch sweeps), V(3,3) on the coarse ones.  On the 256^3 stratified
-# medium (face alpha spanning ~8 decades) the coarse levels need the extra
-# sweeps: 7.2-7.6 V-cycles per step instead of 11.6 with V(2,2) everywhere.
-# Against V(1,2) with coarse V(4,4) (one sweep of colour passes and one
-# fused pair on the finest level): FP64 12.7 instead of 12.9 ms per step,
-# FP32 refinement 10.6 instead of 11.3.
+# V-cycles of the 3D workload: V(2,2) on the finest level (two fused
+# one-launch sweeps each side) and more sweeps on the coarse levels, whose
+# rediscretised operators are the weak part on the stratified 256^3 medium
+# (face alpha spanning ~8 decades).  Over the first 12 steps, plain V-cycles
+# (FP64, or FP32 in FP64 refinement) do best with coarse V(5,5): FP64 15.5
+# ms per step against 16.0 with V(4,4), 15.7 with V(6,6), 20.6 with V(3,3);
+# as flexible-CG preconditioners they do best with coarse V(4,4) and two
+# FP32 V-cycles per iteration (11.6 ms against 12.1 with V(5,5), 13.1 with
+# V(3,3); one V-cycle per iteration 12.6-13.5).
 PRE3, POST3 = 2, 2
-COARSE_PRE3, COARSE_POST3 = 3, 3
+COARSE3, COARSE_KRYLOV3 = 5, 4
+COARSE_PRE3, COARSE_POST3 = COARSE3, COARSE3
 
-# Steps of the batched config (its own count), and of the 3D one: its 50
-# configured steps are out of reach, because from the 14th step on the
-# stratified medium's thin top mixes free-streaming and diffusive cells
-# (face coefficients ~4 next to ~1e6) and the V-cycles stop converging
-# (flexible CG around FP64 V-cycles lasts to the 32nd with growing
-# iteration counts); the bench times the first 12 steps, where every
-# variant converges.
+# Steps of the batched config (its own count), and of the 3D one.  Its 50
+# configured steps are out of reach of plain V-cycles: from about the 18th
+# step on the stratified medium's thin top mixes free-streaming and
+# diffusive cells (face coefficients ~4 next to ~1e6) and the V-cycles stop
+# converging; flexible CG around them runs all 50 (FP64 V-cycles, or FP32
+# ones that give way to FP64 where they stall).  The comparison of every
+# variant covers the first 12 steps; the configured 50-step run covers the
+# flexible-CG variants.
 C3_STEPS, C3_CONFIG_STEPS, C4_STEPS = 12, 50, 20
 
 
@@ -168,7 +172,7 @@ def cpu_baseline(steps_c2=2, n3=128):
 # ---------------------------------------------------------------------------
 
 def step_model_bytes(ndim, precision, vcycles, pre, post, cpre, cpost,
-                     outer=0.0, inner=2):
+                     outer=0.0, inner=2, krylov=False):
     """Per-pass byte model of one split step per fine cell, at the V-cycle
     actually run: every pass streams its operands once (w = 8 FP64, 4 FP32),
     each smoothing sweep reads b, the d face arrays and the iterate and
@@ -179,7 +183,10 @@ def step_model_bytes(ndim, precision, vcycles, pre, post, cpre, cpost,
     coefficients (3 + d) 8 (+ 4 d for the FP32 copies), hierarchy
     d w (2g - 1) (g = 4/3, 8/7), copy of E^n 16, exchange 48.  FP32
     refinement adds per outer iteration the FP64 residual (2 + d) 8 + 4 and
-    the correction 20."""
+    the correction 20.  Flexible CG (krylov; `outer` its iterations,
+    `vcycles` all V-cycles, FP32 widths in FP32_IR) adds its initial
+    residual (2 + d) 8 + 8 (+ 4) once and per iteration (z, q) w + 8, the
+    direction and q = A p w + (4 + d) 8, and the update 48 (+ 4)."""
     d = ndim
     gsum = {1: 1.0, 2: 1.0 / 3.0, 3: 1.0 / 7.0}[d]
     g = 1.0 + gsum
@@ -189,6 +196,13 @@ def step_model_bytes(ndim, precision, vcycles, pre, post, cpre, cpost,
             return nu * (3 + d) * w + (2 + d) * w + 2 * w + 2 * w / 2 ** d
         return level(pre + post) + gsum * level(cpre + cpost)
 
+    if krylov:
+        w = 8 if precision == "fp64" else 4
+        x = 0 if precision == "fp64" else 4
+        base = (3 + d) * 8 + (4 * d if x else 0) + d * w * (2 * g - 1) + 16 + 48
+        base += (2 + d) * 8 + 8 + x
+        per_iter = (w + 8) + (w + (4 + d) * 8) + 48 + x
+        return base + outer * per_iter + vcycles * cycle(w)
     if precision == "fp64":
         base = (3 + d) * 8 + d * 8 * (2 * g - 1) + 16 + 48
         return base + vcycles * cycle(8)
@@ -438,37 +452,43 @@ def run_c2(args, weights):
 # 3D 256^3 stratified medium
 # ---------------------------------------------------------------------------
 
-def run_c3(steps, warmup, weights):
-    """FP64 V-cycles, FP32 V-cycles in FP64 refinement, both inside flexible
-    CG, and FP32 refinement with the learned guess applied per z-slice,
-    each from the initial state over `steps` steps.  Every step's error
-    against its exact solve is bounded by its FP64 relative residual x
-    sqrt(N)|b|/sum(b) (the GPU tests check, on the same workload, that the
-    oracle's own residual of the iterate agrees with the GPU's)."""
+def run_c3(steps, warmup, weights, config_run=True):
+    """The 3D workload in two parts.  First every variant over `steps`
+    steps after `warmup` (from the initial state): plain FP64 V-cycles, FP32
+    V-cycles in FP64 refinement, both inside flexible CG, and FP32
+    refinement with the learned guess applied per z-slice (adaptive policy,
+    and on every step).  Then (config_run) the configured 50 steps from the
+    initial state with the flexible-CG variants, the only ones that last
+    them.  Every step's error against its exact solve is bounded by its
+    FP64 relative residual x sqrt(N)|b|/sum(b) (the GPU tests check, on the
+    same workload, that the oracle's own residual of the iterate agrees
+    with the GPU's)."""
     import numpy as np
     import torch
     import media
     from paper_2503_02764_amd import fld
     from paper_2503_02764_amd.solver import Stepper, make_params
     m = media.config_c3()
-    cyc = f"V({PRE3},{POST3}), coarse V({COARSE_PRE3},{COARSE_POST3})"
 
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
-    def run(precision, weights=None, policy="adaptive", krylov=False):
+    def run(precision, weights=None, policy="adaptive", krylov=False,
+            nsteps=steps, nwarm=warmup):
+        coarse = COARSE_KRYLOV3 if krylov else COARSE3
+        cyc = f"V({PRE3},{POST3}), coarse V({coarse},{coarse})"
         params = make_params(3, m.n, m.dx, m.bc, rtol=1e-8, precision=precision,
                              guess="prev" if weights is None else "learned",
                              guess_policy=policy, krylov=krylov,
-                             max_cycles=300, pre_smooth=PRE3,
-                             post_smooth=POST3, coarse_pre_smooth=COARSE_PRE3,
-                             coarse_post_smooth=COARSE_POST3)
+                             max_cycles=400, pre_smooth=PRE3,
+                             post_smooth=POST3, coarse_pre_smooth=coarse,
+                             coarse_post_smooth=coarse)
         st = Stepper(params, opacity=m.opacity)
         if weights is not None:
             fld.fld_set_model(st.ctx, weights)
         rho, E, e = d(m.rho), d(m.E), d(m.e)
         kap = torch.empty_like(rho)
-        for _ in range(warmup):
+        for _ in range(nwarm):
             st.step(m.dt, rho, kap, E, e)
         torch.cuda.synchronize()
         f0 = _bound_factor(E)
@@ -476,33 +496,42 @@ def run_c3(steps, warmup, weights):
         # duration (HIP events the launch records)
         fld.fld_kernel_timing_enable(st.ctx, True)
         fld.fld_kernel_timing_read(st.ctx)  # reset
-        cyc_n, outer, res, rej, skip = [], [], [], [], []
+        cyc_n, outer, res, rej, skip, pre64 = [], [], [], [], [], []
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(nsteps):
             s = st.step(m.dt, rho, kap, E, e)
             cyc_n.append(s["cycles"])
             outer.append(s["outer_iters"])
             res.append(s["rel_res_final"])
             rej.append(s["guess_rejected"])
             skip.append(s["guess_skipped"])
+            pre64.append(s["precond_fp64"])
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         kt = fld.fld_kernel_timing_read(st.ctx)
         fld.fld_kernel_timing_enable(st.ctx, False)
         factor = max(f0, _bound_factor(E))
-        value = m.cells * steps / secs
-        r = dict(value=value, ms_per_step=secs * 1e3 / steps,
+        value = m.cells * nsteps / secs
+        r = dict(value=value, ms_per_step=secs * 1e3 / nsteps, cycle=cyc,
                  vcycles_per_step=float(np.mean(cyc_n)),
                  outer_per_step=float(np.mean(outer)),
                  rel_res_final_max=float(np.max(res)),
                  bound_factor=factor,
-                 error_bound_per_step=[float(x) * factor for x in res],
+                 error_bound_max=float(np.max(res)) * factor,
                  roofline=_hbm_roofline(kt, "256^3"))
+        if nsteps <= 16:
+            r["error_bound_per_step"] = [float(x) * factor for x in res]
+        else:
+            r["iterations_per_step"] = [int(x) for x in
+                                        (outer if krylov or precision != "fp64"
+                                         else cyc_n)]
+        if krylov and precision == "fp32_ir":
+            r["steps_with_fp64_vcycles"] = int(np.sum(pre64))
         r["step_model_roofline"] = step_model_roofline(step_model_bytes(
-            3, precision, r["vcycles_per_step"], PRE3, POST3, COARSE_PRE3,
-            COARSE_POST3, r["outer_per_step"], 2), value, cyc)
+            3, precision, r["vcycles_per_step"], PRE3, POST3, coarse, coarse,
+            r["outer_per_step"], 2, krylov), value, cyc)
         if weights is not None:
-            r["network_steps"] = steps - int(np.sum(skip))
+            r["network_steps"] = nsteps - int(np.sum(skip))
             r["guess_rejected_steps"] = int(np.sum(rej))
         E_out = E.cpu().numpy()
         del st, rho, E, e, kap
@@ -521,14 +550,18 @@ def run_c3(steps, warmup, weights):
         np.linalg.norm(E32 - E64) / np.linalg.norm(E64))
     for r in (f32, k64, k32, lrn, lrnk, lrne):
         r["speedup_vs_fp64"] = r["value"] / f64["value"]
-    return {
+    out = {
         "workload": "3d-256cube-stratified-kramers",
-        "grid": list(m.n), "bc": list(m.bc), "rtol": 1e-8, "cycle": cyc,
+        "grid": list(m.n), "bc": list(m.bc), "rtol": 1e-8,
+        "cycle": f"V({PRE3},{POST3}), coarse V({COARSE3},{COARSE3}); as "
+                 f"flexible-CG preconditioner coarse V({COARSE_KRYLOV3},"
+                 f"{COARSE_KRYLOV3})",
         "steps": steps, "warmup": warmup, "dt": m.dt,
         "config_steps": C3_CONFIG_STEPS,
-        "steps_note": "the first 12 of the configured 50 steps: from the "
-                      "14th on, plain V-cycles stop converging on this "
-                      "medium (see fld_params.krylov)",
+        "steps_note": f"every variant over steps {warmup + 1}-"
+                      f"{warmup + steps}; plain V-cycles stop converging "
+                      f"from about the 18th step on this medium, flexible CG "
+                      f"runs the configured {C3_CONFIG_STEPS} (config_run)",
         "value": f32["value"], "ms_per_step": f32["ms_per_step"],
         "dtype": "f32 V-cycles, f64 refinement and exchange",
         "learned_fp32_vs_plain_fp64": lrn["value"] / f64["value"],
@@ -543,6 +576,32 @@ def run_c3(steps, warmup, weights):
                      "learned_guess_every_step_fp32_vcycles_fp64_refinement":
                          lrne},
     }
+    if config_run:
+        n = C3_CONFIG_STEPS
+        c64, _ = run("fp64", krylov=True, nsteps=n, nwarm=0)
+        c32, _ = run("fp32_ir", krylov=True, nsteps=n, nwarm=0)
+        cl, _ = run("fp32_ir", weights, krylov=True, nsteps=n, nwarm=0)
+        for r in (c32, cl):
+            r["speedup_vs_fp64_flexible_cg"] = r["value"] / c64["value"]
+        out["config_run"] = {
+            "steps": n, "warmup": 0,
+            "note": "the configured steps from the initial state; plain "
+                    "V-cycles (FP64 or FP32 refinement) diverge before the "
+                    "end, so the FP64 reference here is flexible CG over "
+                    "FP64 V-cycles",
+            "learned_fp32_vs_fp64": cl["value"] / c64["value"],
+            "variants": {"fp64_vcycles_in_flexible_cg": c64,
+                         "fp32_vcycles_in_fp64_flexible_cg": c32,
+                         "learned_guess_fp32_vcycles_in_fp64_flexible_cg": cl},
+        }
+        # the configured workload: its 50 steps, FP32 V-cycles in FP64
+        # iterations
+        out.update(value=c32["value"], ms_per_step=c32["ms_per_step"],
+                   roofline=c32["roofline"],
+                   value_from="config_run fp32_vcycles_in_fp64_flexible_cg")
+    else:
+        out["value_from"] = "variants fp32_vcycles_fp64_refinement"
+    return out
 
 
 def _explicit_roofline(m, reps=10):
@@ -733,6 +792,9 @@ def main():
                     help="all: the headline line with the 3D and batched "
                          "configs under `configs`; c2 / c3 / c4: one workload "
                          "alone (for profiling)")
+    ap.add_argument("--skip-config-run", action="store_true",
+                    help="3D workload: leave out the configured 50-step run "
+                         "(for profiling)")
     ap.add_argument("--unet-only", action="store_true",
                     help="only run the learned guess's network on a 1024^2 "
                          "image (for profiling its kernels)")
@@ -787,8 +849,12 @@ def main():
                           "tflops": fl / (ms * 1e-3) / 1e12}))
         return
     if args.workload == "c3":
-        r = run_c3(min(args.steps, C3_STEPS), min(args.warmup, 1), weights)
-        args.steps, args.warmup = r["steps"], r["warmup"]
+        r = run_c3(min(args.steps, C3_STEPS), min(args.warmup, 1), weights,
+                   config_run=not args.skip_config_run)
+        if "config_run" in r:
+            args.steps, args.warmup = r["config_run"]["steps"], 0
+        else:
+            args.steps, args.warmup = r["steps"], r["warmup"]
         _line(r["value"], r["ms_per_step"], args, r["workload"], "f32",
               {"roofline": r["roofline"], "c3": r,
                "achievable_copy": copy_bandwidth()})

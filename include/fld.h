@@ -118,7 +118,13 @@ typedef struct {
   int32_t krylov;        /* 0: the V-cycle is the iteration; 1: V-cycles
                             precondition flexible conjugate gradients
                             (stays convergent where coefficient jumps make
-                            a V-cycle overshoot); single grids only      */
+                            a V-cycle overshoot); single grids only.
+                            With FP32_IR the FP32 V-cycles give way to
+                            FP64 ones (same iterate) when the FP64
+                            residual falls less than 4x over 4 iterations,
+                            and the next 2, 4, ... 32 steps start with
+                            FP64 ones; the workspace then also holds the
+                            FP64 hierarchy                                */
 } fld_params;
 
 typedef struct {
@@ -130,6 +136,11 @@ typedef struct {
   int32_t guess_rejected;  /* 1 when a learned guess lost to E^n          */
   int32_t guess_skipped;   /* 1 when FLD_GUESS_ADAPTIVE ran this step
                               without the network (guess E^n)              */
+  int32_t precond_fp64;    /* FP32_IR with krylov: 1 when this step ran
+                              flexible-CG iterations with FP64 V-cycles
+                              (the FP32 ones stalled on it, or on a recent
+                              step), else 0                                */
+  int32_t pad;
   int64_t flagged_cells;   /* cells with E <= 0, rho kappa <= 0 or NaN     */
   double rel_res_initial;  /* |b - A x0| / |b|                              */
   double rel_res_final;    /* |b - A x| / |b| of the returned E_out        */

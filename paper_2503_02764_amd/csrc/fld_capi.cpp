@@ -122,6 +122,10 @@ struct fld_ctx {
   double* kr_p[2] = {};
   double* kr_q = nullptr;
   double* kr_z = nullptr;
+  // FP32_IR + flexible CG: steps left that start with FP64 V-cycles after
+  // the FP32 ones stalled, the current pause, and this step's fallback
+  int pre64_skip = 0, pre64_span = 0;
+  bool pre64_used = false;
 };
 
 namespace {
@@ -215,6 +219,7 @@ struct Plan {
   size_t a64[kMaxLevels][3] = {}, x64[kMaxLevels] = {}, b64[kMaxLevels] = {};
   size_t a32[kMaxLevels][3] = {}, x32[kMaxLevels] = {}, b32[kMaxLevels] = {};
   size_t alt[kMaxLevels] = {};  // tiled 2D levels: iterate double buffer
+  size_t alt64[kMaxLevels] = {};  // FP64 ones beside FP32 (see pre64)
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
   size_t dscr = 0;  // 3D coefficient stage: D per cell
   size_t guess = 0;
@@ -334,9 +339,12 @@ void make_plan(const fld_params* p, Plan* P) {
   };
   const int nd = p->ndim;
   const bool mixed = p->precision == FLD_PREC_FP32_IR;
+  // FP32_IR with flexible CG keeps an FP64 hierarchy as well: its
+  // preconditioner falls back to FP64 V-cycles where FP32 ones stall
+  const bool pre64 = mixed && p->krylov;
   for (int l = 0; l < P->L; ++l) {
     const size_t cells = (size_t)P->g[l].N;
-    if (l == 0 || !mixed) {
+    if (l == 0 || !mixed || pre64) {
       for (int d = 0; d < nd; ++d) P->a64[l][d] = take(cells * 8);
       if (l > 0) {
         P->x64[l] = take(cells * 8);
@@ -348,11 +356,16 @@ void make_plan(const fld_params* p, Plan* P) {
       P->x32[l] = take(cells * 4);
       P->b32[l] = take(cells * 4);
     }
-    if (nd == 2 && l + 1 < P->L) P->alt[l] = take(cells * (mixed ? 4 : 8));
-    // 3D: out-of-place buffer of the fused red-black sweep
-    if (nd == 3 && l + 1 < P->L && (int64_t)cells >= sweep_min_cells() &&
-        gs_sweep3d_ok(P->g[l]))
+    // 2D: the tiled levels' iterate double buffer; 3D: out-of-place buffer
+    // of the fused red-black sweep
+    const bool alt = (nd == 2 && l + 1 < P->L) ||
+                     (nd == 3 && l + 1 < P->L &&
+                      (int64_t)cells >= sweep_min_cells() &&
+                      gs_sweep3d_ok(P->g[l]));
+    if (alt) {
       P->alt[l] = take(cells * (mixed ? 4 : 8));
+      if (pre64) P->alt64[l] = take(cells * 8);
+    }
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   if (nd == 3) P->dscr = take((size_t)P->g[0].N * 8);
@@ -388,7 +401,9 @@ void make_plan(const fld_params* p, Plan* P) {
     P->kr_p[0] = take(n0);
     P->kr_p[1] = take(n0);
     P->kr_q = take(n0);
-    if (!mixed) P->kr_z = take(n0);  // FP32_IR: z is the FP32 level-0 iterate
+    // FP64 preconditioner output (FP32_IR: the FP32 level-0 iterate, and
+    // this one after a fallback to FP64 V-cycles)
+    P->kr_z = take(n0);
   }
   P->total = o;
 }
@@ -483,6 +498,9 @@ fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
   T* alt = H.alt[l];
   const bool fused = fused_level(c, H, l);
   const int pairs = fused ? sweeps / 2 : 0;
+  // only the context's own precision is timed (an FP32_IR solve whose
+  // flexible CG fell back to FP64 V-cycles runs both)
+  if ((sizeof(T) == 4) != c->mixed) timed_fused = timed_colour = false;
   const int plain = sweeps - 2 * pairs;
   for (int s = 0; s < plain; ++s)
     for (int color = 0; color < gs_colors(v.g); ++color) {
@@ -738,32 +756,68 @@ fld_status solve_mixed(fld_ctx* c) {
   return FLD_OK;
 }
 
+// Face coefficients of every coarse level from the finest one's.
+template <typename T>
+fld_status coarsen_levels(fld_ctx* c, Levels<T>& H) {
+  if (c->coarsen_multi && c->geom[0].ndim == 2) {
+    HIP_TRY(c, launch_coarsen2d<T>(c->geom, c->L, H.a, c->stream));
+    return FLD_OK;
+  }
+  for (int l = 0; l + 1 < c->L; ++l) {
+    const T* fa[3] = {H.a[l][0], H.a[l][1], H.a[l][2]};
+    T* ca[3] = {H.a[l + 1][0], H.a[l + 1][1], H.a[l + 1][2]};
+    HIP_TRY(c, launch_coarsen<T>(c->geom[l], c->geom[l + 1], fa, ca,
+                                 c->stream));
+  }
+  return FLD_OK;
+}
+
 // Flexible conjugate gradients preconditioned by V-cycles (FP64 V-cycles,
 // or `inner` FP32 V-cycles in FP32_IR) until the device stop flag is set.
 // The FP64 residual is carried by the recurrence r -= alpha A p; its norm
 // is the stop test.  Iterations are enqueued in batches like the V-cycles
 // of solve_fp64 (launches after the stop return at once).
+//
+// FP32 V-cycles cannot resolve a correction whose right-hand side is below
+// their rounding of the large face terms (face coefficients many decades
+// above 1): there the FP32-preconditioned iteration stops contracting.  The
+// host watches the FP64 residual at every read of the control block; when it
+// has fallen by less than kStallDrop over kStallIters iterations, the solve
+// continues from its current iterate with FP64 V-cycles (FP64 coarse levels
+// built then), and the next steps start with them (2, 4, 8, ... up to
+// kMaxPre64Pause steps while the stall recurs).
+constexpr int kStallIters = 4;
+constexpr double kStallDrop = 0.25;
+constexpr int kMaxPre64Pause = 32;
+
 fld_status solve_krylov(fld_ctx* c) {
   const Geom& g0 = c->geom[0];
   KrylovArgs K{};
   K.g = g0;
   for (int d = 0; d < g0.ndim; ++d) K.a[d] = c->h64.a[0][d];
   K.r = c->kr_r;
-  K.r32 = c->mixed ? c->h32.b[0] : nullptr;
   K.q = c->kr_q;
   K.partials = c->partials;
   K.ctrl = c->ctrl;
-  const int nb = krylov_blocks(g0);
-  HIP_TRY(c, launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream));
-  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl,
-                             c->stream));
   // FP64 preconditioner: level 0 of the hierarchy solves A z = r from zero
   Levels<double> pre = c->h64;
   pre.x[0] = c->kr_z;
   pre.b[0] = c->kr_r;
-  const int per = c->mixed ? c->inner : 1;
-  const int max_iter = c->p.max_cycles / per + 1;
-  int k = 0;
+  const int nb = krylov_blocks(g0);
+  bool fp32 = c->mixed && c->pre64_skip == 0;
+  if (c->mixed && !fp32) {  // step_impl initialised the control with inner 1
+    --c->pre64_skip;
+    FLD_TRY(coarsen_levels<double>(c, c->h64));
+  }
+  c->pre64_used = c->mixed && !fp32;
+  K.r32 = fp32 ? c->h32.b[0] : nullptr;
+  HIP_TRY(c, launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream));
+  HIP_TRY(c, launch_finalize(kFinInitial, c->partials, nb, c->ctrl,
+                             c->stream));
+  const int max_iter = c->p.max_cycles + 1;
+  int k = 0, k_first = 0;  // iteration count; first iteration of this run
+  int k_mark = -1;         // stall watch: iteration and residual at a mark
+  double res_mark = 0.0;
   int batch = c->last_batch < 1 ? 1 : c->last_batch;
   c->precond = true;
   fld_status st = FLD_OK;
@@ -771,22 +825,23 @@ fld_status solve_krylov(fld_ctx* c) {
     for (int j = 0; j < batch && k < max_iter && st == FLD_OK; ++j, ++k) {
       K.p_old = c->kr_p[(k + 1) & 1];
       K.p_new = c->kr_p[k & 1];
-      if (c->mixed) {
+      if (fp32) {
         for (int i = 0; i < c->inner && st == FLD_OK; ++i)
           st = vcycle<float>(c, c->h32, i == 0);
       } else {
         st = vcycle<double>(c, pre, true);
       }
       if (st != FLD_OK) break;
+      const int first = k == k_first;
       hipError_t e = hipSuccess;
-      if (k > 0) {
-        e = c->mixed ? launch_fcg_zq<float>(K, c->h32.x[0], c->stream)
-                     : launch_fcg_zq<double>(K, c->kr_z, c->stream);
+      if (!first) {
+        e = fp32 ? launch_fcg_zq<float>(K, c->h32.x[0], c->stream)
+                 : launch_fcg_zq<double>(K, c->kr_z, c->stream);
         if (e == hipSuccess) e = launch_fcg_scalar(0, K, c->stream);
       }
       if (e == hipSuccess)
-        e = c->mixed ? launch_fcg_dir<float>(K, c->h32.x[0], k == 0, c->stream)
-                     : launch_fcg_dir<double>(K, c->kr_z, k == 0, c->stream);
+        e = fp32 ? launch_fcg_dir<float>(K, c->h32.x[0], first, c->stream)
+                 : launch_fcg_dir<double>(K, c->kr_z, first, c->stream);
       if (e == hipSuccess) e = launch_fcg_scalar(1, K, c->stream);
       if (e == hipSuccess) e = launch_fcg_update(K, c->h64.x[0], c->stream);
       if (e == hipSuccess)
@@ -799,11 +854,40 @@ fld_status solve_krylov(fld_ctx* c) {
     st = read_control(c);
     if (st != FLD_OK || c->host_ctrl->done != kRunning || k >= max_iter) break;
     batch = 2;
+    if (!fp32) continue;
+    if (k_mark < 0 || k - k_mark < kStallIters) {
+      if (k_mark < 0) {
+        k_mark = k;
+        res_mark = c->host_ctrl->res;
+      }
+      continue;
+    }
+    if (c->host_ctrl->res > kStallDrop * res_mark) {
+      // FP32 V-cycles stalled: FP64 V-cycles from the current iterate
+      fp32 = false;
+      c->pre64_used = true;
+      c->pre64_span = std::min(std::max(2, 2 * c->pre64_span), kMaxPre64Pause);
+      c->pre64_skip = c->pre64_span;
+      st = coarsen_levels<double>(c, c->h64);
+      if (st != FLD_OK) break;
+      K.r32 = nullptr;
+      HIP_TRY(c, launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream));
+      HIP_TRY(c, launch_finalize(kFinRestart, c->partials, nb, c->ctrl,
+                                 c->stream));
+      k_first = k;
+    } else {
+      k_mark = k;
+      res_mark = c->host_ctrl->res;
+    }
   }
   c->precond = false;
   FLD_TRY(st);
   if (c->host_ctrl->done == kRunning) c->host_ctrl->done = kCapped;
-  if (c->host_ctrl->done == kConverged) c->last_batch = c->host_ctrl->outer;
+  if (c->host_ctrl->done == kConverged) {
+    c->last_batch = c->host_ctrl->outer;
+    // an FP32 run that converged ends the pause
+    if (c->mixed && fp32 && !c->pre64_used) c->pre64_span = 0;
+  }
   return FLD_OK;
 }
 
@@ -1275,7 +1359,7 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
   char* w = c->ws;
   for (int l = 0; l < P.L; ++l) {
     c->geom[l] = P.g[l];
-    const bool has64 = l == 0 || !c->mixed;
+    const bool has64 = l == 0 || !c->mixed || p->krylov;
     for (int d = 0; d < p->ndim; ++d) {
       c->h64.a[l][d] = has64 ? (double*)(w + P.a64[l][d]) : nullptr;
       c->h32.a[l][d] = c->mixed ? (float*)(w + P.a32[l][d]) : nullptr;
@@ -1290,6 +1374,7 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
       else
         c->h64.alt[l] = (double*)(w + P.alt[l]);
     }
+    if (P.alt64[l]) c->h64.alt[l] = (double*)(w + P.alt64[l]);
   }
   const char* path = getenv("FLD_KERNEL_PATH");
   c->fast = !(path && strcmp(path, "simple") == 0);
@@ -1428,9 +1513,12 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
   double* copy_dst = aliased ? c->bcopy
                              : (c->p.guess == FLD_GUESS_ZERO ? nullptr : E_out);
+  // V-cycles per iteration: flexible CG with FP64 V-cycles runs one
+  const bool one_inner =
+      c->krylov && (!c->mixed || c->pre64_skip > 0);
   HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, c->p.max_cycles,
-                             (c->krylov && !c->mixed) ? 1 : c->inner,
-                             c->host_ctrl_dev, c->stream));
+                             one_inner ? 1 : c->inner, c->host_ctrl_dev,
+                             c->stream));
   CoefArgs A;
   A.g = g0;
   for (int d = 0; d < 3; ++d) {
@@ -1459,27 +1547,8 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
                                c->stream));
   }
-  if (c->coarsen_multi && g0.ndim == 2) {
-    if (c->mixed)
-      HIP_TRY(c, launch_coarsen2d<float>(c->geom, c->L, c->h32.a, c->stream));
-    else
-      HIP_TRY(c, launch_coarsen2d<double>(c->geom, c->L, c->h64.a, c->stream));
-  }
-  for (int l = 0; l + 1 < c->L && !(c->coarsen_multi && g0.ndim == 2); ++l) {
-    if (c->mixed) {
-      const float* fa[3] = {c->h32.a[l][0], c->h32.a[l][1], c->h32.a[l][2]};
-      float* ca[3] = {c->h32.a[l + 1][0], c->h32.a[l + 1][1],
-                      c->h32.a[l + 1][2]};
-      HIP_TRY(c, launch_coarsen<float>(c->geom[l], c->geom[l + 1], fa, ca,
-                                       c->stream));
-    } else {
-      const double* fa[3] = {c->h64.a[l][0], c->h64.a[l][1], c->h64.a[l][2]};
-      double* ca[3] = {c->h64.a[l + 1][0], c->h64.a[l + 1][1],
-                       c->h64.a[l + 1][2]};
-      HIP_TRY(c, launch_coarsen<double>(c->geom[l], c->geom[l + 1], fa, ca,
-                                        c->stream));
-    }
-  }
+  FLD_TRY(c->mixed ? coarsen_levels<float>(c, c->h32)
+                   : coarsen_levels<double>(c, c->h64));
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
   if (use_net) FLD_TRY(learned_guess(c, rho, kappa));
@@ -1512,6 +1581,7 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     stats->guess_rejected = use_net ? h.guess_rejected : 0;
     stats->guess_skipped = learned && !use_net;
     stats->outer_iters = (c->mixed || c->krylov) ? h.outer : 0;
+    stats->precond_fp64 = c->krylov && c->mixed && c->pre64_used;
     stats->flagged_cells = h.flagged;
     stats->rel_res_initial = h.res_initial;
     stats->rel_res_final = h.res;

@@ -97,6 +97,60 @@ __device__ __forceinline__ void upper_nb(const Geom& g, const T* a, int d,
     nb = idx;  // wall: al == 0
 }
 
+// A cell and its two neighbours along each of the first ND dimensions
+// (periodic wrap, or the cell itself at a Neumann wall), taken before any
+// load and without branches so that a stencil's loads issue together.
+// lo_face[d] is false where the lower face is a wall (the upper face
+// coefficient there is stored as 0).
+template <int ND>
+struct Nbrs {
+  int64_t idx, lo[ND], up[ND];
+  bool lo_face[ND];
+};
+
+template <int ND>
+__device__ __forceinline__ Nbrs<ND> neighbours(const Geom& g, const int c[3],
+                                               int64_t idx) {
+  Nbrs<ND> n;
+  n.idx = idx;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const int64_t st =
+        d == 0 ? 1 : (d == 1 ? (int64_t)g.n[0] : (int64_t)g.n[0] * g.n[1]);
+    const int64_t wrap = (int64_t)(g.n[d] - 1) * st;
+    const bool per = g.per[d] != 0;
+    n.lo_face[d] = c[d] > 0 || per;
+    n.lo[d] = c[d] > 0 ? idx - st : (per ? idx + wrap : idx);
+    n.up[d] = c[d] < g.n[d] - 1 ? idx + st : (per ? idx - wrap : idx);
+  }
+  return n;
+}
+
+// r = b - A x at the cell of n: the operations of residual_value in the
+// same order (same bits), loads first.
+template <int ND, typename T>
+__device__ __forceinline__ T residual_nb(const T* const a[3],
+                                         const T* __restrict__ x,
+                                         const T* __restrict__ b,
+                                         const Nbrs<ND>& n) {
+  T xl[ND], xu[ND], al[ND], au[ND];
+  const T xi = x[n.idx], bi = b[n.idx];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    xl[d] = x[n.lo[d]];
+    xu[d] = x[n.up[d]];
+    al[d] = a[d][n.lo[d]];
+    au[d] = a[d][n.idx];
+  }
+  T ax = xi;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const T a_l = n.lo_face[d] ? al[d] : T(0);
+    ax += a_l * (xi - xl[d]) + au[d] * (xi - xu[d]);
+  }
+  return bi - ax;
+}
+
 // Gauss-Seidel / Jacobi value of cell idx: (b + sum alpha x_nb) / (1 + sum alpha),
 // faces taken in the order -x, +x, -y, +y, -z, +z.
 template <typename T>
@@ -202,6 +256,11 @@ __device__ __forceinline__ void finalize_update(int mode, double s,
   ctrl->res = r;
   if (mode == kFinInitial) {
     ctrl->res_initial = r;
+    if (r <= ctrl->rtol) ctrl->done = kConverged;
+    return;
+  }
+  if (mode == kFinRestart) {
+    ctrl->inner = 1;
     if (r <= ctrl->rtol) ctrl->done = kConverged;
     return;
   }

@@ -217,7 +217,9 @@ enum FinalizeMode {
   kFinCycle = 2,
   kFinOuter = 3,
   kFinCoef = 4,  // |b|^2 in partials[0, count), |b - A x0|^2 in [count, 2 count)
-  kFinKrylov = 5  // |r|^2 after a flexible-CG iteration (counts iterations)
+  kFinKrylov = 5,  // |r|^2 after a flexible-CG iteration (counts iterations)
+  kFinRestart = 6  // |r|^2 of a flexible-CG restart with FP64 V-cycles
+                   // (one V-cycle per iteration from then on)
 };
 
 // Flexible CG around the V-cycle (fld_krylov.hip): level-0 geometry and
@@ -235,7 +237,7 @@ struct KrylovArgs {
   double* partials;
   Control* ctrl;
 };
-constexpr int kKrylovBlocks = 1024;
+constexpr int kKrylovBlocks = 2048;
 int krylov_blocks(const Geom& g);  // blocks (and partials) of each pass
 hipError_t launch_fcg_init(const KrylovArgs& K, const double* x,
                            const double* b, hipStream_t s);

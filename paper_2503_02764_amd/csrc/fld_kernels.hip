@@ -365,9 +365,9 @@ __global__ void __launch_bounds__(k3T)
   double r2 = 0.0;
   if (x < nx && y < ny) {
     const int c[3] = {x, y, z};
-    const int64_t idx = ((int64_t)z * ny + y) * nx + x;
-    const double r = residual_value(L, c, idx);
-    if (r32) r32[idx] = (float)r;
+    const Nbrs<3> n = neighbours<3>(L.g, c, ((int64_t)z * ny + y) * nx + x);
+    const double r = residual_nb<3>(L.a, L.x, L.b, n);
+    if (r32) r32[n.idx] = (float)r;
     r2 = r * r;
   }
   const double t = block_sum<k3T>(r2, sh);

@@ -68,6 +68,7 @@ class fld_stats(ctypes.Structure):
     _fields_ = [
         ("cycles", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
         ("guess_rejected", ctypes.c_int32), ("guess_skipped", ctypes.c_int32),
+        ("precond_fp64", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("flagged_cells", ctypes.c_int64),
         ("rel_res_initial", ctypes.c_double),
         ("rel_res_final", ctypes.c_double),
