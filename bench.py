@@ -639,7 +639,8 @@ def _explicit_roofline(m, reps=10):
     torch.cuda.empty_cache()
     return {"bound": "hbm", "kernel": "k_explicit", "achieved": gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "avg_launch_us": us,
+            "traffic": measured_traffic("k_explicit", "256^3"),
+            "avg_launch_us": us,
             "algorithmic_bytes_per_launch": nbytes, "launches": reps}
 
 
