@@ -637,9 +637,9 @@ def _explicit_roofline(m, reps=10):
     gbs = nbytes / (us * 1e-6) / 1e9
     del ctx, outs, v
     torch.cuda.empty_cache()
-    return {"bound": "hbm", "kernel": "k_explicit", "achieved": gbs,
+    return {"bound": "hbm", "kernel": "k_explicit_3d<true>", "achieved": gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_explicit", "256^3"),
+            "traffic": measured_traffic("k_explicit_3d<true>", "256^3"),
             "avg_launch_us": us,
             "algorithmic_bytes_per_launch": nbytes, "launches": reps}
 
