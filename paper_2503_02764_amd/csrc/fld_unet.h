@@ -19,6 +19,15 @@ struct ConvArgs {
   int out_f32;
   int out_stride, out_off, cout, cout_pad;
   int relu, accumulate, ksize;
+  // 3x3 BF16 convolutions only (null: unused):
+  // input channels from up_c0 on are read from up_in, nearest-upsampled by
+  // 2 on the fly (channel c at (y, x) = up_in[y / 2][x / 2][c - up_c0]);
+  const uint16_t* up_in;
+  int up_stride, up_off, up_c0;
+  // the 2x2 average pool of the (BF16) output is also written to pool_out,
+  // with the roundings of the separate pool kernel
+  uint16_t* pool_out;
+  int pool_stride, pool_off;
 };
 
 // dW[t][co][ci] += sum_p in[p + off_t][ci] dz[p][co]

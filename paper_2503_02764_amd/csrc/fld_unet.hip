@@ -183,35 +183,77 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs A) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int chunks = A.cin_pad / 16;
-  for (int cc = 0; cc < chunks; ++cc) {
-    const int c0 = cc * 16;
-    __syncthreads();
-    for (int i = tid; i < AR * AC * 2; i += 256) {
+  // Staging of one chunk of 16 input channels: the input tile with its halo
+  // (AR x AC pixels, two 8-channel pieces each) and the chunk's weights of
+  // the 9 taps (+ the zero tap), RA and RB 16-byte pieces per thread.  The
+  // next chunk's pieces are loaded into registers while the matrix cores
+  // work on the current one (double buffering through registers).
+  constexpr int NA = AR * AC * 2, NB = 10 * COG * 2;
+  constexpr int RA = (NA + 255) / 256, RB = (NB + 255) / 256;
+  uint4 ra[RA], rb[RB];
+  auto load_chunk = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {
+      const int i = tid + k * 256;
       const int piece = i & 1, px = i >> 1;
       const int col = px % AC, row = px / AC;
       const int yy = y0 - 1 + row, xx = x0 - 1 + col;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        const int64_t q = (((int64_t)n * H + yy) * W + xx) * A.in_stride +
-                          A.in_off + c0 + piece * 8;
-        if (A.in_f32)
-          v = pack8_f32((const float*)A.in + q);
-        else
-          v = *reinterpret_cast<const uint4*>((const uint16_t*)A.in + q);
+      if (i < NA && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        if (A.up_in && c0 >= A.up_c0) {
+          const int64_t q =
+              (((int64_t)n * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) *
+                  A.up_stride +
+              A.up_off + (c0 - A.up_c0) + piece * 8;
+          v = *reinterpret_cast<const uint4*>(A.up_in + q);
+        } else {
+          const int64_t q = (((int64_t)n * H + yy) * W + xx) * A.in_stride +
+                            A.in_off + c0 + piece * 8;
+          if (A.in_f32)
+            v = pack8_f32((const float*)A.in + q);
+          else
+            v = *reinterpret_cast<const uint4*>((const uint16_t*)A.in + q);
+        }
       }
-      *reinterpret_cast<uint4*>(sA + (row * AC + col) * kCPS + piece * 8) = v;
+      ra[k] = v;
     }
-    for (int i = tid; i < 10 * COG * 2; i += 256) {
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int i = tid + k * 256;
       const int piece = i & 1, r = i >> 1;
       const int co = r % COG, t = r / COG;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (t < 9)
+      if (i < NB && t < 9)
         v = *reinterpret_cast<const uint4*>(
             A.w + ((int64_t)t * A.cout_pad + cg * COG + co) * A.cin_pad + c0 +
             piece * 8);
-      *reinterpret_cast<uint4*>(sB + (t * COG + co) * kCPS + piece * 8) = v;
+      rb[k] = v;
     }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {
+      const int i = tid + k * 256;
+      if (i >= NA) break;
+      const int piece = i & 1, px = i >> 1;
+      const int col = px % AC, row = px / AC;
+      *reinterpret_cast<uint4*>(sA + (row * AC + col) * kCPS + piece * 8) = ra[k];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int i = tid + k * 256;
+      if (i >= NB) break;
+      const int piece = i & 1, r = i >> 1;
+      const int co = r % COG, t = r / COG;
+      *reinterpret_cast<uint4*>(sB + (t * COG + co) * kCPS + piece * 8) = rb[k];
+    }
+  };
+  load_chunk(0);
+  for (int cc = 0; cc < chunks; ++cc) {
+    __syncthreads();  // the previous chunk's reads of LDS are done
+    store_chunk();
     __syncthreads();
+    if (cc + 1 < chunks) load_chunk((cc + 1) * 16);
 #pragma unroll
     for (int ks = 0; ks < 5; ++ks) {
       const int t = 2 * ks + (kq >> 1);
@@ -283,6 +325,34 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs A) {
                               A.out_off + co) =
         *reinterpret_cast<const uint4*>(sO + px * OS + piece * 8);
   }
+  if (!A.pool_out) return;
+  // 2x2 average pool of the tile (even H, W; the tile's rows and columns
+  // start at even indices): children summed in FP32 in the pool kernel's
+  // order, then scaled and rounded to BF16 as there
+  const int Ho = H >> 1, Wo = W >> 1;
+  for (int i = tid; i < (kCTH / 2) * (kCTW / 2) * V; i += 256) {
+    const int piece = i % V, pp = i / V;
+    const int px = pp % (kCTW / 2), py = pp / (kCTW / 2);
+    const int xo = (x0 >> 1) + px, yo = (y0 >> 1) + py;
+    const int co = cg * COG + piece * 8;
+    if (xo >= Wo || yo >= Ho || co >= A.cout) continue;
+    float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const uint16_t* c =
+            sO + ((2 * py + dy) * kCTW + 2 * px + dx) * OS + piece * 8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum[k] += bf2f(c[k]);
+      }
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      o[k] = (uint32_t)f2bf(0.25f * sum[2 * k]) |
+             ((uint32_t)f2bf(0.25f * sum[2 * k + 1]) << 16);
+    *reinterpret_cast<uint4*>(A.pool_out +
+                              (((int64_t)n * Ho + yo) * Wo + xo) * A.pool_stride +
+                              A.pool_off + co) = make_uint4(o[0], o[1], o[2], o[3]);
+  }
 }
 
 template <int NS>
@@ -295,9 +365,16 @@ static hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s) {
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int chunks = a.cout_pad / 16;
+  const bool fused = a.up_in || a.pool_out;
+  if (fused && (a.ksize != 3 || a.out_f32 || a.in_f32 || (a.H | a.W) & 1))
+    return hipErrorInvalidValue;  // the fused forms are BF16 3x3 only
   if (a.ksize == 3 && !a.accumulate && a.cout % 8 == 0 && a.cin_pad % 16 == 0) {
-    // output channels per block: all up to 64, else groups of 64 or 48
-    const int ns = chunks <= 4 ? chunks : (chunks % 4 == 0 ? 4 : 3);
+    // output channels per block: all up to 64, else groups of 64 or 48;
+    // halved (even counts) while the launch has fewer than 256 blocks
+    int ns = chunks <= 4 ? chunks : (chunks % 4 == 0 ? 4 : 3);
+    const int64_t tiles = (int64_t)((a.W + kCTW - 1) / kCTW) *
+                          ((a.H + kCTH - 1) / kCTH) * a.N;
+    while (ns % 2 == 0 && tiles * (chunks / ns) < 256) ns /= 2;
     if (chunks % ns == 0) {
       switch (ns) {
         case 1: return launch_conv3x3<1>(a, s);
@@ -307,6 +384,7 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
       }
     }
   }
+  if (fused) return hipErrorInvalidValue;
   const int nco = chunks >= 4 ? 4 : chunks;
   const int groups = (chunks + nco - 1) / nco;
   dim3 grid((a.W + 63) / 64, a.H, a.N * groups);

@@ -238,9 +238,14 @@ bool get_params(Net* n, float* host, size_t count) {
   return true;
 }
 
-// conv layer i: input view -> output view (BF16), ReLU
+// conv layer i: input view -> output view (BF16), ReLU; optionally the
+// 2x2 pool of the output to `pool` (channel stride ps) and the input's
+// channels from up_c0 on read upsampled from `up` (channel stride us)
 static hipError_t conv_fwd(Net* n, int i, int level, const uint16_t* in,
-                           int is, int io, uint16_t* out, int os, int oo) {
+                           int is, int io, uint16_t* out, int os, int oo,
+                           uint16_t* pool = nullptr, int ps = 0,
+                           const uint16_t* up = nullptr, int us = 0,
+                           int up_c0 = 0) {
   const LayerDef& L = kLayers[i];
   ConvArgs a{};
   a.in = in;
@@ -262,6 +267,11 @@ static hipError_t conv_fwd(Net* n, int i, int level, const uint16_t* in,
   a.relu = 1;
   a.accumulate = 0;
   a.ksize = L.k;
+  a.pool_out = pool;
+  a.pool_stride = ps;
+  a.up_in = up;
+  a.up_stride = us;
+  a.up_c0 = up_c0;
   return launch_conv(a, n->stream);
 }
 
@@ -271,30 +281,47 @@ static hipError_t conv_fwd(Net* n, int i, int level, const uint16_t* in,
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
-// Forward from the BF16 input tensor T_X to delta (FP32).
+// Forward from the BF16 input tensor T_X to delta (FP32).  The encoders'
+// second convolutions also write the pooled tensor the next level reads;
+// without training, the decoders' first convolutions read the upsampled
+// half of their input straight from the coarser level (training keeps the
+// upsampled copy in the concatenation buffer: the weight gradients read it).
 hipError_t forward_x(Net* n) {
   uint16_t** a = n->act;
   const int N = n->N, H = n->H, W = n->W;
   hipStream_t s = n->stream;
+  const bool fuse_up = !n->training;
   NN_TRY(conv_fwd(n, 0, 0, a[T_X], 16, 0, a[T_E0A], 16, 0));
-  NN_TRY(conv_fwd(n, 1, 0, a[T_E0A], 16, 0, a[T_C0], 48, 0));
-  NN_TRY(launch_pool(a[T_C0], 48, 0, a[T_P0], 16, 0, N, H / 2, W / 2, 16, s));
+  NN_TRY(conv_fwd(n, 1, 0, a[T_E0A], 16, 0, a[T_C0], 48, 0, a[T_P0], 16));
   NN_TRY(conv_fwd(n, 2, 1, a[T_P0], 16, 0, a[T_E1A], 32, 0));
-  NN_TRY(conv_fwd(n, 3, 1, a[T_E1A], 32, 0, a[T_C1], 96, 0));
-  NN_TRY(launch_pool(a[T_C1], 96, 0, a[T_P1], 32, 0, N, H / 4, W / 4, 32, s));
+  NN_TRY(conv_fwd(n, 3, 1, a[T_E1A], 32, 0, a[T_C1], 96, 0, a[T_P1], 32));
   NN_TRY(conv_fwd(n, 4, 2, a[T_P1], 32, 0, a[T_E2A], 64, 0));
-  NN_TRY(conv_fwd(n, 5, 2, a[T_E2A], 64, 0, a[T_C2], 192, 0));
-  NN_TRY(launch_pool(a[T_C2], 192, 0, a[T_P2], 64, 0, N, H / 8, W / 8, 64, s));
+  NN_TRY(conv_fwd(n, 5, 2, a[T_E2A], 64, 0, a[T_C2], 192, 0, a[T_P2], 64));
   NN_TRY(conv_fwd(n, 6, 3, a[T_P2], 64, 0, a[T_E3A], 128, 0));
   NN_TRY(conv_fwd(n, 7, 3, a[T_E3A], 128, 0, a[T_BT], 128, 0));
-  NN_TRY(launch_up(a[T_BT], 128, 0, a[T_C2], 192, 64, N, H / 8, W / 8, 128, s));
-  NN_TRY(conv_fwd(n, 8, 2, a[T_C2], 192, 0, a[T_D2A], 64, 0));
+  if (fuse_up) {
+    NN_TRY(conv_fwd(n, 8, 2, a[T_C2], 192, 0, a[T_D2A], 64, 0, nullptr, 0,
+                    a[T_BT], 128, 64));
+  } else {
+    NN_TRY(launch_up(a[T_BT], 128, 0, a[T_C2], 192, 64, N, H / 8, W / 8, 128, s));
+    NN_TRY(conv_fwd(n, 8, 2, a[T_C2], 192, 0, a[T_D2A], 64, 0));
+  }
   NN_TRY(conv_fwd(n, 9, 2, a[T_D2A], 64, 0, a[T_U2], 64, 0));
-  NN_TRY(launch_up(a[T_U2], 64, 0, a[T_C1], 96, 32, N, H / 4, W / 4, 64, s));
-  NN_TRY(conv_fwd(n, 10, 1, a[T_C1], 96, 0, a[T_D1A], 32, 0));
+  if (fuse_up) {
+    NN_TRY(conv_fwd(n, 10, 1, a[T_C1], 96, 0, a[T_D1A], 32, 0, nullptr, 0,
+                    a[T_U2], 64, 32));
+  } else {
+    NN_TRY(launch_up(a[T_U2], 64, 0, a[T_C1], 96, 32, N, H / 4, W / 4, 64, s));
+    NN_TRY(conv_fwd(n, 10, 1, a[T_C1], 96, 0, a[T_D1A], 32, 0));
+  }
   NN_TRY(conv_fwd(n, 11, 1, a[T_D1A], 32, 0, a[T_U1], 32, 0));
-  NN_TRY(launch_up(a[T_U1], 32, 0, a[T_C0], 48, 16, N, H / 2, W / 2, 32, s));
-  NN_TRY(conv_fwd(n, 12, 0, a[T_C0], 48, 0, a[T_D0A], 16, 0));
+  if (fuse_up) {
+    NN_TRY(conv_fwd(n, 12, 0, a[T_C0], 48, 0, a[T_D0A], 16, 0, nullptr, 0,
+                    a[T_U1], 32, 16));
+  } else {
+    NN_TRY(launch_up(a[T_U1], 32, 0, a[T_C0], 48, 16, N, H / 2, W / 2, 32, s));
+    NN_TRY(conv_fwd(n, 12, 0, a[T_C0], 48, 0, a[T_D0A], 16, 0));
+  }
   NN_TRY(conv_fwd(n, 13, 0, a[T_D0A], 16, 0, a[T_U0], 16, 0));
   NN_TRY(launch_head(a[T_U0], 16, 0, n->w32 + n->woff[14], n->w32 + n->boff[14],
                      16, pix(*n, 0), n->delta, s));

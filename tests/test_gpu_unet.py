@@ -90,6 +90,29 @@ def test_forward_vs_oracle(N, H, W):
     np.testing.assert_array_equal(fld.fldnn_get_params(net), _flat(p))
 
 
+@pytest.mark.parametrize("N,H,W", [(2, 16, 16), (1, 24, 80), (3, 64, 136)])
+def test_fused_inference_forward_is_bit_identical(N, H, W):
+    """Without training the decoders read their upsampled input straight
+    from the coarser level and the encoders write the pooled tensor from
+    their convolution's epilogue; a training-mode network (upsampled copy
+    materialised) must give the same bits."""
+    import torch
+    from paper_2503_02764_amd import fld
+    rng = np.random.default_rng(7 * N + H + W)
+    p = _params(2)
+    x = _f32dev(_bf16(rng.standard_normal((N, H, W, 4))))
+    announce(f"unet fused inference vs training forward N={N} H={H} W={W}")
+    out = []
+    for training in (False, True):
+        net = fld.fldnn_create(N, H, W, training=training)
+        fld.fldnn_set_params(net, _flat(p))
+        delta = torch.empty(N * H * W, dtype=torch.float32, device="cuda")
+        fld.fldnn_forward(net, x, delta)
+        torch.cuda.synchronize()
+        out.append(host(delta))
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 def test_gradients_vs_oracle():
     from paper_2503_02764_amd import fld
     N, H, W = 2, 16, 16
