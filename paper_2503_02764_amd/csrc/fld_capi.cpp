@@ -819,6 +819,9 @@ fld_status solve_krylov(fld_ctx* c) {
   int k_mark = -1;         // stall watch: iteration and residual at a mark
   double res_mark = 0.0;
   int batch = c->last_batch < 1 ? 1 : c->last_batch;
+  // an FP32 retry after a pause: the first batch (sized by the last, FP64,
+  // step) is cut so that a stall shows after a few iterations
+  if (fp32 && c->pre64_span > 0) batch = std::min(batch, 2 * kStallIters);
   c->precond = true;
   fld_status st = FLD_OK;
   for (;;) {
@@ -871,9 +874,14 @@ fld_status solve_krylov(fld_ctx* c) {
       st = coarsen_levels<double>(c, c->h64);
       if (st != FLD_OK) break;
       K.r32 = nullptr;
-      HIP_TRY(c, launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream));
-      HIP_TRY(c, launch_finalize(kFinRestart, c->partials, nb, c->ctrl,
-                                 c->stream));
+      hipError_t e = launch_fcg_init(K, c->h64.x[0], c->h64.b[0], c->stream);
+      if (e == hipSuccess)
+        e = launch_finalize(kFinRestart, c->partials, nb, c->ctrl, c->stream);
+      if (e != hipSuccess) {
+        st = fail(c, FLD_ERR_DEVICE, "flexible CG restart: %s",
+                  hipGetErrorString(e));
+        break;
+      }
       k_first = k;
     } else {
       k_mark = k;
@@ -927,6 +935,9 @@ struct Phase {  // one batched launch: table offset, block starts, counts
 
 struct BatchState {
   int ng = 0;
+  // kernel timing: the first finest-level down pass of the step (every grid
+  // still running) is timed, without graph replay
+  bool time_next = false;
   int tile_var[kMaxLevels][2] = {};  // tile shape per level index: down, up
   std::vector<fld_ctx*> sub;
   char* dev_tab = nullptr;  // device table area (end of the workspace)
@@ -1147,10 +1158,23 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
   const fld_params& p = B->sub[0]->p;
   for (int l = 0; l < B->maxl0; ++l) {
     const Phase& ph = B->down[var][l];
+    // x (unless zero), b, two face arrays read; x and the coarse rhs written
+    double bytes = 0.0;
+    const bool timed = l == 0 && B->time_next;
+    if (timed) {
+      const double w = sizeof(T);
+      for (fld_ctx* c : B->sub)
+        bytes += (double)c->geom[0].N * (w * (var == 0 ? 4.0 : 5.0) + w / 4.0);
+      B->time_next = false;
+    }
+    TimedLaunch t(bc, timed, bytes,
+                  sizeof(T) == 8 ? "k_tile2d_batch<double,down>"
+                                 : "k_tile2d_batch<float,down>");
+    FLD_TRY(t.st);
     HIP_TRY(bc, launch_tile2d_batch<T>(tab_ptr<Tile2DArgs<T>>(B, ph),
                                        start_ptr(B, ph), ph.ng, ph.nblocks,
                                        nu_pre(p, l), true, B->tile_var[l][0],
-                                       s));
+                                       s, t.e0, t.e1));
     if (sizeof(T) == 8 && l == 0)
       HIP_TRY(bc, launch_finalize_batch(kFinCycle,
                                         tab_ptr<JobFinalize>(B, B->fin_c),
@@ -1267,6 +1291,7 @@ fld_status batch_step_impl(fld_ctx* bc, const double* dt,
       B->sub[0]->mixed ? maxc / B->sub[0]->inner + 2 : maxc;
   int done_iters = 0;
   int batch = B->last_batch < 1 ? 1 : B->last_batch;
+  B->time_next = bc->timing && !B->graph_on;
   for (;;) {
     if (batch > max_iters - done_iters) batch = max_iters - done_iters;
     if (batch < 1) break;
@@ -1281,6 +1306,16 @@ fld_status batch_step_impl(fld_ctx* bc, const double* dt,
     batch = 1;
   }
   if (all_stopped(B)) B->last_batch = done_iters;
+  // the timed launches ran while every grid was running: all count
+  for (size_t i = 0; i + 1 < bc->ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(bc, hipEventElapsedTime(&ms, bc->ev[i], bc->ev[i + 1]));
+    bc->t_ms += ms;
+    bc->t_launches += 1;
+    bc->t_bytes += bc->ev_bytes[i / 2];
+  }
+  bc->ev_used = 0;
+  bc->ev_bytes.clear();
   return FLD_OK;
 }
 

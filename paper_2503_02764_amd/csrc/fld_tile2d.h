@@ -63,10 +63,12 @@ int tile2d_grid(const Geom& g, int nu, bool down, int variant, int* tiles_x,
 
 // Batched form: tab[g] (device memory, tiles_x/tiles_y filled in) are the
 // arguments of grid g, whose tiles are blocks start[g] .. start[g+1]-1 of a
-// launch of nblocks blocks.
+// launch of nblocks blocks.  With ev0/ev1 the launch records them itself.
 template <typename T>
 hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
                                int ng, int nblocks, int nu, bool down,
-                               int variant, hipStream_t s);
+                               int variant, hipStream_t s,
+                               hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr);
 
 }  // namespace fld

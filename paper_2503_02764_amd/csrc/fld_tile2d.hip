@@ -505,28 +505,34 @@ int tile2d_vec_ok(const Tile2DArgs<T>& a) {
 
 template <typename T, int RX, int NPY, int K, int NU, bool DOWN>
 static hipError_t launch_batch_one(const Tile2DArgs<T>* tab, const int* start,
-                                   int ng, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_tile2d_batch<T, RX, NPY, K, NU, DOWN>), dim3(nblocks),
-                     dim3(RX / 2 * NPY), 0, s, tab, start, ng);
+                                   int ng, int nblocks, hipStream_t s,
+                                   hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL((k_tile2d_batch<T, RX, NPY, K, NU, DOWN>),
+                          dim3(nblocks), dim3(RX / 2 * NPY), 0, s, ev0, ev1, 0,
+                          tab, start, ng);
+  else
+    hipLaunchKernelGGL((k_tile2d_batch<T, RX, NPY, K, NU, DOWN>), dim3(nblocks),
+                       dim3(RX / 2 * NPY), 0, s, tab, start, ng);
   return hipGetLastError();
 }
 
 template <typename T, int RX, int NPY, int K>
 static hipError_t batch_shape(const Tile2DArgs<T>* tab, const int* start,
                               int ng, int nblocks, int nu, bool down,
-                              hipStream_t s) {
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (down) {
     switch (nu) {
-      case 1: return launch_batch_one<T, RX, NPY, K, 1, true>(tab, start, ng, nblocks, s);
-      case 2: return launch_batch_one<T, RX, NPY, K, 2, true>(tab, start, ng, nblocks, s);
-      case 3: return launch_batch_one<T, RX, NPY, K, 3, true>(tab, start, ng, nblocks, s);
+      case 1: return launch_batch_one<T, RX, NPY, K, 1, true>(tab, start, ng, nblocks, s, ev0, ev1);
+      case 2: return launch_batch_one<T, RX, NPY, K, 2, true>(tab, start, ng, nblocks, s, ev0, ev1);
+      case 3: return launch_batch_one<T, RX, NPY, K, 3, true>(tab, start, ng, nblocks, s, ev0, ev1);
       default: return hipErrorInvalidValue;
     }
   }
   switch (nu) {
-    case 1: return launch_batch_one<T, RX, NPY, K, 1, false>(tab, start, ng, nblocks, s);
-    case 2: return launch_batch_one<T, RX, NPY, K, 2, false>(tab, start, ng, nblocks, s);
-    case 3: return launch_batch_one<T, RX, NPY, K, 3, false>(tab, start, ng, nblocks, s);
+    case 1: return launch_batch_one<T, RX, NPY, K, 1, false>(tab, start, ng, nblocks, s, ev0, ev1);
+    case 2: return launch_batch_one<T, RX, NPY, K, 2, false>(tab, start, ng, nblocks, s, ev0, ev1);
+    case 3: return launch_batch_one<T, RX, NPY, K, 3, false>(tab, start, ng, nblocks, s, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -534,12 +540,13 @@ static hipError_t batch_shape(const Tile2DArgs<T>* tab, const int* start,
 template <typename T>
 hipError_t launch_tile2d_batch(const Tile2DArgs<T>* tab, const int* start,
                                int ng, int nblocks, int nu, bool down,
-                               int variant, hipStream_t s) {
+                               int variant, hipStream_t s, hipEvent_t ev0,
+                               hipEvent_t ev1) {
   if (nblocks == 0) return hipSuccess;
   if (variant < 0 || variant >= kTileVariantsBatch) return hipErrorInvalidValue;
   switch (variant) {
 #define FLD_SHAPE_CASE(v, rx, npy, k) \
-  case v: return batch_shape<T, rx, npy, k>(tab, start, ng, nblocks, nu, down, s);
+  case v: return batch_shape<T, rx, npy, k>(tab, start, ng, nblocks, nu, down, s, ev0, ev1);
     FLD_TILE_SHAPES(FLD_SHAPE_CASE)
 #undef FLD_SHAPE_CASE
     default: return hipErrorInvalidValue;
@@ -628,9 +635,11 @@ template hipError_t launch_tile2d<float>(const Tile2DArgs<float>&, int, bool,
                                          hipEvent_t);
 template hipError_t launch_tile2d_batch<double>(const Tile2DArgs<double>*,
                                                 const int*, int, int, int,
-                                                bool, int, hipStream_t);
+                                                bool, int, hipStream_t,
+                                                hipEvent_t, hipEvent_t);
 template hipError_t launch_tile2d_batch<float>(const Tile2DArgs<float>*,
                                                const int*, int, int, int, bool,
-                                               int, hipStream_t);
+                                               int, hipStream_t, hipEvent_t,
+                                               hipEvent_t);
 
 }  // namespace fld
