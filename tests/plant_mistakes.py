@@ -3,7 +3,9 @@ catch every one.
 
 Runs on the CPU only: each entry replaces one expression of oracle/ in a
 temporary copy of the repository and runs `pytest -m "not gpu"` there; a
-mistake that no pin catches is reported as MISSED.  Usage:
+mistake that no pin catches is reported as MISSED.  (Transposing grad v in
+the tiring term is no mistake: the Eddington tensor is symmetric, so
+P : grad v = P : grad v^T; it is not listed.)  Usage:
     python tests/plant_mistakes.py
 """
 import os, shutil, subprocess, sys
@@ -37,6 +39,16 @@ M = [
  ("fldref.py", "S = E_star + e\n", "S = E_star\n", "S without e"),
  ("fldref.py", "x = quartic_root(a4, 1.0 + beta, e + beta * S)", "x = quartic_root(a4, beta, e + beta * S)", "quartic linear coefficient without 1"),
  ("fldref.py", "return S - x, x", "return S - x, S - x", "exchange returns wrong e"),
+ ("fldref.py", "low = 2.0 / (3.0 + np.sqrt(9.0 + 12.0 * R * R))", "low = 2.0 / (3.0 + np.sqrt(9.0 + 6.0 * R * R))", "Minerbo low branch 6 R^2"),
+ ("fldref.py", "high = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))", "high = 1.0 / (1.0 + R + np.sqrt(1.0 + R))", "Minerbo high branch sqrt(1 + R)"),
+ ("fldref.py", "return np.where(R <= 1.5, low, high)", "return np.where(R <= 1.0, low, high)", "Minerbo switch at R = 1"),
+ ("fldref.py", "return lam + lam * lam * R * R", "return lam + lam * R * R", "Eddington factor lambda R^2"),
+ ("explicit.py", "fr = [-lam * g for g in G]", "fr = [lam * g for g in G]", "radiation force sign"),
+ ("explicit.py", "work = sum(v[d] * fr[d] for d in range(nd))", "work = sum(v[0] * fr[d] for d in range(nd))", "work with v_x only"),
+ ("explicit.py", "t_ij = 0.5 * (3.0 * f - 1.0) * n[i] * n[j]", "t_ij = 0.5 * (3.0 * f - 1.0) * n[i] * n[i]", "Eddington tensor n_i n_i"),
+ ("explicit.py", "                t_ij = t_ij + 0.5 * (1.0 - f)", "                t_ij = t_ij + (1.0 - f)", "Eddington tensor isotropic part without 1/2"),
+ ("explicit.py", "tiring = tiring + t_ij * grads[j][i]", "tiring = tiring + t_ij * grads[j][j]", "tiring with d_j v_j in every entry"),
+ ("explicit.py", "tiring = E * tiring", "tiring = tiring", "tiring without E"),
  ("unet_ref.py", "mh = m[k] / (1 - b1 ** t)", "mh = m[k]", "Adam without first-moment bias correction"),
  ("unet_ref.py", "vh = v[k] / (1 - b2 ** t)", "vh = v[k]", "Adam without second-moment bias correction"),
  ("unet_ref.py", "p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)", "p[k] = p[k] - lr * mh / np.sqrt(vh + eps)", "Adam eps inside sqrt"),

@@ -237,6 +237,12 @@ def test_minerbo_limiter_hand_values_and_limits():
     assert lam(0.0, "minerbo") == pytest.approx(1.0 / 3.0, rel=1e-15)
     assert lam(1.0, "minerbo") == pytest.approx(2.0 / (3.0 + np.sqrt(21.0)),
                                                 rel=1e-15)
+    # between R = 1 and 3/2 the lower branch still holds: at R = 6/5,
+    # 2 / (3 + sqrt(9 + 17.28)) = 0.246105..., not the upper branch's
+    # 1 / (2.2 + sqrt 3.4) = 0.247285...
+    assert lam(1.2, "minerbo") == pytest.approx(
+        2.0 / (3.0 + np.sqrt(26.28)), rel=1e-15)
+    assert abs(lam(1.2, "minerbo") - 1.0 / (2.2 + np.sqrt(3.4))) > 1e-3
     assert lam(1.5, "minerbo") == pytest.approx(2.0 / 9.0, rel=1e-15)
     assert lam(1.5 + 1e-12, "minerbo") == pytest.approx(2.0 / 9.0, rel=1e-10)
     assert lam(4.0, "minerbo") == pytest.approx(0.125, rel=1e-15)

@@ -132,6 +132,35 @@ def test_tiring_of_a_shear_across_a_diagonal_gradient():
     assert np.all(f[INNER] > 1.0 / 3.0)
 
 
+def test_tiring_of_a_shear_across_an_oblique_gradient():
+    """E = exp(kx x + ky y) with kx != ky: the five-point stencil gives
+    G = E (gx, gy) with gx = (16 sinh(kx h) - 2 sinh(2 kx h)) / (12 h) (and
+    gy likewise), so n = (gx, gy)/|g| is constant and oblique; R = |g| /
+    (rho kappa).  The pure shear v = (c y, 0) gives P : grad v =
+    E (3 f - 1)/2 n_x n_y c, which tells n_x n_y from n_y^2 (the off-axis
+    entry of the Eddington tensor)."""
+    n = (40, 40)
+    h = 1.0 / 40
+    prob = _prob(n, ["neumann", "neumann"])
+    x, y = _xy(n)
+    kx, ky = 2.0, 0.5
+    E = np.exp(kx * x + ky * y)
+    rho = np.full_like(E, 0.5)
+    kap = np.full_like(E, 3.0)
+    c = 0.9
+    _, _, tir, f = X.explicit_sources(E, rho, kap, [c * y, np.zeros_like(E)],
+                                      prob)
+    g = [(16.0 * np.sinh(k * h) - 2.0 * np.sinh(2.0 * k * h)) / (12.0 * h)
+         for k in (kx, ky)]
+    gm = np.hypot(g[0], g[1])
+    R = gm / 1.5
+    lam = (2.0 + R) / (6.0 + 3.0 * R + R * R)
+    fe = lam + lam * lam * R * R
+    expect = E * 0.5 * (3.0 * fe - 1.0) * (g[0] / gm) * (g[1] / gm) * c
+    np.testing.assert_allclose(f[INNER], fe, rtol=1e-12)
+    np.testing.assert_allclose(tir[INNER], expect[INNER], rtol=1e-11)
+
+
 def test_uniform_motion_does_no_work_on_radiation():
     """A uniform velocity has grad v = 0: no photon tiring (3D, periodic)."""
     n = (8, 6, 10)
