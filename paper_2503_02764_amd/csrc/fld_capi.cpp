@@ -728,22 +728,32 @@ fld_status solve_fp64(fld_ctx* c) {
   return FLD_OK;
 }
 
-// FP32 V-cycles inside an FP64 iterative refinement.
+// FP32 V-cycles inside an FP64 iterative refinement.  The FP64 residual
+// (with its FP32 copy and the stop test) is taken once up front and then at
+// the end of every correction, so a batch is exactly the corrections the
+// last step needed: no correction's V-cycles are enqueued behind the test
+// that ends the solve (they would return at once, but still cost their
+// launches).
 fld_status solve_mixed(fld_ctx* c) {
   const Geom& g0 = c->geom[0];
+  auto check = [&]() -> fld_status {
+    int nb = 0;
+    HIP_TRY(c, launch_resid_to32(view(c, c->h64, 0), c->h32.b[0], c->partials,
+                                 &nb, c->ctrl, c->stream));
+    HIP_TRY(c, launch_finalize(kFinOuter, c->partials, nb, c->ctrl, c->stream));
+    return FLD_OK;
+  };
   int enqueued = 0;
   int batch = c->last_batch < 1 ? 1 : c->last_batch;
   const int max_outer = c->p.max_cycles / c->inner + 2;
+  FLD_TRY(check());
   for (;;) {
     for (int k = 0; k < batch; ++k) {
-      int nb = 0;
-      HIP_TRY(c, launch_resid_to32(view(c, c->h64, 0), c->h32.b[0],
-                                   c->partials, &nb, c->ctrl, c->stream));
-      HIP_TRY(c, launch_finalize(kFinOuter, c->partials, nb, c->ctrl, c->stream));
       for (int i = 0; i < c->inner; ++i)
         FLD_TRY(vcycle<float>(c, c->h32, i == 0));
       HIP_TRY(c, launch_correct(g0.N, c->h64.x[0], c->h32.x[0], c->ctrl,
                                 c->stream));
+      FLD_TRY(check());
     }
     enqueued += batch;
     FLD_TRY(read_control(c));
@@ -751,8 +761,7 @@ fld_status solve_mixed(fld_ctx* c) {
     batch = 1;
   }
   if (c->host_ctrl->done == kRunning) c->host_ctrl->done = kCapped;
-  if (c->host_ctrl->done == kConverged)
-    c->last_batch = c->host_ctrl->outer + 1;
+  if (c->host_ctrl->done == kConverged) c->last_batch = c->host_ctrl->outer;
   return FLD_OK;
 }
 
@@ -1196,22 +1205,30 @@ fld_status batch_vcycle(fld_ctx* bc, int var) {
   return FLD_OK;
 }
 
-// One refinement iteration (mixed) or one V-cycle (FP64) over all grids.
-fld_status batch_iteration(fld_ctx* bc) {
+// FP64 residual, its FP32 copy and the refinement stop test of every grid.
+fld_status batch_check(fld_ctx* bc) {
   BatchState* B = bc->batch;
   hipStream_t s = bc->stream;
-  if (!B->sub[0]->mixed) return batch_vcycle<double>(bc, 1);
   HIP_TRY(bc, launch_resid_batch(tab_ptr<JobResid>(B, B->resid),
                                  start_ptr(B, B->resid), B->resid.ng,
                                  B->resid.nblocks, s));
   HIP_TRY(bc, launch_finalize_batch(kFinOuter, tab_ptr<JobFinalize>(B, B->fin_r),
                                     B->fin_r.ng, s));
+  return FLD_OK;
+}
+
+// One refinement correction followed by its check (mixed; the first check
+// comes before the iterations), or one V-cycle (FP64), over all grids.
+fld_status batch_iteration(fld_ctx* bc) {
+  BatchState* B = bc->batch;
+  hipStream_t s = bc->stream;
+  if (!B->sub[0]->mixed) return batch_vcycle<double>(bc, 1);
   const int inner = B->sub[0]->inner;
   for (int i = 0; i < inner; ++i) FLD_TRY(batch_vcycle<float>(bc, i == 0 ? 0 : 1));
   HIP_TRY(bc, launch_correct_batch(tab_ptr<JobCorrect>(B, B->correct),
                                    start_ptr(B, B->correct), B->correct.ng,
                                    B->correct.nblocks, s));
-  return FLD_OK;
+  return batch_check(bc);
 }
 
 // `iters` iterations, replayed from a captured graph when enabled.
@@ -1292,6 +1309,7 @@ fld_status batch_step_impl(fld_ctx* bc, const double* dt,
   int done_iters = 0;
   int batch = B->last_batch < 1 ? 1 : B->last_batch;
   B->time_next = bc->timing && !B->graph_on;
+  if (B->sub[0]->mixed) FLD_TRY(batch_check(bc));
   for (;;) {
     if (batch > max_iters - done_iters) batch = max_iters - done_iters;
     if (batch < 1) break;
