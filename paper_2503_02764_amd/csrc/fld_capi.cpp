@@ -661,6 +661,29 @@ fld_status vcycle(fld_ctx* c, const Levels<T>& H, bool zero_first) {
   return FLD_OK;
 }
 
+// An FP64 V-cycle split at its stop test (multi-level fast path): `head`
+// is the finest down pass with the test itself (a finalize launch where a
+// tiled level 1 would otherwise take it), `tail` the rest of the cycle.
+fld_status vcycle_head(fld_ctx* c, const Levels<double>& H) {
+  FLD_TRY(down<double>(c, H, 0, false));
+  if (c->pending_fin > 0) {
+    HIP_TRY(c, launch_finalize(kFinCycle, c->partials, c->pending_fin, c->ctrl,
+                               c->stream));
+    c->pending_fin = 0;
+  }
+  return FLD_OK;
+}
+
+fld_status vcycle_tail(fld_ctx* c, const Levels<double>& H) {
+  const int l0 = c->tail_l0;
+  for (int l = 1; l < l0; ++l) FLD_TRY(down<double>(c, H, l, true));
+  TailArgs<double> ta = tail_args<double>(c, H, l0, false);
+  ta.zero = l0 > 0;
+  HIP_TRY(c, launch_tail<double>(ta, c->stream));
+  for (int l = l0 - 1; l >= 0; --l) FLD_TRY(up<double>(c, H, l));
+  return FLD_OK;
+}
+
 // Launches after the stop flag was set return at once; the first `cycles`
 // timed launches of the solve are the ones that did the work.
 fld_status collect_timing(fld_ctx* c) {
@@ -688,7 +711,12 @@ fld_status read_control(fld_ctx* c) {
   return FLD_OK;
 }
 
-// FP64 V-cycles until the device stop flag is set.
+// FP64 V-cycles until the device stop flag is set.  Cycles are enqueued in
+// batches between reads of the control block; a batch ends with the finest
+// down pass and stop test of the cycle predicted to stop (the last step's
+// count), so the rest of that cycle is not enqueued behind the test that
+// ends the solve (its launches would return at once, but still cost their
+// issue); when the test says to go on, the cycle is finished first.
 fld_status solve_fp64(fld_ctx* c) {
   int nb = 0;
   if (!c->init_fused) {
@@ -703,16 +731,25 @@ fld_status solve_fp64(fld_ctx* c) {
                                    c->stream));
     return read_control(c);
   }
+  const bool split = c->fast && c->tail_l0 > 0;
   int enqueued = 0;
+  bool open_cycle = false;  // the last batch stopped after a cycle's head
   int batch = c->last_batch < 1 ? 1 : c->last_batch;
   for (;;) {
+    if (open_cycle) {
+      FLD_TRY(vcycle_tail(c, c->h64));
+      open_cycle = false;
+    }
     if (batch > c->p.max_cycles - enqueued) batch = c->p.max_cycles - enqueued;
     for (int k = 0; k < batch; ++k) {
       c->fin_cycle = enqueued + k;
-      const fld_status st = vcycle<double>(c, c->h64, false);
+      const bool head_only = split && k == batch - 1;
+      const fld_status st = head_only ? vcycle_head(c, c->h64)
+                                      : vcycle<double>(c, c->h64, false);
       c->fin_cycle = -1;
       c->pending_fin = 0;
       FLD_TRY(st);
+      open_cycle = head_only;
     }
     // a stop right after the finest down pass leaves the iterate in the
     // alternate buffer of the tiled path (the copy checks the device flag)
