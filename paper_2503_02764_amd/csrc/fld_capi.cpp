@@ -95,6 +95,7 @@ struct fld_ctx {
   int tail_l0 = 0;   // first level handled by the single-workgroup tail
   bool coarsen_multi = true;  // 2D: several coarse levels per launch
   bool sweep3d = true;        // 3D: fused red-black sweeps where planned
+  bool level_lds = true;      // small 3D coarse levels in one workgroup
   int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
@@ -491,6 +492,13 @@ bool fused_level(const fld_ctx* c, const Levels<T>& H, int l) {
 // iterate, and writing its half: 4.5 N elements touched once; a fused sweep
 // reads b, the three face arrays and the iterate and writes the whole
 // iterate: 6 N.
+// a coarse 3D level small enough for one workgroup (fld_level.hip), above
+// the tail
+bool level_lds(const fld_ctx* c, int l) {
+  return c->level_lds && l >= 1 && l < c->tail_l0 &&
+         level_lds_ok(c->geom[l], c->geom[l + 1]);
+}
+
 template <typename T>
 fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
                          bool timed_fused, bool timed_colour) {
@@ -533,6 +541,11 @@ template <typename T>
 fld_status down(fld_ctx* c, const Levels<T>& H, int l, bool zero_init) {
   const bool norm = (sizeof(T) == 8) && l == 0 && !c->precond;
   int nb = 0;
+  if (level_lds(c, l)) {  // (l >= 1: its x was zeroed by the restriction)
+    HIP_TRY(c, launch_level_down<T>(view(c, H, l), view(c, H, l + 1),
+                                    nu_pre(c->p, l), c->ctrl, c->stream));
+    return FLD_OK;
+  }
   if (tile_path(c)) {
     Tile2DArgs<T> a{};
     a.g = c->geom[l];
@@ -608,6 +621,11 @@ fld_status up(fld_ctx* c, const Levels<T>& H, int l) {
     int nb = 0;
     HIP_TRY(c, launch_tile2d<T>(a, nu_post(c->p, l), false, c->tile_var[l][1],
                                 c->stream, &nb));
+    return FLD_OK;
+  }
+  if (level_lds(c, l)) {
+    HIP_TRY(c, launch_level_up<T>(view(c, H, l), view(c, H, l + 1),
+                                  nu_post(c->p, l), c->ctrl, c->stream));
     return FLD_OK;
   }
   HIP_TRY(c, launch_prolong<T>(view(c, H, l + 1), view(c, H, l), c->ctrl,
@@ -1478,6 +1496,10 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
     if (v > 1) c->sweep_zc = v;
   }
   c->sweep3d = c->sweep3d && c->fast;
+  // small 3D coarse levels by colour-pass launches ("0"; tests that both
+  // forms agree bitwise)
+  if (const char* lv = getenv("FLD_LEVEL_LDS")) c->level_lds = atoi(lv) != 0;
+  c->level_lds = c->level_lds && c->fast;
   // fixed tile shape for every level (tests of shape independence)
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {
     const int v = atoi(tv);

@@ -207,6 +207,16 @@ hipError_t launch_fill32(float* x, int64_t n, hipStream_t s);
 
 // Levels up to this many cells run in the single-workgroup tail, in LDS.
 constexpr int64_t kTailLdsCells = 1024;
+// 3D coarse levels of at most this many cells above the tail run their down
+// and up passes in one workgroup each (fld_level.hip)
+constexpr int kLevelLdsCells = 4096;
+bool level_lds_ok(const Geom& g, const Geom& coarse);
+template <typename T>
+hipError_t launch_level_down(const LevelView<T>& F, const LevelView<T>& C,
+                             int sweeps, const Control* ctrl, hipStream_t s);
+template <typename T>
+hipError_t launch_level_up(const LevelView<T>& F, const LevelView<T>& C,
+                           int sweeps, const Control* ctrl, hipStream_t s);
 
 // finalize modes
 // kFinOuter: FP64 residual of a refinement iteration (first call also sets

@@ -105,3 +105,31 @@ def test_marching_residual_restriction_matches_plane_pairs(precision,
                         precision=precision)
         assert s0["cycles"] == s1["cycles"], (n, s0, s1)
         assert np.linalg.norm(x1 - x0) <= 1e-13 * np.linalg.norm(x0), n
+
+
+@pytest.mark.parametrize("n,bc", [
+    ((32, 32, 32), ("periodic", "periodic", "periodic")),
+    ((40, 24, 16), ("neumann", "periodic", "neumann")),
+    ((64, 32, 16), ("neumann", "periodic", "neumann")),
+])
+@pytest.mark.parametrize("precision,krylov", [("fp64", False), ("fp32_ir", False),
+                                              ("fp32_ir", True)])
+def test_small_levels_in_one_workgroup_match_colour_passes(n, bc, precision,
+                                                           krylov,
+                                                           monkeypatch):
+    """Coarse 3D levels of at most 4096 cells above the tail run their down
+    and up passes in one workgroup each (the default); FLD_LEVEL_LDS=0 runs
+    them by colour passes, the residual-restriction and the prolongation
+    kernels.  Same operations in the same order: the same cycle counts and
+    the same iterate, bit for bit."""
+    m = media.random_small_medium(sum(n) + 5, n, bc)
+    kw = dict(rtol=1e-12, max_cycles=300, precision=precision, krylov=krylov,
+              coarse_pre_smooth=3, coarse_post_smooth=3)
+    announce(f"small levels in one workgroup n={n} {precision} krylov={krylov}")
+    monkeypatch.setenv("FLD_LEVEL_LDS", "0")
+    x0, s0 = _solve(m, None, monkeypatch, **kw)
+    monkeypatch.delenv("FLD_LEVEL_LDS")
+    x1, s1 = _solve(m, None, monkeypatch, **kw)
+    assert s0["cycles"] == s1["cycles"] and s0["outer_iters"] == s1["outer_iters"]
+    np.testing.assert_array_equal(x0, x1)
+    assert s1["rel_res_final"] <= 1e-12
