@@ -172,7 +172,13 @@ fld_status fld_setup(const fld_params* p, void* workspace, size_t ws_bytes,
  * Solved by V-cycles until |E_in - A E_out|_2 / |E_in|_2 <= rtol.
  * rho, kappa, E_in: device, read only.  E_out: device, written; it may
  * alias E_in.  stats: host pointer or NULL.
- * Blocks the calling thread until convergence is known.  Returns
+ * Blocks the calling thread until convergence is known, with or without
+ * stats: the number of V-cycles is not known in advance, so cycles are
+ * enqueued in batches (sized by the last step's count) between reads of
+ * the device's stop flag, and the host decides after each read whether to
+ * enqueue more (a solve entirely on the device would need a launch that
+ * enqueues launches, or a persistent kernel with grid barriers, which cost
+ * as much as the launches they replace on this GPU).  Returns
  * FLD_ERR_NONPHYSICAL if any cell has E <= 0, rho kappa <= 0 or a
  * non-finite input (outputs unspecified), FLD_ERR_NOT_CONVERGED after
  * max_cycles (E_out holds the last iterate, stats the residual). */
