@@ -12,10 +12,11 @@
 // eight coarsening launches (most of them a single block of latency) become
 // three.
 //
-//   k_coarsen2d_pair: levels l+1 and l+2 from level l.  A block owns a 16x16
+//   k_coarsen2d_pair: levels l+1 and l+2 from level l.  A block owns a PT x PT
 //     tile of level l+2; it computes the level-(l+1) faces that tile needs
-//     (its own 32x32 plus one more face along the face direction) into LDS,
-//     writes its own 32x32 of them, then the level-(l+2) tile from LDS.
+//     (its own 2PT x 2PT plus one more face along the face direction) into
+//     LDS, writes its own 2PT x 2PT of them, then the level-(l+2) tile from
+//     LDS.
 //   k_coarsen2d_whole: every remaining level from level l in one block of
 //     1024 threads, whole levels in LDS (level l+1 of at most 1024 cells).
 #include "fld_internal.h"
@@ -25,7 +26,10 @@ namespace fld {
 
 namespace {
 
-constexpr int PT = 16;           // level-(l+2) tile of the pair kernel
+// level-(l+2) tile of the pair kernel: 8 x 8, so that a 1024^2 grid's
+// first pair runs 1024 blocks of about one round of loads each (16 x 16:
+// 256 blocks, one per CU, each thread four dependent rounds)
+constexpr int PT = 8;
 constexpr int PR = 2 * PT;       // level-(l+1) cells of the tile per side
 constexpr int PNT = 256;         // pair kernel threads
 constexpr int WNT = 1024;        // whole-levels kernel threads
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(PNT) k_coarsen2d_pair(Coarsen2DArgs<T> A) {
   // global indices of coarse_face)
   const int i = threadIdx.x % PT, j = threadIdx.x / PT;
   const int X = ox2 + i, Y = oy2 + j;
-  if (X < n2 && Y < m2) {
+  if (j < PT && X < n2 && Y < m2) {
     auto lx_ = [&](int d, int x, int y) {
       // x, y are level-(l+1) indices relative to the tile origin
       return d == 0 ? fx[y][x] : fy[y][x];
