@@ -96,6 +96,7 @@ struct fld_ctx {
   bool coarsen_multi = true;  // 2D: several coarse levels per launch
   bool sweep3d = true;        // 3D: fused red-black sweeps where planned
   bool level_lds = true;      // small 3D coarse levels in one workgroup
+  bool tail_big = true;       // 2D: tail from a level of up to 4096 cells
   int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
@@ -1455,6 +1456,21 @@ fld_status check_setup(const fld_params* p, const void* workspace,
 // Point a context's level buffers into the workspace and apply the
 // environment switches of the tests (kernel path, coarsening form, fused
 // 3D sweeps, fixed tile shape).  Allocates nothing.
+// First level of the single-workgroup tail: the first of at most 1024
+// cells, or the level above it where the 2D tail from a level of up to
+// 4096 cells fits (c->tail_big).
+void choose_tail(fld_ctx* c) {
+  c->tail_l0 = c->L - 1;
+  for (int l = 0; l < c->L; ++l)
+    if (c->geom[l].N <= kTailLdsCells) {
+      c->tail_l0 = l;
+      break;
+    }
+  if (c->fast && c->tail_big && c->tail_l0 >= 2 &&
+      tail2d_big_fits(c->geom + c->tail_l0 - 1, c->L - c->tail_l0 + 1))
+    c->tail_l0 -= 1;
+}
+
 void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
               size_t ws_bytes, void* hip_stream) {
   c->p = *p;
@@ -1506,12 +1522,12 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
     if (v >= 0 && v < kTileVariants)
       for (int l = 0; l < kMaxLevels; ++l) c->tile_var[l][0] = c->tile_var[l][1] = v;
   }
-  c->tail_l0 = c->L - 1;
-  for (int l = 0; l < c->L; ++l)
-    if (c->geom[l].N <= kTailLdsCells) {
-      c->tail_l0 = l;
-      break;
-    }
+  // a 2D tail starts one level higher where that level (not the finest)
+  // has at most 4096 cells: two launches fewer per V-cycle ("0": the tail
+  // from the first level of at most 1024 cells; tests that both forms
+  // agree bitwise)
+  if (const char* tb = getenv("FLD_TAIL_BIG")) c->tail_big = atoi(tb) != 0;
+  choose_tail(c);
   c->bcopy = (double*)(w + P.bcopy);
   c->dscr = P.dscr ? (double*)(w + P.dscr) : nullptr;
   c->partials = (double*)(w + P.partials);
@@ -2209,6 +2225,9 @@ fld_status fld_setup_batch(int32_t count, const fld_params* each,
       fld_destroy(bc);
       return fail(nullptr, st, "grid %d: %s", g, msg.c_str());
     }
+    // the batched tails start at the first level of at most 1024 cells
+    c->tail_big = false;
+    choose_tail(c);
     B->sub.push_back(c);
     B->maxL = std::max(B->maxL, c->L);
     B->maxl0 = std::max(B->maxl0, c->tail_l0);

@@ -178,6 +178,13 @@ template <typename T>
 hipError_t launch_tail2d(const TailArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_tail2d_batch(const TailArgs<T>* tab, int ng, hipStream_t s);
+// The same for tails whose first level has 1025..4096 cells (one block of
+// 1024 threads); tail2d_big_fits checks the level geometries g[0..nt).
+bool tail2d_big_fits(const Geom* g, int nt);
+template <typename T>
+bool tail2d_big_ok(const TailArgs<T>& a);
+template <typename T>
+hipError_t launch_tail2d_big(const TailArgs<T>& a, hipStream_t s);
 // LDS bytes the LDS tail needs (0 when the levels do not fit).
 template <typename T>
 size_t tail_lds_bytes(const TailArgs<T>& a);

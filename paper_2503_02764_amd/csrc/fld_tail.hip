@@ -415,6 +415,10 @@ hipError_t launch_tail_lds(const TailArgs<T>& a, hipStream_t s, bool* used) {
     *used = true;
     return launch_tail2d(a, s);
   }
+  if (tail2d_big_ok(a)) {
+    *used = true;
+    return launch_tail2d_big(a, s);
+  }
   const size_t lds = tail_lds_bytes(a);
   *used = lds > 0 && lds <= 62 * 1024;
   if (!*used) return hipSuccess;

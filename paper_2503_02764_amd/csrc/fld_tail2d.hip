@@ -18,6 +18,11 @@
 // d (x_update - x).  Only the iterates (and a residual scratch for the
 // restriction onto tiny levels) live in LDS.
 //
+// A second kernel, k_tail2d_big (1024 threads), starts one level higher,
+// on a level of 1025..4096 cells held as 2x2 blocks, and runs the next two
+// levels one cell per thread: on a 1024^2 grid that replaces the tiled
+// down and up passes of the 64^2 level (two launches per V-cycle).
+//
 // The multigrid itself is that of the other tail kernels: pre-smoothing,
 // residual restricted by the mean of the 2x2 children, coarse correction
 // from zero, coarsest red-black sweeps until the residual drops by 1e-3
@@ -502,6 +507,466 @@ __device__ __forceinline__ void tail2d_body(const TailArgs<T>& A) {
   }
 }
 
+namespace {
+
+// ---- tails whose first level has 1025..4096 cells ----
+//
+// One block of 1024 threads.  The first level ("big") is owned as 2x2 cell
+// blocks, thread t owning block t; the next two levels (257..1024 and
+// 65..256 cells) one cell per thread; the tiny levels run in wave 0 as in
+// tail2d_body.  Big thread t's block restricts onto cell t of the next
+// level, which thread t owns, and that cell is the block's own parent in
+// the prolongation, so neither transfer goes through LDS.  At this block
+// size a thread has at most 128 registers: the tiny levels' weights wait in
+// LDS, and the LDS copy of the big iterate serves as the residual scratch
+// while the coarser levels run (the big level's prolongation rewrites it).
+// Every operation and its rounding are those of the tiled down and up
+// passes on the big level followed by tail2d_body on the rest.
+
+constexpr int NTB = 1024;
+constexpr int kBigMax = 4 * NTB;
+constexpr int kSingles = 2;
+constexpr int kGX = 0;                            // big iterate
+constexpr int kGR = kGX;                          // residual scratch
+constexpr int kG1 = kGX + kBigMax;                // first single level
+constexpr int kG2 = kG1 + kWideMax;               // second single level
+constexpr int kGT = kG2 + kNarrowMax;             // tiny iterates
+constexpr int kGW = kGT + kTinyMax * kTinyCells;  // tiny weights, 6 a cell
+constexpr int kGTotal = kGW + 6 * kTinyMax * kTinyCells;
+
+}  // namespace
+
+// Levels g[0..nt) fit k_tail2d_big: 2D with a red-black colouring, the
+// first of 1025..4096 cells, every next one with both sides halved, and
+// one to kTinyMax levels after the two single ones.
+bool tail2d_big_fits(const Geom* g, int nt) {
+  if (nt < 2 + kSingles || nt > 1 + kSingles + kTinyMax) return false;
+  if (g[0].N <= kWideMax || g[0].N > kBigMax) return false;
+  for (int j = 0; j < nt; ++j) {
+    if (g[j].ndim != 2 || gs_colors(g[j]) != 2) return false;
+    if (j > 0 && (g[j - 1].n[0] != 2 * g[j].n[0] ||
+                  g[j - 1].n[1] != 2 * g[j].n[1]))
+      return false;
+  }
+  return true;
+}
+
+template <typename T>
+bool tail2d_big_ok(const TailArgs<T>& a) {
+  if (a.whole || a.l0 < 0 || a.L > kMaxLevels || a.L - a.l0 < 1) return false;
+  Geom g[kMaxLevels];
+  for (int l = a.l0; l < a.L; ++l) g[l - a.l0] = a.lv[l].g;
+  return tail2d_big_fits(g, a.L - a.l0);
+}
+
+namespace {
+
+// Weights of a one-cell-per-thread level with the four LDS offsets packed
+// in pairs (left | right << 16, below | above << 16; every offset of the
+// layout is below 2^16).
+template <typename T>
+struct CellS {
+  T wl, wr, wd, wu, inv, dn;
+  int lr, du;
+};
+static_assert(kGTotal < (1 << 16), "LDS offsets fit 16 bits");
+
+template <typename T>
+__device__ __forceinline__ CellS<T> pack_cell(const CellW<T>& w) {
+  CellS<T> c;
+  c.wl = w.wl;
+  c.wr = w.wr;
+  c.wd = w.wd;
+  c.wu = w.wu;
+  c.inv = w.inv;
+  c.dn = w.dn;
+  c.lr = w.ol | (w.orr << 16);
+  c.du = w.od | (w.ou << 16);
+  return c;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NTB) k_tail2d_big(TailArgs<T> A) {
+  __shared__ T S[kGTotal];
+  __shared__ int SO[4 * kTinyMax * kTinyCells];
+  const int done = A.ctrl->done;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const bool wave0 = t < 64;
+  const int l0 = A.l0;
+  const int ntiny = A.L - l0 - 1 - kSingles;
+
+  // ---- set-up loads, all issued before the stop flag is tested ----
+  const LevelView<T>& Lb = A.lv[l0];
+  const int bnx = Lb.g.n[0], hx = bnx / 2;
+  const bool own_b = t < (int)Lb.g.N / 4;
+  const int bi = own_b ? t % hx : 0, bj = own_b ? t / hx : 0;
+  // the block's 12 distinct face coefficients (the faces between its own
+  // cells are loaded once), as cell_alpha loads them
+  CellA<T> ab[2][2];
+  T xb[2][2], bb[2][2];
+  {
+    const int x0 = 2 * bi, y0 = 2 * bj;
+    const int xl = x0 > 0 ? x0 - 1 : bnx - 1;
+    const int yd = y0 > 0 ? y0 - 1 : Lb.g.n[1] - 1;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int row = (y0 + v) * bnx;
+      const T left = Lb.a[0][row + xl];
+      const T r0 = Lb.a[0][row + x0], r1 = Lb.a[0][row + x0 + 1];
+      ab[v][0].al = left;
+      ab[v][0].ar = r0;
+      ab[v][1].al = r0;
+      ab[v][1].ar = r1;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const T down = Lb.a[1][yd * bnx + x0 + u];
+      const T u0 = Lb.a[1][y0 * bnx + x0 + u];
+      const T u1 = Lb.a[1][(y0 + 1) * bnx + x0 + u];
+      ab[0][u].ad = down;
+      ab[0][u].au = u0;
+      ab[1][u].ad = u0;
+      ab[1][u].au = u1;
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = x0 + u, j = y0 + v;
+        ab[v][u].i = i;
+        ab[v][u].j = j;
+        xb[v][u] = A.zero ? T(0) : Lb.x[j * bnx + i];
+        bb[v][u] = Lb.b[j * bnx + i];
+      }
+  }
+  const LevelView<T>& L1 = A.lv[l0 + 1];
+  const bool own_1 = t < (int)L1.g.N;
+  const int i1 = own_1 ? t % L1.g.n[0] : 0, j1 = own_1 ? t / L1.g.n[0] : 0;
+  const CellA<T> a1 = cell_alpha(L1, i1, j1);
+  const LevelView<T>& L2 = A.lv[l0 + 2];
+  const bool own_2 = t < (int)L2.g.N;
+  const int i2 = own_2 ? t % L2.g.n[0] : 0, j2 = own_2 ? t / L2.g.n[0] : 0;
+  const CellA<T> a2 = cell_alpha(L2, i2, j2);
+  // tiny cell (qw, lane) is set up by thread 64 qw + lane (waves 0..2);
+  // wave 0 runs every tiny level
+  bool own_t[kTinyMax];
+#pragma unroll
+  for (int q = 0; q < kTinyMax; ++q)
+    own_t[q] = wave0 && q < ntiny &&
+               lane < (int)A.lv[l0 + 1 + kSingles + min(q, ntiny - 1)].g.N;
+  const int qw = min(t >> 6, ntiny - 1);
+  const LevelView<T>& Lq = A.lv[l0 + 1 + kSingles + qw];
+  const bool set_t = (t >> 6) < ntiny && lane < (int)Lq.g.N;
+  const CellA<T> aq = cell_alpha(Lq, set_t ? lane % Lq.g.n[0] : 0,
+                                 set_t ? lane / Lq.g.n[0] : 0);
+  if (done != kRunning) return;
+
+  // ---- weights; the tiny levels' go to LDS ----
+  // big level: weights in registers; the neighbours outside the 2x2 block
+  // by column (left of u = 0, right of u = 1) and row (below v = 0, above
+  // v = 1), the block's own cell behind a Neumann wall as in cell_weights
+  T bpb[2][2], wlb[2][2], wrb[2][2], wdb[2][2], wub[2][2], dnb[2][2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const CellW<T> w = cell_weights(Lb.g, ab[v][u], kGX);
+      bpb[v][u] = bb[v][u] * w.inv;
+      wlb[v][u] = w.wl;
+      wrb[v][u] = w.wr;
+      wdb[v][u] = w.wd;
+      wub[v][u] = w.wu;
+      dnb[v][u] = w.dn;
+      if (!own_b) xb[v][u] = T(0);
+    }
+  int colb[2], rowb[2];
+  {
+    const int nx = bnx, ny = Lb.g.n[1], x0 = 2 * bi, y0 = 2 * bj;
+    const int px = Lb.g.per[0], py = Lb.g.per[1];
+    colb[0] = x0 > 0 ? x0 - 1 : (px ? nx - 1 : x0);
+    colb[1] = x0 + 2 < nx ? x0 + 2 : (px ? 0 : x0 + 1);
+    rowb[0] = y0 > 0 ? y0 - 1 : (py ? ny - 1 : y0);
+    rowb[1] = y0 + 2 < ny ? y0 + 2 : (py ? 0 : y0 + 1);
+  }
+  // the iterate of the big level's neighbour of cell (u, v) on side
+  // 0 left, 1 right, 2 below, 3 above
+  auto big_nb = [&](int v, int u, int side) -> T {
+    if (side == 0) return u ? xb[v][0] : S[kGX + (2 * bj + v) * bnx + colb[0]];
+    if (side == 1) return u ? S[kGX + (2 * bj + v) * bnx + colb[1]] : xb[v][1];
+    if (side == 2) return v ? xb[0][u] : S[kGX + rowb[0] * bnx + 2 * bi + u];
+    return v ? S[kGX + rowb[1] * bnx + 2 * bi + u] : xb[1][u];
+  };
+  const CellS<T> c1 = pack_cell(cell_weights(L1.g, a1, kG1));
+  const CellS<T> c2 = pack_cell(cell_weights(L2.g, a2, kG2));
+  if ((t >> 6) < ntiny) {
+    const CellW<T> w = cell_weights(Lq.g, aq, kGT + qw * kTinyCells);
+    {
+      T* W = S + kGW + qw * 6 * kTinyCells + lane;
+      W[0] = w.wl;
+      W[kTinyCells] = w.wr;
+      W[2 * kTinyCells] = w.wd;
+      W[3 * kTinyCells] = w.wu;
+      W[4 * kTinyCells] = w.inv;
+      W[5 * kTinyCells] = w.dn;
+      int* O = SO + qw * 4 * kTinyCells + lane;
+      O[0] = w.ol;
+      O[kTinyCells] = w.orr;
+      O[2 * kTinyCells] = w.od;
+      O[3 * kTinyCells] = w.ou;
+    }
+  }
+  if (own_b) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        S[kGX + (2 * bj + v) * bnx + 2 * bi + u] = xb[v][u];
+  }
+  __syncthreads();
+
+  // ---- big level: pre-smoothing, residual restricted onto cell t ----
+  auto big_pass = [&](int c) {
+    if (own_b) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (((u + v) & 1) != c) continue;
+          xb[v][u] = gs_val(bpb[v][u], wlb[v][u], big_nb(v, u, 0), wrb[v][u],
+                            big_nb(v, u, 1), wdb[v][u], big_nb(v, u, 2),
+                            wub[v][u], big_nb(v, u, 3));
+          S[kGX + (2 * bj + v) * bnx + 2 * bi + u] = xb[v][u];
+        }
+    }
+    __syncthreads();
+  };
+  for (int s = 0; s < A.pre; ++s) {
+    big_pass(0);
+    big_pass(1);
+  }
+  T b1 = T(0);
+  if (own_b) {
+    T r[2][2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        r[v][u] = dnb[v][u] * (gs_val(bpb[v][u], wlb[v][u], big_nb(v, u, 0),
+                                      wrb[v][u], big_nb(v, u, 1), wdb[v][u],
+                                      big_nb(v, u, 2), wub[v][u],
+                                      big_nb(v, u, 3)) -
+                               xb[v][u]);
+    b1 = T(0.25) * ((r[0][0] + r[0][1]) + (r[1][0] + r[1][1]));
+  }
+
+  // ---- single levels: cell t, x from zero ----
+  auto single_pass = [&](bool own, const CellS<T>& w, T bp, T& x, int base,
+                         int color, int c) {
+    if (own && color == c) {
+      x = gs_val(bp, w.wl, S[w.lr & 0xffff], w.wr, S[w.lr >> 16], w.wd,
+                 S[w.du & 0xffff], w.wu, S[w.du >> 16]);
+      S[base + t] = x;
+    }
+    __syncthreads();
+  };
+  auto single_resid = [&](const CellS<T>& w, T bp, T x) {
+    return w.dn * (gs_val(bp, w.wl, S[w.lr & 0xffff], w.wr, S[w.lr >> 16],
+                          w.wd, S[w.du & 0xffff], w.wu, S[w.du >> 16]) -
+                   x);
+  };
+  T x1 = T(0);
+  const T bp1 = b1 * c1.inv;
+  const int col1 = (i1 + j1) & 1;
+  if (own_1) S[kG1 + t] = T(0);
+  __syncthreads();  // also: the big residual's reads precede the scratch
+  for (int s = 0; s < A.pre; ++s) {
+    single_pass(own_1, c1, bp1, x1, kG1, col1, 0);
+    single_pass(own_1, c1, bp1, x1, kG1, col1, 1);
+  }
+  if (own_1) S[kGR + t] = single_resid(c1, bp1, x1);
+  __syncthreads();
+
+  T x2 = T(0), b2 = T(0);
+  if (own_2) {
+    const int fnx = L1.g.n[0];
+    const int f0 = 2 * j2 * fnx + 2 * i2;
+    b2 = T(0.25) * ((S[kGR + f0] + S[kGR + f0 + 1]) +
+                    (S[kGR + f0 + fnx] + S[kGR + f0 + fnx + 1]));
+    S[kG2 + t] = T(0);
+  }
+  const T bp2 = b2 * c2.inv;
+  const int col2 = (i2 + j2) & 1;
+  __syncthreads();
+  for (int s = 0; s < A.pre; ++s) {
+    single_pass(own_2, c2, bp2, x2, kG2, col2, 0);
+    single_pass(own_2, c2, bp2, x2, kG2, col2, 1);
+  }
+  if (own_2) S[kGR + t] = single_resid(c2, bp2, x2);
+  __syncthreads();
+
+  // ---- tiny levels: wave 0 alone ----
+  // Weights, offsets and b/d are read from LDS at every update (kept in
+  // registers they would push the block past 128 registers a thread).
+  if (wave0) {
+    // Gauss-Seidel value of lane's cell on tiny level q (b/d in slot 4)
+    auto tiny_gs = [&](int q) {
+      const T* W = S + kGW + q * 6 * kTinyCells + lane;
+      const int* O = SO + q * 4 * kTinyCells + lane;
+      return gs_val(W[4 * kTinyCells], W[0], S[O[0]], W[kTinyCells],
+                    S[O[kTinyCells]], W[2 * kTinyCells], S[O[2 * kTinyCells]],
+                    W[3 * kTinyCells], S[O[3 * kTinyCells]]);
+    };
+    auto tiny_pass = [&](int q, int color, int c) {
+      if (own_t[q] && color == c)
+        S[kGT + q * kTinyCells + lane] = tiny_gs(q);
+      wave_lds_sync();
+    };
+    auto tiny_resid = [&](int q) {
+      return S[kGW + (q * 6 + 5) * kTinyCells + lane] *
+             (tiny_gs(q) - S[kGT + q * kTinyCells + lane]);
+    };
+#pragma unroll
+    for (int q = 0; q < kTinyMax; ++q) {
+      if (q >= ntiny) break;
+      const LevelView<T>& L = A.lv[l0 + 1 + kSingles + q];
+      const int ti = lane % L.g.n[0], tj = lane / L.g.n[0];
+      // rhs: mean of the four children's residuals (scratch), x = 0; b/d
+      // replaces 1/d in slot 4
+      T bt = T(0);
+      if (own_t[q]) {
+        const int fnx = A.lv[l0 + kSingles + q].g.n[0];
+        const int f0 = 2 * tj * fnx + 2 * ti;
+        bt = T(0.25) * ((S[kGR + f0] + S[kGR + f0 + 1]) +
+                        (S[kGR + f0 + fnx] + S[kGR + f0 + fnx + 1]));
+      }
+      T* slot = S + kGW + (q * 6 + 4) * kTinyCells + lane;
+      *slot = bt * *slot;
+      S[kGT + q * kTinyCells + lane] = T(0);
+      wave_lds_sync();
+      const int color = (ti + tj) & 1;
+      if (q < ntiny - 1) {
+        for (int s = 0; s < A.pre; ++s) {
+          tiny_pass(q, color, 0);
+          tiny_pass(q, color, 1);
+        }
+        if (own_t[q]) S[kGR + lane] = tiny_resid(q);
+        wave_lds_sync();
+      } else {
+        // coarsest: sweeps from zero until the residual dropped by 1e-3
+        const double b = own_t[q] ? (double)bt : 0.0;
+        const double r0 = wave_sum(b * b);
+        auto r2 = [&]() {
+          double v = 0.0;
+          if (own_t[q]) {
+            const double r = (double)tiny_resid(q);
+            v = r * r;
+          }
+          return wave_sum(v);
+        };
+        auto sweeps2 = [&]() {
+          for (int s = 0; s < 2; ++s) {
+            tiny_pass(q, color, 0);
+            tiny_pass(q, color, 1);
+          }
+        };
+        sweeps2();
+        if (r2() > 1e-6 * r0) {  // squared norms
+          for (int it = 0; it < 4000; it += 2) {
+            sweeps2();
+            if (!(r2() > 1e-6 * r0)) break;
+          }
+        }
+      }
+    }
+    // up through the tiny levels
+#pragma unroll
+    for (int q = kTinyMax - 2; q >= 0; --q) {
+      if (q + 1 >= ntiny) continue;
+      const LevelView<T>& L = A.lv[l0 + 1 + kSingles + q];
+      const LevelView<T>& C = A.lv[l0 + 2 + kSingles + q];
+      const int ti = lane % L.g.n[0], tj = lane / L.g.n[0];
+      const int cbase = kGT + (q + 1) * kTinyCells;
+      if (own_t[q]) {
+        const int cnx = C.g.n[0], cny = C.g.n[1];
+        const int I = ti >> 1, J = tj >> 1;
+        const int I2 = second_parent(ti, cnx, C.g.per[0]);
+        const int J2 = second_parent(tj, cny, C.g.per[1]);
+        S[kGT + q * kTinyCells + lane] +=
+            bilin(S[cbase + J * cnx + I], S[cbase + J * cnx + I2],
+                  S[cbase + J2 * cnx + I], S[cbase + J2 * cnx + I2]);
+      }
+      wave_lds_sync();
+      const int color = (ti + tj) & 1;
+      for (int s = 0; s < A.post; ++s) {
+        tiny_pass(q, color, 0);
+        tiny_pass(q, color, 1);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- single levels: correction from the next coarser, post-smoothing
+  auto correct = [&](bool own, int i, int j, const Geom& gc, int cbase, T& x,
+                     int base) {
+    if (own) {
+      const int cnx = gc.n[0], cny = gc.n[1];
+      const int I = i >> 1, J = j >> 1;
+      const int I2 = second_parent(i, cnx, gc.per[0]);
+      const int J2 = second_parent(j, cny, gc.per[1]);
+      x += bilin(S[cbase + J * cnx + I], S[cbase + J * cnx + I2],
+                 S[cbase + J2 * cnx + I], S[cbase + J2 * cnx + I2]);
+      S[base + t] = x;
+    }
+    __syncthreads();
+  };
+  correct(own_2, i2, j2, A.lv[l0 + 1 + kSingles].g, kGT, x2, kG2);
+  for (int s = 0; s < A.post; ++s) {
+    single_pass(own_2, c2, bp2, x2, kG2, col2, 0);
+    single_pass(own_2, c2, bp2, x2, kG2, col2, 1);
+  }
+  correct(own_1, i1, j1, L2.g, kG2, x1, kG1);
+  for (int s = 0; s < A.post; ++s) {
+    single_pass(own_1, c1, bp1, x1, kG1, col1, 0);
+    single_pass(own_1, c1, bp1, x1, kG1, col1, 1);
+  }
+
+  // ---- big level: correction (its own parent is x1), post-smoothing ----
+  if (own_b) {
+    const int cnx = L1.g.n[0], cny = L1.g.n[1];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int I2 = second_parent(2 * bi + u, cnx, L1.g.per[0]);
+        const int J2 = second_parent(2 * bj + v, cny, L1.g.per[1]);
+        xb[v][u] += bilin(x1, S[kG1 + bj * cnx + I2], S[kG1 + J2 * cnx + bi],
+                          S[kG1 + J2 * cnx + I2]);
+        S[kGX + (2 * bj + v) * bnx + 2 * bi + u] = xb[v][u];
+      }
+  }
+  __syncthreads();
+  for (int s = 0; s < A.post; ++s) {
+    big_pass(0);
+    big_pass(1);
+  }
+  if (own_b) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        Lb.x[(2 * bj + v) * bnx + 2 * bi + u] = xb[v][u];
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_tail2d_big(const TailArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail2d_big<T>), dim3(1), dim3(NTB), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT2) k_tail2d(TailArgs<T> A) {
   tail2d_body<T>(A);
@@ -527,6 +992,12 @@ hipError_t launch_tail2d_batch(const TailArgs<T>* tab, int ng, hipStream_t s) {
 }
 
 template bool tail2d_ok<double>(const TailArgs<double>&);
+template bool tail2d_big_ok<double>(const TailArgs<double>&);
+template bool tail2d_big_ok<float>(const TailArgs<float>&);
+template hipError_t launch_tail2d_big<double>(const TailArgs<double>&,
+                                              hipStream_t);
+template hipError_t launch_tail2d_big<float>(const TailArgs<float>&,
+                                             hipStream_t);
 template bool tail2d_ok<float>(const TailArgs<float>&);
 template hipError_t launch_tail2d<double>(const TailArgs<double>&, hipStream_t);
 template hipError_t launch_tail2d<float>(const TailArgs<float>&, hipStream_t);
