@@ -96,6 +96,7 @@ struct fld_ctx {
   bool coarsen_multi = true;  // 2D: several coarse levels per launch
   bool sweep3d = true;        // 3D: fused red-black sweeps where planned
   bool level_lds = true;      // small 3D coarse levels in one workgroup
+  bool tile3d = true;         // 3D: tiled sweeps below the marching ones
   bool tail_big = true;       // 2D: tail from a level of up to 4096 cells
   int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
@@ -362,8 +363,10 @@ void make_plan(const fld_params* p, Plan* P) {
     // of the fused red-black sweep
     const bool alt = (nd == 2 && l + 1 < P->L) ||
                      (nd == 3 && l + 1 < P->L &&
-                      (int64_t)cells >= sweep_min_cells() &&
-                      gs_sweep3d_ok(P->g[l]));
+                      (((int64_t)cells >= sweep_min_cells() &&
+                        gs_sweep3d_ok(P->g[l])) ||
+                       ((int64_t)cells > kLevelLdsCells &&
+                        gs_tile3d_ok(P->g[l]))));
     if (alt) {
       P->alt[l] = take(cells * (mixed ? 4 : 8));
       if (pre64) P->alt64[l] = take(cells * 8);
@@ -474,13 +477,19 @@ fld_status fill_zero<float>(fld_ctx* c, float* x, int64_t n) {
   return FLD_OK;
 }
 
-// Whether level l smooths by fused 3D sweeps (it has the alternate buffer
-// and some pre or post count of at least two).
+// How level l smooths in 3D: 0 colour passes only; pairs of one-launch
+// sweeps where it has the alternate buffer and some pre or post count of at
+// least two: 1 z-marching sweeps (large levels), 2 tiled sweeps.
+constexpr int kFusedNone = 0, kFusedMarch = 1, kFusedTile = 2;
 template <typename T>
-bool fused_level(const fld_ctx* c, const Levels<T>& H, int l) {
-  return c->sweep3d && c->geom[l].ndim == 3 && H.alt[l] &&
-         gs_sweep3d_ok(c->geom[l]) &&
-         (nu_pre(c->p, l) >= 2 || nu_post(c->p, l) >= 2);
+int fused_level(const fld_ctx* c, const Levels<T>& H, int l) {
+  const Geom& g = c->geom[l];
+  if (!c->sweep3d || g.ndim != 3 || !H.alt[l] ||
+      (nu_pre(c->p, l) < 2 && nu_post(c->p, l) < 2))
+    return kFusedNone;
+  if (g.N >= sweep_min_cells() && gs_sweep3d_ok(g)) return kFusedMarch;
+  if (c->tile3d && gs_tile3d_ok(g)) return kFusedTile;
+  return kFusedNone;
 }
 
 // Simple path: one launch per colour pass, or, on a 3D level with an
@@ -505,7 +514,8 @@ fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
                          bool timed_fused, bool timed_colour) {
   LevelView<T> v = view(c, H, l);
   T* alt = H.alt[l];
-  const bool fused = fused_level(c, H, l);
+  const int mode = fused_level(c, H, l);
+  const bool fused = mode != kFusedNone;
   const int pairs = fused ? sweeps / 2 : 0;
   // only the context's own precision is timed (an FP32_IR solve whose
   // flexible CG fell back to FP64 V-cycles runs both)
@@ -524,13 +534,21 @@ fld_status smooth_simple(fld_ctx* c, const Levels<T>& H, int l, int sweeps,
   LevelView<T> va = v;
   va.x = alt;
   for (int s = 0; s < pairs; ++s) {
+    const bool march = mode == kFusedMarch;
+    const char* name =
+        march ? (sizeof(T) == 8 ? "k_gs_sweep_3d<double>" : "k_gs_sweep_3d<float>")
+              : (sizeof(T) == 8 ? "k_gs_tile_3d<double>" : "k_gs_tile_3d<float>");
     TimedLaunch tl(c, timed_fused && s == 0, 6.0 * (double)v.g.N * sizeof(T),
-                   sizeof(T) == 8 ? "k_gs_sweep_3d<double>"
-                                  : "k_gs_sweep_3d<float>");
+                   name);
     FLD_TRY(tl.st);
-    HIP_TRY(c, launch_gs_sweep3d<T>(v, alt, c->sweep_zc, c->ctrl, c->stream,
-                                    tl.e0, tl.e1));
-    HIP_TRY(c, launch_gs_sweep3d<T>(va, v.x, c->sweep_zc, c->ctrl, c->stream));
+    if (march) {
+      HIP_TRY(c, launch_gs_sweep3d<T>(v, alt, c->sweep_zc, c->ctrl, c->stream,
+                                      tl.e0, tl.e1));
+      HIP_TRY(c, launch_gs_sweep3d<T>(va, v.x, c->sweep_zc, c->ctrl, c->stream));
+    } else {
+      HIP_TRY(c, launch_gs_tile3d<T>(v, alt, c->ctrl, c->stream, tl.e0, tl.e1));
+      HIP_TRY(c, launch_gs_tile3d<T>(va, v.x, c->ctrl, c->stream));
+    }
   }
   return FLD_OK;
 }
@@ -1515,6 +1533,9 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
   // small 3D coarse levels by colour-pass launches ("0"; tests that both
   // forms agree bitwise)
   if (const char* lv = getenv("FLD_LEVEL_LDS")) c->level_lds = atoi(lv) != 0;
+  // 3D levels below the marching sweeps by colour passes ("0"; tests that
+  // both forms agree bitwise)
+  if (const char* tv = getenv("FLD_TILE3D")) c->tile3d = atoi(tv) != 0;
   c->level_lds = c->level_lds && c->fast;
   // fixed tile shape for every level (tests of shape independence)
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {

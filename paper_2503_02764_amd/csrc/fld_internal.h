@@ -113,6 +113,14 @@ template <typename T>
 hipError_t launch_gs_sweep3d(const LevelView<T>& L, T* xo, int zc,
                              const Control* ctrl, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The same sweep by 32 x 8 x 4 tiles in one launch (fld_tile3d.hip), for
+// levels too small for the z-marching sweep: nx % 32 == 0, ny % 8 == 0,
+// nz % 4 == 0 and two colours.
+bool gs_tile3d_ok(const Geom& g);
+template <typename T>
+hipError_t launch_gs_tile3d(const LevelView<T>& L, T* xo, const Control* ctrl,
+                            hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 
 template <typename T>
 hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,

@@ -1,6 +1,6 @@
 """Fused red-black sweeps of the 3D levels (one launch per sweep, out of
-place) against the two colour passes per sweep they replace, and against
-the oracle.
+place: z-marching on large levels, 32x8x4 tiles below them) against the
+two colour passes per sweep they replace, and against the oracle.
 
 The fused kernel applies the colour-pass update to every cell in the same
 order (red from old black, then black from new red), so the solves agree bit
@@ -72,7 +72,8 @@ def test_fused_sweeps_vs_oracle(n, bc, monkeypatch):
 def test_default_fused_levels(bc, precision, monkeypatch):
     """The default choice (levels of at least 2^22 cells, z chunk chosen
     from the shape) on a 256x128x128 grid: the finest level takes fused
-    sweeps."""
+    z-marching sweeps, the levels below it tiled ones, against colour passes
+    everywhere (FLD_SWEEP3D=0)."""
     n = (256, 128, 128)
     m = media.random_small_medium(128 + len(bc[0]), n, bc)
     kw = dict(rtol=1e-10, precision=precision, max_cycles=200,
@@ -133,3 +134,45 @@ def test_small_levels_in_one_workgroup_match_colour_passes(n, bc, precision,
     assert s0["cycles"] == s1["cycles"] and s0["outer_iters"] == s1["outer_iters"]
     np.testing.assert_array_equal(x0, x1)
     assert s1["rel_res_final"] <= 1e-12
+
+
+@pytest.mark.parametrize("n,bc", [
+    ((128, 64, 32), ("neumann", "neumann", "neumann")),
+    ((64, 32, 32), ("periodic", "periodic", "periodic")),
+    ((96, 48, 40), ("neumann", "periodic", "neumann")),
+    ((64, 64, 16), ("periodic", "neumann", "periodic")),
+])
+@pytest.mark.parametrize("precision,krylov", [("fp64", False), ("fp32_ir", False),
+                                              ("fp32_ir", True)])
+def test_tiled_sweeps_match_colour_passes(n, bc, precision, krylov,
+                                          monkeypatch):
+    """3D levels below the marching sweeps (fewer than 2^22 cells) with
+    nx % 32 == ny % 8 == nz % 4 == 0 sweep by 32x8x4 tiles, one launch per
+    sweep (the default); FLD_TILE3D=0 takes two colour passes per sweep.
+    Same operations in the same order: the same cycle counts and the same
+    iterate, bit for bit."""
+    m = media.random_small_medium(2 * n[0] + n[2], n, bc)
+    kw = dict(rtol=1e-11, max_cycles=300, precision=precision, krylov=krylov,
+              pre_smooth=2, post_smooth=2, coarse_pre_smooth=4,
+              coarse_post_smooth=4)
+    announce(f"tiled 3D sweeps n={n} {bc} {precision} krylov={krylov}")
+    monkeypatch.setenv("FLD_TILE3D", "0")
+    x0, s0 = _solve(m, None, monkeypatch, **kw)
+    monkeypatch.delenv("FLD_TILE3D")
+    x1, s1 = _solve(m, None, monkeypatch, **kw)
+    assert s0["cycles"] == s1["cycles"] and s0["outer_iters"] == s1["outer_iters"]
+    np.testing.assert_array_equal(x0, x1)
+    assert s1["rel_res_final"] <= 1e-11
+
+
+@pytest.mark.parametrize("n,bc", [((64, 32, 16), ("periodic", "periodic", "periodic")),
+                                  ((32, 16, 24), ("neumann", "periodic", "neumann"))])
+def test_tiled_sweeps_vs_oracle(n, bc, monkeypatch):
+    m = media.random_small_medium(5 + n[2], n, bc)
+    announce(f"tiled 3D sweeps vs oracle {n} {bc}")
+    x, st = _solve(m, None, monkeypatch, rtol=1e-12, max_cycles=300,
+                   pre_smooth=2, post_smooth=2)
+    ref = F.diffusion_step(m.E, m.rho, m.kappa, m.dt,
+                           F.problem_from_medium(m))
+    assert st["rel_res_final"] <= 1e-12
+    assert rel_l2(x, ref) <= 1e-10, st
