@@ -79,14 +79,17 @@ typedef enum { FLD_GUESS_PREV = 0, FLD_GUESS_ZERO = 1, FLD_GUESS_LEARNED = 2 } f
 
 /* When the learned guess evaluates its network (FLD_GUESS_LEARNED only).
  * FLD_GUESS_ADAPTIVE: the context's first step runs without the network and
- * its count of V-cycles (FP64) or refinement iterations (FP32_IR) becomes
- * the reference, which every later step without the network renews.  A
- * step with the network that does not lower that count (or whose guess the
+ * its count of V-cycles (FP64) or refinement iterations (FP32_IR), and the
+ * solve's time per cycle or iteration (events on the stream), become the
+ * reference, which every later step without the network renews.  A step
+ * with the network pays when the cycles or iterations it saved took longer
+ * than the network did.  One that does not pay (or whose guess the
  * residual judge rejects) makes the next 2, 4, 8, 16, then 32 steps run
- * without it before it is tried again; a step where it lowers the count
- * keeps it on for the next step.  A step without the network is exactly a
- * step with guess E^n.  FLD_GUESS_EVERY_STEP: the network runs on every
- * step. */
+ * without it before it is tried again; one where the network took longer
+ * than a whole solve without it makes the next 32 steps run without it; a
+ * step that pays keeps it on for the next step.  A step without the network
+ * is exactly a step with guess E^n.  FLD_GUESS_EVERY_STEP: the network runs
+ * on every step. */
 typedef enum { FLD_GUESS_ADAPTIVE = 0, FLD_GUESS_EVERY_STEP = 1 } fld_guess_policy;
 
 typedef struct {

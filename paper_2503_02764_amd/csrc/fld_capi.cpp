@@ -97,6 +97,7 @@ struct fld_ctx {
   bool sweep3d = true;        // 3D: fused red-black sweeps where planned
   bool level_lds = true;      // small 3D coarse levels in one workgroup
   bool tile3d = true;         // 3D: tiled sweeps below the marching ones
+  bool tile3d_all = false;    // 3D: tiled sweeps on the large levels too
   bool tail_big = true;       // 2D: tail from a level of up to 4096 cells
   int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
@@ -118,6 +119,13 @@ struct fld_ctx {
   // the square of that step's contraction per V-cycle or refinement
   // iteration, so that an accepted guess is predicted to save one
   double judge_q2 = 1.0;
+  // the policy's clock (events on the stream): [0] before the network,
+  // [1] before the solve, [2] at the solve's last control read; the
+  // solve's time per unit on the last step without the network
+  hipEvent_t net_ev[3] = {nullptr, nullptr, nullptr};
+  bool net_clock = false;
+  bool net_ev_end = false;  // net_ev[2] recorded during this solve
+  double unit_ms = -1.0;
   // flexible CG around the V-cycle (fld_params.krylov)
   bool krylov = false;
   bool precond = false;  // V-cycles run as a preconditioner: no stop test
@@ -487,6 +495,7 @@ int fused_level(const fld_ctx* c, const Levels<T>& H, int l) {
   if (!c->sweep3d || g.ndim != 3 || !H.alt[l] ||
       (nu_pre(c->p, l) < 2 && nu_post(c->p, l) < 2))
     return kFusedNone;
+  if (c->tile3d_all && gs_tile3d_ok(g)) return kFusedTile;
   if (g.N >= sweep_min_cells() && gs_sweep3d_ok(g)) return kFusedMarch;
   if (c->tile3d && gs_tile3d_ok(g)) return kFusedTile;
   return kFusedNone;
@@ -741,6 +750,10 @@ fld_status collect_timing(fld_ctx* c) {
 // The kernels that decide the stop flag also write the control block into
 // host-visible pinned memory, so reading it needs only the stream sync.
 fld_status read_control(fld_ctx* c) {
+  if (c->net_clock) {
+    HIP_TRY(c, hipEventRecord(c->net_ev[2], c->stream));
+    c->net_ev_end = true;
+  }
   if (c->ctrl_by_copy)
     HIP_TRY(c, hipMemcpyAsync(c->host_ctrl, c->ctrl, sizeof(Control),
                               hipMemcpyDeviceToHost, c->stream));
@@ -1534,8 +1547,11 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
   // forms agree bitwise)
   if (const char* lv = getenv("FLD_LEVEL_LDS")) c->level_lds = atoi(lv) != 0;
   // 3D levels below the marching sweeps by colour passes ("0"; tests that
-  // both forms agree bitwise)
-  if (const char* tv = getenv("FLD_TILE3D")) c->tile3d = atoi(tv) != 0;
+  // both forms agree bitwise), or tiled sweeps on every level ("2")
+  if (const char* tv = getenv("FLD_TILE3D")) {
+    c->tile3d = atoi(tv) != 0;
+    c->tile3d_all = atoi(tv) == 2;
+  }
   c->level_lds = c->level_lds && c->fast;
   // fixed tile shape for every level (tests of shape independence)
   if (const char* tv = getenv("FLD_TILE_VARIANT")) {
@@ -1700,28 +1716,62 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
                    : coarsen_levels<double>(c, c->h64));
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
-  if (use_net) FLD_TRY(learned_guess(c, rho, kappa));
-  FLD_TRY(c->krylov ? solve_krylov(c)
-                    : (c->mixed ? solve_mixed(c) : solve_fp64(c)));
+  // the adaptive policy times the network and the solve on the stream
+  const bool adaptive = learned && c->p.guess_policy == FLD_GUESS_ADAPTIVE;
+  if (adaptive && !c->net_ev[0]) {
+    for (hipEvent_t& e : c->net_ev) HIP_TRY(c, hipEventCreate(&e));
+  }
+  c->net_clock = adaptive;
+  c->net_ev_end = false;
+  if (use_net) {
+    if (adaptive) HIP_TRY(c, hipEventRecord(c->net_ev[0], c->stream));
+    FLD_TRY(learned_guess(c, rho, kappa));
+  }
+  if (adaptive) HIP_TRY(c, hipEventRecord(c->net_ev[1], c->stream));
+  const fld_status solved = c->krylov ? solve_krylov(c)
+                                      : (c->mixed ? solve_mixed(c)
+                                                  : solve_fp64(c));
+  c->net_clock = false;
+  FLD_TRY(solved);
   FLD_TRY(collect_timing(c));
   const Control& h = *c->host_ctrl;
-  if (learned && c->p.guess_policy == FLD_GUESS_ADAPTIVE &&
-      h.done == kConverged) {
+  if (adaptive && h.done == kConverged) {
+    // the solve's last control read recorded net_ev[2] and synchronised
+    float solve_ms = 0.f, net_ms = 0.f;
+    bool timed = c->net_ev_end &&
+                 hipEventElapsedTime(&solve_ms, c->net_ev[1], c->net_ev[2]) ==
+                     hipSuccess;
+    if (timed && use_net)
+      timed = hipEventElapsedTime(&net_ms, c->net_ev[0], c->net_ev[1]) ==
+              hipSuccess;
+    if (!timed) (void)hipGetLastError();  // no stale error for later launches
     const int units = c->mixed ? h.outer : h.cycles;
     if (!use_net) {
       c->plain_units = units;
+      if (units > 0 && timed) c->unit_ms = solve_ms / units;
       if (c->net_skip > 0) --c->net_skip;
       if (units > 0 && h.res_initial > 0.0 && h.res > 0.0) {
         const double rho = std::pow(h.res / h.res_initial, 1.0 / units);
         const double r = std::min(std::max(rho, 1e-3), 1.0);
         c->judge_q2 = r * r;
       }
-    } else if (h.guess_rejected ||
-               (c->plain_units >= 0 && units >= c->plain_units)) {
-      c->net_span = std::min(std::max(2, 2 * c->net_span), kMaxNetPause);
-      c->net_skip = c->net_span;
     } else {
-      c->net_span = 0;
+      // the guess pays when the work it saved took longer than the
+      // network; when the network costs more than a whole solve without
+      // it, no saving can repay it, and the next try waits the longest
+      const bool known = timed && c->plain_units >= 0 && c->unit_ms > 0.0;
+      const double saved_ms =
+          known ? (c->plain_units - units) * c->unit_ms : 0.0;
+      const bool pays = !h.guess_rejected && known && saved_ms > net_ms;
+      if (known && net_ms >= c->plain_units * c->unit_ms) {
+        c->net_span = kMaxNetPause;
+        c->net_skip = kMaxNetPause;
+      } else if (!pays) {
+        c->net_span = std::min(std::max(2, 2 * c->net_span), kMaxNetPause);
+        c->net_skip = c->net_span;
+      } else {
+        c->net_span = 0;
+      }
     }
   }
   if (stats) {
@@ -2085,6 +2135,8 @@ void fld_destroy(fld_ctx* c) {
     c->batch = nullptr;
   }
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->net_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
   delete c;
 }

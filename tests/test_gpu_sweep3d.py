@@ -73,7 +73,8 @@ def test_default_fused_levels(bc, precision, monkeypatch):
     """The default choice (levels of at least 2^22 cells, z chunk chosen
     from the shape) on a 256x128x128 grid: the finest level takes fused
     z-marching sweeps, the levels below it tiled ones, against colour passes
-    everywhere (FLD_SWEEP3D=0)."""
+    everywhere (FLD_SWEEP3D=0); FLD_TILE3D=2 takes tiled sweeps on the
+    finest level too."""
     n = (256, 128, 128)
     m = media.random_small_medium(128 + len(bc[0]), n, bc)
     kw = dict(rtol=1e-10, precision=precision, max_cycles=200,
@@ -84,6 +85,11 @@ def test_default_fused_levels(bc, precision, monkeypatch):
     x1, s1 = _solve(m, None, monkeypatch, **kw)
     assert s1["cycles"] == s0["cycles"] and s1["rel_res_final"] <= 1e-10, (s0, s1)
     np.testing.assert_array_equal(x1, x0)
+    monkeypatch.setenv("FLD_TILE3D", "2")
+    x2, s2 = _solve(m, None, monkeypatch, **kw)
+    monkeypatch.delenv("FLD_TILE3D")
+    assert s2["cycles"] == s0["cycles"], (s0, s2)
+    np.testing.assert_array_equal(x2, x0)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])

@@ -470,7 +470,9 @@ def test_adaptive_policy_on_heldout_1024():
     step; a step whose guess the judge accepted needed no more V-cycles than
     the plain step (the judge asks the guess's smoothed residual to be a
     cycle's contraction below that of E^n); the first step runs without
-    the network and unproductive tries pause it."""
+    the network, and tries whose saved V-cycles took less time than the
+    network pause it (at 1024^2 the network costs about a whole solve, so
+    it runs on a few steps only)."""
     import torch
     import bench
     from paper_2503_02764_amd import fld
@@ -511,5 +513,5 @@ def test_adaptive_policy_on_heldout_1024():
         E = xp
     print(f"network on {net_steps} of 12 steps, accepted {accepted}; "
           f"V-cycles {cyc_l} (plain {cyc_p})")
-    assert 1 <= net_steps <= 11
+    assert 1 <= net_steps <= 4
     assert cyc_l <= cyc_p
