@@ -86,8 +86,9 @@ typedef enum { FLD_GUESS_PREV = 0, FLD_GUESS_ZERO = 1, FLD_GUESS_LEARNED = 2 } f
  * than the network did.  One that does not pay (or whose guess the
  * residual judge rejects) makes the next 2, 4, 8, 16, then 32 steps run
  * without it before it is tried again; one where the network took longer
- * than a whole solve without it makes the next 32 steps run without it; a
- * step that pays keeps it on for the next step.  A step without the network
+ * than all but one cycle or iteration of a solve without it (a solve runs
+ * at least one) makes the next 32 steps run without it; a step that pays
+ * keeps it on for the next step.  A step without the network
  * is exactly a step with guess E^n.  FLD_GUESS_EVERY_STEP: the network runs
  * on every step. */
 typedef enum { FLD_GUESS_ADAPTIVE = 0, FLD_GUESS_EVERY_STEP = 1 } fld_guess_policy;

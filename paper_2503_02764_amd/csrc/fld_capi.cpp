@@ -1757,13 +1757,15 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
       }
     } else {
       // the guess pays when the work it saved took longer than the
-      // network; when the network costs more than a whole solve without
-      // it, no saving can repay it, and the next try waits the longest
+      // network; a solve still runs at least one cycle or iteration (its
+      // stop test follows one), so when the network costs more than all
+      // the others of a solve without it, no guess can repay it, and the
+      // next try waits the longest
       const bool known = timed && c->plain_units >= 0 && c->unit_ms > 0.0;
       const double saved_ms =
           known ? (c->plain_units - units) * c->unit_ms : 0.0;
       const bool pays = !h.guess_rejected && known && saved_ms > net_ms;
-      if (known && net_ms >= c->plain_units * c->unit_ms) {
+      if (known && net_ms >= (c->plain_units - 1) * c->unit_ms) {
         c->net_span = kMaxNetPause;
         c->net_skip = kMaxNetPause;
       } else if (!pays) {
