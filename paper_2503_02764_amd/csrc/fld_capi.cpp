@@ -1484,9 +1484,6 @@ fld_status check_setup(const fld_params* p, const void* workspace,
   return FLD_OK;
 }
 
-// Point a context's level buffers into the workspace and apply the
-// environment switches of the tests (kernel path, coarsening form, fused
-// 3D sweeps, fixed tile shape).  Allocates nothing.
 // First level of the single-workgroup tail: the first of at most 1024
 // cells, or the level above it where the 2D tail from a level of up to
 // 4096 cells fits (c->tail_big).
@@ -1502,6 +1499,10 @@ void choose_tail(fld_ctx* c) {
     c->tail_l0 -= 1;
 }
 
+// Point a context's level buffers into the workspace and apply the
+// environment switches of the tests (kernel path, coarsening form, fused
+// 3D sweeps, tiled 3D sweeps, 2D tail start, fixed tile shape).  Allocates
+// nothing.
 void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
               size_t ws_bytes, void* hip_stream) {
   c->p = *p;
@@ -1718,8 +1719,16 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
   // the adaptive policy times the network and the solve on the stream
   const bool adaptive = learned && c->p.guess_policy == FLD_GUESS_ADAPTIVE;
-  if (adaptive && !c->net_ev[0]) {
-    for (hipEvent_t& e : c->net_ev) HIP_TRY(c, hipEventCreate(&e));
+  if (adaptive) {
+    // the two events inside the step skip the system-scope fence (a default
+    // event writes back and invalidates the caches where it is recorded);
+    // the one before the solve's synchronisation keeps it, as the last
+    // command the host waits for
+    for (int k = 0; k < 2; ++k)
+      if (!c->net_ev[k])
+        HIP_TRY(c, hipEventCreateWithFlags(&c->net_ev[k],
+                                           hipEventDisableSystemFence));
+    if (!c->net_ev[2]) HIP_TRY(c, hipEventCreate(&c->net_ev[2]));
   }
   c->net_clock = adaptive;
   c->net_ev_end = false;
