@@ -34,6 +34,14 @@ limiter and D live at cell centres and faces take a mean of D; Neumann
 flux on the boundary face; D is lagged (computed from E^n); diffusion is
 done before the exchange, one backward-Euler stage each.
 
+A wall can instead hold E at a given value E_w (a Dirichlet wall: the
+radiation temperature tied to the gas temperature on the boundary of the
+magnetoconvection case, Sect. 4.5).  Readings: the gradient's ghosts are
+the odd reflection about E_w (E_ghost = 2 E_w - E_mirror), and the wall
+face, half a cell from the centre, carries the boundary cell's D:
+(A x)_i gains alpha_w x_i and b_i gains alpha_w E_w, alpha_w = 2 dt D_i /
+dx_d^2 (``dirichlet_terms``).
+
 Arrays are float64, C order, x fastest: shape (nx,), (ny, nx) or
 (nz, ny, nx).
 """
@@ -61,6 +69,9 @@ class Problem:
     gas_const: float = 1.0  # R_g = k_B / (mu m_p)
     limiter: str = "lp"  # "lp", "diffusion" or "minerbo"
     face_mean: str = "arith"  # "arith" or "harmonic"
+    # Dirichlet walls: {(d, side): E_w}, side 0 the lower wall of dimension
+    # d and 1 the upper one; that dimension's bc must be NEUMANN
+    dirichlet: dict = dataclasses.field(default_factory=dict)
 
     @property
     def shape(self):
@@ -102,8 +113,16 @@ def gradient(E, prob):
     """Five-point 4th-order central gradient of E, one array per dimension.
 
     G_d = (E_{i-2} - 8 E_{i-1} + 8 E_{i+1} - E_{i+2}) / (12 dx_d)  (Sect. 3).
+    A Dirichlet wall's ghosts are the odd reflection about its value,
+    E_{-1} = 2 E_w - E_0, E_{-2} = 2 E_w - E_1 (mirror ghosts reflected).
     """
     Ep = _with_ghosts(E, prob, 2)
+    for (d, side), Ew in prob.dirichlet.items():
+        ax = prob.axis(d)
+        for k in (0, 1):  # the two ghost layers of that wall
+            sl = [slice(None)] * prob.ndim
+            sl[ax] = k if side == 0 else Ep.shape[ax] - 1 - k
+            Ep[tuple(sl)] = 2.0 * Ew - Ep[tuple(sl)]
     interior = [slice(2, -2)] * prob.ndim
     out = []
     for d in range(prob.ndim):
@@ -185,27 +204,56 @@ def face_coefficients(E, rho, kappa, dt, prob):
     return alphas
 
 
+def dirichlet_terms(E, rho, kappa, dt, prob):
+    """Diagonal and right-hand-side terms of the Dirichlet walls.
+
+    For a cell on a Dirichlet wall along d the wall face lies half a cell
+    away and carries the cell's D: the face flux is 2 D_i (E_i - E_w) /
+    dx_d, so (A x)_i gains alpha_w x_i and b_i gains alpha_w E_w with
+    alpha_w = 2 dt D_i / dx_d^2.  Returns (alpha_w summed per cell,
+    alpha_w E_w summed per cell); zeros without Dirichlet walls.
+    """
+    diag = np.zeros(prob.shape)
+    rhs = np.zeros(prob.shape)
+    if not prob.dirichlet:
+        return diag, rhs
+    D, _, _ = diffusion_coefficient(E, rho, kappa, prob)
+    for (d, side), Ew in prob.dirichlet.items():
+        ax = prob.axis(d)
+        sl = [slice(None)] * prob.ndim
+        sl[ax] = 0 if side == 0 else -1
+        sl = tuple(sl)
+        aw = 2.0 * dt * D[sl] / (prob.dx[d] ** 2)
+        diag[sl] += aw
+        rhs[sl] += aw * Ew
+    return diag, rhs
+
+
 # ---------------------------------------------------------------------------
 # Backward-Euler diffusion operator and its exact solution
 # ---------------------------------------------------------------------------
 
-def apply_operator(x, alphas, prob):
-    """(A x)_i = x_i + sum_faces alpha_f (x_i - x_neighbour)."""
+def apply_operator(x, alphas, prob, diag=None):
+    """(A x)_i = x_i + sum_faces alpha_f (x_i - x_neighbour) (+ the
+    Dirichlet walls' diag_i x_i)."""
     Ax = x.copy()
     for d in range(prob.ndim):
         ax = prob.axis(d)
         flux = alphas[d] * (x - np.roll(x, -1, axis=ax))  # through face i+1/2
         Ax += flux
         Ax -= np.roll(flux, 1, axis=ax)  # face i-1/2 seen from cell i
+    if diag is not None:
+        Ax += diag * x
     return Ax
 
 
-def assemble(alphas, prob):
+def assemble(alphas, prob, diag=None):
     """Sparse matrix of the operator in ``apply_operator`` (CSR, float64)."""
     shape = prob.shape
     N = int(np.prod(shape))
     idx = np.arange(N).reshape(shape)
-    rows, cols, vals = [np.arange(N)], [np.arange(N)], [np.ones(N)]
+    one = np.ones(N) if diag is None else 1.0 + diag.ravel()
+    rows, cols, vals = [np.arange(N)], [np.arange(N)], [one]
     for d in range(prob.ndim):
         ax = prob.axis(d)
         nb = np.roll(idx, -1, axis=ax).ravel()
@@ -220,13 +268,13 @@ def assemble(alphas, prob):
     return A.tocsr()
 
 
-def solve(alphas, b, prob, rtol=1e-13, method=None):
+def solve(alphas, b, prob, rtol=1e-13, method=None, diag=None):
     """Exact solution of A x = b.
 
     Dense LU up to 4096 cells, sparse LU (SuperLU) up to ``SPLU_MAX`` cells,
     else Jacobi-preconditioned conjugate gradients (A is SPD) to ``rtol``.
     """
-    A = assemble(alphas, prob)
+    A = assemble(alphas, prob, diag)
     N = A.shape[0]
     bf = b.ravel()
     if method is None:
@@ -251,13 +299,17 @@ SPLU_MAX = 1 << 18
 
 
 def diffusion_step(E, rho, kappa, dt, prob, **kw):
-    """E* = A^-1 E^n with A built from E^n (lagged D)."""
+    """E* = A^-1 b with A built from E^n (lagged D); b = E^n plus the
+    Dirichlet walls' alpha_w E_w."""
     alphas = face_coefficients(E, rho, kappa, dt, prob)
-    return solve(alphas, E, prob, **kw)
+    if not prob.dirichlet:
+        return solve(alphas, E, prob, **kw)
+    diag, rhs = dirichlet_terms(E, rho, kappa, dt, prob)
+    return solve(alphas, E + rhs, prob, diag=diag, **kw)
 
 
-def relative_residual(x, b, alphas, prob):
-    r = b - apply_operator(x, alphas, prob)
+def relative_residual(x, b, alphas, prob, diag=None):
+    r = b - apply_operator(x, alphas, prob, diag)
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))
 
 

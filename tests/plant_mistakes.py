@@ -57,6 +57,11 @@ M = [
  ("unet_ref.py", "f1 = np.log(rhokappa_dx) / 4.0", "f1 = np.log(rhokappa_dx)", "features: f1 unscaled"),
  ("unet_ref.py", "f2 = np.log1p(alpha_x) / 4.0", "f2 = np.log(alpha_x + 1e-30) / 4.0", "features: log for log1p"),
  ("unet_ref.py", "return np.stack([f0, f1, f2, f3], axis=-1)[None]", "return np.stack([f0, f1, f3, f2], axis=-1)[None]", "features: x/y swapped"),
+ ("fldref.py", "aw = 2.0 * dt * D[sl] / (prob.dx[d] ** 2)", "aw = dt * D[sl] / (prob.dx[d] ** 2)", "Dirichlet wall face a full cell away"),
+ ("fldref.py", "rhs[sl] += aw * Ew", "rhs[sl] += aw", "Dirichlet rhs without E_w"),
+ ("fldref.py", "Ep[tuple(sl)] = 2.0 * Ew - Ep[tuple(sl)]", "Ep[tuple(sl)] = Ew", "Dirichlet ghosts set to E_w"),
+ ("fldref.py", "Ep[tuple(sl)] = 2.0 * Ew - Ep[tuple(sl)]", "pass", "Dirichlet ghosts mirrored"),
+ ("fldref.py", "    return solve(alphas, E + rhs, prob, diag=diag, **kw)", "    return solve(alphas, E + rhs, prob, **kw)", "Dirichlet diagonal dropped"),
 ]
 import tempfile
 tmp = os.path.join(tempfile.gettempdir(), "fld_oracle_mutant")
