@@ -56,8 +56,21 @@ typedef enum {
 /* Boundary condition of one side of one dimension.  Periodic must be set on
  * both sides of a dimension.  Neumann is the paper's zero-gradient boundary
  * (Sect. 4.1, 4.4): mirror ghost cells for the gradient (E[-1] = E[0],
- * E[-2] = E[1]) and no flux through the boundary face. */
-typedef enum { FLD_BC_PERIODIC = 0, FLD_BC_NEUMANN = 1 } fld_bc;
+ * E[-2] = E[1]) and no flux through the boundary face.  Dirichlet holds E
+ * at bc_value_lo/hi on the boundary face (the radiation temperature tied to
+ * the gas temperature on the walls of the magnetoconvection case, Sect.
+ * 4.5): the gradient's ghosts are the mirror ghosts reflected about that
+ * value (2 E_w - E[0], 2 E_w - E[1]), and the boundary face, half a cell
+ * from the centre with the boundary cell's D, adds alpha_w = 2 dt D / dx^2
+ * to the cell's diagonal and alpha_w E_w to its right-hand side.  Contexts
+ * with a Dirichlet wall solve in FP64 with V-cycles alone (precision FP64,
+ * krylov 0, guess E^n or zero, not batched) on the one-launch-per-pass
+ * kernels; fld_explicit_sources rejects them. */
+typedef enum {
+  FLD_BC_PERIODIC = 0,
+  FLD_BC_NEUMANN = 1,
+  FLD_BC_DIRICHLET = 2
+} fld_bc;
 
 /* eq. fld_lambda (Levermore-Pomraning), the diffusion value 1/3 used by
  * the paper for its stationary shocks (Sect. 4.1), or Minerbo's limiter
@@ -129,6 +142,8 @@ typedef struct {
                             and the next 2, 4, ... 32 steps start with
                             FP64 ones; the workspace then also holds the
                             FP64 hierarchy                                */
+  double bc_value_lo[3]; /* E on a Dirichlet lower / upper wall (finite,  */
+  double bc_value_hi[3]; /* > 0); unused on other walls                   */
 } fld_params;
 
 typedef struct {

@@ -48,6 +48,7 @@ struct Levels {
   T* x[kMaxLevels] = {};
   T* b[kMaxLevels] = {};
   T* a[kMaxLevels][3] = {};
+  T* sd[kMaxLevels] = {};   // Dirichlet walls' diagonal term (or null)
   T* alt[kMaxLevels] = {};  // second iterate buffer of the tiled 2D levels
   T* tmp = nullptr;  // coarsest-level scratch (global-memory tail only)
 };
@@ -233,12 +234,21 @@ struct Plan {
   size_t alt64[kMaxLevels] = {};  // FP64 ones beside FP32 (see pre64)
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
   size_t dscr = 0;  // 3D coefficient stage: D per cell
+  size_t sd64[kMaxLevels] = {};  // Dirichlet walls' diagonal term per level
   size_t guess = 0;
   size_t kr_r = 0, kr_p[2] = {}, kr_q = 0, kr_z = 0;  // flexible CG vectors
   size_t net_bytes = 0;
   int64_t n_partials = 0;
   size_t total = 0;
 };
+
+// Whether some wall holds E (FLD_BC_DIRICHLET).
+inline bool has_dirichlet(const fld_params& p) {
+  for (int d = 0; d < p.ndim; ++d)
+    if (p.bc_lo[d] == FLD_BC_DIRICHLET || p.bc_hi[d] == FLD_BC_DIRICHLET)
+      return true;
+  return false;
+}
 
 // Smoothing sweeps on level l: the finest level's pre/post_smooth, the
 // coarse levels' coarse_pre/coarse_post_smooth (0: the same as the finest).
@@ -266,17 +276,26 @@ std::string validate(const fld_params* p) {
         snprintf(buf, sizeof buf, "dx[%d] must be positive and finite", d);
         return buf;
       }
-      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 1 || p->bc_hi[d] < 0 ||
-          p->bc_hi[d] > 1) {
-        snprintf(buf, sizeof buf, "bc[%d]: only periodic and neumann", d);
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 ||
+          p->bc_hi[d] > 2) {
+        snprintf(buf, sizeof buf, "bc[%d]: periodic, neumann or dirichlet", d);
         return buf;
+      }
+      for (int side = 0; side < 2; ++side) {
+        const int bc = side ? p->bc_hi[d] : p->bc_lo[d];
+        const double v = side ? p->bc_value_hi[d] : p->bc_value_lo[d];
+        if (bc == FLD_BC_DIRICHLET && !(v > 0.0 && std::isfinite(v))) {
+          snprintf(buf, sizeof buf,
+                   "bc_value[%d]: a Dirichlet wall's E must be > 0", d);
+          return buf;
+        }
       }
       if ((p->bc_lo[d] == FLD_BC_PERIODIC) != (p->bc_hi[d] == FLD_BC_PERIODIC)) {
         snprintf(buf, sizeof buf, "bc[%d]: periodic must be set on both sides", d);
         return buf;
       }
-      if (p->bc_lo[d] == FLD_BC_NEUMANN && p->n[d] < 2) {
-        snprintf(buf, sizeof buf, "n[%d] must be >= 2 with Neumann walls", d);
+      if (p->bc_lo[d] != FLD_BC_PERIODIC && p->n[d] < 2) {
+        snprintf(buf, sizeof buf, "n[%d] must be >= 2 with walls", d);
         return buf;
       }
       if (p->n[d] > (int64_t)1 << 30) return "n too large";
@@ -308,6 +327,10 @@ std::string validate(const fld_params* p) {
       p->guess_policy != FLD_GUESS_EVERY_STEP)
     return "unknown guess_policy";
   if (p->krylov != 0 && p->krylov != 1) return "krylov must be 0 or 1";
+  if (has_dirichlet(*p) &&
+      (p->precision != FLD_PREC_FP64 || p->krylov ||
+       p->guess == FLD_GUESS_LEARNED))
+    return "Dirichlet walls: precision FP64, krylov 0, guess E^n or zero";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->ir_inner < 0 || p->ir_inner > 8) return "ir_inner must be in [0, 8]";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
@@ -329,6 +352,9 @@ void make_plan(const fld_params* p, Plan* P) {
   for (int d = 0; d < 3; ++d) {
     g.n[d] = (int)p->n[d];
     g.per[d] = (d < p->ndim && p->bc_lo[d] == FLD_BC_PERIODIC) ? 1 : 0;
+    g.dirw[d] = d < p->ndim ? (p->bc_lo[d] == FLD_BC_DIRICHLET ? 1 : 0) |
+                                  (p->bc_hi[d] == FLD_BC_DIRICHLET ? 2 : 0)
+                            : 0;
   }
   g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
   P->L = 0;
@@ -379,6 +405,7 @@ void make_plan(const fld_params* p, Plan* P) {
       P->alt[l] = take(cells * (mixed ? 4 : 8));
       if (pre64) P->alt64[l] = take(cells * 8);
     }
+    if (has_dirichlet(*p)) P->sd64[l] = take(cells * 8);
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   if (nd == 3) P->dscr = take((size_t)P->g[0].N * 8);
@@ -428,6 +455,7 @@ LevelView<T> view(const fld_ctx* c, const Levels<T>& H, int l) {
   v.x = H.x[l];
   v.b = H.b[l];
   for (int d = 0; d < 3; ++d) v.a[d] = H.a[l][d];
+  v.sd = H.sd[l];
   return v;
 }
 
@@ -855,6 +883,12 @@ fld_status solve_mixed(fld_ctx* c) {
 // Face coefficients of every coarse level from the finest one's.
 template <typename T>
 fld_status coarsen_levels(fld_ctx* c, Levels<T>& H) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (H.sd[0])  // Dirichlet walls' diagonal term on every level
+      for (int l = 0; l + 1 < c->L; ++l)
+        HIP_TRY(c, launch_coarsen_sd(c->geom[l], c->geom[l + 1], H.sd[l],
+                                     H.sd[l + 1], c->stream));
+  }
   if (c->coarsen_multi && c->geom[0].ndim == 2) {
     HIP_TRY(c, launch_coarsen2d<T>(c->geom, c->L, H.a, c->stream));
     return FLD_OK;
@@ -1139,6 +1173,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
       J.O.a32[d] = c->mixed ? c->h32.a[0][d] : nullptr;
     }
     J.O.copy_dst = aliased ? c->bcopy : E_out[g];
+    J.O.sd = J.O.rhs = nullptr;  // batched grids have no Dirichlet walls
     J.O.partials = c->partials;
     J.O.ctrl = c->ctrl;
     bcoef[g] = blocks_for(c->geom[0].N);
@@ -1148,6 +1183,7 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
     v0.x = c->h64.x[0];
     v0.b = c->h64.b[0];
     for (int d = 0; d < 3; ++d) v0.a[d] = c->h64.a[0][d];
+    v0.sd = nullptr;
     jr[g] = {v0, c->mixed ? c->h32.b[0] : nullptr, c->partials, c->ctrl};
     bres[g] = blocks_for(c->geom[0].N);
     fr[g] = {c->partials, bres[g], c->ctrl};
@@ -1531,9 +1567,12 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
         c->h64.alt[l] = (double*)(w + P.alt[l]);
     }
     if (P.alt64[l]) c->h64.alt[l] = (double*)(w + P.alt64[l]);
+    c->h64.sd[l] = P.sd64[l] ? (double*)(w + P.sd64[l]) : nullptr;
   }
   const char* path = getenv("FLD_KERNEL_PATH");
-  c->fast = !(path && strcmp(path, "simple") == 0);
+  // Dirichlet walls: the one-launch-per-pass kernels (the only ones with
+  // the walls' diagonal term)
+  c->fast = !(path && strcmp(path, "simple") == 0) && !has_dirichlet(*p);
   // one coarsening launch per level (tests that both forms agree bitwise)
   c->coarsen_multi = c->fast && !getenv("FLD_COARSEN_PER_LEVEL");
   // 3D smoothing by colour passes only ("0"; tests that both forms agree),
@@ -1674,11 +1713,16 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
                                    c->net_skip == 0);
   // a learned-guess step without its network is a step with guess E^n
   const bool prev_guess = c->p.guess == FLD_GUESS_PREV || (learned && !use_net);
-  // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it)
+  // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it);
+  // with Dirichlet walls b is always the copy, E^n + sum alpha_w E_w,
+  // which the coefficient stage writes beside the walls' diagonal term
+  const bool dirichlet = c->h64.sd[0] != nullptr;
   c->h64.x[0] = E_out;
-  c->h64.b[0] = aliased ? c->bcopy : const_cast<double*>(E_in);
-  double* copy_dst = aliased ? c->bcopy
-                             : (c->p.guess == FLD_GUESS_ZERO ? nullptr : E_out);
+  c->h64.b[0] = (aliased || dirichlet) ? c->bcopy : const_cast<double*>(E_in);
+  double* copy_dst =
+      (aliased && !dirichlet) ? c->bcopy
+      : (aliased || c->p.guess == FLD_GUESS_ZERO) ? nullptr
+                                                  : E_out;
   // V-cycles per iteration: flexible CG with FP64 V-cycles runs one
   const bool one_inner =
       c->krylov && (!c->mixed || c->pre64_skip > 0);
@@ -1695,10 +1739,16 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   A.c = c->p.c;
   A.limiter = c->p.limiter;
   A.face_mean = c->p.face_mean;
+  for (int d = 0; d < 3; ++d) {
+    A.wall[d][0] = c->p.bc_value_lo[d];
+    A.wall[d][1] = c->p.bc_value_hi[d];
+  }
   // 2D grids: the LDS-tiled coefficient stage; with x0 = E^n in FP64 it also
   // forms the initial residual, so the solve needs no separate first pass
-  c->init_fused = coef2d_ok(g0) && !c->mixed && prev_guess && !c->krylov;
-  if (coef2d_ok(g0)) {
+  // (Dirichlet walls: the one-pass kernels, which write the walls' terms)
+  const bool tiled_coef = coef2d_ok(g0) && !dirichlet;
+  c->init_fused = tiled_coef && !c->mixed && prev_guess && !c->krylov;
+  if (tiled_coef) {
     HIP_TRY(c, launch_coef2d(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
                              copy_dst, c->partials, c->ctrl, c->init_fused,
                              c->stream));
@@ -1709,7 +1759,8 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     int nb = 0;
     HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
                            copy_dst, c->partials, c->ctrl, c->stream, &nb,
-                           c->dscr));
+                           c->dscr, c->h64.sd[0],
+                           dirichlet ? c->bcopy : nullptr));
     HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
                                c->stream));
   }
@@ -1866,6 +1917,9 @@ fld_status fld_explicit_sources(fld_ctx* c, const double* rho,
   if (c->batch)
     return fail(c, FLD_ERR_INVALID_ARG, "batched contexts have no explicit "
                                         "source call");
+  if (has_dirichlet(c->p))
+    return fail(c, FLD_ERR_INVALID_ARG, "explicit sources take periodic or "
+                                        "Neumann walls");
   if (!rho || !kappa || !E)
     return fail(c, FLD_ERR_INVALID_ARG, "NULL field pointer");
   const Geom& g = c->geom[0];
@@ -2190,6 +2244,7 @@ static std::string validate_batch(int32_t count, const fld_params* each) {
         nu_post(p, 1) != nu_post(each[0], 1))
       return "batched grids need equal pre/post smoothing in 1..3";
     if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
+    if (has_dirichlet(p)) return "batched grids take periodic or Neumann walls";
     if (p.krylov) return "batched grids iterate V-cycles (krylov = 0)";
     if (p.ir_inner != each[0].ir_inner)
       return "batched grids must share ir_inner";

@@ -166,6 +166,7 @@ __device__ __forceinline__ T relax_value(const LevelView<T>& L, const int c[3],
     num += al * xs[nl] + au * xs[nu];
     den += al + au;
   }
+  if (L.sd) den += L.sd[idx];  // Dirichlet walls of this cell
   return num / den;
 }
 
@@ -183,6 +184,7 @@ __device__ __forceinline__ T residual_value(const LevelView<T>& L,
     upper_nb(L.g, L.a[d], d, c[d], idx, st, nu, au);
     ax += al * (xi - L.x[nl]) + au * (xi - L.x[nu]);
   }
+  if (L.sd) ax += L.sd[idx] * xi;  // Dirichlet walls of this cell
   return L.b[idx] - ax;
 }
 
@@ -306,10 +308,23 @@ __device__ __forceinline__ double cell_D(const CoefArgs& A, const double* E,
     const int64_t st = stride_of(A.g, d);
     const int64_t base = idx - (int64_t)c[d] * st;
     const int n = A.g.n[d], p = A.g.per[d];
-    const double em2 = E[base + (int64_t)ghost(c[d] - 2, n, p) * st];
-    const double em1 = E[base + (int64_t)ghost(c[d] - 1, n, p) * st];
-    const double ep1 = E[base + (int64_t)ghost(c[d] + 1, n, p) * st];
-    const double ep2 = E[base + (int64_t)ghost(c[d] + 2, n, p) * st];
+    double em2 = E[base + (int64_t)ghost(c[d] - 2, n, p) * st];
+    double em1 = E[base + (int64_t)ghost(c[d] - 1, n, p) * st];
+    double ep1 = E[base + (int64_t)ghost(c[d] + 1, n, p) * st];
+    double ep2 = E[base + (int64_t)ghost(c[d] + 2, n, p) * st];
+    // a Dirichlet wall's ghosts: the mirror ghosts reflected about the
+    // wall value (2 E_w - E_mirror), which continue a line through E_w
+    const int w = A.g.dirw[d];
+    if (w & 1) {
+      const double Ew = A.wall[d][0];
+      if (c[d] - 2 < 0) em2 = 2.0 * Ew - em2;
+      if (c[d] - 1 < 0) em1 = 2.0 * Ew - em1;
+    }
+    if (w & 2) {
+      const double Ew = A.wall[d][1];
+      if (c[d] + 1 >= n) ep1 = 2.0 * Ew - ep1;
+      if (c[d] + 2 >= n) ep2 = 2.0 * Ew - ep2;
+    }
     const double G = (em2 - 8.0 * em1 + 8.0 * ep1 - ep2) * A.gscale[d];
     g2 += G * G;
   }
@@ -325,6 +340,10 @@ struct CoefOut {
   double* copy_dst;
   double* partials;
   Control* ctrl;
+  // with Dirichlet walls (A.g.dirw): their diagonal term and the right-hand
+  // side E^n + sum alpha_w E_w (both null without such walls)
+  double* sd;
+  double* rhs;
 };
 
 // One cell's face coefficients (and its copy of E); returns E^2 and sets
@@ -355,6 +374,27 @@ __device__ __forceinline__ double coef_cell(const CoefArgs& A,
   }
   const double Ei = E[idx];
   if (O.copy_dst) O.copy_dst[idx] = Ei;
+  if (O.sd) {
+    // Dirichlet walls: the wall face lies half a cell away with this
+    // cell's D, alpha_w = 2 dt D / dx^2 on the diagonal, alpha_w E_w on the
+    // right-hand side, whose square norm is then the stop test's |b|^2
+    double sd = 0.0, bw = 0.0;
+    for (int d = 0; d < A.g.ndim; ++d) {
+      const double aw = 2.0 * A.dt * D0 / (A.dx[d] * A.dx[d]);
+      if ((A.g.dirw[d] & 1) && c[d] == 0) {
+        sd += aw;
+        bw += aw * A.wall[d][0];
+      }
+      if ((A.g.dirw[d] & 2) && c[d] == A.g.n[d] - 1) {
+        sd += aw;
+        bw += aw * A.wall[d][1];
+      }
+    }
+    const double bi = Ei + bw;
+    O.sd[idx] = sd;
+    O.rhs[idx] = bi;
+    return bi * bi;
+  }
   return Ei * Ei;
 }
 

@@ -20,6 +20,7 @@ struct Geom {
   int ndim;
   int n[3];    // cells per dimension (unused = 1)
   int per[3];  // 1 if periodic along that dimension
+  int dirw[3]; // Dirichlet walls along that dimension: bit 0 lower, 1 upper
   int64_t N;   // cells
 };
 
@@ -29,6 +30,9 @@ struct LevelView {
   T* x;          // iterate (correction on coarse levels)
   T* b;          // right-hand side (restricted residual on coarse levels)
   const T* a[3]; // face coefficients, one array per dimension
+  // Dirichlet walls' diagonal term per cell (null without such walls): the
+  // operator is (1 + sd) x + sum_f alpha_f (x - x_f)
+  const T* sd;
 };
 
 // Device control block of one solve: norms, counters and the stop flag
@@ -64,6 +68,7 @@ struct CoefArgs {
   double dt, c;
   int limiter;   // 0 LP, 1 diffusion, 2 Minerbo
   int face_mean; // 0 arithmetic, 1 harmonic
+  double wall[3][2];  // E held on the Dirichlet walls (g.dirw), lower, upper
 };
 
 // Explicit source terms of one grid (fld_explicit_sources): inputs E, rho,
@@ -88,7 +93,14 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s, int* nblocks = nullptr,
-                       double* dscr = nullptr);
+                       double* dscr = nullptr, double* sd = nullptr,
+                       double* rhs = nullptr);
+// Dirichlet walls (a.g.dirw): with sd and rhs the coefficient stage also
+// writes each cell's wall diagonal term and the right-hand side E^n +
+// sum alpha_w E_w (one-pass kernels); launch_coarsen_sd carries the wall
+// term to a coarse level.
+hipError_t launch_coarsen_sd(const Geom& fine, const Geom& coarse,
+                             const double* sdf, double* sdc, hipStream_t s);
 hipError_t launch_finalize(int mode, const double* partials, int count,
                            Control* ctrl, hipStream_t s);
 hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,

@@ -170,7 +170,7 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s, int* nblocks,
-                       double* dscr) {
+                       double* dscr, double* sd, double* rhs) {
   CoefOut O;
   for (int d = 0; d < 3; ++d) {
     O.a64[d] = a64[d];
@@ -179,6 +179,9 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
   O.copy_dst = copy_dst;
   O.partials = partials;
   O.ctrl = ctrl;
+  O.sd = sd;
+  O.rhs = rhs;
+  if (sd) dscr = nullptr;  // the one-pass kernels write the wall terms
   if (fits3(a.g)) {
     if (nblocks) *nblocks = (int)blocks3(a.g);
     const dim3 grid = grid3(a.g.n[0], a.g.n[1], a.g.n[2]);
@@ -220,6 +223,38 @@ hipError_t launch_coarsen(const Geom& fine, const Geom& coarse,
   return hipGetLastError();
 }
 
+// Dirichlet walls' diagonal term of a coarse level: the coarse wall face
+// carries the mean of its fine faces' alpha_w, a quarter as large with the
+// spacing doubled, so sd_c = (sum over the 2^d children of sd_f) /
+// 2^(d+1) (the children off the wall contribute 0; a corner cell sums its
+// walls).
+__global__ void __launch_bounds__(kBlock)
+    k_coarsen_sd(Geom F, Geom C, const double* __restrict__ sdf,
+                 double* __restrict__ sdc) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= C.N) return;
+  int c[3];
+  coords(C, idx, c);
+  const int nd = F.ndim;
+  const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
+  double s = 0.0;
+  for (int q2 = 0; q2 < o2; ++q2)
+    for (int q1 = 0; q1 < o1; ++q1)
+      for (int q0 = 0; q0 < 2; ++q0) {
+        const int f0 = 2 * c[0] + q0, f1 = nd > 1 ? 2 * c[1] + q1 : 0;
+        const int f2 = nd > 2 ? 2 * c[2] + q2 : 0;
+        s += sdf[f0 + (int64_t)F.n[0] * (f1 + (int64_t)F.n[1] * f2)];
+      }
+  sdc[idx] = s / (double)(2 << nd);
+}
+
+hipError_t launch_coarsen_sd(const Geom& fine, const Geom& coarse,
+                             const double* sdf, double* sdc, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen_sd, dim3(blocks_for(coarse.N)), dim3(kBlock), 0,
+                     s, fine, coarse, sdf, sdc);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // multigrid, one launch per phase (1D/3D levels and the reference path)
 // ---------------------------------------------------------------------------
@@ -248,8 +283,9 @@ hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
                              hipStream_t s) {
   if constexpr (sizeof(T) == sizeof(double)) {
     // 3D FP64: the residual kernel of the 3D launch grid, without its FP32
-    // output (same residual per cell)
-    if (fits3(L.g)) {
+    // output (same residual per cell); a level with Dirichlet walls takes
+    // the generic kernel (residual_value has their diagonal term)
+    if (fits3(L.g) && !L.sd) {
       *nblocks = (int)blocks3(L.g);
       hipLaunchKernelGGL(k_resid_to32_3d, grid3(L.g.n[0], L.g.n[1], L.g.n[2]),
                          dim3(k3T), 0, s, L, (float*)nullptr, partials, ctrl);
@@ -688,7 +724,8 @@ hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  const LevelView<T>& coarse, double* partials,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
-  const int zc = fits3(fine.g) ? rr3_chunk(fine.g) : 0;
+  // the z-marching kernel has no Dirichlet diagonal term
+  const int zc = fits3(fine.g) && !fine.sd ? rr3_chunk(fine.g) : 0;
   if (zc > 0) {
     const int gx = (fine.g.n[0] + 63) / 64, gy = (fine.g.n[1] + kRRY - 1) / kRRY;
     const int gz = (fine.g.n[2] + zc - 1) / zc;

@@ -23,6 +23,7 @@ FLD_ERR_MODEL = 6
 
 FLD_BC_PERIODIC = 0
 FLD_BC_NEUMANN = 1
+FLD_BC_DIRICHLET = 2
 FLD_LIMITER_LP = 0
 FLD_LIMITER_MINERBO = 2
 FLD_LIMITER_DIFFUSION = 1
@@ -61,6 +62,8 @@ class fld_params(ctypes.Structure):
         ("coarse_pre_smooth", ctypes.c_int32),
         ("coarse_post_smooth", ctypes.c_int32),
         ("guess_policy", ctypes.c_int32), ("krylov", ctypes.c_int32),
+        ("bc_value_lo", ctypes.c_double * 3),
+        ("bc_value_hi", ctypes.c_double * 3),
     ]
 
 
@@ -152,7 +155,7 @@ def fld_params_default(**overrides):
     p = fld_params()
     load().fld_params_default(ctypes.byref(p))
     for k, v in overrides.items():
-        if k in ("n", "dx", "bc_lo", "bc_hi"):
+        if k in ("n", "dx", "bc_lo", "bc_hi", "bc_value_lo", "bc_value_hi"):
             arr = getattr(p, k)
             for i, x in enumerate(v):
                 arr[i] = x

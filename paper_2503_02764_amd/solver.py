@@ -23,12 +23,22 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
                 gas_const=1.0, limiter="lp", face_mean="arith",
                 precision="fp64", guess="prev", rtol=1e-8, max_cycles=50,
                 pre_smooth=2, post_smooth=2, ir_inner=0, coarse_pre_smooth=0,
-                coarse_post_smooth=0, guess_policy="adaptive", krylov=False):
+                coarse_post_smooth=0, guess_policy="adaptive", krylov=False,
+                dirichlet=None):
+    """`bc`: "periodic" or "neumann" per dimension; `dirichlet`: optional
+    {(d, side): E_w} (side 0 the lower wall of dimension d, 1 the upper)
+    turning those walls of non-periodic dimensions into Dirichlet walls."""
     n = list(n) + [1] * (3 - len(n))
     dx = list(dx) + [1.0] * (3 - len(dx))
     codes = [_BC[b] for b in bc] + [fld.FLD_BC_PERIODIC] * (3 - len(bc))
+    lo, hi = list(codes), list(codes)
+    vlo, vhi = [0.0] * 3, [0.0] * 3
+    for (d, side), v in (dirichlet or {}).items():
+        (hi if side else lo)[d] = fld.FLD_BC_DIRICHLET
+        (vhi if side else vlo)[d] = float(v)
     return fld.fld_params_default(
-        ndim=ndim, n=n[:3], dx=dx[:3], bc_lo=codes, bc_hi=codes, c=c,
+        ndim=ndim, n=n[:3], dx=dx[:3], bc_lo=lo, bc_hi=hi,
+        bc_value_lo=vlo, bc_value_hi=vhi, c=c,
         a_rad=a_rad, gamma=gamma, gas_const=gas_const,
         limiter=_LIM[limiter], face_mean=_FACE[face_mean],
         precision=_PREC[precision], guess=_GUESS[guess], rtol=rtol,

@@ -135,6 +135,43 @@ def test_bc_and_shape_validation():
                          ctypes.byref(out)) == fld.FLD_ERR_WORKSPACE
 
 
+def test_dirichlet_validation():
+    """Dirichlet walls (FLD_BC_DIRICHLET): a positive finite wall value, a
+    non-periodic dimension, and an FP64 V-cycle solve (no FP32 refinement,
+    flexible CG or learned guess); a valid set-up sizes its workspace with
+    the walls' diagonal terms."""
+    from paper_2503_02764_amd.solver import make_params
+    lib = fld.load()
+    out = ctypes.c_void_p()
+    D = fld.FLD_BC_DIRICHLET
+    good = dict(ndim=1, n=(64, 1, 1), dx=(1 / 64, 1, 1), bc_lo=(1, 0, 0),
+                bc_hi=(D, 0, 0), bc_value_hi=(2.0, 0, 0))
+    p = fld.fld_params_default(**good)
+    with_walls = fld.fld_workspace_bytes(p)
+    p0 = fld.fld_params_default(ndim=1, n=(64, 1, 1), dx=(1 / 64, 1, 1),
+                                bc_lo=(1, 0, 0), bc_hi=(1, 0, 0))
+    assert with_walls > fld.fld_workspace_bytes(p0) > 0
+    bad = [
+        dict(good, bc_value_hi=(0.0, 0, 0)),
+        dict(good, bc_value_hi=(float("nan"), 0, 0)),
+        dict(good, bc_lo=(0, 0, 0)),  # periodic on the other side
+        dict(good, precision=fld.FLD_PREC_FP32_IR),
+        dict(good, krylov=1),
+        dict(good, bc_lo=(3, 0, 0)),
+    ]
+    for kw in bad:
+        p = fld.fld_params_default(**kw)
+        assert fld.fld_workspace_bytes(p) == 0, kw
+        st = lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
+                           None, ctypes.byref(out))
+        assert st == fld.FLD_ERR_INVALID_ARG, kw
+    p = make_params(2, (16, 16), (0.1, 0.1), ("periodic", "neumann"),
+                    dirichlet={(1, 0): 3.0, (1, 1): 1.5})
+    assert list(p.bc_lo)[:2] == [0, D] and list(p.bc_hi)[:2] == [0, D]
+    assert p.bc_value_lo[1] == 3.0 and p.bc_value_hi[1] == 1.5
+    assert fld.fld_workspace_bytes(p) > 0
+
+
 def test_status_strings():
     assert fld.status_str(fld.FLD_OK) == "FLD_OK"
     assert fld.status_str(fld.FLD_ERR_NOT_CONVERGED) == "FLD_ERR_NOT_CONVERGED"
