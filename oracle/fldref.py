@@ -42,6 +42,11 @@ face, half a cell from the centre, carries the boundary cell's D:
 (A x)_i gains alpha_w x_i and b_i gains alpha_w E_w, alpha_w = 2 dt D_i /
 dx_d^2 (``dirichlet_terms``).
 
+Cells can also be held at a prescribed new value (``held_step``, an
+interior boundary: the linear-wave tests of Sect. 4.3 overwrite the first
+wavelength of the domain).  Reading: their rows become x_i = E_hold_i and
+free neighbours couple to them through the usual face coefficients.
+
 Arrays are float64, C order, x fastest: shape (nx,), (ny, nx) or
 (nz, ny, nx).
 """
@@ -306,6 +311,37 @@ def diffusion_step(E, rho, kappa, dt, prob, **kw):
         return solve(alphas, E, prob, **kw)
     diag, rhs = dirichlet_terms(E, rho, kappa, dt, prob)
     return solve(alphas, E + rhs, prob, diag=diag, **kw)
+
+
+def held_step(E, rho, kappa, dt, prob, held, E_hold, method=None):
+    """Backward-Euler step with held cells: an interior boundary whose
+    cells (``held`` true) take a prescribed new value ``E_hold`` (the
+    linear-wave tests of Sect. 4.3 overwrite the first wavelength of the
+    domain with a known solution).
+
+    Reading: a held cell's row of the system becomes x_i = E_hold_i; every
+    other row is the plain one (with the Dirichlet walls' terms), so a free
+    cell next to a held one couples to the held value through the usual
+    face coefficient: the held cells are interior Dirichlet data at cell
+    centres.  D is still computed from E^n in every cell.  The system is no
+    longer symmetric, so only the direct solves apply.
+    """
+    alphas = face_coefficients(E, rho, kappa, dt, prob)
+    diag, rhs = dirichlet_terms(E, rho, kappa, dt, prob)
+    A = assemble(alphas, prob, diag)
+    h = np.asarray(held, dtype=bool).ravel()
+    free_rows = sp.diags((~h).astype(np.float64))
+    A = (free_rows @ A + sp.diags(h.astype(np.float64))).tocsr()
+    b = np.where(held, E_hold, E + rhs).ravel()
+    if method is None:
+        method = "dense" if A.shape[0] <= 4096 else "splu"
+    if method == "dense":
+        x = np.linalg.solve(A.toarray(), b)
+    elif method == "splu":
+        x = spla.splu(A.tocsc()).solve(b)
+    else:
+        raise ValueError(f"held cells: direct solves only, not {method}")
+    return x.reshape(E.shape)
 
 
 def relative_residual(x, b, alphas, prob, diag=None):

@@ -62,6 +62,10 @@ M = [
  ("fldref.py", "Ep[tuple(sl)] = 2.0 * Ew - Ep[tuple(sl)]", "Ep[tuple(sl)] = Ew", "Dirichlet ghosts set to E_w"),
  ("fldref.py", "Ep[tuple(sl)] = 2.0 * Ew - Ep[tuple(sl)]", "pass", "Dirichlet ghosts mirrored"),
  ("fldref.py", "    return solve(alphas, E + rhs, prob, diag=diag, **kw)", "    return solve(alphas, E + rhs, prob, **kw)", "Dirichlet diagonal dropped"),
+ ("fldref.py", "b = np.where(held, E_hold, E + rhs).ravel()", "b = np.where(held, E, E + rhs).ravel()", "held cells keep E^n"),
+ ("fldref.py", "b = np.where(held, E_hold, E + rhs).ravel()", "b = np.where(held, E_hold, E).ravel()", "held step without the Dirichlet walls' rhs"),
+ ("fldref.py", "A = (free_rows @ A + sp.diags(h.astype(np.float64))).tocsr()", "A = A.tocsr()", "held rows not replaced"),
+ ("fldref.py", "A = (free_rows @ A + sp.diags(h.astype(np.float64))).tocsr()", "A = (free_rows @ A @ free_rows + sp.diags(h.astype(np.float64))).tocsr()", "free cells decoupled from the held values"),
 ]
 import tempfile
 tmp = os.path.join(tempfile.gettempdir(), "fld_oracle_mutant")
