@@ -144,6 +144,8 @@ typedef struct {
                             FP64 hierarchy                                */
   double bc_value_lo[3]; /* E on a Dirichlet lower / upper wall (finite,  */
   double bc_value_hi[3]; /* > 0); unused on other walls                   */
+  int32_t held_cells;    /* 1: held cells (fld_set_held) take part in every
+                            step; same restrictions as Dirichlet walls    */
 } fld_params;
 
 typedef struct {
@@ -231,6 +233,35 @@ fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
                             const double* kappa, const double* E_in,
                             double* E_out, fld_stats* stats,
                             void* hip_stream);
+
+/* Held cells: an interior boundary whose cells take a prescribed new E
+ * (the linear-wave tests of Sect. 4.3 overwrite the first wavelength of
+ * the domain with a known solution).  A held cell's row of the system
+ * becomes E*_i = E_hold[i]; every other row is unchanged, so a free cell
+ * next to a held one couples to the held value through the usual face
+ * coefficient (interior Dirichlet data at cell centres), and D is still
+ * computed from E^n in every cell.  The library solves the equivalent
+ * system with the held cells eliminated: a free cell's faces to held
+ * neighbours go onto its diagonal and their held values times those faces
+ * onto its right-hand side, and every face touching a held cell is cut, so
+ * the free cells' block is symmetric.  On the coarse levels a cell with a
+ * held child is a point of zero correction, coupled to its free neighbours
+ * through faces coarsened from the faces before the cut.  The stop test's
+ * |b| is that of the eliminated system's right-hand side.  Held cells end
+ * exactly at E_hold.
+ * mask: device array of the grid's cells (layout of E), nonzero = held;
+ * E_hold: device array of the same cells (read where the mask is set;
+ * must not overlap the step's E_out).  Both stay owned by the caller and
+ * are read by every following fld_step, so they must stay valid until the
+ * next fld_set_held or fld_destroy; their contents may change between
+ * steps.  NULL for both clears them, after which fld_step fails until they
+ * are given again.  Needs a context set up with held_cells = 1, whose
+ * steps then solve in FP64 with V-cycles alone (precision FP64, krylov 0,
+ * guess E^n or zero, not batched, not fld_step_noalloc) on the
+ * one-launch-per-pass kernels.  FLD_ERR_INVALID_ARG otherwise, or when
+ * only one of the two pointers is NULL.  Enqueues nothing. */
+fld_status fld_set_held(fld_ctx* ctx, const uint8_t* mask,
+                        const double* E_hold);
 
 /* Implicit gas-radiation exchange (eqs. heating, qdot) for one step dt:
  * per cell, with beta = dt c kappa rho and S = E + e_int,

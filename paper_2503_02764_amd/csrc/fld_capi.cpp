@@ -48,7 +48,11 @@ struct Levels {
   T* x[kMaxLevels] = {};
   T* b[kMaxLevels] = {};
   T* a[kMaxLevels][3] = {};
-  T* sd[kMaxLevels] = {};   // Dirichlet walls' diagonal term (or null)
+  // extra diagonal term (or null): Dirichlet walls, and on the finest
+  // level the faces of free cells to held cells
+  T* sd[kMaxLevels] = {};
+  // coarse levels' held points (or null): some child held
+  uint8_t* held[kMaxLevels] = {};
   T* alt[kMaxLevels] = {};  // second iterate buffer of the tiled 2D levels
   T* tmp = nullptr;  // coarsest-level scratch (global-memory tail only)
 };
@@ -100,6 +104,10 @@ struct fld_ctx {
   bool tile3d = true;         // 3D: tiled sweeps below the marching ones
   bool tile3d_all = false;    // 3D: tiled sweeps on the large levels too
   bool tail_big = true;       // 2D: tail from a level of up to 4096 cells
+  // held cells (fld_params.held_cells): the caller's mask and prescribed
+  // values, given by fld_set_held
+  const uint8_t* held_mask = nullptr;
+  const double* held_vals = nullptr;
   int sweep_zc = 0;           // z planes per block of a fused sweep (0: auto)
   int tile_var[kMaxLevels][2] = {};  // tile shape per level: down, up
   BatchState* batch = nullptr;  // set for a batched context (sub-grids)
@@ -234,7 +242,8 @@ struct Plan {
   size_t alt64[kMaxLevels] = {};  // FP64 ones beside FP32 (see pre64)
   size_t bcopy = 0, partials = 0, tmp = 0, ctrl = 0, mean = 0, net = 0;
   size_t dscr = 0;  // 3D coefficient stage: D per cell
-  size_t sd64[kMaxLevels] = {};  // Dirichlet walls' diagonal term per level
+  size_t sd64[kMaxLevels] = {};  // extra diagonal term per level
+  size_t held[kMaxLevels] = {};  // coarse levels' held points
   size_t guess = 0;
   size_t kr_r = 0, kr_p[2] = {}, kr_q = 0, kr_z = 0;  // flexible CG vectors
   size_t net_bytes = 0;
@@ -243,6 +252,12 @@ struct Plan {
 };
 
 // Whether some wall holds E (FLD_BC_DIRICHLET).
+inline bool has_dirichlet(const fld_params& p);
+// Whether the system has rows of its own beside E^n's: Dirichlet walls or
+// held cells (FP64 V-cycles on the one-launch-per-pass kernels).
+inline bool own_rows(const fld_params& p) {
+  return has_dirichlet(p) || p.held_cells != 0;
+}
 inline bool has_dirichlet(const fld_params& p) {
   for (int d = 0; d < p.ndim; ++d)
     if (p.bc_lo[d] == FLD_BC_DIRICHLET || p.bc_hi[d] == FLD_BC_DIRICHLET)
@@ -327,10 +342,12 @@ std::string validate(const fld_params* p) {
       p->guess_policy != FLD_GUESS_EVERY_STEP)
     return "unknown guess_policy";
   if (p->krylov != 0 && p->krylov != 1) return "krylov must be 0 or 1";
-  if (has_dirichlet(*p) &&
+  if (p->held_cells != 0 && p->held_cells != 1) return "held_cells must be 0 or 1";
+  if (own_rows(*p) &&
       (p->precision != FLD_PREC_FP64 || p->krylov ||
        p->guess == FLD_GUESS_LEARNED))
-    return "Dirichlet walls: precision FP64, krylov 0, guess E^n or zero";
+    return "Dirichlet walls and held cells: precision FP64, krylov 0, guess "
+           "E^n or zero";
   if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return "rtol must be in (0, 1)";
   if (p->ir_inner < 0 || p->ir_inner > 8) return "ir_inner must be in [0, 8]";
   if (p->max_cycles < 1) return "max_cycles must be >= 1";
@@ -405,7 +422,8 @@ void make_plan(const fld_params* p, Plan* P) {
       P->alt[l] = take(cells * (mixed ? 4 : 8));
       if (pre64) P->alt64[l] = take(cells * 8);
     }
-    if (has_dirichlet(*p)) P->sd64[l] = take(cells * 8);
+    if (own_rows(*p)) P->sd64[l] = take(cells * 8);
+    if (p->held_cells && l > 0) P->held[l] = take(cells);
   }
   P->bcopy = take((size_t)P->g[0].N * 8);
   if (nd == 3) P->dscr = take((size_t)P->g[0].N * 8);
@@ -456,6 +474,7 @@ LevelView<T> view(const fld_ctx* c, const Levels<T>& H, int l) {
   v.b = H.b[l];
   for (int d = 0; d < 3; ++d) v.a[d] = H.a[l][d];
   v.sd = H.sd[l];
+  v.held = H.held[l];
   return v;
 }
 
@@ -884,10 +903,15 @@ fld_status solve_mixed(fld_ctx* c) {
 template <typename T>
 fld_status coarsen_levels(fld_ctx* c, Levels<T>& H) {
   if constexpr (sizeof(T) == sizeof(double)) {
-    if (H.sd[0])  // Dirichlet walls' diagonal term on every level
+    if (H.sd[0])  // the Dirichlet walls' diagonal term on every level
       for (int l = 0; l + 1 < c->L; ++l)
         HIP_TRY(c, launch_coarsen_sd(c->geom[l], c->geom[l + 1], H.sd[l],
                                      H.sd[l + 1], c->stream));
+    if (c->p.held_cells)  // held points: a coarse cell with a held child
+      for (int l = 0; l + 1 < c->L; ++l)
+        HIP_TRY(c, launch_coarsen_held(c->geom[l], c->geom[l + 1],
+                                       l == 0 ? c->held_mask : H.held[l],
+                                       H.held[l + 1], c->stream));
   }
   if (c->coarsen_multi && c->geom[0].ndim == 2) {
     HIP_TRY(c, launch_coarsen2d<T>(c->geom, c->L, H.a, c->stream));
@@ -1173,7 +1197,10 @@ void build_image(fld_ctx* bc, Image& im, const double* dt,
       J.O.a32[d] = c->mixed ? c->h32.a[0][d] : nullptr;
     }
     J.O.copy_dst = aliased ? c->bcopy : E_out[g];
-    J.O.sd = J.O.rhs = nullptr;  // batched grids have no Dirichlet walls
+    // batched grids have no Dirichlet walls and no held cells
+    J.O.sd = J.O.rhs = nullptr;
+    J.O.held = nullptr;
+    J.O.hold = nullptr;
     J.O.partials = c->partials;
     J.O.ctrl = c->ctrl;
     bcoef[g] = blocks_for(c->geom[0].N);
@@ -1568,11 +1595,12 @@ void fill_ctx(fld_ctx* c, const fld_params* p, const Plan& P, void* workspace,
     }
     if (P.alt64[l]) c->h64.alt[l] = (double*)(w + P.alt64[l]);
     c->h64.sd[l] = P.sd64[l] ? (double*)(w + P.sd64[l]) : nullptr;
+    c->h64.held[l] = P.held[l] ? (uint8_t*)(w + P.held[l]) : nullptr;
   }
   const char* path = getenv("FLD_KERNEL_PATH");
-  // Dirichlet walls: the one-launch-per-pass kernels (the only ones with
-  // the walls' diagonal term)
-  c->fast = !(path && strcmp(path, "simple") == 0) && !has_dirichlet(*p);
+  // Dirichlet walls and held cells: the one-launch-per-pass kernels (the
+  // only ones with the extra diagonal term)
+  c->fast = !(path && strcmp(path, "simple") == 0) && !own_rows(*p);
   // one coarsening launch per level (tests that both forms agree bitwise)
   c->coarsen_multi = c->fast && !getenv("FLD_COARSEN_PER_LEVEL");
   // 3D smoothing by colour passes only ("0"; tests that both forms agree),
@@ -1706,6 +1734,9 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     return fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
   if (c->p.guess == FLD_GUESS_LEARNED && !c->net)
     return fail(c, FLD_ERR_MODEL, "no model: call fld_set_model first");
+  if (c->p.held_cells && !c->held_mask)
+    return fail(c, FLD_ERR_INVALID_ARG,
+                "held_cells: give the mask and values by fld_set_held first");
   const bool aliased = (E_in == E_out);
   const Geom& g0 = c->geom[0];
   const bool learned = c->p.guess == FLD_GUESS_LEARNED;
@@ -1714,13 +1745,16 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   // a learned-guess step without its network is a step with guess E^n
   const bool prev_guess = c->p.guess == FLD_GUESS_PREV || (learned && !use_net);
   // level 0: x = E_out, b = E_in (or its copy when E_out overwrites it);
-  // with Dirichlet walls b is always the copy, E^n + sum alpha_w E_w,
-  // which the coefficient stage writes beside the walls' diagonal term
-  const bool dirichlet = c->h64.sd[0] != nullptr;
+  // with Dirichlet walls or held cells b is always the copy, which the
+  // coefficient stage writes: E^n + sum alpha_w E_w beside the walls'
+  // diagonal term, the prescribed values in the held cells, and in a free
+  // cell next to held ones their values times its faces to them
+  const bool own_b = own_rows(c->p);
+  const bool held = c->p.held_cells != 0;
   c->h64.x[0] = E_out;
-  c->h64.b[0] = (aliased || dirichlet) ? c->bcopy : const_cast<double*>(E_in);
+  c->h64.b[0] = (aliased || own_b) ? c->bcopy : const_cast<double*>(E_in);
   double* copy_dst =
-      (aliased && !dirichlet) ? c->bcopy
+      (aliased && !own_b) ? c->bcopy
       : (aliased || c->p.guess == FLD_GUESS_ZERO) ? nullptr
                                                   : E_out;
   // V-cycles per iteration: flexible CG with FP64 V-cycles runs one
@@ -1745,8 +1779,8 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
   }
   // 2D grids: the LDS-tiled coefficient stage; with x0 = E^n in FP64 it also
   // forms the initial residual, so the solve needs no separate first pass
-  // (Dirichlet walls: the one-pass kernels, which write the walls' terms)
-  const bool tiled_coef = coef2d_ok(g0) && !dirichlet;
+  // (Dirichlet walls, held cells: the one-pass kernels, which write b)
+  const bool tiled_coef = coef2d_ok(g0) && !own_b;
   c->init_fused = tiled_coef && !c->mixed && prev_guess && !c->krylov;
   if (tiled_coef) {
     HIP_TRY(c, launch_coef2d(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
@@ -1759,13 +1793,28 @@ static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
     int nb = 0;
     HIP_TRY(c, launch_coef(A, E_in, rho, kappa, c->h64.a[0], c->h32.a[0],
                            copy_dst, c->partials, c->ctrl, c->stream, &nb,
-                           c->dscr, c->h64.sd[0],
-                           dirichlet ? c->bcopy : nullptr));
-    HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
-                               c->stream));
+                           c->dscr, c->h64.sd[0], own_b ? c->bcopy : nullptr,
+                           held ? c->held_mask : nullptr,
+                           held ? c->held_vals : nullptr));
+    if (!held)
+      HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
+                                 c->stream));
   }
   FLD_TRY(c->mixed ? coarsen_levels<float>(c, c->h32)
                    : coarsen_levels<double>(c, c->h64));
+  if (held) {
+    // with the coarse levels built from the uncut faces, the held cells
+    // leave the finest level's free rows (their faces become diagonal and
+    // right-hand-side terms) and their faces are cut: a held row is
+    // x = E_hold, the free block is symmetric
+    int nb = 0;
+    HIP_TRY(c, launch_held_fold(g0, c->h64.a[0], c->held_mask, c->held_vals,
+                                c->h64.sd[0], c->bcopy, c->partials, &nb,
+                                c->stream));
+    HIP_TRY(c, launch_held_cut(g0, c->h64.a[0], c->held_mask, c->stream));
+    HIP_TRY(c, launch_finalize(kFinBnorm, c->partials, nb, c->ctrl,
+                               c->stream));
+  }
   if (c->p.guess == FLD_GUESS_ZERO)
     HIP_TRY(c, launch_fill(E_out, g0.N, 0.0, c->stream));
   // the adaptive policy times the network and the solve on the stream
@@ -1873,6 +1922,10 @@ fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
     return fail(nullptr, FLD_ERR_INVALID_ARG,
                 "fld_step_noalloc takes guess E^n or zero (the learned guess "
                 "needs a context with a model)");
+  if (p->held_cells)
+    return fail(nullptr, FLD_ERR_INVALID_ARG,
+                "fld_step_noalloc has no held cells (they are given to a "
+                "context by fld_set_held)");
   void* ws = nullptr;
   FLD_TRY(static_scratch(&ws));
   Plan P;
@@ -1895,6 +1948,21 @@ fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
   // the step has synchronised with the stream (its stop test reads the
   // control block), so nothing of this call is still in flight
   return st;
+}
+
+fld_status fld_set_held(fld_ctx* c, const uint8_t* mask,
+                        const double* E_hold) {
+  if (!c) return fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->batch)
+    return fail(c, FLD_ERR_INVALID_ARG, "batched contexts have no held cells");
+  if (!c->p.held_cells)
+    return fail(c, FLD_ERR_INVALID_ARG,
+                "the context was set up with held_cells = 0");
+  if ((mask == nullptr) != (E_hold == nullptr))
+    return fail(c, FLD_ERR_INVALID_ARG, "give both mask and E_hold, or neither");
+  c->held_mask = mask;
+  c->held_vals = E_hold;
+  return FLD_OK;
 }
 
 fld_status fld_exchange(fld_ctx* c, double dt, const double* rho,
@@ -2245,6 +2313,7 @@ static std::string validate_batch(int32_t count, const fld_params* each) {
       return "batched grids need equal pre/post smoothing in 1..3";
     if (p.guess != FLD_GUESS_PREV) return "batched grids use guess E^n";
     if (has_dirichlet(p)) return "batched grids take periodic or Neumann walls";
+    if (p.held_cells) return "batched grids have no held cells";
     if (p.krylov) return "batched grids iterate V-cycles (krylov = 0)";
     if (p.ir_inner != each[0].ir_inner)
       return "batched grids must share ir_inner";

@@ -182,7 +182,10 @@ hipError_t launch_coef2d(const CoefArgs& a, const double* E, const double* rho,
     P.O.a32[d] = a32[d];
   }
   P.O.copy_dst = copy_dst;
-  P.O.sd = P.O.rhs = nullptr;  // Dirichlet walls take the one-pass kernel
+  // Dirichlet walls and held cells take the one-pass kernel
+  P.O.sd = P.O.rhs = nullptr;
+  P.O.held = nullptr;
+  P.O.hold = nullptr;
   P.O.partials = partials;
   P.O.ctrl = ctrl;
   P.tiles_x = (a.g.n[0] + CX - 1) / CX;

@@ -156,6 +156,7 @@ __device__ __forceinline__ T residual_nb(const T* const a[3],
 template <typename T>
 __device__ __forceinline__ T relax_value(const LevelView<T>& L, const int c[3],
                                          int64_t idx, const T* xs) {
+  if (L.held && L.held[idx]) return T(0);  // a coarse held point
   T num = L.b[idx], den = T(1);
   for (int d = 0; d < L.g.ndim; ++d) {
     const int64_t st = stride_of(L.g, d);
@@ -175,6 +176,7 @@ template <typename T>
 __device__ __forceinline__ T residual_value(const LevelView<T>& L,
                                             const int c[3], int64_t idx) {
   const T xi = L.x[idx];
+  if (L.held && L.held[idx]) return T(0);  // a coarse held point
   T ax = xi;
   for (int d = 0; d < L.g.ndim; ++d) {
     const int64_t st = stride_of(L.g, d);
@@ -340,10 +342,14 @@ struct CoefOut {
   double* copy_dst;
   double* partials;
   Control* ctrl;
-  // with Dirichlet walls (A.g.dirw): their diagonal term and the right-hand
-  // side E^n + sum alpha_w E_w (both null without such walls)
+  // the finest level's own right-hand side (null: b is E^n itself), with
+  // Dirichlet walls (A.g.dirw) E^n + sum alpha_w E_w and their diagonal
+  // term sd (null without such walls), and with held cells (mask `held`,
+  // null without them) the prescribed value `hold` in the held cells
   double* sd;
   double* rhs;
+  const uint8_t* held;
+  const double* hold;
 };
 
 // One cell's face coefficients (and its copy of E); returns E^2 and sets
@@ -374,24 +380,28 @@ __device__ __forceinline__ double coef_cell(const CoefArgs& A,
   }
   const double Ei = E[idx];
   if (O.copy_dst) O.copy_dst[idx] = Ei;
-  if (O.sd) {
+  if (O.rhs) {
     // Dirichlet walls: the wall face lies half a cell away with this
     // cell's D, alpha_w = 2 dt D / dx^2 on the diagonal, alpha_w E_w on the
-    // right-hand side, whose square norm is then the stop test's |b|^2
+    // right-hand side; a held cell's right-hand side is its prescribed
+    // value (its row is x = b).  The square norm of this b is the stop
+    // test's |b|^2.
     double sd = 0.0, bw = 0.0;
-    for (int d = 0; d < A.g.ndim; ++d) {
-      const double aw = 2.0 * A.dt * D0 / (A.dx[d] * A.dx[d]);
-      if ((A.g.dirw[d] & 1) && c[d] == 0) {
-        sd += aw;
-        bw += aw * A.wall[d][0];
+    if (O.sd) {
+      for (int d = 0; d < A.g.ndim; ++d) {
+        const double aw = 2.0 * A.dt * D0 / (A.dx[d] * A.dx[d]);
+        if ((A.g.dirw[d] & 1) && c[d] == 0) {
+          sd += aw;
+          bw += aw * A.wall[d][0];
+        }
+        if ((A.g.dirw[d] & 2) && c[d] == A.g.n[d] - 1) {
+          sd += aw;
+          bw += aw * A.wall[d][1];
+        }
       }
-      if ((A.g.dirw[d] & 2) && c[d] == A.g.n[d] - 1) {
-        sd += aw;
-        bw += aw * A.wall[d][1];
-      }
+      O.sd[idx] = sd;
     }
-    const double bi = Ei + bw;
-    O.sd[idx] = sd;
+    const double bi = (O.held && O.held[idx]) ? O.hold[idx] : Ei + bw;
     O.rhs[idx] = bi;
     return bi * bi;
   }

@@ -33,6 +33,9 @@ struct LevelView {
   // Dirichlet walls' diagonal term per cell (null without such walls): the
   // operator is (1 + sd) x + sum_f alpha_f (x - x_f)
   const T* sd;
+  // coarse levels with held cells below them (null otherwise): nonzero
+  // where some child is held; such a cell's correction stays 0
+  const uint8_t* held;
 };
 
 // Device control block of one solve: norms, counters and the stop flag
@@ -94,13 +97,30 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s, int* nblocks = nullptr,
                        double* dscr = nullptr, double* sd = nullptr,
-                       double* rhs = nullptr);
-// Dirichlet walls (a.g.dirw): with sd and rhs the coefficient stage also
-// writes each cell's wall diagonal term and the right-hand side E^n +
-// sum alpha_w E_w (one-pass kernels); launch_coarsen_sd carries the wall
-// term to a coarse level.
+                       double* rhs = nullptr, const uint8_t* held = nullptr,
+                       const double* hold = nullptr);
+// With rhs the coefficient stage also writes the finest level's own
+// right-hand side (one-pass kernels): with sd each cell's Dirichlet-wall
+// diagonal term (0 off the walls of a.g.dirw) and E^n + sum alpha_w E_w;
+// with held cells (mask `held`) the prescribed value `hold` in them.
+// launch_coarsen_sd carries the diagonal term to a coarse level.
 hipError_t launch_coarsen_sd(const Geom& fine, const Geom& coarse,
                              const double* sdf, double* sdc, hipStream_t s);
+// Held cells eliminated from the free cells' rows, after the coefficient
+// stage: launch_held_fold moves each free cell's faces to held neighbours
+// onto its diagonal (sd) and their held values times alpha onto its
+// right-hand side (rhs), and leaves the per-block sums of rhs^2 in
+// partials (*nblocks of them); launch_held_cut then zeroes every face
+// that touches a held cell, so a held row is x = b = E_hold.
+hipError_t launch_held_fold(const Geom& g, double* const a[3],
+                            const uint8_t* held, const double* hold,
+                            double* sd, double* rhs, double* partials,
+                            int* nblocks, hipStream_t s);
+hipError_t launch_held_cut(const Geom& g, double* const a[3],
+                           const uint8_t* held, hipStream_t s);
+// Coarse held mask: nonzero where some child is held.
+hipError_t launch_coarsen_held(const Geom& fine, const Geom& coarse,
+                               const uint8_t* hf, uint8_t* hc, hipStream_t s);
 hipError_t launch_finalize(int mode, const double* partials, int count,
                            Control* ctrl, hipStream_t s);
 hipError_t launch_exchange(int64_t N, double dt, double c, double a_rad,

@@ -170,7 +170,8 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
                        const double* kappa, double* const a64[3],
                        float* const a32[3], double* copy_dst, double* partials,
                        Control* ctrl, hipStream_t s, int* nblocks,
-                       double* dscr, double* sd, double* rhs) {
+                       double* dscr, double* sd, double* rhs,
+                       const uint8_t* held, const double* hold) {
   CoefOut O;
   for (int d = 0; d < 3; ++d) {
     O.a64[d] = a64[d];
@@ -181,7 +182,9 @@ hipError_t launch_coef(const CoefArgs& a, const double* E, const double* rho,
   O.ctrl = ctrl;
   O.sd = sd;
   O.rhs = rhs;
-  if (sd) dscr = nullptr;  // the one-pass kernels write the wall terms
+  O.held = held;
+  O.hold = hold;
+  if (rhs) dscr = nullptr;  // the one-pass kernels write the own b
   if (fits3(a.g)) {
     if (nblocks) *nblocks = (int)blocks3(a.g);
     const dim3 grid = grid3(a.g.n[0], a.g.n[1], a.g.n[2]);
@@ -255,6 +258,122 @@ hipError_t launch_coarsen_sd(const Geom& fine, const Geom& coarse,
   return hipGetLastError();
 }
 
+// Held cells (an interior boundary with prescribed new values) eliminated
+// from the free cells' rows: a free cell's face to a held neighbour goes
+// onto its diagonal and the neighbour's held value times that face onto its
+// right-hand side, exactly as a Dirichlet wall at the neighbour's centre.
+// Each thread writes its own cell only (the faces are read here and cut by
+// the next kernel), so the two kernels need no ordering inside a launch.
+__global__ void __launch_bounds__(kBlock)
+    k_held_fold(Geom g, const double* __restrict__ a0,
+                const double* __restrict__ a1, const double* __restrict__ a2,
+                const uint8_t* __restrict__ held,
+                const double* __restrict__ hold, double* __restrict__ sd,
+                double* __restrict__ rhs, double* __restrict__ partials) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double b2 = 0.0;
+  if (idx < g.N) {
+    double bi = rhs[idx];
+    if (!held[idx]) {
+      const double* a[3] = {a0, a1, a2};
+      int c[3];
+      coords(g, idx, c);
+      double s = 0.0, add = 0.0;
+      for (int d = 0; d < g.ndim; ++d) {
+        const int64_t st = stride_of(g, d);
+        int64_t nl, nu;
+        double al, au;
+        lower_nb(g, a[d], d, c[d], idx, st, nl, al);
+        upper_nb(g, a[d], d, c[d], idx, st, nu, au);
+        if (held[nl]) {
+          s += al;
+          add += al * hold[nl];
+        }
+        if (held[nu]) {
+          s += au;
+          add += au * hold[nu];
+        }
+      }
+      sd[idx] += s;
+      bi += add;
+      rhs[idx] = bi;
+    } else {
+      sd[idx] = 0.0;  // a held row is x = E_hold, walls or not
+    }
+    b2 = bi * bi;
+  }
+  const double t = block_sum<kBlock>(b2, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Zero every face touching a held cell (each thread its own upper faces).
+__global__ void __launch_bounds__(kBlock)
+    k_held_cut(Geom g, double* __restrict__ a0, double* __restrict__ a1,
+               double* __restrict__ a2, const uint8_t* __restrict__ held) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= g.N) return;
+  double* a[3] = {a0, a1, a2};
+  int c[3];
+  coords(g, idx, c);
+  for (int d = 0; d < g.ndim; ++d) {
+    const int64_t st = stride_of(g, d);
+    int64_t nu;
+    double au;
+    upper_nb(g, (const double*)a[d], d, c[d], idx, st, nu, au);
+    if (held[idx] || held[nu]) a[d][idx] = 0.0;
+  }
+}
+
+hipError_t launch_held_fold(const Geom& g, double* const a[3],
+                            const uint8_t* held, const double* hold,
+                            double* sd, double* rhs, double* partials,
+                            int* nblocks, hipStream_t s) {
+  *nblocks = blocks_for(g.N);
+  hipLaunchKernelGGL(k_held_fold, dim3(*nblocks), dim3(kBlock), 0, s, g, a[0],
+                     a[1], a[2], held, hold, sd, rhs, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_held_cut(const Geom& g, double* const a[3],
+                           const uint8_t* held, hipStream_t s) {
+  hipLaunchKernelGGL(k_held_cut, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g,
+                     a[0], a[1], a[2], held);
+  return hipGetLastError();
+}
+
+// Held points of a coarse level: a coarse cell with any held child.  The
+// coarse faces come from the finest level's faces before the cut, so a
+// free coarse cell next to such a point couples to it as to a Dirichlet
+// point of zero correction, which keeps the coarse operator as stiff as
+// the fine one near the held cells.
+__global__ void __launch_bounds__(kBlock)
+    k_coarsen_held(Geom F, Geom C, const uint8_t* __restrict__ hf,
+                   uint8_t* __restrict__ hc) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= C.N) return;
+  int c[3];
+  coords(C, idx, c);
+  const int nd = F.ndim;
+  const int o1 = nd > 1 ? 2 : 1, o2 = nd > 2 ? 2 : 1;
+  bool any = false;
+  for (int q2 = 0; q2 < o2; ++q2)
+    for (int q1 = 0; q1 < o1; ++q1)
+      for (int q0 = 0; q0 < 2; ++q0) {
+        const int f0 = 2 * c[0] + q0, f1 = nd > 1 ? 2 * c[1] + q1 : 0;
+        const int f2 = nd > 2 ? 2 * c[2] + q2 : 0;
+        any = any || hf[f0 + (int64_t)F.n[0] * (f1 + (int64_t)F.n[1] * f2)];
+      }
+  hc[idx] = any ? 1 : 0;
+}
+
+hipError_t launch_coarsen_held(const Geom& fine, const Geom& coarse,
+                               const uint8_t* hf, uint8_t* hc, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen_held, dim3(blocks_for(coarse.N)), dim3(kBlock),
+                     0, s, fine, coarse, hf, hc);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // multigrid, one launch per phase (1D/3D levels and the reference path)
 // ---------------------------------------------------------------------------
@@ -285,7 +404,7 @@ hipError_t launch_resid_norm(const LevelView<T>& L, double* partials,
     // 3D FP64: the residual kernel of the 3D launch grid, without its FP32
     // output (same residual per cell); a level with Dirichlet walls takes
     // the generic kernel (residual_value has their diagonal term)
-    if (fits3(L.g) && !L.sd) {
+    if (fits3(L.g) && !L.sd && !L.held) {
       *nblocks = (int)blocks3(L.g);
       hipLaunchKernelGGL(k_resid_to32_3d, grid3(L.g.n[0], L.g.n[1], L.g.n[2]),
                          dim3(k3T), 0, s, L, (float*)nullptr, partials, ctrl);
@@ -724,8 +843,9 @@ hipError_t launch_resid_restrict(const LevelView<T>& fine,
                                  const LevelView<T>& coarse, double* partials,
                                  int* nblocks, const Control* ctrl,
                                  hipStream_t s) {
-  // the z-marching kernel has no Dirichlet diagonal term
-  const int zc = fits3(fine.g) && !fine.sd ? rr3_chunk(fine.g) : 0;
+  // the z-marching kernel has no Dirichlet diagonal term and no held cells
+  const int zc =
+      fits3(fine.g) && !fine.sd && !fine.held ? rr3_chunk(fine.g) : 0;
   if (zc > 0) {
     const int gx = (fine.g.n[0] + 63) / 64, gy = (fine.g.n[1] + kRRY - 1) / kRRY;
     const int gz = (fine.g.n[2] + zc - 1) / zc;

@@ -40,7 +40,7 @@ FLD_GUESS_EVERY_STEP = 1
 EXPORTED = [
     "fld_params_default", "fld_workspace_bytes", "fld_setup", "fld_step",
     "fld_step_noalloc", "fld_exchange", "fld_opacity_powerlaw",
-    "fld_explicit_sources",
+    "fld_explicit_sources", "fld_set_held",
     "fld_kernel_timing_enable",
     "fld_kernel_timing_read", "fld_destroy", "fld_status_str",
     "fld_last_error", "fld_autotune", "fld_tile_shape_name",
@@ -64,6 +64,7 @@ class fld_params(ctypes.Structure):
         ("guess_policy", ctypes.c_int32), ("krylov", ctypes.c_int32),
         ("bc_value_lo", ctypes.c_double * 3),
         ("bc_value_hi", ctypes.c_double * 3),
+        ("held_cells", ctypes.c_int32),
     ]
 
 
@@ -117,6 +118,8 @@ def load(path=LIB_PATH):
     lib.fld_step_noalloc.restype = ctypes.c_int
     lib.fld_explicit_sources.argtypes = [V, V, V, V, V, V, V, V, V]
     lib.fld_explicit_sources.restype = ctypes.c_int
+    lib.fld_set_held.argtypes = [V, V, V]
+    lib.fld_set_held.restype = ctypes.c_int
     lib.fld_exchange.argtypes = [V, D, V, V, V, V]
     lib.fld_exchange.restype = ctypes.c_int
     lib.fld_opacity_powerlaw.argtypes = [V, V, V, D, D, D, D, D, V]
@@ -289,6 +292,26 @@ def fld_explicit_sources(ctx, rho, kappa, E, v=None, f_r=None, work=None,
         vp, fp, opt(work, "work"), opt(tiring, "tiring"), opt(fedd, "fedd"))
     if check:
         _check(ctx.ptr, st)
+    return st
+
+
+def fld_set_held(ctx, mask, E_hold, check=True):
+    """Held cells of a context set up with held_cells = 1: `mask` a uint8
+    device tensor (nonzero = held), `E_hold` a float64 device tensor of the
+    same cells, or both None to clear.  The library keeps the pointers, so
+    the context keeps the tensors alive until the next call."""
+    import torch
+    n = ctx.cells
+    if mask is None and E_hold is None:
+        mp = hp = None
+    else:
+        mp = _ptr(mask, "mask", n, torch.uint8)
+        hp = _ptr(E_hold, "E_hold", n, torch.float64)
+    st = load().fld_set_held(ctx.ptr, mp, hp)
+    if check:
+        _check(ctx.ptr, st)
+    if st == FLD_OK:
+        ctx.held = (mask, E_hold)
     return st
 
 

@@ -24,10 +24,11 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
                 precision="fp64", guess="prev", rtol=1e-8, max_cycles=50,
                 pre_smooth=2, post_smooth=2, ir_inner=0, coarse_pre_smooth=0,
                 coarse_post_smooth=0, guess_policy="adaptive", krylov=False,
-                dirichlet=None):
+                dirichlet=None, held_cells=False):
     """`bc`: "periodic" or "neumann" per dimension; `dirichlet`: optional
     {(d, side): E_w} (side 0 the lower wall of dimension d, 1 the upper)
-    turning those walls of non-periodic dimensions into Dirichlet walls."""
+    turning those walls of non-periodic dimensions into Dirichlet walls;
+    `held_cells`: the context takes held cells (fld.fld_set_held)."""
     n = list(n) + [1] * (3 - len(n))
     dx = list(dx) + [1.0] * (3 - len(dx))
     codes = [_BC[b] for b in bc] + [fld.FLD_BC_PERIODIC] * (3 - len(bc))
@@ -46,7 +47,8 @@ def make_params(ndim, n, dx, bc, c=1.0, a_rad=1.0, gamma=5.0 / 3.0,
         post_smooth=post_smooth, ir_inner=ir_inner,
         coarse_pre_smooth=coarse_pre_smooth,
         coarse_post_smooth=coarse_post_smooth,
-        guess_policy=_POLICY[guess_policy], krylov=int(bool(krylov)))
+        guess_policy=_POLICY[guess_policy], krylov=int(bool(krylov)),
+        held_cells=int(bool(held_cells)))
 
 
 class Stepper:

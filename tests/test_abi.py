@@ -172,6 +172,34 @@ def test_dirichlet_validation():
     assert fld.fld_workspace_bytes(p) > 0
 
 
+def test_held_cells_validation():
+    """Held cells (fld_set_held): held_cells 0 or 1, an FP64 V-cycle solve,
+    not batched; the workspace grows by the coarse levels' masks."""
+    lib = fld.load()
+    out = ctypes.c_void_p()
+    good = dict(ndim=2, n=(32, 32, 1), dx=(1 / 32, 1 / 32, 1),
+                bc_lo=(0, 1, 0), bc_hi=(0, 1, 0), held_cells=1)
+    p = fld.fld_params_default(**good)
+    p0 = fld.fld_params_default(**dict(good, held_cells=0))
+    assert fld.fld_workspace_bytes(p) > fld.fld_workspace_bytes(p0) > 0
+    for kw in [dict(good, held_cells=2), dict(good, krylov=1),
+               dict(good, precision=fld.FLD_PREC_FP32_IR),
+               dict(good, guess=fld.FLD_GUESS_LEARNED)]:
+        p = fld.fld_params_default(**kw)
+        assert fld.fld_workspace_bytes(p) == 0, kw
+        st = lib.fld_setup(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
+                           None, ctypes.byref(out))
+        assert st == fld.FLD_ERR_INVALID_ARG, kw
+    # no context: fld_step_noalloc and the batch take no held cells
+    p = fld.fld_params_default(**good)
+    st = lib.fld_step_noalloc(ctypes.byref(p), ctypes.c_double(0.1), None,
+                              None, None, None, None, None)
+    assert st == fld.FLD_ERR_INVALID_ARG
+    assert "held" in lib.fld_last_error(None).decode()
+    assert fld.fld_workspace_bytes_batch([p, p]) == 0
+    assert lib.fld_set_held(None, None, None) == fld.FLD_ERR_INVALID_ARG
+
+
 def test_status_strings():
     assert fld.status_str(fld.FLD_OK) == "FLD_OK"
     assert fld.status_str(fld.FLD_ERR_NOT_CONVERGED) == "FLD_ERR_NOT_CONVERGED"
