@@ -263,6 +263,63 @@ fld_status fld_step_noalloc(const fld_params* p, double dt, const double* rho,
 fld_status fld_set_held(fld_ctx* ctx, const uint8_t* mask,
                         const double* E_hold);
 
+/* ---- Block-adaptive 2D grids ----------------------------------------
+ * The backward-Euler diffusion step (eq. mhd_r_e, the implicit part of
+ * Sect. 3) on a block-adaptive grid, as MPI-AMRVAC runs it (Sect. 3, 4.1):
+ * a base grid of n[0] x n[1] cells (spacing dx[0], dx[1]) tiled by
+ * `block` x `block` blocks, of which the listed ones are refined into
+ * 2 block x 2 block fine cells of half the spacing.  The unknowns are the
+ * leaf cells (base cells outside refined blocks, all fine cells).  The
+ * paper does not give the discretisation at a block edge; here:
+ * - D on each level from that level's view of E, rho, kappa: the fine
+ *   level sees the fine cells where refined and each base value copied to
+ *   its four fine cells elsewhere; the base level sees the base cells and,
+ *   where refined, the mean of the four fine children; limiter, five-point
+ *   gradient and walls as on a uniform grid of the level's spacing;
+ * - faces between two leaf cells of one level as on a uniform grid;
+ * - a face between a fine leaf cell f and a base leaf cell c: the flux
+ *   between the two centres, 3/2 fine spacings apart, beta (x_f - x_c) with
+ *   beta = (2/3) dt D_face / h_f^2 on the fine row, and beta / 4 (x_c -
+ *   x_f) from each of the two fine cells along the face on the base row
+ *   (conservative; the system is symmetric with volume weights).
+ * The solve is flexible conjugate gradients in the volume-weighted product,
+ * preconditioned by a two-level multigrid cycle (fine red-black
+ * Gauss-Seidel sweeps, pre_smooth before and post_smooth after, at least
+ * one each, around one V-cycle of the base grid's own multigrid); it stops
+ * at |b - A x|_V / |b|_V <= rtol (volume-weighted 2-norms) or after
+ * max_cycles iterations.
+ * params: ndim 2, precision FP64, guess E^n or zero, krylov 0, periodic or
+ * zero-gradient walls, n[0] and n[1] >= 4 and multiples of block (>= 2).
+ * blocks_xy: host array of nblocks (bx, by) pairs (block coordinates, x
+ * first), distinct, inside the base grid; refined block k holds fine
+ * cells k * (2 block)^2 ... in the fine arrays, row-major (y, x) inside.
+ * Base arrays: n[0] * n[1] doubles, x fastest (the values of cells under
+ * refined blocks are not read; on output they hold the mean of their four
+ * fine children).  Fine arrays: nblocks * (2 block)^2 doubles.  All device
+ * pointers; E_*_out may equal E_*_in.  Workspace: device memory of
+ * fld_amr_workspace_bytes (0 for invalid arguments), 256-byte aligned,
+ * owned by the caller.  fld_amr_step blocks until the solve ends (the
+ * Krylov scalars are summed on the host); stats as fld_step's (cycles and
+ * outer_iters: iterations).  Errors: FLD_ERR_INVALID_ARG, FLD_ERR_WORKSPACE,
+ * FLD_ERR_NONPHYSICAL, FLD_ERR_NOT_CONVERGED (last iterate returned),
+ * FLD_ERR_DEVICE; the message is read by fld_amr_last_error. */
+typedef struct fld_amr_ctx fld_amr_ctx;
+
+size_t fld_amr_workspace_bytes(const fld_params* p, int32_t block,
+                               const int32_t* blocks_xy, int32_t nblocks);
+fld_status fld_amr_setup(const fld_params* p, int32_t block,
+                         const int32_t* blocks_xy, int32_t nblocks,
+                         void* workspace, size_t ws_bytes, void* hip_stream,
+                         fld_amr_ctx** out);
+fld_status fld_amr_step(fld_amr_ctx* ctx, double dt, const double* rho_base,
+                        const double* kappa_base, const double* E_base_in,
+                        double* E_base_out, const double* rho_fine,
+                        const double* kappa_fine, const double* E_fine_in,
+                        double* E_fine_out, fld_stats* stats);
+/* Last error of a context, or with NULL of the last failed set-up. */
+const char* fld_amr_last_error(const fld_amr_ctx* ctx);
+void fld_amr_destroy(fld_amr_ctx* ctx);
+
 /* Implicit gas-radiation exchange (eqs. heating, qdot) for one step dt:
  * per cell, with beta = dt c kappa rho and S = E + e_int,
  *   e' solves a4 e'^4 + (1 + beta) e' = e_int + beta S,

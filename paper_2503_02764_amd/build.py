@@ -21,7 +21,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["fld_kernels.hip", "fld_tile2d.hip", "fld_tail.hip", "fld_tail2d.hip",
            "fld_coef2d.hip", "fld_coarsen2d.hip", "fld_sweep3d.hip", "fld_batch.hip",
            "fld_explicit.hip", "fld_krylov.hip", "fld_level.hip", "fld_tile3d.hip",
-           "fld_unet.hip", "fld_unet_net.cpp", "fld_capi.cpp"]
+           "fld_unet.hip", "fld_unet_net.cpp", "fld_capi.cpp", "fld_amr.hip",
+           "fld_amr.cpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

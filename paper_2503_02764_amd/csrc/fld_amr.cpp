@@ -1,0 +1,425 @@
+// Block-adaptive 2D step (include/fld.h, fld_amr_*): a base grid and one
+// level of refined blocks, the backward-Euler diffusion of eq. mhd_r_e on
+// the leaf cells (Sect. 3 solves it by multigrid on MPI-AMRVAC's
+// block-adaptive grids).
+//
+// The composite operator (fld_amr.hip) is symmetric in the volume-weighted
+// inner product, so the solve is conjugate gradients in that product,
+// flexible (one previous direction) because its preconditioner is a
+// multigrid cycle over the two levels:
+//   1. Gauss-Seidel sweeps (red-black) on the fine cells for A z = r from
+//      z = 0, the base cells' z held at 0;
+//   2. the base grid's right-hand side: a base leaf cell's residual with
+//      the fine correction's flux across the block edges, a covered cell's
+//      the mean of its children's residuals;
+//   3. one V-cycle of the base grid's own multigrid (a single-grid context,
+//      its faces from the base view of E) for the base correction;
+//   4. the base correction prolonged (bilinear) onto the fine cells, then
+//      the sweeps of 1 in reverse colour order with the base values fixed.
+// The stop test is the volume-weighted relative residual |r|_V / |b|_V;
+// the scalars of each iteration are summed on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fld.h"
+#include "fld_amr.h"
+#include "fld_hooks.h"
+
+using namespace fld;
+
+struct fld_amr_ctx {
+  AmrGeom G{};
+  AmrPhys P{};
+  fld_params p{};
+  fld_ctx* base = nullptr;
+  hipStream_t stream = nullptr;
+  int* bmap = nullptr;
+  int* bxy = nullptr;
+  double *Ev = nullptr, *rv = nullptr, *kv = nullptr;
+  double *Db = nullptr, *Df = nullptr, *cf = nullptr, *rhs = nullptr;
+  double *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr;
+  double *p2[2] = {}, *q2[2] = {};
+  double* partials = nullptr;
+  int* bad = nullptr;
+  std::vector<double> host_part;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_amr_err;
+
+fld_status amr_fail(fld_amr_ctx* c, fld_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  g_amr_err = buf;
+  return st;
+}
+
+#define AMR_HIP(c, expr)                                                    \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return amr_fail(c, FLD_ERR_DEVICE, "%s: %s", #expr,                  \
+                      hipGetErrorString(e_));                               \
+  } while (0)
+
+#define AMR_TRY(expr)              \
+  do {                             \
+    fld_status s_ = (expr);        \
+    if (s_ != FLD_OK) return s_;   \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// The base grid's own context: FP64 V-cycles, zero guess (it only ever
+// runs as the preconditioner's base solve).
+fld_params base_params(const fld_params& p) {
+  fld_params q = p;
+  q.guess = FLD_GUESS_ZERO;
+  q.precision = FLD_PREC_FP64;
+  q.krylov = 0;
+  q.held_cells = 0;
+  return q;
+}
+
+std::string validate_amr(const fld_params* p, int32_t block,
+                         const int32_t* blocks_xy, int32_t nblocks) {
+  if (!p) return "params is NULL";
+  if (p->ndim != 2) return "the block-adaptive step is 2D (ndim = 2)";
+  if (p->precision != FLD_PREC_FP64) return "precision must be FP64";
+  if (p->guess != FLD_GUESS_PREV && p->guess != FLD_GUESS_ZERO)
+    return "guess must be E^n or zero";
+  if (p->krylov) return "krylov must be 0 (the step is a Krylov solve)";
+  if (p->held_cells) return "no held cells on a block-adaptive grid";
+  for (int d = 0; d < 2; ++d)
+    if (p->bc_lo[d] == FLD_BC_DIRICHLET || p->bc_hi[d] == FLD_BC_DIRICHLET)
+      return "walls must be periodic or zero-gradient";
+  if (block < 2) return "block must be >= 2 base cells";
+  if (p->n[0] < 4 || p->n[1] < 4) return "the base grid needs >= 4 x 4 cells";
+  if (p->n[0] % block || p->n[1] % block)
+    return "the base grid's sides must be multiples of block";
+  if (nblocks < 0) return "nblocks must be >= 0";
+  if (nblocks > 0 && !blocks_xy) return "blocks_xy is NULL";
+  const int64_t nbx = p->n[0] / block, nby = p->n[1] / block;
+  std::vector<char> seen((size_t)(nbx * nby), 0);
+  for (int32_t k = 0; k < nblocks; ++k) {
+    const int32_t bx = blocks_xy[2 * k], by = blocks_xy[2 * k + 1];
+    if (bx < 0 || by < 0 || bx >= nbx || by >= nby)
+      return "a refined block lies outside the base grid";
+    char& s = seen[(size_t)(by * nbx + bx)];
+    if (s) return "a block is listed twice";
+    s = 1;
+  }
+  return "";
+}
+
+struct AmrPlan {
+  size_t base_ws = 0, bmap = 0, bxy = 0, views = 0, Db = 0, Df = 0, cf = 0;
+  size_t rhs = 0, vec = 0, partials = 0, bad = 0, total = 0;
+  int64_t Nb = 0, Nf = 0, nvec = 0;
+  int dot_blocks = 0;
+};
+
+AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nblocks) {
+  AmrPlan P;
+  P.Nb = p.n[0] * p.n[1];
+  P.Nf = (int64_t)nblocks * 4 * block * block;
+  P.nvec = P.Nb + P.Nf;
+  P.dot_blocks = (int)((P.nvec + 255) / 256);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return r;
+  };
+  const fld_params bp = base_params(p);
+  P.base_ws = take(fld_workspace_bytes(&bp));
+  const int64_t nbb = (p.n[0] / block) * (p.n[1] / block);
+  P.bmap = take((size_t)nbb * 4);
+  P.bxy = take((size_t)nblocks * 8);
+  P.views = take((size_t)P.Nb * 8 * 3);
+  P.Db = take((size_t)P.Nb * 8);
+  P.Df = take((size_t)P.Nf * 8);
+  P.cf = take((size_t)P.Nf * 8 * 4);
+  P.rhs = take((size_t)P.Nb * 8);
+  P.vec = take((size_t)P.nvec * 8 * 8);  // x, b, r, z, p[2], q[2]
+  P.partials = take((size_t)P.dot_blocks * 3 * 8);
+  P.bad = take(8);
+  P.total = o;
+  return P;
+}
+
+fld_status dots(fld_amr_ctx* c, int n, const double* u0, const double* v0,
+                const double* u1, const double* v1, double out[2]) {
+  AmrDots D{};
+  D.n = n;
+  D.u[0] = u0;
+  D.v[0] = v0;
+  D.u[1] = u1;
+  D.v[1] = v1;
+  const int nb = amr_dot_blocks(c->G);
+  AMR_HIP(c, amr_dots(c->G, D, c->partials, c->stream));
+  c->host_part.resize((size_t)nb * n);
+  AMR_HIP(c, hipMemcpyAsync(c->host_part.data(), c->partials,
+                            sizeof(double) * nb * n, hipMemcpyDeviceToHost,
+                            c->stream));
+  AMR_HIP(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += c->host_part[(size_t)k * nb + i];
+    out[k] = s;
+  }
+  return FLD_OK;
+}
+
+// z = M r (the two-level cycle of the file comment)
+fld_status precondition(fld_amr_ctx* c, const double* r, double* z) {
+  const AmrGeom& G = c->G;
+  hipStream_t s = c->stream;
+  AMR_HIP(c, hipMemsetAsync(z, 0, sizeof(double) * (G.Nb + G.Nf), s));
+  const int pre = std::max(c->p.pre_smooth, 1);
+  const int post = std::max(c->p.post_smooth, 1);
+  for (int k = 0; k < pre; ++k)
+    for (int colour = 0; colour < 2; ++colour)
+      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s));
+  AMR_HIP(c, amr_base_rhs(G, c->cf, r, z, c->rhs, s));
+  const fld_status st = precond_vcycle(c->base, c->rhs, z);
+  if (st != FLD_OK)
+    return amr_fail(c, st, "base V-cycle: %s", ctx_error(c->base));
+  AMR_HIP(c, amr_prolong(G, z, s));
+  for (int k = 0; k < post; ++k)
+    for (int colour = 1; colour >= 0; --colour)
+      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s));
+  AMR_HIP(c, amr_zero_covered(G, z, s));
+  return FLD_OK;
+}
+
+fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
+                     const double* kap_b, const double* E_b,
+                     double* E_b_out, const double* rho_f,
+                     const double* kap_f, const double* E_f,
+                     double* E_f_out, fld_stats* stats) {
+  const AmrGeom& G = c->G;
+  hipStream_t s = c->stream;
+  const int64_t n = G.Nb + G.Nf;
+  // coefficients: views, D on both levels, fine faces, base faces
+  AMR_HIP(c, amr_views(G, E_b, rho_b, kap_b, E_f, rho_f, kap_f, c->Ev, c->rv,
+                       c->kv, s));
+  AMR_HIP(c, hipMemsetAsync(c->bad, 0, sizeof(int), s));
+  AMR_HIP(c, amr_coefficients(G, c->P, dt, c->Ev, c->rv, c->kv, E_f, rho_f,
+                              kap_f, c->Db, c->Df, c->cf, c->bad, s));
+  int bad = 0;
+  AMR_HIP(c, hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost,
+                            s));
+  AMR_HIP(c, hipStreamSynchronize(s));
+  if (stats) stats->flagged_cells = bad;
+  if (bad > 0)
+    return amr_fail(c, FLD_ERR_NONPHYSICAL,
+                    "%d cells with E <= 0, rho kappa <= 0 or non-finite", bad);
+  fld_status st = precond_begin(c->base, dt, c->Ev, c->rv, c->kv);
+  if (st != FLD_OK) return amr_fail(c, st, "base grid: %s", ctx_error(c->base));
+  const double* ax = nullptr;
+  const double* ay = nullptr;
+  base_faces(c->base, &ax, &ay);
+  // b = E^n on the leaf cells, x0 = E^n or 0, r = b - A x0
+  AMR_HIP(c, amr_pack(G, E_b, E_f, c->b, s));
+  if (c->p.guess == FLD_GUESS_ZERO) {
+    AMR_HIP(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, s));
+    AMR_HIP(c, hipMemcpyAsync(c->r, c->b, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, s));
+  } else {
+    AMR_HIP(c, hipMemcpyAsync(c->x, c->b, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, s));
+    AMR_HIP(c, amr_apply(G, ax, ay, c->cf, c->x, c->q2[0], s));
+    AMR_HIP(c, amr_axpy(n, -1.0, c->q2[0], c->b, c->r, s));
+  }
+  double d2[2];
+  AMR_TRY(dots(c, 2, c->b, c->b, c->r, c->r, d2));
+  const double bb = d2[0];
+  double res = bb > 0.0 ? std::sqrt(d2[1] / bb) : 0.0;
+  const double res0 = res;
+  int k = 0;
+  double pq_old = 0.0;
+  bool converged = !(res > c->p.rtol);
+  while (!converged && k < c->p.max_cycles) {
+    double* p = c->p2[k & 1];
+    double* p_old = c->p2[(k + 1) & 1];
+    double* q = c->q2[k & 1];
+    double* q_old = c->q2[(k + 1) & 1];
+    AMR_TRY(precondition(c, c->r, c->z));
+    if (k == 0) {
+      AMR_HIP(c, hipMemcpyAsync(p, c->z, sizeof(double) * n,
+                                hipMemcpyDeviceToDevice, s));
+    } else {
+      AMR_TRY(dots(c, 1, c->z, q_old, nullptr, nullptr, d2));
+      AMR_HIP(c, amr_axpy(n, -d2[0] / pq_old, p_old, c->z, p, s));
+    }
+    AMR_HIP(c, amr_apply(G, ax, ay, c->cf, p, q, s));
+    AMR_TRY(dots(c, 2, c->r, p, p, q, d2));
+    const double alpha = d2[0] / d2[1];
+    pq_old = d2[1];
+    AMR_HIP(c, amr_axpy(n, alpha, p, c->x, c->x, s));
+    AMR_HIP(c, amr_axpy(n, -alpha, q, c->r, c->r, s));
+    AMR_TRY(dots(c, 1, c->r, c->r, nullptr, nullptr, d2));
+    res = std::sqrt(d2[0] / bb);
+    ++k;
+    converged = !(res > c->p.rtol);
+    if (!std::isfinite(res)) break;
+  }
+  precond_end(c->base);
+  AMR_HIP(c, amr_unpack(G, c->x, E_b_out, E_f_out, s));
+  AMR_HIP(c, hipStreamSynchronize(s));
+  if (stats) {
+    stats->cycles = k;
+    stats->outer_iters = k;
+    stats->guess_rejected = 0;
+    stats->guess_skipped = 0;
+    stats->precond_fp64 = 1;
+    stats->rel_res_initial = res0;
+    stats->rel_res_final = res;
+  }
+  if (!converged)
+    return amr_fail(c, FLD_ERR_NOT_CONVERGED,
+                    "relative residual %.3e > rtol %.3e after %d iterations",
+                    res, c->p.rtol, k);
+  return FLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fld_amr_workspace_bytes(const fld_params* p, int32_t block,
+                               const int32_t* blocks_xy, int32_t nblocks) {
+  if (!validate_amr(p, block, blocks_xy, nblocks).empty()) return 0;
+  const fld_params bp = base_params(*p);
+  if (fld_workspace_bytes(&bp) == 0) return 0;
+  return make_amr_plan(*p, block, nblocks).total;
+}
+
+fld_status fld_amr_setup(const fld_params* p, int32_t block,
+                         const int32_t* blocks_xy, int32_t nblocks,
+                         void* workspace, size_t ws_bytes, void* hip_stream,
+                         fld_amr_ctx** out) {
+  if (!out) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate_amr(p, block, blocks_xy, nblocks);
+  if (!why.empty()) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "%s", why.c_str());
+  const AmrPlan P = make_amr_plan(*p, block, nblocks);
+  if (!workspace || ws_bytes < P.total)
+    return amr_fail(nullptr, FLD_ERR_WORKSPACE,
+                    "workspace of %zu bytes needed", P.total);
+  if ((uintptr_t)workspace % kAlign)
+    return amr_fail(nullptr, FLD_ERR_WORKSPACE, "workspace not 256-aligned");
+  char* w = (char*)workspace;
+  fld_amr_ctx* c = new fld_amr_ctx();
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  const fld_params bp = base_params(*p);
+  fld_status st = fld_setup(&bp, w + P.base_ws, fld_workspace_bytes(&bp),
+                            hip_stream, &c->base);
+  if (st != FLD_OK) {
+    delete c;
+    return amr_fail(nullptr, st, "base grid set-up: %s",
+                    fld_last_error(nullptr));
+  }
+  AmrGeom& G = c->G;
+  G.nx = (int)p->n[0];
+  G.ny = (int)p->n[1];
+  G.b = block;
+  G.S = 2 * block;
+  G.nbx = G.nx / block;
+  G.nby = G.ny / block;
+  G.nbf = nblocks;
+  for (int d = 0; d < 2; ++d) G.per[d] = p->bc_lo[d] == FLD_BC_PERIODIC;
+  G.Nb = P.Nb;
+  G.Nf = P.Nf;
+  G.dx = p->dx[0];
+  G.dy = p->dx[1];
+  G.vb = G.dx * G.dy;
+  G.vf = 0.25 * G.vb;
+  c->bmap = (int*)(w + P.bmap);
+  c->bxy = (int*)(w + P.bxy);
+  G.bmap = c->bmap;
+  G.bxy = c->bxy;
+  c->P.c = p->c;
+  c->P.limiter = p->limiter;
+  c->P.face_mean = p->face_mean;
+  c->Ev = (double*)(w + P.views);
+  c->rv = c->Ev + P.Nb;
+  c->kv = c->rv + P.Nb;
+  c->Db = (double*)(w + P.Db);
+  c->Df = (double*)(w + P.Df);
+  c->cf = (double*)(w + P.cf);
+  c->rhs = (double*)(w + P.rhs);
+  double* v = (double*)(w + P.vec);
+  double** vecs[8] = {&c->x, &c->b, &c->r, &c->z,
+                      &c->p2[0], &c->p2[1], &c->q2[0], &c->q2[1]};
+  for (int k = 0; k < 8; ++k) *vecs[k] = v + (size_t)k * P.nvec;
+  c->partials = (double*)(w + P.partials);
+  c->bad = (int*)(w + P.bad);
+  // tables: the refined block of every base block, each block's corner
+  std::vector<int> bmap((size_t)G.nbx * G.nby, -1), bxy((size_t)2 * nblocks);
+  for (int32_t k = 0; k < nblocks; ++k) {
+    bxy[2 * k] = blocks_xy[2 * k];
+    bxy[2 * k + 1] = blocks_xy[2 * k + 1];
+    bmap[(size_t)blocks_xy[2 * k + 1] * G.nbx + blocks_xy[2 * k]] = k;
+  }
+  hipError_t e = hipMemcpyAsync(c->bmap, bmap.data(), bmap.size() * 4,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && nblocks > 0)
+    e = hipMemcpyAsync(c->bxy, bxy.data(), bxy.size() * 4,
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    fld_destroy(c->base);
+    delete c;
+    return amr_fail(nullptr, FLD_ERR_DEVICE, "table upload: %s",
+                    hipGetErrorString(e));
+  }
+  *out = c;
+  return FLD_OK;
+}
+
+fld_status fld_amr_step(fld_amr_ctx* c, double dt, const double* rho_base,
+                        const double* kappa_base, const double* E_base_in,
+                        double* E_base_out, const double* rho_fine,
+                        const double* kappa_fine, const double* E_fine_in,
+                        double* E_fine_out, fld_stats* stats) {
+  if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (!rho_base || !kappa_base || !E_base_in || !E_base_out)
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
+  if (c->G.nbf > 0 && (!rho_fine || !kappa_fine || !E_fine_in || !E_fine_out))
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
+  // in place is allowed: the inputs are read before the outputs are written
+  return amr_solve(c, dt, rho_base, kappa_base, E_base_in, E_base_out,
+                   rho_fine, kappa_fine, E_fine_in, E_fine_out, stats);
+}
+
+const char* fld_amr_last_error(const fld_amr_ctx* c) {
+  return c ? c->err.c_str() : g_amr_err.c_str();
+}
+
+void fld_amr_destroy(fld_amr_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  fld_destroy(c->base);
+  delete c;
+}
+
+}  // extern "C"

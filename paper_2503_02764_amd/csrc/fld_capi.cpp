@@ -21,6 +21,7 @@
 #include "fld.h"
 #include "fldnn.h"
 #include "fld_internal.h"
+#include "fld_hooks.h"
 #include "fld_tile2d.h"
 #include "fld_batch.h"
 #include "fld_unet.h"
@@ -1723,6 +1724,64 @@ fld_status learned_guess(fld_ctx* c, const double* rho, const double* kappa) {
 }
 
 }  // namespace
+
+}  // extern "C"
+
+// ---- hooks for the block-adaptive step (fld_hooks.h) ----
+
+fld_status fld::precond_begin(fld_ctx* c, double dt, const double* E,
+                              const double* rho, const double* kappa) {
+  if (c->mixed || c->batch || c->p.guess == FLD_GUESS_LEARNED)
+    return fail(c, FLD_ERR_INVALID_ARG, "preconditioner: an FP64 single grid");
+  const Geom& g0 = c->geom[0];
+  // no stop test: the kernels only need the control block to say running
+  HIP_TRY(c, launch_ctrl_init(c->ctrl, c->p.rtol, INT_MAX / 2, 1,
+                             c->host_ctrl_dev, c->stream));
+  CoefArgs A;
+  A.g = g0;
+  for (int d = 0; d < 3; ++d) {
+    A.dx[d] = c->p.dx[d];
+    A.gscale[d] = 1.0 / (12.0 * c->p.dx[d]);
+    A.wall[d][0] = A.wall[d][1] = 0.0;
+  }
+  A.dt = dt;
+  A.c = c->p.c;
+  A.limiter = c->p.limiter;
+  A.face_mean = c->p.face_mean;
+  c->init_fused = false;
+  if (coef2d_ok(g0)) {
+    HIP_TRY(c, launch_coef2d(A, E, rho, kappa, c->h64.a[0], c->h32.a[0],
+                             nullptr, c->partials, c->ctrl, false, c->stream));
+  } else {
+    int nb = 0;
+    HIP_TRY(c, launch_coef(A, E, rho, kappa, c->h64.a[0], c->h32.a[0],
+                           nullptr, c->partials, c->ctrl, c->stream, &nb,
+                           c->dscr));
+  }
+  FLD_TRY(coarsen_levels<double>(c, c->h64));
+  c->precond = true;
+  return FLD_OK;
+}
+
+fld_status fld::precond_vcycle(fld_ctx* c, const double* rhs, double* z) {
+  Levels<double> pre = c->h64;
+  pre.x[0] = z;
+  pre.b[0] = const_cast<double*>(rhs);
+  return vcycle<double>(c, pre, true);
+}
+
+void fld::base_faces(const fld_ctx* c, const double** ax, const double** ay) {
+  *ax = c->h64.a[0][0];
+  *ay = c->h64.a[0][1];
+}
+
+void fld::precond_end(fld_ctx* c) { c->precond = false; }
+
+hipStream_t fld::ctx_stream(const fld_ctx* c) { return c->stream; }
+
+const char* fld::ctx_error(const fld_ctx* c) { return c->err.c_str(); }
+
+extern "C" {
 
 static fld_status step_impl(fld_ctx* c, double dt, const double* rho,
                             const double* kappa, const double* E_in,

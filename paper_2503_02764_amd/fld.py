@@ -382,6 +382,115 @@ EXPORTED += ["fld_workspace_bytes_batch", "fld_setup_batch", "fld_step_batch",
              "fld_batch_set_graph"]
 
 
+# ---- block-adaptive 2D grids -------------------------------------------
+
+EXPORTED += ["fld_amr_workspace_bytes", "fld_amr_setup", "fld_amr_step",
+             "fld_amr_last_error", "fld_amr_destroy"]
+
+
+def _amr_argtypes(lib):
+    if getattr(lib, "_amr_ready", False):
+        return
+    P, V, D, I32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32
+    lib.fld_amr_workspace_bytes.argtypes = [P(fld_params), I32, V, I32]
+    lib.fld_amr_workspace_bytes.restype = ctypes.c_size_t
+    lib.fld_amr_setup.argtypes = [P(fld_params), I32, V, I32, V,
+                                  ctypes.c_size_t, V, P(V)]
+    lib.fld_amr_setup.restype = ctypes.c_int
+    lib.fld_amr_step.argtypes = [V, D, V, V, V, V, V, V, V, V, V]
+    lib.fld_amr_step.restype = ctypes.c_int
+    lib.fld_amr_last_error.argtypes = [V]
+    lib.fld_amr_last_error.restype = ctypes.c_char_p
+    lib.fld_amr_destroy.argtypes = [V]
+    lib.fld_amr_destroy.restype = None
+    lib._amr_ready = True
+
+
+def _amrlib():
+    lib = load()
+    _amr_argtypes(lib)
+    return lib
+
+
+def _blocks_arr(blocks):
+    flat = [int(v) for xy in blocks for v in xy]
+    return (ctypes.c_int32 * max(1, len(flat)))(*flat), len(blocks)
+
+
+class AmrCtx:
+    """An fld_amr_ctx* with its workspace, stream and sizes."""
+
+    def __init__(self, ptr, params, block, nblocks, workspace, stream):
+        self.ptr = ptr
+        self.params = params
+        self.block = block
+        self.nblocks = nblocks
+        self.workspace = workspace
+        self.stream = stream
+        self.base_cells = int(params.n[0] * params.n[1])
+        self.fine_cells = nblocks * 4 * block * block
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.fld_amr_destroy(self.ptr)
+            self.ptr = None
+
+
+def fld_amr_workspace_bytes(params, block, blocks):
+    arr, nb = _blocks_arr(blocks)
+    return int(_amrlib().fld_amr_workspace_bytes(ctypes.byref(params), block,
+                                                 arr, nb))
+
+
+def fld_amr_setup(params, block, blocks, workspace=None, stream=None):
+    """Context of a block-adaptive 2D grid: `blocks` lists the refined
+    base blocks as (bx, by)."""
+    import torch
+    lib = _amrlib()
+    arr, nb = _blocks_arr(blocks)
+    need = fld_amr_workspace_bytes(params, block, blocks)
+    out = ctypes.c_void_p()
+    if need == 0:
+        st = lib.fld_amr_setup(ctypes.byref(params), block, arr, nb, None, 0,
+                               None, ctypes.byref(out))
+        raise FldError(st, lib.fld_amr_last_error(None).decode())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.fld_amr_setup(ctypes.byref(params), block, arr, nb,
+                           _ptr(workspace, "workspace", dtype=torch.uint8),
+                           workspace.numel(),
+                           ctypes.c_void_p(stream.cuda_stream),
+                           ctypes.byref(out))
+    if st != FLD_OK:
+        raise FldError(st, lib.fld_amr_last_error(None).decode())
+    return AmrCtx(out, params, block, nb, workspace, stream)
+
+
+def fld_amr_step(ctx, dt, rho_b, kappa_b, E_b_in, E_b_out, rho_f, kappa_f,
+                 E_f_in, E_f_out, check=True):
+    """Block-adaptive diffusion step; returns (status, stats dict)."""
+    import torch
+    lib = _amrlib()
+    nb, nf = ctx.base_cells, ctx.fine_cells
+    f64 = torch.float64
+
+    def fine(t, name):
+        return _ptr(t, name, nf, f64) if nf else None
+    s = fld_stats()
+    st = lib.fld_amr_step(ctx.ptr, float(dt), _ptr(rho_b, "rho_b", nb, f64),
+                          _ptr(kappa_b, "kappa_b", nb, f64),
+                          _ptr(E_b_in, "E_b_in", nb, f64),
+                          _ptr(E_b_out, "E_b_out", nb, f64),
+                          fine(rho_f, "rho_f"), fine(kappa_f, "kappa_f"),
+                          fine(E_f_in, "E_f_in"), fine(E_f_out, "E_f_out"),
+                          ctypes.byref(s))
+    if check and st != FLD_OK:
+        raise FldError(st, lib.fld_amr_last_error(ctx.ptr).decode())
+    return st, s.as_dict()
+
+
 def _batch_argtypes(lib):
     P, V, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double
     VP = P(ctypes.c_void_p)

@@ -200,6 +200,29 @@ def test_held_cells_validation():
     assert lib.fld_set_held(None, None, None) == fld.FLD_ERR_INVALID_ARG
 
 
+def test_amr_validation():
+    """Block-adaptive set-up: a 2D FP64 grid whose sides are multiples of
+    the block, distinct refined blocks inside it."""
+    good = fld.fld_params_default(ndim=2, n=(32, 16, 1), dx=(1 / 32, 1 / 32, 1),
+                                  bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
+    assert fld.fld_amr_workspace_bytes(good, 8, [(1, 1), (2, 0)]) > \
+        fld.fld_amr_workspace_bytes(good, 8, []) > 0
+    assert fld.fld_amr_workspace_bytes(good, 8, [(4, 0)]) == 0   # outside
+    assert fld.fld_amr_workspace_bytes(good, 8, [(1, 1), (1, 1)]) == 0
+    assert fld.fld_amr_workspace_bytes(good, 5, []) == 0         # 32 % 5
+    assert fld.fld_amr_workspace_bytes(good, 1, []) == 0
+    for kw in [dict(ndim=3, n=(32, 16, 8)), dict(precision=1), dict(krylov=1),
+               dict(guess=fld.FLD_GUESS_LEARNED), dict(held_cells=1),
+               dict(bc_hi=(0, 2, 0), bc_value_hi=(0, 1.0, 0))]:
+        base = dict(ndim=2, n=(32, 16, 1), dx=(1 / 32, 1 / 32, 1),
+                    bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
+        base.update(kw)
+        p = fld.fld_params_default(**base)
+        assert fld.fld_amr_workspace_bytes(p, 8, []) == 0, kw
+    with pytest.raises(fld.FldError):
+        fld.fld_amr_setup(fld.fld_params_default(ndim=1, n=(32, 1, 1)), 8, [])
+
+
 def test_status_strings():
     assert fld.status_str(fld.FLD_OK) == "FLD_OK"
     assert fld.status_str(fld.FLD_ERR_NOT_CONVERGED) == "FLD_ERR_NOT_CONVERGED"

@@ -1,0 +1,181 @@
+"""Block-adaptive 2D step on the GPU (fld_amr_*) against the oracle's
+direct solve of the composite system (oracle/amr.py), through the C ABI.
+
+The solve runs to a volume-weighted relative residual of 1e-12; in that
+norm the composite operator (identity plus a positive semi-definite
+diffusion part) has eigenvalues >= 1, so the error is at most the residual
+and the leaf values must meet the oracle's to relative L2 1e-10.  Cases:
+one block, neighbouring blocks, a strip, blocks across the periodic seams
+and on the walls; all three limiters; everything refined (the uniform fine
+grid) and nothing refined (the base grid); conservation of sum V E; in
+place and from a zero guess; a 256 x 256 base with a refined band.
+"""
+import numpy as np
+import pytest
+
+from oracle import amr as M
+from oracle import fldref as F
+
+from gpu_common import announce, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(g, **kw):
+    from paper_2503_02764_amd.solver import make_params
+    bc = tuple("periodic" if b == F.PERIODIC else "neumann" for b in g.bc)
+    kw.setdefault("rtol", 1e-12)
+    kw.setdefault("max_cycles", 400)
+    return make_params(2, (g.nx, g.ny), (g.dx, g.dy), bc, c=g.c,
+                       limiter=g.limiter, face_mean=g.face_mean, **kw)
+
+
+def _medium(g, seed, contrast=1.0):
+    rng = np.random.default_rng(seed)
+    s = 2 * g.b
+    nb = len(g.blocks)
+
+    def pair(scale, amp):
+        return (scale * np.exp(amp * contrast * rng.standard_normal((g.ny, g.nx))),
+                scale * np.exp(amp * contrast * rng.standard_normal((nb, s, s))))
+    return pair(1.0, 0.3), pair(1.0, 0.4), pair(20.0, 0.8)
+
+
+def _run(g, fields, dt, **kw):
+    from paper_2503_02764_amd import fld
+    (Eb, Ef), (rb, rf), (kb, kf) = fields
+    ctx = fld.fld_amr_setup(_params(g, **kw), g.b, g.blocks)
+    out_b = dev(np.zeros_like(Eb))
+    out_f = dev(np.zeros_like(Ef)) if Ef.size else dev(np.zeros(1))[:0]
+    ef = dev(Ef) if Ef.size else dev(np.zeros(1))[:0]
+    rf_, kf_ = (dev(rf), dev(kf)) if Ef.size else (ef, ef)
+    _, stats = fld.fld_amr_step(ctx, dt, dev(rb), dev(kb), dev(Eb), out_b,
+                                rf_, kf_, ef, out_f)
+    return host(out_b), host(out_f), stats
+
+
+def _check(g, fields, dt, tol=1e-10, **kw):
+    xb, xf, stats = _run(g, fields, dt, **kw)
+    (Eb, Ef), (rb, rf), (kb, kf) = fields
+    rb_, rf_ = M.amr_step(g, Eb, rb, kb, Ef, rf, kf, dt)
+    got, ref = M.to_leaf(g, xb, xf), M.to_leaf(g, rb_, rf_)
+    assert stats["rel_res_final"] <= 1e-12, stats
+    assert rel_l2(got, ref) <= tol, (stats, rel_l2(got, ref))
+    # covered base cells: the mean of their children
+    ref_mask = g.refined()
+    np.testing.assert_allclose(xb[ref_mask], rb_[ref_mask], rtol=1e-9)
+    return got, ref, stats
+
+
+CASES = [
+    ("one", [(1, 1)], (F.PERIODIC, F.NEUMANN)),
+    ("pair", [(1, 1), (2, 1)], (F.NEUMANN, F.NEUMANN)),
+    ("strip", [(1, k) for k in range(4)], (F.NEUMANN, F.PERIODIC)),
+    ("seams", [(0, 0), (3, 0), (0, 3), (3, 3)], (F.PERIODIC, F.PERIODIC)),
+    ("walls", [(0, 1), (3, 2), (2, 0)], (F.NEUMANN, F.NEUMANN)),
+]
+
+
+@pytest.mark.parametrize("name,blocks,bc", CASES)
+@pytest.mark.parametrize("limiter", ["lp", "minerbo", "diffusion"])
+def test_amr_step_vs_oracle(name, blocks, bc, limiter):
+    g = M.AmrGrid(nx=32, ny=32, dx=1.0 / 32, dy=1.0 / 32, b=8, bc=bc,
+                  blocks=blocks, limiter=limiter)
+    announce(f"amr step {name} {limiter}")
+    _check(g, _medium(g, len(name) + len(limiter)), 0.02)
+
+
+@pytest.mark.parametrize("dt", [1e-4, 1.0])
+def test_amr_step_time_steps(dt):
+    # from nearly the identity to far beyond the diffusion time
+    g = M.AmrGrid(nx=24, ny=16, dx=1.0 / 24, dy=1.0 / 24, b=4,
+                  bc=(F.PERIODIC, F.NEUMANN),
+                  blocks=[(1, 1), (2, 1), (4, 3)], limiter="lp")
+    announce(f"amr step dt={dt}")
+    _check(g, _medium(g, 7), dt)
+
+
+def test_nothing_and_everything_refined():
+    g0 = M.AmrGrid(nx=16, ny=16, dx=1 / 16, dy=1 / 16, b=4,
+                   bc=(F.PERIODIC, F.NEUMANN), blocks=[])
+    f0 = _medium(g0, 3)
+    announce("amr nothing refined")
+    xb, _, _ = _run(g0, f0, 0.05)
+    (Eb, _), (rb, _), (kb, _) = f0
+    ref = F.diffusion_step(Eb, rb, kb, 0.05, g0.base_problem())
+    assert rel_l2(xb, ref) <= 1e-10
+    g1 = M.AmrGrid(nx=16, ny=16, dx=1 / 16, dy=1 / 16, b=4,
+                   bc=(F.PERIODIC, F.NEUMANN),
+                   blocks=[(i, j) for j in range(4) for i in range(4)])
+    f1 = _medium(g1, 4)
+    announce("amr everything refined")
+    _, xf, _ = _run(g1, f1, 0.05)
+    (_, Ef), (_, rf), (_, kf) = f1
+    z = np.zeros((32, 32))
+    full = lambda a: M.fine_to_full(g1, a, z)  # noqa: E731
+    ref = F.diffusion_step(full(Ef), full(rf), full(kf), 0.05,
+                           g1.fine_problem())
+    assert rel_l2(full(xf), ref) <= 1e-10
+
+
+def test_conservation_in_place_and_zero_guess():
+    from paper_2503_02764_amd import fld
+    g = M.AmrGrid(nx=32, ny=32, dx=1 / 32, dy=1 / 32, b=8,
+                  bc=(F.PERIODIC, F.PERIODIC), blocks=[(1, 1), (1, 2), (2, 2)],
+                  limiter="minerbo")
+    fields = _medium(g, 9)
+    (Eb, Ef), (rb, rf), (kb, kf) = fields
+    announce("amr conservation / in place / zero guess")
+    got, ref, _ = _check(g, fields, 0.05)
+    _, vol = M.assemble(g, *M.coefficients(g, Eb, rb, kb, Ef, rf, kf), 0.05)
+    e0 = M.to_leaf(g, Eb, Ef)
+    assert vol @ got == pytest.approx(vol @ e0, rel=1e-11)
+    ctx = fld.fld_amr_setup(_params(g), g.b, g.blocks)
+    eb, ef = dev(Eb), dev(Ef)
+    fld.fld_amr_step(ctx, 0.05, dev(rb), dev(kb), eb, eb, dev(rf), dev(kf),
+                     ef, ef)
+    np.testing.assert_allclose(M.to_leaf(g, host(eb), host(ef)), got,
+                               rtol=1e-13)
+    _check(g, fields, 0.05, guess="zero")
+
+
+def test_band_at_256sq():
+    # a refined band around a front of E across a 256 x 256 base (16 x 16
+    # blocks of 16 base cells; 3 rows of blocks refined)
+    nx = 256
+    blocks = [(i, j) for j in (7, 8, 9) for i in range(16)]
+    g = M.AmrGrid(nx=nx, ny=nx, dx=1 / nx, dy=1 / nx, b=16,
+                  bc=(F.PERIODIC, F.NEUMANN), blocks=blocks, limiter="lp")
+    rng = np.random.default_rng(256)
+    s = 2 * g.b
+    yb = (np.arange(nx) + 0.5) / nx
+    yf = (np.arange(2 * nx) + 0.5) / (2 * nx)
+    front = lambda y: 1.0 + 9.0 / (1.0 + np.exp((y - 0.5) / 0.02))  # noqa: E731
+    Eb = np.broadcast_to(front(yb)[:, None], (nx, nx)).copy()
+    Ef = M.full_to_fine(g, np.broadcast_to(front(yf)[:, None],
+                                           (2 * nx, 2 * nx)).copy())
+    rb = np.exp(0.3 * rng.standard_normal((nx, nx)))
+    rf = np.exp(0.3 * rng.standard_normal((len(blocks), s, s)))
+    kb = 20.0 * np.exp(0.5 * rng.standard_normal((nx, nx)))
+    kf = 20.0 * np.exp(0.5 * rng.standard_normal((len(blocks), s, s)))
+    announce("amr band 256^2")
+    _check(g, ((Eb, Ef), (rb, rf), (kb, kf)), 2e-4)
+
+
+def test_errors():
+    from paper_2503_02764_amd import fld
+    g = M.AmrGrid(nx=16, ny=16, dx=1 / 16, dy=1 / 16, b=4,
+                  bc=(F.PERIODIC, F.NEUMANN), blocks=[(1, 1)])
+    (Eb, Ef), (rb, rf), (kb, kf) = _medium(g, 2)
+    ctx = fld.fld_amr_setup(_params(g), g.b, g.blocks)
+    bad = Eb.copy()
+    bad[3, 3] = -1.0
+    announce("amr nonphysical input")
+    st, _ = fld.fld_amr_step(ctx, 0.1, dev(rb), dev(kb), dev(bad),
+                             dev(np.zeros_like(Eb)), dev(rf), dev(kf),
+                             dev(Ef), dev(np.zeros_like(Ef)), check=False)
+    assert st == fld.FLD_ERR_NONPHYSICAL
+    with pytest.raises(fld.FldError):
+        fld.fld_amr_step(ctx, -1.0, dev(rb), dev(kb), dev(Eb),
+                         dev(np.zeros_like(Eb)), dev(rf), dev(kf), dev(Ef),
+                         dev(np.zeros_like(Ef)))
