@@ -62,7 +62,7 @@ COARSE_PRE3, COARSE_POST3 = COARSE3, COARSE3
 # ones that give way to FP64 where they stall).  The comparison of every
 # variant covers the first 12 steps; the configured 50-step run covers the
 # flexible-CG variants.
-C3_STEPS, C3_CONFIG_STEPS, C4_STEPS = 12, 50, 20
+C3_STEPS, C3_CONFIG_STEPS, C4_STEPS, AMR_STEPS = 12, 50, 20, 10
 
 
 def measured_traffic(kernel, shape, nu=None):
@@ -779,6 +779,62 @@ def run_c4(steps, warmup):
     }
 
 
+def run_amr(steps, warmup):
+    """The block-adaptive 2D step: the 1024^2 Kramers / log-normal medium as
+    the base grid (16 x 16 blocks), the 1/8 of the blocks with the steepest
+    log E refined (fine fields interpolated from the base), FP64 flexible
+    CG to rel. residual 1e-8 preconditioned by fine sweeps around a base
+    V-cycle; E stepped in place, rho and kappa fixed.  Throughput counts
+    leaf cells."""
+    import numpy as np
+    import torch
+    import media
+    from paper_2503_02764_amd import fld
+    from paper_2503_02764_amd.solver import make_params
+    w = media.config_amr()
+    n, b = w["n"], w["b"]
+    leaf = n * n - len(w["blocks"]) * b * b + w["E_f"].size
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = make_params(2, (n, n), (w["dx"], w["dx"]), w["bc"], rtol=1e-8,
+                        pre_smooth=PRE, post_smooth=POST, max_cycles=200)
+        ctx = fld.fld_amr_setup(p, b, w["blocks"], stream=stream)
+        rb, kb, eb = d(w["rho_b"]), d(w["kappa_b"]), d(w["E_b"])
+        rf, kf, ef = d(w["rho_f"]), d(w["kappa_f"]), d(w["E_f"])
+        for _ in range(warmup):
+            fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf, ef, ef)
+        stream.synchronize()
+        fld.fld_amr_kernel_timing_enable(ctx, True)
+        fld.fld_amr_kernel_timing_read(ctx)
+        iters, res = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf,
+                                     ef, ef)
+            iters.append(st["cycles"])
+            res.append(st["rel_res_final"])
+        stream.synchronize()
+        secs = time.perf_counter() - t0
+        kt = fld.fld_amr_kernel_timing_read(ctx)
+    del ctx
+    torch.cuda.empty_cache()
+    value = leaf * steps / secs
+    return {"workload": w["name"], "leaf_cells": int(leaf),
+            "refined_blocks": len(w["blocks"]), "block": b, "rtol": 1e-8,
+            "steps": steps, "warmup": warmup, "value": value,
+            "ms_per_step": secs * 1e3 / steps,
+            "iterations_per_step": float(np.mean(iters)),
+            "rel_res_final_max": float(np.max(res)), "dtype": "f64",
+            "cycle": f"FCG; fine RB-GS {PRE}+{POST} around one base V-cycle",
+            "roofline": dict(_hbm_roofline(kt, "amr-1024sq-b16") or {},
+                             timed="the first fine red-black half-sweep of "
+                                   "each timed step (events in the library)")}
+
+
 def _line(metric_value, ms, args, workload, dtype, extra):
     out = {
         "metric": METRIC, "value": metric_value, "unit": "cell-updates/s",
@@ -802,7 +858,7 @@ def main():
                     help="keep the default tile shape on every level")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline variant (for profiling)")
-    ap.add_argument("--workload", choices=("all", "c2", "c3", "c4"),
+    ap.add_argument("--workload", choices=("all", "c2", "c3", "c4", "amr"),
                     default="all",
                     help="all: the headline line with the 3D and batched "
                          "configs under `configs`; c2 / c3 / c4: one workload "
@@ -874,6 +930,12 @@ def main():
               {"roofline": r["roofline"], "c3": r,
                "achievable_copy": copy_bandwidth()})
         return
+    if args.workload == "amr":
+        r = run_amr(min(args.steps, AMR_STEPS), min(args.warmup, 2))
+        args.steps, args.warmup = r["steps"], r["warmup"]
+        _line(r["value"], r["ms_per_step"], args, r["workload"], "f64",
+              {"amr": r})
+        return
     if args.workload == "c4":
         r = run_c4(min(args.steps, C4_STEPS), min(args.warmup, 1))
         args.steps, args.warmup = r["steps"], r["warmup"]
@@ -886,7 +948,8 @@ def main():
     if args.workload == "all":
         out["configs"] = {}
         for name, fn in (("c3", lambda: run_c3(C3_STEPS, 1, weights)),
-                         ("c4", lambda: run_c4(C4_STEPS, 1))):
+                         ("c4", lambda: run_c4(C4_STEPS, 1)),
+                         ("amr", lambda: run_amr(AMR_STEPS, 2))):
             try:
                 out["configs"][name] = fn()
             except Exception as exc:  # reported in the line, not hidden

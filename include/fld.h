@@ -316,6 +316,16 @@ fld_status fld_amr_step(fld_amr_ctx* ctx, double dt, const double* rho_base,
                         double* E_base_out, const double* rho_fine,
                         const double* kappa_fine, const double* E_fine_in,
                         double* E_fine_out, fld_stats* stats);
+/* Kernel timing of the block-adaptive step: with `on`, the first fine
+ * red-black half-sweep of every step (the step's dominant kernel) is
+ * bracketed by events on the context's stream; the read returns the summed
+ * milliseconds, the launch count and the algorithmic bytes of those
+ * launches (r and the four faces of half the fine cells and z of all of
+ * them read, half of z written), then resets the counters. */
+fld_status fld_amr_kernel_timing_enable(fld_amr_ctx* ctx, int32_t on);
+fld_status fld_amr_kernel_timing_read(fld_amr_ctx* ctx, double* ms_total,
+                                      int64_t* launches, double* bytes_total,
+                                      const char** kernel_name);
 /* Last error of a context, or with NULL of the last failed set-up. */
 const char* fld_amr_last_error(const fld_amr_ctx* ctx);
 void fld_amr_destroy(fld_amr_ctx* ctx);

@@ -14,6 +14,7 @@ from .generators import (  # noqa: F401
     config_c3,
     config_c4,
     config_c5_train,
+    config_amr,
     random_small_medium,
     velocity_field,
     KRAMERS,

@@ -242,3 +242,53 @@ def velocity_field(shape, ndim, seed, amplitude=0.1, ell=16.0):
     The update does not evolve v; it only differentiates it."""
     rng = np.random.default_rng(seed)
     return [amplitude * grf(tuple(shape), ell, rng) for _ in range(ndim)]
+
+
+def _bilinear_up(f):
+    """Fine-lattice values of a base field: 9/16 of the parent, 3/16 of the
+    two edge neighbours towards the fine cell, 1/16 of the corner one
+    (zero-gradient ghosts at the edges)."""
+    p = np.pad(f, 1, mode="edge")
+    ny, nx = f.shape
+    out = np.empty((2 * ny, 2 * nx))
+    for sy in (0, 1):
+        for sx in (0, 1):
+            oy, ox = (1 if sy else -1), (1 if sx else -1)
+            c = p[1:-1, 1:-1]
+            ex = p[1:-1, 1 + ox:1 + ox + nx]
+            ey = p[1 + oy:1 + oy + ny, 1:-1]
+            cr = p[1 + oy:1 + oy + ny, 1 + ox:1 + ox + nx]
+            out[sy::2, sx::2] = (9 * c + 3 * ex + 3 * ey + cr) / 16.0
+    return out
+
+
+def config_amr(n=1024, b=16, frac=0.125, seed=2, nu=100.0):
+    """The 2D n x n Kramers / log-normal medium as the base grid of a
+    block-adaptive grid (b x b blocks, Neumann walls); the fraction `frac`
+    of the blocks with the steepest mean |grad log E| refined, their fine
+    fields interpolated bilinearly from the base (rho, T, E), kappa from the
+    Kramers law on each level.  Returns a dict of the grid and fields."""
+    rho, E, e, dt = _c2_fields(n, seed, nu)
+    gamma = 5.0 / 3.0
+    T = (gamma - 1.0) * e / rho
+    gy, gx = np.gradient(np.log(E))
+    steep = np.sqrt(gx * gx + gy * gy) * n
+    nbx = n // b
+    score = steep.reshape(nbx, b, nbx, b).mean(axis=(1, 3))
+    k = int(round(frac * nbx * nbx))
+    order = np.argsort(-score.ravel(), kind="stable")[:k]
+    blocks = sorted(((int(i % nbx), int(i // nbx)) for i in order),
+                    key=lambda xy: (xy[1], xy[0]))
+    up = {name: _bilinear_up(f) for name, f in (("rho", rho), ("T", T),
+                                                ("E", E))}
+    s = 2 * b
+
+    def cut(full):
+        return np.stack([full[by * s:(by + 1) * s, bx * s:(bx + 1) * s]
+                         for bx, by in blocks])
+    rho_f, T_f, E_f = cut(up["rho"]), cut(up["T"]), cut(up["E"])
+    return dict(n=n, b=b, blocks=blocks, dx=1.0 / n, dt=dt,
+                bc=("neumann", "neumann"),
+                rho_b=rho, E_b=E, kappa_b=_kramers(rho, T, KRAMERS),
+                rho_f=rho_f, E_f=E_f, kappa_f=_kramers(rho_f, T_f, KRAMERS),
+                name=f"amr-2d-{n}sq-base-b{b}-{len(blocks)}-refined-blocks")

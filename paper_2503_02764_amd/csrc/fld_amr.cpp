@@ -50,6 +50,12 @@ struct fld_amr_ctx {
   int* bad = nullptr;
   std::vector<double> host_part;
   std::string err;
+  // kernel timing: the first fine half-sweep of every step, between events
+  bool timing = false;
+  bool timed_this_step = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double t_ms = 0.0, t_bytes = 0.0;
+  int64_t t_launches = 0;
 };
 
 namespace {
@@ -193,8 +199,13 @@ fld_status precondition(fld_amr_ctx* c, const double* r, double* z) {
   const int pre = std::max(c->p.pre_smooth, 1);
   const int post = std::max(c->p.post_smooth, 1);
   for (int k = 0; k < pre; ++k)
-    for (int colour = 0; colour < 2; ++colour)
-      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s));
+    for (int colour = 0; colour < 2; ++colour) {
+      const bool timed = c->timing && !c->timed_this_step;
+      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s,
+                            timed ? c->ev[0] : nullptr,
+                            timed ? c->ev[1] : nullptr));
+      if (timed) c->timed_this_step = true;
+    }
   AMR_HIP(c, amr_base_rhs(G, c->cf, r, z, c->rhs, s));
   const fld_status st = precond_vcycle(c->base, c->rhs, z);
   if (st != FLD_OK)
@@ -215,6 +226,7 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   const AmrGeom& G = c->G;
   hipStream_t s = c->stream;
   const int64_t n = G.Nb + G.Nf;
+  c->timed_this_step = false;
   // coefficients: views, D on both levels, fine faces, base faces
   AMR_HIP(c, amr_views(G, E_b, rho_b, kap_b, E_f, rho_f, kap_f, c->Ev, c->rv,
                        c->kv, s));
@@ -282,6 +294,15 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   precond_end(c->base);
   AMR_HIP(c, amr_unpack(G, c->x, E_b_out, E_f_out, s));
   AMR_HIP(c, hipStreamSynchronize(s));
+  if (c->timed_this_step) {
+    float ms = 0.0f;
+    AMR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    c->t_ms += ms;
+    c->t_launches += 1;
+    // one colour: r and the four faces of half the fine cells read, z of
+    // every fine cell read once, half of z written
+    c->t_bytes += 8.0 * (double)G.Nf * (0.5 + 2.0 + 1.0 + 0.5);
+  }
   if (stats) {
     stats->cycles = k;
     stats->outer_iters = k;
@@ -411,6 +432,29 @@ fld_status fld_amr_step(fld_amr_ctx* c, double dt, const double* rho_base,
                    rho_fine, kappa_fine, E_fine_in, E_fine_out, stats);
 }
 
+fld_status fld_amr_kernel_timing_enable(fld_amr_ctx* c, int32_t on) {
+  if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (on && !c->ev[0]) {
+    for (int k = 0; k < 2; ++k)
+      AMR_HIP(c, hipEventCreate(&c->ev[k]));
+  }
+  c->timing = on != 0;
+  return FLD_OK;
+}
+
+fld_status fld_amr_kernel_timing_read(fld_amr_ctx* c, double* ms_total,
+                                      int64_t* launches, double* bytes_total,
+                                      const char** kernel_name) {
+  if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (ms_total) *ms_total = c->t_ms;
+  if (launches) *launches = c->t_launches;
+  if (bytes_total) *bytes_total = c->t_bytes;
+  if (kernel_name) *kernel_name = "k_amr_smooth";
+  c->t_ms = c->t_bytes = 0.0;
+  c->t_launches = 0;
+  return FLD_OK;
+}
+
 const char* fld_amr_last_error(const fld_amr_ctx* c) {
   return c ? c->err.c_str() : g_amr_err.c_str();
 }
@@ -418,6 +462,8 @@ const char* fld_amr_last_error(const fld_amr_ctx* c) {
 void fld_amr_destroy(fld_amr_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < 2; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   fld_destroy(c->base);
   delete c;
 }

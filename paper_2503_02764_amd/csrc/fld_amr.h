@@ -44,8 +44,10 @@ hipError_t amr_coefficients(const AmrGeom& G, const AmrPhys& P, double dt,
 hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
                      const double* cf, const double* x, double* y,
                      hipStream_t s);
+// with ev0 and ev1 the launch records its start and end on them
 hipError_t amr_smooth(const AmrGeom& G, const double* cf, const double* r,
-                      double* z, int colour, hipStream_t s);
+                      double* z, int colour, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t amr_base_rhs(const AmrGeom& G, const double* cf, const double* r,
                         const double* z, double* rhs, hipStream_t s);
 hipError_t amr_prolong(const AmrGeom& G, double* z, hipStream_t s);

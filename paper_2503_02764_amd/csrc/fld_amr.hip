@@ -11,6 +11,8 @@
 // else that base cell's value (the fine level's view of the base grid).
 // One thread per cell everywhere; tables (block of a base block, corner of
 // a refined block) come from the host.
+#include <hip/hip_ext.h>
+
 #include "fld_amr.h"
 #include "fld_device.h"
 
@@ -49,6 +51,20 @@ __device__ __forceinline__ int64_t amr_fine_idx(const AmrGeom& G, int blk,
                                                 int I, int J) {
   const int lx = I - G.S * G.bxy[2 * blk], ly = J - G.S * G.bxy[2 * blk + 1];
   return ((int64_t)blk * G.S + ly) * G.S + lx;
+}
+
+// z at the fine neighbour of fine cell f (block-local (lx, ly), lattice
+// (I, J)) in direction k (0 -x, 1 +x, 2 -y, 3 +y), for a face that exists:
+// in-block neighbours by offset, the others through the tables
+__device__ __forceinline__ double amr_nb(const AmrGeom& G, const double* vb,
+                                         const double* vf, int64_t f, int lx,
+                                         int ly, int I, int J, int k) {
+  const int d = k >> 1, s = (k & 1) ? 1 : -1;
+  const int l = d == 0 ? lx + s : ly + s;
+  if (l >= 0 && l < G.S) return vf[f + (d == 0 ? s : s * G.S)];
+  const int II = amr_wrap(I + (d == 0 ? s : 0), 2 * G.nx, 1);
+  const int JJ = amr_wrap(J + (d == 1 ? s : 0), 2 * G.ny, 1);
+  return amr_fine_at(G, vb, vf, II, JJ);
 }
 
 __device__ __forceinline__ double amr_mean(double a, double b, int kind) {
@@ -252,18 +268,14 @@ __global__ void __launch_bounds__(kT)
   if (f >= G.Nf) return;
   const int blk = (int)(f / ((int64_t)G.S * G.S));
   const int loc = (int)(f % ((int64_t)G.S * G.S));
-  const int I = G.S * G.bxy[2 * blk] + loc % G.S;
-  const int J = G.S * G.bxy[2 * blk + 1] + loc / G.S;
-  const int NX = 2 * G.nx, NY = 2 * G.ny;
+  const int lx = loc % G.S, ly = loc / G.S;
+  const int I = G.S * G.bxy[2 * blk] + lx, J = G.S * G.bxy[2 * blk + 1] + ly;
   const double xi = xf[f];
   double acc = xi;
   for (int k = 0; k < 4; ++k) {
     const double a = cf[(int64_t)k * G.Nf + f];
     if (a == 0.0) continue;
-    const int d = k >> 1, s = (k & 1) ? 1 : -1;
-    const int II = amr_wrap(I + (d == 0 ? s : 0), NX, 1);
-    const int JJ = amr_wrap(J + (d == 1 ? s : 0), NY, 1);
-    acc += a * (xi - amr_fine_at(G, x, xf, II, JJ));
+    acc += a * (xi - amr_nb(G, x, xf, f, lx, ly, I, J, k));
   }
   y[G.Nb + f] = acc;
 }
@@ -278,19 +290,16 @@ __global__ void __launch_bounds__(kT)
   if (f >= G.Nf) return;
   const int blk = (int)(f / ((int64_t)G.S * G.S));
   const int loc = (int)(f % ((int64_t)G.S * G.S));
-  const int I = G.S * G.bxy[2 * blk] + loc % G.S;
-  const int J = G.S * G.bxy[2 * blk + 1] + loc / G.S;
-  if (((I + J) & 1) != colour) return;
-  const int NX = 2 * G.nx, NY = 2 * G.ny;
+  const int lx = loc % G.S, ly = loc / G.S;
+  // S is even, so the colour of (I, J) is that of (lx, ly)
+  if (((lx + ly) & 1) != colour) return;
+  const int I = G.S * G.bxy[2 * blk] + lx, J = G.S * G.bxy[2 * blk + 1] + ly;
   const double* zf = z + G.Nb;
   double num = r[G.Nb + f], den = 1.0;
   for (int k = 0; k < 4; ++k) {
     const double a = cf[(int64_t)k * G.Nf + f];
     if (a == 0.0) continue;
-    const int d = k >> 1, s = (k & 1) ? 1 : -1;
-    const int II = amr_wrap(I + (d == 0 ? s : 0), NX, 1);
-    const int JJ = amr_wrap(J + (d == 1 ? s : 0), NY, 1);
-    num += a * amr_fine_at(G, z, zf, II, JJ);
+    num += a * amr_nb(G, z, zf, f, lx, ly, I, J, k);
     den += a;
   }
   z[G.Nb + f] = num / den;
@@ -299,7 +308,9 @@ __global__ void __launch_bounds__(kT)
 // right-hand side of the base correction after the fine pre-smoothing:
 // a base leaf cell's residual with the fine correction's flux into it; a
 // covered cell's the mean of its children's residuals (base entries of z
-// are 0 here)
+// are 0 here).  The pre-smoothing ends with a half-sweep of colour 1, which
+// leaves those cells' residuals at 0 (up to rounding): only the two
+// colour-0 children are evaluated.
 __global__ void __launch_bounds__(kT)
     k_amr_base_rhs(AmrGeom G, const double* __restrict__ cf,
                    const double* __restrict__ r, const double* __restrict__ z,
@@ -315,19 +326,16 @@ __global__ void __launch_bounds__(kT)
     rhs[c] = r[c] - acc;
     return;
   }
-  const int NX = 2 * G.nx, NY = 2 * G.ny;
   double s = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int I = 2 * i + (q & 1), J = 2 * j + (q >> 1);
+  for (int q = 0; q < 2; ++q) {  // (0, 0) and (1, 1) of the 2 x 2 children
+    const int I = 2 * i + q, J = 2 * j + q;
     const int64_t f = amr_fine_idx(G, blk, I, J);
+    const int lx = I - G.S * G.bxy[2 * blk], ly = J - G.S * G.bxy[2 * blk + 1];
     double az = zf[f];
     for (int k = 0; k < 4; ++k) {
       const double a = cf[(int64_t)k * G.Nf + f];
       if (a == 0.0) continue;
-      const int d = k >> 1, sg = (k & 1) ? 1 : -1;
-      const int II = amr_wrap(I + (d == 0 ? sg : 0), NX, 1);
-      const int JJ = amr_wrap(J + (d == 1 ? sg : 0), NY, 1);
-      az += a * (zf[f] - amr_fine_at(G, z, zf, II, JJ));
+      az += a * (zf[f] - amr_nb(G, z, zf, f, lx, ly, I, J, k));
     }
     s += r[G.Nb + f] - az;
   }
@@ -456,10 +464,15 @@ hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
 }
 
 hipError_t amr_smooth(const AmrGeom& G, const double* cf, const double* r,
-                      double* z, int colour, hipStream_t s) {
+                      double* z, int colour, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
   if (G.Nf == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_amr_smooth, dim3(nblk(G.Nf)), dim3(kT), 0, s, G, cf, r,
-                     z, colour);
+  if (ev0 && ev1)  // the launch records its own start and end
+    hipExtLaunchKernelGGL(k_amr_smooth, dim3(nblk(G.Nf)), dim3(kT), 0, s, ev0,
+                          ev1, 0, G, cf, r, z, colour);
+  else
+    hipLaunchKernelGGL(k_amr_smooth, dim3(nblk(G.Nf)), dim3(kT), 0, s, G, cf,
+                       r, z, colour);
   return hipGetLastError();
 }
 

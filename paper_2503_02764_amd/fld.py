@@ -385,7 +385,8 @@ EXPORTED += ["fld_workspace_bytes_batch", "fld_setup_batch", "fld_step_batch",
 # ---- block-adaptive 2D grids -------------------------------------------
 
 EXPORTED += ["fld_amr_workspace_bytes", "fld_amr_setup", "fld_amr_step",
-             "fld_amr_last_error", "fld_amr_destroy"]
+             "fld_amr_last_error", "fld_amr_destroy",
+             "fld_amr_kernel_timing_enable", "fld_amr_kernel_timing_read"]
 
 
 def _amr_argtypes(lib):
@@ -403,6 +404,11 @@ def _amr_argtypes(lib):
     lib.fld_amr_last_error.restype = ctypes.c_char_p
     lib.fld_amr_destroy.argtypes = [V]
     lib.fld_amr_destroy.restype = None
+    lib.fld_amr_kernel_timing_enable.argtypes = [V, I32]
+    lib.fld_amr_kernel_timing_enable.restype = ctypes.c_int
+    lib.fld_amr_kernel_timing_read.argtypes = [V, P(D), P(ctypes.c_int64),
+                                               P(D), P(ctypes.c_char_p)]
+    lib.fld_amr_kernel_timing_read.restype = ctypes.c_int
     lib._amr_ready = True
 
 
@@ -466,6 +472,21 @@ def fld_amr_setup(params, block, blocks, workspace=None, stream=None):
     if st != FLD_OK:
         raise FldError(st, lib.fld_amr_last_error(None).decode())
     return AmrCtx(out, params, block, nb, workspace, stream)
+
+
+def fld_amr_kernel_timing_enable(ctx, on=True):
+    _amrlib().fld_amr_kernel_timing_enable(ctx.ptr, int(bool(on)))
+
+
+def fld_amr_kernel_timing_read(ctx):
+    """dict(kernel, ms, launches, bytes) since the last read."""
+    ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    name = ctypes.c_char_p()
+    _amrlib().fld_amr_kernel_timing_read(ctx.ptr, ctypes.byref(ms),
+                                         ctypes.byref(n), ctypes.byref(by),
+                                         ctypes.byref(name))
+    return {"kernel": name.value.decode() if name.value else "none",
+            "ms": ms.value, "launches": n.value, "bytes": by.value}
 
 
 def fld_amr_step(ctx, dt, rho_b, kappa_b, E_b_in, E_b_out, rho_f, kappa_f,
