@@ -299,7 +299,8 @@ fld_status fld_set_held(fld_ctx* ctx, const uint8_t* mask,
  * pointers; E_*_out may equal E_*_in.  Workspace: device memory of
  * fld_amr_workspace_bytes (0 for invalid arguments), 256-byte aligned,
  * owned by the caller.  fld_amr_step blocks until the solve ends (the
- * Krylov scalars are summed on the host); stats as fld_step's (cycles and
+ * Krylov scalars stay on the device; the host reads the residual once per
+ * iteration for the stop test); stats as fld_step's (cycles and
  * outer_iters: iterations).  Errors: FLD_ERR_INVALID_ARG, FLD_ERR_WORKSPACE,
  * FLD_ERR_NONPHYSICAL, FLD_ERR_NOT_CONVERGED (last iterate returned),
  * FLD_ERR_DEVICE; the message is read by fld_amr_last_error. */

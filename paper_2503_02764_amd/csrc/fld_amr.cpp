@@ -16,8 +16,11 @@
 //      its faces from the base view of E) for the base correction;
 //   4. the base correction prolonged (bilinear) onto the fine cells, then
 //      the sweeps of 1 in reverse colour order with the base values fixed.
-// The stop test is the volume-weighted relative residual |r|_V / |b|_V;
-// the scalars of each iteration are summed on the host.
+// The stop test is the volume-weighted relative residual |r|_V / |b|_V.
+// The scalars of an iteration stay on the device: the operator and update
+// kernels leave block sums, one-block reductions turn them into the
+// scalars the next kernels read, and the host reads (r, r) once an
+// iteration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +50,7 @@ struct fld_amr_ctx {
   double *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr;
   double *p2[2] = {}, *q2[2] = {};
   double* partials = nullptr;
+  double* sc = nullptr;  // Krylov scalars on the device (amr_reduce)
   int* bad = nullptr;
   std::vector<double> host_part;
   std::string err;
@@ -134,7 +138,7 @@ std::string validate_amr(const fld_params* p, int32_t block,
 
 struct AmrPlan {
   size_t base_ws = 0, bmap = 0, bxy = 0, views = 0, Db = 0, Df = 0, cf = 0;
-  size_t rhs = 0, vec = 0, partials = 0, bad = 0, total = 0;
+  size_t rhs = 0, vec = 0, partials = 0, sc = 0, bad = 0, total = 0;
   int64_t Nb = 0, Nf = 0, nvec = 0;
   int dot_blocks = 0;
 };
@@ -163,6 +167,7 @@ AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nblocks) {
   P.rhs = take((size_t)P.Nb * 8);
   P.vec = take((size_t)P.nvec * 8 * 8);  // x, b, r, z, p[2], q[2]
   P.partials = take((size_t)P.dot_blocks * 3 * 8);
+  P.sc = take(8 * 8);
   P.bad = take(8);
   P.total = o;
   return P;
@@ -263,30 +268,35 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   const double bb = d2[0];
   double res = bb > 0.0 ? std::sqrt(d2[1] / bb) : 0.0;
   const double res0 = res;
+  // the iteration's scalars stay on the device (amr_reduce); the host
+  // reads (r, r) once per iteration for the stop test
   int k = 0;
-  double pq_old = 0.0;
   bool converged = !(res > c->p.rtol);
+  const int nbd = amr_dot_blocks(G);
+  double rr = 0.0;
   while (!converged && k < c->p.max_cycles) {
     double* p = c->p2[k & 1];
     double* p_old = c->p2[(k + 1) & 1];
     double* q = c->q2[k & 1];
     double* q_old = c->q2[(k + 1) & 1];
     AMR_TRY(precondition(c, c->r, c->z));
-    if (k == 0) {
-      AMR_HIP(c, hipMemcpyAsync(p, c->z, sizeof(double) * n,
-                                hipMemcpyDeviceToDevice, s));
-    } else {
-      AMR_TRY(dots(c, 1, c->z, q_old, nullptr, nullptr, d2));
-      AMR_HIP(c, amr_axpy(n, -d2[0] / pq_old, p_old, c->z, p, s));
+    if (k > 0) {
+      AmrDots D{};
+      D.n = 1;
+      D.u[0] = c->z;
+      D.v[0] = q_old;
+      AMR_HIP(c, amr_dots(G, D, c->partials, s));
+      AMR_HIP(c, amr_reduce(c->partials, nbd, 1, c->sc, 0, 0, s));
     }
-    AMR_HIP(c, amr_apply(G, ax, ay, c->cf, p, q, s));
-    AMR_TRY(dots(c, 2, c->r, p, p, q, d2));
-    const double alpha = d2[0] / d2[1];
-    pq_old = d2[1];
-    AMR_HIP(c, amr_axpy(n, alpha, p, c->x, c->x, s));
-    AMR_HIP(c, amr_axpy(n, -alpha, q, c->r, c->r, s));
-    AMR_TRY(dots(c, 1, c->r, c->r, nullptr, nullptr, d2));
-    res = std::sqrt(d2[0] / bb);
+    AMR_HIP(c, amr_dir(n, c->z, p_old, p, c->sc, k == 0, s));
+    AMR_HIP(c, amr_apply(G, ax, ay, c->cf, p, q, s, c->r, c->partials));
+    AMR_HIP(c, amr_reduce(c->partials, nbd, 2, c->sc, 2, 0, s));
+    AMR_HIP(c, amr_update(G, p, q, c->x, c->r, c->sc, c->partials, s));
+    AMR_HIP(c, amr_reduce(c->partials, nbd, 1, c->sc, 4, 1, s));
+    AMR_HIP(c, hipMemcpyAsync(&rr, c->sc + 4, sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    AMR_HIP(c, hipStreamSynchronize(s));
+    res = std::sqrt(rr / bb);
     ++k;
     converged = !(res > c->p.rtol);
     if (!std::isfinite(res)) break;
@@ -391,6 +401,7 @@ fld_status fld_amr_setup(const fld_params* p, int32_t block,
                       &c->p2[0], &c->p2[1], &c->q2[0], &c->q2[1]};
   for (int k = 0; k < 8; ++k) *vecs[k] = v + (size_t)k * P.nvec;
   c->partials = (double*)(w + P.partials);
+  c->sc = (double*)(w + P.sc);
   c->bad = (int*)(w + P.bad);
   // tables: the refined block of every base block, each block's corner
   std::vector<int> bmap((size_t)G.nbx * G.nby, -1), bxy((size_t)2 * nblocks);

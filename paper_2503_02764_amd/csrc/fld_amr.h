@@ -41,9 +41,24 @@ hipError_t amr_coefficients(const AmrGeom& G, const AmrPhys& P, double dt,
                             const double* kv, const double* Ef,
                             const double* rf, const double* kf, double* Db,
                             double* Df, double* cf, int* bad, hipStream_t s);
+// y = A x; with r and partials also the block sums of (r, x) and (x, y)
+// (rows 0 and 1 of amr_dot_blocks entries each)
 hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
                      const double* cf, const double* x, double* y,
-                     hipStream_t s);
+                     hipStream_t s, const double* r = nullptr,
+                     double* partials = nullptr);
+// Krylov scalars kept on the device (sc[0..4]: (z, q_old), (p_old, q_old),
+// (r, p), (p, q), (r, r)): a one-block sum of `npair` rows of partials into
+// sc[slot ...] (copy: sc[1] = sc[3] first); p = z - sc[0] / sc[1] p_old
+// (or z); x += a p, r -= a q with a = sc[2] / sc[3] and the block sums of
+// (r, r).
+hipError_t amr_reduce(const double* partials, int nb, int npair, double* sc,
+                      int slot, int copy, hipStream_t s);
+hipError_t amr_dir(int64_t n, const double* z, const double* p_old, double* p,
+                   const double* sc, int first, hipStream_t s);
+hipError_t amr_update(const AmrGeom& G, const double* p, const double* q,
+                      double* x, double* r, const double* sc,
+                      double* partials, hipStream_t s);
 // with ev0 and ev1 the launch records its start and end on them
 hipError_t amr_smooth(const AmrGeom& G, const double* cf, const double* r,
                       double* z, int colour, hipStream_t s,

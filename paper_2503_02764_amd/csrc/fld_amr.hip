@@ -230,18 +230,14 @@ __device__ __forceinline__ bool amr_base_to_fine(const AmrGeom& G,
 }
 
 // y = A x over the leaf cells (covered base entries: 0)
-__global__ void __launch_bounds__(kT)
-    k_amr_apply(AmrGeom G, const double* __restrict__ ax,
-                const double* __restrict__ ay, const double* __restrict__ cf,
-                const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+__device__ __forceinline__ double amr_apply_cell(
+    const AmrGeom& G, const double* __restrict__ ax,
+    const double* __restrict__ ay, const double* __restrict__ cf,
+    const double* __restrict__ x, int64_t t) {
   const double* xf = x + G.Nb;
   if (t < G.Nb) {
     const int i = (int)(t % G.nx), j = (int)(t / G.nx);
-    if (amr_block(G, i, j) >= 0) {
-      y[t] = 0.0;
-      return;
-    }
+    if (amr_block(G, i, j) >= 0) return 0.0;
     const double xc = x[t];
     double acc = xc;
     for (int k = 0; k < 4; ++k) {
@@ -261,11 +257,9 @@ __global__ void __launch_bounds__(kT)
       const double a = (d == 0 ? ax : ay)[owner];
       acc += a * (xc - x[(int64_t)jj * G.nx + ii]);
     }
-    y[t] = acc;
-    return;
+    return acc;
   }
   const int64_t f = t - G.Nb;
-  if (f >= G.Nf) return;
   const int blk = (int)(f / ((int64_t)G.S * G.S));
   const int loc = (int)(f % ((int64_t)G.S * G.S));
   const int lx = loc % G.S, ly = loc / G.S;
@@ -277,7 +271,91 @@ __global__ void __launch_bounds__(kT)
     if (a == 0.0) continue;
     acc += a * (xi - amr_nb(G, x, xf, f, lx, ly, I, J, k));
   }
-  y[G.Nb + f] = acc;
+  return acc;
+}
+
+// y = A x; with `partials`, also the per-block sums of the volume-weighted
+// r . x (row 0) and x . y (row 1)
+__global__ void __launch_bounds__(kT)
+    k_amr_apply(AmrGeom G, const double* __restrict__ ax,
+                const double* __restrict__ ay, const double* __restrict__ cf,
+                const double* __restrict__ x, double* __restrict__ y,
+                const double* __restrict__ r, double* __restrict__ partials) {
+  __shared__ double sh[kT / 64];
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  double rx = 0.0, xy = 0.0;
+  if (t < G.Nb + G.Nf) {
+    const double v = amr_apply_cell(G, ax, ay, cf, x, t);
+    y[t] = v;
+    const double w = t < G.Nb ? G.vb : G.vf;
+    if (partials) {
+      rx = w * r[t] * x[t];
+      xy = w * x[t] * v;
+    }
+  }
+  if (!partials) return;
+  const double s0 = block_sum<kT>(rx, sh);
+  __syncthreads();
+  const double s1 = block_sum<kT>(xy, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s0;
+    partials[gridDim.x + blockIdx.x] = s1;
+  }
+}
+
+// Krylov scalars on the device: sc[0] (z, q_old), sc[1] (p_old, q_old),
+// sc[2] (r, p), sc[3] (p, q), sc[4] (r, r).  One block sums rows of
+// block partials in a fixed order into sc[slot ...]; with copy, sc[1] takes
+// sc[3] first (this iteration's (p, q) is the next one's (p_old, q_old)).
+constexpr int kRT = 1024;  // one wide block: few partials per thread
+__global__ void __launch_bounds__(kRT)
+    k_amr_reduce(const double* __restrict__ partials, int nb, int npair,
+                 double* __restrict__ sc, int slot, int copy) {
+  __shared__ double sh[kRT / 64];
+  if (copy && threadIdx.x == 0) sc[1] = sc[3];
+  for (int k = 0; k < npair; ++k) {
+    const double* row = partials + (int64_t)k * nb;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // four loads in flight
+    int i = threadIdx.x;
+    for (; i + 3 * kRT < nb; i += 4 * kRT)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] += row[i + u * kRT];
+    for (; i < nb; i += kRT) v[0] += row[i];
+    const double tot = block_sum<kRT>((v[0] + v[1]) + (v[2] + v[3]), sh);
+    __syncthreads();
+    if (threadIdx.x == 0) sc[slot + k] = tot;
+  }
+}
+
+// p = z (first) or z - (sc[0] / sc[1]) p_old
+__global__ void __launch_bounds__(kT)
+    k_amr_dir(int64_t n, const double* __restrict__ z,
+              const double* __restrict__ p_old, double* __restrict__ p,
+              const double* __restrict__ sc, int first) {
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (t >= n) return;
+  p[t] = first ? z[t] : z[t] - (sc[0] / sc[1]) * p_old[t];
+}
+
+// x += a p, r -= a q with a = sc[2] / sc[3]; per-block sums of the
+// volume-weighted r . r
+__global__ void __launch_bounds__(kT)
+    k_amr_update(AmrGeom G, const double* __restrict__ p,
+                 const double* __restrict__ q, double* __restrict__ x,
+                 double* __restrict__ r, const double* __restrict__ sc,
+                 double* __restrict__ partials) {
+  __shared__ double sh[kT / 64];
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  double rr = 0.0;
+  if (t < G.Nb + G.Nf) {
+    const double a = sc[2] / sc[3];
+    x[t] += a * p[t];
+    const double rv = r[t] - a * q[t];
+    r[t] = rv;
+    rr = (t < G.Nb ? G.vb : G.vf) * rv * rv;
+  }
+  const double tot = block_sum<kT>(rr, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 // one colour ((I + J) & 1) of a Gauss-Seidel sweep over the fine cells for
@@ -422,6 +500,7 @@ __global__ void __launch_bounds__(kT)
   for (int k = 0; k < D.n; ++k) {
     const double s = t < G.Nb + G.Nf ? w * D.u[k][t] * D.v[k][t] : 0.0;
     const double tot = block_sum<kT>(s, sh);
+    __syncthreads();  // sh is reused by the next sum
     if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = tot;
   }
 }
@@ -457,9 +536,31 @@ hipError_t amr_coefficients(const AmrGeom& G, const AmrPhys& P, double dt,
 
 hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
                      const double* cf, const double* x, double* y,
-                     hipStream_t s) {
+                     hipStream_t s, const double* r, double* partials) {
   hipLaunchKernelGGL(k_amr_apply, dim3(nblk(G.Nb + G.Nf)), dim3(kT), 0, s, G,
-                     ax, ay, cf, x, y);
+                     ax, ay, cf, x, y, r, partials);
+  return hipGetLastError();
+}
+
+hipError_t amr_reduce(const double* partials, int nb, int npair, double* sc,
+                      int slot, int copy, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_reduce, dim3(1), dim3(kRT), 0, s, partials, nb,
+                     npair, sc, slot, copy);
+  return hipGetLastError();
+}
+
+hipError_t amr_dir(int64_t n, const double* z, const double* p_old, double* p,
+                   const double* sc, int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_dir, dim3(nblk(n)), dim3(kT), 0, s, n, z, p_old, p,
+                     sc, first);
+  return hipGetLastError();
+}
+
+hipError_t amr_update(const AmrGeom& G, const double* p, const double* q,
+                      double* x, double* r, const double* sc,
+                      double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_update, dim3(nblk(G.Nb + G.Nf)), dim3(kT), 0, s, G,
+                     p, q, x, r, sc, partials);
   return hipGetLastError();
 }
 
