@@ -317,6 +317,22 @@ fld_status fld_amr_step(fld_amr_ctx* ctx, double dt, const double* rho_base,
                         double* E_base_out, const double* rho_fine,
                         const double* kappa_fine, const double* E_fine_in,
                         double* E_fine_out, fld_stats* stats);
+/* fld_exchange and fld_opacity_powerlaw on a block-adaptive grid: both are
+ * per cell, so they run over the base array (every cell, covered ones
+ * included) and over the fine array, with the context's constants.  Same
+ * layouts as fld_amr_step; asynchronous (stream-ordered); the same
+ * argument errors as the single-grid calls. */
+fld_status fld_amr_exchange(fld_amr_ctx* ctx, double dt,
+                            const double* rho_base, const double* kappa_base,
+                            double* E_base, double* e_base,
+                            const double* rho_fine, const double* kappa_fine,
+                            double* E_fine, double* e_fine);
+fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* ctx, const double* rho_base,
+                                    const double* e_base,
+                                    const double* rho_fine,
+                                    const double* e_fine, double k0, double a,
+                                    double b, double kmin, double kmax,
+                                    double* kappa_base, double* kappa_fine);
 /* Kernel timing of the block-adaptive step: with `on`, the first fine
  * red-black half-sweep of every step (the step's dominant kernel) is
  * bracketed by events on the context's stream; the read returns the summed

@@ -34,6 +34,7 @@
 #include "fld.h"
 #include "fld_amr.h"
 #include "fld_hooks.h"
+#include "fld_internal.h"
 
 using namespace fld;
 
@@ -441,6 +442,52 @@ fld_status fld_amr_step(fld_amr_ctx* c, double dt, const double* rho_base,
   // in place is allowed: the inputs are read before the outputs are written
   return amr_solve(c, dt, rho_base, kappa_base, E_base_in, E_base_out,
                    rho_fine, kappa_fine, E_fine_in, E_fine_out, stats);
+}
+
+fld_status fld_amr_exchange(fld_amr_ctx* c, double dt, const double* rho_base,
+                            const double* kappa_base, double* E_base,
+                            double* e_base, const double* rho_fine,
+                            const double* kappa_fine, double* E_fine,
+                            double* e_fine) {
+  if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (!rho_base || !kappa_base || !E_base || !e_base)
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
+  if (c->G.nbf > 0 && (!rho_fine || !kappa_fine || !E_fine || !e_fine))
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
+  const fld_params& p = c->p;
+  AMR_HIP(c, launch_exchange(c->G.Nb, dt, p.c, p.a_rad, p.gamma, p.gas_const,
+                             rho_base, kappa_base, E_base, e_base, c->stream));
+  if (c->G.nbf > 0)
+    AMR_HIP(c, launch_exchange(c->G.Nf, dt, p.c, p.a_rad, p.gamma,
+                               p.gas_const, rho_fine, kappa_fine, E_fine,
+                               e_fine, c->stream));
+  return FLD_OK;
+}
+
+fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* c, const double* rho_base,
+                                    const double* e_base,
+                                    const double* rho_fine,
+                                    const double* e_fine, double k0, double a,
+                                    double b, double kmin, double kmax,
+                                    double* kappa_base, double* kappa_fine) {
+  if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
+  if (!rho_base || !e_base || !kappa_base)
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
+  if (c->G.nbf > 0 && (!rho_fine || !e_fine || !kappa_fine))
+    return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
+  if (!(k0 > 0.0) || !(kmin > 0.0) || !(kmax >= kmin) || !std::isfinite(a) ||
+      !std::isfinite(b) || !std::isfinite(kmax))
+    return amr_fail(c, FLD_ERR_INVALID_ARG,
+                    "need k0 > 0, 0 < kmin <= kmax, finite exponents");
+  const fld_params& p = c->p;
+  AMR_HIP(c, launch_opacity(c->G.Nb, p.gamma, p.gas_const, rho_base, e_base,
+                            k0, a, b, kmin, kmax, kappa_base, c->stream));
+  if (c->G.nbf > 0)
+    AMR_HIP(c, launch_opacity(c->G.Nf, p.gamma, p.gas_const, rho_fine, e_fine,
+                              k0, a, b, kmin, kmax, kappa_fine, c->stream));
+  return FLD_OK;
 }
 
 fld_status fld_amr_kernel_timing_enable(fld_amr_ctx* c, int32_t on) {

@@ -386,7 +386,8 @@ EXPORTED += ["fld_workspace_bytes_batch", "fld_setup_batch", "fld_step_batch",
 
 EXPORTED += ["fld_amr_workspace_bytes", "fld_amr_setup", "fld_amr_step",
              "fld_amr_last_error", "fld_amr_destroy",
-             "fld_amr_kernel_timing_enable", "fld_amr_kernel_timing_read"]
+             "fld_amr_kernel_timing_enable", "fld_amr_kernel_timing_read",
+             "fld_amr_exchange", "fld_amr_opacity_powerlaw"]
 
 
 def _amr_argtypes(lib):
@@ -404,6 +405,11 @@ def _amr_argtypes(lib):
     lib.fld_amr_last_error.restype = ctypes.c_char_p
     lib.fld_amr_destroy.argtypes = [V]
     lib.fld_amr_destroy.restype = None
+    lib.fld_amr_exchange.argtypes = [V, D, V, V, V, V, V, V, V, V]
+    lib.fld_amr_exchange.restype = ctypes.c_int
+    lib.fld_amr_opacity_powerlaw.argtypes = [V, V, V, V, V, D, D, D, D, D, V,
+                                             V]
+    lib.fld_amr_opacity_powerlaw.restype = ctypes.c_int
     lib.fld_amr_kernel_timing_enable.argtypes = [V, I32]
     lib.fld_amr_kernel_timing_enable.restype = ctypes.c_int
     lib.fld_amr_kernel_timing_read.argtypes = [V, P(D), P(ctypes.c_int64),
@@ -472,6 +478,49 @@ def fld_amr_setup(params, block, blocks, workspace=None, stream=None):
     if st != FLD_OK:
         raise FldError(st, lib.fld_amr_last_error(None).decode())
     return AmrCtx(out, params, block, nb, workspace, stream)
+
+
+def _amr_fine(ctx, t, name):
+    import torch
+    return _ptr(t, name, ctx.fine_cells, torch.float64) if ctx.fine_cells \
+        else None
+
+
+def fld_amr_exchange(ctx, dt, rho_b, kappa_b, E_b, e_b, rho_f, kappa_f, E_f,
+                     e_f, check=True):
+    """The exchange quartic on the base and fine arrays (in place)."""
+    import torch
+    lib = _amrlib()
+    nb = ctx.base_cells
+    f64 = torch.float64
+    st = lib.fld_amr_exchange(ctx.ptr, float(dt),
+                              _ptr(rho_b, "rho_b", nb, f64),
+                              _ptr(kappa_b, "kappa_b", nb, f64),
+                              _ptr(E_b, "E_b", nb, f64),
+                              _ptr(e_b, "e_b", nb, f64),
+                              _amr_fine(ctx, rho_f, "rho_f"),
+                              _amr_fine(ctx, kappa_f, "kappa_f"),
+                              _amr_fine(ctx, E_f, "E_f"),
+                              _amr_fine(ctx, e_f, "e_f"))
+    if check and st != FLD_OK:
+        raise FldError(st, lib.fld_amr_last_error(ctx.ptr).decode())
+    return st
+
+
+def fld_amr_opacity_powerlaw(ctx, rho_b, e_b, rho_f, e_f, k0, a, b, kmin,
+                             kmax, kappa_b, kappa_f, check=True):
+    import torch
+    lib = _amrlib()
+    nb = ctx.base_cells
+    f64 = torch.float64
+    st = lib.fld_amr_opacity_powerlaw(
+        ctx.ptr, _ptr(rho_b, "rho_b", nb, f64), _ptr(e_b, "e_b", nb, f64),
+        _amr_fine(ctx, rho_f, "rho_f"), _amr_fine(ctx, e_f, "e_f"),
+        float(k0), float(a), float(b), float(kmin), float(kmax),
+        _ptr(kappa_b, "kappa_b", nb, f64), _amr_fine(ctx, kappa_f, "kappa_f"))
+    if check and st != FLD_OK:
+        raise FldError(st, lib.fld_amr_last_error(ctx.ptr).decode())
+    return st
 
 
 def fld_amr_kernel_timing_enable(ctx, on=True):
