@@ -343,6 +343,30 @@ fld_status fld_amr_kernel_timing_enable(fld_amr_ctx* ctx, int32_t on);
 fld_status fld_amr_kernel_timing_read(fld_amr_ctx* ctx, double* ms_total,
                                       int64_t* launches, double* bytes_total,
                                       const char** kernel_name);
+/* Deeper hierarchies: nlevels (<= 4) refined levels.  Level l has spacing
+ * dx / 2^l on a (n[0] << l) x (n[1] << l) lattice; each of its blocks
+ * refines the block x block patch of level-(l-1) cells whose corner is
+ * (bx block, by block) into 2 block x 2 block level-l cells.  nblocks:
+ * host array of nlevels counts; blocks_xy: the (bx, by) of level 1's
+ * blocks, then level 2's, ...  A level-l block (l >= 2) must lie inside a
+ * level-(l-1) block, and so must the four patches sharing its faces (2:1
+ * nesting: a leaf cell's face neighbour is of its own level or of the next
+ * coarser one); walls end that condition.  The fine arrays hold level 1's
+ * blocks, then level 2's, ..., (2 block)^2 doubles each; the cells under
+ * finer blocks are not read, and on output hold the mean of their four
+ * children.  Same readings and solve as one level (the preconditioner
+ * sweeps the fine levels from the finest down, restricts the residual level
+ * by level to the base, runs the base V-cycle and prolongs its correction
+ * level by level before sweeping again upwards).  fld_amr_setup and
+ * fld_amr_workspace_bytes are the one-level case. */
+size_t fld_amr_workspace_bytes_levels(const fld_params* p, int32_t block,
+                                      int32_t nlevels, const int32_t* nblocks,
+                                      const int32_t* blocks_xy);
+fld_status fld_amr_setup_levels(const fld_params* p, int32_t block,
+                                int32_t nlevels, const int32_t* nblocks,
+                                const int32_t* blocks_xy, void* workspace,
+                                size_t ws_bytes, void* hip_stream,
+                                fld_amr_ctx** out);
 /* Last error of a context, or with NULL of the last failed set-up. */
 const char* fld_amr_last_error(const fld_amr_ctx* ctx);
 void fld_amr_destroy(fld_amr_ctx* ctx);

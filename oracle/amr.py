@@ -248,3 +248,206 @@ def amr_step(grid, Eb, rhob, kapb, Ef, rhof, kapf, dt, method="splu"):
     else:
         x = spla.splu(A.tocsc()).solve(b)
     return from_leaf(grid, x)
+
+
+# ---------------------------------------------------------------------------
+# Deeper hierarchies: refined blocks inside refined blocks
+# ---------------------------------------------------------------------------
+#
+# Readings (the same as one level, applied between each level and the next
+# coarser one): level l has spacing dx / 2^l on a lattice of 2^l nx x 2^l ny
+# cells; a block of level l >= 1 refines a b x b patch of level l-1 cells
+# (its corner (bx, by) counted in units of b level-(l-1) cells) into 2b x 2b
+# level-l cells, and that patch must lie inside a level-(l-1) block (the
+# base for l = 1).  A leaf cell's face neighbour is a cell of its own level
+# or, across the edge of its level's blocks, a leaf cell of the next coarser
+# level (2:1 nesting; the step checks it).  Views: each level's cells under
+# finer blocks take the mean of their four children (from the finest level
+# down); a level's view outside its blocks is the next coarser level's view
+# copied to the four cells under each of its cells.
+
+
+def level_lattice(grid, l):
+    return (grid.ny << l, grid.nx << l)
+
+
+def level_present(grid, levels, l):
+    """Cells of the level-l lattice inside level-l blocks (l = 0: all)."""
+    shape = level_lattice(grid, l)
+    if l == 0:
+        return np.ones(shape, dtype=bool)
+    m = np.zeros(shape, dtype=bool)
+    s = 2 * grid.b
+    for bx, by in levels[l - 1]:
+        m[by * s:(by + 1) * s, bx * s:(bx + 1) * s] = True
+    return m
+
+
+def level_problem(grid, l):
+    return F.Problem(ndim=2, n=(grid.nx << l, grid.ny << l, 1),
+                     dx=(grid.dx / (1 << l), grid.dy / (1 << l), 1.0),
+                     bc=tuple(grid.bc), c=grid.c, limiter=grid.limiter,
+                     face_mean=grid.face_mean)
+
+
+def blocks_to_full(grid, blocks, arr, fill):
+    out = np.array(fill, dtype=np.float64, copy=True)
+    s = 2 * grid.b
+    for k, (bx, by) in enumerate(blocks):
+        out[by * s:(by + 1) * s, bx * s:(bx + 1) * s] = arr[k]
+    return out
+
+
+def full_to_blocks(grid, blocks, full):
+    s = 2 * grid.b
+    if not blocks:
+        return np.zeros((0, s, s))
+    return np.stack([full[by * s:(by + 1) * s, bx * s:(bx + 1) * s]
+                     for bx, by in blocks])
+
+
+def hier_views(grid, levels, fields):
+    """Full-lattice views of one field on every level; `fields` = [base
+    (ny, nx), level-1 blocks, level-2 blocks, ...]."""
+    L = len(levels)
+    present = [level_present(grid, levels, l) for l in range(L + 1)]
+    vals = [fields[0]] + [blocks_to_full(grid, levels[l - 1], fields[l],
+                                         np.zeros(level_lattice(grid, l)))
+                          for l in range(1, L + 1)]
+    avg = [None] * (L + 1)
+    avg[L] = vals[L]
+    for l in range(L - 1, -1, -1):  # under finer blocks: child means
+        avg[l] = np.where(present[l + 1][0::2, 0::2], child_mean(avg[l + 1]),
+                          vals[l])
+    view = [avg[0]]
+    for l in range(1, L + 1):  # outside a level's blocks: the coarser view
+        view.append(np.where(present[l], avg[l], inject(view[l - 1])))
+    return view, present
+
+
+def hier_numbering(grid, levels):
+    """Leaf index per lattice cell of every level (-1: not a leaf)."""
+    L = len(levels)
+    present = [level_present(grid, levels, l) for l in range(L + 1)]
+    idx, k = [], 0
+    for l in range(L + 1):
+        covered = present[l + 1][0::2, 0::2] if l < L else \
+            np.zeros_like(present[l])
+        leaf = present[l] & ~covered
+        a = np.full(present[l].shape, -1, dtype=np.int64)
+        if l == 0:
+            n = int(np.count_nonzero(leaf))
+            a[leaf] = np.arange(k, k + n)
+            k += n
+        else:
+            s = 2 * grid.b
+            for bx, by in levels[l - 1]:
+                blk = leaf[by * s:(by + 1) * s, bx * s:(bx + 1) * s]
+                sub = a[by * s:(by + 1) * s, bx * s:(bx + 1) * s]
+                n = int(np.count_nonzero(blk))
+                sub[blk] = np.arange(k, k + n)
+                k += n
+        idx.append(a)
+    return idx, k
+
+
+def hier_assemble(grid, levels, D, dt):
+    """Composite operator over the leaf cells of every level, and their
+    volumes; D: full-lattice D per level."""
+    idx, N = hier_numbering(grid, levels)
+    L = len(levels)
+    per = [b == F.PERIODIC for b in grid.bc]
+    rows, cols, vals = [], [], []
+
+    def couple(i, j, wi, wj):
+        rows.extend([i, i, j, j])
+        cols.extend([i, j, j, i])
+        vals.extend([wi, -wi, wj, -wj])
+
+    for l in range(L + 1):
+        NY, NX = idx[l].shape
+        h = (grid.dx / (1 << l), grid.dy / (1 << l))
+        present = level_present(grid, levels, l)
+        for J in range(NY):
+            for I in range(NX):
+                me = idx[l][J, I]
+                if me < 0:
+                    continue
+                for d, (di, dj) in enumerate(((1, 0), (0, 1))):
+                    for sgn in (1, -1):
+                        II, JJ = I + sgn * di, J + sgn * dj
+                        if not (0 <= (II, JJ)[d] < (NX, NY)[d]):
+                            if not per[d]:
+                                continue
+                            II, JJ = II % NX, JJ % NY
+                        if present[JJ, II]:
+                            nb = idx[l][JJ, II]
+                            if nb < 0 or sgn < 0:
+                                continue  # finer side, or counted below
+                            a = dt * _mean(D[l][J, I], D[l][JJ, II],
+                                           grid.face_mean) / h[d] ** 2
+                            couple(me, nb, a, a)
+                        else:
+                            c = idx[l - 1][JJ // 2, II // 2]
+                            if c < 0:
+                                raise ValueError("levels not 2:1 nested")
+                            beta = (2.0 / 3.0) * dt * _mean(
+                                D[l][J, I], D[l - 1][JJ // 2, II // 2],
+                                grid.face_mean) / h[d] ** 2
+                            couple(me, c, beta, beta / 4.0)
+    rows.extend(range(N))
+    cols.extend(range(N))
+    vals.extend([1.0] * N)
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    vol = np.empty(N)
+    for l in range(L + 1):
+        m = idx[l] >= 0
+        vol[idx[l][m]] = grid.dx * grid.dy / (4 ** l)
+    return A, vol
+
+
+def hier_to_leaf(grid, levels, fields):
+    idx, N = hier_numbering(grid, levels)
+    v = np.empty(N)
+    for l, f in enumerate(fields):
+        full = f if l == 0 else blocks_to_full(
+            grid, levels[l - 1], f, np.zeros(level_lattice(grid, l)))
+        m = idx[l] >= 0
+        v[idx[l][m]] = full[m]
+    return v
+
+
+def hier_from_leaf(grid, levels, v):
+    """Per-level arrays from a leaf vector; cells under finer blocks get the
+    mean of their children (from the finest level down)."""
+    idx, _ = hier_numbering(grid, levels)
+    L = len(levels)
+    full = []
+    for l in range(L + 1):
+        a = np.zeros(idx[l].shape)
+        m = idx[l] >= 0
+        a[m] = v[idx[l][m]]
+        full.append(a)
+    for l in range(L - 1, -1, -1):
+        cov = level_present(grid, levels, l + 1)[0::2, 0::2]
+        full[l] = np.where(cov, child_mean(full[l + 1]), full[l])
+    return [full[0]] + [full_to_blocks(grid, levels[l - 1], full[l])
+                        for l in range(1, L + 1)]
+
+
+def hier_coefficients(grid, levels, E, rho, kappa):
+    views = [hier_views(grid, levels, f)[0] for f in (E, rho, kappa)]
+    return [F.diffusion_coefficient(views[0][l], views[1][l], views[2][l],
+                                    level_problem(grid, l))[0]
+            for l in range(len(levels) + 1)]
+
+
+def hier_step(grid, levels, E, rho, kappa, dt, method="splu"):
+    """E* on every leaf cell of a hierarchy; fields and result as lists
+    [base, level-1 blocks, ...]."""
+    D = hier_coefficients(grid, levels, E, rho, kappa)
+    A, _ = hier_assemble(grid, levels, D, dt)
+    b = hier_to_leaf(grid, levels, E)
+    x = np.linalg.solve(A.toarray(), b) if method == "dense" else \
+        spla.splu(A.tocsc()).solve(b)
+    return hier_from_leaf(grid, levels, x)

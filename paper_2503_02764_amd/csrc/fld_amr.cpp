@@ -44,9 +44,9 @@ struct fld_amr_ctx {
   fld_params p{};
   fld_ctx* base = nullptr;
   hipStream_t stream = nullptr;
-  int* bmap = nullptr;
-  int* bxy = nullptr;
   double *Ev = nullptr, *rv = nullptr, *kv = nullptr;
+  double *Evf = nullptr, *rvf = nullptr, *kvf = nullptr;  // fine views
+  double* t = nullptr;  // preconditioner temporary (a leaf vector)
   double *Db = nullptr, *Df = nullptr, *cf = nullptr, *rhs = nullptr;
   double *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr;
   double *p2[2] = {}, *q2[2] = {};
@@ -106,8 +106,11 @@ fld_params base_params(const fld_params& p) {
   return q;
 }
 
-std::string validate_amr(const fld_params* p, int32_t block,
-                         const int32_t* blocks_xy, int32_t nblocks) {
+// Levels: nlevels entries of nblocks; blocks_xy holds the (bx, by) of
+// level 1's blocks, then level 2's, ...  A level-l block refines the b x b
+// patch of level-(l-1) cells with corner (bx b, by b).
+std::string validate_amr(const fld_params* p, int32_t block, int32_t nlevels,
+                         const int32_t* nblocks, const int32_t* blocks_xy) {
   if (!p) return "params is NULL";
   if (p->ndim != 2) return "the block-adaptive step is 2D (ndim = 2)";
   if (p->precision != FLD_PREC_FP64) return "precision must be FP64";
@@ -122,32 +125,71 @@ std::string validate_amr(const fld_params* p, int32_t block,
   if (p->n[0] < 4 || p->n[1] < 4) return "the base grid needs >= 4 x 4 cells";
   if (p->n[0] % block || p->n[1] % block)
     return "the base grid's sides must be multiples of block";
-  if (nblocks < 0) return "nblocks must be >= 0";
-  if (nblocks > 0 && !blocks_xy) return "blocks_xy is NULL";
-  const int64_t nbx = p->n[0] / block, nby = p->n[1] / block;
-  std::vector<char> seen((size_t)(nbx * nby), 0);
-  for (int32_t k = 0; k < nblocks; ++k) {
-    const int32_t bx = blocks_xy[2 * k], by = blocks_xy[2 * k + 1];
-    if (bx < 0 || by < 0 || bx >= nbx || by >= nby)
-      return "a refined block lies outside the base grid";
-    char& s = seen[(size_t)(by * nbx + bx)];
-    if (s) return "a block is listed twice";
-    s = 1;
+  if (nlevels < 0 || nlevels > kAmrMaxLevels) return "nlevels must be in [0, 4]";
+  if (nlevels > 0 && !nblocks) return "nblocks is NULL";
+  int64_t total = 0;
+  for (int l = 0; l < nlevels; ++l) {
+    if (nblocks[l] < 0) return "nblocks must be >= 0";
+    if (l > 0 && nblocks[l] > 0 && nblocks[l - 1] == 0)
+      return "a level follows an empty one";
+    total += nblocks[l];
+  }
+  if (total > 0 && !blocks_xy) return "blocks_xy is NULL";
+  const bool per[2] = {p->bc_lo[0] == FLD_BC_PERIODIC,
+                       p->bc_lo[1] == FLD_BC_PERIODIC};
+  // units (b cells) of each level's lattice, and which hold a block
+  std::vector<std::vector<char>> has(nlevels + 1);
+  const int32_t* xy = blocks_xy;
+  for (int l = 1; l <= nlevels; ++l) {
+    const int64_t ux = (p->n[0] << (l - 1)) / block;
+    const int64_t uy = (p->n[1] << (l - 1)) / block;
+    has[l].assign((size_t)(ux * uy), 0);
+    for (int32_t k = 0; k < nblocks[l - 1]; ++k, xy += 2) {
+      const int32_t bx = xy[0], by = xy[1];
+      if (bx < 0 || by < 0 || bx >= ux || by >= uy)
+        return "a refined block lies outside its level's lattice";
+      char& sl = has[l][(size_t)(by * ux + bx)];
+      if (sl) return "a block is listed twice";
+      sl = 1;
+      if (l == 1) continue;
+      // nested: inside a level-(l-1) block (whose corner unit is (bx/2,
+      // by/2) of level l-2); 2:1: so are the four face-adjacent patches
+      const int64_t pux = (p->n[0] << (l - 2)) / block;
+      auto inside = [&](int64_t x, int64_t y) {
+        if (x < 0 || x >= ux) {
+          if (!per[0]) return true;  // a wall
+          x = (x + ux) % ux;
+        }
+        if (y < 0 || y >= uy) {
+          if (!per[1]) return true;
+          y = (y + uy) % uy;
+        }
+        return has[l - 1][(size_t)((y / 2) * pux + x / 2)] != 0;
+      };
+      if (!inside(bx, by)) return "a block lies outside the coarser level";
+      if (!inside(bx - 1, by) || !inside(bx + 1, by) || !inside(bx, by - 1) ||
+          !inside(bx, by + 1))
+        return "levels not 2:1 nested: a block's face neighbour is two "
+               "levels coarser";
+    }
   }
   return "";
 }
 
 struct AmrPlan {
-  size_t base_ws = 0, bmap = 0, bxy = 0, views = 0, Db = 0, Df = 0, cf = 0;
+  size_t base_ws = 0, bmap[kAmrMaxLevels] = {}, bxy[kAmrMaxLevels] = {};
+  size_t views = 0, fviews = 0, Db = 0, Df = 0, cf = 0;
   size_t rhs = 0, vec = 0, partials = 0, sc = 0, bad = 0, total = 0;
   int64_t Nb = 0, Nf = 0, nvec = 0;
   int dot_blocks = 0;
 };
 
-AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nblocks) {
+AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nlevels,
+                      const int32_t* nblocks) {
   AmrPlan P;
   P.Nb = p.n[0] * p.n[1];
-  P.Nf = (int64_t)nblocks * 4 * block * block;
+  for (int l = 0; l < nlevels; ++l)
+    P.Nf += (int64_t)nblocks[l] * 4 * block * block;
   P.nvec = P.Nb + P.Nf;
   P.dot_blocks = (int)((P.nvec + 255) / 256);
   size_t o = 0;
@@ -158,15 +200,19 @@ AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nblocks) {
   };
   const fld_params bp = base_params(p);
   P.base_ws = take(fld_workspace_bytes(&bp));
-  const int64_t nbb = (p.n[0] / block) * (p.n[1] / block);
-  P.bmap = take((size_t)nbb * 4);
-  P.bxy = take((size_t)nblocks * 8);
+  for (int l = 1; l <= nlevels; ++l) {
+    const int64_t units = ((p.n[0] << (l - 1)) / block) *
+                          ((p.n[1] << (l - 1)) / block);
+    P.bmap[l - 1] = take((size_t)units * 4);
+    P.bxy[l - 1] = take((size_t)nblocks[l - 1] * 8);
+  }
   P.views = take((size_t)P.Nb * 8 * 3);
+  P.fviews = take((size_t)P.Nf * 8 * 3);
   P.Db = take((size_t)P.Nb * 8);
   P.Df = take((size_t)P.Nf * 8);
   P.cf = take((size_t)P.Nf * 8 * 4);
   P.rhs = take((size_t)P.Nb * 8);
-  P.vec = take((size_t)P.nvec * 8 * 8);  // x, b, r, z, p[2], q[2]
+  P.vec = take((size_t)P.nvec * 8 * 9);  // x, b, r, z, p[2], q[2], t
   P.partials = take((size_t)P.dot_blocks * 3 * 8);
   P.sc = take(8 * 8);
   P.bad = take(8);
@@ -197,29 +243,44 @@ fld_status dots(fld_amr_ctx* c, int n, const double* u0, const double* v0,
   return FLD_OK;
 }
 
-// z = M r (the two-level cycle of the file comment)
+// z = M r (the cycle of the file comment)
 fld_status precondition(fld_amr_ctx* c, const double* r, double* z) {
   const AmrGeom& G = c->G;
   hipStream_t s = c->stream;
-  AMR_HIP(c, hipMemsetAsync(z, 0, sizeof(double) * (G.Nb + G.Nf), s));
+  const int64_t n = G.Nb + G.Nf;
+  AMR_HIP(c, hipMemsetAsync(z, 0, sizeof(double) * n, s));
   const int pre = std::max(c->p.pre_smooth, 1);
   const int post = std::max(c->p.post_smooth, 1);
   for (int k = 0; k < pre; ++k)
-    for (int colour = 0; colour < 2; ++colour) {
-      const bool timed = c->timing && !c->timed_this_step;
-      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s,
-                            timed ? c->ev[0] : nullptr,
-                            timed ? c->ev[1] : nullptr));
-      if (timed) c->timed_this_step = true;
-    }
-  AMR_HIP(c, amr_base_rhs(G, c->cf, r, z, c->rhs, s));
+    for (int l = G.L; l >= 1; --l)  // finest level first
+      for (int colour = 0; colour < 2; ++colour) {
+        const bool timed = c->timing && !c->timed_this_step && l == 1;
+        AMR_HIP(c, amr_smooth(G, l, c->cf, r, z, colour, s,
+                              timed ? c->ev[0] : nullptr,
+                              timed ? c->ev[1] : nullptr));
+        if (timed) c->timed_this_step = true;
+      }
+  // the residual of the smoothed correction, restricted level by level
+  const double* ax = nullptr;
+  const double* ay = nullptr;
+  base_faces(c->base, &ax, &ay);
+  AMR_HIP(c, amr_apply(G, ax, ay, c->cf, z, c->t, s));
+  AMR_HIP(c, amr_axpy(n, -1.0, c->t, r, c->t, s));
+  for (int l = G.L - 1; l >= 1; --l)
+    AMR_HIP(c, amr_restrict_level(G, l, c->t, s));
+  AMR_HIP(c, amr_base_rhs(G, c->t, c->rhs, s));
   const fld_status st = precond_vcycle(c->base, c->rhs, z);
   if (st != FLD_OK)
     return amr_fail(c, st, "base V-cycle: %s", ctx_error(c->base));
-  AMR_HIP(c, amr_prolong(G, z, s));
+  // the base correction prolonged level by level onto every fine cell
+  AMR_HIP(c, hipMemcpyAsync(c->t, z, sizeof(double) * G.Nb,
+                            hipMemcpyDeviceToDevice, s));
+  for (int l = 1; l <= G.L; ++l) AMR_HIP(c, amr_prolong_level(G, l, c->t, s));
+  AMR_HIP(c, amr_axpy(G.Nf, 1.0, c->t + G.Nb, z + G.Nb, z + G.Nb, s));
   for (int k = 0; k < post; ++k)
-    for (int colour = 1; colour >= 0; --colour)
-      AMR_HIP(c, amr_smooth(G, c->cf, r, z, colour, s));
+    for (int l = 1; l <= G.L; ++l)
+      for (int colour = 1; colour >= 0; --colour)
+        AMR_HIP(c, amr_smooth(G, l, c->cf, r, z, colour, s));
   AMR_HIP(c, amr_zero_covered(G, z, s));
   return FLD_OK;
 }
@@ -235,10 +296,10 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   c->timed_this_step = false;
   // coefficients: views, D on both levels, fine faces, base faces
   AMR_HIP(c, amr_views(G, E_b, rho_b, kap_b, E_f, rho_f, kap_f, c->Ev, c->rv,
-                       c->kv, s));
+                       c->kv, c->Evf, c->rvf, c->kvf, s));
   AMR_HIP(c, hipMemsetAsync(c->bad, 0, sizeof(int), s));
-  AMR_HIP(c, amr_coefficients(G, c->P, dt, c->Ev, c->rv, c->kv, E_f, rho_f,
-                              kap_f, c->Db, c->Df, c->cf, c->bad, s));
+  AMR_HIP(c, amr_coefficients(G, c->P, dt, c->Ev, c->rv, c->kv, c->Evf,
+                              c->rvf, c->kvf, c->Db, c->Df, c->cf, c->bad, s));
   int bad = 0;
   AMR_HIP(c, hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost,
                             s));
@@ -312,7 +373,8 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
     c->t_launches += 1;
     // one colour: r and the four faces of half the fine cells read, z of
     // every fine cell read once, half of z written
-    c->t_bytes += 8.0 * (double)G.Nf * (0.5 + 2.0 + 1.0 + 0.5);
+    c->t_bytes += 8.0 * (double)(G.off[1] - G.off[0]) *
+                  (0.5 + 2.0 + 1.0 + 0.5);
   }
   if (stats) {
     stats->cycles = k;
@@ -334,23 +396,30 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
 
 extern "C" {
 
-size_t fld_amr_workspace_bytes(const fld_params* p, int32_t block,
-                               const int32_t* blocks_xy, int32_t nblocks) {
-  if (!validate_amr(p, block, blocks_xy, nblocks).empty()) return 0;
+size_t fld_amr_workspace_bytes_levels(const fld_params* p, int32_t block,
+                                      int32_t nlevels, const int32_t* nblocks,
+                                      const int32_t* blocks_xy) {
+  if (!validate_amr(p, block, nlevels, nblocks, blocks_xy).empty()) return 0;
   const fld_params bp = base_params(*p);
   if (fld_workspace_bytes(&bp) == 0) return 0;
-  return make_amr_plan(*p, block, nblocks).total;
+  return make_amr_plan(*p, block, nlevels, nblocks).total;
 }
 
-fld_status fld_amr_setup(const fld_params* p, int32_t block,
-                         const int32_t* blocks_xy, int32_t nblocks,
-                         void* workspace, size_t ws_bytes, void* hip_stream,
-                         fld_amr_ctx** out) {
+size_t fld_amr_workspace_bytes(const fld_params* p, int32_t block,
+                               const int32_t* blocks_xy, int32_t nblocks) {
+  return fld_amr_workspace_bytes_levels(p, block, 1, &nblocks, blocks_xy);
+}
+
+fld_status fld_amr_setup_levels(const fld_params* p, int32_t block,
+                                int32_t nlevels, const int32_t* nblocks,
+                                const int32_t* blocks_xy, void* workspace,
+                                size_t ws_bytes, void* hip_stream,
+                                fld_amr_ctx** out) {
   if (!out) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  const std::string why = validate_amr(p, block, blocks_xy, nblocks);
+  const std::string why = validate_amr(p, block, nlevels, nblocks, blocks_xy);
   if (!why.empty()) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "%s", why.c_str());
-  const AmrPlan P = make_amr_plan(*p, block, nblocks);
+  const AmrPlan P = make_amr_plan(*p, block, nlevels, nblocks);
   if (!workspace || ws_bytes < P.total)
     return amr_fail(nullptr, FLD_ERR_WORKSPACE,
                     "workspace of %zu bytes needed", P.total);
@@ -375,47 +444,64 @@ fld_status fld_amr_setup(const fld_params* p, int32_t block,
   G.S = 2 * block;
   G.nbx = G.nx / block;
   G.nby = G.ny / block;
-  G.nbf = nblocks;
   for (int d = 0; d < 2; ++d) G.per[d] = p->bc_lo[d] == FLD_BC_PERIODIC;
   G.Nb = P.Nb;
   G.Nf = P.Nf;
   G.dx = p->dx[0];
   G.dy = p->dx[1];
   G.vb = G.dx * G.dy;
-  G.vf = 0.25 * G.vb;
-  c->bmap = (int*)(w + P.bmap);
-  c->bxy = (int*)(w + P.bxy);
-  G.bmap = c->bmap;
-  G.bxy = c->bxy;
+  G.L = 0;
+  G.off[0] = 0;
+  for (int l = 1; l <= nlevels; ++l)
+    if (nblocks[l - 1] > 0) G.L = l;
+  // tables: the block of every unit of each level's parent lattice, each
+  // block's corner
+  std::vector<std::vector<int>> maps(nlevels), corners(nlevels);
+  const int32_t* xy = blocks_xy;
+  for (int l = 1; l <= nlevels; ++l) {
+    const int ux = (G.nx << (l - 1)) / block, uy = (G.ny << (l - 1)) / block;
+    G.units_x[l - 1] = ux;
+    G.nblk[l - 1] = nblocks[l - 1];
+    G.off[l] = G.off[l - 1] + (int64_t)nblocks[l - 1] * G.S * G.S;
+    maps[l - 1].assign((size_t)ux * uy, -1);
+    corners[l - 1].resize((size_t)2 * nblocks[l - 1]);
+    for (int32_t k = 0; k < nblocks[l - 1]; ++k, xy += 2) {
+      corners[l - 1][2 * k] = xy[0];
+      corners[l - 1][2 * k + 1] = xy[1];
+      maps[l - 1][(size_t)xy[1] * ux + xy[0]] = k;
+    }
+    G.bmap[l - 1] = (int*)(w + P.bmap[l - 1]);
+    G.bxy[l - 1] = (int*)(w + P.bxy[l - 1]);
+  }
   c->P.c = p->c;
   c->P.limiter = p->limiter;
   c->P.face_mean = p->face_mean;
   c->Ev = (double*)(w + P.views);
   c->rv = c->Ev + P.Nb;
   c->kv = c->rv + P.Nb;
+  c->Evf = (double*)(w + P.fviews);
+  c->rvf = c->Evf + P.Nf;
+  c->kvf = c->rvf + P.Nf;
   c->Db = (double*)(w + P.Db);
   c->Df = (double*)(w + P.Df);
   c->cf = (double*)(w + P.cf);
   c->rhs = (double*)(w + P.rhs);
   double* v = (double*)(w + P.vec);
-  double** vecs[8] = {&c->x, &c->b, &c->r, &c->z,
-                      &c->p2[0], &c->p2[1], &c->q2[0], &c->q2[1]};
-  for (int k = 0; k < 8; ++k) *vecs[k] = v + (size_t)k * P.nvec;
+  double** vecs[9] = {&c->x, &c->b, &c->r, &c->z, &c->p2[0],
+                      &c->p2[1], &c->q2[0], &c->q2[1], &c->t};
+  for (int k = 0; k < 9; ++k) *vecs[k] = v + (size_t)k * P.nvec;
   c->partials = (double*)(w + P.partials);
   c->sc = (double*)(w + P.sc);
   c->bad = (int*)(w + P.bad);
-  // tables: the refined block of every base block, each block's corner
-  std::vector<int> bmap((size_t)G.nbx * G.nby, -1), bxy((size_t)2 * nblocks);
-  for (int32_t k = 0; k < nblocks; ++k) {
-    bxy[2 * k] = blocks_xy[2 * k];
-    bxy[2 * k + 1] = blocks_xy[2 * k + 1];
-    bmap[(size_t)blocks_xy[2 * k + 1] * G.nbx + blocks_xy[2 * k]] = k;
-  }
-  hipError_t e = hipMemcpyAsync(c->bmap, bmap.data(), bmap.size() * 4,
-                                hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess && nblocks > 0)
-    e = hipMemcpyAsync(c->bxy, bxy.data(), bxy.size() * 4,
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < nlevels && e == hipSuccess; ++l) {
+    e = hipMemcpyAsync((void*)G.bmap[l], maps[l].data(), maps[l].size() * 4,
                        hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !corners[l].empty())
+      e = hipMemcpyAsync((void*)G.bxy[l], corners[l].data(),
+                         corners[l].size() * 4, hipMemcpyHostToDevice,
+                         c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     fld_destroy(c->base);
@@ -427,6 +513,14 @@ fld_status fld_amr_setup(const fld_params* p, int32_t block,
   return FLD_OK;
 }
 
+fld_status fld_amr_setup(const fld_params* p, int32_t block,
+                         const int32_t* blocks_xy, int32_t nblocks,
+                         void* workspace, size_t ws_bytes, void* hip_stream,
+                         fld_amr_ctx** out) {
+  return fld_amr_setup_levels(p, block, 1, &nblocks, blocks_xy, workspace,
+                              ws_bytes, hip_stream, out);
+}
+
 fld_status fld_amr_step(fld_amr_ctx* c, double dt, const double* rho_base,
                         const double* kappa_base, const double* E_base_in,
                         double* E_base_out, const double* rho_fine,
@@ -435,7 +529,7 @@ fld_status fld_amr_step(fld_amr_ctx* c, double dt, const double* rho_base,
   if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   if (!rho_base || !kappa_base || !E_base_in || !E_base_out)
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
-  if (c->G.nbf > 0 && (!rho_fine || !kappa_fine || !E_fine_in || !E_fine_out))
+  if (c->G.Nf > 0 && (!rho_fine || !kappa_fine || !E_fine_in || !E_fine_out))
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
   if (!(dt > 0.0) || !std::isfinite(dt))
     return amr_fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
@@ -452,14 +546,14 @@ fld_status fld_amr_exchange(fld_amr_ctx* c, double dt, const double* rho_base,
   if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   if (!rho_base || !kappa_base || !E_base || !e_base)
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
-  if (c->G.nbf > 0 && (!rho_fine || !kappa_fine || !E_fine || !e_fine))
+  if (c->G.Nf > 0 && (!rho_fine || !kappa_fine || !E_fine || !e_fine))
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
   if (!(dt > 0.0) || !std::isfinite(dt))
     return amr_fail(c, FLD_ERR_INVALID_ARG, "dt must be positive and finite");
   const fld_params& p = c->p;
   AMR_HIP(c, launch_exchange(c->G.Nb, dt, p.c, p.a_rad, p.gamma, p.gas_const,
                              rho_base, kappa_base, E_base, e_base, c->stream));
-  if (c->G.nbf > 0)
+  if (c->G.Nf > 0)
     AMR_HIP(c, launch_exchange(c->G.Nf, dt, p.c, p.a_rad, p.gamma,
                                p.gas_const, rho_fine, kappa_fine, E_fine,
                                e_fine, c->stream));
@@ -475,7 +569,7 @@ fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* c, const double* rho_base,
   if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
   if (!rho_base || !e_base || !kappa_base)
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL base field pointer");
-  if (c->G.nbf > 0 && (!rho_fine || !e_fine || !kappa_fine))
+  if (c->G.Nf > 0 && (!rho_fine || !e_fine || !kappa_fine))
     return amr_fail(c, FLD_ERR_INVALID_ARG, "NULL fine field pointer");
   if (!(k0 > 0.0) || !(kmin > 0.0) || !(kmax >= kmin) || !std::isfinite(a) ||
       !std::isfinite(b) || !std::isfinite(kmax))
@@ -484,7 +578,7 @@ fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* c, const double* rho_base,
   const fld_params& p = c->p;
   AMR_HIP(c, launch_opacity(c->G.Nb, p.gamma, p.gas_const, rho_base, e_base,
                             k0, a, b, kmin, kmax, kappa_base, c->stream));
-  if (c->G.nbf > 0)
+  if (c->G.Nf > 0)
     AMR_HIP(c, launch_opacity(c->G.Nf, p.gamma, p.gas_const, rho_fine, e_fine,
                               k0, a, b, kmin, kmax, kappa_fine, c->stream));
   return FLD_OK;

@@ -387,7 +387,8 @@ EXPORTED += ["fld_workspace_bytes_batch", "fld_setup_batch", "fld_step_batch",
 EXPORTED += ["fld_amr_workspace_bytes", "fld_amr_setup", "fld_amr_step",
              "fld_amr_last_error", "fld_amr_destroy",
              "fld_amr_kernel_timing_enable", "fld_amr_kernel_timing_read",
-             "fld_amr_exchange", "fld_amr_opacity_powerlaw"]
+             "fld_amr_exchange", "fld_amr_opacity_powerlaw",
+             "fld_amr_workspace_bytes_levels", "fld_amr_setup_levels"]
 
 
 def _amr_argtypes(lib):
@@ -399,6 +400,12 @@ def _amr_argtypes(lib):
     lib.fld_amr_setup.argtypes = [P(fld_params), I32, V, I32, V,
                                   ctypes.c_size_t, V, P(V)]
     lib.fld_amr_setup.restype = ctypes.c_int
+    lib.fld_amr_workspace_bytes_levels.argtypes = [P(fld_params), I32, I32,
+                                                   V, V]
+    lib.fld_amr_workspace_bytes_levels.restype = ctypes.c_size_t
+    lib.fld_amr_setup_levels.argtypes = [P(fld_params), I32, I32, V, V, V,
+                                         ctypes.c_size_t, V, P(V)]
+    lib.fld_amr_setup_levels.restype = ctypes.c_int
     lib.fld_amr_step.argtypes = [V, D, V, V, V, V, V, V, V, V, V]
     lib.fld_amr_step.restype = ctypes.c_int
     lib.fld_amr_last_error.argtypes = [V]
@@ -448,36 +455,53 @@ class AmrCtx:
             self.ptr = None
 
 
+def _levels(blocks):
+    """A list of (bx, by) is one level; a list of such lists, several."""
+    if blocks and isinstance(blocks[0][0], (list, tuple)):
+        return [list(b) for b in blocks]
+    return [list(blocks)]
+
+
+def _levels_arr(levels):
+    counts = (ctypes.c_int32 * max(1, len(levels)))(*[len(b) for b in levels])
+    flat = [int(v) for bl in levels for xy in bl for v in xy]
+    return counts, (ctypes.c_int32 * max(1, len(flat)))(*flat)
+
+
 def fld_amr_workspace_bytes(params, block, blocks):
-    arr, nb = _blocks_arr(blocks)
-    return int(_amrlib().fld_amr_workspace_bytes(ctypes.byref(params), block,
-                                                 arr, nb))
+    levels = _levels(blocks)
+    counts, arr = _levels_arr(levels)
+    return int(_amrlib().fld_amr_workspace_bytes_levels(
+        ctypes.byref(params), block, len(levels), counts, arr))
 
 
 def fld_amr_setup(params, block, blocks, workspace=None, stream=None):
     """Context of a block-adaptive 2D grid: `blocks` lists the refined
-    base blocks as (bx, by)."""
+    base blocks as (bx, by), or is a list of such lists, one per refined
+    level (level l's corners in units of `block` level-(l-1) cells)."""
     import torch
     lib = _amrlib()
-    arr, nb = _blocks_arr(blocks)
+    levels = _levels(blocks)
+    counts, arr = _levels_arr(levels)
     need = fld_amr_workspace_bytes(params, block, blocks)
     out = ctypes.c_void_p()
     if need == 0:
-        st = lib.fld_amr_setup(ctypes.byref(params), block, arr, nb, None, 0,
-                               None, ctypes.byref(out))
+        st = lib.fld_amr_setup_levels(ctypes.byref(params), block,
+                                      len(levels), counts, arr, None, 0, None,
+                                      ctypes.byref(out))
         raise FldError(st, lib.fld_amr_last_error(None).decode())
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
     if stream is None:
         stream = torch.cuda.current_stream()
-    st = lib.fld_amr_setup(ctypes.byref(params), block, arr, nb,
-                           _ptr(workspace, "workspace", dtype=torch.uint8),
-                           workspace.numel(),
-                           ctypes.c_void_p(stream.cuda_stream),
-                           ctypes.byref(out))
+    st = lib.fld_amr_setup_levels(
+        ctypes.byref(params), block, len(levels), counts, arr,
+        _ptr(workspace, "workspace", dtype=torch.uint8), workspace.numel(),
+        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
     if st != FLD_OK:
         raise FldError(st, lib.fld_amr_last_error(None).decode())
-    return AmrCtx(out, params, block, nb, workspace, stream)
+    return AmrCtx(out, params, block, sum(len(b) for b in levels), workspace,
+                  stream)
 
 
 def _amr_fine(ctx, t, name):

@@ -66,7 +66,11 @@ M = [
  ("fldref.py", "b = np.where(held, E_hold, E + rhs).ravel()", "b = np.where(held, E_hold, E).ravel()", "held step without the Dirichlet walls' rhs"),
  ("fldref.py", "A = (free_rows @ A + sp.diags(h.astype(np.float64))).tocsr()", "A = A.tocsr()", "held rows not replaced"),
  ("fldref.py", "A = (free_rows @ A + sp.diags(h.astype(np.float64))).tocsr()", "A = (free_rows @ A @ free_rows + sp.diags(h.astype(np.float64))).tocsr()", "free cells decoupled from the held values"),
- ("amr.py", "beta = (2.0 / 3.0) * dt * _mean(", "beta = dt * _mean(", "coarse-fine flux over one fine spacing"),
+ ("amr.py", "beta = (2.0 / 3.0) * dt * _mean(\n                            Df[J, I]", "beta = dt * _mean(\n                            Df[J, I]", "coarse-fine flux over one fine spacing"),
+ ("amr.py", "beta = (2.0 / 3.0) * dt * _mean(\n                                D[l][J, I]", "beta = dt * _mean(\n                                D[l][J, I]", "hierarchy: coarse-fine flux over one fine spacing"),
+ ("amr.py", "couple(me, c, beta, beta / 4.0)", "couple(me, c, beta, beta / 2.0)", "hierarchy: coarser side of an edge at 1/2"),
+ ("amr.py", "child_mean(avg[l + 1])", "vals[l]", "hierarchy: covered cells keep their own values"),
+ ("amr.py", "view.append(np.where(present[l], avg[l], inject(view[l - 1])))", "view.append(np.where(present[l], avg[l], inject(avg[l - 1]) * 0 + 1.0))", "hierarchy: outside a level's blocks a constant view"),
  ("amr.py", "couple(fidx[J, I], bidx[cb], beta, beta / 4.0)", "couple(fidx[J, I], bidx[cb], beta, beta / 2.0)", "base side of a block edge at 1/2"),
  ("amr.py", "cb = (JJ // 2, II // 2)", "cb = ((JJ // 2) % grid.ny, (I // 2) % grid.nx)", "coarse neighbour taken along the wrong axis"),
  ("amr.py", "base_view = np.where(ref, child_mean(fine_full), base)", "base_view = base", "covered base cells keep their own values"),

@@ -259,3 +259,99 @@ def test_split_step_opacity_diffusion_exchange():
         E_ref, e_ref = F.exchange(E_in, e_in, rho, kap, dt, prob)
         np.testing.assert_allclose(host(E_d), E_ref, rtol=1e-12)
         np.testing.assert_allclose(host(e_d), e_ref, rtol=1e-12)
+
+
+# ---- deeper hierarchies ----------------------------------------------------
+
+def _hier_run(g, levels, E, rho, kap, dt, **kw):
+    from paper_2503_02764_amd import fld
+    cat = lambda fs: np.concatenate([f.reshape(-1) for f in fs[1:]]) \
+        if len(fs) > 1 else np.zeros(0)  # noqa: E731
+    ctx = fld.fld_amr_setup(_params(g, **kw), g.b, levels)
+    ob = dev(np.zeros_like(E[0]))
+    ef = cat(E)
+    of = dev(np.zeros_like(ef))
+    _, stats = fld.fld_amr_step(ctx, dt, dev(rho[0]), dev(kap[0]), dev(E[0]),
+                                ob, dev(cat(rho)), dev(cat(kap)), dev(ef), of)
+    out_f, k = host(of), 0
+    per_level = [host(ob)]
+    s = 2 * g.b
+    for bl in levels:
+        n = len(bl) * s * s
+        per_level.append(out_f[k:k + n].reshape(len(bl), s, s))
+        k += n
+    return per_level, stats
+
+
+def _hier_medium(g, levels, seed):
+    rng = np.random.default_rng(seed)
+    s = 2 * g.b
+    out = []
+    for scale, amp in ((1.0, 0.3), (1.0, 0.4), (20.0, 0.8)):
+        f = [scale * np.exp(amp * rng.standard_normal((g.ny, g.nx)))]
+        f += [scale * np.exp(amp * rng.standard_normal((len(bl), s, s)))
+              for bl in levels]
+        out.append(f)
+    return out
+
+
+@pytest.mark.parametrize("limiter", ["lp", "minerbo"])
+@pytest.mark.parametrize("bc", [(F.PERIODIC, F.NEUMANN),
+                                (F.NEUMANN, F.NEUMANN)])
+def test_two_levels_vs_oracle(limiter, bc):
+    g = M.AmrGrid(nx=32, ny=32, dx=1 / 32, dy=1 / 32, b=4, bc=bc, blocks=[],
+                  limiter=limiter)
+    lv1 = [(i, j) for j in range(2, 6) for i in range(2, 6)]   # base 8..23
+    lv2 = [(i, j) for j in range(5, 11) for i in range(5, 11)]  # inside, 2:1
+    E, rho, kap = _hier_medium(g, [lv1, lv2], 31)
+    announce(f"amr two levels {limiter} {bc}")
+    got, stats = _hier_run(g, [lv1, lv2], E, rho, kap, 0.02)
+    ref = M.hier_step(g, [lv1, lv2], E, rho, kap, 0.02)
+    assert stats["rel_res_final"] <= 1e-12, stats
+    r = rel_l2(M.hier_to_leaf(g, [lv1, lv2], got),
+               M.hier_to_leaf(g, [lv1, lv2], ref))
+    assert r <= 1e-10, (r, stats)
+    for l in (0, 1):  # cells under finer blocks: their children's mean
+        np.testing.assert_allclose(got[l], ref[l], rtol=1e-9)
+
+
+def test_two_levels_everything_refined_is_the_uniform_step():
+    g = M.AmrGrid(nx=8, ny=8, dx=1 / 8, dy=1 / 8, b=4,
+                  bc=(F.PERIODIC, F.NEUMANN), blocks=[])
+    lv1 = [(i, j) for j in range(2) for i in range(2)]
+    lv2 = [(i, j) for j in range(4) for i in range(4)]
+    E, rho, kap = _hier_medium(g, [lv1, lv2], 32)
+    announce("amr two levels everything refined")
+    got, _ = _hier_run(g, [lv1, lv2], E, rho, kap, 0.01)
+    z = np.zeros((32, 32))
+    full = lambda a: M.blocks_to_full(g, lv2, a, z)  # noqa: E731
+    ref = F.diffusion_step(full(E[2]), full(rho[2]), full(kap[2]), 0.01,
+                           M.level_problem(g, 2))
+    assert rel_l2(full(got[2]), ref) <= 1e-10
+
+
+def test_three_levels_around_a_front():
+    g = M.AmrGrid(nx=64, ny=64, dx=1 / 64, dy=1 / 64, b=8,
+                  bc=(F.PERIODIC, F.NEUMANN), blocks=[], limiter="lp")
+    lv1 = [(i, j) for j in (2, 3, 4, 5) for i in range(8)]        # base rows 16..47
+    lv2 = [(i, j) for j in (5, 6, 7, 8, 9, 10) for i in range(16)]  # l1 rows 40..87
+    lv3 = [(i, j) for j in (12, 13, 14, 15, 16, 17, 18, 19) for i in range(32)]
+    levels = [lv1, lv2, lv3]
+    E, rho, kap = _hier_medium(g, levels, 33)
+    announce("amr three levels")
+    got, stats = _hier_run(g, levels, E, rho, kap, 0.005)
+    ref = M.hier_step(g, levels, E, rho, kap, 0.005)
+    r = rel_l2(M.hier_to_leaf(g, levels, got), M.hier_to_leaf(g, levels, ref))
+    assert stats["rel_res_final"] <= 1e-12 and r <= 1e-10, (r, stats)
+
+
+def test_unbalanced_levels_are_refused():
+    from paper_2503_02764_amd import fld
+    g = M.AmrGrid(nx=16, ny=16, dx=1 / 16, dy=1 / 16, b=4,
+                  bc=(F.PERIODIC, F.NEUMANN), blocks=[])
+    p = _params(g)
+    assert fld.fld_amr_workspace_bytes(p, 4, [[(1, 1)], [(2, 2)]]) == 0
+    assert fld.fld_amr_workspace_bytes(p, 4, [[(1, 1)], [(5, 5)]]) == 0
+    ok = [[(1, 1), (2, 1), (1, 2), (2, 2), (0, 1), (3, 1), (1, 0), (1, 3),
+           (0, 2), (3, 2), (2, 0), (2, 3)], [(3, 3)]]
+    assert fld.fld_amr_workspace_bytes(p, 4, ok) > 0

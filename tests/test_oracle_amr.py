@@ -167,3 +167,133 @@ def test_covered_base_values_do_not_matter():
     x1 = M.amr_step(g, Eb2, rb, kb, Ef, rf, kf, 0.4)
     np.testing.assert_array_equal(x0[0], x1[0])
     np.testing.assert_array_equal(x0[1], x1[1])
+
+
+# ---- deeper hierarchies (hier_*) ------------------------------------------
+
+def _hier_fields(g, levels, seed, lo=1.0):
+    rng = np.random.default_rng(seed)
+    s = 2 * g.b
+    out = []
+    for amp in (1.0, 1.0, 3.0):
+        f = [lo + amp * rng.random((g.ny, g.nx))]
+        f += [lo + amp * rng.random((len(bl), s, s)) for bl in levels]
+        out.append(f)
+    return out
+
+
+def test_one_level_hierarchy_is_the_one_level_step():
+    g = _grid([(1, 1), (2, 1), (0, 3)])
+    (Eb, Ef), (rb, rf), (kb, kf) = _fields(g, 21)
+    x1 = M.amr_step(g, Eb, rb, kb, Ef, rf, kf, 0.3)
+    x2 = M.hier_step(g, [g.blocks], [Eb, Ef], [rb, rf], [kb, kf], 0.3)
+    np.testing.assert_array_equal(x1[0], x2[0])
+    np.testing.assert_array_equal(x1[1], x2[1])
+
+
+def test_two_levels_everything_refined_is_the_uniform_step_at_4x():
+    g = _grid([], nx=8, ny=8, b=4)
+    lv1 = [(i, j) for j in range(2) for i in range(2)]
+    lv2 = [(i, j) for j in range(4) for i in range(4)]
+    E, rho, kap = _hier_fields(g, [lv1, lv2], 22)
+    x = M.hier_step(g, [lv1, lv2], E, rho, kap, 0.05)
+    z = np.zeros((32, 32))
+    full = lambda a: M.blocks_to_full(g, lv2, a, z)  # noqa: E731
+    ref = F.diffusion_step(full(E[2]), full(rho[2]), full(kap[2]), 0.05,
+                           M.level_problem(g, 2))
+    np.testing.assert_allclose(full(x[2]), ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_linear_field_across_two_levels_of_edges(axis):
+    # strips across the other axis at both levels: every edge is normal to
+    # `axis`; uniform D and a linear E give no flux divergence off the walls
+    g = _grid([], bc=(F.NEUMANN, F.PERIODIC) if axis == 0 else
+              (F.PERIODIC, F.NEUMANN), limiter="diffusion")
+    if axis == 0:
+        lv1 = [(1, k) for k in range(4)] + [(2, k) for k in range(4)]
+        lv2 = [(3, k) for k in range(8)]   # inside level-1 column 1
+    else:
+        lv1 = [(k, 1) for k in range(4)] + [(k, 2) for k in range(4)]
+        lv2 = [(k, 3) for k in range(8)]
+    levels = [lv1, lv2]
+    fields = []
+    for f in (lambda c: 3.0 + 2.0 * c, lambda c: 1.0 + 0.0 * c,
+              lambda c: 3.0 + 0.0 * c):
+        per_level = []
+        for l in range(3):
+            ny, nx = M.level_lattice(g, l)
+            h = (g.dx, g.dy)[axis] / (1 << l)
+            c = (np.arange((nx, ny)[axis]) + 0.5) * h
+            full = np.broadcast_to(f(c) if axis == 0 else f(c)[:, None],
+                                   (ny, nx)).copy()
+            per_level.append(full if l == 0 else
+                             M.full_to_blocks(g, levels[l - 1], full))
+        fields.append(per_level)
+    E, rho, kap = fields
+    D = M.hier_coefficients(g, levels, E, rho, kap)
+    A, _ = M.hier_assemble(g, levels, D, 0.7)
+    e = M.hier_to_leaf(g, levels, E)
+    div = A @ e - e
+    idx, _ = M.hier_numbering(g, levels)
+    for l in range(3):
+        ny, nx = idx[l].shape
+        inner = np.ones((ny, nx), dtype=bool)
+        if axis == 0:
+            inner[:, [0, -1]] = False
+        else:
+            inner[[0, -1], :] = False
+        m = (idx[l] >= 0) & inner
+        assert np.max(np.abs(div[idx[l][m]])) < 1e-11, l
+
+
+def test_two_levels_conserve_and_are_symmetric():
+    g = _grid([], bc=(F.PERIODIC, F.NEUMANN), limiter="minerbo")
+    lv1 = [(1, 1), (2, 1), (1, 2)]
+    # the one unit of b level-1 cells whose face neighbours all lie in
+    # level-1 blocks (2:1 nesting)
+    lv2 = [(3, 3)]
+    E, rho, kap = _hier_fields(g, [lv1, lv2], 23)
+    D = M.hier_coefficients(g, [lv1, lv2], E, rho, kap)
+    A, vol = M.hier_assemble(g, [lv1, lv2], D, 0.4)
+    S = (sp_diag(vol) @ A).toarray()
+    np.testing.assert_allclose(S, S.T, rtol=1e-13, atol=0)
+    x = M.hier_step(g, [lv1, lv2], E, rho, kap, 0.4)
+    before = vol @ M.hier_to_leaf(g, [lv1, lv2], E)
+    assert vol @ M.hier_to_leaf(g, [lv1, lv2], x) == pytest.approx(before,
+                                                                    rel=1e-13)
+
+
+def test_unbalanced_levels_are_refused():
+    # a level-2 block on the edge of its level-1 block whose outside
+    # neighbour is a base cell: two levels across one face
+    g = _grid([])
+    lv1 = [(1, 1)]
+    lv2 = [(2, 2)]                      # level-1 cells 8..11: edge of block (1,1)
+    E, rho, kap = _hier_fields(g, [lv1, lv2], 24)
+    with pytest.raises(ValueError):
+        M.hier_step(g, [lv1, lv2], E, rho, kap, 0.1)
+
+
+def test_views_of_an_injected_field():
+    # fields that are the base field copied down to every level: each
+    # level's view (inside and outside its blocks) is that copy, so each
+    # level's D is the uniform grid's D of the copied field
+    g = _grid([], limiter="lp")
+    lv1 = [(1, 1), (2, 1), (1, 2)]
+    lv2 = [(3, 3)]
+    rng = np.random.default_rng(25)
+    base = [1.0 + rng.random((g.ny, g.nx)) for _ in range(3)]
+    fields = []
+    for f in base:
+        per_level, full = [f], f
+        for l, bl in enumerate((lv1, lv2), start=1):
+            full = M.inject(full)
+            per_level.append(M.full_to_blocks(g, bl, full))
+        fields.append(per_level)
+    D = M.hier_coefficients(g, [lv1, lv2], *fields)
+    full = [f for f in base]
+    for l in (1, 2):
+        full = [M.inject(f) for f in full]
+        ref, _, _ = F.diffusion_coefficient(*full, M.level_problem(g, l))
+        np.testing.assert_allclose(D[l], ref, rtol=1e-14)
