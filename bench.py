@@ -779,60 +779,85 @@ def run_c4(steps, warmup):
     }
 
 
-def run_amr(steps, warmup):
+def run_amr(steps, warmup, one_level_only=False):
     """The block-adaptive 2D step: the 1024^2 Kramers / log-normal medium as
     the base grid (16 x 16 blocks), the 1/8 of the blocks with the steepest
     log E refined (fine fields interpolated from the base), FP64 flexible
     CG to rel. residual 1e-8 preconditioned by fine sweeps around a base
     V-cycle; E stepped in place, rho and kappa fixed.  Throughput counts
-    leaf cells."""
+    leaf cells.  A second variant refines half of the 2:1-eligible patches
+    of level 1 again (two refined levels)."""
     import numpy as np
     import torch
     import media
     from paper_2503_02764_amd import fld
     from paper_2503_02764_amd.solver import make_params
-    w = media.config_amr()
-    n, b = w["n"], w["b"]
-    leaf = n * n - len(w["blocks"]) * b * b + w["E_f"].size
+
+    def leaf_cells(w):
+        levels = w["blocks"] if w["blocks"] and isinstance(
+            w["blocks"][0][0], (list, tuple)) else [w["blocks"]]
+        n, b = w["n"], w["b"]
+        cells = n * n - len(levels[0]) * b * b
+        for k, bl in enumerate(levels):
+            cells += len(bl) * 4 * b * b
+            if k + 1 < len(levels):
+                cells -= len(levels[k + 1]) * b * b
+        return cells, len(levels)
 
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        p = make_params(2, (n, n), (w["dx"], w["dx"]), w["bc"], rtol=1e-8,
-                        pre_smooth=PRE, post_smooth=POST, max_cycles=200)
-        ctx = fld.fld_amr_setup(p, b, w["blocks"], stream=stream)
-        rb, kb, eb = d(w["rho_b"]), d(w["kappa_b"]), d(w["E_b"])
-        rf, kf, ef = d(w["rho_f"]), d(w["kappa_f"]), d(w["E_f"])
-        for _ in range(warmup):
-            fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf, ef, ef)
-        stream.synchronize()
-        fld.fld_amr_kernel_timing_enable(ctx, True)
-        fld.fld_amr_kernel_timing_read(ctx)
-        iters, res = [], []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            _, st = fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf,
-                                     ef, ef)
-            iters.append(st["cycles"])
-            res.append(st["rel_res_final"])
-        stream.synchronize()
-        secs = time.perf_counter() - t0
-        kt = fld.fld_amr_kernel_timing_read(ctx)
-    del ctx
-    torch.cuda.empty_cache()
-    value = leaf * steps / secs
-    return {"workload": w["name"], "leaf_cells": int(leaf),
-            "refined_blocks": len(w["blocks"]), "block": b, "rtol": 1e-8,
-            "steps": steps, "warmup": warmup, "value": value,
-            "ms_per_step": secs * 1e3 / steps,
-            "iterations_per_step": float(np.mean(iters)),
-            "rel_res_final_max": float(np.max(res)), "dtype": "f64",
+    def one(w, timed_kernel):
+        n, b = w["n"], w["b"]
+        leaf, nlev = leaf_cells(w)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            p = make_params(2, (n, n), (w["dx"], w["dx"]), w["bc"], rtol=1e-8,
+                            pre_smooth=PRE, post_smooth=POST, max_cycles=200)
+            ctx = fld.fld_amr_setup(p, b, w["blocks"], stream=stream)
+            rb, kb, eb = d(w["rho_b"]), d(w["kappa_b"]), d(w["E_b"])
+            rf, kf, ef = d(w["rho_f"]), d(w["kappa_f"]), d(w["E_f"])
+            for _ in range(warmup):
+                fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf, ef, ef)
+            stream.synchronize()
+            if timed_kernel:
+                fld.fld_amr_kernel_timing_enable(ctx, True)
+                fld.fld_amr_kernel_timing_read(ctx)
+            iters, res = [], []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st = fld.fld_amr_step(ctx, w["dt"], rb, kb, eb, eb, rf, kf,
+                                         ef, ef)
+                iters.append(st["cycles"])
+                res.append(st["rel_res_final"])
+            stream.synchronize()
+            secs = time.perf_counter() - t0
+            kt = fld.fld_amr_kernel_timing_read(ctx) if timed_kernel else None
+        del ctx
+        torch.cuda.empty_cache()
+        return dict(workload=w["name"], refined_levels=nlev,
+                    leaf_cells=int(leaf), value=leaf * steps / secs,
+                    ms_per_step=secs * 1e3 / steps,
+                    iterations_per_step=float(np.mean(iters)),
+                    rel_res_final_max=float(np.max(res))), kt
+
+    r1, kt = one(media.config_amr(), True)
+    variants = {"one_refined_level": r1}
+    if not one_level_only:
+        variants["two_refined_levels"], _ = one(media.config_amr(levels=2),
+                                                False)
+    return {"workload": r1["workload"], "leaf_cells": r1["leaf_cells"],
+            "refined_blocks": len(media.config_amr()["blocks"]), "block": 16,
+            "rtol": 1e-8, "steps": steps, "warmup": warmup,
+            "value": r1["value"], "ms_per_step": r1["ms_per_step"],
+            "iterations_per_step": r1["iterations_per_step"],
+            "rel_res_final_max": r1["rel_res_final_max"], "dtype": "f64",
             "cycle": f"FCG; fine RB-GS {PRE}+{POST} around one base V-cycle",
             "roofline": dict(_hbm_roofline(kt, "amr-1024sq-b16") or {},
-                             timed="the first fine red-black half-sweep of "
-                                   "each timed step (events in the library)")}
+                             timed="the first level-1 red-black half-sweep "
+                                   "of each timed step (events in the "
+                                   "library)"),
+            "variants": variants}
 
 
 def _line(metric_value, ms, args, workload, dtype, extra):
@@ -858,6 +883,8 @@ def main():
                     help="keep the default tile shape on every level")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline variant (for profiling)")
+    ap.add_argument("--amr-one-level", action="store_true",
+                    help="block-adaptive leg: the one-level variant only")
     ap.add_argument("--workload", choices=("all", "c2", "c3", "c4", "amr"),
                     default="all",
                     help="all: the headline line with the 3D and batched "
@@ -931,7 +958,8 @@ def main():
                "achievable_copy": copy_bandwidth()})
         return
     if args.workload == "amr":
-        r = run_amr(min(args.steps, AMR_STEPS), min(args.warmup, 2))
+        r = run_amr(min(args.steps, AMR_STEPS), min(args.warmup, 2),
+                    one_level_only=args.amr_one_level)
         args.steps, args.warmup = r["steps"], r["warmup"]
         _line(r["value"], r["ms_per_step"], args, r["workload"], "f64",
               {"amr": r})

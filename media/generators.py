@@ -262,33 +262,60 @@ def _bilinear_up(f):
     return out
 
 
-def config_amr(n=1024, b=16, frac=0.125, seed=2, nu=100.0):
+def config_amr(n=1024, b=16, frac=0.125, seed=2, nu=100.0, levels=1,
+               frac_deeper=0.5):
     """The 2D n x n Kramers / log-normal medium as the base grid of a
     block-adaptive grid (b x b blocks, Neumann walls); the fraction `frac`
-    of the blocks with the steepest mean |grad log E| refined, their fine
-    fields interpolated bilinearly from the base (rho, T, E), kappa from the
-    Kramers law on each level.  Returns a dict of the grid and fields."""
+    of the blocks with the steepest mean |grad log E| refined; with
+    `levels` > 1, on each further level the fraction `frac_deeper` of the
+    steepest b x b patches of the level below whose four face-neighbouring
+    patches also lie on that level (2:1 nesting) refined again.  Fine fields
+    are interpolated bilinearly from the level below (rho, T, E), kappa from
+    the Kramers law on each level.  Returns a dict of the grid and fields:
+    `blocks` is one list of (bx, by) per refined level, the fine arrays hold
+    level 1's blocks, then level 2's, ..."""
     rho, E, e, dt = _c2_fields(n, seed, nu)
     gamma = 5.0 / 3.0
     T = (gamma - 1.0) * e / rho
-    gy, gx = np.gradient(np.log(E))
-    steep = np.sqrt(gx * gx + gy * gy) * n
-    nbx = n // b
-    score = steep.reshape(nbx, b, nbx, b).mean(axis=(1, 3))
-    k = int(round(frac * nbx * nbx))
-    order = np.argsort(-score.ravel(), kind="stable")[:k]
-    blocks = sorted(((int(i % nbx), int(i // nbx)) for i in order),
-                    key=lambda xy: (xy[1], xy[0]))
-    up = {name: _bilinear_up(f) for name, f in (("rho", rho), ("T", T),
-                                                ("E", E))}
     s = 2 * b
-
-    def cut(full):
-        return np.stack([full[by * s:(by + 1) * s, bx * s:(bx + 1) * s]
-                         for bx, by in blocks])
-    rho_f, T_f, E_f = cut(up["rho"]), cut(up["T"]), cut(up["E"])
-    return dict(n=n, b=b, blocks=blocks, dx=1.0 / n, dt=dt,
-                bc=("neumann", "neumann"),
+    full = {"rho": rho, "T": T, "E": E}
+    present = np.ones((n, n), dtype=bool)
+    all_blocks, parts = [], {"rho": [], "T": [], "E": []}
+    for lev in range(1, levels + 1):
+        m = n << (lev - 1)  # the lattice being refined
+        gy, gx = np.gradient(np.log(full["E"]))
+        steep = np.sqrt(gx * gx + gy * gy) * m
+        ub = m // b
+        score = steep.reshape(ub, b, ub, b).mean(axis=(1, 3))
+        inside = present.reshape(ub, b, ub, b).all(axis=(1, 3))
+        if lev == 1:
+            ok = inside
+            k = int(round(frac * ub * ub))
+        else:
+            pad = np.pad(inside, 1, constant_values=True)  # walls end it
+            ok = inside & pad[:-2, 1:-1] & pad[2:, 1:-1] & pad[1:-1, :-2] \
+                & pad[1:-1, 2:]
+            k = int(round(frac_deeper * np.count_nonzero(ok)))
+        cand = np.flatnonzero(ok.ravel())
+        order = cand[np.argsort(-score.ravel()[cand], kind="stable")][:k]
+        blocks = sorted(((int(i % ub), int(i // ub)) for i in order),
+                        key=lambda xy: (xy[1], xy[0]))
+        all_blocks.append(blocks)
+        up = {name: _bilinear_up(f) for name, f in full.items()}
+        for name in parts:
+            parts[name].append(np.stack(
+                [up[name][by * s:(by + 1) * s, bx * s:(bx + 1) * s]
+                 for bx, by in blocks]))
+        present = np.zeros((2 * m, 2 * m), dtype=bool)
+        for bx, by in blocks:
+            present[by * s:(by + 1) * s, bx * s:(bx + 1) * s] = True
+        full = up
+    rho_f = np.concatenate(parts["rho"])
+    T_f = np.concatenate(parts["T"])
+    E_f = np.concatenate(parts["E"])
+    counts = "-".join(str(len(bl)) for bl in all_blocks)
+    return dict(n=n, b=b, blocks=all_blocks[0] if levels == 1 else all_blocks,
+                dx=1.0 / n, dt=dt, bc=("neumann", "neumann"),
                 rho_b=rho, E_b=E, kappa_b=_kramers(rho, T, KRAMERS),
                 rho_f=rho_f, E_f=E_f, kappa_f=_kramers(rho_f, T_f, KRAMERS),
-                name=f"amr-2d-{n}sq-base-b{b}-{len(blocks)}-refined-blocks")
+                name=f"amr-2d-{n}sq-base-b{b}-{counts}-refined-blocks")

@@ -1,5 +1,6 @@
 """FP64 CPU oracle of the backward-Euler FLD diffusion step on a 2D
-block-adaptive grid: a base grid and one level of refined blocks.
+block-adaptive grid: a base grid and one level of refined blocks
+(``amr_step``), or several nested levels (``hier_step``, at the end).
 
 TEST INFRASTRUCTURE ONLY: imported by tests, never by the product path.
 Shares no code with the HIP library.

@@ -60,6 +60,15 @@ __device__ __forceinline__ double amr_val(const AmrGeom& G, int l,
   return vb[(int64_t)J * G.nx + I];
 }
 
+// the value of the leaf cell of level l under lattice point (I, J), which
+// 2:1 nesting places on level l itself (l = 0: the base)
+__device__ __forceinline__ double amr_val_at(const AmrGeom& G, int l,
+                                             const double* vb,
+                                             const double* vf, int I, int J) {
+  if (l == 0) return vb[(int64_t)J * G.nx + I];
+  return vf[amr_fidx(G, l, amr_blk(G, l, I, J), I, J)];
+}
+
 // a cell of level l (inside l's blocks) lies under a level-(l+1) block
 __device__ __forceinline__ bool amr_covered(const AmrGeom& G, int l, int I,
                                             int J) {
@@ -104,8 +113,7 @@ __device__ __forceinline__ double amr_weight(const AmrGeom& G, int64_t t) {
 //    along the face, beta / 4 each (their faces pointing back);
 //  - neighbour outside the level's blocks: the coarser leaf cell, beta
 //    (this cell's face k).
-// (Not inlined: inlining it into its callers crashes this compiler.)
-__device__ __noinline__ void amr_couple(
+__device__ __forceinline__ void amr_couple(
     const AmrGeom& G, const double* __restrict__ ax,
     const double* __restrict__ ay, const double* __restrict__ cf,
     const double* __restrict__ xb, const double* __restrict__ xf, int l,
@@ -121,7 +129,7 @@ __device__ __noinline__ void amr_couple(
   if (nb < 0) {  // the coarser leaf cell
     const double w = cf[(int64_t)k * G.Nf + f];
     ws += w;
-    wx += w * amr_val(G, l - 1, xb, xf, II >> 1, JJ >> 1);
+    wx += w * amr_val_at(G, l - 1, xb, xf, II >> 1, JJ >> 1);
     return;
   }
   if (amr_covered(G, l, II, JJ)) {  // the finer cells along the face
@@ -149,6 +157,32 @@ __device__ __noinline__ void amr_couple(
   }
   ws += w;
   wx += w * xn;
+}
+
+// The four directions of a fine leaf cell (level l, block-local (lx, ly)):
+// a neighbour inside the same block and not under finer blocks by offset,
+// the others through amr_couple.
+__device__ __forceinline__ void amr_couple_fine(
+    const AmrGeom& G, const double* __restrict__ cf,
+    const double* __restrict__ xb, const double* __restrict__ xf,
+    const AmrCell& c, int64_t f, int lx, int ly, double& ws, double& wx) {
+  const bool top = c.l >= G.L;  // no finer level: no covered neighbour
+  for (int k = 0; k < 4; ++k) {
+    const double a = cf[(int64_t)k * G.Nf + f];
+    if (a == 0.0) continue;  // a wall (faces are positive otherwise)
+    const int d = k >> 1, s = (k & 1) ? 1 : -1;
+    const int ln = d == 0 ? lx + s : ly + s;
+    if (ln >= 0 && ln < G.S) {
+      const int64_t fn = f + (d == 0 ? s : s * G.S);
+      if (top || !amr_covered(G, c.l, c.I + (d == 0 ? s : 0),
+                              c.J + (d == 1 ? s : 0))) {
+        ws += a;
+        wx += a * xf[fn];
+        continue;
+      }
+    }
+    amr_couple(G, nullptr, nullptr, cf, xb, xf, c.l, f, c.I, c.J, k, ws, wx);
+  }
 }
 
 // ---- views and coefficients ----
@@ -317,8 +351,13 @@ __device__ __forceinline__ double amr_apply_cell(
   }
   if (amr_covered(G, l, I, J)) return 0.0;
   double ws = 0.0, wx = 0.0;
-  for (int k = 0; k < 4; ++k)
-    amr_couple(G, ax, ay, cf, x, xf, l, f, I, J, k, ws, wx);
+  if (l == 0) {
+    for (int k = 0; k < 4; ++k)
+      amr_couple(G, ax, ay, cf, x, xf, 0, -1, I, J, k, ws, wx);
+  } else {
+    const AmrCell c = {l, 0, I, J};
+    amr_couple_fine(G, cf, x, xf, c, f, I % G.S, J % G.S, ws, wx);
+  }
   return x[t] * (1.0 + ws) - wx;
 }
 
@@ -357,14 +396,19 @@ __global__ void __launch_bounds__(kT)
     k_amr_smooth(AmrGeom G, int l, const double* __restrict__ cf,
                  const double* __restrict__ r, double* __restrict__ z,
                  int colour) {
-  const int64_t f = G.off[l - 1] + (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t loc = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t f = G.off[l - 1] + loc;
   if (f >= G.off[l]) return;
-  const AmrCell c = amr_cell(G, f);
-  if (((c.I + c.J) & 1) != colour || amr_covered(G, l, c.I, c.J)) return;
+  // the colour from the block-local position (S is even)
+  const int in = (int)(loc % ((int64_t)G.S * G.S));
+  const int lx = in % G.S, ly = in / G.S;
+  if (((lx + ly) & 1) != colour) return;
+  const int blk = (int)(loc / ((int64_t)G.S * G.S));
+  const AmrCell c = {l, blk, G.S * G.bxy[l - 1][2 * blk] + lx,
+                     G.S * G.bxy[l - 1][2 * blk + 1] + ly};
+  if (l < G.L && amr_covered(G, l, c.I, c.J)) return;
   double ws = 0.0, wx = 0.0;
-  for (int k = 0; k < 4; ++k)
-    amr_couple(G, nullptr, nullptr, cf, z, z + G.Nb, l, f, c.I, c.J, k, ws,
-               wx);
+  amr_couple_fine(G, cf, z, z + G.Nb, c, f, lx, ly, ws, wx);
   z[G.Nb + f] = (r[G.Nb + f] + wx) / (1.0 + ws);
 }
 
