@@ -1,21 +1,22 @@
-// Block-adaptive 2D step (include/fld.h, fld_amr_*): a base grid and one
-// level of refined blocks, the backward-Euler diffusion of eq. mhd_r_e on
-// the leaf cells (Sect. 3 solves it by multigrid on MPI-AMRVAC's
-// block-adaptive grids).
+// Block-adaptive 2D step (include/fld.h, fld_amr_*): a base grid and up
+// to four levels of nested refined blocks, the backward-Euler diffusion of
+// eq. mhd_r_e on the leaf cells (Sect. 3 solves it by multigrid on
+// MPI-AMRVAC's block-adaptive grids).
 //
 // The composite operator (fld_amr.hip) is symmetric in the volume-weighted
 // inner product, so the solve is conjugate gradients in that product,
 // flexible (one previous direction) because its preconditioner is a
-// multigrid cycle over the two levels:
-//   1. Gauss-Seidel sweeps (red-black) on the fine cells for A z = r from
-//      z = 0, the base cells' z held at 0;
-//   2. the base grid's right-hand side: a base leaf cell's residual with
-//      the fine correction's flux across the block edges, a covered cell's
-//      the mean of its children's residuals;
+// multigrid cycle over the levels:
+//   1. Gauss-Seidel sweeps (red-black) over the leaf cells of every refined
+//      level, finest first, for A z = r from z = 0, the base cells' z held
+//      at 0;
+//   2. the composite residual r - A z, restricted level by level (a cell
+//      under finer blocks: the mean of its children) to the base grid;
 //   3. one V-cycle of the base grid's own multigrid (a single-grid context,
 //      its faces from the base view of E) for the base correction;
-//   4. the base correction prolonged (bilinear) onto the fine cells, then
-//      the sweeps of 1 in reverse colour order with the base values fixed.
+//   4. the base correction prolonged (bilinear) level by level onto every
+//      refined cell, then the sweeps of 1, coarsest refined level first, in
+//      reverse colour order with the base values fixed.
 // The stop test is the volume-weighted relative residual |r|_V / |b|_V.
 // The scalars of an iteration stay on the device: the operator and update
 // kernels leave block sums, one-block reductions turn them into the
