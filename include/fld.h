@@ -333,9 +333,9 @@ fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* ctx, const double* rho_base,
                                     const double* e_fine, double k0, double a,
                                     double b, double kmin, double kmax,
                                     double* kappa_base, double* kappa_fine);
-/* Kernel timing of the block-adaptive step: with `on`, the first fine
- * red-black half-sweep of every step (the step's dominant kernel) is
- * bracketed by events on the context's stream; the read returns the summed
+/* Kernel timing of the block-adaptive step: with `on`, every level-1
+ * red-black half-sweep of a step (the step's dominant kernel) is
+ * bracketed by events recorded by the launch; the read returns the summed
  * milliseconds, the launch count and the algorithmic bytes of those
  * launches (r and the four faces of half the fine cells and z of all of
  * them read, half of z written), then resets the counters. */

@@ -7,16 +7,18 @@
 // inner product, so the solve is conjugate gradients in that product,
 // flexible (one previous direction) because its preconditioner is a
 // multigrid cycle over the levels:
-//   1. Gauss-Seidel sweeps (red-black) over the leaf cells of every refined
-//      level, finest first, for A z = r from z = 0, the base cells' z held
-//      at 0;
-//   2. the composite residual r - A z, restricted level by level (a cell
-//      under finer blocks: the mean of its children) to the base grid;
-//   3. one V-cycle of the base grid's own multigrid (a single-grid context,
+//   1. down, from the finest level: red-black Gauss-Seidel sweeps over
+//      every cell of the level (those under finer blocks included) for the
+//      level's own correction problem, whose right-hand side is r on leaf
+//      cells and the restricted residual of the finer level under finer
+//      blocks; then the level's residual restricted to the next coarser
+//      level, whose leaf cells next to this level also take the flux of
+//      its correction;
+//   2. one V-cycle of the base grid's own multigrid (a single-grid context,
 //      its faces from the base view of E) for the base correction;
-//   4. the base correction prolonged (bilinear) level by level onto every
-//      refined cell, then the sweeps of 1, coarsest refined level first, in
-//      reverse colour order with the base values fixed.
+//   3. up, from level 1: each level's correction += the coarser one
+//      prolonged (bilinear), then the sweeps again in reverse colour order;
+//   4. each leaf cell takes its level's correction.
 // The stop test is the volume-weighted relative residual |r|_V / |b|_V.
 // The scalars of an iteration stay on the device: the operator and update
 // kernels leave block sums, one-block reductions turn them into the
@@ -47,7 +49,8 @@ struct fld_amr_ctx {
   hipStream_t stream = nullptr;
   double *Ev = nullptr, *rv = nullptr, *kv = nullptr;
   double *Evf = nullptr, *rvf = nullptr, *kvf = nullptr;  // fine views
-  double* t = nullptr;  // preconditioner temporary (a leaf vector)
+  double* t = nullptr;  // preconditioner: level residuals
+  double* g = nullptr;  // preconditioner: right-hand sides per level
   double *Db = nullptr, *Df = nullptr, *cf = nullptr, *rhs = nullptr;
   double *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr;
   double *p2[2] = {}, *q2[2] = {};
@@ -56,10 +59,11 @@ struct fld_amr_ctx {
   int* bad = nullptr;
   std::vector<double> host_part;
   std::string err;
-  // kernel timing: the first fine half-sweep of every step, between events
+  // kernel timing: every level-1 half-sweep of a step, each between a pair
+  // of events from this pool (ev_used pairs taken in the current step)
   bool timing = false;
-  bool timed_this_step = false;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
   double t_ms = 0.0, t_bytes = 0.0;
   int64_t t_launches = 0;
 };
@@ -213,7 +217,7 @@ AmrPlan make_amr_plan(const fld_params& p, int32_t block, int32_t nlevels,
   P.Df = take((size_t)P.Nf * 8);
   P.cf = take((size_t)P.Nf * 8 * 4);
   P.rhs = take((size_t)P.Nb * 8);
-  P.vec = take((size_t)P.nvec * 8 * 9);  // x, b, r, z, p[2], q[2], t
+  P.vec = take((size_t)P.nvec * 8 * 10);  // x, b, r, z, p[2], q[2], t, g
   P.partials = take((size_t)P.dot_blocks * 3 * 8);
   P.sc = take(8 * 8);
   P.bad = take(8);
@@ -244,44 +248,53 @@ fld_status dots(fld_amr_ctx* c, int n, const double* u0, const double* v0,
   return FLD_OK;
 }
 
-// z = M r (the cycle of the file comment)
+// the next pair of timing events of this step (created on first use)
+fld_status timing_pair(fld_amr_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
+  while (c->ev.size() < 2 * (c->ev_used + 1)) {
+    hipEvent_t e = nullptr;
+    AMR_HIP(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  *e0 = c->ev[2 * c->ev_used];
+  *e1 = c->ev[2 * c->ev_used + 1];
+  ++c->ev_used;
+  return FLD_OK;
+}
+
+// z = M r (the cycle of the file comment); z holds each level's correction
+// e on every cell of the level (cells under finer blocks included) until
+// the end, where those cells are zeroed
 fld_status precondition(fld_amr_ctx* c, const double* r, double* z) {
   const AmrGeom& G = c->G;
   hipStream_t s = c->stream;
   const int64_t n = G.Nb + G.Nf;
   AMR_HIP(c, hipMemsetAsync(z, 0, sizeof(double) * n, s));
+  AMR_HIP(c, hipMemcpyAsync(c->g, r, sizeof(double) * n,
+                            hipMemcpyDeviceToDevice, s));
   const int pre = std::max(c->p.pre_smooth, 1);
   const int post = std::max(c->p.post_smooth, 1);
-  for (int k = 0; k < pre; ++k)
-    for (int l = G.L; l >= 1; --l)  // finest level first
+  for (int l = G.L; l >= 1; --l) {  // down: the finest level first
+    for (int k = 0; k < pre; ++k)
       for (int colour = 0; colour < 2; ++colour) {
-        const bool timed = c->timing && !c->timed_this_step && l == 1;
-        AMR_HIP(c, amr_smooth(G, l, c->cf, r, z, colour, s,
-                              timed ? c->ev[0] : nullptr,
-                              timed ? c->ev[1] : nullptr));
-        if (timed) c->timed_this_step = true;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing && l == 1) AMR_TRY(timing_pair(c, &e0, &e1));
+        AMR_HIP(c, amr_smooth_level(G, l, c->cf, c->g, z, colour, s, e0, e1));
       }
-  // the residual of the smoothed correction, restricted level by level
-  const double* ax = nullptr;
-  const double* ay = nullptr;
-  base_faces(c->base, &ax, &ay);
-  AMR_HIP(c, amr_apply(G, ax, ay, c->cf, z, c->t, s));
-  AMR_HIP(c, amr_axpy(n, -1.0, c->t, r, c->t, s));
-  for (int l = G.L - 1; l >= 1; --l)
-    AMR_HIP(c, amr_restrict_level(G, l, c->t, s));
-  AMR_HIP(c, amr_base_rhs(G, c->t, c->rhs, s));
-  const fld_status st = precond_vcycle(c->base, c->rhs, z);
+    AMR_HIP(c, amr_resid_level(G, l, c->cf, c->g, z, c->t, s));
+    AMR_HIP(c, amr_coarse_rhs(G, l - 1, c->cf, z, c->t, c->g, s));
+  }
+  const fld_status st = precond_vcycle(c->base, c->g, z);
   if (st != FLD_OK)
     return amr_fail(c, st, "base V-cycle: %s", ctx_error(c->base));
-  // the base correction prolonged level by level onto every fine cell
-  AMR_HIP(c, hipMemcpyAsync(c->t, z, sizeof(double) * G.Nb,
-                            hipMemcpyDeviceToDevice, s));
-  for (int l = 1; l <= G.L; ++l) AMR_HIP(c, amr_prolong_level(G, l, c->t, s));
-  AMR_HIP(c, amr_axpy(G.Nf, 1.0, c->t + G.Nb, z + G.Nb, z + G.Nb, s));
-  for (int k = 0; k < post; ++k)
-    for (int l = 1; l <= G.L; ++l)
-      for (int colour = 1; colour >= 0; --colour)
-        AMR_HIP(c, amr_smooth(G, l, c->cf, r, z, colour, s));
+  for (int l = 1; l <= G.L; ++l) {  // up: prolong, then sweep again
+    AMR_HIP(c, amr_prolong_level(G, l, z, s));
+    for (int k = 0; k < post; ++k)
+      for (int colour = 1; colour >= 0; --colour) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing && l == 1) AMR_TRY(timing_pair(c, &e0, &e1));
+        AMR_HIP(c, amr_smooth_level(G, l, c->cf, c->g, z, colour, s, e0, e1));
+      }
+  }
   AMR_HIP(c, amr_zero_covered(G, z, s));
   return FLD_OK;
 }
@@ -294,7 +307,7 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   const AmrGeom& G = c->G;
   hipStream_t s = c->stream;
   const int64_t n = G.Nb + G.Nf;
-  c->timed_this_step = false;
+  c->ev_used = 0;
   // coefficients: views, D on both levels, fine faces, base faces
   AMR_HIP(c, amr_views(G, E_b, rho_b, kap_b, E_f, rho_f, kap_f, c->Ev, c->rv,
                        c->kv, c->Evf, c->rvf, c->kvf, s));
@@ -367,16 +380,17 @@ fld_status amr_solve(fld_amr_ctx* c, double dt, const double* rho_b,
   precond_end(c->base);
   AMR_HIP(c, amr_unpack(G, c->x, E_b_out, E_f_out, s));
   AMR_HIP(c, hipStreamSynchronize(s));
-  if (c->timed_this_step) {
+  for (size_t k = 0; k < c->ev_used; ++k) {
     float ms = 0.0f;
-    AMR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    AMR_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
     c->t_ms += ms;
     c->t_launches += 1;
-    // one colour: r and the four faces of half the fine cells read, z of
-    // every fine cell read once, half of z written
+    // one colour: g and the four faces of half the level-1 cells read, e
+    // of every level-1 cell read once, half of e written
     c->t_bytes += 8.0 * (double)(G.off[1] - G.off[0]) *
                   (0.5 + 2.0 + 1.0 + 0.5);
   }
+  c->ev_used = 0;
   if (stats) {
     stats->cycles = k;
     stats->outer_iters = k;
@@ -488,9 +502,9 @@ fld_status fld_amr_setup_levels(const fld_params* p, int32_t block,
   c->cf = (double*)(w + P.cf);
   c->rhs = (double*)(w + P.rhs);
   double* v = (double*)(w + P.vec);
-  double** vecs[9] = {&c->x, &c->b, &c->r, &c->z, &c->p2[0],
-                      &c->p2[1], &c->q2[0], &c->q2[1], &c->t};
-  for (int k = 0; k < 9; ++k) *vecs[k] = v + (size_t)k * P.nvec;
+  double** vecs[10] = {&c->x, &c->b, &c->r, &c->z, &c->p2[0],
+                       &c->p2[1], &c->q2[0], &c->q2[1], &c->t, &c->g};
+  for (int k = 0; k < 10; ++k) *vecs[k] = v + (size_t)k * P.nvec;
   c->partials = (double*)(w + P.partials);
   c->sc = (double*)(w + P.sc);
   c->bad = (int*)(w + P.bad);
@@ -587,11 +601,8 @@ fld_status fld_amr_opacity_powerlaw(fld_amr_ctx* c, const double* rho_base,
 
 fld_status fld_amr_kernel_timing_enable(fld_amr_ctx* c, int32_t on) {
   if (!c) return amr_fail(nullptr, FLD_ERR_INVALID_ARG, "ctx is NULL");
-  if (on && !c->ev[0]) {
-    for (int k = 0; k < 2; ++k)
-      AMR_HIP(c, hipEventCreate(&c->ev[k]));
-  }
   c->timing = on != 0;
+  c->ev_used = 0;
   return FLD_OK;
 }
 
@@ -602,7 +613,7 @@ fld_status fld_amr_kernel_timing_read(fld_amr_ctx* c, double* ms_total,
   if (ms_total) *ms_total = c->t_ms;
   if (launches) *launches = c->t_launches;
   if (bytes_total) *bytes_total = c->t_bytes;
-  if (kernel_name) *kernel_name = "k_amr_smooth";
+  if (kernel_name) *kernel_name = "k_amr_smooth_level";
   c->t_ms = c->t_bytes = 0.0;
   c->t_launches = 0;
   return FLD_OK;
@@ -615,8 +626,7 @@ const char* fld_amr_last_error(const fld_amr_ctx* c) {
 void fld_amr_destroy(fld_amr_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (int k = 0; k < 2; ++k)
-    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   fld_destroy(c->base);
   delete c;
 }

@@ -62,21 +62,29 @@ hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
                      const double* cf, const double* x, double* y,
                      hipStream_t s, const double* r = nullptr,
                      double* partials = nullptr);
-// One colour of a red-black sweep over the leaf cells of level l >= 1 for
-// A z = r, the other levels' z fixed; with ev0 and ev1 the launch records
-// its start and end on them.
-hipError_t amr_smooth(const AmrGeom& G, int level, const double* cf,
-                      const double* r, double* z, int colour, hipStream_t s,
-                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The preconditioner's cycle through the levels.  amr_smooth_level: one
+// colour of a red-black sweep over every cell of level l >= 1 for the
+// level's own correction problem L_l e = g (the coarser level's e fixed
+// outside the level's blocks); with ev0 and ev1 the launch records its
+// start and end on them.  amr_resid_level: t = g - L_l e on level l.
+// amr_coarse_rhs: g on level l (0: the base) after level l + 1's sweeps
+// (cells under level-(l+1) blocks: the mean of their children's t; leaf
+// cells next to level-(l+1) cells: plus the flux of those cells' e).
+// amr_prolong_level: e of every cell of level l += bilinear from level
+// l - 1's e.
+hipError_t amr_smooth_level(const AmrGeom& G, int level, const double* cf,
+                            const double* g, double* e, int colour,
+                            hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
+hipError_t amr_resid_level(const AmrGeom& G, int level, const double* cf,
+                           const double* g, const double* e, double* t,
+                           hipStream_t s);
+hipError_t amr_coarse_rhs(const AmrGeom& G, int level, const double* cf,
+                          const double* e, const double* t, double* g,
+                          hipStream_t s);
 // Cells of level l >= 1 under finer blocks: the mean of their children.
 hipError_t amr_restrict_level(const AmrGeom& G, int level, double* v,
                               hipStream_t s);
-// The base correction's right-hand side: a leaf base cell's entry of v, a
-// covered one's the mean of its level-1 children.
-hipError_t amr_base_rhs(const AmrGeom& G, const double* v, double* rhs,
-                        hipStream_t s);
-// e on every cell of level l >= 1: bilinear from the level below (its e,
-// or z of the base for l = 1, stored in e's base part).
 hipError_t amr_prolong_level(const AmrGeom& G, int level, double* e,
                              hipStream_t s);
 // entries of cells under finer blocks (base and fine) back to 0

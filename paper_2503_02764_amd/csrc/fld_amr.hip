@@ -390,26 +390,138 @@ __global__ void __launch_bounds__(kT)
   }
 }
 
-// one colour ((I + J) & 1) of a Gauss-Seidel sweep over the leaf cells of
-// level l for the correction z
-__global__ void __launch_bounds__(kT)
-    k_amr_smooth(AmrGeom G, int l, const double* __restrict__ cf,
-                 const double* __restrict__ r, double* __restrict__ z,
-                 int colour) {
-  const int64_t loc = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const int64_t f = G.off[l - 1] + loc;
-  if (f >= G.off[l]) return;
-  // the colour from the block-local position (S is even)
+// The couplings of a cell of level l (any of its cells, under finer blocks
+// or not) in the level's own operator: same-level neighbours by alpha, the
+// next coarser level's cell outside the level's blocks by beta; adds sum w
+// to ws and sum w e_nb to wx.
+__device__ __forceinline__ void amr_couple_level(
+    const AmrGeom& G, const double* __restrict__ cf,
+    const double* __restrict__ eb, const double* __restrict__ ef, int l,
+    int64_t f, int lx, int ly, int I, int J, double& ws, double& wx) {
+  const int NX = G.nx << l, NY = G.ny << l;
+  for (int k = 0; k < 4; ++k) {
+    const double a = cf[(int64_t)k * G.Nf + f];
+    if (a == 0.0) continue;  // a wall
+    const int d = k >> 1, s = (k & 1) ? 1 : -1;
+    const int ln = d == 0 ? lx + s : ly + s;
+    double v;
+    if (ln >= 0 && ln < G.S) {
+      v = ef[f + (d == 0 ? s : s * G.S)];
+    } else {
+      const int II = amr_wrap(I + (d == 0 ? s : 0), NX, 1);
+      const int JJ = amr_wrap(J + (d == 1 ? s : 0), NY, 1);
+      const int nb = amr_blk(G, l, II, JJ);
+      v = nb >= 0 ? ef[amr_fidx(G, l, nb, II, JJ)]
+                  : amr_val_at(G, l - 1, eb, ef, II >> 1, JJ >> 1);
+    }
+    ws += a;
+    wx += a * v;
+  }
+}
+
+__device__ __forceinline__ AmrCell amr_level_cell(const AmrGeom& G, int l,
+                                                  int64_t loc, int& lx,
+                                                  int& ly) {
   const int in = (int)(loc % ((int64_t)G.S * G.S));
-  const int lx = in % G.S, ly = in / G.S;
-  if (((lx + ly) & 1) != colour) return;
+  lx = in % G.S;
+  ly = in / G.S;
   const int blk = (int)(loc / ((int64_t)G.S * G.S));
   const AmrCell c = {l, blk, G.S * G.bxy[l - 1][2 * blk] + lx,
                      G.S * G.bxy[l - 1][2 * blk + 1] + ly};
-  if (l < G.L && amr_covered(G, l, c.I, c.J)) return;
+  return c;
+}
+
+// one colour ((I + J) & 1) of a Gauss-Seidel sweep over every cell of
+// level l for the level's correction e (L_l e = g), the coarser level's e
+// fixed outside the level's blocks
+__global__ void __launch_bounds__(kT)
+    k_amr_smooth_level(AmrGeom G, int l, const double* __restrict__ cf,
+                       const double* __restrict__ g, double* __restrict__ e,
+                       int colour) {
+  const int64_t loc = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t f = G.off[l - 1] + loc;
+  if (f >= G.off[l]) return;
+  int lx, ly;
+  const int in = (int)(loc % ((int64_t)G.S * G.S));
+  if ((((in % G.S) + (in / G.S)) & 1) != colour) return;  // S is even
+  const AmrCell c = amr_level_cell(G, l, loc, lx, ly);
   double ws = 0.0, wx = 0.0;
-  amr_couple_fine(G, cf, z, z + G.Nb, c, f, lx, ly, ws, wx);
-  z[G.Nb + f] = (r[G.Nb + f] + wx) / (1.0 + ws);
+  amr_couple_level(G, cf, e, e + G.Nb, l, f, lx, ly, c.I, c.J, ws, wx);
+  e[G.Nb + f] = (g[G.Nb + f] + wx) / (1.0 + ws);
+}
+
+// t = g - L_l e on every cell of level l
+__global__ void __launch_bounds__(kT)
+    k_amr_resid_level(AmrGeom G, int l, const double* __restrict__ cf,
+                      const double* __restrict__ g,
+                      const double* __restrict__ e, double* __restrict__ t) {
+  const int64_t loc = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t f = G.off[l - 1] + loc;
+  if (f >= G.off[l]) return;
+  int lx, ly;
+  const AmrCell c = amr_level_cell(G, l, loc, lx, ly);
+  double ws = 0.0, wx = 0.0;
+  amr_couple_level(G, cf, e, e + G.Nb, l, f, lx, ly, c.I, c.J, ws, wx);
+  t[G.Nb + f] = g[G.Nb + f] - (e[G.Nb + f] * (1.0 + ws) - wx);
+}
+
+// The right-hand side of level l (the base for l = 0) after level l + 1's
+// smoothing: a cell under level-(l+1) blocks takes the mean of its
+// children's residuals t; a leaf cell next to level-(l+1) cells adds the
+// flux of their correction e into it (beta / 4 e_f per finer cell).
+__device__ __forceinline__ void amr_coarse_rhs_cell(
+    const AmrGeom& G, int l, int64_t t_idx, int I, int J,
+    const double* __restrict__ cf, const double* __restrict__ e,
+    const double* __restrict__ t, double* __restrict__ g) {
+  const double* ef = e + G.Nb;
+  if (amr_covered(G, l, I, J)) {
+    double acc = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int I2 = 2 * I + (q & 1), J2 = 2 * J + (q >> 1);
+      acc += t[G.Nb + amr_fidx(G, l + 1, amr_blk(G, l + 1, I2, J2), I2, J2)];
+    }
+    g[t_idx] = 0.25 * acc;
+    return;
+  }
+  const int NX = G.nx << l, NY = G.ny << l;
+  double add = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int d = k >> 1, s = (k & 1) ? 1 : -1;
+    int II = I + (d == 0 ? s : 0), JJ = J + (d == 1 ? s : 0);
+    const int cc = d == 0 ? II : JJ, n = d == 0 ? NX : NY;
+    if ((cc < 0 || cc >= n) && !G.per[d]) continue;
+    II = amr_wrap(II, NX, 1);
+    JJ = amr_wrap(JJ, NY, 1);
+    if (l > 0 && amr_blk(G, l, II, JJ) < 0) continue;  // coarser side
+    if (!amr_covered(G, l, II, JJ)) continue;
+    const int back = k ^ 1;
+    for (int q = 0; q < 2; ++q) {
+      const int I2 = d == 0 ? (s > 0 ? 2 * II : 2 * II + 1) : 2 * II + q;
+      const int J2 = d == 0 ? 2 * JJ + q : (s > 0 ? 2 * JJ : 2 * JJ + 1);
+      const int64_t f2 =
+          amr_fidx(G, l + 1, amr_blk(G, l + 1, I2, J2), I2, J2);
+      add += 0.25 * cf[(int64_t)back * G.Nf + f2] * ef[f2];
+    }
+  }
+  g[t_idx] += add;
+}
+
+__global__ void __launch_bounds__(kT)
+    k_amr_coarse_rhs(AmrGeom G, int l, const double* __restrict__ cf,
+                     const double* __restrict__ e,
+                     const double* __restrict__ t, double* __restrict__ g) {
+  const int64_t loc = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (l == 0) {
+    if (loc >= G.Nb) return;
+    amr_coarse_rhs_cell(G, 0, loc, (int)(loc % G.nx), (int)(loc / G.nx), cf,
+                        e, t, g);
+    return;
+  }
+  const int64_t f = G.off[l - 1] + loc;
+  if (f >= G.off[l]) return;
+  int lx, ly;
+  const AmrCell c = amr_level_cell(G, l, loc, lx, ly);
+  amr_coarse_rhs_cell(G, l, G.Nb + f, c.I, c.J, cf, e, t, g);
 }
 
 // cells of level l under finer blocks: the mean of their four children
@@ -428,28 +540,7 @@ __global__ void __launch_bounds__(kT)
   v[G.Nb + f] = 0.25 * acc;
 }
 
-// rhs of the base correction: a leaf base cell's entry, a covered one's
-// the mean of its level-1 children
-__global__ void __launch_bounds__(kT)
-    k_amr_base_rhs(AmrGeom G, const double* __restrict__ v,
-                   double* __restrict__ rhs) {
-  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (c >= G.Nb) return;
-  const int i = (int)(c % G.nx), j = (int)(c / G.nx);
-  if (!amr_covered(G, 0, i, j)) {
-    rhs[c] = v[c];
-    return;
-  }
-  const double* vf = v + G.Nb;
-  double acc = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int I2 = 2 * i + (q & 1), J2 = 2 * j + (q >> 1);
-    acc += vf[amr_fidx(G, 1, amr_blk(G, 1, I2, J2), I2, J2)];
-  }
-  rhs[c] = 0.25 * acc;
-}
-
-// e on the cells of level l: bilinear from the parent cell and its
+// e of every cell of level l += bilinear from the parent cell and its
 // neighbours towards the cell (weights 9, 3, 3, 1 over 16), on the level
 // below (its view of e)
 __global__ void __launch_bounds__(kT)
@@ -466,7 +557,7 @@ __global__ void __launch_bounds__(kT)
                     3.0 * amr_val(G, l - 1, e, ef, i2, j) +
                     3.0 * amr_val(G, l - 1, e, ef, i, j2) +
                     amr_val(G, l - 1, e, ef, i2, j2)) / 16.0;
-  e[G.Nb + f] = v;
+  e[G.Nb + f] += v;
 }
 
 // entries of cells under finer blocks back to 0
@@ -646,17 +737,37 @@ hipError_t amr_apply(const AmrGeom& G, const double* ax, const double* ay,
   return hipGetLastError();
 }
 
-hipError_t amr_smooth(const AmrGeom& G, int level, const double* cf,
-                      const double* r, double* z, int colour, hipStream_t s,
-                      hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t amr_smooth_level(const AmrGeom& G, int level, const double* cf,
+                            const double* g, double* e, int colour,
+                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t n = level_cells(G, level);
   if (n == 0) return hipSuccess;
   if (ev0 && ev1)  // the launch records its own start and end
-    hipExtLaunchKernelGGL(k_amr_smooth, dim3(nblk(n)), dim3(kT), 0, s, ev0,
-                          ev1, 0, G, level, cf, r, z, colour);
+    hipExtLaunchKernelGGL(k_amr_smooth_level, dim3(nblk(n)), dim3(kT), 0, s,
+                          ev0, ev1, 0, G, level, cf, g, e, colour);
   else
-    hipLaunchKernelGGL(k_amr_smooth, dim3(nblk(n)), dim3(kT), 0, s, G, level,
-                       cf, r, z, colour);
+    hipLaunchKernelGGL(k_amr_smooth_level, dim3(nblk(n)), dim3(kT), 0, s, G,
+                       level, cf, g, e, colour);
+  return hipGetLastError();
+}
+
+hipError_t amr_resid_level(const AmrGeom& G, int level, const double* cf,
+                           const double* g, const double* e, double* t,
+                           hipStream_t s) {
+  const int64_t n = level_cells(G, level);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_amr_resid_level, dim3(nblk(n)), dim3(kT), 0, s, G,
+                     level, cf, g, e, t);
+  return hipGetLastError();
+}
+
+hipError_t amr_coarse_rhs(const AmrGeom& G, int level, const double* cf,
+                          const double* e, const double* t, double* g,
+                          hipStream_t s) {
+  const int64_t n = level == 0 ? G.Nb : level_cells(G, level);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_amr_coarse_rhs, dim3(nblk(n)), dim3(kT), 0, s, G,
+                     level, cf, e, t, g);
   return hipGetLastError();
 }
 
@@ -666,13 +777,6 @@ hipError_t amr_restrict_level(const AmrGeom& G, int level, double* v,
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_amr_restrict_level, dim3(nblk(n)), dim3(kT), 0, s, G,
                      level, v);
-  return hipGetLastError();
-}
-
-hipError_t amr_base_rhs(const AmrGeom& G, const double* v, double* rhs,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_amr_base_rhs, dim3(nblk(G.Nb)), dim3(kT), 0, s, G, v,
-                     rhs);
   return hipGetLastError();
 }
 
