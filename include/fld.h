@@ -354,10 +354,15 @@ fld_status fld_amr_kernel_timing_read(fld_amr_ctx* ctx, double* ms_total,
  * coarser one); walls end that condition.  The fine arrays hold level 1's
  * blocks, then level 2's, ..., (2 block)^2 doubles each; the cells under
  * finer blocks are not read, and on output hold the mean of their four
- * children.  Same readings and solve as one level (the preconditioner
- * sweeps the fine levels from the finest down, restricts the residual level
- * by level to the base, runs the base V-cycle and prolongs its correction
- * level by level before sweeping again upwards).  fld_amr_setup and
+ * children.  Same readings and solve as one level; the preconditioner
+ * cycles through the levels: from the finest down, red-black sweeps of
+ * each level's own correction problem over all of its cells (the coarser
+ * correction held outside its blocks), then that level's residual,
+ * averaged onto the cells under its blocks, plus the fluxes of its
+ * correction into the coarser leaf cells beside them, as the next coarser
+ * level's right-hand side; the base V-cycle; then from level 1 up,
+ * bilinear prolongation of the coarser correction added to the level's
+ * own and sweeps in reverse colour order.  fld_amr_setup and
  * fld_amr_workspace_bytes are the one-level case. */
 size_t fld_amr_workspace_bytes_levels(const fld_params* p, int32_t block,
                                       int32_t nlevels, const int32_t* nblocks,
